@@ -1,0 +1,197 @@
+/*
+ * rte.h - C ABI of librte, an MI355X (gfx950) solver for the even-parity
+ * discretisation of the anisotropic radiative transfer equation by the
+ * preconditioned Richardson iteration of Doelz, Palii and Schlottbom,
+ * "On robustly convergent and efficient iterative methods for anisotropic
+ * radiative transfer" (arXiv:2102.09038).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - No C++ exception crosses this boundary.  Every function returns an
+ *   rte_status; RTE_OK is 0.  On failure rte_last_error() returns a
+ *   thread-local description of the last non-OK status.
+ * - Pointers named host_* or passed in rte_problem_desc are host memory.
+ *   Pointers documented as "device" are HIP device memory owned by the caller;
+ *   the library never frees them and never keeps them after the call returns.
+ * - hip_stream is a hipStream_t (NULL = the default stream).  Device work is
+ *   enqueued on it; calls documented as blocking also synchronise it.
+ * - Even-space vectors are n_R+ x n_S+ matrices U (column-major, spatial index
+ *   fastest: U[i + n_R+ * k]); vec(U) stacks the columns (Sec. 4).
+ *   Odd-space vectors are n_R- x n_S- matrices, n_S- = 3 n_S+, odd column
+ *   3k + m holds the coefficient of psi_(k,m) = s_m mu_k.
+ * - The even angular index k is the order, in desc->stri, of the triangles
+ *   whose centroid lies in the upper half-sphere (z > 0; ties broken on y,
+ *   then x).  Every such triangle must have its antipode in the mesh.
+ * - All floating-point inputs are FP64.
+ */
+#ifndef RTE_H
+#define RTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rte_status {
+    RTE_OK = 0,
+    RTE_E_ARG = 1,        /* invalid pointer, size, option or descriptor field        */
+    RTE_E_PHYS = 2,       /* sigma_t <= 0, sigma_s < 0, max sigma_s/sigma_t >= 1, g not in [0,1) */
+    RTE_E_MESH = 3,       /* degenerate simplex, non-antipodal sphere mesh, bad index */
+    RTE_E_NOMEM = 4,      /* device allocation failed                                 */
+    RTE_E_HIP = 5,        /* a HIP / rocSOLVER call failed                             */
+    RTE_E_NOTCONV = 6,    /* iteration cap reached; the last iterate is returned      */
+    RTE_E_NONFINITE = 7   /* a residual became NaN or Inf                              */
+} rte_status;
+
+typedef enum rte_precision {
+    RTE_FP64 = 0,         /* every step in FP64                                        */
+    RTE_MIXED = 1         /* scattering GEMMs BF16 in / FP32 accumulate, CG vectors FP32;
+                             outer residual, all dot products and the coarse solve FP64 */
+} rte_precision;
+
+typedef enum rte_dtype { RTE_DT_F64 = 0, RTE_DT_F32 = 1, RTE_DT_BF16 = 2 } rte_dtype;
+
+/* How (M- - K-)^{-1} is applied inside E (Sec. 5.1, Alg. 1). */
+typedef enum rte_odd_solver {
+    RTE_ODD_PCG = 0,      /* PCG preconditioned by (M- - K-_N)^{-1} (Lemma in Sec. 5.1) */
+    RTE_ODD_EXACT = 1     /* exact: per-cell inverse through the full eigendecomposition
+                             of (S-, M_S-); one GEMM when sigma_s/sigma_t is uniform,
+                             two otherwise                                            */
+} rte_odd_solver;
+
+/* How each block of E_0^{-1} is applied (Sec. 5.3). */
+typedef enum rte_e0_solver {
+    RTE_E0_CG = 0,        /* Jacobi-preconditioned CG per direction                    */
+    RTE_E0_BANDED = 1     /* banded Cholesky factors per direction, factored once      */
+} rte_e0_solver;
+
+typedef struct rte_handle rte_handle;   /* opaque; owns all device memory it allocates */
+
+/* Problem statement (Sec. 1, RTE with Henyey-Greenstein scattering and vacuum or
+ * inflow boundary; Sec. 2.2 parameter assumptions; Sec. 4 meshes).  Host pointers,
+ * copied by rte_assemble; the caller may free them after it returns. */
+typedef struct rte_problem_desc {
+    int32_t dim;                 /* spatial dimension d, 2 or 3                              */
+    int32_t n_vert;              /* number of spatial vertices (P1 dofs, n_R+)               */
+    const double* vert;          /* [n_vert * dim] coordinates, vertex-major                 */
+    int32_t n_cell;              /* number of simplices (P0 dofs, n_R-)                      */
+    const int32_t* cell;         /* [n_cell * (dim+1)] vertex indices                        */
+    const double* sigma_t;       /* [n_cell] total attenuation, > 0, piecewise constant      */
+    const double* sigma_s;       /* [n_cell] scattering rate, 0 <= sigma_s < sigma_t         */
+    double g;                    /* HG anisotropy factor, 0 <= g < 1                         */
+    int32_t n_svert;             /* number of sphere-mesh vertices                           */
+    const double* svert;         /* [n_svert * 3] unit vectors                               */
+    int32_t n_stri;              /* number of sphere triangles (even, antipodally symmetric) */
+    const int32_t* stri;         /* [n_stri * 3] vertex indices                              */
+    const double* q_nodal;       /* [n_vert] isotropic volume source at the vertices; the
+                                    even load is l+[:,k] = 2|K_k| (P1 mass) q_nodal          */
+    const double* g_inflow;      /* must be NULL (vacuum boundary); reserved for inflow data */
+} rte_problem_desc;
+
+typedef struct rte_assemble_opts {
+    int32_t quad_level;          /* each sphere triangle's flat image is cut into 4^quad_level
+                                    parts with a 7-point degree-5 rule on each (0..6)        */
+    int32_t n_even;              /* N+ >= 0: correction space = top (N+1)(N+2)/2 eigenvectors
+                                    of (S+, M_S+)  (Sec. 5.4)                                */
+    int32_t n_odd;               /* N- >= 1 odd: PCG preconditioner uses the top
+                                    (N+1)(N+2)/2 eigenpairs of (S-, M_S-)  (Sec. 5.1)        */
+    int32_t e0_solver;           /* rte_e0_solver prepared at assembly (CG is always there)  */
+    int32_t mixed;               /* nonzero: also prepare BF16/FP32 operator copies          */
+} rte_assemble_opts;
+
+typedef struct rte_solve_opts {
+    int32_t l;                   /* inner Richardson steps of P_1^l (Sec. 5.3), >= 1          */
+    double tol;                  /* stop when ||r_n||_2 <= tol ||q||_2                       */
+    int32_t max_iter;            /* outer iteration cap                                      */
+    int32_t precision;           /* rte_precision                                            */
+    int32_t odd_solver;          /* rte_odd_solver                                           */
+    int32_t e0_solver;           /* rte_e0_solver (BANDED needs it at assembly)              */
+    double pcg_tol_resid;        /* relative PCG tolerance inside the residual's E           */
+    double pcg_tol_inner;        /* relative PCG tolerance inside P_1 and the correction     */
+    int32_t pcg_max_iter;        /* PCG iteration cap per E application                      */
+    double cg_tol;               /* relative CG tolerance per E_0 block                      */
+    int32_t cg_max_iter;         /* CG iteration cap per E_0 block                           */
+} rte_solve_opts;
+
+typedef struct rte_solve_info {
+    int32_t iters;               /* outer iterations taken                                   */
+    double rel_resid;            /* final ||r||_2 / ||q||_2 (FP64)                           */
+    double stop_quantity;        /* ||u_n - u_{n-1}||_{E-K} / ||u_1||_{E-K}  (Sec. 6.4)     */
+    int64_t pcg_iters_total;     /* PCG iterations over all E applications                   */
+    int64_t cg_iters_total;      /* sum over directions of E_0 CG iterations                 */
+    int32_t cg_iters_max;        /* largest per-direction CG count in one E_0 application    */
+    double t_solve;              /* seconds spent in rte_solve                               */
+} rte_solve_info;
+
+/* Fill opts with the defaults: quad_level 2, N+ 0, N- 5, CG E_0, no mixed copies. */
+void rte_default_assemble_opts(rte_assemble_opts* opts);
+/* Defaults: l 4, tol 1e-8, max_iter 200, FP64, PCG odd solve, CG E_0, PCG tolerances
+ * 1e-12 (residual) / 1e-10 (inner), pcg_max_iter 200, cg_tol 1e-10, cg_max_iter 20000. */
+void rte_default_solve_opts(rte_solve_opts* opts);
+
+/* Validate the problem and assemble every operator of the mixed system (Sec. 4) on
+ * the device: the spatial P1/P0 matrices, the angular moments, the dense scattering
+ * matrices S+ and S- by double quadrature of the HG kernel, the eigenpairs of
+ * (S+-, M_S+-) (Secs. 5.1, 5.4), the E_0 block data (Sec. 5.3) and the factored
+ * coarse matrix E_c = W^T (E - K+) W (Sec. 5.4).  Blocking.  On success *out owns
+ * all device memory; release it with rte_destroy.  Errors: RTE_E_ARG, RTE_E_PHYS,
+ * RTE_E_MESH before any device work; RTE_E_NOMEM, RTE_E_HIP after. */
+rte_status rte_assemble(const rte_problem_desc* desc, const rte_assemble_opts* opts,
+                        void* hip_stream, rte_handle** out);
+
+/* Dimensions: n_R+ (vertices), n_R- (cells), n_S+ (antipodal pairs), n_S- = 3 n_S+. */
+rte_status rte_query_dims(const rte_handle* h, int32_t* nRp, int32_t* nRm, int32_t* nSp,
+                          int32_t* nSm);
+
+/* Device bytes the handle holds (operators and solver workspace at full size). */
+rte_status rte_footprint(const rte_handle* h, size_t* bytes);
+
+/* Y = K+ X = Ms+ X S+ (parity +1, X and Y n_R+ x n_S+) or Y = K- X = Ms- X S-
+ * (parity -1, n_R- x n_S-); Sec. 4 with the Kronecker identity of Sec. 5.1.
+ * X and Y are device arrays of dtype_in / dtype_out (F64 or F32; BF16 input only
+ * with dtype_out F32 and a handle assembled with mixed != 0).  Enqueue only. */
+rte_status rte_apply_scatter(rte_handle* h, int32_t parity, int32_t dtype_in, const void* X,
+                             int32_t dtype_out, void* Y, void* hip_stream);
+
+/* Y = E X = A^T (M- - K-)^{-1} A X + M+ X + R X (Sec. 4; Alg. 1).  X, Y device FP64
+ * n_R+ x n_S+.  The odd solve follows opts->odd_solver with tolerance
+ * opts->pcg_tol_resid.  Synchronises the stream once per PCG iteration. */
+rte_status rte_apply_E(rte_handle* h, const rte_solve_opts* opts, const double* X, double* Y,
+                       void* hip_stream);
+
+/* Y = E_0^{-1} X, block by block over the directions (Sec. 5.3).  Device FP64. */
+rte_status rte_apply_E0inv(rte_handle* h, const rte_solve_opts* opts, const double* X,
+                           double* Y, void* hip_stream);
+
+/* s = P_1^l r (which = 0, Alg. 2) or s = P_2 P_1^l r (which = 1, product
+ * preconditioner of Sec. 5).  r, s device FP64 n_R+ x n_S+. */
+rte_status rte_precond(rte_handle* h, const rte_solve_opts* opts, int32_t which, const double* r,
+                       double* s, void* hip_stream);
+
+/* Preconditioned Richardson iteration (Sec. 5, Alg. 3) from U0 (device, NULL = 0)
+ * until ||r_n|| <= tol ||q||.  U_even (device FP64 n_R+ x n_S+) receives the iterate.
+ * U_odd must be NULL (reserved).  info may be NULL.  Blocking.  Returns
+ * RTE_E_NOTCONV at the iteration cap (U_even still holds the last iterate) and
+ * RTE_E_NONFINITE if the residual is not finite. */
+rte_status rte_solve(rte_handle* h, const rte_solve_opts* opts, const double* U0, double* U_even,
+                     double* U_odd, rte_solve_info* info, void* hip_stream);
+
+/* Copy an assembled array to host memory, for inspection and tests.
+ * which: 0 S+ [n_S+ x n_S+], 1 S- [n_S- x n_S-], 2 m_k [n_S+], 3 T_k [n_S+ x 9],
+ * 4 q = l+ [n_R+ x n_S+], 5 even eigenvalues [d_N+], 6 even eigenvectors
+ * [n_S+ x d_N+], 7 odd eigenvalues [n_S-].  host_bytes must equal the array size in
+ * bytes (FP64).  Blocking. */
+rte_status rte_get_array(rte_handle* h, int32_t which, void* host_dst, size_t host_bytes);
+
+/* Release the handle (synchronises its stream first).  NULL is accepted. */
+rte_status rte_destroy(rte_handle* h);
+
+/* Thread-local text of the last non-OK status ("" if none). */
+const char* rte_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTE_H */
