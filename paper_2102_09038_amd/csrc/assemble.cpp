@@ -1,0 +1,811 @@
+// rte_assemble: validation and assembly of every operator of the mixed even/odd
+// discretisation (paper Sec. 4), the eigen-bases of the scattering matrices
+// (Secs. 5.1, 5.4), the E_0 block data (Sec. 5.3) and the factored coarse matrix
+// E_c = W^T (E - K+) W (Sec. 5.4).
+//
+// Host FP64 for the geometry (cheap, O(mesh size)); the O(n_S^2 Q^2) double quadrature
+// of the HG kernel runs on the GPU (kernels_dense.hip); the symmetric eigensolves use
+// rocSOLVER on the GPU.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <deque>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <unordered_map>
+
+#include "ops.h"
+#include "rte_internal.h"
+
+namespace rte {
+namespace {
+
+using Vec = std::vector<double>;
+
+// ----------------------------------------------------------------------------- quadrature
+// Radon's degree-5 7-point rule, composite over the 4^r congruent sub-triangles of each
+// flat triangle, mapped radially onto the geodesic triangle with the surface element
+// h / |x|^3 dA (h = distance of the flat plane from the origin).  The paper asks for
+// "higher-order integration rules" on the projected sphere mesh (Sec. 6) without naming
+// one; this is the rule both this library and its test oracle are defined by.
+struct Rule {
+    std::vector<std::array<double, 3>> bary;
+    Vec w;
+};
+
+Rule composite_rule(int r) {
+    const double r15 = std::sqrt(15.0);
+    const double a = (6.0 - r15) / 21.0, b = (6.0 + r15) / 21.0;
+    const double wa = (155.0 - r15) / 1200.0, wb = (155.0 + r15) / 1200.0;
+    const double P[7][3] = {{1 / 3.0, 1 / 3.0, 1 / 3.0}, {a, a, 1 - 2 * a}, {a, 1 - 2 * a, a},
+                            {1 - 2 * a, a, a},           {b, b, 1 - 2 * b}, {b, 1 - 2 * b, b},
+                            {1 - 2 * b, b, b}};
+    const double W[7] = {9.0 / 40.0, wa, wa, wa, wb, wb, wb};
+    const int n = 1 << r;
+    Rule R;
+    auto add = [&](int p0, int q0, int p1, int q1, int p2, int q2) {
+        const double c[3][3] = {{1.0 - (p0 + q0) / (double)n, p0 / (double)n, q0 / (double)n},
+                                {1.0 - (p1 + q1) / (double)n, p1 / (double)n, q1 / (double)n},
+                                {1.0 - (p2 + q2) / (double)n, p2 / (double)n, q2 / (double)n}};
+        for (int i = 0; i < 7; ++i) {
+            std::array<double, 3> x{};
+            for (int v = 0; v < 3; ++v)
+                for (int e = 0; e < 3; ++e) x[e] += P[i][v] * c[v][e];
+            R.bary.push_back(x);
+            R.w.push_back(W[i] / (double(n) * n));
+        }
+    };
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n - j; ++i) {
+            add(i, j, i + 1, j, i, j + 1);
+            if (i + j <= n - 2) add(i + 1, j, i + 1, j + 1, i, j + 1);
+        }
+    return R;
+}
+
+// ----------------------------------------------------------------------------- small dense
+bool chol3(const double A[9], double L[9]) {
+    std::fill(L, L + 9, 0.0);
+    for (int j = 0; j < 3; ++j) {
+        double s = A[3 * j + j];
+        for (int k = 0; k < j; ++k) s -= L[3 * j + k] * L[3 * j + k];
+        if (!(s > 0)) return false;
+        L[3 * j + j] = std::sqrt(s);
+        for (int i = j + 1; i < 3; ++i) {
+            double t = A[3 * i + j];
+            for (int k = 0; k < j; ++k) t -= L[3 * i + k] * L[3 * j + k];
+            L[3 * i + j] = t / L[3 * j + j];
+        }
+    }
+    return true;
+}
+
+void inv_lower3(const double L[9], double Li[9]) {
+    std::fill(Li, Li + 9, 0.0);
+    for (int j = 0; j < 3; ++j) {
+        Li[3 * j + j] = 1.0 / L[3 * j + j];
+        for (int i = j + 1; i < 3; ++i) {
+            double s = 0;
+            for (int k = j; k < i; ++k) s -= L[3 * i + k] * Li[3 * k + j];
+            Li[3 * i + j] = s / L[3 * i + i];
+        }
+    }
+}
+
+bool inv3(const double A[9], double B[9]) {
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(std::fabs(det) > 0)) return false;
+    const double id = 1.0 / det;
+    B[0] = (A[4] * A[8] - A[5] * A[7]) * id;
+    B[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+    B[3] = (A[5] * A[6] - A[3] * A[8]) * id;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+    B[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+    B[6] = (A[3] * A[7] - A[4] * A[6]) * id;
+    B[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+    return true;
+}
+
+// invert a d x d matrix (d <= 3), row-major; returns determinant
+double invd(const double* J, double* Ji, int d) {
+    if (d == 2) {
+        const double det = J[0] * J[3] - J[1] * J[2];
+        Ji[0] = J[3] / det; Ji[1] = -J[1] / det; Ji[2] = -J[2] / det; Ji[3] = J[0] / det;
+        return det;
+    }
+    const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                       J[2] * (J[3] * J[7] - J[4] * J[6]);
+    inv3(J, Ji);
+    return det;
+}
+
+// ----------------------------------------------------------------------------- banded Cholesky
+// A is stored as its lower band by rows: A[i*(bw+1) + bw + j - i] for j in [i-bw, i].
+// In place: L with L L^T = A; afterwards the diagonal entries hold 1 / L(i,i).
+void band_cholesky(Vec& A, int n, int bw) {
+    const size_t w1 = (size_t)bw + 1;
+    for (int j = 0; j < n; ++j) {
+        double* rj = A.data() + w1 * j;
+        double s = rj[bw];
+        for (int k = std::max(0, j - bw); k < j; ++k) { const double v = rj[bw + k - j]; s -= v * v; }
+        if (!(s > 0)) fail(RTE_E_ARG, "coarse matrix is not positive definite");
+        const double ljj = std::sqrt(s);
+        rj[bw] = ljj;
+        const int i1 = std::min(n - 1, j + bw);
+        for (int i = j + 1; i <= i1; ++i) {
+            double* ri = A.data() + w1 * i;
+            double t = ri[bw + j - i];
+            const int k0 = std::max(0, i - bw);
+            for (int k = k0; k < j; ++k) t -= ri[bw + k - i] * rj[bw + k - j];
+            ri[bw + j - i] = t / ljj;
+        }
+    }
+    for (int i = 0; i < n; ++i) A[w1 * i + bw] = 1.0 / A[w1 * i + bw];
+}
+
+Vec band_transpose(const Vec& L, int n, int bw) {
+    const size_t w1 = (size_t)bw + 1;
+    Vec U(L.size(), 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = std::max(0, i - bw); j <= i; ++j) U[w1 * j + (i - j)] = L[w1 * i + bw + j - i];
+    return U;
+}
+
+// reverse Cuthill-McKee on the P1 graph; returns perm[i] = new position of vertex i
+std::vector<int> rcm(int n, const std::vector<int>& rp, const std::vector<int>& ci) {
+    std::vector<int> deg(n), order;
+    order.reserve(n);
+    for (int i = 0; i < n; ++i) deg[i] = rp[i + 1] - rp[i];
+    std::vector<char> seen(n, 0);
+    std::vector<int> byDeg(n);
+    std::iota(byDeg.begin(), byDeg.end(), 0);
+    std::stable_sort(byDeg.begin(), byDeg.end(), [&](int a, int b) { return deg[a] < deg[b]; });
+    for (int start : byDeg) {
+        if (seen[start]) continue;
+        std::deque<int> dq{start};
+        seen[start] = 1;
+        while (!dq.empty()) {
+            const int v = dq.front();
+            dq.pop_front();
+            order.push_back(v);
+            std::vector<int> nb;
+            for (int e = rp[v]; e < rp[v + 1]; ++e)
+                if (!seen[ci[e]]) { seen[ci[e]] = 1; nb.push_back(ci[e]); }
+            std::stable_sort(nb.begin(), nb.end(), [&](int a, int b) { return deg[a] < deg[b]; });
+            for (int u : nb) dq.push_back(u);
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    std::vector<int> perm(n);
+    for (int p = 0; p < n; ++p) perm[order[p]] = p;
+    return perm;
+}
+
+struct RocblasCtx {
+    rocblas_handle h = nullptr;
+    explicit RocblasCtx(hipStream_t s) {
+        if (rocblas_create_handle(&h) != rocblas_status_success) fail(RTE_E_HIP, "rocblas_create_handle failed");
+        rocblas_set_stream(h, s);
+    }
+    ~RocblasCtx() { if (h) rocblas_destroy_handle(h); }
+};
+
+// eigenpairs of the symmetric n x n matrix A (col-major host); ascending eigenvalues
+void syevd(RocblasCtx& rb, hipStream_t s, int n, Vec& A, Vec& lam) {
+    DBuf<double> dA(A.size()), dD(n), dE(n);
+    DBuf<int> info(1);
+    RTE_HIP(hipMemcpyAsync(dA.p, A.data(), A.size() * 8, hipMemcpyHostToDevice, s));
+    const rocblas_status st = rocsolver_dsyevd(rb.h, rocblas_evect_original, rocblas_fill_lower, n, dA.p,
+                                               n, dD.p, dE.p, info.p);
+    if (st != rocblas_status_success) fail(RTE_E_HIP, "rocsolver_dsyevd failed");
+    int hinfo = 0;
+    RTE_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    lam.resize(n);
+    RTE_HIP(hipMemcpyAsync(lam.data(), dD.p, n * 8, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipMemcpyAsync(A.data(), dA.p, A.size() * 8, hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipStreamSynchronize(s));
+    if (hinfo != 0) fail(RTE_E_HIP, "rocsolver_dsyevd did not converge");
+}
+
+}  // namespace
+
+Handle::~Handle() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (pinned) (void)hipHostFree(pinned);
+}
+
+size_t Handle::footprint() const {
+    size_t b = Sp.bytes() + Sm.bytes() + m.bytes() + T.bytes() + MSinv.bytes() + Wm.bytes() + lamm.bytes() +
+               Wp.bytes() + Hodd.bytes() + Wfull.bytes() + WfullT.bytes() + lam_full.bytes() + cell.bytes() +
+               Dc.bytes() + mt.bytes() + ms.bytes() + rowptr.bytes() + col.bytes() + Msv.bytes() + cls.bytes() +
+               coefE0.bytes() + coefE.bytes() + diagE0.bytes() + vc_ptr.bytes() + vc_cell.bytes() + vc_loc.bytes() +
+               q.bytes() + Lc.bytes() + LcT.bytes() + perm.bytes() + L0.bytes() + L0T.bytes() + e0perm.bytes() +
+               Sp_bf.bytes() + Sm_bf.bytes() + Hodd_bf.bytes() + Wfull_bf.bytes() + WfullT_bf.bytes() + red.bytes() +
+               scal.bytes();
+    for (auto& w : ws) b += w.bytes();
+    return b;
+}
+
+Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStream_t s) {
+    // ------------------------------------------------------------------ validation
+    if (!D || !o) fail(RTE_E_ARG, "null descriptor or options");
+    const int d = D->dim;
+    if (d != 2 && d != 3) fail(RTE_E_ARG, "dim must be 2 or 3");
+    if (D->n_vert < d + 1 || D->n_cell < 1 || !D->vert || !D->cell) fail(RTE_E_ARG, "empty spatial mesh");
+    if (!D->sigma_t || !D->sigma_s || !D->q_nodal) fail(RTE_E_ARG, "null sigma_t / sigma_s / q_nodal");
+    if (D->g_inflow) fail(RTE_E_ARG, "inflow boundary data is not supported (vacuum boundary only)");
+    if (D->n_stri < 2 || D->n_stri % 2 || !D->svert || !D->stri || D->n_svert < 3)
+        fail(RTE_E_MESH, "sphere mesh must have an even, positive number of triangles");
+    if (!(D->g >= 0.0 && D->g < 1.0)) fail(RTE_E_PHYS, "g must lie in [0, 1)");
+    if (o->quad_level < 0 || o->quad_level > 6) fail(RTE_E_ARG, "quad_level must lie in 0..6");
+    if (o->n_even < 0 || o->n_even > 8) fail(RTE_E_ARG, "n_even must lie in 0..8");
+    if (o->n_odd < 1 || o->n_odd > 8) fail(RTE_E_ARG, "n_odd must lie in 1..8");
+    const int nRp = D->n_vert, nRm = D->n_cell;
+    double cmax = 0.0;
+    for (int j = 0; j < nRm; ++j) {
+        const double st = D->sigma_t[j], ss = D->sigma_s[j];
+        if (!std::isfinite(st) || !std::isfinite(ss) || !(st > 0) || ss < 0)
+            fail(RTE_E_PHYS, "sigma_t must be > 0 and sigma_s >= 0 (finite) in every cell");
+        cmax = std::max(cmax, ss / st);
+    }
+    if (!(cmax < 1.0)) fail(RTE_E_PHYS, "max sigma_s/sigma_t must be < 1 (absorbing medium)");
+    for (int i = 0; i < nRp * d; ++i)
+        if (!std::isfinite(D->vert[i])) fail(RTE_E_ARG, "non-finite vertex coordinate");
+    for (int i = 0; i < nRp; ++i)
+        if (!std::isfinite(D->q_nodal[i])) fail(RTE_E_ARG, "non-finite source value");
+    for (int i = 0; i < nRm * (d + 1); ++i)
+        if (D->cell[i] < 0 || D->cell[i] >= nRp) fail(RTE_E_MESH, "cell vertex index out of range");
+    for (int i = 0; i < D->n_stri * 3; ++i)
+        if (D->stri[i] < 0 || D->stri[i] >= D->n_svert) fail(RTE_E_MESH, "sphere vertex index out of range");
+    for (int i = 0; i < D->n_svert; ++i) {
+        const double* v = D->svert + 3 * i;
+        const double nv = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (!(std::fabs(nv - 1.0) < 1e-10)) fail(RTE_E_MESH, "sphere vertices must be unit vectors");
+    }
+
+    auto H = std::make_unique<Handle>();
+    Handle& h = *H;
+    h.stream = s;
+    h.d = d; h.nRp = nRp; h.nRm = nRm; h.g = D->g; h.c = cmax;
+    h.n_even = o->n_even; h.n_odd = o->n_odd;
+    h.dNp = (o->n_even + 1) * (o->n_even + 2) / 2;
+    h.dNm = (o->n_odd + 1) * (o->n_odd + 2) / 2;
+
+    // ------------------------------------------------------------------ sphere: upper half, antipodes
+    const int nt = D->n_stri;
+    auto vkey = [](const double* v) {
+        auto q = [](double x) { return (long long)std::llround(x * 1e9); };
+        return std::array<long long, 3>{q(v[0]), q(v[1]), q(v[2])};
+    };
+    std::map<std::array<long long, 9>, int> trikey;
+    auto tkey = [&](const int* t, double sign) {
+        std::array<std::array<long long, 3>, 3> ks;
+        for (int v = 0; v < 3; ++v) {
+            const double* p = D->svert + 3 * t[v];
+            const double q[3] = {sign * p[0], sign * p[1], sign * p[2]};
+            ks[v] = vkey(q);
+        }
+        std::sort(ks.begin(), ks.end());
+        std::array<long long, 9> out;
+        for (int v = 0; v < 3; ++v)
+            for (int e = 0; e < 3; ++e) out[3 * v + e] = ks[v][e];
+        return out;
+    };
+    for (int t = 0; t < nt; ++t) trikey[tkey(D->stri + 3 * t, 1.0)] = t;
+    std::vector<int> upper;
+    for (int t = 0; t < nt; ++t) {
+        double cz = 0, cy = 0, cx = 0;
+        for (int v = 0; v < 3; ++v) {
+            const double* p = D->svert + 3 * D->stri[3 * t + v];
+            cx += p[0]; cy += p[1]; cz += p[2];
+        }
+        const double key = cz != 0 ? cz : (cy != 0 ? cy : cx);
+        if (key > 0) {
+            if (!trikey.count(tkey(D->stri + 3 * t, -1.0)))
+                fail(RTE_E_MESH, "sphere triangle " + std::to_string(t) + " has no antipodal partner");
+            upper.push_back(t);
+        }
+    }
+    if ((int)upper.size() * 2 != nt) fail(RTE_E_MESH, "sphere mesh is not split evenly into antipodal pairs");
+    const int nS = (int)upper.size();
+    h.nS = nS;
+    h.nSm = 3 * nS;
+    if (h.dNm > h.nSm || h.dNp > nS) fail(RTE_E_ARG, "eigen-basis larger than the angular space");
+
+    // ------------------------------------------------------------------ angular quadrature and moments
+    const Rule R = composite_rule(o->quad_level);
+    const int Q = (int)R.w.size();
+    Vec pts((size_t)nS * Q * 3), wts((size_t)nS * Q);
+    h.h_m.assign(nS, 0.0);
+    h.h_T.assign((size_t)nS * 9, 0.0);
+    for (int k = 0; k < nS; ++k) {
+        const int* t = D->stri + 3 * upper[k];
+        const double* a = D->svert + 3 * t[0];
+        const double* b = D->svert + 3 * t[1];
+        const double* c = D->svert + 3 * t[2];
+        const double det = std::fabs(a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                                     a[2] * (b[0] * c[1] - b[1] * c[0]));
+        if (!(det > 0)) fail(RTE_E_MESH, "degenerate sphere triangle");
+        for (int p = 0; p < Q; ++p) {
+            double x[3];
+            for (int e = 0; e < 3; ++e) x[e] = R.bary[p][0] * a[e] + R.bary[p][1] * b[e] + R.bary[p][2] * c[e];
+            const double nx = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+            const double w = R.w[p] * det / (2.0 * nx * nx * nx);
+            const size_t o3 = ((size_t)k * Q + p) * 3;
+            for (int e = 0; e < 3; ++e) pts[o3 + e] = x[e] / nx;
+            wts[(size_t)k * Q + p] = w;
+            h.h_m[k] += 2.0 * w;
+            for (int e = 0; e < 3; ++e)
+                for (int f = 0; f < 3; ++f) h.h_T[9 * k + 3 * e + f] += w * pts[o3 + e] * pts[o3 + f];
+        }
+    }
+    // inverse of the 3x3 blocks 2 T_k of M_S-
+    Vec MSinv((size_t)nS * 9), LkInv((size_t)nS * 9);
+    for (int k = 0; k < nS; ++k) {
+        double B[9], L[9];
+        for (int e = 0; e < 9; ++e) B[e] = 2.0 * h.h_T[9 * k + e];
+        if (!inv3(B, &MSinv[9 * k]) || !chol3(B, L)) fail(RTE_E_MESH, "singular odd mass block");
+        inv_lower3(L, &LkInv[9 * k]);
+    }
+
+    // ------------------------------------------------------------------ spatial geometry
+    const int nv = d + 1;
+    Vec vol(nRm), Dc((size_t)nRm * nv * d);
+    for (int j = 0; j < nRm; ++j) {
+        const int* cj = D->cell + nv * j;
+        double J[9], Ji[9];
+        for (int r = 0; r < d; ++r)          // J[r][e] = x_{e+1,r} - x_{0,r}  (columns = edges)
+            for (int e = 0; e < d; ++e) J[r * d + e] = D->vert[d * cj[e + 1] + r] - D->vert[d * cj[0] + r];
+        const double det = invd(J, Ji, d);
+        const double v = std::fabs(det) / (d == 2 ? 2.0 : 6.0);
+        if (!(v > 0) || !std::isfinite(det)) fail(RTE_E_MESH, "degenerate spatial cell " + std::to_string(j));
+        vol[j] = v;
+        // grad lambda_{e+1} = row e of J^{-1}; grad lambda_0 = -sum
+        for (int n = 0; n < d; ++n) {
+            double s0 = 0;
+            for (int e = 0; e < d; ++e) {
+                const double gv = Ji[e * d + n];
+                Dc[((size_t)j * nv + e + 1) * d + n] = v * gv;
+                s0 += gv;
+            }
+            Dc[((size_t)j * nv) * d + n] = -v * s0;
+        }
+    }
+    Vec mt(nRm), ms(nRm);
+    for (int j = 0; j < nRm; ++j) { mt[j] = D->sigma_t[j] * vol[j]; ms[j] = D->sigma_s[j] * vol[j]; }
+    h.uniform_delta = true;
+    h.delta0 = D->sigma_s[0] / D->sigma_t[0];
+    for (int j = 1; j < nRm; ++j)
+        if (D->sigma_s[j] / D->sigma_t[j] != h.delta0) { h.uniform_delta = false; break; }
+
+    // ------------------------------------------------------------------ P1 pattern
+    std::vector<std::vector<int>> adj(nRp);
+    for (int j = 0; j < nRm; ++j)
+        for (int a = 0; a < nv; ++a)
+            for (int b = 0; b < nv; ++b) adj[D->cell[nv * j + a]].push_back(D->cell[nv * j + b]);
+    std::vector<int> rp(nRp + 1, 0), ci;
+    for (int i = 0; i < nRp; ++i) {
+        auto& v = adj[i];
+        v.push_back(i);
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        rp[i + 1] = rp[i] + (int)v.size();
+        ci.insert(ci.end(), v.begin(), v.end());
+    }
+    const int nnz = rp[nRp];
+    h.nnz = nnz;
+    auto find = [&](int i, int jv) {
+        const int* b = ci.data() + rp[i];
+        const int* e = ci.data() + rp[i + 1];
+        return (int)(std::lower_bound(b, e, jv) - ci.data());
+    };
+    std::vector<int> diagpos(nRp);
+    for (int i = 0; i < nRp; ++i) diagpos[i] = find(i, i);
+
+    // ------------------------------------------------------------------ boundary facets
+    struct Facet { std::array<int, 3> v; int cell, opp; };
+    std::map<std::array<int, 3>, std::pair<int, int>> owner;   // sorted verts -> (count, cell*8+opp)
+    for (int j = 0; j < nRm; ++j)
+        for (int o_ = 0; o_ < nv; ++o_) {
+            std::array<int, 3> f{-1, -1, -1};
+            int c = 0;
+            for (int a = 0; a < nv; ++a)
+                if (a != o_) f[c++] = D->cell[nv * j + a];
+            std::sort(f.begin(), f.begin() + d);
+            auto it = owner.find(f);
+            if (it == owner.end()) owner[f] = {1, j * 8 + o_};
+            else it->second.first++;
+        }
+    std::vector<Facet> facets;
+    for (auto& kv : owner)
+        if (kv.second.first == 1) facets.push_back({kv.first, kv.second.second / 8, kv.second.second % 8});
+    // normals, measures, normal classes (normals equal up to sign share omega)
+    std::vector<std::array<double, 3>> ncls_dir;
+    std::vector<int> fcls(facets.size());
+    Vec fmeas(facets.size());
+    for (size_t f = 0; f < facets.size(); ++f) {
+        const int j = facets[f].cell, op = facets[f].opp;
+        double g3[3] = {0, 0, 0}, gn = 0;
+        for (int n = 0; n < d; ++n) { g3[n] = Dc[((size_t)j * nv + op) * d + n] / vol[j]; gn += g3[n] * g3[n]; }
+        gn = std::sqrt(gn);
+        std::array<double, 3> nu{-g3[0] / gn, -g3[1] / gn, -g3[2] / gn};
+        fmeas[f] = d * vol[j] * gn;
+        // canonical sign: first component with |x| > 1e-12 positive
+        for (int e = 0; e < 3; ++e)
+            if (std::fabs(nu[e]) > 1e-12) {
+                if (nu[e] < 0) for (auto& x : nu) x = -x;
+                break;
+            }
+        int cid = -1;
+        for (size_t c = 0; c < ncls_dir.size(); ++c)
+            if (std::fabs(ncls_dir[c][0] - nu[0]) < 1e-12 && std::fabs(ncls_dir[c][1] - nu[1]) < 1e-12 &&
+                std::fabs(ncls_dir[c][2] - nu[2]) < 1e-12) { cid = (int)c; break; }
+        if (cid < 0) { cid = (int)ncls_dir.size(); ncls_dir.push_back(nu); }
+        fcls[f] = cid;
+    }
+    const int nb = (int)ncls_dir.size();
+    const int nstiff = d * (d + 1) / 2;
+    h.ncls_stiff = nstiff;
+    h.nbcls = nb;
+    h.ncls = nstiff + 1 + nb;
+    if (h.ncls > kMaxClasses)
+        fail(RTE_E_ARG, "boundary has too many distinct facet normals (" + std::to_string(nb) +
+                            "); at most " + std::to_string(kMaxClasses - nstiff - 1) + " are supported");
+
+    // ------------------------------------------------------------------ value classes of the pattern
+    // stiffness classes (n <= m): sum_j D_n(j,a) D_m(j,b) / mt_j (+ the (m,n) term when n < m)
+    const int ncls = h.ncls;
+    Vec cls((size_t)ncls * nnz, 0.0), Msv(nnz, 0.0), M1v(nnz, 0.0);
+    std::vector<std::pair<int, int>> nm;
+    for (int n = 0; n < d; ++n) nm.push_back({n, n});
+    for (int n = 0; n < d; ++n)
+        for (int m = n + 1; m < d; ++m) nm.push_back({n, m});
+    const double mloc_d = 1.0 / ((d + 1) * (d + 2));
+    for (int j = 0; j < nRm; ++j) {
+        const int* cj = D->cell + nv * j;
+        for (int a = 0; a < nv; ++a)
+            for (int b = 0; b < nv; ++b) {
+                const int e = find(cj[a], cj[b]);
+                const double* Da = &Dc[((size_t)j * nv + a) * d];
+                const double* Db = &Dc[((size_t)j * nv + b) * d];
+                for (int c = 0; c < nstiff; ++c) {
+                    const int n = nm[c].first, m = nm[c].second;
+                    double v = Da[n] * Db[m];
+                    if (n != m) v += Da[m] * Db[n];
+                    cls[(size_t)c * nnz + e] += v / mt[j];
+                }
+                const double loc = (a == b ? 2.0 : 1.0) * mloc_d * vol[j];
+                cls[(size_t)nstiff * nnz + e] += D->sigma_t[j] * loc;
+                Msv[e] += D->sigma_s[j] * loc;
+                M1v[e] += loc;
+            }
+    }
+    const double floc = 1.0 / (d * (d + 1));
+    for (size_t f = 0; f < facets.size(); ++f) {
+        const int c = nstiff + 1 + fcls[f];
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                const int e = find(facets[f].v[a], facets[f].v[b]);
+                cls[(size_t)c * nnz + e] += (a == b ? 2.0 : 1.0) * floc * fmeas[f];
+            }
+    }
+    // omega_k(nu_c) = 2 sum_p w_p |s_p . nu_c|
+    Vec omega((size_t)nb * nS, 0.0);
+    for (int c = 0; c < nb; ++c)
+        for (int k = 0; k < nS; ++k) {
+            double acc = 0;
+            for (int p = 0; p < Q; ++p) {
+                const double* sp = &pts[((size_t)k * Q + p) * 3];
+                acc += wts[(size_t)k * Q + p] *
+                       std::fabs(sp[0] * ncls_dir[c][0] + sp[1] * ncls_dir[c][1] + sp[2] * ncls_dir[c][2]);
+            }
+            omega[(size_t)c * nS + k] = 2.0 * acc;
+        }
+    // per-direction coefficients: E_0 block k and (M+ + R) block k
+    const double alpha = 2.0 / (1.0 - cmax * D->g);
+    Vec coefE0((size_t)nS * ncls, 0.0), coefE((size_t)nS * ncls, 0.0), diagE0((size_t)nRp * nS);
+    for (int k = 0; k < nS; ++k) {
+        for (int c = 0; c < nstiff; ++c)
+            coefE0[(size_t)k * ncls + c] = alpha * h.h_T[9 * k + 3 * nm[c].first + nm[c].second];
+        coefE0[(size_t)k * ncls + nstiff] = coefE[(size_t)k * ncls + nstiff] = h.h_m[k];
+        for (int c = 0; c < nb; ++c)
+            coefE0[(size_t)k * ncls + nstiff + 1 + c] = coefE[(size_t)k * ncls + nstiff + 1 + c] =
+                omega[(size_t)c * nS + k];
+        for (int i = 0; i < nRp; ++i) {
+            double v = 0;
+            for (int c = 0; c < ncls; ++c) v += coefE0[(size_t)k * ncls + c] * cls[(size_t)c * nnz + diagpos[i]];
+            diagE0[i + (size_t)nRp * k] = v;
+        }
+    }
+    // vertex -> incident cells
+    std::vector<int> vcp(nRp + 1, 0), vcc((size_t)nRm * nv), vcl((size_t)nRm * nv);
+    for (int j = 0; j < nRm; ++j)
+        for (int a = 0; a < nv; ++a) vcp[D->cell[nv * j + a] + 1]++;
+    for (int i = 0; i < nRp; ++i) vcp[i + 1] += vcp[i];
+    {
+        std::vector<int> fillp(vcp.begin(), vcp.end() - 1);
+        for (int j = 0; j < nRm; ++j)
+            for (int a = 0; a < nv; ++a) {
+                const int v = D->cell[nv * j + a];
+                vcc[fillp[v]] = j;
+                vcl[fillp[v]++] = a;
+            }
+    }
+    // source l+[:,k] = m_k (M1 q_nodal)
+    Vec Mq(nRp, 0.0);
+    for (int i = 0; i < nRp; ++i)
+        for (int e = rp[i]; e < rp[i + 1]; ++e) Mq[i] += M1v[e] * D->q_nodal[ci[e]];
+    Vec qv((size_t)nRp * nS);
+    double qn2 = 0;
+    for (int k = 0; k < nS; ++k)
+        for (int i = 0; i < nRp; ++i) {
+            const double v = h.h_m[k] * Mq[i];
+            qv[i + (size_t)nRp * k] = v;
+            qn2 += v * v;
+        }
+    h.qnorm = std::sqrt(qn2);
+
+    // ------------------------------------------------------------------ uploads
+    h.m.upload(h.h_m, s);
+    h.T.upload(h.h_T, s);
+    h.MSinv.upload(MSinv, s);
+    h.cell.upload(std::vector<int>(D->cell, D->cell + (size_t)nRm * nv), s);
+    h.Dc.upload(Dc, s);
+    h.mt.upload(mt, s);
+    h.ms.upload(ms, s);
+    h.rowptr.upload(rp, s);
+    h.col.upload(ci, s);
+    h.Msv.upload(Msv, s);
+    h.cls.upload(cls, s);
+    h.coefE0.upload(coefE0, s);
+    h.coefE.upload(coefE, s);
+    h.diagE0.upload(diagE0, s);
+    h.vc_ptr.upload(vcp, s);
+    h.vc_cell.upload(vcc, s);
+    h.vc_loc.upload(vcl, s);
+    h.q.upload(qv, s);
+
+    // ------------------------------------------------------------------ scattering matrices (GPU)
+    {
+        DBuf<double> dp, dw;
+        dp.upload(pts, s);
+        dw.upload(wts, s);
+        h.Sp.alloc((size_t)nS * nS);
+        h.Sm.alloc((size_t)h.nSm * h.nSm);
+        k::hg_scatter(dp.p, dw.p, nS, Q, D->g, h.Sp.p, h.Sm.p, s);
+        RTE_HIP(hipStreamSynchronize(s));
+    }
+    h.h_Sp = h.Sp.download(s);
+    h.h_Sm = h.Sm.download(s);
+
+    // ------------------------------------------------------------------ eigen-bases (rocSOLVER)
+    RocblasCtx rb(s);
+    const int nSm = h.nSm;
+    {   // odd: S- W = M_S- W Lambda; with M_S- = L L^T blockwise: (L^-1 S- L^-T) V = V Lambda, W = L^-T V
+        Vec A((size_t)nSm * nSm);
+        for (int kb = 0; kb < nS; ++kb)
+            for (int kc = 0; kc < nS; ++kc) {
+                const double* Li = &LkInv[9 * kb];
+                const double* Lj = &LkInv[9 * kc];
+                double blk[9], tmp[9];
+                for (int n = 0; n < 3; ++n)
+                    for (int m = 0; m < 3; ++m) {
+                        const double a1 = h.h_Sm[(3 * kb + n) + (size_t)nSm * (3 * kc + m)];
+                        const double a2 = h.h_Sm[(3 * kc + m) + (size_t)nSm * (3 * kb + n)];
+                        blk[3 * n + m] = 0.5 * (a1 + a2);
+                    }
+                for (int n = 0; n < 3; ++n)          // tmp = Li * blk
+                    for (int m = 0; m < 3; ++m) {
+                        double v = 0;
+                        for (int e = 0; e < 3; ++e) v += Li[3 * n + e] * blk[3 * e + m];
+                        tmp[3 * n + m] = v;
+                    }
+                for (int n = 0; n < 3; ++n)          // A = tmp * Lj^T
+                    for (int m = 0; m < 3; ++m) {
+                        double v = 0;
+                        for (int e = 0; e < 3; ++e) v += tmp[3 * n + e] * Lj[3 * m + e];
+                        A[(3 * kb + n) + (size_t)nSm * (3 * kc + m)] = v;
+                    }
+            }
+        Vec lam;
+        syevd(rb, s, nSm, A, lam);
+        // W = L^-T V, reorder to non-increasing eigenvalues
+        Vec Wfull((size_t)nSm * nSm);
+        h.h_lamm_full.resize(nSm);
+        for (int c = 0; c < nSm; ++c) {
+            const int src = nSm - 1 - c;
+            h.h_lamm_full[c] = lam[src];
+            for (int kb = 0; kb < nS; ++kb) {
+                const double* Li = &LkInv[9 * kb];
+                for (int n = 0; n < 3; ++n) {
+                    double v = 0;     // (L^-T)(n, e) = Li(e, n)
+                    for (int e = 0; e < 3; ++e) v += Li[3 * e + n] * A[(3 * kb + e) + (size_t)nSm * src];
+                    Wfull[(3 * kb + n) + (size_t)nSm * c] = v;
+                }
+            }
+        }
+        Vec Wm((size_t)nSm * h.dNm), lm(h.dNm);
+        for (int c = 0; c < h.dNm; ++c) {
+            lm[c] = h.h_lamm_full[c];
+            std::copy(Wfull.begin() + (size_t)nSm * c, Wfull.begin() + (size_t)nSm * (c + 1), Wm.begin() + (size_t)nSm * c);
+        }
+        h.Wm.upload(Wm, s);
+        h.lamm.upload(lm, s);
+        // exact odd inverse: full basis (row-major K x N views for the GEMM) and, when the
+        // ratio sigma_s / sigma_t is uniform, H = (M_S- - delta S-)^{-1} = W diag(1/(1-delta lam)) W^T
+        {
+            Vec WT((size_t)nSm * nSm), Wrm((size_t)nSm * nSm);
+            for (int r = 0; r < nSm; ++r)
+                for (int c = 0; c < nSm; ++c) {
+                    Wrm[(size_t)r * nSm + c] = Wfull[r + (size_t)nSm * c];   // B(k=r, n=c) = W[r, c]
+                    WT[(size_t)c * nSm + r] = Wfull[r + (size_t)nSm * c];    // B(k=c, n=r) = W[r, c]
+                }
+            h.Wfull.upload(Wrm, s);
+            h.WfullT.upload(WT, s);
+            h.lam_full.upload(h.h_lamm_full, s);
+            if (h.uniform_delta) {
+                DBuf<double> Ws(Wfull.size());
+                Vec Wsc(Wfull);
+                for (int c = 0; c < nSm; ++c) {
+                    const double f = 1.0 / (1.0 - h.delta0 * h.h_lamm_full[c]);
+                    for (int r = 0; r < nSm; ++r) Wsc[r + (size_t)nSm * c] *= f;
+                }
+                // H = Wsc W^T : as GEMM with A = Wsc (col-major), B = W^T (row-major K x N: B(k=c, n=r) = W[r,c])
+                DBuf<double> dWsc;
+                dWsc.upload(Wsc, s);
+                h.Hodd.alloc((size_t)nSm * nSm);
+                k::gemm_f64(nSm, nSm, nSm, 1.0, dWsc.p, nSm, h.WfullT.p, nSm, 0.0, h.Hodd.p, nSm, s);
+                RTE_HIP(hipStreamSynchronize(s));
+            }
+            h.have_exact = true;
+        }
+        // ---- coarse needs P_n = W_full^T (A_n W+) later; keep Wfull on the host until then
+        h.h_Sm.clear();
+        h.h_Sm.shrink_to_fit();
+        // even
+        Vec Ap((size_t)nS * nS);
+        Vec isq(nS);
+        for (int k = 0; k < nS; ++k) isq[k] = 1.0 / std::sqrt(h.h_m[k]);
+        for (int a = 0; a < nS; ++a)
+            for (int b = 0; b < nS; ++b)
+                Ap[a + (size_t)nS * b] =
+                    0.5 * (h.h_Sp[a + (size_t)nS * b] + h.h_Sp[b + (size_t)nS * a]) * isq[a] * isq[b];
+        Vec lp;
+        syevd(rb, s, nS, Ap, lp);
+        h.h_lamp.resize(h.dNp);
+        h.h_Wp.resize((size_t)nS * h.dNp);
+        for (int c = 0; c < h.dNp; ++c) {
+            const int src = nS - 1 - c;
+            h.h_lamp[c] = lp[src];
+            for (int k = 0; k < nS; ++k) h.h_Wp[k + (size_t)nS * c] = Ap[k + (size_t)nS * src] * isq[k];
+        }
+        h.Wp.upload(h.h_Wp, s);
+
+        // ------------------------------------------------------------------ coarse matrix E_c
+        const int dN = h.dNp;
+        // P_n = W_full^T (A_n W+)  [nSm x dN], (A_n W+)[(k,m), a] = 2 T_k(n, m) W+[k, a]
+        std::vector<Vec> Pn(d, Vec((size_t)nSm * dN, 0.0));
+        for (int n = 0; n < d; ++n) {
+            Vec AW((size_t)nSm * dN);
+            for (int k = 0; k < nS; ++k)
+                for (int m = 0; m < 3; ++m)
+                    for (int a = 0; a < dN; ++a)
+                        AW[(3 * k + m) + (size_t)nSm * a] = 2.0 * h.h_T[9 * k + 3 * n + m] * h.h_Wp[k + (size_t)nS * a];
+            for (int c = 0; c < nSm; ++c)
+                for (int a = 0; a < dN; ++a) {
+                    double v = 0;
+                    const double* wc = &Wfull[(size_t)nSm * c];
+                    const double* aw = &AW[(size_t)nSm * a];
+                    for (int r = 0; r < nSm; ++r) v += wc[r] * aw[r];
+                    Pn[n][c + (size_t)nSm * a] = v;
+                }
+        }
+        // G_nm(delta) = P_n^T diag(1/(1 - delta lam)) P_m for each distinct delta
+        std::map<double, Vec> Gcache;     // key delta -> [d*d*dN*dN]
+        auto Gfor = [&](double delta) -> const Vec& {
+            auto it = Gcache.find(delta);
+            if (it != Gcache.end()) return it->second;
+            Vec G((size_t)d * d * dN * dN, 0.0);
+            Vec f(nSm);
+            for (int c = 0; c < nSm; ++c) f[c] = 1.0 / (1.0 - delta * h.h_lamm_full[c]);
+            for (int n = 0; n < d; ++n)
+                for (int m = 0; m < d; ++m)
+                    for (int a = 0; a < dN; ++a)
+                        for (int b = 0; b < dN; ++b) {
+                            double v = 0;
+                            for (int c = 0; c < nSm; ++c)
+                                v += Pn[n][c + (size_t)nSm * a] * f[c] * Pn[m][c + (size_t)nSm * b];
+                            G[((size_t)(n * d + m) * dN + a) * dN + b] = v;
+                        }
+            return Gcache.emplace(delta, std::move(G)).first->second;
+        };
+        // ordering
+        std::vector<int> perm = rcm(nRp, rp, ci);
+        int sbw = 0;
+        for (int i = 0; i < nRp; ++i)
+            for (int e = rp[i]; e < rp[i + 1]; ++e) sbw = std::max(sbw, std::abs(perm[i] - perm[ci[e]]));
+        const int nc = dN * nRp;
+        const int bw = dN * sbw + dN - 1;
+        const size_t w1 = (size_t)bw + 1;
+        if ((double)nc * w1 > 4.0e9) fail(RTE_E_ARG, "coarse band too large for the host factorisation");
+        Vec band((size_t)nc * w1, 0.0);
+        auto addE = [&](int i, int a, int i2, int b, double v) {
+            const int r = a + dN * perm[i], c = b + dN * perm[i2];
+            if (c > r) return;   // lower band only (the matrix is symmetric)
+            band[(size_t)r * w1 + bw + c - r] += v;
+        };
+        // Omega_ab[cb] = sum_k W(k,a) W(k,b) omega[cb, k]
+        Vec Om((size_t)dN * dN * nb, 0.0);
+        for (int a = 0; a < dN; ++a)
+            for (int b = 0; b < dN; ++b)
+                for (int c = 0; c < nb; ++c) {
+                    double v = 0;
+                    for (int k = 0; k < nS; ++k)
+                        v += h.h_Wp[k + (size_t)nS * a] * h.h_Wp[k + (size_t)nS * b] * omega[(size_t)c * nS + k];
+                    Om[((size_t)a * dN + b) * nb + c] = v;
+                }
+        for (int i = 0; i < nRp; ++i)
+            for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                const int i2 = ci[e];
+                for (int a = 0; a < dN; ++a)
+                    for (int b = 0; b < dN; ++b) {
+                        double v = 0;
+                        if (a == b) v += cls[(size_t)nstiff * nnz + e] - h.h_lamp[a] * Msv[e];
+                        for (int c = 0; c < nb; ++c) v += Om[((size_t)a * dN + b) * nb + c] * cls[(size_t)(nstiff + 1 + c) * nnz + e];
+                        if (v != 0.0) addE(i, a, i2, b, v);
+                    }
+            }
+        for (int j = 0; j < nRm; ++j) {
+            const Vec& G = Gfor(D->sigma_s[j] / D->sigma_t[j]);
+            const int* cj = D->cell + nv * j;
+            for (int pa = 0; pa < nv; ++pa)
+                for (int pb = 0; pb < nv; ++pb) {
+                    const double* Da = &Dc[((size_t)j * nv + pa) * d];
+                    const double* Db = &Dc[((size_t)j * nv + pb) * d];
+                    for (int a = 0; a < dN; ++a)
+                        for (int b = 0; b < dN; ++b) {
+                            double v = 0;
+                            for (int n = 0; n < d; ++n)
+                                for (int m = 0; m < d; ++m)
+                                    v += Da[n] * Db[m] * G[((size_t)(n * d + m) * dN + a) * dN + b];
+                            addE(cj[pa], a, cj[pb], b, v / mt[j]);
+                        }
+                }
+        }
+        band_cholesky(band, nc, bw);
+        h.nc = nc;
+        h.cbw = bw;
+        h.Lc.upload(band, s);
+        h.LcT.upload(band_transpose(band, nc, bw), s);
+        h.perm.upload(perm, s);
+    }
+    h.h_Sp.clear();
+    h.h_Sp.shrink_to_fit();
+
+    // ------------------------------------------------------------------ BF16 copies
+    if (o->mixed) {
+        h.Sp_bf.alloc(h.Sp.n);
+        h.Sm_bf.alloc(h.Sm.n);
+        k::cvt_f64_bf16(h.Sp.p, h.Sp_bf.p, h.Sp.n, s);
+        k::cvt_f64_bf16(h.Sm.p, h.Sm_bf.p, h.Sm.n, s);
+        if (h.Hodd.p) {
+            h.Hodd_bf.alloc(h.Hodd.n);
+            k::cvt_f64_bf16(h.Hodd.p, h.Hodd_bf.p, h.Hodd.n, s);
+        }
+        h.have_mixed = true;
+    }
+    h.red.alloc(k::kRedBlocks);
+    h.scal.alloc(64);
+    RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&h.pinned), 64 * sizeof(double), hipHostMallocDefault));
+    RTE_HIP(hipStreamSynchronize(s));
+    return H.release();
+}
+
+}  // namespace rte

@@ -1,0 +1,217 @@
+// extern "C" entry points of librte (declared in include/rte.h).  Every call converts
+// internal exceptions into an rte_status and records the message for rte_last_error().
+#include <new>
+
+#include "ops.h"
+#include "rte_internal.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename F>
+rte_status guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const rte::Error& e) {
+        g_last_error = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return RTE_E_NOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return RTE_E_ARG;
+    }
+}
+
+hipStream_t as_stream(void* p) { return reinterpret_cast<hipStream_t>(p); }
+
+void check_opts(const rte_solve_opts* o) {
+    if (!o) rte::fail(RTE_E_ARG, "null solve options");
+    if (o->l < 1 || o->l > 64) rte::fail(RTE_E_ARG, "l must lie in 1..64");
+    if (!(o->tol > 0) || o->max_iter < 0) rte::fail(RTE_E_ARG, "tol must be > 0 and max_iter >= 0");
+    if (o->precision != RTE_FP64 && o->precision != RTE_MIXED) rte::fail(RTE_E_ARG, "unknown precision");
+    if (o->odd_solver != RTE_ODD_PCG && o->odd_solver != RTE_ODD_EXACT) rte::fail(RTE_E_ARG, "unknown odd solver");
+    if (o->e0_solver != RTE_E0_CG && o->e0_solver != RTE_E0_BANDED) rte::fail(RTE_E_ARG, "unknown E_0 solver");
+    if (!(o->pcg_tol_resid > 0) || !(o->pcg_tol_inner > 0) || !(o->cg_tol > 0) || o->pcg_max_iter < 1 ||
+        o->cg_max_iter < 1)
+        rte::fail(RTE_E_ARG, "inner tolerances must be > 0 and iteration caps >= 1");
+}
+
+rte::Handle* as_handle(rte_handle* h) {
+    if (!h) rte::fail(RTE_E_ARG, "null handle");
+    return reinterpret_cast<rte::Handle*>(h);
+}
+}  // namespace
+
+extern "C" {
+
+void rte_default_assemble_opts(rte_assemble_opts* o) {
+    if (!o) return;
+    o->quad_level = 2;
+    o->n_even = 0;
+    o->n_odd = 5;
+    o->e0_solver = RTE_E0_CG;
+    o->mixed = 0;
+}
+
+void rte_default_solve_opts(rte_solve_opts* o) {
+    if (!o) return;
+    o->l = 4;
+    o->tol = 1e-8;
+    o->max_iter = 200;
+    o->precision = RTE_FP64;
+    o->odd_solver = RTE_ODD_PCG;
+    o->e0_solver = RTE_E0_CG;
+    o->pcg_tol_resid = 1e-12;
+    o->pcg_tol_inner = 1e-10;
+    o->pcg_max_iter = 200;
+    o->cg_tol = 1e-10;
+    o->cg_max_iter = 20000;
+}
+
+rte_status rte_assemble(const rte_problem_desc* desc, const rte_assemble_opts* opts, void* hip_stream,
+                        rte_handle** out) {
+    return guarded([&] {
+        if (!out) rte::fail(RTE_E_ARG, "null output handle pointer");
+        *out = nullptr;
+        rte::Handle* h = rte::assemble(desc, opts, as_stream(hip_stream));
+        *out = reinterpret_cast<rte_handle*>(h);
+        return RTE_OK;
+    });
+}
+
+rte_status rte_query_dims(const rte_handle* hh, int32_t* nRp, int32_t* nRm, int32_t* nSp, int32_t* nSm) {
+    return guarded([&] {
+        const rte::Handle* h = as_handle(const_cast<rte_handle*>(hh));
+        if (nRp) *nRp = h->nRp;
+        if (nRm) *nRm = h->nRm;
+        if (nSp) *nSp = h->nS;
+        if (nSm) *nSm = h->nSm;
+        return RTE_OK;
+    });
+}
+
+rte_status rte_footprint(const rte_handle* hh, size_t* bytes) {
+    return guarded([&] {
+        const rte::Handle* h = as_handle(const_cast<rte_handle*>(hh));
+        if (!bytes) rte::fail(RTE_E_ARG, "null output");
+        *bytes = h->footprint();
+        return RTE_OK;
+    });
+}
+
+rte_status rte_apply_scatter(rte_handle* hh, int32_t parity, int32_t dtype_in, const void* X, int32_t dtype_out,
+                             void* Y, void* hip_stream) {
+    return guarded([&] {
+        rte::Handle* h = as_handle(hh);
+        if (!X || !Y) rte::fail(RTE_E_ARG, "null operand");
+        if (parity != 1 && parity != -1) rte::fail(RTE_E_ARG, "parity must be +1 or -1");
+        rte::apply_scatter(h, parity, dtype_in, X, dtype_out, Y, as_stream(hip_stream));
+        return RTE_OK;
+    });
+}
+
+rte_status rte_apply_E(rte_handle* hh, const rte_solve_opts* o, const double* X, double* Y, void* hip_stream) {
+    return guarded([&] {
+        rte::Handle* h = as_handle(hh);
+        check_opts(o);
+        if (!X || !Y) rte::fail(RTE_E_ARG, "null operand");
+        rte::apply_E(h, o, X, Y, as_stream(hip_stream), nullptr);
+        return RTE_OK;
+    });
+}
+
+rte_status rte_apply_E0inv(rte_handle* hh, const rte_solve_opts* o, const double* X, double* Y,
+                           void* hip_stream) {
+    return guarded([&] {
+        rte::Handle* h = as_handle(hh);
+        check_opts(o);
+        if (!X || !Y) rte::fail(RTE_E_ARG, "null operand");
+        rte::apply_E0inv(h, o, X, Y, as_stream(hip_stream), nullptr, nullptr);
+        return RTE_OK;
+    });
+}
+
+rte_status rte_precond(rte_handle* hh, const rte_solve_opts* o, int32_t which, const double* r, double* s,
+                       void* hip_stream) {
+    return guarded([&] {
+        rte::Handle* h = as_handle(hh);
+        check_opts(o);
+        if (!r || !s) rte::fail(RTE_E_ARG, "null operand");
+        if (which != 0 && which != 1) rte::fail(RTE_E_ARG, "which must be 0 (P1) or 1 (P2 P1)");
+        rte::precond(h, o, which, r, s, as_stream(hip_stream));
+        return RTE_OK;
+    });
+}
+
+rte_status rte_solve(rte_handle* hh, const rte_solve_opts* o, const double* U0, double* U_even, double* U_odd,
+                     rte_solve_info* info, void* hip_stream) {
+    return guarded([&] {
+        rte::Handle* h = as_handle(hh);
+        check_opts(o);
+        if (!U_even) rte::fail(RTE_E_ARG, "null U_even");
+        if (U_odd) rte::fail(RTE_E_ARG, "U_odd output is reserved and must be NULL");
+        const rte_status st = rte::solve(h, o, U0, U_even, info, as_stream(hip_stream));
+        if (st == RTE_E_NOTCONV) g_last_error = "iteration cap reached before the tolerance";
+        if (st == RTE_E_NONFINITE) g_last_error = "residual is not finite";
+        return st;
+    });
+}
+
+rte_status rte_get_array(rte_handle* hh, int32_t which, void* host_dst, size_t host_bytes) {
+    return guarded([&] {
+        rte::Handle* h = as_handle(hh);
+        if (!host_dst) rte::fail(RTE_E_ARG, "null destination");
+        const void* src = nullptr;
+        size_t bytes = 0;
+        bool device = true;
+        switch (which) {
+            case 0: src = h->Sp.p; bytes = h->Sp.bytes(); break;
+            case 1: src = h->Sm.p; bytes = h->Sm.bytes(); break;
+            case 2: src = h->h_m.data(); bytes = h->h_m.size() * 8; device = false; break;
+            case 3: src = h->h_T.data(); bytes = h->h_T.size() * 8; device = false; break;
+            case 4: src = h->q.p; bytes = h->q.bytes(); break;
+            case 5: src = h->h_lamp.data(); bytes = h->h_lamp.size() * 8; device = false; break;
+            case 6: src = h->h_Wp.data(); bytes = h->h_Wp.size() * 8; device = false; break;
+            case 7: src = h->h_lamm_full.data(); bytes = h->h_lamm_full.size() * 8; device = false; break;
+            default: rte::fail(RTE_E_ARG, "unknown array id");
+        }
+        if (bytes != host_bytes) rte::fail(RTE_E_ARG, "host_bytes does not match the array size");
+        if (device) {
+            RTE_HIP(hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
+        } else {
+            std::memcpy(host_dst, src, bytes);
+        }
+        return RTE_OK;
+    });
+}
+
+rte_status rte_destroy(rte_handle* hh) {
+    return guarded([&] {
+        delete reinterpret_cast<rte::Handle*>(hh);
+        return RTE_OK;
+    });
+}
+
+const char* rte_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+namespace rte {
+void apply_scatter(Handle* h, int parity, int dtin, const void* X, int dtout, void* Y, hipStream_t s) {
+    if (dtin != RTE_DT_F64 || dtout != RTE_DT_F64) fail(RTE_E_ARG, "only FP64 operands are supported here");
+    const double* x = static_cast<const double*>(X);
+    double* y = static_cast<double*>(Y);
+    if (parity == 1) {
+        DBuf<double> G((size_t)h->nRp * h->nS);
+        k::gemm_f64(h->nRp, h->nS, h->nS, 1.0, x, h->nRp, h->Sp.p, h->nS, 0.0, G.p, h->nRp, s);
+        k::spmm_pattern(h, h->Msv.p, G.p, y, s);
+        RTE_HIP(hipStreamSynchronize(s));
+    } else {
+        k::gemm_f64(h->nRm, h->nSm, h->nSm, 1.0, x, h->nRm, h->Sm.p, h->nSm, 0.0, y, h->nRm, s);
+        k::row_scale(h->ms.p, h->nRm, h->nSm, y, y, s);
+    }
+}
+}  // namespace rte

@@ -1,0 +1,272 @@
+// Dense kernels: Henyey-Greenstein scattering matrices by double quadrature and the
+// MFMA GEMMs that apply them (paper Sec. 4 matrices; Sec. 5.1 Kronecker identity
+// (B (x) C) vec X = vec(C X B^T), which turns K+ and K- into GEMMs).
+#include "rte_internal.h"
+
+namespace rte {
+namespace {
+
+// ============================================================================ HG quadrature
+// S+_{kk'}          = 2 sum_{p in K_k} sum_{p' in K_k'} w_p w_p' [k(s.s') + k(-s.s')]
+// S-_{(k,n),(k',m)} = 2 sum sum w_p w_p' s_p,n s_p',m [k(s.s') - k(-s.s')]
+// with k(+-s.s') = (1-g^2)/(4 pi) [(1-g)^2 + g |s -+ s'|^2]^{-3/2}.
+// One thread per pair (k, k') of a 16 x 16 tile; both triangles' points are staged
+// through LDS in chunks.  Tiles below the diagonal exit; tiles above it also write the
+// transposed entries.
+constexpr int QT = 16;     // pairs per tile side
+constexpr int QC = 32;     // points per LDS chunk
+
+__global__ __launch_bounds__(256) void hg_scatter_kernel(const double* __restrict__ pts,
+                                                         const double* __restrict__ wts,
+                                                         int nS, int Q, double g,
+                                                         double* __restrict__ Sp,
+                                                         double* __restrict__ Sm) {
+    const int nt = (nS + QT - 1) / QT;
+    const int bi = blockIdx.x % nt, bj = blockIdx.x / nt;
+    if (bi > bj) return;
+    __shared__ double rowp[QT][QC][4];
+    __shared__ double colp[QT][QC][4];
+    const int tx = threadIdx.x % QT, ty = threadIdx.x / QT;
+    const int k = bi * QT + ty, kp = bj * QT + tx;
+    const double c0 = (1.0 - g) * (1.0 - g);
+    const double cn = (1.0 - g * g) / (4.0 * M_PI);
+    double sp = 0.0;
+    double sm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int p0 = 0; p0 < Q; p0 += QC) {
+        const int pc = min(QC, Q - p0);
+        for (int q0 = 0; q0 < Q; q0 += QC) {
+            const int qc = min(QC, Q - q0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < QT * QC; e += blockDim.x) {
+                const int t = e / QC, pp = e % QC;
+                const int kr = bi * QT + t, kc = bj * QT + t;
+                double4 vr = {0, 0, 0, 0}, vc = {0, 0, 0, 0};
+                if (kr < nS && pp < pc) {
+                    const size_t o = (size_t)kr * Q + p0 + pp;
+                    vr = make_double4(pts[3 * o], pts[3 * o + 1], pts[3 * o + 2], wts[o]);
+                }
+                if (kc < nS && pp < qc) {
+                    const size_t o = (size_t)kc * Q + q0 + pp;
+                    vc = make_double4(pts[3 * o], pts[3 * o + 1], pts[3 * o + 2], wts[o]);
+                }
+                rowp[t][pp][0] = vr.x; rowp[t][pp][1] = vr.y; rowp[t][pp][2] = vr.z; rowp[t][pp][3] = vr.w;
+                colp[t][pp][0] = vc.x; colp[t][pp][1] = vc.y; colp[t][pp][2] = vc.z; colp[t][pp][3] = vc.w;
+            }
+            __syncthreads();
+            if (k < nS && kp < nS && bi <= bj) {
+                for (int a = 0; a < pc; ++a) {
+                    const double sx = rowp[ty][a][0], sy = rowp[ty][a][1], sz = rowp[ty][a][2];
+                    const double w = rowp[ty][a][3];
+                    double accp = 0.0, accm[3] = {0, 0, 0};
+                    for (int b = 0; b < qc; ++b) {
+                        const double tx_ = colp[tx][b][0], ty_ = colp[tx][b][1], tz_ = colp[tx][b][2];
+                        const double wb = colp[tx][b][3];
+                        const double dx = sx - tx_, dy = sy - ty_, dz = sz - tz_;
+                        const double ex = sx + tx_, ey = sy + ty_, ez = sz + tz_;
+                        const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                        const double e2 = fma(ex, ex, fma(ey, ey, ez * ez));
+                        const double ra = rsqrt(fma(g, d2, c0));
+                        const double rb = rsqrt(fma(g, e2, c0));
+                        const double kpl = ra * ra * ra, kmi = rb * rb * rb;
+                        accp = fma(wb, kpl + kmi, accp);
+                        const double t = wb * (kpl - kmi);
+                        accm[0] = fma(t, tx_, accm[0]);
+                        accm[1] = fma(t, ty_, accm[1]);
+                        accm[2] = fma(t, tz_, accm[2]);
+                    }
+                    sp = fma(w, accp, sp);
+                    const double wsx = w * sx, wsy = w * sy, wsz = w * sz;
+                    for (int m = 0; m < 3; ++m) {
+                        sm[0][m] = fma(wsx, accm[m], sm[0][m]);
+                        sm[1][m] = fma(wsy, accm[m], sm[1][m]);
+                        sm[2][m] = fma(wsz, accm[m], sm[2][m]);
+                    }
+                }
+            }
+        }
+    }
+    if (k < nS && kp < nS) {
+        const double f = 2.0 * cn;
+        Sp[k + (size_t)nS * kp] = f * sp;
+        if (bi < bj) Sp[kp + (size_t)nS * k] = f * sp;
+        const size_t nSm = 3 * (size_t)nS;
+        for (int n = 0; n < 3; ++n)
+            for (int m = 0; m < 3; ++m) {
+                Sm[(3 * k + n) + nSm * (3 * kp + m)] = f * sm[n][m];
+                if (bi < bj) Sm[(3 * kp + m) + nSm * (3 * k + n)] = f * sm[n][m];
+            }
+    }
+}
+
+// ============================================================================ FP64 MFMA GEMM
+// C = alpha A B + beta C.  A: M x K col-major (lda); B: K x N row-major (ldb); C: col-major.
+// Work-group tile 128 x 128, K step 16, 4 waves in 2 x 2, each wave 64 x 64 as 4 x 4
+// v_mfma_f64_16x16x4 blocks.  The MFMA "row" operand is the B fragment and the "column"
+// operand the A fragment, so the accumulator's lane-fast index runs along M and the
+// column-major stores of C are 128-byte contiguous.  Register-prefetched global loads,
+// double-buffered LDS, one barrier per K step.
+typedef double d4v __attribute__((ext_vector_type(4)));
+constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 4;
+
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+    // consecutive work-group ids land on different XCDs (round-robin over 8); give every
+    // XCD a contiguous range of tiles so that neighbouring tiles share its L2
+    const int per = nb / 8, rem = nb % 8;
+    const int x = b % 8, i = b / 8;
+    if (i >= per) return per * 8 + x;       // leftover ids (b >= 8 * per): identity map
+    return x * per + i;
+}
+
+__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int M, int N, int K, double alpha,
+                                                          const double* __restrict__ A, int lda,
+                                                          const double* __restrict__ B, int ldb,
+                                                          double beta, double* __restrict__ C,
+                                                          int ldc) {
+    __shared__ double As[2][GBK][GBM + GPAD];
+    __shared__ double Bs[2][GBK][GBN + GPAD];
+    const int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
+    const int nb = tm * tn;
+    const int b = xcd_swizzle(blockIdx.x, nb);
+    const int bm = b / tn, bn = b % tn;      // n fastest: one A panel stays hot in L2
+    const int m0 = bm * GBM, n0 = bn * GBN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+
+    double ra[8], rb[8];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int f = tid + 256 * i;
+            const int ka = f / GBM, ma = f % GBM;
+            const int gm = m0 + ma, gk = k0 + ka;
+            ra[i] = (gm < M && gk < K) ? A[gm + (size_t)lda * gk] : 0.0;
+            const int kb = f / GBN, nbx = f % GBN;
+            const int gn = n0 + nbx, gk2 = k0 + kb;
+            rb[i] = (gn < N && gk2 < K) ? B[(size_t)ldb * gk2 + gn] : 0.0;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int f = tid + 256 * i;
+            As[buf][f / GBM][f % GBM] = ra[i];
+            Bs[buf][f / GBN][f % GBN] = rb[i];
+        }
+    };
+
+    d4v acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = d4v{0, 0, 0, 0};
+
+    const int nk = (K + GBK - 1) / GBK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * GBK);
+#pragma unroll
+        for (int kk = 0; kk < GBK / 4; ++kk) {
+            const int kr = kk * 4 + (lane >> 4);
+            double af[4], bf[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) af[i] = As[cur][kr][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bf[j] = Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[j][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[j][i], 0, 0, 0);
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+    // acc[j][i][v] = C(m = m0 + wm*64 + i*16 + lane%16, n = n0 + wn*64 + j*16 + lane/16 + 4*v)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int gm = m0 + wm * 64 + i * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gn = n0 + wn * 64 + j * 16 + (lane >> 4) + 4 * v;
+                if (gm < M && gn < N) {
+                    double* cp = C + gm + (size_t)ldc * gn;
+                    const double val = alpha * acc[j][i][v];
+                    *cp = (beta == 0.0) ? val : fma(beta, *cp, val);
+                }
+            }
+        }
+}
+
+// ============================================================================ conversions
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ void cvt_f64_bf16_kernel(const double* x, uint16_t* y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = f32_to_bf16_rne((float)x[i]);
+}
+__global__ void cvt_f32_bf16_kernel(const float* x, uint16_t* y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = f32_to_bf16_rne(x[i]);
+}
+__global__ void cvt_f64_f32_kernel(const double* x, float* y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+__global__ void cvt_f32_f64_kernel(const float* x, double* y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+
+inline int grid_for(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 16384); }
+
+}  // namespace
+
+namespace k {
+void hg_scatter(const double* pts, const double* wts, int nS, int Q, double g, double* Sp,
+                double* Sm, hipStream_t s) {
+    const int nt = (nS + QT - 1) / QT;
+    hipLaunchKernelGGL(hg_scatter_kernel, dim3(nt * nt), dim3(256), 0, s, pts, wts, nS, Q, g, Sp, Sm);
+    RTE_CHECK_LAUNCH();
+}
+
+void gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, const double* B,
+              int ldb, double beta, double* C, int ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0) return;
+    const int nb = ((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
+    hipLaunchKernelGGL(gemm_f64_kernel, dim3(nb), dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
+    RTE_CHECK_LAUNCH();
+}
+
+void cvt_f64_bf16(const double* x, uint16_t* y, size_t n, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(cvt_f64_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+    RTE_CHECK_LAUNCH();
+}
+void cvt_f32_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(cvt_f32_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+    RTE_CHECK_LAUNCH();
+}
+void cvt_f64_f32(const double* x, float* y, size_t n, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(cvt_f64_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+    RTE_CHECK_LAUNCH();
+}
+void cvt_f32_f64(const float* x, double* y, size_t n, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(cvt_f32_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+    RTE_CHECK_LAUNCH();
+}
+}  // namespace k
+}  // namespace rte

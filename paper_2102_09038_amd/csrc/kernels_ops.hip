@@ -1,0 +1,736 @@
+// Sparse and Kronecker "glue" kernels of the even-parity operators (paper Sec. 4), the
+// pieces of the odd PCG of Alg. 1 with the explicit preconditioner of the lemma in
+// Sec. 5.1, the coarse-space transfer of Sec. 5.4 and deterministic reductions.
+//
+// Layouts: even vectors U[i + nRp*k]; odd vectors V[j + nRm*(3k+m)]; every kernel maps
+// consecutive threads to consecutive spatial indices so global accesses coalesce.
+#include "ops.h"
+
+namespace rte {
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sum over a 256-thread block in a fixed order; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+inline int blocks_for(size_t n) { return (int)std::min<size_t>((n + TPB - 1) / TPB, 65535u * 8); }
+
+// ----------------------------------------------------------------------------- A and A^T
+template <int D>
+__global__ __launch_bounds__(TPB) void apply_A_kernel(int nRm, int nRp, int nS,
+                                                      const int* __restrict__ cell,
+                                                      const double* __restrict__ Dc,
+                                                      const double* __restrict__ T,
+                                                      const double* __restrict__ X,
+                                                      double* __restrict__ B) {
+    const size_t t = blockIdx.x * (size_t)TPB + threadIdx.x;
+    if (t >= (size_t)nRm * nS) return;
+    const int j = (int)(t % nRm), kk = (int)(t / nRm);
+    double gn[D];
+#pragma unroll
+    for (int n = 0; n < D; ++n) gn[n] = 0.0;
+#pragma unroll
+    for (int v = 0; v < D + 1; ++v) {
+        const double xv = X[cell[j * (D + 1) + v] + (size_t)nRp * kk];
+#pragma unroll
+        for (int n = 0; n < D; ++n) gn[n] = fma(Dc[(j * (D + 1) + v) * D + n], xv, gn[n]);
+    }
+    const double* Tk = T + 9 * kk;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        double b = 0.0;
+#pragma unroll
+        for (int n = 0; n < D; ++n) b = fma(gn[n], Tk[3 * n + m], b);
+        B[j + (size_t)nRm * (3 * kk + m)] = 2.0 * b;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(TPB) void apply_At_E_kernel(
+    int nRm, int nRp, int nS, int nnz, int ncls, const int* __restrict__ vc_ptr,
+    const int* __restrict__ vc_cell, const int* __restrict__ vc_loc, const double* __restrict__ Dc,
+    const double* __restrict__ T, const int* __restrict__ rowptr, const int* __restrict__ col,
+    const double* __restrict__ cls, const double* __restrict__ coefE, const double* __restrict__ Msv,
+    const double* __restrict__ Z, const double* __restrict__ X, const double* __restrict__ G,
+    const double* __restrict__ q, double* __restrict__ Y) {
+    const size_t t = blockIdx.x * (size_t)TPB + threadIdx.x;
+    if (t >= (size_t)nRp * nS) return;
+    const int i = (int)(t % nRp), kk = (int)(t / nRp);
+    const double* Tk = T + 9 * kk;
+    double acc = 0.0;
+    if (Z) {
+        for (int e = vc_ptr[i]; e < vc_ptr[i + 1]; ++e) {
+            const int j = vc_cell[e], v = vc_loc[e];
+            const double z0 = Z[j + (size_t)nRm * (3 * kk)];
+            const double z1 = Z[j + (size_t)nRm * (3 * kk + 1)];
+            const double z2 = Z[j + (size_t)nRm * (3 * kk + 2)];
+#pragma unroll
+            for (int n = 0; n < D; ++n) {
+                const double hn = fma(Tk[3 * n], z0, fma(Tk[3 * n + 1], z1, Tk[3 * n + 2] * z2));
+                acc = fma(2.0 * Dc[(j * (D + 1) + v) * D + n], hn, acc);
+            }
+        }
+    }
+    const double* cf = coefE + (size_t)kk * ncls;
+    const double* xk = X + (size_t)nRp * kk;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        double val = 0.0;
+        for (int c = 0; c < ncls; ++c) val = fma(cf[c], cls[(size_t)c * nnz + e], val);
+        const int cc = col[e];
+        acc = fma(val, xk[cc], acc);
+        if (G) acc = fma(-Msv[e], G[cc + (size_t)nRp * kk], acc);
+    }
+    if (q) acc -= q[i + (size_t)nRp * kk];
+    Y[i + (size_t)nRp * kk] = acc;
+}
+
+// ----------------------------------------------------------------------------- odd PCG
+__global__ __launch_bounds__(TPB) void odd_apply_kernel(int nRm, int nS, const double* __restrict__ mt,
+                                                        const double* __restrict__ ms,
+                                                        const double* __restrict__ T,
+                                                        const double* __restrict__ P,
+                                                        const double* __restrict__ G,
+                                                        double* __restrict__ W, double* __restrict__ red) {
+    __shared__ double sh[4];
+    double part = 0.0;
+    const size_t total = (size_t)nRm * nS;
+    for (size_t t = blockIdx.x * (size_t)TPB + threadIdx.x; t < total; t += (size_t)gridDim.x * TPB) {
+        const int j = (int)(t % nRm), kk = (int)(t / nRm);
+        const double* Tk = T + 9 * kk;
+        double p[3], w[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) p[m] = P[j + (size_t)nRm * (3 * kk + m)];
+        const double a = mt[j], b = ms[j];
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+            const double mp = 2.0 * fma(Tk[3 * n], p[0], fma(Tk[3 * n + 1], p[1], Tk[3 * n + 2] * p[2]));
+            const size_t o = j + (size_t)nRm * (3 * kk + n);
+            w[n] = fma(a, mp, -b * G[o]);
+            W[o] = w[n];
+        }
+        part += p[0] * w[0] + p[1] * w[1] + p[2] * w[2];
+    }
+    const double s = block_sum(part, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(TPB) void reduce_kernel(const double* __restrict__ red, double* scal, int out) {
+    __shared__ double sh[4];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < k::kRedBlocks; i += TPB) v += red[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) scal[out] = v;
+}
+
+__global__ void sdiv_kernel(double* scal, int out, int a, int b) {
+    const double den = scal[b];
+    scal[out] = (den != 0.0) ? scal[a] / den : 0.0;
+}
+
+template <int DN>
+__global__ __launch_bounds__(TPB) void pcg_update_kernel(int nRm, int nSm, int nch,
+                                                         double* __restrict__ z, double* __restrict__ r,
+                                                         const double* __restrict__ p,
+                                                         const double* __restrict__ w,
+                                                         const double* __restrict__ scal, int ia,
+                                                         const double* __restrict__ Wm,
+                                                         double* __restrict__ Cpart,
+                                                         double* __restrict__ red) {
+    __shared__ double sh[4];
+    const double a = scal[ia];
+    const int cw = (nSm + nch - 1) / nch;
+    double rr = 0.0;
+    const size_t total = (size_t)nRm * nch;
+    for (size_t t = blockIdx.x * (size_t)TPB + threadIdx.x; t < total; t += (size_t)gridDim.x * TPB) {
+        const int j = (int)(t % nRm), ch = (int)(t / nRm);
+        double acc[DN];
+#pragma unroll
+        for (int q = 0; q < DN; ++q) acc[q] = 0.0;
+        const int c1 = min(nSm, (ch + 1) * cw);
+        for (int c = ch * cw; c < c1; ++c) {
+            const size_t o = j + (size_t)nRm * c;
+            z[o] = fma(a, p[o], z[o]);
+            const double rn = fma(-a, w[o], r[o]);
+            r[o] = rn;
+            rr = fma(rn, rn, rr);
+#pragma unroll
+            for (int q = 0; q < DN; ++q) acc[q] = fma(rn, Wm[c + (size_t)nSm * q], acc[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < DN; ++q) Cpart[j + (size_t)nRm * (q + (size_t)DN * ch)] = acc[q];
+    }
+    const double s = block_sum(rr, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+// Cfin[j, a] = (sum_ch Cpart) * (1/(mt_j - lam_a ms_j) - 1/mt_j)
+__global__ __launch_bounds__(TPB) void odd_coarse_scale_kernel(int nRm, int dN, int nch,
+                                                               const double* __restrict__ mt,
+                                                               const double* __restrict__ ms,
+                                                               const double* __restrict__ lam,
+                                                               const double* __restrict__ Cpart,
+                                                               double* __restrict__ Cfin) {
+    const size_t t = blockIdx.x * (size_t)TPB + threadIdx.x;
+    if (t >= (size_t)nRm * dN) return;
+    const int j = (int)(t % nRm), q = (int)(t / nRm);
+    double s = 0.0;
+    for (int ch = 0; ch < nch; ++ch) s += Cpart[j + (size_t)nRm * (q + (size_t)dN * ch)];
+    const double a = mt[j];
+    Cfin[t] = s * (1.0 / (a - lam[q] * ms[j]) - 1.0 / a);
+}
+
+template <int DN>
+__global__ __launch_bounds__(TPB) void odd_precond_kernel(int nRm, int nS, const double* __restrict__ mt,
+                                                          const double* __restrict__ MSinv,
+                                                          const double* __restrict__ Wm,
+                                                          const double* __restrict__ Cfin,
+                                                          const double* __restrict__ r,
+                                                          double* __restrict__ y,
+                                                          double* __restrict__ red) {
+    __shared__ double sh[4];
+    const int nSm = 3 * nS;
+    double part = 0.0;
+    const size_t total = (size_t)nRm * nS;
+    for (size_t t = blockIdx.x * (size_t)TPB + threadIdx.x; t < total; t += (size_t)gridDim.x * TPB) {
+        const int j = (int)(t % nRm), kk = (int)(t / nRm);
+        double rv[3], out[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) rv[m] = r[j + (size_t)nRm * (3 * kk + m)];
+        const double inv = 1.0 / mt[j];
+        const double* Mi = MSinv + 9 * kk;
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+            out[n] = inv * fma(Mi[3 * n], rv[0], fma(Mi[3 * n + 1], rv[1], Mi[3 * n + 2] * rv[2]));
+#pragma unroll
+        for (int q = 0; q < DN; ++q) {
+            const double cq = Cfin[j + (size_t)nRm * q];
+#pragma unroll
+            for (int n = 0; n < 3; ++n) out[n] = fma(cq, Wm[3 * kk + n + (size_t)nSm * q], out[n]);
+        }
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+            y[j + (size_t)nRm * (3 * kk + n)] = out[n];
+            part = fma(rv[n], out[n], part);
+        }
+    }
+    const double s = block_sum(part, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = s;
+}
+
+// ----------------------------------------------------------------------------- vectors
+__global__ void xpby_kernel(const double* __restrict__ y, double* __restrict__ p,
+                            const double* __restrict__ scal, int ib, size_t n) {
+    const double b = ib >= 0 ? scal[ib] : 0.0;
+    for (size_t i = blockIdx.x * (size_t)TPB + threadIdx.x; i < n; i += (size_t)gridDim.x * TPB)
+        p[i] = ib >= 0 ? fma(b, p[i], y[i]) : y[i];
+}
+__global__ void axpy_s_kernel(double* __restrict__ y, const double* __restrict__ x,
+                              const double* __restrict__ z, const double* __restrict__ scal, int ia,
+                              double sign, size_t n) {
+    const double a = sign * scal[ia];
+    for (size_t i = blockIdx.x * (size_t)TPB + threadIdx.x; i < n; i += (size_t)gridDim.x * TPB)
+        y[i] = fma(a, z[i], x[i]);
+}
+__global__ __launch_bounds__(TPB) void dot_kernel(const double* __restrict__ x,
+                                                  const double* __restrict__ y, size_t n,
+                                                  double* __restrict__ red) {
+    __shared__ double sh[4];
+    double v = 0.0;
+    for (size_t i = blockIdx.x * (size_t)TPB + threadIdx.x; i < n; i += (size_t)gridDim.x * TPB)
+        v = fma(x[i], y[i], v);
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = v;
+}
+__global__ void fill_kernel(double* x, double v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)TPB + threadIdx.x; i < n; i += (size_t)gridDim.x * TPB) x[i] = v;
+}
+__global__ void copy_kernel(const double* __restrict__ x, double* __restrict__ y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)TPB + threadIdx.x; i < n; i += (size_t)gridDim.x * TPB) y[i] = x[i];
+}
+__global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)TPB + threadIdx.x; i < n; i += (size_t)gridDim.x * TPB)
+        y[i] = fma(a, x[i], b * y[i]);
+}
+__global__ void row_scale_inv_mt_kernel(int nRm, int ncols, const double* __restrict__ mt,
+                                        const double* __restrict__ C, double* __restrict__ Z) {
+    const size_t n = (size_t)nRm * ncols;
+    for (size_t t = blockIdx.x * (size_t)TPB + threadIdx.x; t < n; t += (size_t)gridDim.x * TPB)
+        Z[t] = C[t] / mt[t % nRm];
+}
+__global__ void scale_eigbasis_kernel(int nRm, int nSm, const double* __restrict__ mt,
+                                      const double* __restrict__ ms, const double* __restrict__ lam,
+                                      double* __restrict__ C) {
+    const size_t n = (size_t)nRm * nSm;
+    for (size_t t = blockIdx.x * (size_t)TPB + threadIdx.x; t < n; t += (size_t)gridDim.x * TPB) {
+        const int j = (int)(t % nRm), a = (int)(t / nRm);
+        C[t] = C[t] / (mt[j] - lam[a] * ms[j]);
+    }
+}
+
+// ----------------------------------------------------------------------------- coarse
+template <int DN>
+__global__ __launch_bounds__(TPB) void coarse_project_kernel(int nRp, int nS, const double* __restrict__ T,
+                                                             const double* __restrict__ Wp,
+                                                             const int* __restrict__ perm,
+                                                             double* __restrict__ rhs) {
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    if (i >= nRp) return;
+    double acc[DN];
+#pragma unroll
+    for (int a = 0; a < DN; ++a) acc[a] = 0.0;
+    for (int kk = 0; kk < nS; ++kk) {
+        const double t = T[i + (size_t)nRp * kk];
+#pragma unroll
+        for (int a = 0; a < DN; ++a) acc[a] = fma(t, Wp[kk + (size_t)nS * a], acc[a]);
+    }
+    const int pi = perm[i];
+#pragma unroll
+    for (int a = 0; a < DN; ++a) rhs[a + (size_t)DN * pi] = acc[a];
+}
+
+template <int DN>
+__global__ __launch_bounds__(TPB) void richardson_update_kernel(int nRp, int nS, double* __restrict__ U,
+                                                                const double* __restrict__ S,
+                                                                const double* __restrict__ uc,
+                                                                const double* __restrict__ Wp,
+                                                                const int* __restrict__ perm) {
+    const size_t t = blockIdx.x * (size_t)TPB + threadIdx.x;
+    if (t >= (size_t)nRp * nS) return;
+    const int i = (int)(t % nRp), kk = (int)(t / nRp);
+    const int pi = perm[i];
+    double v = U[t] - S[t];
+#pragma unroll
+    for (int a = 0; a < DN; ++a) v = fma(uc[a + (size_t)DN * pi], Wp[kk + (size_t)nS * a], v);
+    U[t] = v;
+}
+
+// Banded Cholesky solve L L^T x = b for one system per 64-lane work-group.
+// L: lower band by rows, L[i*(bw+1) + bw + j - i] = L(i,j), diagonal stored inverted.
+// LT: upper band of L^T by rows, LT[i*(bw+1) + j - i] = L(j,i), diagonal stored inverted.
+// Rows are processed in blocks of 64: lane l owns row 64B + l; the contribution of
+// earlier blocks is a per-lane dot product over the band (no cross-lane reduction); the
+// 64 x 64 triangular diagonal block is solved with the block's coefficients held in
+// registers and one broadcast per row.  The solution window lives in LDS.
+constexpr int BS_WIN = 8192;   // LDS window (doubles), must exceed bw + 64
+
+__global__ __launch_bounds__(64) void band_solve_kernel(const double* __restrict__ Lb,
+                                                        const double* __restrict__ LTb, int n, int bw,
+                                                        size_t stride_sys, const double* __restrict__ bb,
+                                                        double* __restrict__ xb, size_t stride_vec,
+                                                        const int* __restrict__ iperm) {
+    __shared__ double win[BS_WIN];
+    const int sys = blockIdx.x;
+    const double* L = Lb + stride_sys * sys;
+    const double* LT = LTb + stride_sys * sys;
+    const double* b = bb + stride_vec * sys;
+    double* x = xb + stride_vec * sys;
+    const int lane = threadIdx.x;
+    const size_t w1 = (size_t)bw + 1;
+    const int nblk = (n + 63) / 64;
+    // ---- forward: L y = b   (y kept in win, indices modulo BS_WIN)
+    for (int B = 0; B < nblk; ++B) {
+        const int row = 64 * B + lane;
+        const bool ok = row < n;
+        double s = 0.0, invd = 0.0;
+        double Ld[64];
+        if (ok) {
+            s = b[iperm ? iperm[row] : row];
+            const double* Lr = L + w1 * row;     // Lr[bw + j - row] = L(row, j)
+            const int j0 = max(0, row - bw);
+            for (int j = j0; j < 64 * B; ++j) s = fma(-Lr[bw + j - row], win[j % BS_WIN], s);
+            invd = Lr[bw];
+#pragma unroll
+            for (int u = 0; u < 64; ++u) {
+                const int j = 64 * B + u;
+                Ld[u] = (u < lane && j >= row - bw) ? Lr[bw + j - row] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 64; ++u) Ld[u] = 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 64; ++u) {
+            const double yu = __shfl(s * invd, u, 64);
+            s = fma(-Ld[u], yu, s);
+        }
+        if (ok) {
+            const double yv = s * invd;
+            win[row % BS_WIN] = yv;
+            x[iperm ? iperm[row] : row] = yv;   // kept for the backward sweep
+        }
+        __syncthreads();
+    }
+    // ---- backward: L^T x = y
+    for (int B = nblk - 1; B >= 0; --B) {
+        const int row = 64 * B + lane;
+        const bool ok = row < n;
+        double s = 0.0, invd = 0.0;
+        double Ud[64];
+        if (ok) {
+            s = x[iperm ? iperm[row] : row];
+            const double* Ur = LT + w1 * row;    // Ur[j - row] = L(j, row)
+            const int j1 = min(n - 1, row + bw);
+            for (int j = 64 * B + 64; j <= j1; ++j) s = fma(-Ur[j - row], win[j % BS_WIN], s);
+            invd = Ur[0];
+#pragma unroll
+            for (int u = 0; u < 64; ++u) {
+                const int j = 64 * B + u;
+                Ud[u] = (u > lane && j <= row + bw && j < n) ? Ur[j - row] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 64; ++u) Ud[u] = 0.0;
+        }
+#pragma unroll
+        for (int u = 63; u >= 0; --u) {
+            const double xu = __shfl(s * invd, u, 64);
+            s = fma(-Ud[u], xu, s);
+        }
+        if (ok) {
+            const double xv = s * invd;
+            win[row % BS_WIN] = xv;
+            x[iperm ? iperm[row] : row] = xv;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------- E_0
+// Jacobi-preconditioned CG, one 256-thread work-group per direction, all iterations in
+// one launch (no grid-wide synchronisation: directions are independent).  Vectors live
+// in global memory; the block values are formed on the fly from the shared pattern
+// classes and the direction's coefficients.
+__device__ __forceinline__ double e0_row(int i, const int* __restrict__ rowptr, const int* __restrict__ col,
+                                         const double* __restrict__ cls, int nnz, int ncls,
+                                         const double* cf, const double* __restrict__ xk) {
+    double acc = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        double val = 0.0;
+        for (int c = 0; c < ncls; ++c) val = fma(cf[c], cls[(size_t)c * nnz + e], val);
+        acc = fma(val, xk[col[e]], acc);
+    }
+    return acc;
+}
+
+__global__ __launch_bounds__(TPB) void e0_cg_kernel(int nRp, int nnz, int ncls,
+                                                    const int* __restrict__ rowptr,
+                                                    const int* __restrict__ col,
+                                                    const double* __restrict__ cls,
+                                                    const double* __restrict__ coefE0,
+                                                    const double* __restrict__ diag,
+                                                    const double* __restrict__ B, double* __restrict__ X,
+                                                    double* __restrict__ R, double* __restrict__ P,
+                                                    double* __restrict__ Q, double tol, int maxit,
+                                                    int* __restrict__ iters) {
+    __shared__ double sh[4];
+    __shared__ double bc[3];
+    __shared__ double cf[kMaxClasses];
+    const int kk = blockIdx.x;
+    const size_t off = (size_t)nRp * kk;
+    const double* b = B + off;
+    double* x = X + off;
+    double* r = R + off;
+    double* p = P + off;
+    double* q = Q + off;
+    const double* dg = diag + off;
+    if (threadIdx.x < ncls) cf[threadIdx.x] = coefE0[(size_t)kk * ncls + threadIdx.x];
+    double bb = 0.0, rz = 0.0;
+    for (int i = threadIdx.x; i < nRp; i += TPB) {
+        const double bi = b[i];
+        x[i] = 0.0;
+        r[i] = bi;
+        const double zi = bi / dg[i];
+        p[i] = zi;
+        bb = fma(bi, bi, bb);
+        rz = fma(bi, zi, rz);
+    }
+    bb = block_sum(bb, sh);
+    rz = block_sum(rz, sh);
+    if (threadIdx.x == 0) { bc[0] = bb; bc[1] = rz; }
+    __syncthreads();
+    bb = bc[0];
+    rz = bc[1];
+    __syncthreads();
+    int it = 0;
+    const double stop = tol * tol * bb;
+    if (bb > 0.0) {
+        while (it < maxit) {
+            double pq = 0.0;
+            for (int i = threadIdx.x; i < nRp; i += TPB) {
+                const double qi = e0_row(i, rowptr, col, cls, nnz, ncls, cf, p);
+                q[i] = qi;
+                pq = fma(p[i], qi, pq);
+            }
+            pq = block_sum(pq, sh);
+            if (threadIdx.x == 0) bc[0] = pq;
+            __syncthreads();
+            const double alpha = rz / bc[0];
+            double rzn = 0.0, rr = 0.0;
+            for (int i = threadIdx.x; i < nRp; i += TPB) {
+                x[i] = fma(alpha, p[i], x[i]);
+                const double ri = fma(-alpha, q[i], r[i]);
+                r[i] = ri;
+                rzn = fma(ri, ri / dg[i], rzn);
+                rr = fma(ri, ri, rr);
+            }
+            rzn = block_sum(rzn, sh);
+            rr = block_sum(rr, sh);
+            if (threadIdx.x == 0) { bc[1] = rzn; bc[2] = rr; }
+            __syncthreads();
+            rzn = bc[1];
+            rr = bc[2];
+            ++it;
+            if (rr <= stop) break;
+            const double beta = rzn / rz;
+            rz = rzn;
+            for (int i = threadIdx.x; i < nRp; i += TPB) p[i] = fma(beta, p[i], r[i] / dg[i]);
+            __syncthreads();
+        }
+    } else {
+        for (int i = threadIdx.x; i < nRp; i += TPB) x[i] = 0.0;
+    }
+    if (threadIdx.x == 0) iters[kk] = it;
+}
+
+__global__ __launch_bounds__(TPB) void e0_apply_kernel(int nRp, int nS, int nnz, int ncls,
+                                                       const int* __restrict__ rowptr,
+                                                       const int* __restrict__ col,
+                                                       const double* __restrict__ cls,
+                                                       const double* __restrict__ coefE0,
+                                                       const double* __restrict__ X, double* __restrict__ Y) {
+    const size_t t = blockIdx.x * (size_t)TPB + threadIdx.x;
+    if (t >= (size_t)nRp * nS) return;
+    const int i = (int)(t % nRp), kk = (int)(t / nRp);
+    Y[t] = e0_row(i, rowptr, col, cls, nnz, ncls, coefE0 + (size_t)kk * ncls, X + (size_t)nRp * kk);
+}
+
+// compile-time dispatch over the eigen-basis sizes d_N = (N+1)(N+2)/2, N = 0..8
+template <template <int> class F, typename... Args>
+void dispatch_dn(int dn, Args&&... args) {
+    switch (dn) {
+        case 1: F<1>::run(args...); break;
+        case 3: F<3>::run(args...); break;
+        case 6: F<6>::run(args...); break;
+        case 10: F<10>::run(args...); break;
+        case 15: F<15>::run(args...); break;
+        case 21: F<21>::run(args...); break;
+        case 28: F<28>::run(args...); break;
+        case 36: F<36>::run(args...); break;
+        case 45: F<45>::run(args...); break;
+        default: fail(RTE_E_ARG, "eigen-basis size " + std::to_string(dn) + " not supported");
+    }
+}
+
+template <int DN> struct PcgUpdateL {
+    static void run(const Handle* h, double* z, double* r, const double* p, const double* w,
+                    const double* scal, int ia, double* Cpart, double* red, int nch, hipStream_t s) {
+        hipLaunchKernelGGL(pcg_update_kernel<DN>, dim3(k::kRedBlocks), dim3(TPB), 0, s, h->nRm, h->nSm, nch,
+                           z, r, p, w, scal, ia, h->Wm.p, Cpart, red);
+    }
+};
+template <int DN> struct OddPrecondL {
+    static void run(const Handle* h, const double* r, const double* Cfin, double* y, double* red, hipStream_t s) {
+        hipLaunchKernelGGL(odd_precond_kernel<DN>, dim3(k::kRedBlocks), dim3(TPB), 0, s, h->nRm, h->nS,
+                           h->mt.p, h->MSinv.p, h->Wm.p, Cfin, r, y, red);
+    }
+};
+template <int DN> struct CoarseProjectL {
+    static void run(const Handle* h, const double* T, double* rhs, hipStream_t s) {
+        hipLaunchKernelGGL(coarse_project_kernel<DN>, dim3((h->nRp + TPB - 1) / TPB), dim3(TPB), 0, s,
+                           h->nRp, h->nS, T, h->Wp.p, h->perm.p, rhs);
+    }
+};
+template <int DN> struct RichUpdateL {
+    static void run(const Handle* h, double* U, const double* S, const double* uc, hipStream_t s) {
+        const size_t n = (size_t)h->nRp * h->nS;
+        hipLaunchKernelGGL(richardson_update_kernel<DN>, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, s,
+                           h->nRp, h->nS, U, S, uc, h->Wp.p, h->perm.p);
+    }
+};
+
+inline int pcg_chunks(const Handle* h) { return std::min(8, h->nSm); }
+
+}  // namespace
+
+namespace k {
+
+void apply_A(const Handle* h, const double* X, double* B, hipStream_t s) {
+    const size_t n = (size_t)h->nRm * h->nS;
+    const dim3 g((unsigned)((n + TPB - 1) / TPB));
+    if (h->d == 2)
+        hipLaunchKernelGGL(apply_A_kernel<2>, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->cell.p, h->Dc.p, h->T.p, X, B);
+    else
+        hipLaunchKernelGGL(apply_A_kernel<3>, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->cell.p, h->Dc.p, h->T.p, X, B);
+    RTE_CHECK_LAUNCH();
+}
+
+void apply_At_E(const Handle* h, const double* Z, const double* X, const double* G, const double* q,
+                double* Y, hipStream_t s) {
+    const size_t n = (size_t)h->nRp * h->nS;
+    const dim3 g((unsigned)((n + TPB - 1) / TPB));
+    auto* f = h->d == 2 ? apply_At_E_kernel<2> : apply_At_E_kernel<3>;
+    hipLaunchKernelGGL(f, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->nnz, h->ncls, h->vc_ptr.p,
+                       h->vc_cell.p, h->vc_loc.p, h->Dc.p, h->T.p, h->rowptr.p, h->col.p, h->cls.p,
+                       h->coefE.p, h->Msv.p, Z, X, G, q, Y);
+    RTE_CHECK_LAUNCH();
+}
+
+void odd_apply(const Handle* h, const double* P, const double* G, double* W, double* red, hipStream_t s) {
+    hipLaunchKernelGGL(odd_apply_kernel, dim3(kRedBlocks), dim3(TPB), 0, s, h->nRm, h->nS, h->mt.p,
+                       h->ms.p, h->T.p, P, G, W, red);
+    RTE_CHECK_LAUNCH();
+}
+
+void reduce(const double* red, double* scal, int out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(TPB), 0, s, red, scal, out);
+    RTE_CHECK_LAUNCH();
+}
+
+void sdiv(double* scal, int out, int a, int b, hipStream_t s) {
+    hipLaunchKernelGGL(sdiv_kernel, dim3(1), dim3(1), 0, s, scal, out, a, b);
+    RTE_CHECK_LAUNCH();
+}
+
+void pcg_update(const Handle* h, double* z, double* r, const double* p, const double* w,
+                const double* scal, int ia, double* Cpart, double* red, hipStream_t s) {
+    dispatch_dn<PcgUpdateL>(h->dNm, h, z, r, p, w, scal, ia, Cpart, red, pcg_chunks(h), s);
+    RTE_CHECK_LAUNCH();
+}
+
+void odd_precond(const Handle* h, const double* r, const double* Cpart, double* Cfin, double* y,
+                 double* red, hipStream_t s) {
+    const size_t n = (size_t)h->nRm * h->dNm;
+    hipLaunchKernelGGL(odd_coarse_scale_kernel, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s,
+                       h->nRm, h->dNm, pcg_chunks(h), h->mt.p, h->ms.p, h->lamm.p, Cpart, Cfin);
+    RTE_CHECK_LAUNCH();
+    dispatch_dn<OddPrecondL>(h->dNm, h, r, (const double*)Cfin, y, red, s);
+    RTE_CHECK_LAUNCH();
+}
+
+void xpby(const double* y, double* p, const double* scal, int ib, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(xpby_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, y, p, scal, ib, n);
+    RTE_CHECK_LAUNCH();
+}
+void axpy_s(double* y, const double* x, const double* z, const double* scal, int ia, double sign,
+            size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_s_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, y, x, z, scal, ia, sign, n);
+    RTE_CHECK_LAUNCH();
+}
+void dot(const double* x, const double* y, size_t n, double* red, hipStream_t s) {
+    hipLaunchKernelGGL(dot_kernel, dim3(kRedBlocks), dim3(TPB), 0, s, x, y, n, red);
+    RTE_CHECK_LAUNCH();
+}
+void fill(double* x, double v, size_t n, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, x, v, n);
+    RTE_CHECK_LAUNCH();
+}
+void copy(const double* x, double* y, size_t n, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, x, y, n);
+    RTE_CHECK_LAUNCH();
+}
+void axpby(double a, const double* x, double b, double* y, size_t n, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(axpby_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, a, x, b, y, n);
+    RTE_CHECK_LAUNCH();
+}
+void row_scale_inv_mt(const Handle* h, const double* C, double* Z, int ncols, hipStream_t s) {
+    const size_t n = (size_t)h->nRm * ncols;
+    hipLaunchKernelGGL(row_scale_inv_mt_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, h->nRm, ncols, h->mt.p, C, Z);
+    RTE_CHECK_LAUNCH();
+}
+void scale_eigbasis(const Handle* h, double* C, hipStream_t s) {
+    const size_t n = (size_t)h->nRm * h->nSm;
+    hipLaunchKernelGGL(scale_eigbasis_kernel, dim3(blocks_for(n)), dim3(TPB), 0, s, h->nRm, h->nSm,
+                       h->mt.p, h->ms.p, h->lam_full.p, C);
+    RTE_CHECK_LAUNCH();
+}
+
+void coarse_project(const Handle* h, const double* T, double* rhs, hipStream_t s) {
+    dispatch_dn<CoarseProjectL>(h->dNp, h, T, rhs, s);
+    RTE_CHECK_LAUNCH();
+}
+
+void band_solve(const double* L, const double* LT, int n, int bw, int nsys, size_t stride_sys,
+                const double* b, double* x, size_t stride_vec, const int* iperm, int, hipStream_t s) {
+    if (bw + 64 >= BS_WIN) fail(RTE_E_ARG, "band too wide for the LDS window");
+    hipLaunchKernelGGL(band_solve_kernel, dim3(nsys), dim3(64), 0, s, L, LT, n, bw, stride_sys, b, x,
+                       stride_vec, iperm);
+    RTE_CHECK_LAUNCH();
+}
+
+void richardson_update(const Handle* h, double* U, const double* S, const double* uc, hipStream_t s) {
+    dispatch_dn<RichUpdateL>(h->dNp, h, U, S, uc, s);
+    RTE_CHECK_LAUNCH();
+}
+
+void e0_cg(const Handle* h, const double* B, double* X, double* r, double* p, double* q, double tol,
+           int maxit, int* iters, hipStream_t s) {
+    hipLaunchKernelGGL(e0_cg_kernel, dim3(h->nS), dim3(TPB), 0, s, h->nRp, h->nnz, h->ncls, h->rowptr.p,
+                       h->col.p, h->cls.p, h->coefE0.p, h->diagE0.p, B, X, r, p, q, tol, maxit, iters);
+    RTE_CHECK_LAUNCH();
+}
+
+void e0_apply(const Handle* h, const double* X, double* Y, hipStream_t s) {
+    const size_t n = (size_t)h->nRp * h->nS;
+    hipLaunchKernelGGL(e0_apply_kernel, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, h->nRp,
+                       h->nS, h->nnz, h->ncls, h->rowptr.p, h->col.p, h->cls.p, h->coefE0.p, X, Y);
+    RTE_CHECK_LAUNCH();
+}
+
+}  // namespace k
+}  // namespace rte
+
+namespace rte {
+namespace {
+__global__ __launch_bounds__(256) void spmm_pattern_kernel(int nRp, int nS, const int* __restrict__ rowptr,
+                                                           const int* __restrict__ col,
+                                                           const double* __restrict__ vals,
+                                                           const double* __restrict__ X, double* __restrict__ Y) {
+    const size_t t = blockIdx.x * (size_t)256 + threadIdx.x;
+    if (t >= (size_t)nRp * nS) return;
+    const int i = (int)(t % nRp), kk = (int)(t / nRp);
+    const double* xk = X + (size_t)nRp * kk;
+    double acc = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc = fma(vals[e], xk[col[e]], acc);
+    Y[t] = acc;
+}
+__global__ void row_scale_kernel(const double* __restrict__ v, int nrow, size_t n, const double* __restrict__ X,
+                                 double* __restrict__ Y) {
+    for (size_t t = blockIdx.x * (size_t)256 + threadIdx.x; t < n; t += (size_t)gridDim.x * 256)
+        Y[t] = v[t % nrow] * X[t];
+}
+}  // namespace
+namespace k {
+void spmm_pattern(const Handle* h, const double* vals, const double* X, double* Y, hipStream_t s) {
+    const size_t n = (size_t)h->nRp * h->nS;
+    hipLaunchKernelGGL(spmm_pattern_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->nRp, h->nS,
+                       h->rowptr.p, h->col.p, vals, X, Y);
+    RTE_CHECK_LAUNCH();
+}
+void row_scale(const double* v, int nrow, int ncol, const double* X, double* Y, hipStream_t s) {
+    const size_t n = (size_t)nrow * ncol;
+    if (!n) return;
+    hipLaunchKernelGGL(row_scale_kernel, dim3((unsigned)std::min<size_t>((n + 255) / 256, 65535)), dim3(256), 0, s,
+                       v, nrow, n, X, Y);
+    RTE_CHECK_LAUNCH();
+}
+}  // namespace k
+}  // namespace rte

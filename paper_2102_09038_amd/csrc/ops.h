@@ -1,0 +1,77 @@
+// Launchers of the sparse / Kronecker glue kernels (kernels_ops.hip) and of the
+// per-direction E_0 solvers (kernels_e0.hip).
+#pragma once
+#include "rte_internal.h"
+
+namespace rte {
+namespace k {
+
+constexpr int kRedBlocks = 1024;        // partial sums per deterministic reduction
+
+// B = A X  (B: nRm x 3nS, X: nRp x nS)        [Sec. 4: A = sum_n A_n (x) D_n]
+void apply_A(const Handle* h, const double* X, double* B, hipStream_t s);
+// Y = A^T Z + (M+ + R) X  [- Ms+ G - q]  (Y, X, G: nRp x nS, Z: nRm x 3nS).
+// G and q may be null (no scattering / source term).  Alg. 1, last line; with G = X S+
+// and q it is the residual (E - K+) X - q of Alg. 3.
+void apply_At_E(const Handle* h, const double* Z, const double* X, const double* G,
+                const double* q, double* Y, hipStream_t s);
+// W = (M- - K-) P given G = P S-:  W = Mt- P M_S- - Ms- G;  red <- partials of P.W
+void odd_apply(const Handle* h, const double* P, const double* G, double* W, double* red,
+               hipStream_t s);
+// scal[out] = sum of kRedBlocks partials (fixed order)
+void reduce(const double* red, double* scal, int out, hipStream_t s);
+// scal[out] = scal[a] / scal[b]  (0 if scal[b] == 0)
+void sdiv(double* scal, int out, int a, int b, hipStream_t s);
+// z += a p ; r -= a w ; Cpart <- per-chunk projections r W_N ; red <- partials of r.r
+// (a = scal[ia])
+void pcg_update(const Handle* h, double* z, double* r, const double* p, const double* w,
+                const double* scal, int ia, double* Cpart, double* red, hipStream_t s);
+// y = (M- - K-_N)^{-1} r  (Lemma of Sec. 5.1) from r and the chunked projections;
+// red <- partials of r.y
+void odd_precond(const Handle* h, const double* r, const double* Cpart, double* Cfin, double* y,
+                 double* red, hipStream_t s);
+// p = y + b p  (b = scal[ib]); with ib < 0: p = y
+void xpby(const double* y, double* p, const double* scal, int ib, size_t n, hipStream_t s);
+// y = x + a z  (a = scal[ia] * sign)
+void axpy_s(double* y, const double* x, const double* z, const double* scal, int ia, double sign,
+            size_t n, hipStream_t s);
+// red <- partials of x.y
+void dot(const double* x, const double* y, size_t n, double* red, hipStream_t s);
+void fill(double* x, double v, size_t n, hipStream_t s);
+void copy(const double* x, double* y, size_t n, hipStream_t s);
+// y = a x + b y (host scalars)
+void axpby(double a, const double* x, double b, double* y, size_t n, hipStream_t s);
+// Z = Mt-^{-1} (C) row scaling: Z[j, :] = C[j, :] / mt_j
+void row_scale_inv_mt(const Handle* h, const double* C, double* Z, int ncols, hipStream_t s);
+// C[j, a] /= mt_j (1 - Delta_j lam_a)   (exact odd inverse in the eigenbasis)
+void scale_eigbasis(const Handle* h, double* C, hipStream_t s);
+
+// ---- coarse correction (Sec. 5.4)
+// rhs[a + dN*perm[i]] = sum_k T[i,k] Wp[k,a]
+void coarse_project(const Handle* h, const double* T, double* rhs, hipStream_t s);
+// x = L^{-T} L^{-1} b for nsys independent banded systems (one wavefront each)
+void band_solve(const double* L, const double* LT, int n, int bw, int nsys, size_t stride_sys,
+                const double* b, double* x, size_t stride_vec, const int* perm, int perm_mode,
+                hipStream_t s);
+// U = U - S + sum_a uc[a + dN*perm[i]] Wp[k, a]
+void richardson_update(const Handle* h, double* U, const double* S, const double* uc,
+                       hipStream_t s);
+
+// ---- E_0 (Sec. 5.3)
+// X = E_0^{-1} B by Jacobi-preconditioned CG per direction; iters[k] <- count
+void e0_cg(const Handle* h, const double* B, double* X, double* r, double* p, double* q,
+           double tol, int maxit, int* iters, hipStream_t s);
+// Y = E_0 X (all directions)
+void e0_apply(const Handle* h, const double* X, double* Y, hipStream_t s);
+
+}  // namespace k
+}  // namespace rte
+
+namespace rte {
+namespace k {
+// Y = M X column by column for a matrix with the P1 pattern and values vals[nnz]
+void spmm_pattern(const Handle* h, const double* vals, const double* X, double* Y, hipStream_t s);
+// Y[j, c] = v[j] X[j, c]   (nrow x ncol, col-major)
+void row_scale(const double* v, int nrow, int ncol, const double* X, double* Y, hipStream_t s);
+}  // namespace k
+}  // namespace rte

@@ -1,0 +1,187 @@
+// Internal declarations of librte: the handle, device buffers, error handling and the
+// kernel launchers shared by the host orchestration code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/rte.h"
+
+namespace rte {
+
+// ----------------------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    rte_status status;
+    Error(rte_status s, const std::string& msg) : std::runtime_error(msg), status(s) {}
+};
+
+[[noreturn]] inline void fail(rte_status s, const std::string& msg) { throw Error(s, msg); }
+
+#define RTE_HIP(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            ::rte::fail(e_ == hipErrorOutOfMemory ? RTE_E_NOMEM : RTE_E_HIP,             \
+                        std::string(#call) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+#define RTE_CHECK_LAUNCH() RTE_HIP(hipGetLastError())
+
+// ----------------------------------------------------------------------------- buffers
+// Owning device buffer (hipMalloc / hipFree); movable, not copyable.
+template <typename T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf& operator=(DBuf&& o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count) RTE_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+    // blocking: the host vector may be a temporary
+    void upload(const std::vector<T>& h, hipStream_t s) {
+        alloc(h.size());
+        if (n) {
+            RTE_HIP(hipMemcpyAsync(p, h.data(), bytes(), hipMemcpyHostToDevice, s));
+            RTE_HIP(hipStreamSynchronize(s));
+        }
+    }
+    std::vector<T> download(hipStream_t s) const {
+        std::vector<T> h(n);
+        if (n) {
+            RTE_HIP(hipMemcpyAsync(h.data(), p, bytes(), hipMemcpyDeviceToHost, s));
+            RTE_HIP(hipStreamSynchronize(s));
+        }
+        return h;
+    }
+};
+
+// ----------------------------------------------------------------------------- handle
+constexpr int kMaxClasses = 16;   // sparse value classes of the P1 pattern (see below)
+
+struct Handle {
+    // sizes
+    int d = 0, nRp = 0, nRm = 0, nS = 0, nSm = 0;
+    int dNp = 1, dNm = 21;         // sizes of the even correction / odd PCG eigen-bases
+    int n_even = 0, n_odd = 5;
+    double g = 0, c = 0;           // anisotropy and max sigma_s / sigma_t
+    bool uniform_delta = false;    // sigma_s / sigma_t is the same in every cell
+    double delta0 = 0;             // that ratio when uniform
+    hipStream_t stream = nullptr;  // stream the handle was assembled on
+
+    // ---- angular (Sec. 4)
+    DBuf<double> Sp, Sm;           // [nS x nS], [nSm x nSm] symmetric, dense
+    DBuf<double> m;                // [nS]   (M_S+)_kk = 2|K_k|
+    DBuf<double> T;                // [nS*9] T_k row-major
+    DBuf<double> MSinv;            // [nS*9] inverse of the 3x3 block 2 T_k of M_S-
+    DBuf<double> Wm, lamm;         // odd eigenvectors [nSm x dNm] col-major, eigenvalues [dNm]
+    DBuf<double> Wp;               // even eigenvectors [nS x dNp] col-major
+    std::vector<double> h_m, h_T, h_lamp, h_Wp, h_lamm_full, h_Sp, h_Sm;
+
+    // ---- exact odd inverse (RTE_ODD_EXACT)
+    bool have_exact = false;
+    DBuf<double> Hodd;             // [nSm x nSm] (M_S- - delta0 S-)^{-1} when uniform_delta
+    DBuf<double> Wfull, WfullT;    // full odd eigenvectors and transpose (both row-major K x N)
+    DBuf<double> lam_full;         // [nSm]
+
+    // ---- spatial (Sec. 4)
+    DBuf<int> cell;                // [nRm*(d+1)]
+    DBuf<double> Dc;               // [nRm*(d+1)*d] |T_j| d_n phi_v on T_j
+    DBuf<double> mt, ms;           // [nRm] sigma_t|T|, sigma_s|T|
+    DBuf<int> rowptr, col;         // P1 pattern (CSR, nRp rows, sorted columns)
+    int nnz = 0;
+    DBuf<double> Msv;              // [nnz] sigma_s-weighted P1 mass values
+    int ncls = 0;                  // value classes of the pattern:
+    DBuf<double> cls;              //   [ncls*nnz]: d(d+1)/2 stiffness terms
+                                   //   D_n^T Mt-^{-1} D_m (+ transpose), Mt+, then one
+                                   //   boundary facet mass per normal class
+    int ncls_stiff = 0, nbcls = 0;
+    DBuf<double> coefE0;           // [nS*ncls] E_0 block k = sum_c coefE0[k,c] cls_c
+    DBuf<double> coefE;            // [nS*ncls] (M+ + R) block k = sum_c coefE[k,c] cls_c
+    DBuf<double> diagE0;           // [nRp*nS] diagonal of every E_0 block (Jacobi)
+    DBuf<int> vc_ptr, vc_cell, vc_loc;   // vertex -> incident cells (for A^T)
+    DBuf<double> q;                // [nRp*nS] even load l+
+    double qnorm = 0;
+
+    // ---- coarse (Sec. 5.4): banded Cholesky of E_c in the order a + dNp * perm[i]
+    int nc = 0, cbw = 0;
+    DBuf<double> Lc, LcT;          // [nc*(cbw+1)] lower band by rows, its transpose by rows
+    DBuf<int> perm;                // [nRp] spatial reordering (reverse Cuthill-McKee)
+
+    // ---- banded E_0 (RTE_E0_BANDED)
+    bool have_e0_banded = false;
+    int ebw = 0;
+    DBuf<double> L0, L0T;          // [nS][nRp*(ebw+1)]
+    DBuf<int> e0perm;              // [nRp]
+
+    // ---- BF16 copies (mixed precision)
+    bool have_mixed = false;
+    DBuf<uint16_t> Sp_bf, Sm_bf, Hodd_bf, Wfull_bf, WfullT_bf;
+
+    // ---- workspace (allocated lazily, sized for one solve)
+    std::vector<DBuf<double>> ws;
+    DBuf<int> cg_iters;            // per-direction CG counts of the last E_0 application
+    DBuf<double> red;              // reduction scratch
+    DBuf<double> scal;             // device scalars
+    std::vector<double> hscal;
+    double* pinned = nullptr;      // small pinned host buffer for scalar readback
+    void* rocblas = nullptr;       // rocblas handle for setup eigensolves
+
+    ~Handle();
+    size_t footprint() const;
+};
+
+// Assembly (assemble.cpp)
+Handle* assemble(const rte_problem_desc* desc, const rte_assemble_opts* opts, hipStream_t s);
+
+// Solver (solver.cpp)
+void apply_scatter(Handle* h, int parity, int dtin, const void* X, int dtout, void* Y,
+                   hipStream_t s);
+void apply_E(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s,
+             int64_t* pcg_iters);
+void apply_E0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s,
+                 int64_t* cg_total, int* cg_max);
+void precond(Handle* h, const rte_solve_opts* o, int which, const double* r, double* out,
+             hipStream_t s);
+rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U,
+                 rte_solve_info* info, hipStream_t s);
+
+// ----------------------------------------------------------------------------- launchers
+namespace k {
+// Dense scattering matrices by double quadrature of the HG kernel.
+void hg_scatter(const double* pts, const double* wts, int nS, int Q, double g, double* Sp,
+                double* Sm, hipStream_t s);
+// C[MxN] = alpha * A[MxK] (col-major, lda) * B (row-major KxN, ldb) + beta * C (col-major).
+void gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, const double* B,
+              int ldb, double beta, double* C, int ldc, hipStream_t s);
+// BF16 inputs, FP32 accumulate; A col-major bf16, B row-major bf16, C col-major f32.
+void gemm_bf16(int M, int N, int K, float alpha, const uint16_t* A, int lda, const uint16_t* B,
+               int ldb, float beta, float* C, int ldc, hipStream_t s);
+void cvt_f64_bf16(const double* x, uint16_t* y, size_t n, hipStream_t s);
+void cvt_f32_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s);
+void cvt_f64_f32(const double* x, float* y, size_t n, hipStream_t s);
+void cvt_f32_f64(const float* x, double* y, size_t n, hipStream_t s);
+}  // namespace k
+
+}  // namespace rte

@@ -1,0 +1,260 @@
+// Host orchestration of the preconditioned Richardson iteration (paper Sec. 5):
+// ApplyE (Alg. 1), E_0^{-1} (Sec. 5.3), P_1^l (Alg. 2), the subspace correction P_2
+// (Sec. 5.4) and the outer loop (Alg. 3).  Every arithmetic step is a HIP kernel on the
+// caller's stream; the host only sequences launches and reads back one scalar per PCG
+// or outer iteration for the convergence tests.
+#include <chrono>
+#include <cmath>
+
+#include "ops.h"
+#include "rte_internal.h"
+
+namespace rte {
+namespace {
+
+// device scalar slots
+enum Slot { S_BB = 0, S_PW, S_ALPHA, S_RR, S_RZ0, S_RZ1, S_BETA, S_DOT0, S_DOT1, S_DOT2 };
+
+enum WsId {
+    // odd workspace (nRm x nSm)
+    W_OB = 0, W_OZ, W_OR, W_OP, W_OW, W_OY, W_OG,
+    // thin odd workspace
+    W_CPART, W_CFIN,
+    // even workspace (nRp x nS)
+    W_EG, W_ET, W_ER, W_ES, W_ESTEP, W_EZ, W_ET2, W_CGR, W_CGP, W_CGQ,
+    // coarse
+    W_CRHS, W_CSOL,
+    W_COUNT
+};
+
+double* ws(Handle* h, int id) {
+    if (h->ws.size() < W_COUNT) h->ws.resize(W_COUNT);
+    DBuf<double>& b = h->ws[id];
+    if (!b.p) {
+        size_t n = 0;
+        const size_t odd = (size_t)h->nRm * h->nSm, even = (size_t)h->nRp * h->nS;
+        if (id <= W_OG) n = odd;
+        else if (id == W_CPART) n = (size_t)h->nRm * h->dNm * std::min(8, h->nSm);
+        else if (id == W_CFIN) n = (size_t)h->nRm * h->dNm;
+        else if (id <= W_CGQ) n = even;
+        else n = (size_t)h->nc;
+        b.alloc(n);
+    }
+    return b.p;
+}
+
+double read_scalar(Handle* h, int slot, hipStream_t s) {
+    RTE_HIP(hipMemcpyAsync(h->pinned, h->scal.p + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipStreamSynchronize(s));
+    return h->pinned[0];
+}
+
+double dot_dev(Handle* h, const double* x, const double* y, size_t n, int slot, hipStream_t s) {
+    k::dot(x, y, n, h->red.p, s);
+    k::reduce(h->red.p, h->scal.p, slot, s);
+    return read_scalar(h, slot, s);
+}
+
+// ----------------------------------------------------------------------------- odd solves
+// (M- - K-) Z = B by PCG preconditioned with (M- - K-_N)^{-1} (Alg. 1, lemma of Sec. 5.1).
+int odd_pcg(Handle* h, const double* B, double* Z, double tol, int maxit, hipStream_t s) {
+    const size_t n = (size_t)h->nRm * h->nSm;
+    double* R = ws(h, W_OR);
+    double* P = ws(h, W_OP);
+    double* W = ws(h, W_OW);
+    double* Y = ws(h, W_OY);
+    double* G = ws(h, W_OG);
+    double* Cp = ws(h, W_CPART);
+    double* Cf = ws(h, W_CFIN);
+    k::fill(Z, 0.0, n, s);
+    const double bb = dot_dev(h, B, B, n, S_BB, s);
+    if (!std::isfinite(bb)) fail(RTE_E_NONFINITE, "non-finite right-hand side in the odd solve");
+    if (bb == 0.0) return 0;
+    k::copy(B, R, n, s);
+    // projections of r onto the truncated eigenbasis: pcg_update with a = 0 computes them
+    k::fill(h->scal.p + S_ALPHA, 0.0, 1, s);
+    k::pcg_update(h, Z, R, R, R, h->scal.p, S_ALPHA, Cp, h->red.p, s);
+    int rz = S_RZ0, rzn = S_RZ1;
+    k::odd_precond(h, R, Cp, Cf, Y, h->red.p, s);
+    k::reduce(h->red.p, h->scal.p, rz, s);
+    k::copy(Y, P, n, s);
+    int it = 0;
+    const double stop = tol * tol * bb;
+    while (it < maxit) {
+        k::gemm_f64(h->nRm, h->nSm, h->nSm, 1.0, P, h->nRm, h->Sm.p, h->nSm, 0.0, G, h->nRm, s);
+        k::odd_apply(h, P, G, W, h->red.p, s);
+        k::reduce(h->red.p, h->scal.p, S_PW, s);
+        k::sdiv(h->scal.p, S_ALPHA, rz, S_PW, s);
+        k::pcg_update(h, Z, R, P, W, h->scal.p, S_ALPHA, Cp, h->red.p, s);
+        k::reduce(h->red.p, h->scal.p, S_RR, s);
+        ++it;
+        const double rr = read_scalar(h, S_RR, s);
+        if (!std::isfinite(rr)) fail(RTE_E_NONFINITE, "non-finite residual in the odd PCG");
+        if (rr <= stop) break;
+        k::odd_precond(h, R, Cp, Cf, Y, h->red.p, s);
+        k::reduce(h->red.p, h->scal.p, rzn, s);
+        k::sdiv(h->scal.p, S_BETA, rzn, rz, s);
+        k::xpby(Y, P, h->scal.p, S_BETA, n, s);
+        std::swap(rz, rzn);
+    }
+    return it;
+}
+
+// (M- - K-) Z = B exactly via the eigen-decomposition of (S-, M_S-).
+void odd_exact(Handle* h, const double* B, double* Z, hipStream_t s) {
+    const int nRm = h->nRm, nSm = h->nSm;
+    if (h->uniform_delta) {
+        double* G = ws(h, W_OG);
+        k::gemm_f64(nRm, nSm, nSm, 1.0, B, nRm, h->Hodd.p, nSm, 0.0, G, nRm, s);
+        k::row_scale_inv_mt(h, G, Z, nSm, s);
+    } else {
+        double* C = ws(h, W_OG);
+        k::gemm_f64(nRm, nSm, nSm, 1.0, B, nRm, h->Wfull.p, nSm, 0.0, C, nRm, s);
+        k::scale_eigbasis(h, C, s);
+        k::gemm_f64(nRm, nSm, nSm, 1.0, C, nRm, h->WfullT.p, nSm, 0.0, Z, nRm, s);
+    }
+}
+
+// Y = E X  [- Ms+ G - q]   (Alg. 1; G and q optional)
+void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const double* G,
+                  const double* q, double* Y, double tol, hipStream_t s, int64_t* pcg) {
+    double* B = ws(h, W_OB);
+    double* Z = ws(h, W_OZ);
+    k::apply_A(h, X, B, s);
+    if (o->odd_solver == RTE_ODD_EXACT) {
+        odd_exact(h, B, Z, s);
+    } else {
+        const int it = odd_pcg(h, B, Z, tol, o->pcg_max_iter, s);
+        if (pcg) *pcg += it;
+    }
+    k::apply_At_E(h, Z, X, G, q, Y, s);
+}
+
+// Y = (E - K+) X - q0 with q0 = q (residual) or any vector (nullable)
+void residual_like(Handle* h, const rte_solve_opts* o, const double* X, const double* q0, double* Y,
+                   double tol, hipStream_t s, int64_t* pcg) {
+    double* G = ws(h, W_EG);
+    k::gemm_f64(h->nRp, h->nS, h->nS, 1.0, X, h->nRp, h->Sp.p, h->nS, 0.0, G, h->nRp, s);
+    apply_E_core(h, o, X, G, q0, Y, tol, s, pcg);
+}
+
+void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s, int64_t* cgt,
+           int* cgmax) {
+    if (o->e0_solver == RTE_E0_BANDED) {
+        if (!h->have_e0_banded) fail(RTE_E_ARG, "banded E_0 factors were not prepared at assembly");
+        k::band_solve(h->L0.p, h->L0T.p, h->nRp, h->ebw, h->nS, (size_t)h->nRp * (h->ebw + 1), X, Y,
+                      (size_t)h->nRp, h->e0perm.p, 0, s);
+        return;
+    }
+    double* r = ws(h, W_CGR);
+    double* p = ws(h, W_CGP);
+    double* q = ws(h, W_CGQ);
+    DBuf<int>& iters = h->cg_iters;
+    if (iters.n < (size_t)h->nS) iters.alloc(h->nS);
+    k::e0_cg(h, X, Y, r, p, q, o->cg_tol, o->cg_max_iter, iters.p, s);
+    if (cgt || cgmax) {
+        std::vector<int> hi(h->nS);
+        RTE_HIP(hipMemcpyAsync(hi.data(), iters.p, h->nS * sizeof(int), hipMemcpyDeviceToHost, s));
+        RTE_HIP(hipStreamSynchronize(s));
+        for (int v : hi) {
+            if (cgt) *cgt += v;
+            if (cgmax) *cgmax = std::max(*cgmax, v);
+        }
+    }
+}
+
+// z = P_1^l r  (Alg. 2 with l steps; z_0 = 0 so the first step is E_0^{-1} r)
+void apply_P1(Handle* h, const rte_solve_opts* o, const double* r, double* z, hipStream_t s,
+              int64_t* pcg, int64_t* cgt, int* cgmax) {
+    const size_t n = (size_t)h->nRp * h->nS;
+    double* t = ws(h, W_ET2);
+    double* t2 = ws(h, W_EZ);
+    e0inv(h, o, r, z, s, cgt, cgmax);
+    for (int i = 1; i < o->l; ++i) {
+        apply_E_core(h, o, z, nullptr, r, t, o->pcg_tol_inner, s, pcg);   // t = E z - r
+        e0inv(h, o, t, t2, s, cgt, cgmax);
+        k::axpby(-1.0, t2, 1.0, z, n, s);
+    }
+}
+
+// step = -s + W E_c^{-1} W^T ((E - K+) s - r)   (Sec. 5.4; the correction right-hand side
+// without Alg. 3's extra "-q", which would move the fixed point)
+void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const double* sv, double* step,
+                     hipStream_t s, int64_t* pcg) {
+    const size_t n = (size_t)h->nRp * h->nS;
+    double* t = ws(h, W_ET);
+    residual_like(h, o, sv, r, t, o->pcg_tol_inner, s, pcg);
+    double* rhs = ws(h, W_CRHS);
+    double* uc = ws(h, W_CSOL);
+    k::coarse_project(h, t, rhs, s);
+    k::band_solve(h->Lc.p, h->LcT.p, h->nc, h->cbw, 1, 0, rhs, uc, 0, nullptr, 0, s);
+    k::fill(step, 0.0, n, s);
+    k::richardson_update(h, step, sv, uc, s);
+}
+
+}  // namespace
+
+void apply_E(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s, int64_t* pcg) {
+    apply_E_core(h, o, X, nullptr, nullptr, Y, o->pcg_tol_resid, s, pcg);
+}
+
+void apply_E0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s,
+                 int64_t* cgt, int* cgmax) {
+    e0inv(h, o, X, Y, s, cgt, cgmax);
+}
+
+void precond(Handle* h, const rte_solve_opts* o, int which, const double* r, double* out, hipStream_t s) {
+    const size_t n = (size_t)h->nRp * h->nS;
+    if (which == 0) {
+        apply_P1(h, o, r, out, s, nullptr, nullptr, nullptr);
+        return;
+    }
+    double* sv = ws(h, W_ES);
+    apply_P1(h, o, r, sv, s, nullptr, nullptr, nullptr);
+    correction_step(h, o, r, sv, out, s, nullptr);   // out = -s + W uc
+    k::axpby(0.0, out, -1.0, out, n, s);             // P2 P1 r = s - W uc
+}
+
+rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U, rte_solve_info* info,
+                 hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t n = (size_t)h->nRp * h->nS;
+    rte_solve_info inf{};
+    double* r = ws(h, W_ER);
+    double* sv = ws(h, W_ES);
+    double* step = ws(h, W_ESTEP);
+    if (U0) k::copy(U0, U, n, s);
+    else k::fill(U, 0.0, n, s);
+    double e1 = -1.0, step_rprev = 0.0;
+    bool have_step = false;
+    rte_status st = RTE_E_NOTCONV;
+    int it = 0;
+    for (;;) {
+        residual_like(h, o, U, h->q.p, r, o->pcg_tol_resid, s, &inf.pcg_iters_total);
+        const double rr = dot_dev(h, r, r, n, S_DOT0, s);
+        if (!std::isfinite(rr)) { st = RTE_E_NONFINITE; break; }
+        inf.rel_resid = std::sqrt(rr) / h->qnorm;
+        if (have_step) {
+            // ||u_n - u_{n-1}||^2_{E-K} = step^T (r_n - r_{n-1})
+            const double sr = dot_dev(h, step, r, n, S_DOT1, s);
+            const double en = std::sqrt(std::max(sr - step_rprev, 0.0));
+            if (e1 < 0) e1 = en;
+            inf.stop_quantity = e1 > 0 ? en / e1 : 0.0;
+        }
+        if (inf.rel_resid <= o->tol) { st = RTE_OK; break; }
+        if (it >= o->max_iter) { st = RTE_E_NOTCONV; break; }
+        apply_P1(h, o, r, sv, s, &inf.pcg_iters_total, &inf.cg_iters_total, &inf.cg_iters_max);
+        correction_step(h, o, r, sv, step, s, &inf.pcg_iters_total);
+        step_rprev = dot_dev(h, step, r, n, S_DOT2, s);
+        have_step = true;
+        k::axpby(1.0, step, 1.0, U, n, s);
+        ++it;
+    }
+    RTE_HIP(hipStreamSynchronize(s));
+    inf.iters = it;
+    inf.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return st;
+}
+
+}  // namespace rte

@@ -1,0 +1,234 @@
+"""ctypes binding of librte (include/rte.h): the same entry points, argument marshalling only.
+
+Device operands are torch tensors on ``cuda`` (their ``data_ptr()`` is passed through);
+the stream is torch's current stream unless given.  Every computation happens in
+librte's HIP kernels; there is no CPU fallback: importing this module without a built
+``librte.so`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librte.so")
+
+RTE_OK, RTE_E_ARG, RTE_E_PHYS, RTE_E_MESH, RTE_E_NOMEM, RTE_E_HIP, RTE_E_NOTCONV, RTE_E_NONFINITE = range(8)
+RTE_FP64, RTE_MIXED = 0, 1
+RTE_DT_F64, RTE_DT_F32, RTE_DT_BF16 = 0, 1, 2
+RTE_ODD_PCG, RTE_ODD_EXACT = 0, 1
+RTE_E0_CG, RTE_E0_BANDED = 0, 1
+ARRAY_SP, ARRAY_SM, ARRAY_M, ARRAY_T, ARRAY_Q, ARRAY_LAMP, ARRAY_WP, ARRAY_LAMM = range(8)
+STATUS_NAMES = ["OK", "E_ARG", "E_PHYS", "E_MESH", "E_NOMEM", "E_HIP", "E_NOTCONV", "E_NONFINITE"]
+
+
+class rte_problem_desc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_vert", C.c_int32), ("vert", C.POINTER(C.c_double)),
+                ("n_cell", C.c_int32), ("cell", C.POINTER(C.c_int32)),
+                ("sigma_t", C.POINTER(C.c_double)), ("sigma_s", C.POINTER(C.c_double)),
+                ("g", C.c_double), ("n_svert", C.c_int32), ("svert", C.POINTER(C.c_double)),
+                ("n_stri", C.c_int32), ("stri", C.POINTER(C.c_int32)),
+                ("q_nodal", C.POINTER(C.c_double)), ("g_inflow", C.POINTER(C.c_double))]
+
+
+class rte_assemble_opts(C.Structure):
+    _fields_ = [("quad_level", C.c_int32), ("n_even", C.c_int32), ("n_odd", C.c_int32),
+                ("e0_solver", C.c_int32), ("mixed", C.c_int32)]
+
+
+class rte_solve_opts(C.Structure):
+    _fields_ = [("l", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("precision", C.c_int32), ("odd_solver", C.c_int32), ("e0_solver", C.c_int32),
+                ("pcg_tol_resid", C.c_double), ("pcg_tol_inner", C.c_double),
+                ("pcg_max_iter", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32)]
+
+
+class rte_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("rel_resid", C.c_double), ("stop_quantity", C.c_double),
+                ("pcg_iters_total", C.c_int64), ("cg_iters_total", C.c_int64),
+                ("cg_iters_max", C.c_int32), ("t_solve", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = {
+    "rte_default_assemble_opts": (None, [C.POINTER(rte_assemble_opts)]),
+    "rte_default_solve_opts": (None, [C.POINTER(rte_solve_opts)]),
+    "rte_assemble": (C.c_int, [C.POINTER(rte_problem_desc), C.POINTER(rte_assemble_opts), C.c_void_p,
+                               C.POINTER(C.c_void_p)]),
+    "rte_query_dims": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int32)] * 4),
+    "rte_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "rte_apply_scatter": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                    C.c_void_p]),
+    "rte_apply_E": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rte_apply_E0inv": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rte_precond": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_int32, C.c_void_p, C.c_void_p,
+                              C.c_void_p]),
+    "rte_solve": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.POINTER(rte_solve_info), C.c_void_p]),
+    "rte_get_array": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
+    "rte_destroy": (C.c_int, [C.c_void_p]),
+    "rte_last_error": (C.c_char_p, []),
+}
+
+
+def load_library(path: str = _LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"librte.so not built at {path}; run paper_2102_09038_amd.build.build()")
+    lib = C.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = load_library()
+
+
+class RteError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 8 else status}: {msg}")
+        self.status = status
+
+
+def _check(st):
+    if st != RTE_OK:
+        raise RteError(st, lib.rte_last_error().decode())
+    return st
+
+
+def _dptr(a):
+    return C.cast(a.ctypes.data, C.POINTER(C.c_double))
+
+
+def _iptr(a):
+    return C.cast(a.ctypes.data, C.POINTER(C.c_int32))
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_assemble_opts(**kw) -> rte_assemble_opts:
+    o = rte_assemble_opts()
+    lib.rte_default_assemble_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def default_solve_opts(**kw) -> rte_solve_opts:
+    o = rte_solve_opts()
+    lib.rte_default_solve_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class Dims:
+    nRp: int
+    nRm: int
+    nSp: int
+    nSm: int
+
+
+class Handle:
+    """Owns an rte_handle; thin wrapper over the C entry points."""
+
+    def __init__(self, vert, cell, sigma_t, sigma_s, g, svert, stri, q_nodal, opts=None, stream=None,
+                 **opt_kw):
+        self._keep = [np.ascontiguousarray(vert, np.float64), np.ascontiguousarray(cell, np.int32),
+                      np.ascontiguousarray(sigma_t, np.float64), np.ascontiguousarray(sigma_s, np.float64),
+                      np.ascontiguousarray(svert, np.float64), np.ascontiguousarray(stri, np.int32),
+                      np.ascontiguousarray(q_nodal, np.float64)]
+        v, c, st, ss, sv, stt, q = self._keep
+        d = rte_problem_desc()
+        d.dim = v.shape[1]
+        d.n_vert = v.shape[0]
+        d.vert = _dptr(v)
+        d.n_cell = c.shape[0]
+        d.cell = _iptr(c)
+        d.sigma_t = _dptr(st)
+        d.sigma_s = _dptr(ss)
+        d.g = float(g)
+        d.n_svert = sv.shape[0]
+        d.svert = _dptr(sv)
+        d.n_stri = stt.shape[0]
+        d.stri = _iptr(stt)
+        d.q_nodal = _dptr(q)
+        d.g_inflow = None
+        self.desc = d
+        self.opts = opts if opts is not None else default_assemble_opts(**opt_kw)
+        h = C.c_void_p()
+        _check(lib.rte_assemble(C.byref(d), C.byref(self.opts), _stream(stream), C.byref(h)))
+        self.h = h
+        a = [C.c_int32() for _ in range(4)]
+        _check(lib.rte_query_dims(h, *[C.byref(x) for x in a]))
+        self.dims = Dims(*[x.value for x in a])
+
+    @classmethod
+    def from_instance(cls, inst, stream=None, **opt_kw):
+        kw = dict(quad_level=inst.quad_level, n_even=inst.n_even, n_odd=inst.n_odd)
+        kw.update(opt_kw)
+        return cls(inst.vert, inst.cell, inst.sigma_t, inst.sigma_s, inst.g, inst.svert, inst.stri,
+                   inst.q_nodal, stream=stream, **kw)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.rte_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def footprint(self) -> int:
+        b = C.c_size_t()
+        _check(lib.rte_footprint(self.h, C.byref(b)))
+        return b.value
+
+    def get_array(self, which: int, shape) -> np.ndarray:
+        out = np.empty(shape, dtype=np.float64, order="F")
+        _check(lib.rte_get_array(self.h, which, out.ctypes.data, out.nbytes))
+        return out
+
+    # --- operators on torch device tensors (column-major matrices are passed as the
+    #     transposed-contiguous storage: a (n_rows, n_cols) Fortran matrix == a torch tensor
+    #     of shape (n_cols, n_rows) contiguous)
+    def apply_scatter(self, parity, X, Y, dtype_in=RTE_DT_F64, dtype_out=RTE_DT_F64, stream=None):
+        _check(lib.rte_apply_scatter(self.h, parity, dtype_in, C.c_void_p(X.data_ptr()), dtype_out,
+                                     C.c_void_p(Y.data_ptr()), _stream(stream)))
+
+    def apply_E(self, X, Y, opts=None, stream=None):
+        o = opts or default_solve_opts()
+        _check(lib.rte_apply_E(self.h, C.byref(o), C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                               _stream(stream)))
+
+    def apply_E0inv(self, X, Y, opts=None, stream=None):
+        o = opts or default_solve_opts()
+        _check(lib.rte_apply_E0inv(self.h, C.byref(o), C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+                                   _stream(stream)))
+
+    def precond(self, which, r, s, opts=None, stream=None):
+        o = opts or default_solve_opts()
+        _check(lib.rte_precond(self.h, C.byref(o), which, C.c_void_p(r.data_ptr()), C.c_void_p(s.data_ptr()),
+                               _stream(stream)))
+
+    def solve(self, U, U0=None, opts=None, stream=None, raise_on_notconv=True):
+        o = opts or default_solve_opts()
+        info = rte_solve_info()
+        st = lib.rte_solve(self.h, C.byref(o), C.c_void_p(U0.data_ptr() if U0 is not None else 0),
+                           C.c_void_p(U.data_ptr()), None, C.byref(info), _stream(stream))
+        if st != RTE_OK and (raise_on_notconv or st != RTE_E_NOTCONV):
+            _check(st)
+        return st, info

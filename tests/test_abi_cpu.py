@@ -1,0 +1,73 @@
+"""Host-only checks of the C ABI: librte.so loads, exports every function declared in
+include/rte.h, and rejects invalid problem descriptions before any device work
+(no compute call is made here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2102_09038_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2102_09038_amd", "librte.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="librte.so not built")
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "rte.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rte_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    lib = C.CDLL(LIB)
+    names = header_functions()
+    assert "rte_solve" in names and "rte_assemble" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2102_09038_amd import rte
+    assert set(header_functions()) <= set(rte.EXPORTS)
+
+
+def test_defaults():
+    from paper_2102_09038_amd import rte
+    o = rte.default_solve_opts()
+    assert o.l == 4 and o.tol == 1e-8 and o.precision == rte.RTE_FP64
+    a = rte.default_assemble_opts()
+    assert a.n_odd == 5 and a.n_even == 0
+
+
+def _bad(**changes):
+    from paper_2102_09038_amd import rte
+    inst = inputs.tiny_instance(n=2, sphere_level=0)
+    kw = dict(vert=inst.vert, cell=inst.cell, sigma_t=inst.sigma_t, sigma_s=inst.sigma_s, g=inst.g,
+              svert=inst.svert, stri=inst.stri, q_nodal=inst.q_nodal)
+    kw.update(changes)
+    with pytest.raises(rte.RteError) as e:
+        rte.Handle(stream=0, **kw)
+    return e.value.status
+
+
+def test_validation_errors_before_device_work():
+    from paper_2102_09038_amd import rte
+    inst = inputs.tiny_instance(n=2, sphere_level=0)
+    assert _bad(g=1.0) == rte.RTE_E_PHYS
+    assert _bad(g=-0.1) == rte.RTE_E_PHYS
+    assert _bad(sigma_s=inst.sigma_t.copy()) == rte.RTE_E_PHYS            # c = 1
+    assert _bad(sigma_t=-inst.sigma_t) == rte.RTE_E_PHYS
+    st = inst.sigma_t.copy(); st[0] = np.nan
+    assert _bad(sigma_t=st) == rte.RTE_E_PHYS
+    cell = inst.cell.copy(); cell[0, 0] = 10 ** 6
+    assert _bad(cell=cell) == rte.RTE_E_MESH
+    stri = inst.stri.copy(); stri[-1] = stri[0]                            # antipode missing
+    assert _bad(stri=stri) in (rte.RTE_E_MESH,)
+    assert _bad(stri=inst.stri[:-1]) == rte.RTE_E_MESH                     # odd count
+    assert _bad(svert=inst.svert * 2) == rte.RTE_E_MESH                    # not unit vectors
+    q = inst.q_nodal.copy(); q[0] = np.inf
+    assert _bad(q_nodal=q) == rte.RTE_E_ARG

@@ -1,0 +1,171 @@
+"""GPU parity: every librte entry point against the FP64 oracle on the same seeded inputs.
+
+Bar (FP64): relative l2 (or max-abs relative to the array's max) <= 1e-10 for operators
+and converged iterates; assembled matrices <= 1e-12 (they differ only by summation
+order and the kernel's rsqrt vs the oracle's division).
+Sizes: tiny 2D/3D meshes (ragged GEMM tiles: 25 x 16 and 32 x 48 operands) and the
+16x16 / 128-triangle instance (several 128-wide tiles plus a ragged tail).
+"""
+import numpy as np
+import pytest
+
+from oracle.discretize import discretize_instance
+from oracle.operators import Operators
+from oracle.solver import richardson
+from paper_2102_09038_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def to_dev(U):
+    """(n_rows, n_cols) numpy matrix -> its column-major storage as a cuda tensor."""
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(U, dtype=np.float64).T)).cuda()
+
+
+def from_dev(t):
+    return t.cpu().numpy().T
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def make(inst, **kw):
+    from paper_2102_09038_amd import rte
+    D = discretize_instance(inst)
+    ops = Operators(D, n_even=inst.n_even, n_odd=inst.n_odd)
+    h = rte.Handle.from_instance(inst, **kw)
+    return D, ops, h
+
+
+def varied_ratio(inst, seed=5):
+    rng = np.random.default_rng(seed)
+    inst.sigma_s = inst.sigma_t * rng.uniform(0.5, 0.95, size=len(inst.sigma_t))
+    return inst
+
+
+CASES = {
+    "tiny2d": lambda: inputs.tiny_instance(n=4, sphere_level=1, g=0.5, ratio=0.9, n_even=2, n_odd=3, l=2),
+    "tiny2d-hetero": lambda: varied_ratio(inputs.tiny_instance(n=5, sphere_level=1, g=0.7, ratio=0.9,
+                                                               n_even=0, n_odd=3, l=3)),
+    "tiny3d": lambda: inputs.tiny_instance(n=2, sphere_level=1, g=0.6, ratio=0.9, dim=3, n_even=2, n_odd=1),
+    "small": inputs.config_small,
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    inst = CASES[request.param]()
+    print(f"[case {request.param}] nR+={len(inst.vert)} nS+={len(inst.stri)//2}", flush=True)
+    D, ops, h = make(inst)
+    yield request.param, inst, D, ops, h
+    h.close()
+
+
+def test_assembly(case):
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    nS = D.nS
+    assert h.dims.nRp == D.nRp and h.dims.nRm == D.nRm and h.dims.nSp == nS
+    Sp = h.get_array(rte.ARRAY_SP, (nS, nS))
+    Sm = h.get_array(rte.ARRAY_SM, (3 * nS, 3 * nS))
+    assert relmax(Sp, D.Sp) < 1e-12
+    assert relmax(Sm, D.Sm) < 1e-12
+    assert relmax(h.get_array(rte.ARRAY_M, (nS,)), D.m) < 1e-13
+    T = h.get_array(rte.ARRAY_T, (9 * nS,)).reshape(nS, 3, 3)
+    assert relmax(T, D.T) < 1e-13
+    q = h.get_array(rte.ARRAY_Q, (D.nRp, nS))
+    assert relmax(q, D.q) < 1e-13
+
+
+def test_eigenbases(case):
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    W, lam = ops.even_eig()
+    dN = W.shape[1]
+    lg = h.get_array(rte.ARRAY_LAMP, (dN,))
+    assert np.allclose(lg, lam, rtol=0, atol=1e-10)
+    Wg = h.get_array(rte.ARRAY_WP, (D.nS, dN))
+    # the spanned subspace is unique (eigenvectors are not, inside clusters)
+    assert relmax(Wg @ Wg.T, W @ W.T) < 1e-8
+    lm, _ = ops.odd_eig()
+    assert np.allclose(h.get_array(rte.ARRAY_LAMM, (3 * D.nS,)), lm, rtol=0, atol=1e-10)
+
+
+def test_scatter(case):
+    name, inst, D, ops, h = case
+    rng = np.random.default_rng(11)
+    U = rng.standard_normal((D.nRp, D.nS))
+    Y = torch.empty_like(to_dev(U))
+    h.apply_scatter(1, to_dev(U), Y)
+    assert rel(from_dev(Y), ops.K_even(U)) < 1e-12
+    V = rng.standard_normal((D.nRm, 3 * D.nS))
+    Yv = torch.empty_like(to_dev(V))
+    h.apply_scatter(-1, to_dev(V), Yv)
+    assert rel(from_dev(Yv), ops.K_odd(V)) < 1e-12
+
+
+@pytest.mark.parametrize("odd", ["pcg", "exact"])
+def test_apply_E(case, odd):
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    o = rte.default_solve_opts(pcg_tol_resid=1e-14, pcg_max_iter=500,
+                               odd_solver=rte.RTE_ODD_PCG if odd == "pcg" else rte.RTE_ODD_EXACT)
+    U = np.random.default_rng(12).standard_normal((D.nRp, D.nS))
+    Y = torch.empty_like(to_dev(U))
+    h.apply_E(to_dev(U), Y, o)
+    assert rel(from_dev(Y), ops.E(U)) < 1e-10
+
+
+def test_apply_E0inv(case):
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    o = rte.default_solve_opts(cg_tol=1e-14, cg_max_iter=50000)
+    B = np.random.default_rng(13).standard_normal((D.nRp, D.nS))
+    X = torch.empty_like(to_dev(B))
+    h.apply_E0inv(to_dev(B), X, o)
+    assert rel(from_dev(X), ops.E0_solve(B)) < 1e-10
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_precond(case, which):
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    o = rte.default_solve_opts(l=inst.l, cg_tol=1e-14, cg_max_iter=50000, pcg_tol_resid=1e-14,
+                               pcg_tol_inner=1e-14, pcg_max_iter=500)
+    r = np.random.default_rng(14).standard_normal((D.nRp, D.nS))
+    S = torch.empty_like(to_dev(r))
+    h.precond(which, to_dev(r), S, o)
+    ref = ops.P1(r, inst.l) if which == 0 else ops.P2P1(r, inst.l)
+    assert rel(from_dev(S), ref) < 1e-10
+
+
+def test_solve(case):
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    o = rte.default_solve_opts(l=inst.l, tol=1e-12, cg_tol=1e-13, cg_max_iter=50000, pcg_tol_resid=1e-14,
+                               pcg_tol_inner=1e-12, pcg_max_iter=500)
+    U = torch.empty((D.nS, D.nRp), dtype=torch.float64, device="cuda")
+    st, info = h.solve(U, opts=o)
+    uref, rinfo = richardson(ops, l=inst.l, tol=1e-12, max_iter=200)
+    print(f"[{name}] gpu iters {info.iters} rel_resid {info.rel_resid:.2e}  oracle iters {rinfo['iters']}")
+    assert info.rel_resid <= 1e-12
+    assert rel(from_dev(U), uref) < 1e-10
+    assert abs(info.iters - rinfo["iters"]) <= 1
+
+
+def test_deterministic(case):
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    o = rte.default_solve_opts(pcg_tol_resid=1e-12)
+    U = to_dev(np.random.default_rng(15).standard_normal((D.nRp, D.nS)))
+    Y1 = torch.empty_like(U)
+    Y2 = torch.empty_like(U)
+    h.apply_E(U, Y1, o)
+    h.apply_E(U, Y2, o)
+    assert torch.equal(Y1, Y2)
