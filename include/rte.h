@@ -113,6 +113,8 @@ typedef struct rte_solve_opts {
     int32_t pcg_max_iter;        /* PCG iteration cap per E application                      */
     double cg_tol;               /* relative CG tolerance per E_0 block                      */
     int32_t cg_max_iter;         /* CG iteration cap per E_0 block                           */
+    int32_t profile;             /* nonzero: time the E_0 solves and the scattering GEMMs with
+                                    HIP events on hip_stream (rte_solve_info.t_*)            */
 } rte_solve_opts;
 
 typedef struct rte_solve_info {
@@ -123,12 +125,18 @@ typedef struct rte_solve_info {
     int64_t cg_iters_total;      /* sum over directions of E_0 CG iterations                 */
     int32_t cg_iters_max;        /* largest per-direction CG count in one E_0 application    */
     double t_solve;              /* seconds spent in rte_solve                               */
+    double t_e0inv;              /* with opts->profile: seconds inside E_0^{-1} kernels      */
+    int64_t n_e0inv;             /*   number of E_0^{-1} launches                            */
+    double t_gemm;               /*   seconds inside scattering / odd-inverse GEMM kernels   */
+    int64_t n_gemm;              /*   number of those GEMM launches                          */
+    double gemm_flops;           /*   their algorithmic flops (2 M N K summed)               */
 } rte_solve_info;
 
 /* Fill opts with the defaults: quad_level 2, N+ 0, N- 5, CG E_0, no mixed copies. */
 void rte_default_assemble_opts(rte_assemble_opts* opts);
 /* Defaults: l 4, tol 1e-8, max_iter 200, FP64, PCG odd solve, CG E_0, PCG tolerances
- * 1e-12 (residual) / 1e-10 (inner), pcg_max_iter 200, cg_tol 1e-10, cg_max_iter 20000. */
+ * 1e-12 (residual) / 1e-10 (inner), pcg_max_iter 200, cg_tol 1e-10, cg_max_iter 20000,
+ * profile 0. */
 void rte_default_solve_opts(rte_solve_opts* opts);
 
 /* Validate the problem and assemble every operator of the mixed system (Sec. 4) on
@@ -144,6 +152,10 @@ rte_status rte_assemble(const rte_problem_desc* desc, const rte_assemble_opts* o
 /* Dimensions: n_R+ (vertices), n_R- (cells), n_S+ (antipodal pairs), n_S- = 3 n_S+. */
 rte_status rte_query_dims(const rte_handle* h, int32_t* nRp, int32_t* nRm, int32_t* nSp,
                           int32_t* nSm);
+
+/* Band widths of the factored systems: the E_0 blocks (n_R+ unknowns each; 0 when no
+ * banded E_0 factors were prepared) and the coarse matrix E_c (coarse_n unknowns). */
+rte_status rte_query_band(const rte_handle* h, int32_t* e0_bw, int32_t* coarse_n, int32_t* coarse_bw);
 
 /* Device bytes the handle holds (operators and solver workspace at full size). */
 rte_status rte_footprint(const rte_handle* h, size_t* bytes);

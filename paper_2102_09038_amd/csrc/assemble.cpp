@@ -150,12 +150,21 @@ void band_cholesky(Vec& A, int n, int bw) {
     for (int i = 0; i < n; ++i) A[w1 * i + bw] = 1.0 / A[w1 * i + bw];
 }
 
-Vec band_transpose(const Vec& L, int n, int bw) {
+// row-major lower band (band[r*(bw+1) + t], t = bw + c - r) -> blocked layout of
+// kernels_band.hip: BL[((r/64)(bw+1) + t) 64 + r%64]
+Vec band_to_blocked(const Vec& band, int n, int bw) {
     const size_t w1 = (size_t)bw + 1;
-    Vec U(L.size(), 0.0);
-    for (int i = 0; i < n; ++i)
-        for (int j = std::max(0, i - bw); j <= i; ++j) U[w1 * j + (i - j)] = L[w1 * i + bw + j - i];
-    return U;
+    Vec out((size_t)((n + 63) / 64) * w1 * 64, 0.0);
+    for (int r = 0; r < n; ++r)
+        for (size_t t = 0; t < w1; ++t) out[((size_t)(r >> 6) * w1 + t) * 64 + (r & 63)] = band[(size_t)r * w1 + t];
+    return out;
+}
+
+int band_width(const std::vector<int>& perm, const std::vector<int>& rp, const std::vector<int>& ci) {
+    int bw = 0;
+    for (size_t i = 0; i + 1 < rp.size(); ++i)
+        for (int e = rp[i]; e < rp[i + 1]; ++e) bw = std::max(bw, std::abs(perm[i] - perm[ci[e]]));
+    return bw;
 }
 
 // reverse Cuthill-McKee on the P1 graph; returns perm[i] = new position of vertex i
@@ -219,6 +228,8 @@ void syevd(RocblasCtx& rb, hipStream_t s, int n, Vec& A, Vec& lam) {
 Handle::~Handle() {
     if (stream) (void)hipStreamSynchronize(stream);
     if (pinned) (void)hipHostFree(pinned);
+    for (auto& r : prof) { evpool.push_back(r.a); evpool.push_back(r.b); }
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
 }
 
 size_t Handle::footprint() const {
@@ -226,7 +237,7 @@ size_t Handle::footprint() const {
                Wp.bytes() + Hodd.bytes() + Wfull.bytes() + WfullT.bytes() + lam_full.bytes() + cell.bytes() +
                Dc.bytes() + mt.bytes() + ms.bytes() + rowptr.bytes() + col.bytes() + Msv.bytes() + cls.bytes() +
                coefE0.bytes() + coefE.bytes() + diagE0.bytes() + vc_ptr.bytes() + vc_cell.bytes() + vc_loc.bytes() +
-               q.bytes() + Lc.bytes() + LcT.bytes() + perm.bytes() + L0.bytes() + L0T.bytes() + e0perm.bytes() +
+               q.bytes() + Lc.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() +
                Sp_bf.bytes() + Sm_bf.bytes() + Hodd_bf.bytes() + Wfull_bf.bytes() + WfullT_bf.bytes() + red.bytes() +
                scal.bytes();
     for (auto& w : ws) b += w.bytes();
@@ -726,11 +737,16 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
                         }
             return Gcache.emplace(delta, std::move(G)).first->second;
         };
-        // ordering
+        // ordering: reverse Cuthill-McKee or the given vertex order, whichever is narrower
         std::vector<int> perm = rcm(nRp, rp, ci);
-        int sbw = 0;
-        for (int i = 0; i < nRp; ++i)
-            for (int e = rp[i]; e < rp[i + 1]; ++e) sbw = std::max(sbw, std::abs(perm[i] - perm[ci[e]]));
+        std::vector<int> ident(nRp);
+        std::iota(ident.begin(), ident.end(), 0);
+        int sbw = band_width(perm, rp, ci);
+        const int sbw_nat = band_width(ident, rp, ci);
+        if (sbw_nat <= sbw) { perm = ident; sbw = sbw_nat; }
+        std::vector<int> iperm(nRp);
+        for (int i = 0; i < nRp; ++i) iperm[perm[i]] = i;
+        h.sbw = sbw;
         const int nc = dN * nRp;
         const int bw = dN * sbw + dN - 1;
         const size_t w1 = (size_t)bw + 1;
@@ -782,12 +798,28 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         band_cholesky(band, nc, bw);
         h.nc = nc;
         h.cbw = bw;
-        h.Lc.upload(band, s);
-        h.LcT.upload(band_transpose(band, nc, bw), s);
+        h.Lc.upload(band_to_blocked(band, nc, bw), s);
         h.perm.upload(perm, s);
+        h.iperm.upload(iperm, s);
     }
     h.h_Sp.clear();
     h.h_Sp.shrink_to_fit();
+
+    // ------------------------------------------------------------------ banded E_0 factors
+    if (o->e0_solver == RTE_E0_BANDED) {
+        h.e0_stride = k::band_blk_size(nRp, h.sbw);
+        h.L0.alloc(h.e0_stride * nS);
+        DBuf<int> bad(1);
+        RTE_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+        k::e0_band_factor(&h, h.sbw, h.perm.p, h.iperm.p, h.L0.p, h.e0_stride, bad.p, s);
+        int hb = 0;
+        RTE_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        RTE_HIP(hipStreamSynchronize(s));
+        if (hb) fail(RTE_E_ARG, "an E_0 block lost positive definiteness in the band factorisation");
+        h.have_e0_banded = true;
+    } else if (o->e0_solver != RTE_E0_CG) {
+        fail(RTE_E_ARG, "unknown e0_solver");
+    }
 
     // ------------------------------------------------------------------ BF16 copies
     if (o->mixed) {

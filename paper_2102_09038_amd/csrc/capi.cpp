@@ -69,6 +69,7 @@ void rte_default_solve_opts(rte_solve_opts* o) {
     o->pcg_max_iter = 200;
     o->cg_tol = 1e-10;
     o->cg_max_iter = 20000;
+    o->profile = 0;
 }
 
 rte_status rte_assemble(const rte_problem_desc* desc, const rte_assemble_opts* opts, void* hip_stream,
@@ -89,6 +90,16 @@ rte_status rte_query_dims(const rte_handle* hh, int32_t* nRp, int32_t* nRm, int3
         if (nRm) *nRm = h->nRm;
         if (nSp) *nSp = h->nS;
         if (nSm) *nSm = h->nSm;
+        return RTE_OK;
+    });
+}
+
+rte_status rte_query_band(const rte_handle* hh, int32_t* e0_bw, int32_t* coarse_n, int32_t* coarse_bw) {
+    return guarded([&] {
+        const rte::Handle* h = as_handle(const_cast<rte_handle*>(hh));
+        if (e0_bw) *e0_bw = h->have_e0_banded ? h->sbw : 0;
+        if (coarse_n) *coarse_n = h->nc;
+        if (coarse_bw) *coarse_bw = h->cbw;
         return RTE_OK;
     });
 }

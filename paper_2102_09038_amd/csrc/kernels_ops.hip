@@ -320,97 +320,6 @@ __global__ __launch_bounds__(TPB) void richardson_update_kernel(int nRp, int nS,
     U[t] = v;
 }
 
-// Banded Cholesky solve L L^T x = b for one system per 64-lane work-group.
-// L: lower band by rows, L[i*(bw+1) + bw + j - i] = L(i,j), diagonal stored inverted.
-// LT: upper band of L^T by rows, LT[i*(bw+1) + j - i] = L(j,i), diagonal stored inverted.
-// Rows are processed in blocks of 64: lane l owns row 64B + l; the contribution of
-// earlier blocks is a per-lane dot product over the band (no cross-lane reduction); the
-// 64 x 64 triangular diagonal block is solved with the block's coefficients held in
-// registers and one broadcast per row.  The solution window lives in LDS.
-constexpr int BS_WIN = 8192;   // LDS window (doubles), must exceed bw + 64
-
-__global__ __launch_bounds__(64) void band_solve_kernel(const double* __restrict__ Lb,
-                                                        const double* __restrict__ LTb, int n, int bw,
-                                                        size_t stride_sys, const double* __restrict__ bb,
-                                                        double* __restrict__ xb, size_t stride_vec,
-                                                        const int* __restrict__ iperm) {
-    __shared__ double win[BS_WIN];
-    const int sys = blockIdx.x;
-    const double* L = Lb + stride_sys * sys;
-    const double* LT = LTb + stride_sys * sys;
-    const double* b = bb + stride_vec * sys;
-    double* x = xb + stride_vec * sys;
-    const int lane = threadIdx.x;
-    const size_t w1 = (size_t)bw + 1;
-    const int nblk = (n + 63) / 64;
-    // ---- forward: L y = b   (y kept in win, indices modulo BS_WIN)
-    for (int B = 0; B < nblk; ++B) {
-        const int row = 64 * B + lane;
-        const bool ok = row < n;
-        double s = 0.0, invd = 0.0;
-        double Ld[64];
-        if (ok) {
-            s = b[iperm ? iperm[row] : row];
-            const double* Lr = L + w1 * row;     // Lr[bw + j - row] = L(row, j)
-            const int j0 = max(0, row - bw);
-            for (int j = j0; j < 64 * B; ++j) s = fma(-Lr[bw + j - row], win[j % BS_WIN], s);
-            invd = Lr[bw];
-#pragma unroll
-            for (int u = 0; u < 64; ++u) {
-                const int j = 64 * B + u;
-                Ld[u] = (u < lane && j >= row - bw) ? Lr[bw + j - row] : 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < 64; ++u) Ld[u] = 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 64; ++u) {
-            const double yu = __shfl(s * invd, u, 64);
-            s = fma(-Ld[u], yu, s);
-        }
-        if (ok) {
-            const double yv = s * invd;
-            win[row % BS_WIN] = yv;
-            x[iperm ? iperm[row] : row] = yv;   // kept for the backward sweep
-        }
-        __syncthreads();
-    }
-    // ---- backward: L^T x = y
-    for (int B = nblk - 1; B >= 0; --B) {
-        const int row = 64 * B + lane;
-        const bool ok = row < n;
-        double s = 0.0, invd = 0.0;
-        double Ud[64];
-        if (ok) {
-            s = x[iperm ? iperm[row] : row];
-            const double* Ur = LT + w1 * row;    // Ur[j - row] = L(j, row)
-            const int j1 = min(n - 1, row + bw);
-            for (int j = 64 * B + 64; j <= j1; ++j) s = fma(-Ur[j - row], win[j % BS_WIN], s);
-            invd = Ur[0];
-#pragma unroll
-            for (int u = 0; u < 64; ++u) {
-                const int j = 64 * B + u;
-                Ud[u] = (u > lane && j <= row + bw && j < n) ? Ur[j - row] : 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < 64; ++u) Ud[u] = 0.0;
-        }
-#pragma unroll
-        for (int u = 63; u >= 0; --u) {
-            const double xu = __shfl(s * invd, u, 64);
-            s = fma(-Ud[u], xu, s);
-        }
-        if (ok) {
-            const double xv = s * invd;
-            win[row % BS_WIN] = xv;
-            x[iperm ? iperm[row] : row] = xv;
-        }
-        __syncthreads();
-    }
-}
-
 // ----------------------------------------------------------------------------- E_0
 // Jacobi-preconditioned CG, one 256-thread work-group per direction, all iterations in
 // one launch (no grid-wide synchronisation: directions are independent).  Vectors live
@@ -665,14 +574,6 @@ void scale_eigbasis(const Handle* h, double* C, hipStream_t s) {
 
 void coarse_project(const Handle* h, const double* T, double* rhs, hipStream_t s) {
     dispatch_dn<CoarseProjectL>(h->dNp, h, T, rhs, s);
-    RTE_CHECK_LAUNCH();
-}
-
-void band_solve(const double* L, const double* LT, int n, int bw, int nsys, size_t stride_sys,
-                const double* b, double* x, size_t stride_vec, const int* iperm, int, hipStream_t s) {
-    if (bw + 64 >= BS_WIN) fail(RTE_E_ARG, "band too wide for the LDS window");
-    hipLaunchKernelGGL(band_solve_kernel, dim3(nsys), dim3(64), 0, s, L, LT, n, bw, stride_sys, b, x,
-                       stride_vec, iperm);
     RTE_CHECK_LAUNCH();
 }
 

@@ -49,10 +49,15 @@ void scale_eigbasis(const Handle* h, double* C, hipStream_t s);
 // ---- coarse correction (Sec. 5.4)
 // rhs[a + dN*perm[i]] = sum_k T[i,k] Wp[k,a]
 void coarse_project(const Handle* h, const double* T, double* rhs, hipStream_t s);
-// x = L^{-T} L^{-1} b for nsys independent banded systems (one wavefront each)
-void band_solve(const double* L, const double* LT, int n, int bw, int nsys, size_t stride_sys,
-                const double* b, double* x, size_t stride_vec, const int* perm, int perm_mode,
-                hipStream_t s);
+// blocked band storage size (doubles) of an n x n matrix of band width bw
+size_t band_blk_size(int n, int bw);
+// x = L^{-T} L^{-1} b for nsys systems with blocked band factors (kernels_band.hip);
+// b and x are read / written at iperm[band row] when iperm is given
+void band_solve_blk(const double* BL, int n, int bw, int nsys, size_t stride_sys, const double* b, double* x,
+                    size_t stride_vec, const int* iperm, hipStream_t s);
+// factor every E_0 block (one work-group per direction); *bad |= 1 on a non-positive pivot
+void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, double* BL, size_t stride_sys,
+                    int* bad, hipStream_t s);
 // U = U - S + sum_a uc[a + dN*perm[i]] Wp[k, a]
 void richardson_update(const Handle* h, double* U, const double* S, const double* uc,
                        hipStream_t s);

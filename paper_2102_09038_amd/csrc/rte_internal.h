@@ -126,14 +126,14 @@ struct Handle {
 
     // ---- coarse (Sec. 5.4): banded Cholesky of E_c in the order a + dNp * perm[i]
     int nc = 0, cbw = 0;
-    DBuf<double> Lc, LcT;          // [nc*(cbw+1)] lower band by rows, its transpose by rows
-    DBuf<int> perm;                // [nRp] spatial reordering (reverse Cuthill-McKee)
+    DBuf<double> Lc;               // blocked band factor (kernels_band.hip layout)
+    DBuf<int> perm, iperm;         // [nRp] spatial reordering (reverse Cuthill-McKee) and inverse
+    int sbw = 0;                   // spatial band width in that order
 
-    // ---- banded E_0 (RTE_E0_BANDED)
+    // ---- banded E_0 (RTE_E0_BANDED): one blocked band factor per direction
     bool have_e0_banded = false;
-    int ebw = 0;
-    DBuf<double> L0, L0T;          // [nS][nRp*(ebw+1)]
-    DBuf<int> e0perm;              // [nRp]
+    size_t e0_stride = 0;
+    DBuf<double> L0;               // [nS * e0_stride]
 
     // ---- BF16 copies (mixed precision)
     bool have_mixed = false;
@@ -146,7 +146,12 @@ struct Handle {
     DBuf<double> scal;             // device scalars
     std::vector<double> hscal;
     double* pinned = nullptr;      // small pinned host buffer for scalar readback
-    void* rocblas = nullptr;       // rocblas handle for setup eigensolves
+
+    // ---- optional kernel timers (rte_solve_opts.profile): HIP events around launches
+    struct ProfRec { int kind; hipEvent_t a, b; double flops; };
+    bool prof_on = false;
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> evpool;
 
     ~Handle();
     size_t footprint() const;

@@ -43,6 +43,61 @@ double* ws(Handle* h, int id) {
     return b.p;
 }
 
+// ----------------------------------------------------------------------------- timers
+enum ProfKind { P_E0 = 0, P_GEMM = 1 };
+
+hipEvent_t take_event(Handle* h) {
+    if (h->evpool.empty()) {
+        hipEvent_t e;
+        RTE_HIP(hipEventCreate(&e));
+        return e;
+    }
+    hipEvent_t e = h->evpool.back();
+    h->evpool.pop_back();
+    return e;
+}
+
+// RAII: records an event pair around the enclosed launches when profiling is on
+struct Timed {
+    Handle* h;
+    hipStream_t s;
+    int kind;
+    double flops;
+    hipEvent_t a = nullptr;
+    Timed(Handle* h_, hipStream_t s_, int kind_, double flops_ = 0) : h(h_), s(s_), kind(kind_), flops(flops_) {
+        if (h->prof_on) {
+            a = take_event(h);
+            RTE_HIP(hipEventRecord(a, s));
+        }
+    }
+    ~Timed() {
+        if (a) {
+            hipEvent_t b = take_event(h);
+            (void)hipEventRecord(b, s);
+            h->prof.push_back({kind, a, b, flops});
+        }
+    }
+};
+
+void gemm(Handle* h, int M, int N, int K, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+          hipStream_t s) {
+    Timed t(h, s, P_GEMM, 2.0 * M * N * (double)K);
+    k::gemm_f64(M, N, K, 1.0, A, lda, B, ldb, 0.0, C, ldc, s);
+}
+
+void collect_profile(Handle* h, rte_solve_info* inf) {
+    for (auto& r : h->prof) {
+        float ms = 0.f;
+        RTE_HIP(hipEventSynchronize(r.b));
+        RTE_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        if (r.kind == P_E0) { inf->t_e0inv += ms * 1e-3; inf->n_e0inv += 1; }
+        else { inf->t_gemm += ms * 1e-3; inf->n_gemm += 1; inf->gemm_flops += r.flops; }
+        h->evpool.push_back(r.a);
+        h->evpool.push_back(r.b);
+    }
+    h->prof.clear();
+}
+
 double read_scalar(Handle* h, int slot, hipStream_t s) {
     RTE_HIP(hipMemcpyAsync(h->pinned, h->scal.p + slot, sizeof(double), hipMemcpyDeviceToHost, s));
     RTE_HIP(hipStreamSynchronize(s));
@@ -81,7 +136,7 @@ int odd_pcg(Handle* h, const double* B, double* Z, double tol, int maxit, hipStr
     int it = 0;
     const double stop = tol * tol * bb;
     while (it < maxit) {
-        k::gemm_f64(h->nRm, h->nSm, h->nSm, 1.0, P, h->nRm, h->Sm.p, h->nSm, 0.0, G, h->nRm, s);
+        gemm(h, h->nRm, h->nSm, h->nSm, P, h->nRm, h->Sm.p, h->nSm, G, h->nRm, s);
         k::odd_apply(h, P, G, W, h->red.p, s);
         k::reduce(h->red.p, h->scal.p, S_PW, s);
         k::sdiv(h->scal.p, S_ALPHA, rz, S_PW, s);
@@ -105,13 +160,13 @@ void odd_exact(Handle* h, const double* B, double* Z, hipStream_t s) {
     const int nRm = h->nRm, nSm = h->nSm;
     if (h->uniform_delta) {
         double* G = ws(h, W_OG);
-        k::gemm_f64(nRm, nSm, nSm, 1.0, B, nRm, h->Hodd.p, nSm, 0.0, G, nRm, s);
+        gemm(h, nRm, nSm, nSm, B, nRm, h->Hodd.p, nSm, G, nRm, s);
         k::row_scale_inv_mt(h, G, Z, nSm, s);
     } else {
         double* C = ws(h, W_OG);
-        k::gemm_f64(nRm, nSm, nSm, 1.0, B, nRm, h->Wfull.p, nSm, 0.0, C, nRm, s);
+        gemm(h, nRm, nSm, nSm, B, nRm, h->Wfull.p, nSm, C, nRm, s);
         k::scale_eigbasis(h, C, s);
-        k::gemm_f64(nRm, nSm, nSm, 1.0, C, nRm, h->WfullT.p, nSm, 0.0, Z, nRm, s);
+        gemm(h, nRm, nSm, nSm, C, nRm, h->WfullT.p, nSm, Z, nRm, s);
     }
 }
 
@@ -134,7 +189,7 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
 void residual_like(Handle* h, const rte_solve_opts* o, const double* X, const double* q0, double* Y,
                    double tol, hipStream_t s, int64_t* pcg) {
     double* G = ws(h, W_EG);
-    k::gemm_f64(h->nRp, h->nS, h->nS, 1.0, X, h->nRp, h->Sp.p, h->nS, 0.0, G, h->nRp, s);
+    gemm(h, h->nRp, h->nS, h->nS, X, h->nRp, h->Sp.p, h->nS, G, h->nRp, s);
     apply_E_core(h, o, X, G, q0, Y, tol, s, pcg);
 }
 
@@ -142,8 +197,8 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
            int* cgmax) {
     if (o->e0_solver == RTE_E0_BANDED) {
         if (!h->have_e0_banded) fail(RTE_E_ARG, "banded E_0 factors were not prepared at assembly");
-        k::band_solve(h->L0.p, h->L0T.p, h->nRp, h->ebw, h->nS, (size_t)h->nRp * (h->ebw + 1), X, Y,
-                      (size_t)h->nRp, h->e0perm.p, 0, s);
+        Timed t(h, s, P_E0);
+        k::band_solve_blk(h->L0.p, h->nRp, h->sbw, h->nS, h->e0_stride, X, Y, (size_t)h->nRp, h->iperm.p, s);
         return;
     }
     double* r = ws(h, W_CGR);
@@ -151,7 +206,10 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
     double* q = ws(h, W_CGQ);
     DBuf<int>& iters = h->cg_iters;
     if (iters.n < (size_t)h->nS) iters.alloc(h->nS);
-    k::e0_cg(h, X, Y, r, p, q, o->cg_tol, o->cg_max_iter, iters.p, s);
+    {
+        Timed t(h, s, P_E0);
+        k::e0_cg(h, X, Y, r, p, q, o->cg_tol, o->cg_max_iter, iters.p, s);
+    }
     if (cgt || cgmax) {
         std::vector<int> hi(h->nS);
         RTE_HIP(hipMemcpyAsync(hi.data(), iters.p, h->nS * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -187,7 +245,7 @@ void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const 
     double* rhs = ws(h, W_CRHS);
     double* uc = ws(h, W_CSOL);
     k::coarse_project(h, t, rhs, s);
-    k::band_solve(h->Lc.p, h->LcT.p, h->nc, h->cbw, 1, 0, rhs, uc, 0, nullptr, 0, s);
+    k::band_solve_blk(h->Lc.p, h->nc, h->cbw, 1, 0, rhs, uc, 0, nullptr, s);
     k::fill(step, 0.0, n, s);
     k::richardson_update(h, step, sv, uc, s);
 }
@@ -220,6 +278,8 @@ rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U
     const auto t0 = std::chrono::steady_clock::now();
     const size_t n = (size_t)h->nRp * h->nS;
     rte_solve_info inf{};
+    h->prof_on = o->profile != 0;
+    h->prof.clear();
     double* r = ws(h, W_ER);
     double* sv = ws(h, W_ES);
     double* step = ws(h, W_ESTEP);
@@ -251,6 +311,8 @@ rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U
         ++it;
     }
     RTE_HIP(hipStreamSynchronize(s));
+    collect_profile(h, &inf);
+    h->prof_on = false;
     inf.iters = it;
     inf.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;

@@ -42,13 +42,16 @@ class rte_solve_opts(C.Structure):
     _fields_ = [("l", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("odd_solver", C.c_int32), ("e0_solver", C.c_int32),
                 ("pcg_tol_resid", C.c_double), ("pcg_tol_inner", C.c_double),
-                ("pcg_max_iter", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32)]
+                ("pcg_max_iter", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32),
+                ("profile", C.c_int32)]
 
 
 class rte_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("rel_resid", C.c_double), ("stop_quantity", C.c_double),
                 ("pcg_iters_total", C.c_int64), ("cg_iters_total", C.c_int64),
-                ("cg_iters_max", C.c_int32), ("t_solve", C.c_double)]
+                ("cg_iters_max", C.c_int32), ("t_solve", C.c_double), ("t_e0inv", C.c_double),
+                ("n_e0inv", C.c_int64), ("t_gemm", C.c_double), ("n_gemm", C.c_int64),
+                ("gemm_flops", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -61,6 +64,7 @@ EXPORTS = {
                                C.POINTER(C.c_void_p)]),
     "rte_query_dims": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int32)] * 4),
     "rte_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "rte_query_band": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int32)] * 3),
     "rte_apply_scatter": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                     C.c_void_p]),
     "rte_apply_E": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -196,6 +200,12 @@ class Handle:
         b = C.c_size_t()
         _check(lib.rte_footprint(self.h, C.byref(b)))
         return b.value
+
+    def band(self):
+        """(E_0 band width, coarse unknowns, coarse band width)."""
+        a = [C.c_int32() for _ in range(3)]
+        _check(lib.rte_query_band(self.h, *[C.byref(x) for x in a]))
+        return tuple(x.value for x in a)
 
     def get_array(self, which: int, shape) -> np.ndarray:
         out = np.empty(shape, dtype=np.float64, order="F")

@@ -62,7 +62,8 @@ CASES = {
 def case(request):
     inst = CASES[request.param]()
     print(f"[case {request.param}] nR+={len(inst.vert)} nS+={len(inst.stri)//2}", flush=True)
-    D, ops, h = make(inst)
+    from paper_2102_09038_amd import rte
+    D, ops, h = make(inst, e0_solver=rte.RTE_E0_BANDED)
     yield request.param, inst, D, ops, h
     h.close()
 
@@ -122,10 +123,12 @@ def test_apply_E(case, odd):
     assert rel(from_dev(Y), ops.E(U)) < 1e-10
 
 
-def test_apply_E0inv(case):
+@pytest.mark.parametrize("e0", ["cg", "banded"])
+def test_apply_E0inv(case, e0):
     from paper_2102_09038_amd import rte
     name, inst, D, ops, h = case
-    o = rte.default_solve_opts(cg_tol=1e-14, cg_max_iter=50000)
+    o = rte.default_solve_opts(cg_tol=1e-14, cg_max_iter=50000,
+                               e0_solver=rte.RTE_E0_CG if e0 == "cg" else rte.RTE_E0_BANDED)
     B = np.random.default_rng(13).standard_normal((D.nRp, D.nS))
     X = torch.empty_like(to_dev(B))
     h.apply_E0inv(to_dev(B), X, o)
@@ -145,15 +148,19 @@ def test_precond(case, which):
     assert rel(from_dev(S), ref) < 1e-10
 
 
-def test_solve(case):
+@pytest.mark.parametrize("path", ["pcg-cg", "exact-banded"])
+def test_solve(case, path):
     from paper_2102_09038_amd import rte
     name, inst, D, ops, h = case
     o = rte.default_solve_opts(l=inst.l, tol=1e-12, cg_tol=1e-13, cg_max_iter=50000, pcg_tol_resid=1e-14,
                                pcg_tol_inner=1e-12, pcg_max_iter=500)
+    if path == "exact-banded":
+        o.odd_solver = rte.RTE_ODD_EXACT
+        o.e0_solver = rte.RTE_E0_BANDED
     U = torch.empty((D.nS, D.nRp), dtype=torch.float64, device="cuda")
     st, info = h.solve(U, opts=o)
     uref, rinfo = richardson(ops, l=inst.l, tol=1e-12, max_iter=200)
-    print(f"[{name}] gpu iters {info.iters} rel_resid {info.rel_resid:.2e}  oracle iters {rinfo['iters']}")
+    print(f"[{name} {path}] gpu iters {info.iters} rel_resid {info.rel_resid:.2e}  oracle iters {rinfo['iters']}")
     assert info.rel_resid <= 1e-12
     assert rel(from_dev(U), uref) < 1e-10
     assert abs(info.iters - rinfo["iters"]) <= 1
