@@ -120,7 +120,7 @@ def main():
     h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED)
     d = h.dims
     e0_bw, _, _ = h.band()
-    opts = rte.default_solve_opts(l=inst.l, tol=args.tol, max_iter=1000, odd_solver=rte.RTE_ODD_EXACT,
+    opts = rte.default_solve_opts(l=inst.l, tol=args.tol, max_iter=1000, odd_solver=rte.RTE_ODD_CONDENSED,
                                   e0_solver=rte.RTE_E0_BANDED, pcg_tol_inner=1e-6, profile=1)
     U = torch.empty((d.nSp, d.nRp), dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
@@ -165,7 +165,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": inst.name, "n_R+": d.nRp, "n_R-": d.nRm, "n_S+": d.nSp, "n_S-": d.nSm,
                    "tol": args.tol, "l": inst.l, "N+": inst.n_even, "N-": inst.n_odd,
-                   "odd_solver": "exact", "e0_solver": "banded", "e0_band": e0_bw, "precision": "fp64"},
+                   "odd_solver": "condensed", "e0_solver": "banded", "e0_band": e0_bw, "precision": "fp64"},
         "iters": [i.iters for i in infos], "rel_resid": [i.rel_resid for i in infos],
         "roofline": dominant, "roofline_other": other,
         "scatter_gemm_tflops": gemm_tf,

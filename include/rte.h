@@ -56,9 +56,15 @@ typedef enum rte_dtype { RTE_DT_F64 = 0, RTE_DT_F32 = 1, RTE_DT_BF16 = 2 } rte_d
 /* How (M- - K-)^{-1} is applied inside E (Sec. 5.1, Alg. 1). */
 typedef enum rte_odd_solver {
     RTE_ODD_PCG = 0,      /* PCG preconditioned by (M- - K-_N)^{-1} (Lemma in Sec. 5.1) */
-    RTE_ODD_EXACT = 1     /* exact: per-cell inverse through the full eigendecomposition
+    RTE_ODD_EXACT = 1,    /* exact: per-cell inverse through the full eigendecomposition
                              of (S-, M_S-); one GEMM when sigma_s/sigma_t is uniform,
                              two otherwise                                            */
+    RTE_ODD_CONDENSED = 2 /* exact, condensed onto the d spatial directions: with a
+                             uniform ratio delta, A^T (M- - K-)^{-1} A X =
+                             sum_{n,n'} D_n^T Mt-^{-1} D_n' X G_{n'n}, where
+                             G_{n'n} = A_n'^T (M_S- - delta S-)^{-1} A_n is precomputed
+                             (one GEMM with N = K = d n_S+); RTE_E_ARG if the ratio
+                             varies between cells                                    */
 } rte_odd_solver;
 
 /* How each block of E_0^{-1} is applied (Sec. 5.3). */

@@ -152,11 +152,18 @@ void band_cholesky(Vec& A, int n, int bw) {
 
 // row-major lower band (band[r*(bw+1) + t], t = bw + c - r) -> blocked layout of
 // kernels_band.hip: BL[((r/64)(bw+1) + t) 64 + r%64]
-Vec band_to_blocked(const Vec& band, int n, int bw) {
+// (upper = false), or of its transpose, BU[((r/64)(bw+1) + t) 64 + r%64] = L(r+t, r)
+// (upper = true); both padded with k::band_pad() zeros
+Vec band_to_blocked(const Vec& band, int n, int bw, bool upper) {
     const size_t w1 = (size_t)bw + 1;
-    Vec out((size_t)((n + 63) / 64) * w1 * 64, 0.0);
+    Vec out((size_t)((n + 63) / 64) * w1 * 64 + k::band_pad(), 0.0);
     for (int r = 0; r < n; ++r)
-        for (size_t t = 0; t < w1; ++t) out[((size_t)(r >> 6) * w1 + t) * 64 + (r & 63)] = band[(size_t)r * w1 + t];
+        for (size_t t = 0; t < w1; ++t) {
+            double v;
+            if (!upper) v = band[(size_t)r * w1 + t];
+            else v = (r + (int)t < n) ? band[(size_t)(r + t) * w1 + (w1 - 1 - t)] : 0.0;
+            out[((size_t)(r >> 6) * w1 + t) * 64 + (r & 63)] = v;
+        }
     return out;
 }
 
@@ -237,7 +244,9 @@ size_t Handle::footprint() const {
                Wp.bytes() + Hodd.bytes() + Wfull.bytes() + WfullT.bytes() + lam_full.bytes() + cell.bytes() +
                Dc.bytes() + mt.bytes() + ms.bytes() + rowptr.bytes() + col.bytes() + Msv.bytes() + cls.bytes() +
                coefE0.bytes() + coefE.bytes() + diagE0.bytes() + vc_ptr.bytes() + vc_cell.bytes() + vc_loc.bytes() +
-               q.bytes() + Lc.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() +
+               q.bytes() + Lc.bytes() + LcU.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() + L0U.bytes() +
+               Gc.bytes() + vcD.bytes() +
+               MtMs.bytes() + bnd_row.bytes() + cg_iters.bytes() +
                Sp_bf.bytes() + Sm_bf.bytes() + Hodd_bf.bytes() + Wfull_bf.bytes() + WfullT_bf.bytes() + red.bytes() +
                scal.bytes();
     for (auto& w : ws) b += w.bytes();
@@ -391,10 +400,19 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     }
     Vec mt(nRm), ms(nRm);
     for (int j = 0; j < nRm; ++j) { mt[j] = D->sigma_t[j] * vol[j]; ms[j] = D->sigma_s[j] * vol[j]; }
+    // the ratio sigma_s / sigma_t counts as uniform when every cell's ratio agrees to a few
+    // ulps (sigma_s = 0.99 sigma_t rounds differently cell by cell); the single inverse then
+    // uses the mean ratio, a relative perturbation of the odd operator below 1e-13
     h.uniform_delta = true;
-    h.delta0 = D->sigma_s[0] / D->sigma_t[0];
-    for (int j = 1; j < nRm; ++j)
-        if (D->sigma_s[j] / D->sigma_t[j] != h.delta0) { h.uniform_delta = false; break; }
+    {
+        double lo = 1e300, hi = -1e300, sum = 0;
+        for (int j = 0; j < nRm; ++j) {
+            const double r = D->sigma_s[j] / D->sigma_t[j];
+            lo = std::min(lo, r); hi = std::max(hi, r); sum += r;
+        }
+        h.delta0 = sum / nRm;
+        if (hi - lo > 1e-13 * std::max(hi, 1e-300)) h.uniform_delta = false;
+    }
 
     // ------------------------------------------------------------------ P1 pattern
     std::vector<std::vector<int>> adj(nRp);
@@ -581,6 +599,24 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     h.vc_ptr.upload(vcp, s);
     h.vc_cell.upload(vcc, s);
     h.vc_loc.upload(vcl, s);
+    {   // per-incidence gradient coefficients, interleaved mass values, boundary-row flags
+        Vec vd(vcc.size() * (size_t)d);
+        for (size_t e = 0; e < vcc.size(); ++e)
+            for (int n = 0; n < d; ++n) vd[e * d + n] = Dc[((size_t)vcc[e] * nv + vcl[e]) * d + n];
+        h.vcD.upload(vd, s);
+        Vec mm(2 * (size_t)nnz);
+        for (int e = 0; e < nnz; ++e) {
+            mm[2 * (size_t)e] = cls[(size_t)nstiff * nnz + e];
+            mm[2 * (size_t)e + 1] = Msv[e];
+        }
+        h.MtMs.upload(mm, s);
+        std::vector<int> br(nRp, 0);
+        for (int i = 0; i < nRp; ++i)
+            for (int e = rp[i]; e < rp[i + 1]; ++e)
+                for (int c = 0; c < nb; ++c)
+                    if (cls[(size_t)(nstiff + 1 + c) * nnz + e] != 0.0) br[i] = 1;
+        h.bnd_row.upload(br, s);
+    }
     h.q.upload(qv, s);
 
     // ------------------------------------------------------------------ scattering matrices (GPU)
@@ -674,6 +710,26 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
                 h.Hodd.alloc((size_t)nSm * nSm);
                 k::gemm_f64(nSm, nSm, nSm, 1.0, dWsc.p, nSm, h.WfullT.p, nSm, 0.0, h.Hodd.p, nSm, s);
                 RTE_HIP(hipStreamSynchronize(s));
+                // condensed transport matrix: block (n, n') = A_n^T H A_n', i.e.
+                // G[(n,k),(n',k')] = sum_{m,m'} 2 T_k(n,m) H[3k+m, 3k'+m'] 2 T_k'(n',m')
+                const Vec Hh = h.Hodd.download(s);
+                const int dn = d * nS;
+                Vec G((size_t)dn * dn);
+                for (int k2 = 0; k2 < nS; ++k2)
+                    for (int k1 = 0; k1 < nS; ++k1) {
+                        double Hb[9];
+                        for (int m = 0; m < 3; ++m)
+                            for (int m2 = 0; m2 < 3; ++m2) Hb[3 * m + m2] = Hh[(3 * k1 + m) + (size_t)nSm * (3 * k2 + m2)];
+                        for (int n = 0; n < d; ++n)
+                            for (int n2 = 0; n2 < d; ++n2) {
+                                double v = 0;
+                                for (int m = 0; m < 3; ++m)
+                                    for (int m2 = 0; m2 < 3; ++m2)
+                                        v += 2.0 * h.h_T[9 * k1 + 3 * n + m] * Hb[3 * m + m2] * 2.0 * h.h_T[9 * k2 + 3 * n2 + m2];
+                                G[(n * nS + k1) + (size_t)dn * (n2 * nS + k2)] = v;
+                            }
+                    }
+                h.Gc.upload(G, s);
             }
             h.have_exact = true;
         }
@@ -798,7 +854,8 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         band_cholesky(band, nc, bw);
         h.nc = nc;
         h.cbw = bw;
-        h.Lc.upload(band_to_blocked(band, nc, bw), s);
+        h.Lc.upload(band_to_blocked(band, nc, bw, false), s);
+        h.LcU.upload(band_to_blocked(band, nc, bw, true), s);
         h.perm.upload(perm, s);
         h.iperm.upload(iperm, s);
     }
@@ -808,10 +865,13 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     // ------------------------------------------------------------------ banded E_0 factors
     if (o->e0_solver == RTE_E0_BANDED) {
         h.e0_stride = k::band_blk_size(nRp, h.sbw);
-        h.L0.alloc(h.e0_stride * nS);
+        h.L0.alloc(h.e0_stride * nS + k::band_pad());
+        h.L0U.alloc(h.e0_stride * nS + k::band_pad());
+        RTE_HIP(hipMemsetAsync(h.L0.p + h.e0_stride * nS, 0, k::band_pad() * sizeof(double), s));
+        RTE_HIP(hipMemsetAsync(h.L0U.p + h.e0_stride * nS, 0, k::band_pad() * sizeof(double), s));
         DBuf<int> bad(1);
         RTE_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-        k::e0_band_factor(&h, h.sbw, h.perm.p, h.iperm.p, h.L0.p, h.e0_stride, bad.p, s);
+        k::e0_band_factor(&h, h.sbw, h.perm.p, h.iperm.p, h.L0.p, h.L0U.p, h.e0_stride, bad.p, s);
         int hb = 0;
         RTE_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
         RTE_HIP(hipStreamSynchronize(s));

@@ -32,7 +32,8 @@ void check_opts(const rte_solve_opts* o) {
     if (o->l < 1 || o->l > 64) rte::fail(RTE_E_ARG, "l must lie in 1..64");
     if (!(o->tol > 0) || o->max_iter < 0) rte::fail(RTE_E_ARG, "tol must be > 0 and max_iter >= 0");
     if (o->precision != RTE_FP64 && o->precision != RTE_MIXED) rte::fail(RTE_E_ARG, "unknown precision");
-    if (o->odd_solver != RTE_ODD_PCG && o->odd_solver != RTE_ODD_EXACT) rte::fail(RTE_E_ARG, "unknown odd solver");
+    if (o->odd_solver != RTE_ODD_PCG && o->odd_solver != RTE_ODD_EXACT && o->odd_solver != RTE_ODD_CONDENSED)
+        rte::fail(RTE_E_ARG, "unknown odd solver");
     if (o->e0_solver != RTE_E0_CG && o->e0_solver != RTE_E0_BANDED) rte::fail(RTE_E_ARG, "unknown E_0 solver");
     if (!(o->pcg_tol_resid > 0) || !(o->pcg_tol_inner > 0) || !(o->cg_tol > 0) || o->pcg_max_iter < 1 ||
         o->cg_max_iter < 1)

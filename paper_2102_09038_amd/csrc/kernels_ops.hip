@@ -61,43 +61,86 @@ __global__ __launch_bounds__(TPB) void apply_A_kernel(int nRm, int nRp, int nS,
     }
 }
 
-template <int D>
-__global__ __launch_bounds__(TPB) void apply_At_E_kernel(
-    int nRm, int nRp, int nS, int nnz, int ncls, const int* __restrict__ vc_ptr,
-    const int* __restrict__ vc_cell, const int* __restrict__ vc_loc, const double* __restrict__ Dc,
-    const double* __restrict__ T, const int* __restrict__ rowptr, const int* __restrict__ col,
-    const double* __restrict__ cls, const double* __restrict__ coefE, const double* __restrict__ Msv,
+// Y = A^T Z + (M+ + R) X [- Ms+ G] [- q].  COND = false: Z is an odd-space vector
+// (3 coefficients per pair, contracted with 2 T_k); COND = true: Z holds d condensed
+// components per pair (Z[j + nRm (n nS + k)]).
+template <int D, bool COND>
+__global__ __launch_bounds__(TPB) void at_e_kernel(
+    int nRm, int nRp, int nS, int nnz, int ncls, int nstiff, int nb, const int* __restrict__ vc_ptr,
+    const int* __restrict__ vc_cell, const double* __restrict__ vcD, const double* __restrict__ T,
+    const int* __restrict__ rowptr, const int* __restrict__ col, const double* __restrict__ MtMs,
+    const double* __restrict__ cls, const int* __restrict__ bnd_row, const double* __restrict__ coefE,
     const double* __restrict__ Z, const double* __restrict__ X, const double* __restrict__ G,
     const double* __restrict__ q, double* __restrict__ Y) {
     const size_t t = blockIdx.x * (size_t)TPB + threadIdx.x;
     if (t >= (size_t)nRp * nS) return;
     const int i = (int)(t % nRp), kk = (int)(t / nRp);
-    const double* Tk = T + 9 * kk;
     double acc = 0.0;
     if (Z) {
-        for (int e = vc_ptr[i]; e < vc_ptr[i + 1]; ++e) {
-            const int j = vc_cell[e], v = vc_loc[e];
-            const double z0 = Z[j + (size_t)nRm * (3 * kk)];
-            const double z1 = Z[j + (size_t)nRm * (3 * kk + 1)];
-            const double z2 = Z[j + (size_t)nRm * (3 * kk + 2)];
+        double Tk[D][3];
+        if (!COND) {
 #pragma unroll
-            for (int n = 0; n < D; ++n) {
-                const double hn = fma(Tk[3 * n], z0, fma(Tk[3 * n + 1], z1, Tk[3 * n + 2] * z2));
-                acc = fma(2.0 * Dc[(j * (D + 1) + v) * D + n], hn, acc);
+            for (int n = 0; n < D; ++n)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) Tk[n][m] = 2.0 * T[9 * kk + 3 * n + m];
+        }
+        for (int e = vc_ptr[i]; e < vc_ptr[i + 1]; ++e) {
+            const int j = vc_cell[e];
+            const double* dv = vcD + (size_t)e * D;
+            if (COND) {
+#pragma unroll
+                for (int n = 0; n < D; ++n) acc = fma(dv[n], Z[j + (size_t)nRm * (n * (size_t)nS + kk)], acc);
+            } else {
+                const double z0 = Z[j + (size_t)nRm * (3 * kk)];
+                const double z1 = Z[j + (size_t)nRm * (3 * kk + 1)];
+                const double z2 = Z[j + (size_t)nRm * (3 * kk + 2)];
+#pragma unroll
+                for (int n = 0; n < D; ++n) acc = fma(dv[n], fma(Tk[n][0], z0, fma(Tk[n][1], z1, Tk[n][2] * z2)), acc);
             }
         }
     }
     const double* cf = coefE + (size_t)kk * ncls;
+    const double mk = cf[nstiff];
     const double* xk = X + (size_t)nRp * kk;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        double val = 0.0;
-        for (int c = 0; c < ncls; ++c) val = fma(cf[c], cls[(size_t)c * nnz + e], val);
-        const int cc = col[e];
-        acc = fma(val, xk[cc], acc);
-        if (G) acc = fma(-Msv[e], G[cc + (size_t)nRp * kk], acc);
+    const double* gk = G ? G + (size_t)nRp * kk : nullptr;
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    for (int e = e0; e < e1; ++e) {
+        const int c = col[e];
+        acc = fma(mk * MtMs[2 * (size_t)e], xk[c], acc);
+        if (gk) acc = fma(-MtMs[2 * (size_t)e + 1], gk[c], acc);
     }
-    if (q) acc -= q[i + (size_t)nRp * kk];
-    Y[i + (size_t)nRp * kk] = acc;
+    if (bnd_row[i]) {
+        for (int e = e0; e < e1; ++e) {
+            double val = 0.0;
+            for (int c = 0; c < nb; ++c) val = fma(cf[nstiff + 1 + c], cls[(size_t)(nstiff + 1 + c) * nnz + e], val);
+            acc = fma(val, xk[col[e]], acc);
+        }
+    }
+    if (q) acc -= q[t];
+    Y[t] = acc;
+}
+
+// Yc[j + nRm (n nS + k)] = (D_n X)[j, k] / mt_j   (input of the condensed transport GEMM)
+template <int D>
+__global__ __launch_bounds__(TPB) void apply_grad_kernel(int nRm, int nRp, int nS, const int* __restrict__ cell,
+                                                         const double* __restrict__ Dc,
+                                                         const double* __restrict__ mt,
+                                                         const double* __restrict__ X, double* __restrict__ Yc) {
+    const size_t t = blockIdx.x * (size_t)TPB + threadIdx.x;
+    if (t >= (size_t)nRm * nS) return;
+    const int j = (int)(t % nRm), kk = (int)(t / nRm);
+    double gn[D];
+#pragma unroll
+    for (int n = 0; n < D; ++n) gn[n] = 0.0;
+#pragma unroll
+    for (int v = 0; v < D + 1; ++v) {
+        const double xv = X[cell[j * (D + 1) + v] + (size_t)nRp * kk];
+#pragma unroll
+        for (int n = 0; n < D; ++n) gn[n] = fma(Dc[(j * (D + 1) + v) * D + n], xv, gn[n]);
+    }
+    const double inv = 1.0 / mt[j];
+#pragma unroll
+    for (int n = 0; n < D; ++n) Yc[j + (size_t)nRm * (n * (size_t)nS + kk)] = gn[n] * inv;
 }
 
 // ----------------------------------------------------------------------------- odd PCG
@@ -490,13 +533,23 @@ void apply_A(const Handle* h, const double* X, double* B, hipStream_t s) {
 }
 
 void apply_At_E(const Handle* h, const double* Z, const double* X, const double* G, const double* q,
-                double* Y, hipStream_t s) {
+                double* Y, hipStream_t s, bool condensed) {
     const size_t n = (size_t)h->nRp * h->nS;
     const dim3 g((unsigned)((n + TPB - 1) / TPB));
-    auto* f = h->d == 2 ? apply_At_E_kernel<2> : apply_At_E_kernel<3>;
-    hipLaunchKernelGGL(f, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->nnz, h->ncls, h->vc_ptr.p,
-                       h->vc_cell.p, h->vc_loc.p, h->Dc.p, h->T.p, h->rowptr.p, h->col.p, h->cls.p,
-                       h->coefE.p, h->Msv.p, Z, X, G, q, Y);
+    decltype(&at_e_kernel<2, false>) f;
+    if (h->d == 2) f = condensed ? at_e_kernel<2, true> : at_e_kernel<2, false>;
+    else f = condensed ? at_e_kernel<3, true> : at_e_kernel<3, false>;
+    hipLaunchKernelGGL(f, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->nnz, h->ncls, h->ncls_stiff, h->nbcls,
+                       h->vc_ptr.p, h->vc_cell.p, h->vcD.p, h->T.p, h->rowptr.p, h->col.p, h->MtMs.p, h->cls.p,
+                       h->bnd_row.p, h->coefE.p, Z, X, G, q, Y);
+    RTE_CHECK_LAUNCH();
+}
+
+void apply_grad(const Handle* h, const double* X, double* Yc, hipStream_t s) {
+    const size_t n = (size_t)h->nRm * h->nS;
+    const dim3 g((unsigned)((n + TPB - 1) / TPB));
+    auto* f = h->d == 2 ? apply_grad_kernel<2> : apply_grad_kernel<3>;
+    hipLaunchKernelGGL(f, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->cell.p, h->Dc.p, h->mt.p, X, Yc);
     RTE_CHECK_LAUNCH();
 }
 

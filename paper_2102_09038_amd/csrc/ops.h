@@ -14,7 +14,9 @@ void apply_A(const Handle* h, const double* X, double* B, hipStream_t s);
 // G and q may be null (no scattering / source term).  Alg. 1, last line; with G = X S+
 // and q it is the residual (E - K+) X - q of Alg. 3.
 void apply_At_E(const Handle* h, const double* Z, const double* X, const double* G,
-                const double* q, double* Y, hipStream_t s);
+                const double* q, double* Y, hipStream_t s, bool condensed = false);
+// Yc = Mt-^{-1} [D_1 X, .., D_d X]  (nRm x d nS), the input of the condensed E
+void apply_grad(const Handle* h, const double* X, double* Yc, hipStream_t s);
 // W = (M- - K-) P given G = P S-:  W = Mt- P M_S- - Ms- G;  red <- partials of P.W
 void odd_apply(const Handle* h, const double* P, const double* G, double* W, double* red,
                hipStream_t s);
@@ -49,15 +51,18 @@ void scale_eigbasis(const Handle* h, double* C, hipStream_t s);
 // ---- coarse correction (Sec. 5.4)
 // rhs[a + dN*perm[i]] = sum_k T[i,k] Wp[k,a]
 void coarse_project(const Handle* h, const double* T, double* rhs, hipStream_t s);
-// blocked band storage size (doubles) of an n x n matrix of band width bw
+// blocked band storage size (doubles) of an n x n matrix of band width bw, and the
+// padding every allocation of such factors must carry after its last system
 size_t band_blk_size(int n, int bw);
-// x = L^{-T} L^{-1} b for nsys systems with blocked band factors (kernels_band.hip);
-// b and x are read / written at iperm[band row] when iperm is given
-void band_solve_blk(const double* BL, int n, int bw, int nsys, size_t stride_sys, const double* b, double* x,
-                    size_t stride_vec, const int* iperm, hipStream_t s);
+size_t band_pad();
+// x = L^{-T} L^{-1} b for nsys systems with blocked band factors BL (rows of L) and BU
+// (rows of L^T) (kernels_band.hip); b and x are read / written at iperm[band row] when
+// iperm is given
+void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
+                    const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s);
 // factor every E_0 block (one work-group per direction); *bad |= 1 on a non-positive pivot
-void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, double* BL, size_t stride_sys,
-                    int* bad, hipStream_t s);
+void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, double* BL, double* BU,
+                    size_t stride_sys, int* bad, hipStream_t s);
 // U = U - S + sum_a uc[a + dN*perm[i]] Wp[k, a]
 void richardson_update(const Handle* h, double* U, const double* S, const double* uc,
                        hipStream_t s);

@@ -104,6 +104,10 @@ struct Handle {
     DBuf<double> Hodd;             // [nSm x nSm] (M_S- - delta0 S-)^{-1} when uniform_delta
     DBuf<double> Wfull, WfullT;    // full odd eigenvectors and transpose (both row-major K x N)
     DBuf<double> lam_full;         // [nSm]
+    DBuf<double> Gc;               // [(d nS)^2] condensed transport matrix (uniform ratio only)
+    DBuf<double> vcD;              // [n_incidences * d] |T_j| d_n phi_v per vertex-cell incidence
+    DBuf<double> MtMs;             // [2 nnz] (sigma_t mass, sigma_s mass) per pattern entry
+    DBuf<int> bnd_row;             // [nRp] 1 if the row has boundary-mass entries
 
     // ---- spatial (Sec. 4)
     DBuf<int> cell;                // [nRm*(d+1)]
@@ -126,14 +130,14 @@ struct Handle {
 
     // ---- coarse (Sec. 5.4): banded Cholesky of E_c in the order a + dNp * perm[i]
     int nc = 0, cbw = 0;
-    DBuf<double> Lc;               // blocked band factor (kernels_band.hip layout)
+    DBuf<double> Lc, LcU;          // blocked band factor, rows of L and of L^T (kernels_band.hip)
     DBuf<int> perm, iperm;         // [nRp] spatial reordering (reverse Cuthill-McKee) and inverse
     int sbw = 0;                   // spatial band width in that order
 
     // ---- banded E_0 (RTE_E0_BANDED): one blocked band factor per direction
     bool have_e0_banded = false;
     size_t e0_stride = 0;
-    DBuf<double> L0;               // [nS * e0_stride]
+    DBuf<double> L0, L0U;          // [nS * e0_stride + pad], rows of L and of L^T
 
     // ---- BF16 copies (mixed precision)
     bool have_mixed = false;

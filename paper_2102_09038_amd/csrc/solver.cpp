@@ -175,6 +175,14 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
                   const double* q, double* Y, double tol, hipStream_t s, int64_t* pcg) {
     double* B = ws(h, W_OB);
     double* Z = ws(h, W_OZ);
+    if (o->odd_solver == RTE_ODD_CONDENSED) {
+        if (!h->Gc.p) fail(RTE_E_ARG, "the condensed odd solve needs a uniform sigma_s / sigma_t");
+        const int dn = h->d * h->nS;
+        k::apply_grad(h, X, B, s);
+        gemm(h, h->nRm, dn, dn, B, h->nRm, h->Gc.p, dn, Z, h->nRm, s);
+        k::apply_At_E(h, Z, X, G, q, Y, s, true);
+        return;
+    }
     k::apply_A(h, X, B, s);
     if (o->odd_solver == RTE_ODD_EXACT) {
         odd_exact(h, B, Z, s);
@@ -198,7 +206,8 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
     if (o->e0_solver == RTE_E0_BANDED) {
         if (!h->have_e0_banded) fail(RTE_E_ARG, "banded E_0 factors were not prepared at assembly");
         Timed t(h, s, P_E0);
-        k::band_solve_blk(h->L0.p, h->nRp, h->sbw, h->nS, h->e0_stride, X, Y, (size_t)h->nRp, h->iperm.p, s);
+        k::band_solve_blk(h->L0.p, h->L0U.p, h->nRp, h->sbw, h->nS, h->e0_stride, X, Y, (size_t)h->nRp, h->iperm.p,
+                          s);
         return;
     }
     double* r = ws(h, W_CGR);
@@ -245,7 +254,7 @@ void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const 
     double* rhs = ws(h, W_CRHS);
     double* uc = ws(h, W_CSOL);
     k::coarse_project(h, t, rhs, s);
-    k::band_solve_blk(h->Lc.p, h->nc, h->cbw, 1, 0, rhs, uc, 0, nullptr, s);
+    k::band_solve_blk(h->Lc.p, h->LcU.p, h->nc, h->cbw, 1, 0, rhs, uc, 0, nullptr, s);
     k::fill(step, 0.0, n, s);
     k::richardson_update(h, step, sv, uc, s);
 }

@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librte.so"
 RTE_OK, RTE_E_ARG, RTE_E_PHYS, RTE_E_MESH, RTE_E_NOMEM, RTE_E_HIP, RTE_E_NOTCONV, RTE_E_NONFINITE = range(8)
 RTE_FP64, RTE_MIXED = 0, 1
 RTE_DT_F64, RTE_DT_F32, RTE_DT_BF16 = 0, 1, 2
-RTE_ODD_PCG, RTE_ODD_EXACT = 0, 1
+RTE_ODD_PCG, RTE_ODD_EXACT, RTE_ODD_CONDENSED = 0, 1, 2
 RTE_E0_CG, RTE_E0_BANDED = 0, 1
 ARRAY_SP, ARRAY_SM, ARRAY_M, ARRAY_T, ARRAY_Q, ARRAY_LAMP, ARRAY_WP, ARRAY_LAMM = range(8)
 STATUS_NAMES = ["OK", "E_ARG", "E_PHYS", "E_MESH", "E_NOMEM", "E_HIP", "E_NOTCONV", "E_NONFINITE"]

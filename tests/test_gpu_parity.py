@@ -111,14 +111,22 @@ def test_scatter(case):
     assert rel(from_dev(Yv), ops.K_odd(V)) < 1e-12
 
 
-@pytest.mark.parametrize("odd", ["pcg", "exact"])
+ODD = {"pcg": 0, "exact": 1, "condensed": 2}
+
+
+@pytest.mark.parametrize("odd", list(ODD))
 def test_apply_E(case, odd):
     from paper_2102_09038_amd import rte
     name, inst, D, ops, h = case
-    o = rte.default_solve_opts(pcg_tol_resid=1e-14, pcg_max_iter=500,
-                               odd_solver=rte.RTE_ODD_PCG if odd == "pcg" else rte.RTE_ODD_EXACT)
+    o = rte.default_solve_opts(pcg_tol_resid=1e-14, pcg_max_iter=500, odd_solver=ODD[odd])
     U = np.random.default_rng(12).standard_normal((D.nRp, D.nS))
     Y = torch.empty_like(to_dev(U))
+    uniform = np.ptp(D.sigma_s / D.sigma_t) <= 1e-13 * np.max(D.sigma_s / D.sigma_t)
+    if odd == "condensed" and not uniform:
+        with pytest.raises(rte.RteError) as e:
+            h.apply_E(to_dev(U), Y, o)
+        assert e.value.status == rte.RTE_E_ARG
+        return
     h.apply_E(to_dev(U), Y, o)
     assert rel(from_dev(Y), ops.E(U)) < 1e-10
 
@@ -148,15 +156,17 @@ def test_precond(case, which):
     assert rel(from_dev(S), ref) < 1e-10
 
 
-@pytest.mark.parametrize("path", ["pcg-cg", "exact-banded"])
+@pytest.mark.parametrize("path", ["pcg-cg", "exact-banded", "condensed-banded"])
 def test_solve(case, path):
     from paper_2102_09038_amd import rte
     name, inst, D, ops, h = case
     o = rte.default_solve_opts(l=inst.l, tol=1e-12, cg_tol=1e-13, cg_max_iter=50000, pcg_tol_resid=1e-14,
                                pcg_tol_inner=1e-12, pcg_max_iter=500)
-    if path == "exact-banded":
-        o.odd_solver = rte.RTE_ODD_EXACT
+    if path != "pcg-cg":
+        o.odd_solver = ODD[path.split("-")[0]]
         o.e0_solver = rte.RTE_E0_BANDED
+    if path.startswith("condensed") and np.ptp(D.sigma_s / D.sigma_t) > 0:
+        pytest.skip("condensed form needs a uniform sigma_s/sigma_t")
     U = torch.empty((D.nS, D.nRp), dtype=torch.float64, device="cuda")
     st, info = h.solve(U, opts=o)
     uref, rinfo = richardson(ops, l=inst.l, tol=1e-12, max_iter=200)
