@@ -22,6 +22,7 @@ import time
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TFLOPS = 78.6    # MI355X dense FP64 matrix
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 
 
 def cores_used():
@@ -117,7 +118,7 @@ def main():
     from paper_2102_09038_amd import inputs, rte
 
     inst = inputs.config_realistic()
-    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED)
+    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)
     d = h.dims
     e0_bw, _, _ = h.band()
     opts = rte.default_solve_opts(l=inst.l, tol=args.tol, max_iter=1000, odd_solver=rte.RTE_ODD_CONDENSED,
@@ -169,6 +170,43 @@ def main():
         "iters": [i.iters for i in infos], "rel_resid": [i.rel_resid for i in infos],
         "roofline": dominant, "roofline_other": other,
         "scatter_gemm_tflops": gemm_tf,
+    }
+    # ---- the mixed-precision form of the same solve: BF16/FP32 preconditioner (condensed
+    #      transport GEMM in BF16 with FP32 accumulation, FP32 E_0 band factors), FP64
+    #      outer residual, dots and coarse solve
+    U64 = U.clone()
+    mopts = rte.default_solve_opts(l=inst.l, tol=args.tol, max_iter=1000, odd_solver=rte.RTE_ODD_CONDENSED,
+                                   e0_solver=rte.RTE_E0_BANDED, precision=rte.RTE_MIXED, profile=1)
+    Um = torch.empty_like(U)
+    for _ in range(args.warmup):
+        h.solve(Um, opts=mopts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    minfos = []
+    for _ in range(args.steps):
+        st, info = h.solve(Um, opts=mopts)
+        minfos.append(info)
+    torch.cuda.synchronize()
+    mdt = time.perf_counter() - t0
+    tb = sum(i.t_gemm_bf16 for i in minfos)
+    fb = sum(i.gemm_bf16_flops for i in minfos)
+    nb = sum(i.n_gemm_bf16 for i in minfos)
+    bf16_tf = fb / tb / 1e12 if tb else 0.0
+    t_e0m = sum(i.t_e0inv for i in minfos)
+    n_e0m = sum(i.n_e0inv for i in minfos)
+    e0m_bytes = d.nSp * (2 * factor_entries * 4 + 2 * n * 8)
+    out["mixed"] = {
+        "value": args.steps / mdt, "unit": "solves/s", "ms_per_step": 1e3 * mdt / args.steps,
+        "speedup_vs_fp64": (args.steps / mdt) / value, "iters": [i.iters for i in minfos],
+        "rel_resid": [i.rel_resid for i in minfos],
+        "rel_err_vs_fp64_solution": float(torch.linalg.norm(Um - U64) / torch.linalg.norm(U64)),
+        "dtype": "bf16 GEMM (fp32 acc), fp32 E_0 factors, fp64 residual/dots/coarse",
+        "gemm_bf16": {"bound": "mfma", "achieved": bf16_tf, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": bf16_tf / BF16_MFMA_PEAK_TFLOPS, "avg_launch_ms": 1e3 * tb / max(nb, 1),
+                      "launches": nb, "flops_per_launch": fb / max(nb, 1)},
+        "e0inv_fp32": {"bound": "hbm", "achieved": e0m_bytes / (t_e0m / max(n_e0m, 1)) / 1e9 if n_e0m else 0.0,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "avg_launch_ms": 1e3 * t_e0m / max(n_e0m, 1),
+                       "bytes_per_launch": e0m_bytes},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, infos[-1].iters, inst.l)

@@ -136,6 +136,9 @@ typedef struct rte_solve_info {
     double t_gemm;               /*   seconds inside scattering / odd-inverse GEMM kernels   */
     int64_t n_gemm;              /*   number of those GEMM launches                          */
     double gemm_flops;           /*   their algorithmic flops (2 M N K summed)               */
+    double t_gemm_bf16;          /*   seconds inside BF16 (mixed-precision) GEMM kernels     */
+    int64_t n_gemm_bf16;         /*   number of those launches                               */
+    double gemm_bf16_flops;      /*   their algorithmic flops                                */
 } rte_solve_info;
 
 /* Fill opts with the defaults: quad_level 2, N+ 0, N- 5, CG E_0, no mixed copies. */
@@ -175,11 +178,14 @@ rte_status rte_apply_scatter(rte_handle* h, int32_t parity, int32_t dtype_in, co
 
 /* Y = E X = A^T (M- - K-)^{-1} A X + M+ X + R X (Sec. 4; Alg. 1).  X, Y device FP64
  * n_R+ x n_S+.  The odd solve follows opts->odd_solver with tolerance
- * opts->pcg_tol_resid.  Synchronises the stream once per PCG iteration. */
+ * opts->pcg_tol_resid.  With opts->precision == RTE_MIXED and the condensed odd solver
+ * the transport term is applied in BF16 / FP32 (as inside the preconditioner).
+ * Synchronises the stream once per PCG iteration. */
 rte_status rte_apply_E(rte_handle* h, const rte_solve_opts* opts, const double* X, double* Y,
                        void* hip_stream);
 
-/* Y = E_0^{-1} X, block by block over the directions (Sec. 5.3).  Device FP64. */
+/* Y = E_0^{-1} X, block by block over the directions (Sec. 5.3).  Device FP64 vectors;
+ * with opts->precision == RTE_MIXED the banded solver uses FP32 factors. */
 rte_status rte_apply_E0inv(rte_handle* h, const rte_solve_opts* opts, const double* X,
                            double* Y, void* hip_stream);
 

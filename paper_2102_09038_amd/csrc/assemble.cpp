@@ -247,7 +247,7 @@ size_t Handle::footprint() const {
                q.bytes() + Lc.bytes() + LcU.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() + L0U.bytes() +
                Gc.bytes() + vcD.bytes() +
                MtMs.bytes() + bnd_row.bytes() + cg_iters.bytes() +
-               Sp_bf.bytes() + Sm_bf.bytes() + Hodd_bf.bytes() + Wfull_bf.bytes() + WfullT_bf.bytes() + red.bytes() +
+               Sp_bf.bytes() + Sm_bf.bytes() + Hodd_bf.bytes() + Gc_bf.bytes() + L0f.bytes() + L0Uf.bytes() + red.bytes() +
                scal.bytes();
     for (auto& w : ws) b += w.bytes();
     return b;
@@ -890,6 +890,16 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         if (h.Hodd.p) {
             h.Hodd_bf.alloc(h.Hodd.n);
             k::cvt_f64_bf16(h.Hodd.p, h.Hodd_bf.p, h.Hodd.n, s);
+        }
+        if (h.Gc.p) {
+            h.Gc_bf.alloc(h.Gc.n);
+            k::cvt_f64_bf16(h.Gc.p, h.Gc_bf.p, h.Gc.n, s);
+        }
+        if (h.have_e0_banded) {
+            h.L0f.alloc(h.L0.n);
+            h.L0Uf.alloc(h.L0U.n);
+            k::cvt_f64_f32(h.L0.p, h.L0f.p, h.L0.n, s);
+            k::cvt_f64_f32(h.L0U.p, h.L0Uf.p, h.L0U.n, s);
         }
         h.have_mixed = true;
     }

@@ -129,14 +129,14 @@ __device__ __forceinline__ double bcast(double v, int lane) {
 // v holds the first batch (entries tstart..tstart+UNR-1), issued by the caller ahead of
 // time; full batches are double-buffered, the remainder is one clamped batch, so no
 // entry past tend is loaded except the caller's early batch when the range is short.
-template <typename Mask, typename Sink>
-__device__ __forceinline__ double band_dot(const double* __restrict__ P, int tstart, int tend, const double* ring,
-                                           int o, int Wm, Mask mask, Sink sink, double (&v)[UNR]) {
+template <typename FT, typename Mask, typename Sink>
+__device__ __forceinline__ double band_dot(const FT* __restrict__ P, int tstart, int tend, const double* ring,
+                                           int o, int Wm, Mask mask, Sink sink, FT (&v)[UNR]) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int nfull = (tend - tstart + 1) / UNR;
     for (int bt = 0; bt < nfull; ++bt) {
         const int t0 = tstart + bt * UNR;
-        double vn[UNR];
+        FT vn[UNR];
         if (bt + 1 < nfull) {
 #pragma unroll
             for (int q = 0; q < UNR; ++q) vn[q] = P[(size_t)(t0 + UNR + q) * 64];
@@ -147,16 +147,17 @@ __device__ __forceinline__ double band_dot(const double* __restrict__ P, int tst
         for (int q = 0; q < UNR; ++q) y[q] = ring[(o + t0 + q) & Wm];
 #pragma unroll
         for (int q = 0; q < UNR; ++q) {
-            const double f = fma(-v[q], y[q], acc[q & 3]);
+            const double f = fma(-(double)v[q], y[q], acc[q & 3]);
             acc[q & 3] = mask(t0 + q) ? f : acc[q & 3];
-            sink(t0 + q, v[q]);
+            sink(t0 + q, (double)v[q]);
         }
 #pragma unroll
         for (int q = 0; q < UNR; ++q) v[q] = vn[q];
     }
     const int t0 = tstart + nfull * UNR;
     if (t0 <= tend) {
-        double vt[UNR], y[UNR];
+        FT vt[UNR];
+        double y[UNR];
 #pragma unroll
         for (int q = 0; q < UNR; ++q) vt[q] = P[(size_t)min(t0 + q, tend) * 64];
 #pragma unroll
@@ -164,9 +165,9 @@ __device__ __forceinline__ double band_dot(const double* __restrict__ P, int tst
 #pragma unroll
         for (int q = 0; q < UNR; ++q) {
             const int t = t0 + q;
-            const double f = fma(-vt[q], y[q], acc[q & 3]);
+            const double f = fma(-(double)vt[q], y[q], acc[q & 3]);
             acc[q & 3] = (t <= tend && mask(t)) ? f : acc[q & 3];
-            if (t <= tend) sink(t, vt[q]);
+            if (t <= tend) sink(t, (double)vt[q]);
         }
     }
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
@@ -174,25 +175,25 @@ __device__ __forceinline__ double band_dot(const double* __restrict__ P, int tst
 
 // Dynamic LDS: the y/x ring (W doubles) followed by the 64 x 64 diagonal block of the
 // current row block, stored D[u * 64 + lane] = coefficient of row lane, column u.
-template <typename VT>
+template <typename FT, typename VT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void band_solve_blk_kernel(const double* __restrict__ BLall, const double* __restrict__ BUall, int n, int bw,
+void band_solve_blk_kernel(const FT* __restrict__ BLall, const FT* __restrict__ BUall, int n, int bw,
                            size_t stride_sys, const VT* __restrict__ ball, VT* __restrict__ xall,
                            size_t stride_vec, const int* __restrict__ iperm, int W) {
     extern __shared__ double smem[];
     double* win = smem;
     double* D = smem + W;
     const int sys = blockIdx.x;
-    const double* BL = BLall + stride_sys * sys;
-    const double* BU = BUall + stride_sys * sys;
+    const FT* BL = BLall + stride_sys * sys;
+    const FT* BU = BUall + stride_sys * sys;
     const VT* b = ball + stride_vec * sys;
     VT* x = xall + stride_vec * sys;
     const int lane = threadIdx.x;
     const int nblk = (n + 63) / 64;
     const int Wm = W - 1;
     const size_t bstride = (size_t)(bw + 1) * 64;
-    double vpre[UNR];
-    auto prefetch = [&](const double* P, int tstart) {
+    FT vpre[UNR];
+    auto prefetch = [&](const FT* P, int tstart) {
 #pragma unroll
         for (int q = 0; q < UNR; ++q) vpre[q] = P[(size_t)(tstart + q) * 64];
     };
@@ -210,7 +211,7 @@ void band_solve_blk_kernel(const double* __restrict__ BLall, const double* __res
                           const int u = t - tmax;             // column within the block
                           if (u >= 0 && u < lane) D[u * 64 + lane] = v;
                       }, vpre);
-        const double invd = BL[base + (size_t)bw * 64];
+        const double invd = (double)BL[base + (size_t)bw * 64];
         if (B + 1 < nblk) prefetch(BL + base + bstride, 0);  // overlaps the triangular solve
         __syncthreads();
 #pragma unroll 1
@@ -244,7 +245,7 @@ void band_solve_blk_kernel(const double* __restrict__ BLall, const double* __res
                       [&](int t, double v) {
                           if (t < tmin) D[(lane + t) * 64 + lane] = v;   // row lane + t of the block
                       }, vpre);
-        const double invd = ok ? BU[base] : 0.0;
+        const double invd = ok ? (double)BU[base] : 0.0;
         if (B > 0) prefetch(BU + base - bstride, 1);
         __syncthreads();
 #pragma unroll 1
@@ -292,16 +293,27 @@ void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, 
     RTE_CHECK_LAUNCH();
 }
 
-void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
-                    const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
+template <typename FT>
+void band_solve_launch(const FT* BL, const FT* BU, int n, int bw, int nsys, size_t stride_sys, const double* b,
+                       double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
     const int W = pow2_at_least(bw + 128);
     const size_t lds = (size_t)(W + 64 * 64) * 8;
     if (lds > 150 * 1024) fail(RTE_E_ARG, "band too wide for the solve window");
-    RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_blk_kernel<double>),
+    RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_blk_kernel<FT, double>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(band_solve_blk_kernel<double>, dim3(nsys), dim3(64), (size_t)(W + 64 * 64) * 8, s, BL, BU, n, bw,
-                       stride_sys, b, x, stride_vec, iperm, W);
+    hipLaunchKernelGGL((band_solve_blk_kernel<FT, double>), dim3(nsys), dim3(64), lds, s, BL, BU, n, bw, stride_sys, b,
+                       x, stride_vec, iperm, W);
     RTE_CHECK_LAUNCH();
+}
+
+void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
+                    const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
+    band_solve_launch<double>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, s);
+}
+
+void band_solve_blk_f32(const float* BL, const float* BU, int n, int bw, int nsys, size_t stride_sys,
+                        const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
+    band_solve_launch<float>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, s);
 }
 
 }  // namespace k

@@ -1,0 +1,227 @@
+// Mixed-precision kernels: the BF16-input / FP32-accumulate MFMA GEMM that applies the
+// condensed transport operator inside the preconditioner, the BF16 producer of its input,
+// and the A^T + M+ + R kernel reading its FP32 output.  The outer residual, every dot
+// product and the coarse solve stay FP64 (the Richardson iteration then acts as
+// iterative refinement of the reduced-precision preconditioner; Sec. 5's convergence
+// argument only needs P_1 to stay symmetric positive definite).
+#include "ops.h"
+
+namespace rte {
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);    // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+// ============================================================================ BF16 GEMM
+// C (f32, col-major, ldc) = alpha A B + beta C with A (bf16, M x K, row-major: k contiguous,
+// lda) and B (bf16, K x N, column-major: k contiguous, ldb).  K, lda, ldb multiples of 8.
+// Tile 128 x 128 x 64, 4 waves in 2 x 2, each wave 64 x 64 as 4 x 4 blocks of
+// v_mfma_f32_16x16x32_bf16 (operand lanes: row l%16, k = 8 (l/16) + e; result rows
+// 4 (l/16) + v, column l%16).  The MFMA row operand is the B fragment (n) and the column
+// operand the A fragment (m), so the result's lane-fast index runs along m and the
+// column-major stores of C are contiguous.  16-byte global loads, double-buffered LDS
+// with rows padded by 16 bytes, one barrier per K step.
+constexpr int HBM_ = 128, HBN = 128, HBK = 64, HPAD = 8;
+
+__device__ __forceinline__ int xcd_swz(int b, int nb) {
+    const int per = nb / 8, x = b % 8, i = b / 8;
+    if (i >= per) return per * 8 + x;
+    return x * per + i;
+}
+
+__global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(int M, int N, int K, float alpha,
+                                                           const uint16_t* __restrict__ A, int lda,
+                                                           const uint16_t* __restrict__ B, int ldb, float beta,
+                                                           float* __restrict__ C, int ldc) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][HBM_][HBK + HPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][HBN][HBK + HPAD];
+    const int tm = (M + HBM_ - 1) / HBM_, tn = (N + HBN - 1) / HBN;
+    const int b = xcd_swz(blockIdx.x, tm * tn);
+    const int bm = b / tn, bn = b % tn;
+    const int m0 = bm * HBM_, n0 = bn * HBN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+
+    uint4 ra[4], rb[4];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = tid + 256 * i;
+            const int r = f >> 3, ch = f & 7;
+            const int gk = k0 + ch * 8;
+            const int gm = m0 + r, gn = n0 + r;
+            ra[i] = (gm < M && gk < K) ? *reinterpret_cast<const uint4*>(A + (size_t)gm * lda + gk)
+                                       : make_uint4(0, 0, 0, 0);
+            rb[i] = (gn < N && gk < K) ? *reinterpret_cast<const uint4*>(B + (size_t)gn * ldb + gk)
+                                       : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int f = tid + 256 * i;
+            const int r = f >> 3, ch = f & 7;
+            *reinterpret_cast<uint4*>(&As[buf][r][ch * 8]) = ra[i];
+            *reinterpret_cast<uint4*>(&Bs[buf][r][ch * 8]) = rb[i];
+        }
+    };
+    f4v acc[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[j][i] = f4v{0, 0, 0, 0};
+
+    const int nk = (K + HBK - 1) / HBK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * HBK);
+#pragma unroll
+        for (int kk = 0; kk < HBK / 32; ++kk) {
+            const int kc = kk * 32 + 8 * (lane >> 4);
+            bf8v af[4], bfr[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                af[i] = *reinterpret_cast<const bf8v*>(&As[cur][wm * 64 + i * 16 + (lane & 15)][kc]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bfr[j] = *reinterpret_cast<const bf8v*>(&Bs[cur][wn * 64 + j * 16 + (lane & 15)][kc]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[j][i], 0, 0, 0);
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+    // acc[j][i][v] = C(m = m0 + wm*64 + i*16 + lane%16, n = n0 + wn*64 + j*16 + 4*(lane/16) + v)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int gm = m0 + wm * 64 + i * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gn = n0 + wn * 64 + j * 16 + 4 * (lane >> 4) + v;
+                if (gm < M && gn < N) {
+                    float* cp = C + gm + (size_t)ldc * gn;
+                    const float val = alpha * acc[j][i][v];
+                    *cp = (beta == 0.0f) ? val : fmaf(beta, *cp, val);
+                }
+            }
+        }
+}
+
+// ============================================================================ glue
+// Ycb[j * dn + n nS + k] = bf16((D_n X)[j, k] / mt_j): the condensed GEMM's A operand,
+// row-major (angular index contiguous).  Threads run fastest over k so the BF16 stores
+// coalesce.
+template <int D>
+__global__ __launch_bounds__(256) void apply_grad_bf16_kernel(int nRm, int nRp, int nS, const int* __restrict__ cell,
+                                                              const double* __restrict__ Dc,
+                                                              const double* __restrict__ mt,
+                                                              const double* __restrict__ X,
+                                                              uint16_t* __restrict__ Ycb) {
+    const size_t t = blockIdx.x * (size_t)256 + threadIdx.x;
+    if (t >= (size_t)nRm * nS) return;
+    const int kk = (int)(t % nS), j = (int)(t / nS);
+    double gn[D];
+#pragma unroll
+    for (int n = 0; n < D; ++n) gn[n] = 0.0;
+#pragma unroll
+    for (int v = 0; v < D + 1; ++v) {
+        const double xv = X[cell[j * (D + 1) + v] + (size_t)nRp * kk];
+#pragma unroll
+        for (int n = 0; n < D; ++n) gn[n] = fma(Dc[(j * (D + 1) + v) * D + n], xv, gn[n]);
+    }
+    const double inv = 1.0 / mt[j];
+    const size_t dn = (size_t)D * nS;
+#pragma unroll
+    for (int n = 0; n < D; ++n) Ycb[(size_t)j * dn + (size_t)n * nS + kk] = f32_to_bf16((float)(gn[n] * inv));
+}
+
+// Y = A^T Z + (M+ + R) X [- Ms+ G] [- q] with the condensed components Z in FP32
+// (Z[j + nRm (n nS + k)], column-major output of the BF16 GEMM)
+template <int D>
+__global__ __launch_bounds__(256) void at_e_f32_kernel(
+    int nRm, int nRp, int nS, int nnz, int ncls, int nstiff, int nb, const int* __restrict__ vc_ptr,
+    const int* __restrict__ vc_cell, const double* __restrict__ vcD, const int* __restrict__ rowptr,
+    const int* __restrict__ col, const double* __restrict__ MtMs, const double* __restrict__ cls,
+    const int* __restrict__ bnd_row, const double* __restrict__ coefE, const float* __restrict__ Z,
+    const double* __restrict__ X, const double* __restrict__ G, const double* __restrict__ q,
+    double* __restrict__ Y) {
+    const size_t t = blockIdx.x * (size_t)256 + threadIdx.x;
+    if (t >= (size_t)nRp * nS) return;
+    const int i = (int)(t % nRp), kk = (int)(t / nRp);
+    double acc = 0.0;
+    for (int e = vc_ptr[i]; e < vc_ptr[i + 1]; ++e) {
+        const int j = vc_cell[e];
+        const double* dv = vcD + (size_t)e * D;
+#pragma unroll
+        for (int n = 0; n < D; ++n) acc = fma(dv[n], (double)Z[j + (size_t)nRm * (n * (size_t)nS + kk)], acc);
+    }
+    const double* cf = coefE + (size_t)kk * ncls;
+    const double mk = cf[nstiff];
+    const double* xk = X + (size_t)nRp * kk;
+    const double* gk = G ? G + (size_t)nRp * kk : nullptr;
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    for (int e = e0; e < e1; ++e) {
+        const int c = col[e];
+        acc = fma(mk * MtMs[2 * (size_t)e], xk[c], acc);
+        if (gk) acc = fma(-MtMs[2 * (size_t)e + 1], gk[c], acc);
+    }
+    if (bnd_row[i]) {
+        for (int e = e0; e < e1; ++e) {
+            double val = 0.0;
+            for (int c = 0; c < nb; ++c) val = fma(cf[nstiff + 1 + c], cls[(size_t)(nstiff + 1 + c) * nnz + e], val);
+            acc = fma(val, xk[col[e]], acc);
+        }
+    }
+    if (q) acc -= q[t];
+    Y[t] = acc;
+}
+
+}  // namespace
+
+namespace k {
+
+void gemm_bf16(int M, int N, int K, float alpha, const uint16_t* A, int lda, const uint16_t* B, int ldb,
+               float beta, float* C, int ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0) return;
+    if (K % 8 || lda % 8 || ldb % 8) fail(RTE_E_ARG, "BF16 GEMM needs K, lda, ldb multiples of 8");
+    const int nb = ((M + HBM_ - 1) / HBM_) * ((N + HBN - 1) / HBN);
+    hipLaunchKernelGGL(gemm_bf16_kernel, dim3(nb), dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    RTE_CHECK_LAUNCH();
+}
+
+void apply_grad_bf16(const Handle* h, const double* X, uint16_t* Ycb, hipStream_t s) {
+    const size_t n = (size_t)h->nRm * h->nS;
+    const dim3 g((unsigned)((n + 255) / 256));
+    auto* f = h->d == 2 ? apply_grad_bf16_kernel<2> : apply_grad_bf16_kernel<3>;
+    hipLaunchKernelGGL(f, g, dim3(256), 0, s, h->nRm, h->nRp, h->nS, h->cell.p, h->Dc.p, h->mt.p, X, Ycb);
+    RTE_CHECK_LAUNCH();
+}
+
+void apply_At_E_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,
+                    hipStream_t s) {
+    const size_t n = (size_t)h->nRp * h->nS;
+    const dim3 g((unsigned)((n + 255) / 256));
+    auto* f = h->d == 2 ? at_e_f32_kernel<2> : at_e_f32_kernel<3>;
+    hipLaunchKernelGGL(f, g, dim3(256), 0, s, h->nRm, h->nRp, h->nS, h->nnz, h->ncls, h->ncls_stiff, h->nbcls,
+                       h->vc_ptr.p, h->vc_cell.p, h->vcD.p, h->rowptr.p, h->col.p, h->MtMs.p, h->cls.p, h->bnd_row.p,
+                       h->coefE.p, Z, X, G, q, Y);
+    RTE_CHECK_LAUNCH();
+}
+
+}  // namespace k
+}  // namespace rte

@@ -60,6 +60,9 @@ size_t band_pad();
 // iperm is given
 void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
                     const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s);
+// same with FP32 factors (the reduced-precision preconditioner); FP64 vectors and sums
+void band_solve_blk_f32(const float* BL, const float* BU, int n, int bw, int nsys, size_t stride_sys,
+                        const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s);
 // factor every E_0 block (one work-group per direction); *bad |= 1 on a non-positive pivot
 void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, double* BL, double* BU,
                     size_t stride_sys, int* bad, hipStream_t s);
@@ -81,6 +84,11 @@ namespace rte {
 namespace k {
 // Y = M X column by column for a matrix with the P1 pattern and values vals[nnz]
 void spmm_pattern(const Handle* h, const double* vals, const double* X, double* Y, hipStream_t s);
+// Ycb = bf16(Mt-^{-1} [D_1 X, .., D_d X]) row-major (nRm x d nS, angular index contiguous)
+void apply_grad_bf16(const Handle* h, const double* X, uint16_t* Ycb, hipStream_t s);
+// apply_At_E with FP32 condensed components Z (column-major nRm x d nS)
+void apply_At_E_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,
+                    hipStream_t s);
 // Y[j, c] = v[j] X[j, c]   (nrow x ncol, col-major)
 void row_scale(const double* v, int nrow, int ncol, const double* X, double* Y, hipStream_t s);
 }  // namespace k

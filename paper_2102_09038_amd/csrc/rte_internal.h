@@ -141,7 +141,9 @@ struct Handle {
 
     // ---- BF16 copies (mixed precision)
     bool have_mixed = false;
-    DBuf<uint16_t> Sp_bf, Sm_bf, Hodd_bf, Wfull_bf, WfullT_bf;
+    DBuf<uint16_t> Sp_bf, Sm_bf, Hodd_bf;
+    DBuf<uint16_t> Gc_bf;          // BF16 copy of the condensed transport matrix
+    DBuf<float> L0f, L0Uf;         // FP32 copies of the banded E_0 factors (with padding)
 
     // ---- workspace (allocated lazily, sized for one solve)
     std::vector<DBuf<double>> ws;

@@ -44,7 +44,7 @@ double* ws(Handle* h, int id) {
 }
 
 // ----------------------------------------------------------------------------- timers
-enum ProfKind { P_E0 = 0, P_GEMM = 1 };
+enum ProfKind { P_E0 = 0, P_GEMM = 1, P_GEMM_BF16 = 2 };
 
 hipEvent_t take_event(Handle* h) {
     if (h->evpool.empty()) {
@@ -91,7 +91,8 @@ void collect_profile(Handle* h, rte_solve_info* inf) {
         RTE_HIP(hipEventSynchronize(r.b));
         RTE_HIP(hipEventElapsedTime(&ms, r.a, r.b));
         if (r.kind == P_E0) { inf->t_e0inv += ms * 1e-3; inf->n_e0inv += 1; }
-        else { inf->t_gemm += ms * 1e-3; inf->n_gemm += 1; inf->gemm_flops += r.flops; }
+        else if (r.kind == P_GEMM) { inf->t_gemm += ms * 1e-3; inf->n_gemm += 1; inf->gemm_flops += r.flops; }
+        else { inf->t_gemm_bf16 += ms * 1e-3; inf->n_gemm_bf16 += 1; inf->gemm_bf16_flops += r.flops; }
         h->evpool.push_back(r.a);
         h->evpool.push_back(r.b);
     }
@@ -171,13 +172,26 @@ void odd_exact(Handle* h, const double* B, double* Z, hipStream_t s) {
 }
 
 // Y = E X  [- Ms+ G - q]   (Alg. 1; G and q optional)
+// lowp: reduced precision (the condensed transport GEMM in BF16 with FP32 accumulation)
 void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const double* G,
-                  const double* q, double* Y, double tol, hipStream_t s, int64_t* pcg) {
+                  const double* q, double* Y, double tol, hipStream_t s, int64_t* pcg, bool lowp) {
     double* B = ws(h, W_OB);
     double* Z = ws(h, W_OZ);
     if (o->odd_solver == RTE_ODD_CONDENSED) {
         if (!h->Gc.p) fail(RTE_E_ARG, "the condensed odd solve needs a uniform sigma_s / sigma_t");
         const int dn = h->d * h->nS;
+        if (lowp) {
+            if (!h->have_mixed) fail(RTE_E_ARG, "mixed precision needs a handle assembled with mixed != 0");
+            uint16_t* Ycb = reinterpret_cast<uint16_t*>(B);
+            float* Zf = reinterpret_cast<float*>(Z);
+            k::apply_grad_bf16(h, X, Ycb, s);
+            {
+                Timed t(h, s, P_GEMM_BF16, 2.0 * h->nRm * (double)dn * dn);
+                k::gemm_bf16(h->nRm, dn, dn, 1.0f, Ycb, dn, h->Gc_bf.p, dn, 0.0f, Zf, h->nRm, s);
+            }
+            k::apply_At_E_f32(h, Zf, X, G, q, Y, s);
+            return;
+        }
         k::apply_grad(h, X, B, s);
         gemm(h, h->nRm, dn, dn, B, h->nRm, h->Gc.p, dn, Z, h->nRm, s);
         k::apply_At_E(h, Z, X, G, q, Y, s, true);
@@ -195,17 +209,22 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
 
 // Y = (E - K+) X - q0 with q0 = q (residual) or any vector (nullable)
 void residual_like(Handle* h, const rte_solve_opts* o, const double* X, const double* q0, double* Y,
-                   double tol, hipStream_t s, int64_t* pcg) {
+                   double tol, hipStream_t s, int64_t* pcg, bool lowp) {
     double* G = ws(h, W_EG);
     gemm(h, h->nRp, h->nS, h->nS, X, h->nRp, h->Sp.p, h->nS, G, h->nRp, s);
-    apply_E_core(h, o, X, G, q0, Y, tol, s, pcg);
+    apply_E_core(h, o, X, G, q0, Y, tol, s, pcg, lowp);
 }
 
 void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s, int64_t* cgt,
-           int* cgmax) {
+           int* cgmax, bool lowp) {
     if (o->e0_solver == RTE_E0_BANDED) {
         if (!h->have_e0_banded) fail(RTE_E_ARG, "banded E_0 factors were not prepared at assembly");
         Timed t(h, s, P_E0);
+        if (lowp && h->L0f.p) {
+            k::band_solve_blk_f32(h->L0f.p, h->L0Uf.p, h->nRp, h->sbw, h->nS, h->e0_stride, X, Y, (size_t)h->nRp,
+                                  h->iperm.p, s);
+            return;
+        }
         k::band_solve_blk(h->L0.p, h->L0U.p, h->nRp, h->sbw, h->nS, h->e0_stride, X, Y, (size_t)h->nRp, h->iperm.p,
                           s);
         return;
@@ -232,14 +251,14 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
 
 // z = P_1^l r  (Alg. 2 with l steps; z_0 = 0 so the first step is E_0^{-1} r)
 void apply_P1(Handle* h, const rte_solve_opts* o, const double* r, double* z, hipStream_t s,
-              int64_t* pcg, int64_t* cgt, int* cgmax) {
+              int64_t* pcg, int64_t* cgt, int* cgmax, bool lowp) {
     const size_t n = (size_t)h->nRp * h->nS;
     double* t = ws(h, W_ET2);
     double* t2 = ws(h, W_EZ);
-    e0inv(h, o, r, z, s, cgt, cgmax);
+    e0inv(h, o, r, z, s, cgt, cgmax, lowp);
     for (int i = 1; i < o->l; ++i) {
-        apply_E_core(h, o, z, nullptr, r, t, o->pcg_tol_inner, s, pcg);   // t = E z - r
-        e0inv(h, o, t, t2, s, cgt, cgmax);
+        apply_E_core(h, o, z, nullptr, r, t, o->pcg_tol_inner, s, pcg, lowp);   // t = E z - r
+        e0inv(h, o, t, t2, s, cgt, cgmax, lowp);
         k::axpby(-1.0, t2, 1.0, z, n, s);
     }
 }
@@ -247,10 +266,10 @@ void apply_P1(Handle* h, const rte_solve_opts* o, const double* r, double* z, hi
 // step = -s + W E_c^{-1} W^T ((E - K+) s - r)   (Sec. 5.4; the correction right-hand side
 // without Alg. 3's extra "-q", which would move the fixed point)
 void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const double* sv, double* step,
-                     hipStream_t s, int64_t* pcg) {
+                     hipStream_t s, int64_t* pcg, bool lowp) {
     const size_t n = (size_t)h->nRp * h->nS;
     double* t = ws(h, W_ET);
-    residual_like(h, o, sv, r, t, o->pcg_tol_inner, s, pcg);
+    residual_like(h, o, sv, r, t, o->pcg_tol_inner, s, pcg, lowp);
     double* rhs = ws(h, W_CRHS);
     double* uc = ws(h, W_CSOL);
     k::coarse_project(h, t, rhs, s);
@@ -262,23 +281,23 @@ void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const 
 }  // namespace
 
 void apply_E(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s, int64_t* pcg) {
-    apply_E_core(h, o, X, nullptr, nullptr, Y, o->pcg_tol_resid, s, pcg);
+    apply_E_core(h, o, X, nullptr, nullptr, Y, o->pcg_tol_resid, s, pcg, o->precision == RTE_MIXED);
 }
 
 void apply_E0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s,
                  int64_t* cgt, int* cgmax) {
-    e0inv(h, o, X, Y, s, cgt, cgmax);
+    e0inv(h, o, X, Y, s, cgt, cgmax, o->precision == RTE_MIXED);
 }
 
 void precond(Handle* h, const rte_solve_opts* o, int which, const double* r, double* out, hipStream_t s) {
     const size_t n = (size_t)h->nRp * h->nS;
     if (which == 0) {
-        apply_P1(h, o, r, out, s, nullptr, nullptr, nullptr);
+        apply_P1(h, o, r, out, s, nullptr, nullptr, nullptr, o->precision == RTE_MIXED);
         return;
     }
     double* sv = ws(h, W_ES);
-    apply_P1(h, o, r, sv, s, nullptr, nullptr, nullptr);
-    correction_step(h, o, r, sv, out, s, nullptr);   // out = -s + W uc
+    apply_P1(h, o, r, sv, s, nullptr, nullptr, nullptr, o->precision == RTE_MIXED);
+    correction_step(h, o, r, sv, out, s, nullptr, o->precision == RTE_MIXED);   // out = -s + W uc
     k::axpby(0.0, out, -1.0, out, n, s);             // P2 P1 r = s - W uc
 }
 
@@ -287,6 +306,7 @@ rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U
     const auto t0 = std::chrono::steady_clock::now();
     const size_t n = (size_t)h->nRp * h->nS;
     rte_solve_info inf{};
+    const bool lowp = o->precision == RTE_MIXED;   // preconditioner precision; the residual stays FP64
     h->prof_on = o->profile != 0;
     h->prof.clear();
     double* r = ws(h, W_ER);
@@ -299,7 +319,7 @@ rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U
     rte_status st = RTE_E_NOTCONV;
     int it = 0;
     for (;;) {
-        residual_like(h, o, U, h->q.p, r, o->pcg_tol_resid, s, &inf.pcg_iters_total);
+        residual_like(h, o, U, h->q.p, r, o->pcg_tol_resid, s, &inf.pcg_iters_total, false);   // FP64 always
         const double rr = dot_dev(h, r, r, n, S_DOT0, s);
         if (!std::isfinite(rr)) { st = RTE_E_NONFINITE; break; }
         inf.rel_resid = std::sqrt(rr) / h->qnorm;
@@ -312,8 +332,8 @@ rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U
         }
         if (inf.rel_resid <= o->tol) { st = RTE_OK; break; }
         if (it >= o->max_iter) { st = RTE_E_NOTCONV; break; }
-        apply_P1(h, o, r, sv, s, &inf.pcg_iters_total, &inf.cg_iters_total, &inf.cg_iters_max);
-        correction_step(h, o, r, sv, step, s, &inf.pcg_iters_total);
+        apply_P1(h, o, r, sv, s, &inf.pcg_iters_total, &inf.cg_iters_total, &inf.cg_iters_max, lowp);
+        correction_step(h, o, r, sv, step, s, &inf.pcg_iters_total, lowp);
         step_rprev = dot_dev(h, step, r, n, S_DOT2, s);
         have_step = true;
         k::axpby(1.0, step, 1.0, U, n, s);

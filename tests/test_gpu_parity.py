@@ -63,7 +63,7 @@ def case(request):
     inst = CASES[request.param]()
     print(f"[case {request.param}] nR+={len(inst.vert)} nS+={len(inst.stri)//2}", flush=True)
     from paper_2102_09038_amd import rte
-    D, ops, h = make(inst, e0_solver=rte.RTE_E0_BANDED)
+    D, ops, h = make(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)
     yield request.param, inst, D, ops, h
     h.close()
 
@@ -186,3 +186,56 @@ def test_deterministic(case):
     h.apply_E(U, Y1, o)
     h.apply_E(U, Y2, o)
     assert torch.equal(Y1, Y2)
+
+
+# ----------------------------------------------------------------------------- mixed precision
+# Bars: one application of the reduced-precision operators carries BF16 / FP32 rounding
+# (BF16 keeps 8 significant bits: relative error ~ 2^-9 per product, averaged over the
+# GEMM's accumulation), so single applications are checked loosely; the converged
+# solution of the Richardson iteration, whose residual is FP64, must match the FP64
+# oracle to 1e-6.
+
+def _uniform(D):
+    return np.ptp(D.sigma_s / D.sigma_t) <= 1e-13 * np.max(D.sigma_s / D.sigma_t)
+
+
+def test_mixed_apply_E(case):
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    if not _uniform(D):
+        pytest.skip("mixed transport needs the condensed form (uniform ratio)")
+    o = rte.default_solve_opts(odd_solver=rte.RTE_ODD_CONDENSED, precision=rte.RTE_MIXED)
+    U = np.random.default_rng(21).standard_normal((D.nRp, D.nS))
+    Y = torch.empty_like(to_dev(U))
+    h.apply_E(to_dev(U), Y, o)
+    err = rel(from_dev(Y), ops.E(U))
+    print(f"[{name}] mixed E rel err {err:.2e}")
+    assert 1e-12 < err < 2e-2
+
+
+def test_mixed_E0inv(case):
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    o = rte.default_solve_opts(e0_solver=rte.RTE_E0_BANDED, precision=rte.RTE_MIXED)
+    B = np.random.default_rng(22).standard_normal((D.nRp, D.nS))
+    X = torch.empty_like(to_dev(B))
+    h.apply_E0inv(to_dev(B), X, o)
+    err = rel(from_dev(X), ops.E0_solve(B))
+    print(f"[{name}] FP32-factor E0^-1 rel err {err:.2e}")
+    assert err < 1e-4
+
+
+def test_mixed_solve(case):
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    if not _uniform(D):
+        pytest.skip("mixed transport needs the condensed form (uniform ratio)")
+    o = rte.default_solve_opts(l=inst.l, tol=1e-10, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_BANDED,
+                               precision=rte.RTE_MIXED, max_iter=400)
+    U = torch.empty((D.nS, D.nRp), dtype=torch.float64, device="cuda")
+    st, info = h.solve(U, opts=o)
+    uref, rinfo = richardson(ops, l=inst.l, tol=1e-12, max_iter=200)
+    err = rel(from_dev(U), uref)
+    print(f"[{name}] mixed solve iters {info.iters} (fp64 oracle {rinfo['iters']}) rel err {err:.2e}")
+    assert info.rel_resid <= 1e-10
+    assert err < 1e-6
