@@ -150,19 +150,18 @@ void band_cholesky(Vec& A, int n, int bw) {
     for (int i = 0; i < n; ++i) A[w1 * i + bw] = 1.0 / A[w1 * i + bw];
 }
 
-// row-major lower band (band[r*(bw+1) + t], t = bw + c - r) -> blocked layout of
-// kernels_band.hip: BL[((r/64)(bw+1) + t) 64 + r%64]
-// (upper = false), or of its transpose, BU[((r/64)(bw+1) + t) 64 + r%64] = L(r+t, r)
-// (upper = true); both padded with k::band_pad() zeros
+// row-major lower band (band[r*(bw+1) + t], t = bw + c - r) -> blocked FP64 layout of
+// kernels_band.hip (k::band_blk_index with 2 entries per group): rows of L (upper = false)
+// or rows of L^T, at (r, t) = L(r+t, r) (upper = true)
 Vec band_to_blocked(const Vec& band, int n, int bw, bool upper) {
     const size_t w1 = (size_t)bw + 1;
-    Vec out((size_t)((n + 63) / 64) * w1 * 64 + k::band_pad(), 0.0);
+    Vec out(k::band_blk_size(n, bw, 2), 0.0);
     for (int r = 0; r < n; ++r)
         for (size_t t = 0; t < w1; ++t) {
             double v;
             if (!upper) v = band[(size_t)r * w1 + t];
             else v = (r + (int)t < n) ? band[(size_t)(r + t) * w1 + (w1 - 1 - t)] : 0.0;
-            out[((size_t)(r >> 6) * w1 + t) * 64 + (r & 63)] = v;
+            out[k::band_blk_index(r, (int)t, bw, 2)] = v;
         }
     return out;
 }
@@ -214,6 +213,30 @@ struct RocblasCtx {
 };
 
 // eigenpairs of the symmetric n x n matrix A (col-major host); ascending eigenvalues
+// Inv = A^{-1} for the SPD matrix given by its lower band (row-major, band[r (bw+1) + bw + c - r]):
+// dense Cholesky factorisation and inverse on the GPU, both triangles filled
+void dense_spd_inverse(RocblasCtx& rb, hipStream_t s, const Vec& band, int n, int bw, DBuf<double>& Inv) {
+    DBuf<double> dband;
+    dband.upload(band, s);
+    Inv.alloc((size_t)n * n);
+    RTE_HIP(hipMemsetAsync(Inv.p, 0, (size_t)n * n * sizeof(double), s));
+    k::band_to_dense(dband.p, n, bw, Inv.p, s);
+    DBuf<int> info(1);
+    int hinfo = 0;
+    if (rocsolver_dpotrf(rb.h, rocblas_fill_lower, n, Inv.p, n, info.p) != rocblas_status_success)
+        fail(RTE_E_HIP, "rocsolver_dpotrf failed");
+    RTE_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipStreamSynchronize(s));
+    if (hinfo != 0) fail(RTE_E_ARG, "the coarse matrix E_c is not positive definite");
+    if (rocsolver_dpotri(rb.h, rocblas_fill_lower, n, Inv.p, n, info.p) != rocblas_status_success)
+        fail(RTE_E_HIP, "rocsolver_dpotri failed");
+    RTE_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    RTE_HIP(hipStreamSynchronize(s));
+    if (hinfo != 0) fail(RTE_E_HIP, "rocsolver_dpotri failed on the coarse matrix");
+    k::symmetrize_lower(Inv.p, n, s);
+    RTE_HIP(hipStreamSynchronize(s));
+}
+
 void syevd(RocblasCtx& rb, hipStream_t s, int n, Vec& A, Vec& lam) {
     DBuf<double> dA(A.size()), dD(n), dE(n);
     DBuf<int> info(1);
@@ -244,7 +267,7 @@ size_t Handle::footprint() const {
                Wp.bytes() + Hodd.bytes() + Wfull.bytes() + WfullT.bytes() + lam_full.bytes() + cell.bytes() +
                Dc.bytes() + mt.bytes() + ms.bytes() + rowptr.bytes() + col.bytes() + Msv.bytes() + cls.bytes() +
                coefE0.bytes() + coefE.bytes() + diagE0.bytes() + vc_ptr.bytes() + vc_cell.bytes() + vc_loc.bytes() +
-               q.bytes() + Lc.bytes() + LcU.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() + L0U.bytes() +
+               q.bytes() + Lc.bytes() + LcU.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() + L0U.bytes() + Ecinv.bytes() +
                Gc.bytes() + vcD.bytes() +
                MtMs.bytes() + bnd_row.bytes() + cg_iters.bytes() +
                Sp_bf.bytes() + Sm_bf.bytes() + Hodd_bf.bytes() + Gc_bf.bytes() + L0f.bytes() + L0Uf.bytes() + red.bytes() +
@@ -851,11 +874,19 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
                         }
                 }
         }
-        band_cholesky(band, nc, bw);
         h.nc = nc;
         h.cbw = bw;
-        h.Lc.upload(band_to_blocked(band, nc, bw, false), s);
-        h.LcU.upload(band_to_blocked(band, nc, bw, true), s);
+        if ((double)nc * nc * sizeof(double) <= kEcinvMaxBytes) {
+            // A single band solve is one wave walking nc rows in sequence, so the coarse
+            // solve uses the explicit inverse instead (dense Cholesky and inverse on the GPU,
+            // once), applied as a bandwidth-bound matrix-vector product.
+            dense_spd_inverse(rb, s, band, nc, bw, h.Ecinv);
+        } else {
+            if (k::band_groups(bw, 2) == 0) fail(RTE_E_ARG, "coarse band too wide for the band solve");
+            band_cholesky(band, nc, bw);
+            h.Lc.upload(band_to_blocked(band, nc, bw, false), s);
+            h.LcU.upload(band_to_blocked(band, nc, bw, true), s);
+        }
         h.perm.upload(perm, s);
         h.iperm.upload(iperm, s);
     }
@@ -864,11 +895,11 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
 
     // ------------------------------------------------------------------ banded E_0 factors
     if (o->e0_solver == RTE_E0_BANDED) {
-        h.e0_stride = k::band_blk_size(nRp, h.sbw);
-        h.L0.alloc(h.e0_stride * nS + k::band_pad());
-        h.L0U.alloc(h.e0_stride * nS + k::band_pad());
-        RTE_HIP(hipMemsetAsync(h.L0.p + h.e0_stride * nS, 0, k::band_pad() * sizeof(double), s));
-        RTE_HIP(hipMemsetAsync(h.L0U.p + h.e0_stride * nS, 0, k::band_pad() * sizeof(double), s));
+        if (k::band_groups(h.sbw, 2) == 0 || k::band_groups(h.sbw, 4) == 0)
+            fail(RTE_E_ARG, "E_0 band too wide for the band solve");
+        h.e0_stride = k::band_blk_size(nRp, h.sbw, 2);
+        h.L0.alloc(h.e0_stride * nS);
+        h.L0U.alloc(h.e0_stride * nS);
         DBuf<int> bad(1);
         RTE_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
         k::e0_band_factor(&h, h.sbw, h.perm.p, h.iperm.p, h.L0.p, h.L0U.p, h.e0_stride, bad.p, s);
@@ -896,10 +927,11 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             k::cvt_f64_bf16(h.Gc.p, h.Gc_bf.p, h.Gc.n, s);
         }
         if (h.have_e0_banded) {
-            h.L0f.alloc(h.L0.n);
-            h.L0Uf.alloc(h.L0U.n);
-            k::cvt_f64_f32(h.L0.p, h.L0f.p, h.L0.n, s);
-            k::cvt_f64_f32(h.L0U.p, h.L0Uf.p, h.L0U.n, s);
+            h.e0_stride32 = k::band_blk_size(nRp, h.sbw, 4);
+            h.L0f.alloc(h.e0_stride32 * nS);
+            h.L0Uf.alloc(h.e0_stride32 * nS);
+            k::band_to_f32(h.L0.p, h.L0f.p, nRp, h.sbw, nS, h.e0_stride, h.e0_stride32, s);
+            k::band_to_f32(h.L0U.p, h.L0Uf.p, nRp, h.sbw, nS, h.e0_stride, h.e0_stride32, s);
         }
         h.have_mixed = true;
     }

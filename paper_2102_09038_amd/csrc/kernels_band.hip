@@ -7,23 +7,20 @@
 // backward), which makes it HBM bound.  The coarse matrix E_c (Sec. 5.4) uses the same
 // solve kernel.
 //
-// Blocked band layouts, coalesced for one 64-lane wave per system: for band width bw
-// and row r = 64 B + lane, t = 0..bw,
-//   BL[(B (bw+1) + t) 64 + lane] = L(r, r - bw + t)   (row r of L;   t = bw: 1 / L(r,r))
-//   BU[(B (bw+1) + t) 64 + lane] = L(r + t, r)        (row r of L^T; t = 0:  1 / L(r,r))
-// Entries outside the matrix are zero.  Allocations carry band_pad() doubles of padding
-// after the last system so the solve can prefetch past a block without clamping.
+// Blocked band layout (band_blk_index in ops.h), coalesced for one 64-lane wave per
+// system: rows in blocks of 64 (lane = row within the block), and for each row of a block
+// the band offsets t = 0..bw in groups of VEC = 16 bytes / element consecutive entries, so
+// that one group of the whole block is a single 1 KiB load:
+//   BL at (r, t) = L(r, r - bw + t)   (row r of L;   t = bw: 1 / L(r,r))
+//   BU at (r, t) = L(r + t, r)        (row r of L^T; t = 0:  1 / L(r,r))
+// Entries outside the matrix, and the padding of the last group, are zero.
 #include "ops.h"
 
 namespace rte {
 namespace {
 
-constexpr int UNR = 32;   // loads per batch in the band solve (one wave per system: the
-                          // memory-level parallelism must come from within the wave)
 
-__device__ __forceinline__ size_t blk_idx(int row, int t, int bw) {
-    return ((size_t)(row >> 6) * (bw + 1) + t) * 64 + (row & 63);
-}
+__device__ __forceinline__ size_t blk_idx(int row, int t, int bw) { return k::band_blk_index(row, t, bw, 2); }
 
 // ----------------------------------------------------------------------------- factor
 // One 256-thread work-group per direction.  A (bw+1) x (bw+1) window of the active
@@ -43,9 +40,13 @@ __global__ __launch_bounds__(256) void e0_band_factor_kernel(
     double* BU = BUall + stride_sys * kk;
     if (threadIdx.x < ncls) cf[threadIdx.x] = coefE0[(size_t)kk * ncls + threadIdx.x];
     for (int e = threadIdx.x; e < w1 * w1; e += blockDim.x) win[e] = 0.0;
-    // BU entries pointing past the last row stay zero
+    // BU entries pointing past the last row, and the padding of both, stay zero
     const int nb = (n + 63) / 64;
-    for (size_t e = threadIdx.x; e < stride_sys; e += blockDim.x) BU[e] = 0.0;
+    const size_t used = k::band_blk_size(n, bw, 2);
+    for (size_t e = threadIdx.x; e < used; e += blockDim.x) {
+        BU[e] = 0.0;
+        BL[e] = 0.0;
+    }
     __syncthreads();
     auto load_row = [&](int r) {      // lower-triangle entries of band row r, columns [r-bw, r]
         const int slot = r % w1;
@@ -104,169 +105,252 @@ __global__ __launch_bounds__(256) void e0_band_factor_kernel(
         if (j + w1 < n) load_row(j + w1);
         __syncthreads();
     }
-    // rows of the final partial block beyond n
-    for (int r = n + threadIdx.x; r < nb * 64; r += blockDim.x)
-        for (int t = 0; t <= bw; ++t) BL[blk_idx(r, t, bw)] = 0.0;
+    (void)nb;
     if (failed && threadIdx.x == 0) atomicOr(bad, 1);
 }
 
 // ----------------------------------------------------------------------------- solve
 // One wave per system: L L^T x = b.  Rows in blocks of 64 (lane = row within the block).
-// The contribution of earlier (forward) or later (backward) blocks is a per-lane dot
-// product over coalesced band rows, loaded UNR at a time with the next batch issued
-// before the current one is consumed.  The same stream carries the 64 x 64 triangular
-// diagonal block (the masked-out terms); it is captured, transposed, into LDS and then
-// solved in chunks of 16 columns with one uniform-lane broadcast per row.  y and x live
-// in an LDS ring of W >= bw + 64 entries (W a power of two); y is also parked in x.
+// A row block of a factor is G = ceil((bw+1)/VEC) groups of 16 bytes per lane; each group
+// is one coalesced 1 KiB load for the wave.  The wave is the only one on its SIMD, so the
+// memory-level parallelism has to come from inside it: the groups land in a ring of kRing
+// registers (132 VGPRs) that is refilled as soon as a slot is consumed, from the same row
+// block (phase p + 1) or, after the slot's last use, from the next row block of the sweep
+// (or the first block of the backward sweep).  The loads in flight therefore never drain
+// at a block boundary or at the turn between the sweeps; the compiler's own waitcnt
+// tracking orders every use after its load.
+//
+// Per block, the dot product with the already-solved neighbours uses the LDS ring of
+// y (forward) or x (backward) values; the 64 x 64 triangular diagonal block comes from the
+// same stream, is captured transposed into LDS, and is solved with one uniform-lane
+// broadcast per row.  The right-hand side is fetched one block ahead.
 __device__ __forceinline__ double bcast(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
     return __hiloint2double(hi, lo);
 }
 
-// sum over t in [tstart, tend] with mask(t) of -P[t*64] * ring[(o + t) & Wm]; every
-// loaded entry is also offered to sink(t, value) (used to capture the diagonal block).
-// v holds the first batch (entries tstart..tstart+UNR-1), issued by the caller ahead of
-// time; full batches are double-buffered, the remainder is one clamped batch, so no
-// entry past tend is loaded except the caller's early batch when the range is short.
-template <typename FT, typename Mask, typename Sink>
-__device__ __forceinline__ double band_dot(const FT* __restrict__ P, int tstart, int tend, const double* ring,
-                                           int o, int Wm, Mask mask, Sink sink, FT (&v)[UNR]) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int nfull = (tend - tstart + 1) / UNR;
-    for (int bt = 0; bt < nfull; ++bt) {
-        const int t0 = tstart + bt * UNR;
-        FT vn[UNR];
-        if (bt + 1 < nfull) {
-#pragma unroll
-            for (int q = 0; q < UNR; ++q) vn[q] = P[(size_t)(t0 + UNR + q) * 64];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        double y[UNR];
-#pragma unroll
-        for (int q = 0; q < UNR; ++q) y[q] = ring[(o + t0 + q) & Wm];
-#pragma unroll
-        for (int q = 0; q < UNR; ++q) {
-            const double f = fma(-(double)v[q], y[q], acc[q & 3]);
-            acc[q & 3] = mask(t0 + q) ? f : acc[q & 3];
-            sink(t0 + q, (double)v[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < UNR; ++q) v[q] = vn[q];
-    }
-    const int t0 = tstart + nfull * UNR;
-    if (t0 <= tend) {
-        FT vt[UNR];
-        double y[UNR];
-#pragma unroll
-        for (int q = 0; q < UNR; ++q) vt[q] = P[(size_t)min(t0 + q, tend) * 64];
-#pragma unroll
-        for (int q = 0; q < UNR; ++q) y[q] = ring[(o + t0 + q) & Wm];
-#pragma unroll
-        for (int q = 0; q < UNR; ++q) {
-            const int t = t0 + q;
-            const double f = fma(-(double)vt[q], y[q], acc[q & 3]);
-            acc[q & 3] = (t <= tend && mask(t)) ? f : acc[q & 3];
-            if (t <= tend) sink(t, (double)vt[q]);
-        }
-    }
-    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
-}
+template <typename FT> struct Vec16;
+template <> struct Vec16<double> { typedef double T __attribute__((ext_vector_type(2))); static constexpr int N = 2; };
+template <> struct Vec16<float> { typedef float T __attribute__((ext_vector_type(4))); static constexpr int N = 4; };
 
-// Dynamic LDS: the y/x ring (W doubles) followed by the 64 x 64 diagonal block of the
-// current row block, stored D[u * 64 + lane] = coefficient of row lane, column u.
-template <typename FT, typename VT>
+// Dynamic LDS: the y/x ring, mirrored (entry k at k and k + W, so that a window of up to W
+// consecutive entries is contiguous), followed by the 64 x 64 diagonal block of the current
+// row block, stored D[u * 64 + lane] = coefficient of row lane, column u, and 64 dump
+// slots (one per lane) for the stores of entries outside that block.
+// The dot products carry no masks: before a block is processed, the ring entries of its own
+// rows are set to zero, and every other entry a band row can touch is either a solved
+// neighbour or is paired with a zero factor entry (columns outside the matrix, padding), so
+// it only has to be finite (the ring starts zeroed).
+// A row block is P phases of H groups (the layout pads the group count to P H), all
+// unrolled, so every ring slot, band offset and load source is known at compile time; the
+// only loop that carries the ring is the one over row blocks.
+template <typename FT, int H, int P>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void band_solve_blk_kernel(const FT* __restrict__ BLall, const FT* __restrict__ BUall, int n, int bw,
-                           size_t stride_sys, const VT* __restrict__ ball, VT* __restrict__ xall,
-                           size_t stride_vec, const int* __restrict__ iperm, int W) {
+void band_solve_kernel(const FT* __restrict__ BLall, const FT* __restrict__ BUall, int n, int bw,
+                       size_t stride_sys, const double* __restrict__ ball, double* __restrict__ xall,
+                       size_t stride_vec, const int* __restrict__ iperm, int W) {
+    typedef typename Vec16<FT>::T V;
+    constexpr int VEC = Vec16<FT>::N;
+    constexpr int G = H * P;
+    constexpr size_t bs = (size_t)G * 64 * VEC;      // elements per row block
     extern __shared__ double smem[];
-    double* win = smem;
-    double* D = smem + W;
+    double* win = smem;            // 2 W entries
+    double* D = smem + 2 * W;
     const int sys = blockIdx.x;
-    const FT* BL = BLall + stride_sys * sys;
-    const FT* BU = BUall + stride_sys * sys;
-    const VT* b = ball + stride_vec * sys;
-    VT* x = xall + stride_vec * sys;
     const int lane = threadIdx.x;
+    const FT* BLs = BLall + stride_sys * sys;
+    const FT* BUs = BUall + stride_sys * sys;
+    const double* b = ball + stride_vec * sys;
+    double* x = xall + stride_vec * sys;
     const int nblk = (n + 63) / 64;
     const int Wm = W - 1;
-    const size_t bstride = (size_t)(bw + 1) * 64;
-    FT vpre[UNR];
-    auto prefetch = [&](const FT* P, int tstart) {
-#pragma unroll
-        for (int q = 0; q < UNR; ++q) vpre[q] = P[(size_t)(tstart + q) * 64];
+    const int nstep = 2 * nblk;
+    for (int e = lane; e < 2 * W; e += 64) win[e] = 0.0;
+    // step st: forward row block st (st < nblk), else backward row block 2 nblk - 1 - st
+    auto block_ptr = [&](int st) -> const FT* {
+        return st < nblk ? BLs + (size_t)st * bs : BUs + (size_t)(nstep - 1 - st) * bs;
     };
-    // ---- forward: L y = b
-    prefetch(BL + lane, 0);
-    for (int B = 0; B < nblk; ++B) {
+    auto step_row = [&](int st) -> int { return 64 * (st < nblk ? st : nstep - 1 - st) + lane; };
+    // where the right-hand side of step st lives (clamped into the matrix; the value of a
+    // row outside it is discarded)
+    auto src_index = [&](int st) -> int {
+        const int row = min(step_row(min(st, nstep - 1)), n - 1);
+        return iperm ? iperm[row] : row;
+    };
+    V ring[H];
+    {
+        const V* p0 = reinterpret_cast<const V*>(block_ptr(0));
+#pragma unroll
+        for (int i = 0; i < H; ++i) ring[i] = p0[(size_t)i * 64 + lane];
+    }
+    int cidx = src_index(0);
+    double sval = b[cidx];
+    int nidx = src_index(1);
+    double ylast = 0.0;
+    // Drain the prologue's loads once: the loop header then sees only the steady-state
+    // pending loads of the previous step, and the compiler's waits stay partial (a merge
+    // with the prologue's fresher loads would make every step wait for almost all of them).
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int st = 0; st < nstep; ++st) {
+        const bool fwd = st < nblk;
+        const int B = fwd ? st : nstep - 1 - st;
         const int row = 64 * B + lane;
         const bool ok = row < n;
-        double s = ok ? (double)b[iperm ? iperm[row] : row] : 0.0;
-        const size_t base = B * bstride + lane;
-        const int tmax = bw - lane;          // t < tmax: columns in earlier blocks
-        const int tmin = max(0, bw - row);   // columns >= 0
-        s += band_dot(BL + base, 0, bw - 1, win, row - bw, Wm, [&](int t) { return t >= tmin && t < tmax; },
-                      [&](int t, double v) {
-                          const int u = t - tmax;             // column within the block
-                          if (u >= 0 && u < lane) D[u * 64 + lane] = v;
-                      }, vpre);
-        const double invd = (double)BL[base + (size_t)bw * 64];
-        if (B + 1 < nblk) prefetch(BL + base + bstride, 0);  // overlaps the triangular solve
+        double s = (st == nblk) ? ylast : sval;
+        s = ok ? s : 0.0;
+        const int myidx = cidx;
+        // prefetch, ahead of this step's ring loads: the right-hand side of the next step and
+        // the source index of the one after.  Backward steps read the y parked in x (the first
+        // one is served from ylast instead); all addresses stay inside the matrix.
+        {
+            const int s1 = min(st + 1, nstep - 1);
+            sval = (s1 > nblk) ? x[nidx] : b[nidx];
+            cidx = nidx;
+            nidx = src_index(st + 2);
+        }
+        const V* cur = reinterpret_cast<const V*>(block_ptr(st));
+        const V* nxt = reinterpret_cast<const V*>(block_ptr(min(st + 1, nstep - 1)));
+        // the ring entries of this block's own rows are not known yet: zero
+        win[row & Wm] = 0.0;
+        win[(row & Wm) + W] = 0.0;
+        // band offset t of this row touches ring entry yoff + t; it is part of the
+        // diagonal block for t in [clo, clo + span) and is then stored at D[dbase + 64 t].
+        // The range includes the stored 1 / L(r,r) (t = bw forward, 0 backward), which lands
+        // on the tile's diagonal D[65 lane].
+        const int yoff = fwd ? row - bw : row;
+        const int clo = fwd ? bw - lane : 0;
+        const unsigned span = fwd ? (unsigned)lane + 1 : (unsigned)(64 - lane);
+        const int dbase = fwd ? lane - 64 * (bw - lane) : 65 * lane;
+        const int dump = 64 * 64 + lane;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        constexpr int Q = 4;   // ring entries are read Q slots before their use
+        const double* yw = win + (yoff & Wm);
+        double yq[Q][VEC];
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) yq[j][e] = yw[j * VEC + e];
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            const int i = c % H;
+            const V v = ring[i];
+            double yc[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) yc[e] = yq[c % Q][e];
+            if (c + Q < G) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) yq[c % Q][e] = yw[(c + Q) * VEC + e];
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const int t = c * VEC + e;
+                const double val = (double)v[e];
+                acc[t & 3] = fma(-val, yc[e], acc[t & 3]);
+                // branch-free capture: lanes outside the diagonal block write their dump slot
+                D[((unsigned)(t - clo) < span) ? dbase + 64 * t : dump] = val;
+            }
+            // the slot's old value is dead from here on (the empty asm pins this slot's
+            // products here, so the compiler cannot defer them and keep the value live): reload
+            // it in place
+            asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]));
+            __builtin_amdgcn_sched_barrier(0);
+            ring[i] = (c + H < G) ? cur[(size_t)(c + H) * 64 + lane] : nxt[(size_t)i * 64 + lane];
+        }
+        s += (acc[0] + acc[1]) + (acc[2] + acc[3]);
         __syncthreads();
+        const double dinv = ok ? D[65 * lane] : 0.0;
+        if (fwd) {
 #pragma unroll 1
-        for (int c = 0; c < 4; ++c) {
-            double Lc[16];
+            for (int c = 0; c < 4; ++c) {
+                double Lc[16];
 #pragma unroll
-            for (int uu = 0; uu < 16; ++uu) Lc[uu] = D[(16 * c + uu) * 64 + lane];
+                for (int uu = 0; uu < 16; ++uu) Lc[uu] = D[(16 * c + uu) * 64 + lane];
 #pragma unroll
-            for (int uu = 0; uu < 16; ++uu) {
-                const int u = 16 * c + uu;
-                const double yu = bcast(s * invd, u);
-                const double f = fma(-Lc[uu], yu, s);
-                s = (u < lane && u >= lane - bw) ? f : s;
+                for (int uu = 0; uu < 16; ++uu) {
+                    const int u = 16 * c + uu;
+                    const double yu = bcast(s * dinv, u);
+                    const double f = fma(-Lc[uu], yu, s);
+                    s = (u < lane && u >= lane - bw) ? f : s;
+                }
+            }
+        } else {
+#pragma unroll 1
+            for (int c = 3; c >= 0; --c) {
+                double Uc[16];
+#pragma unroll
+                for (int uu = 0; uu < 16; ++uu) Uc[uu] = D[(16 * c + uu) * 64 + lane];
+#pragma unroll
+                for (int uu = 15; uu >= 0; --uu) {
+                    const int u = 16 * c + uu;
+                    const double xu = bcast(s * dinv, u);
+                    const double f = fma(-Uc[uu], xu, s);
+                    s = (u > lane && u - lane <= bw && 64 * B + u < n) ? f : s;
+                }
             }
         }
+        const double res = s * dinv;
+        ylast = res;
         if (ok) {
-            win[row & Wm] = s * invd;
-            x[iperm ? iperm[row] : row] = (VT)(s * invd);
+            win[row & Wm] = res;
+            win[(row & Wm) + W] = res;
+            x[myidx] = res;
         }
         __syncthreads();
     }
-    // ---- backward: L^T x = y
-    prefetch(BU + (nblk - 1) * bstride + lane, 1);
-    for (int B = nblk - 1; B >= 0; --B) {
-        const int row = 64 * B + lane;
-        const bool ok = row < n;
-        double s = ok ? (double)x[iperm ? iperm[row] : row] : 0.0;
-        const size_t base = B * bstride + lane;
-        const int tmin = 64 - lane;          // t >= tmin: rows in later blocks
-        s += band_dot(BU + base, 1, bw, win, row, Wm, [&](int t) { return t >= tmin && t <= bw && row + t < n; },
-                      [&](int t, double v) {
-                          if (t < tmin) D[(lane + t) * 64 + lane] = v;   // row lane + t of the block
-                      }, vpre);
-        const double invd = ok ? (double)BU[base] : 0.0;
-        if (B > 0) prefetch(BU + base - bstride, 1);
-        __syncthreads();
-#pragma unroll 1
-        for (int c = 3; c >= 0; --c) {
-            double Uc[16];
-#pragma unroll
-            for (int uu = 0; uu < 16; ++uu) Uc[uu] = D[(16 * c + uu) * 64 + lane];
-#pragma unroll
-            for (int uu = 15; uu >= 0; --uu) {
-                const int u = 16 * c + uu;
-                const double xu = bcast(s * invd, u);
-                const double f = fma(-Uc[uu], xu, s);
-                s = (u > lane && u - lane <= bw && 64 * B + u < n) ? f : s;
-            }
-        }
-        if (ok) {
-            win[row & Wm] = s * invd;
-            x[iperm ? iperm[row] : row] = (VT)(s * invd);
-        }
-        __syncthreads();
+}
+
+// lower band (row-major, band[r (bw+1) + bw + c - r]) -> lower triangle of a dense
+// column-major n x n matrix (the rest untouched)
+__global__ void band_to_dense_kernel(const double* __restrict__ band, int n, int bw, double* __restrict__ A) {
+    const size_t total = (size_t)n * (bw + 1);
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / (bw + 1));
+        const int c = r - bw + (int)(e % (bw + 1));
+        if (c >= 0) A[(size_t)c * n + r] = band[e];
     }
+}
+
+// A(c, r) = A(r, c) for r > c (copy the lower triangle of a column-major matrix to the upper),
+// through 32 x 32 LDS tiles
+__global__ __launch_bounds__(256) void symmetrize_lower_kernel(double* __restrict__ A, int n) {
+    __shared__ double tile[32][33];
+    const int bi = blockIdx.y, bj = blockIdx.x;     // tile row / column (lower: bi >= bj)
+    if (bi < bj) return;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {
+        const int r = 32 * bi + tx, c = 32 * bj + k;
+        tile[k][tx] = (r < n && c < n) ? A[(size_t)c * n + r] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int r = 32 * bj + tx, c = 32 * bi + k;       // upper entry (r, c) = lower (c, r)
+        if (r < n && c < n && c > r) A[(size_t)c * n + r] = tile[tx][k];
+    }
+}
+
+// Y[i] = sum_j A[i * n + j] X[j] for a dense n x n matrix stored by rows (one wave per row,
+// fixed summation order)
+__global__ __launch_bounds__(256) void gemv_rows_kernel(int n, const double* __restrict__ A,
+                                                        const double* __restrict__ X, double* __restrict__ Y) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    const double* a = A + (size_t)i * n;
+    double acc0 = 0.0, acc1 = 0.0;
+    int j = lane;
+    for (; j + 64 < n; j += 128) {
+        acc0 = fma(a[j], X[j], acc0);
+        acc1 = fma(a[j + 64], X[j + 64], acc1);
+    }
+    if (j < n) acc0 = fma(a[j], X[j], acc0);
+    double v = acc0 + acc1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) Y[i] = v;
 }
 
 int pow2_at_least(int v) {
@@ -275,12 +359,62 @@ int pow2_at_least(int v) {
     return w;
 }
 
+// FP64 blocked factor (VEC 2) -> FP32 blocked factor (VEC 4) of the same band
+__global__ void band_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst, int n, int bw,
+                                   int nsys, size_t stride64, size_t stride32) {
+    const size_t per = k::band_blk_size(n, bw, 4);
+    const size_t total = per * nsys;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t sys = e / per, q = e % per;
+        // q = ((B G4 + g) 64 + lane) 4 + k
+        const int k = (int)(q & 3), lane = (int)((q >> 2) & 63);
+        const size_t bg = q >> 8;
+        const int G4 = (int)k::band_groups(bw, 4);
+        const int B = (int)(bg / G4), g = (int)(bg % G4);
+        const int t = 4 * g + k;
+        const int r = 64 * B + lane;
+        float v = 0.0f;
+        if (t <= bw && r < n) v = (float)src[stride64 * sys + k::band_blk_index(r, t, bw, 2)];
+        dst[stride32 * sys + q] = v;
+    }
+}
+
 }  // namespace
 
 namespace k {
 
-size_t band_blk_size(int n, int bw) { return (size_t)((n + 63) / 64) * (bw + 1) * 64; }
-size_t band_pad() { return (size_t)(2 * UNR + 2) * 64; }
+template <typename FT, int H, int P>
+void band_launch_hp(const FT* BL, const FT* BU, int n, int bw, int nsys, size_t stride_sys, const double* b,
+                    double* x, size_t stride_vec, const int* iperm, int W, size_t lds, hipStream_t s) {
+    RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_kernel<FT, H, P>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((band_solve_kernel<FT, H, P>), dim3(nsys), dim3(64), lds, s, BL, BU, n, bw, stride_sys, b, x,
+                       stride_vec, iperm, W);
+    RTE_CHECK_LAUNCH();
+}
+
+template <typename FT>
+void band_solve_launch(const FT* BL, const FT* BU, int n, int bw, int nsys, size_t stride_sys, const double* b,
+                       double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
+    if (nsys <= 0 || n <= 0) return;
+    constexpr int VEC = 16 / (int)sizeof(FT);
+    // ring: the rows a block reads (bw before it, or after it, its own 64 and up to a group of
+    // padding) fit in W; W >= 256 also covers the window of ring reads ahead
+    const BandShape sh = band_shape(bw, VEC);
+    const int W = std::max(256, pow2_at_least(std::max(bw + 64 + VEC * 8, sh.H * sh.P * VEC)));
+    const size_t lds = (size_t)(2 * W + 64 * 65) * 8;
+    if (lds > 150 * 1024) fail(RTE_E_ARG, "band too wide for the solve window");
+#define RTE_BAND_CASE(HH, PP)                                                                             \
+    if (sh.H == HH && sh.P == PP) {                                                                       \
+        band_launch_hp<FT, HH, PP>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, W, lds, s); \
+        return;                                                                                           \
+    }
+    RTE_BAND_CASE(9, 1) RTE_BAND_CASE(17, 1) RTE_BAND_CASE(33, 1)
+    RTE_BAND_CASE(9, 2) RTE_BAND_CASE(17, 2) RTE_BAND_CASE(33, 2)
+    RTE_BAND_CASE(17, 3) RTE_BAND_CASE(33, 3) RTE_BAND_CASE(33, 4)
+#undef RTE_BAND_CASE
+    fail(RTE_E_ARG, "band too wide for the solve kernel");
+}
 
 void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, double* BL, double* BU,
                     size_t stride_sys, int* bad, hipStream_t s) {
@@ -293,19 +427,6 @@ void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, 
     RTE_CHECK_LAUNCH();
 }
 
-template <typename FT>
-void band_solve_launch(const FT* BL, const FT* BU, int n, int bw, int nsys, size_t stride_sys, const double* b,
-                       double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
-    const int W = pow2_at_least(bw + 128);
-    const size_t lds = (size_t)(W + 64 * 64) * 8;
-    if (lds > 150 * 1024) fail(RTE_E_ARG, "band too wide for the solve window");
-    RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_blk_kernel<FT, double>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((band_solve_blk_kernel<FT, double>), dim3(nsys), dim3(64), lds, s, BL, BU, n, bw, stride_sys, b,
-                       x, stride_vec, iperm, W);
-    RTE_CHECK_LAUNCH();
-}
-
 void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
                     const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
     band_solve_launch<double>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, s);
@@ -314,6 +435,32 @@ void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys,
 void band_solve_blk_f32(const float* BL, const float* BU, int n, int bw, int nsys, size_t stride_sys,
                         const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
     band_solve_launch<float>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, s);
+}
+
+void band_to_f32(const double* src, float* dst, int n, int bw, int nsys, size_t stride64, size_t stride32,
+                 hipStream_t s) {
+    const size_t total = band_blk_size(n, bw, 4) * nsys;
+    const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(band_to_f32_kernel, dim3(blocks), dim3(256), 0, s, src, dst, n, bw, nsys, stride64, stride32);
+    RTE_CHECK_LAUNCH();
+}
+
+void band_to_dense(const double* band, int n, int bw, double* A, hipStream_t s) {
+    const size_t total = (size_t)n * (bw + 1);
+    const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(band_to_dense_kernel, dim3(blocks), dim3(256), 0, s, band, n, bw, A);
+    RTE_CHECK_LAUNCH();
+}
+
+void symmetrize_lower(double* A, int n, hipStream_t s) {
+    const int nt = (n + 31) / 32;
+    hipLaunchKernelGGL(symmetrize_lower_kernel, dim3(nt, nt), dim3(256), 0, s, A, n);
+    RTE_CHECK_LAUNCH();
+}
+
+void gemv_rows(int n, const double* A, const double* X, double* Y, hipStream_t s) {
+    hipLaunchKernelGGL(gemv_rows_kernel, dim3((n + 3) / 4), dim3(256), 0, s, n, A, X, Y);
+    RTE_CHECK_LAUNCH();
 }
 
 }  // namespace k

@@ -51,10 +51,39 @@ void scale_eigbasis(const Handle* h, double* C, hipStream_t s);
 // ---- coarse correction (Sec. 5.4)
 // rhs[a + dN*perm[i]] = sum_k T[i,k] Wp[k,a]
 void coarse_project(const Handle* h, const double* T, double* rhs, hipStream_t s);
-// blocked band storage size (doubles) of an n x n matrix of band width bw, and the
-// padding every allocation of such factors must carry after its last system
-size_t band_blk_size(int n, int bw);
-size_t band_pad();
+// Blocked band layout of a factor with band width bw (kernels_band.hip): rows in blocks of
+// 64, band offsets t = 0..bw in groups of vec consecutive entries (vec = 16 bytes / element);
+// a row block holds H P groups (the solve kernel's ring depth H times its phase count P,
+// chosen here so that H P >= ceil((bw+1)/vec) with little padding), zero past t = bw.
+struct BandShape {
+    int H, P;
+};
+__host__ __device__ inline BandShape band_shape(int bw, int vec) {
+    const int g = (bw + vec) / vec;
+    const int hs[9] = {9, 17, 33, 9, 17, 33, 17, 33, 33};
+    const int ps[9] = {1, 1, 1, 2, 2, 2, 3, 3, 4};
+    BandShape best{0, 0};
+    int waste = 1 << 30;
+    for (int k = 0; k < 9; ++k) {
+        const int cap = hs[k] * ps[k];
+        if (cap < g) continue;
+        // prefer little padding, then a deeper ring
+        const int w = (cap - g) * 4 - hs[k];
+        if (w < waste) { waste = w; best = BandShape{hs[k], ps[k]}; }
+    }
+    return best;
+}
+__host__ __device__ inline size_t band_groups(int bw, int vec) {
+    const BandShape sh = band_shape(bw, vec);
+    return (size_t)sh.H * sh.P;
+}
+__host__ __device__ inline size_t band_blk_index(int r, int t, int bw, int vec) {
+    return (((size_t)(r >> 6) * band_groups(bw, vec) + t / vec) * 64 + (r & 63)) * vec + t % vec;
+}
+// number of elements of one system's factor in that layout (0 if the band is too wide)
+__host__ __device__ inline size_t band_blk_size(int n, int bw, int vec) {
+    return (size_t)((n + 63) / 64) * band_groups(bw, vec) * 64 * vec;
+}
 // x = L^{-T} L^{-1} b for nsys systems with blocked band factors BL (rows of L) and BU
 // (rows of L^T) (kernels_band.hip); b and x are read / written at iperm[band row] when
 // iperm is given
@@ -63,6 +92,15 @@ void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys,
 // same with FP32 factors (the reduced-precision preconditioner); FP64 vectors and sums
 void band_solve_blk_f32(const float* BL, const float* BU, int n, int bw, int nsys, size_t stride_sys,
                         const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s);
+// FP64 blocked factors -> FP32 blocked factors (their own layout, 4 entries per group)
+void band_to_f32(const double* src, float* dst, int n, int bw, int nsys, size_t stride64, size_t stride32,
+                 hipStream_t s);
+// lower band (row-major, band[r (bw+1) + bw + c - r]) -> lower triangle of a dense
+// column-major n x n matrix; and the copy of that lower triangle to the upper one
+void band_to_dense(const double* band, int n, int bw, double* A, hipStream_t s);
+void symmetrize_lower(double* A, int n, hipStream_t s);
+// Y = A X for a dense n x n matrix stored by rows
+void gemv_rows(int n, const double* A, const double* X, double* Y, hipStream_t s);
 // factor every E_0 block (one work-group per direction); *bad |= 1 on a non-positive pivot
 void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, double* BL, double* BU,
                     size_t stride_sys, int* bad, hipStream_t s);

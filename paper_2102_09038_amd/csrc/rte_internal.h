@@ -79,6 +79,7 @@ struct DBuf {
 
 // ----------------------------------------------------------------------------- handle
 constexpr int kMaxClasses = 16;   // sparse value classes of the P1 pattern (see below)
+constexpr double kEcinvMaxBytes = 12.0 * (1 << 30);   // budget of an explicit E_c^{-1}
 
 struct Handle {
     // sizes
@@ -131,19 +132,21 @@ struct Handle {
     // ---- coarse (Sec. 5.4): banded Cholesky of E_c in the order a + dNp * perm[i]
     int nc = 0, cbw = 0;
     DBuf<double> Lc, LcU;          // blocked band factor, rows of L and of L^T (kernels_band.hip)
+    DBuf<double> Ecinv;            // explicit E_c^{-1} (nc x nc, band order) when it fits its budget
     DBuf<int> perm, iperm;         // [nRp] spatial reordering (reverse Cuthill-McKee) and inverse
     int sbw = 0;                   // spatial band width in that order
 
     // ---- banded E_0 (RTE_E0_BANDED): one blocked band factor per direction
     bool have_e0_banded = false;
     size_t e0_stride = 0;
-    DBuf<double> L0, L0U;          // [nS * e0_stride + pad], rows of L and of L^T
+    DBuf<double> L0, L0U;          // [nS * e0_stride], rows of L and of L^T
 
     // ---- BF16 copies (mixed precision)
     bool have_mixed = false;
     DBuf<uint16_t> Sp_bf, Sm_bf, Hodd_bf;
     DBuf<uint16_t> Gc_bf;          // BF16 copy of the condensed transport matrix
-    DBuf<float> L0f, L0Uf;         // FP32 copies of the banded E_0 factors (with padding)
+    size_t e0_stride32 = 0;
+    DBuf<float> L0f, L0Uf;         // FP32 copies of the banded E_0 factors ([nS * e0_stride32])
 
     // ---- workspace (allocated lazily, sized for one solve)
     std::vector<DBuf<double>> ws;

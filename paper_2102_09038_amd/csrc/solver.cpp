@@ -221,7 +221,7 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
         if (!h->have_e0_banded) fail(RTE_E_ARG, "banded E_0 factors were not prepared at assembly");
         Timed t(h, s, P_E0);
         if (lowp && h->L0f.p) {
-            k::band_solve_blk_f32(h->L0f.p, h->L0Uf.p, h->nRp, h->sbw, h->nS, h->e0_stride, X, Y, (size_t)h->nRp,
+            k::band_solve_blk_f32(h->L0f.p, h->L0Uf.p, h->nRp, h->sbw, h->nS, h->e0_stride32, X, Y, (size_t)h->nRp,
                                   h->iperm.p, s);
             return;
         }
@@ -273,7 +273,8 @@ void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const 
     double* rhs = ws(h, W_CRHS);
     double* uc = ws(h, W_CSOL);
     k::coarse_project(h, t, rhs, s);
-    k::band_solve_blk(h->Lc.p, h->LcU.p, h->nc, h->cbw, 1, 0, rhs, uc, 0, nullptr, s);
+    if (h->Ecinv.p) k::gemv_rows(h->nc, h->Ecinv.p, rhs, uc, s);
+    else k::band_solve_blk(h->Lc.p, h->LcU.p, h->nc, h->cbw, 1, 0, rhs, uc, 0, nullptr, s);
     k::fill(step, 0.0, n, s);
     k::richardson_update(h, step, sv, uc, s);
 }
