@@ -109,8 +109,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(DESIGN.md describes how the solver would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver has no multi-GPU path "
+              "(instances would shard by direction and by cells; nothing here uses a second GPU).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
