@@ -332,6 +332,22 @@ __global__ __launch_bounds__(256) void symmetrize_lower_kernel(double* __restric
     }
 }
 
+// column-wise permutation of an n x ncols column-major matrix: gather (dst[r] = src[iperm[r]])
+// or scatter (dst[iperm[r]] = src[r]); one work-group per column, so the scattered side of a
+// column is touched by one work-group in a short time and its cache lines are reused
+__global__ __launch_bounds__(256) void permute_cols_kernel(const int* __restrict__ iperm, int n,
+                                                           const double* __restrict__ src,
+                                                           double* __restrict__ dst, int gather) {
+    const size_t off = (size_t)blockIdx.x * n;
+    const double* sc = src + off;
+    double* dc = dst + off;
+    if (gather) {
+        for (int r = threadIdx.x; r < n; r += blockDim.x) dc[r] = sc[iperm[r]];
+    } else {
+        for (int r = threadIdx.x; r < n; r += blockDim.x) dc[iperm[r]] = sc[r];
+    }
+}
+
 // Y[i] = sum_j A[i * n + j] X[j] for a dense n x n matrix stored by rows (one wave per row,
 // fixed summation order)
 __global__ __launch_bounds__(256) void gemv_rows_kernel(int n, const double* __restrict__ A,
@@ -455,6 +471,12 @@ void band_to_dense(const double* band, int n, int bw, double* A, hipStream_t s) 
 void symmetrize_lower(double* A, int n, hipStream_t s) {
     const int nt = (n + 31) / 32;
     hipLaunchKernelGGL(symmetrize_lower_kernel, dim3(nt, nt), dim3(256), 0, s, A, n);
+    RTE_CHECK_LAUNCH();
+}
+
+void permute_cols(const int* iperm, int n, int ncols, const double* src, double* dst, bool gather, hipStream_t s) {
+    if (n <= 0 || ncols <= 0) return;
+    hipLaunchKernelGGL(permute_cols_kernel, dim3(ncols), dim3(256), 0, s, iperm, n, src, dst, gather ? 1 : 0);
     RTE_CHECK_LAUNCH();
 }
 

@@ -132,63 +132,47 @@ __global__ __launch_bounds__(256) void apply_grad_bf16_kernel(int nRm, int nRp, 
                                                               const double* __restrict__ mt,
                                                               const double* __restrict__ X,
                                                               uint16_t* __restrict__ Ycb) {
+    // one thread per cell and 8 consecutive directions: the cell's data is loaded once, the
+    // 8 BF16 results of each component go out as one 16-byte store
+    const int nkc = nS / 8;
     const size_t t = blockIdx.x * (size_t)256 + threadIdx.x;
-    if (t >= (size_t)nRm * nS) return;
-    const int kk = (int)(t % nS), j = (int)(t / nS);
-    double gn[D];
-#pragma unroll
-    for (int n = 0; n < D; ++n) gn[n] = 0.0;
+    if (t >= (size_t)nRm * nkc) return;
+    const int j = (int)(t % nRm);
+    const int k0 = (int)(t / nRm) * 8;
+    int cv[D + 1];
+    double dc[D + 1][D];
 #pragma unroll
     for (int v = 0; v < D + 1; ++v) {
-        const double xv = X[cell[j * (D + 1) + v] + (size_t)nRp * kk];
+        cv[v] = cell[j * (D + 1) + v];
 #pragma unroll
-        for (int n = 0; n < D; ++n) gn[n] = fma(Dc[(j * (D + 1) + v) * D + n], xv, gn[n]);
+        for (int n = 0; n < D; ++n) dc[v][n] = Dc[(j * (D + 1) + v) * D + n];
     }
     const double inv = 1.0 / mt[j];
+    uint16_t out[D][8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        double gn[D];
+#pragma unroll
+        for (int n = 0; n < D; ++n) gn[n] = 0.0;
+#pragma unroll
+        for (int v = 0; v < D + 1; ++v) {
+            const double xv = X[cv[v] + (size_t)nRp * (k0 + kk)];
+#pragma unroll
+            for (int n = 0; n < D; ++n) gn[n] = fma(dc[v][n], xv, gn[n]);
+        }
+#pragma unroll
+        for (int n = 0; n < D; ++n) out[n][kk] = f32_to_bf16((float)(gn[n] * inv));
+    }
     const size_t dn = (size_t)D * nS;
 #pragma unroll
-    for (int n = 0; n < D; ++n) Ycb[(size_t)j * dn + (size_t)n * nS + kk] = f32_to_bf16((float)(gn[n] * inv));
-}
-
-// Y = A^T Z + (M+ + R) X [- Ms+ G] [- q] with the condensed components Z in FP32
-// (Z[j + nRm (n nS + k)], column-major output of the BF16 GEMM)
-template <int D>
-__global__ __launch_bounds__(256) void at_e_f32_kernel(
-    int nRm, int nRp, int nS, int nnz, int ncls, int nstiff, int nb, const int* __restrict__ vc_ptr,
-    const int* __restrict__ vc_cell, const double* __restrict__ vcD, const int* __restrict__ rowptr,
-    const int* __restrict__ col, const double* __restrict__ MtMs, const double* __restrict__ cls,
-    const int* __restrict__ bnd_row, const double* __restrict__ coefE, const float* __restrict__ Z,
-    const double* __restrict__ X, const double* __restrict__ G, const double* __restrict__ q,
-    double* __restrict__ Y) {
-    const size_t t = blockIdx.x * (size_t)256 + threadIdx.x;
-    if (t >= (size_t)nRp * nS) return;
-    const int i = (int)(t % nRp), kk = (int)(t / nRp);
-    double acc = 0.0;
-    for (int e = vc_ptr[i]; e < vc_ptr[i + 1]; ++e) {
-        const int j = vc_cell[e];
-        const double* dv = vcD + (size_t)e * D;
-#pragma unroll
-        for (int n = 0; n < D; ++n) acc = fma(dv[n], (double)Z[j + (size_t)nRm * (n * (size_t)nS + kk)], acc);
+    for (int n = 0; n < D; ++n) {
+        uint4 w;
+        w.x = out[n][0] | ((uint32_t)out[n][1] << 16);
+        w.y = out[n][2] | ((uint32_t)out[n][3] << 16);
+        w.z = out[n][4] | ((uint32_t)out[n][5] << 16);
+        w.w = out[n][6] | ((uint32_t)out[n][7] << 16);
+        *reinterpret_cast<uint4*>(Ycb + (size_t)j * dn + (size_t)n * nS + k0) = w;
     }
-    const double* cf = coefE + (size_t)kk * ncls;
-    const double mk = cf[nstiff];
-    const double* xk = X + (size_t)nRp * kk;
-    const double* gk = G ? G + (size_t)nRp * kk : nullptr;
-    const int e0 = rowptr[i], e1 = rowptr[i + 1];
-    for (int e = e0; e < e1; ++e) {
-        const int c = col[e];
-        acc = fma(mk * MtMs[2 * (size_t)e], xk[c], acc);
-        if (gk) acc = fma(-MtMs[2 * (size_t)e + 1], gk[c], acc);
-    }
-    if (bnd_row[i]) {
-        for (int e = e0; e < e1; ++e) {
-            double val = 0.0;
-            for (int c = 0; c < nb; ++c) val = fma(cf[nstiff + 1 + c], cls[(size_t)(nstiff + 1 + c) * nnz + e], val);
-            acc = fma(val, xk[col[e]], acc);
-        }
-    }
-    if (q) acc -= q[t];
-    Y[t] = acc;
 }
 
 }  // namespace
@@ -205,23 +189,14 @@ void gemm_bf16(int M, int N, int K, float alpha, const uint16_t* A, int lda, con
 }
 
 void apply_grad_bf16(const Handle* h, const double* X, uint16_t* Ycb, hipStream_t s) {
-    const size_t n = (size_t)h->nRm * h->nS;
+    if (h->nS % 8) fail(RTE_E_ARG, "the BF16 transport path needs a multiple of 8 sphere pairs");
+    const size_t n = (size_t)h->nRm * (h->nS / 8);
     const dim3 g((unsigned)((n + 255) / 256));
     auto* f = h->d == 2 ? apply_grad_bf16_kernel<2> : apply_grad_bf16_kernel<3>;
     hipLaunchKernelGGL(f, g, dim3(256), 0, s, h->nRm, h->nRp, h->nS, h->cell.p, h->Dc.p, h->mt.p, X, Ycb);
     RTE_CHECK_LAUNCH();
 }
 
-void apply_At_E_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,
-                    hipStream_t s) {
-    const size_t n = (size_t)h->nRp * h->nS;
-    const dim3 g((unsigned)((n + 255) / 256));
-    auto* f = h->d == 2 ? at_e_f32_kernel<2> : at_e_f32_kernel<3>;
-    hipLaunchKernelGGL(f, g, dim3(256), 0, s, h->nRm, h->nRp, h->nS, h->nnz, h->ncls, h->ncls_stiff, h->nbcls,
-                       h->vc_ptr.p, h->vc_cell.p, h->vcD.p, h->rowptr.p, h->col.p, h->MtMs.p, h->cls.p, h->bnd_row.p,
-                       h->coefE.p, Z, X, G, q, Y);
-    RTE_CHECK_LAUNCH();
-}
 
 }  // namespace k
 }  // namespace rte

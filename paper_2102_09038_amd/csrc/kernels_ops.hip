@@ -10,6 +10,7 @@ namespace rte {
 namespace {
 
 constexpr int TPB = 256;
+constexpr int kAtEK = 8;   // directions per thread in the A / A^T kernels
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -61,86 +62,130 @@ __global__ __launch_bounds__(TPB) void apply_A_kernel(int nRm, int nRp, int nS,
     }
 }
 
-// Y = A^T Z + (M+ + R) X [- Ms+ G] [- q].  COND = false: Z is an odd-space vector
-// (3 coefficients per pair, contracted with 2 T_k); COND = true: Z holds d condensed
-// components per pair (Z[j + nRm (n nS + k)]).
-template <int D, bool COND>
+// Y = A^T Z + (M+ + R) X [- Ms+ G] [- q] for the even vectors (n_R+ x n_S+, column-major).
+// COND = false: Z holds the odd coefficients of Alg. 1 (3 per pair, Z[j + nRm (3k + m)]),
+// contracted with 2 T_k; COND = true: Z holds the d condensed components per pair
+// (Z[j + nRm (n nS + k)]), in FP64 or FP32 (ZT).  One thread per vertex and KC consecutive
+// directions: the vertex's incidence, derivative and P1-row data are loaded once and reused
+// for all KC outputs, while every access to the big arrays stays coalesced along the
+// vertex index across the wave.
+template <int D, bool COND, typename ZT, int KC>
 __global__ __launch_bounds__(TPB) void at_e_kernel(
     int nRm, int nRp, int nS, int nnz, int ncls, int nstiff, int nb, const int* __restrict__ vc_ptr,
     const int* __restrict__ vc_cell, const double* __restrict__ vcD, const double* __restrict__ T,
     const int* __restrict__ rowptr, const int* __restrict__ col, const double* __restrict__ MtMs,
     const double* __restrict__ cls, const int* __restrict__ bnd_row, const double* __restrict__ coefE,
-    const double* __restrict__ Z, const double* __restrict__ X, const double* __restrict__ G,
+    const ZT* __restrict__ Z, const double* __restrict__ X, const double* __restrict__ G,
     const double* __restrict__ q, double* __restrict__ Y) {
+    const int nkc = (nS + KC - 1) / KC;
     const size_t t = blockIdx.x * (size_t)TPB + threadIdx.x;
-    if (t >= (size_t)nRp * nS) return;
-    const int i = (int)(t % nRp), kk = (int)(t / nRp);
-    double acc = 0.0;
+    if (t >= (size_t)nRp * nkc) return;
+    const int i = (int)(t % nRp);
+    const int k0 = (int)(t / nRp) * KC;
+    double acc[KC];
+    int kq[KC];                       // direction of slot kk, clamped into range
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        acc[kk] = 0.0;
+        kq[kk] = min(k0 + kk, nS - 1);
+    }
     if (Z) {
-        double Tk[D][3];
-        if (!COND) {
-#pragma unroll
-            for (int n = 0; n < D; ++n)
-#pragma unroll
-                for (int m = 0; m < 3; ++m) Tk[n][m] = 2.0 * T[9 * kk + 3 * n + m];
-        }
         for (int e = vc_ptr[i]; e < vc_ptr[i + 1]; ++e) {
             const int j = vc_cell[e];
-            const double* dv = vcD + (size_t)e * D;
-            if (COND) {
+            double dv[D];
 #pragma unroll
-                for (int n = 0; n < D; ++n) acc = fma(dv[n], Z[j + (size_t)nRm * (n * (size_t)nS + kk)], acc);
-            } else {
-                const double z0 = Z[j + (size_t)nRm * (3 * kk)];
-                const double z1 = Z[j + (size_t)nRm * (3 * kk + 1)];
-                const double z2 = Z[j + (size_t)nRm * (3 * kk + 2)];
+            for (int n = 0; n < D; ++n) dv[n] = vcD[(size_t)e * D + n];
 #pragma unroll
-                for (int n = 0; n < D; ++n) acc = fma(dv[n], fma(Tk[n][0], z0, fma(Tk[n][1], z1, Tk[n][2] * z2)), acc);
+            for (int kk = 0; kk < KC; ++kk) {
+                const int k = kq[kk];
+                if (COND) {
+#pragma unroll
+                    for (int n = 0; n < D; ++n)
+                        acc[kk] = fma(dv[n], (double)Z[j + (size_t)nRm * (n * (size_t)nS + k)], acc[kk]);
+                } else {
+                    const double z0 = (double)Z[j + (size_t)nRm * (3 * (size_t)k)];
+                    const double z1 = (double)Z[j + (size_t)nRm * (3 * (size_t)k + 1)];
+                    const double z2 = (double)Z[j + (size_t)nRm * (3 * (size_t)k + 2)];
+                    const double* Tk = T + 9 * (size_t)k;
+#pragma unroll
+                    for (int n = 0; n < D; ++n)
+                        acc[kk] = fma(dv[n], 2.0 * fma(Tk[3 * n], z0, fma(Tk[3 * n + 1], z1, Tk[3 * n + 2] * z2)),
+                                      acc[kk]);
+                }
             }
         }
     }
-    const double* cf = coefE + (size_t)kk * ncls;
-    const double mk = cf[nstiff];
-    const double* xk = X + (size_t)nRp * kk;
-    const double* gk = G ? G + (size_t)nRp * kk : nullptr;
+    double mk[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) mk[kk] = coefE[(size_t)kq[kk] * ncls + nstiff];
     const int e0 = rowptr[i], e1 = rowptr[i + 1];
     for (int e = e0; e < e1; ++e) {
         const int c = col[e];
-        acc = fma(mk * MtMs[2 * (size_t)e], xk[c], acc);
-        if (gk) acc = fma(-MtMs[2 * (size_t)e + 1], gk[c], acc);
+        const double a = MtMs[2 * (size_t)e], bm = MtMs[2 * (size_t)e + 1];
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const size_t o = c + (size_t)nRp * kq[kk];
+            acc[kk] = fma(mk[kk] * a, X[o], acc[kk]);
+            if (G) acc[kk] = fma(-bm, G[o], acc[kk]);
+        }
     }
     if (bnd_row[i]) {
         for (int e = e0; e < e1; ++e) {
-            double val = 0.0;
-            for (int c = 0; c < nb; ++c) val = fma(cf[nstiff + 1 + c], cls[(size_t)(nstiff + 1 + c) * nnz + e], val);
-            acc = fma(val, xk[col[e]], acc);
+            const int c = col[e];
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                const double* cf = coefE + (size_t)kq[kk] * ncls + nstiff + 1;
+                double val = 0.0;
+                for (int b = 0; b < nb; ++b) val = fma(cf[b], cls[(size_t)(nstiff + 1 + b) * nnz + e], val);
+                acc[kk] = fma(val, X[c + (size_t)nRp * kq[kk]], acc[kk]);
+            }
         }
     }
-    if (q) acc -= q[t];
-    Y[t] = acc;
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+        if (k0 + kk >= nS) break;
+        const size_t o = i + (size_t)nRp * (k0 + kk);
+        Y[o] = q ? acc[kk] - q[o] : acc[kk];
+    }
 }
 
-// Yc[j + nRm (n nS + k)] = (D_n X)[j, k] / mt_j   (input of the condensed transport GEMM)
-template <int D>
+// Yc[j + nRm (n nS + k)] = (D_n X)[j, k] / mt_j   (input of the condensed transport GEMM).
+// One thread per cell and KC consecutive directions (cell data loaded once).
+template <int D, int KC>
 __global__ __launch_bounds__(TPB) void apply_grad_kernel(int nRm, int nRp, int nS, const int* __restrict__ cell,
                                                          const double* __restrict__ Dc,
                                                          const double* __restrict__ mt,
                                                          const double* __restrict__ X, double* __restrict__ Yc) {
+    const int nkc = (nS + KC - 1) / KC;
     const size_t t = blockIdx.x * (size_t)TPB + threadIdx.x;
-    if (t >= (size_t)nRm * nS) return;
-    const int j = (int)(t % nRm), kk = (int)(t / nRm);
-    double gn[D];
-#pragma unroll
-    for (int n = 0; n < D; ++n) gn[n] = 0.0;
+    if (t >= (size_t)nRm * nkc) return;
+    const int j = (int)(t % nRm);
+    const int k0 = (int)(t / nRm) * KC;
+    int cv[D + 1];
+    double dc[D + 1][D];
 #pragma unroll
     for (int v = 0; v < D + 1; ++v) {
-        const double xv = X[cell[j * (D + 1) + v] + (size_t)nRp * kk];
+        cv[v] = cell[j * (D + 1) + v];
 #pragma unroll
-        for (int n = 0; n < D; ++n) gn[n] = fma(Dc[(j * (D + 1) + v) * D + n], xv, gn[n]);
+        for (int n = 0; n < D; ++n) dc[v][n] = Dc[(j * (D + 1) + v) * D + n];
     }
     const double inv = 1.0 / mt[j];
 #pragma unroll
-    for (int n = 0; n < D; ++n) Yc[j + (size_t)nRm * (n * (size_t)nS + kk)] = gn[n] * inv;
+    for (int kk = 0; kk < KC; ++kk) {
+        const int k = k0 + kk;
+        if (k >= nS) break;
+        double gn[D];
+#pragma unroll
+        for (int n = 0; n < D; ++n) gn[n] = 0.0;
+#pragma unroll
+        for (int v = 0; v < D + 1; ++v) {
+            const double xv = X[cv[v] + (size_t)nRp * k];
+#pragma unroll
+            for (int n = 0; n < D; ++n) gn[n] = fma(dc[v][n], xv, gn[n]);
+        }
+#pragma unroll
+        for (int n = 0; n < D; ++n) Yc[j + (size_t)nRm * (n * (size_t)nS + k)] = gn[n] * inv;
+    }
 }
 
 // ----------------------------------------------------------------------------- odd PCG
@@ -534,11 +579,22 @@ void apply_A(const Handle* h, const double* X, double* B, hipStream_t s) {
 
 void apply_At_E(const Handle* h, const double* Z, const double* X, const double* G, const double* q,
                 double* Y, hipStream_t s, bool condensed) {
-    const size_t n = (size_t)h->nRp * h->nS;
+    const size_t n = (size_t)h->nRp * ((h->nS + kAtEK - 1) / kAtEK);
     const dim3 g((unsigned)((n + TPB - 1) / TPB));
-    decltype(&at_e_kernel<2, false>) f;
-    if (h->d == 2) f = condensed ? at_e_kernel<2, true> : at_e_kernel<2, false>;
-    else f = condensed ? at_e_kernel<3, true> : at_e_kernel<3, false>;
+    decltype(&at_e_kernel<2, false, double, kAtEK>) f;
+    if (h->d == 2) f = condensed ? at_e_kernel<2, true, double, kAtEK> : at_e_kernel<2, false, double, kAtEK>;
+    else f = condensed ? at_e_kernel<3, true, double, kAtEK> : at_e_kernel<3, false, double, kAtEK>;
+    hipLaunchKernelGGL(f, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->nnz, h->ncls, h->ncls_stiff, h->nbcls,
+                       h->vc_ptr.p, h->vc_cell.p, h->vcD.p, h->T.p, h->rowptr.p, h->col.p, h->MtMs.p, h->cls.p,
+                       h->bnd_row.p, h->coefE.p, Z, X, G, q, Y);
+    RTE_CHECK_LAUNCH();
+}
+
+void apply_At_E_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,
+                    hipStream_t s) {
+    const size_t n = (size_t)h->nRp * ((h->nS + kAtEK - 1) / kAtEK);
+    const dim3 g((unsigned)((n + TPB - 1) / TPB));
+    auto* f = h->d == 2 ? at_e_kernel<2, true, float, kAtEK> : at_e_kernel<3, true, float, kAtEK>;
     hipLaunchKernelGGL(f, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->nnz, h->ncls, h->ncls_stiff, h->nbcls,
                        h->vc_ptr.p, h->vc_cell.p, h->vcD.p, h->T.p, h->rowptr.p, h->col.p, h->MtMs.p, h->cls.p,
                        h->bnd_row.p, h->coefE.p, Z, X, G, q, Y);
@@ -546,9 +602,9 @@ void apply_At_E(const Handle* h, const double* Z, const double* X, const double*
 }
 
 void apply_grad(const Handle* h, const double* X, double* Yc, hipStream_t s) {
-    const size_t n = (size_t)h->nRm * h->nS;
+    const size_t n = (size_t)h->nRm * ((h->nS + kAtEK - 1) / kAtEK);
     const dim3 g((unsigned)((n + TPB - 1) / TPB));
-    auto* f = h->d == 2 ? apply_grad_kernel<2> : apply_grad_kernel<3>;
+    auto* f = h->d == 2 ? apply_grad_kernel<2, kAtEK> : apply_grad_kernel<3, kAtEK>;
     hipLaunchKernelGGL(f, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->cell.p, h->Dc.p, h->mt.p, X, Yc);
     RTE_CHECK_LAUNCH();
 }

@@ -99,6 +99,9 @@ void band_to_f32(const double* src, float* dst, int n, int bw, int nsys, size_t 
 // column-major n x n matrix; and the copy of that lower triangle to the upper one
 void band_to_dense(const double* band, int n, int bw, double* A, hipStream_t s);
 void symmetrize_lower(double* A, int n, hipStream_t s);
+// column-wise permutation of an n x ncols column-major matrix (src != dst):
+// gather dst[r, c] = src[iperm[r], c], or scatter dst[iperm[r], c] = src[r, c]
+void permute_cols(const int* iperm, int n, int ncols, const double* src, double* dst, bool gather, hipStream_t s);
 // Y = A X for a dense n x n matrix stored by rows
 void gemv_rows(int n, const double* A, const double* X, double* Y, hipStream_t s);
 // factor every E_0 block (one work-group per direction); *bad |= 1 on a non-positive pivot

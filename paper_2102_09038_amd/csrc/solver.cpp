@@ -22,6 +22,8 @@ enum WsId {
     W_CPART, W_CFIN,
     // even workspace (nRp x nS)
     W_EG, W_ET, W_ER, W_ES, W_ESTEP, W_EZ, W_ET2, W_CGR, W_CGP, W_CGQ,
+    // right-hand side and solution of the band solves in band order
+    W_BB, W_BX,
     // coarse
     W_CRHS, W_CSOL,
     W_COUNT
@@ -36,7 +38,7 @@ double* ws(Handle* h, int id) {
         if (id <= W_OG) n = odd;
         else if (id == W_CPART) n = (size_t)h->nRm * h->dNm * std::min(8, h->nSm);
         else if (id == W_CFIN) n = (size_t)h->nRm * h->dNm;
-        else if (id <= W_CGQ) n = even;
+        else if (id <= W_BX) n = even;
         else n = (size_t)h->nc;
         b.alloc(n);
     }
@@ -219,14 +221,22 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
            int* cgmax, bool lowp) {
     if (o->e0_solver == RTE_E0_BANDED) {
         if (!h->have_e0_banded) fail(RTE_E_ARG, "banded E_0 factors were not prepared at assembly");
-        Timed t(h, s, P_E0);
-        if (lowp && h->L0f.p) {
-            k::band_solve_blk_f32(h->L0f.p, h->L0Uf.p, h->nRp, h->sbw, h->nS, h->e0_stride32, X, Y, (size_t)h->nRp,
-                                  h->iperm.p, s);
-            return;
+        // the factors are in band (bandwidth-reducing) order: permute the columns of X into
+        // that order and the solution back in coalesced per-column passes, so that the
+        // solve itself reads and writes its vectors contiguously
+        double* Xb = ws(h, W_BB);
+        double* Yb = ws(h, W_BX);
+        k::permute_cols(h->iperm.p, h->nRp, h->nS, X, Xb, true, s);
+        {
+            Timed t(h, s, P_E0);
+            if (lowp && h->L0f.p)
+                k::band_solve_blk_f32(h->L0f.p, h->L0Uf.p, h->nRp, h->sbw, h->nS, h->e0_stride32, Xb, Yb,
+                                      (size_t)h->nRp, nullptr, s);
+            else
+                k::band_solve_blk(h->L0.p, h->L0U.p, h->nRp, h->sbw, h->nS, h->e0_stride, Xb, Yb, (size_t)h->nRp,
+                                  nullptr, s);
         }
-        k::band_solve_blk(h->L0.p, h->L0U.p, h->nRp, h->sbw, h->nS, h->e0_stride, X, Y, (size_t)h->nRp, h->iperm.p,
-                          s);
+        k::permute_cols(h->iperm.p, h->nRp, h->nS, Yb, Y, false, s);
         return;
     }
     double* r = ws(h, W_CGR);
