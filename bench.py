@@ -100,6 +100,51 @@ def cpu_baseline(inst, iters, l, seed=0):
             "est_seconds_per_solve": t_solve, "est_setup_s": t_setup, "est_iter_s": t_iter}
 
 
+COPY_BYTES = 4 << 30
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of a kernel from the committed counter summary, or None when
+    no summary holds the key or the kernel's source changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
+        for line in open(path):
+            f = line.split()
+            if len(f) == 5 and f[0] == "traffic:" and f[1] == key:
+                src = os.path.join(ROOT, f[2])
+                if not os.path.exists(src):
+                    return None
+                if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != f[3]:
+                    return None
+                return float(f[4])
+    return None
+
+
+def kernel_passes(h, inst, torch, rte):
+    """The launches the HBM counter passes read: the condensed FP64 ApplyE (its GEMM),
+    E_0^{-1} with FP64 and FP32 band factors, and a plain device copy of COPY_BYTES."""
+    d = h.dims
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn((d.nSp, d.nRp), dtype=torch.float64, device="cuda", generator=gen)
+    Y = torch.empty_like(X)
+    e_opts = rte.default_solve_opts(odd_solver=rte.RTE_ODD_CONDENSED)
+    for _ in range(2):
+        h.apply_E(X, Y, e_opts)
+    for prec in (rte.RTE_FP64, rte.RTE_MIXED):
+        o = rte.default_solve_opts(e0_solver=rte.RTE_E0_BANDED, precision=prec)
+        for _ in range(2):
+            h.apply_E0inv(X, Y, o)
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel_passes": ["apply_E condensed fp64 x2", "E0inv banded fp64 x2", "E0inv banded fp32 x2",
+                                        f"device copy {COPY_BYTES} bytes x2"]}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +152,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["kernels"], default=None,
+                    help="'kernels': assemble the realistic instance, run the dominant kernels twice each "
+                         "and a plain 4 GiB device copy (the reference for HBM counter passes), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
@@ -119,8 +167,13 @@ def main():
     from paper_2102_09038_amd import inputs, rte
 
     inst = inputs.config_realistic()
+    ta = time.perf_counter()
     h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)
+    t_assemble = time.perf_counter() - ta
     d = h.dims
+    if args.only == "kernels":
+        kernel_passes(h, inst, torch, rte)
+        return
     e0_bw, _, _ = h.band()
     opts = rte.default_solve_opts(l=inst.l, tol=args.tol, max_iter=1000, odd_solver=rte.RTE_ODD_CONDENSED,
                                   e0_solver=rte.RTE_E0_BANDED, pcg_tol_inner=1e-6, profile=1)
@@ -142,6 +195,9 @@ def main():
     t_gm = sum(i.t_gemm for i in infos)
     n_gm = sum(i.n_gemm for i in infos)
     fl_gm = sum(i.gemm_flops for i in infos)
+    t_sc = sum(i.t_scatter for i in infos)
+    n_sc = sum(i.n_scatter for i in infos)
+    fl_sc = sum(i.scatter_flops for i in infos)
     # algorithmic bytes of one E_0^{-1} launch: the band factor streamed twice (forward and
     # backward sweep) plus the right-hand side read and the solution written once
     n, bw = d.nRp, e0_bw
@@ -149,13 +205,15 @@ def main():
     e0_bytes = d.nSp * (2 * factor_entries * 8 + 2 * n * 8)
     e0_gbs = e0_bytes / (t_e0 / n_e0) / 1e9 if n_e0 else 0.0
     gemm_tf = fl_gm / t_gm / 1e12 if t_gm else 0.0
+    scatter_tf = fl_sc / t_sc / 1e12 if t_sc else 0.0
     e0_roof = {"bound": "hbm", "achieved": e0_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "frac": e0_gbs / HBM_PEAK_GBS, "traffic": None,
-               "kernel": "band_solve_blk_kernel (E_0^-1, all directions)",
+               "frac": e0_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("band_solve_f64"),
+               "kernel": "band_solve_kernel<double> (E_0^-1, all directions)",
                "avg_launch_ms": 1e3 * t_e0 / max(n_e0, 1), "launches": n_e0,
                "bytes_per_launch": e0_bytes, "time_share": t_e0 / dt}
     gemm_roof = {"bound": "mfma", "achieved": gemm_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                 "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": None, "kernel": "gemm_f64_kernel",
+                 "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": measured_traffic("gemm_f64_transport"),
+                 "kernel": "gemm_f64_kernel (condensed transport term of E)",
                  "avg_launch_ms": 1e3 * t_gm / max(n_gm, 1), "launches": n_gm,
                  "flops_per_launch": fl_gm / max(n_gm, 1), "time_share": t_gm / dt}
     dominant, other = (e0_roof, gemm_roof) if t_e0 >= t_gm else (gemm_roof, e0_roof)
@@ -169,8 +227,12 @@ def main():
                    "tol": args.tol, "l": inst.l, "N+": inst.n_even, "N-": inst.n_odd,
                    "odd_solver": "condensed", "e0_solver": "banded", "e0_band": e0_bw, "precision": "fp64"},
         "iters": [i.iters for i in infos], "rel_resid": [i.rel_resid for i in infos],
+        "t_assemble_s": t_assemble,
         "roofline": dominant, "roofline_other": other,
-        "scatter_gemm_tflops": gemm_tf,
+        "scatter_gemm": {"bound": "mfma", "achieved": scatter_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": scatter_tf / FP64_MFMA_PEAK_TFLOPS, "kernel": "gemm_f64_kernel (U S+, eq. tpmv)",
+                         "avg_launch_ms": 1e3 * t_sc / max(n_sc, 1), "launches": n_sc,
+                         "flops_per_launch": fl_sc / max(n_sc, 1)},
     }
     # ---- the mixed-precision form of the same solve: BF16/FP32 preconditioner (condensed
     #      transport GEMM in BF16 with FP32 accumulation, FP32 E_0 band factors), FP64
@@ -207,7 +269,7 @@ def main():
                       "launches": nb, "flops_per_launch": fb / max(nb, 1)},
         "e0inv_fp32": {"bound": "hbm", "achieved": e0m_bytes / (t_e0m / max(n_e0m, 1)) / 1e9 if n_e0m else 0.0,
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "avg_launch_ms": 1e3 * t_e0m / max(n_e0m, 1),
-                       "bytes_per_launch": e0m_bytes},
+                       "bytes_per_launch": e0m_bytes, "traffic": measured_traffic("band_solve_f32")},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, infos[-1].iters, inst.l)

@@ -133,12 +133,15 @@ typedef struct rte_solve_info {
     double t_solve;              /* seconds spent in rte_solve                               */
     double t_e0inv;              /* with opts->profile: seconds inside E_0^{-1} kernels      */
     int64_t n_e0inv;             /*   number of E_0^{-1} launches                            */
-    double t_gemm;               /*   seconds inside scattering / odd-inverse GEMM kernels   */
-    int64_t n_gemm;              /*   number of those GEMM launches                          */
-    double gemm_flops;           /*   their algorithmic flops (2 M N K summed)               */
+    double t_gemm;               /*   seconds inside the FP64 GEMMs of ApplyE (odd scatter,  */
+    int64_t n_gemm;              /*   odd inverse or condensed transport), their launches    */
+    double gemm_flops;           /*   and their algorithmic flops (2 M N K summed)           */
     double t_gemm_bf16;          /*   seconds inside BF16 (mixed-precision) GEMM kernels     */
     int64_t n_gemm_bf16;         /*   number of those launches                               */
     double gemm_bf16_flops;      /*   their algorithmic flops                                */
+    double t_scatter;            /*   seconds inside the even scatter GEMMs U S+ (eq. tpmv)  */
+    int64_t n_scatter;           /*   number of those launches                               */
+    double scatter_flops;        /*   their algorithmic flops                                */
 } rte_solve_info;
 
 /* Fill opts with the defaults: quad_level 2, N+ 0, N- 5, CG E_0, no mixed copies. */

@@ -46,7 +46,7 @@ double* ws(Handle* h, int id) {
 }
 
 // ----------------------------------------------------------------------------- timers
-enum ProfKind { P_E0 = 0, P_GEMM = 1, P_GEMM_BF16 = 2 };
+enum ProfKind { P_E0 = 0, P_GEMM = 1, P_GEMM_BF16 = 2, P_GEMM_SCATTER = 3 };
 
 hipEvent_t take_event(Handle* h) {
     if (h->evpool.empty()) {
@@ -94,6 +94,11 @@ void collect_profile(Handle* h, rte_solve_info* inf) {
         RTE_HIP(hipEventElapsedTime(&ms, r.a, r.b));
         if (r.kind == P_E0) { inf->t_e0inv += ms * 1e-3; inf->n_e0inv += 1; }
         else if (r.kind == P_GEMM) { inf->t_gemm += ms * 1e-3; inf->n_gemm += 1; inf->gemm_flops += r.flops; }
+        else if (r.kind == P_GEMM_SCATTER) {
+            inf->t_scatter += ms * 1e-3;
+            inf->n_scatter += 1;
+            inf->scatter_flops += r.flops;
+        }
         else { inf->t_gemm_bf16 += ms * 1e-3; inf->n_gemm_bf16 += 1; inf->gemm_bf16_flops += r.flops; }
         h->evpool.push_back(r.a);
         h->evpool.push_back(r.b);
@@ -213,7 +218,10 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
 void residual_like(Handle* h, const rte_solve_opts* o, const double* X, const double* q0, double* Y,
                    double tol, hipStream_t s, int64_t* pcg, bool lowp) {
     double* G = ws(h, W_EG);
-    gemm(h, h->nRp, h->nS, h->nS, X, h->nRp, h->Sp.p, h->nS, G, h->nRp, s);
+    {
+        Timed t(h, s, P_GEMM_SCATTER, 2.0 * h->nRp * (double)h->nS * h->nS);
+        k::gemm_f64(h->nRp, h->nS, h->nS, 1.0, X, h->nRp, h->Sp.p, h->nS, 0.0, G, h->nRp, s);
+    }
     apply_E_core(h, o, X, G, q0, Y, tol, s, pcg, lowp);
 }
 

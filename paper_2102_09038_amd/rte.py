@@ -52,7 +52,8 @@ class rte_solve_info(C.Structure):
                 ("cg_iters_max", C.c_int32), ("t_solve", C.c_double), ("t_e0inv", C.c_double),
                 ("n_e0inv", C.c_int64), ("t_gemm", C.c_double), ("n_gemm", C.c_int64),
                 ("gemm_flops", C.c_double), ("t_gemm_bf16", C.c_double), ("n_gemm_bf16", C.c_int64),
-                ("gemm_bf16_flops", C.c_double)]
+                ("gemm_bf16_flops", C.c_double), ("t_scatter", C.c_double), ("n_scatter", C.c_int64),
+                ("scatter_flops", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
