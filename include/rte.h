@@ -215,6 +215,51 @@ rte_status rte_get_array(rte_handle* h, int32_t which, void* host_dst, size_t ho
 /* Release the handle (synchronises its stream first).  NULL is accepted. */
 rte_status rte_destroy(rte_handle* h);
 
+/* ------------------------------------------------------------------ batched and served solves
+ * A batch advances several solves of Alg. 3 in lockstep, one outer iteration of every live
+ * slot per step.  In each of the l steps of P_1 (Alg. 2, eq. applyP1), the E_0^{-1} of all
+ * slots (Sec. 5.3) is one band-solve launch per band shape, so the direction systems of
+ * small problems share the GPU.  Slots can be admitted while others run, and they leave the
+ * lockstep as soon as their relative residual reaches their tolerance.  A slot computes
+ * exactly what rte_solve computes with the same options and handle, independently of the
+ * other slots.
+ * Requirements: the handle is assembled with e0_solver = RTE_E0_BANDED (and mixed != 0 for
+ * RTE_MIXED slots); odd_solver is RTE_ODD_EXACT or RTE_ODD_CONDENSED; all slots of a batch
+ * share precision and l; a handle holds at most one slot at a time.  The batch does not own
+ * the handles or the U arrays: both must stay alive until the slot has been polled.  A batch
+ * is not thread-safe. */
+typedef struct rte_batch rte_batch;
+
+/* max_slots in 1..4096; hbm_budget = device bytes the slots' handles and workspace may hold
+ * together (0 = unlimited). */
+rte_status rte_batch_create(int32_t max_slots, size_t hbm_budget, rte_batch** out);
+
+/* Admit a solve of h from U0 (device, n_R+ x n_S+ column-major; NULL = zero) into U
+ * (device, same shape, caller-owned; holds the iterate and, once the slot is done, the
+ * result).  Sets *slot.  Allocates the slot's solver workspace in the handle.  Returns
+ * RTE_E_NOMEM, with nothing admitted, when the handle's footprint plus that workspace exceeds
+ * the budget that is left; RTE_E_ARG when no slot is free or a requirement above fails.
+ * Enqueues the initialisation of U on hip_stream. */
+rte_status rte_batch_admit(rte_batch* b, rte_handle* h, const rte_solve_opts* opts, const double* U0,
+                           double* U, void* hip_stream, int32_t* slot);
+
+/* Run up to outer_iters lockstep iterations on hip_stream (blocking; one host
+ * synchronisation per iteration).  Returns early when no slot is live.  *n_live (nullable)
+ * receives the number of slots still iterating. */
+rte_status rte_batch_step(rte_batch* b, int32_t outer_iters, void* hip_stream, int32_t* n_live);
+
+/* Report and release up to max_out finished slots: slot ids, their solve infos (iters,
+ * rel_resid, stop_quantity, t_solve = seconds from admission to completion) and statuses
+ * (RTE_OK, RTE_E_NOTCONV or RTE_E_NONFINITE).  *n_done receives the count.  The
+ * released slot ids and budget become free. */
+rte_status rte_batch_poll(rte_batch* b, int32_t max_out, int32_t* slots, rte_solve_info* infos,
+                          int32_t* statuses, int32_t* n_done);
+
+/* Slots still iterating, finished slots not yet polled, device bytes held by admitted slots. */
+rte_status rte_batch_usage(const rte_batch* b, int32_t* n_live, int32_t* n_done, size_t* used_bytes);
+
+rte_status rte_batch_destroy(rte_batch* b);
+
 /* Thread-local text of the last non-OK status ("" if none). */
 const char* rte_last_error(void);
 

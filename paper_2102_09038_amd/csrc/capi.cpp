@@ -172,6 +172,64 @@ rte_status rte_solve(rte_handle* hh, const rte_solve_opts* o, const double* U0, 
     });
 }
 
+rte_status rte_batch_create(int32_t max_slots, size_t hbm_budget, rte_batch** out) {
+    return guarded([&] {
+        if (!out) rte::fail(RTE_E_ARG, "null output");
+        *out = nullptr;
+        *out = reinterpret_cast<rte_batch*>(rte::batch_create(max_slots, hbm_budget));
+        return RTE_OK;
+    });
+}
+
+rte_status rte_batch_admit(rte_batch* b, rte_handle* hh, const rte_solve_opts* o, const double* U0, double* U,
+                           void* hip_stream, int32_t* slot) {
+    return guarded([&] {
+        if (!b) rte::fail(RTE_E_ARG, "null batch");
+        rte::Handle* h = as_handle(hh);
+        check_opts(o);
+        if (!U) rte::fail(RTE_E_ARG, "null U");
+        const int id = rte::batch_admit(reinterpret_cast<rte::Batch*>(b), h, o, U0, U, as_stream(hip_stream));
+        if (slot) *slot = id;
+        return RTE_OK;
+    });
+}
+
+rte_status rte_batch_step(rte_batch* b, int32_t outer_iters, void* hip_stream, int32_t* n_live) {
+    return guarded([&] {
+        if (!b) rte::fail(RTE_E_ARG, "null batch");
+        if (outer_iters < 0) rte::fail(RTE_E_ARG, "outer_iters must be >= 0");
+        const int nl = rte::batch_step(reinterpret_cast<rte::Batch*>(b), outer_iters, as_stream(hip_stream));
+        if (n_live) *n_live = nl;
+        return RTE_OK;
+    });
+}
+
+rte_status rte_batch_poll(rte_batch* b, int32_t max_out, int32_t* slots, rte_solve_info* infos, int32_t* statuses,
+                          int32_t* n_done) {
+    return guarded([&] {
+        if (!b) rte::fail(RTE_E_ARG, "null batch");
+        if (max_out < 0) rte::fail(RTE_E_ARG, "max_out must be >= 0");
+        const int n = rte::batch_poll(reinterpret_cast<rte::Batch*>(b), max_out, slots, infos, statuses);
+        if (n_done) *n_done = n;
+        return RTE_OK;
+    });
+}
+
+rte_status rte_batch_usage(const rte_batch* b, int32_t* n_live, int32_t* n_done, size_t* used_bytes) {
+    return guarded([&] {
+        if (!b) rte::fail(RTE_E_ARG, "null batch");
+        rte::batch_usage(reinterpret_cast<const rte::Batch*>(b), n_live, n_done, used_bytes);
+        return RTE_OK;
+    });
+}
+
+rte_status rte_batch_destroy(rte_batch* b) {
+    return guarded([&] {
+        rte::batch_destroy(reinterpret_cast<rte::Batch*>(b));
+        return RTE_OK;
+    });
+}
+
 rte_status rte_get_array(rte_handle* hh, int32_t which, void* host_dst, size_t host_bytes) {
     return guarded([&] {
         rte::Handle* h = as_handle(hh);

@@ -14,6 +14,8 @@
 //   BL at (r, t) = L(r, r - bw + t)   (row r of L;   t = bw: 1 / L(r,r))
 //   BU at (r, t) = L(r + t, r)        (row r of L^T; t = 0:  1 / L(r,r))
 // Entries outside the matrix, and the padding of the last group, are zero.
+#include <algorithm>
+
 #include "ops.h"
 
 namespace rte {
@@ -145,11 +147,21 @@ template <> struct Vec16<float> { typedef float T __attribute__((ext_vector_type
 // A row block is P phases of H groups (the layout pads the group count to P H), all
 // unrolled, so every ring slot, band offset and load source is known at compile time; the
 // only loop that carries the ring is the one over row blocks.
+// The solve's memory is global device memory, said explicitly in the pointer types: a
+// pointer read from memory (the grouped launch's job table) is otherwise generic to the
+// compiler, and generic (flat) loads are also counted as LDS operations, so waiting for one
+// would drain the whole ring.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T* as_global(T* p) {
+    return (GLOBAL T*)p;
+}
+
 template <typename FT, int H, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void band_solve_kernel(const FT* __restrict__ BLall, const FT* __restrict__ BUall, int n, int bw,
-                       size_t stride_sys, const double* __restrict__ ball, double* __restrict__ xall,
-                       size_t stride_vec, const int* __restrict__ iperm, int W) {
+__device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ BLs,
+                                                  const GLOBAL FT* __restrict__ BUs, int n, int bw,
+                                                  const GLOBAL double* __restrict__ b, GLOBAL double* __restrict__ x,
+                                                  const int* __restrict__ iperm, int W) {
     typedef typename Vec16<FT>::T V;
     constexpr int VEC = Vec16<FT>::N;
     constexpr int G = H * P;
@@ -157,18 +169,13 @@ void band_solve_kernel(const FT* __restrict__ BLall, const FT* __restrict__ BUal
     extern __shared__ double smem[];
     double* win = smem;            // 2 W entries
     double* D = smem + 2 * W;
-    const int sys = blockIdx.x;
     const int lane = threadIdx.x;
-    const FT* BLs = BLall + stride_sys * sys;
-    const FT* BUs = BUall + stride_sys * sys;
-    const double* b = ball + stride_vec * sys;
-    double* x = xall + stride_vec * sys;
     const int nblk = (n + 63) / 64;
     const int Wm = W - 1;
     const int nstep = 2 * nblk;
     for (int e = lane; e < 2 * W; e += 64) win[e] = 0.0;
     // step st: forward row block st (st < nblk), else backward row block 2 nblk - 1 - st
-    auto block_ptr = [&](int st) -> const FT* {
+    auto block_ptr = [&](int st) -> const GLOBAL FT* {
         return st < nblk ? BLs + (size_t)st * bs : BUs + (size_t)(nstep - 1 - st) * bs;
     };
     auto step_row = [&](int st) -> int { return 64 * (st < nblk ? st : nstep - 1 - st) + lane; };
@@ -180,7 +187,7 @@ void band_solve_kernel(const FT* __restrict__ BLall, const FT* __restrict__ BUal
     };
     V ring[H];
     {
-        const V* p0 = reinterpret_cast<const V*>(block_ptr(0));
+        const GLOBAL V* p0 = reinterpret_cast<const GLOBAL V*>(block_ptr(0));
 #pragma unroll
         for (int i = 0; i < H; ++i) ring[i] = p0[(size_t)i * 64 + lane];
     }
@@ -212,8 +219,8 @@ void band_solve_kernel(const FT* __restrict__ BLall, const FT* __restrict__ BUal
             cidx = nidx;
             nidx = src_index(st + 2);
         }
-        const V* cur = reinterpret_cast<const V*>(block_ptr(st));
-        const V* nxt = reinterpret_cast<const V*>(block_ptr(min(st + 1, nstep - 1)));
+        const GLOBAL V* cur = reinterpret_cast<const GLOBAL V*>(block_ptr(st));
+        const GLOBAL V* nxt = reinterpret_cast<const GLOBAL V*>(block_ptr(min(st + 1, nstep - 1)));
         // the ring entries of this block's own rows are not known yet: zero
         win[row & Wm] = 0.0;
         win[(row & Wm) + W] = 0.0;
@@ -301,6 +308,36 @@ void band_solve_kernel(const FT* __restrict__ BLall, const FT* __restrict__ BUal
         }
         __syncthreads();
     }
+}
+
+// one system per work-group: factors and vectors at fixed strides
+template <typename FT, int H, int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void band_solve_kernel(const FT* __restrict__ BLall, const FT* __restrict__ BUall, int n, int bw,
+                       size_t stride_sys, const double* __restrict__ ball, double* __restrict__ xall,
+                       size_t stride_vec, const int* __restrict__ iperm, int W) {
+    const int sys = blockIdx.x;
+    band_solve_system<FT, H, P>(as_global(BLall + stride_sys * sys), as_global(BUall + stride_sys * sys), n, bw,
+                                as_global(ball + stride_vec * sys), as_global(xall + stride_vec * sys), iperm, W);
+}
+
+// the systems of several jobs (problem instances of one band shape) in one launch: the
+// work-group finds its job by binary search over the jobs' first work-group indices
+template <typename FT, int H, int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void band_solve_group_kernel(const k::BandJob* __restrict__ jobs, int njobs) {
+    const int wg = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].first <= wg) lo = mid;
+        else hi = mid - 1;
+    }
+    const k::BandJob& J = jobs[lo];
+    const size_t sys = (size_t)(wg - J.first);
+    band_solve_system<FT, H, P>(as_global(static_cast<const FT*>(J.BL) + J.stride_sys * sys),
+                                as_global(static_cast<const FT*>(J.BU) + J.stride_sys * sys), J.n, J.bw,
+                                as_global(J.b + J.stride_vec * sys), as_global(J.x + J.stride_vec * sys), nullptr, J.W);
 }
 
 // lower band (row-major, band[r (bw+1) + bw + c - r]) -> lower triangle of a dense
@@ -409,16 +446,22 @@ void band_launch_hp(const FT* BL, const FT* BU, int n, int bw, int nsys, size_t 
     RTE_CHECK_LAUNCH();
 }
 
+// ring: the rows a block reads (bw before it, or after it, its own 64 and up to a group of
+// padding) fit in W; W >= 256 also covers the window of ring reads ahead
+int band_ring(int bw, int vec) {
+    const BandShape sh = band_shape(bw, vec);
+    return std::max(256, pow2_at_least(std::max(bw + 64 + vec * 8, sh.H * sh.P * vec)));
+}
+size_t band_lds(int W) { return (size_t)(2 * W + 64 * 65) * 8; }
+
 template <typename FT>
 void band_solve_launch(const FT* BL, const FT* BU, int n, int bw, int nsys, size_t stride_sys, const double* b,
                        double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
     if (nsys <= 0 || n <= 0) return;
     constexpr int VEC = 16 / (int)sizeof(FT);
-    // ring: the rows a block reads (bw before it, or after it, its own 64 and up to a group of
-    // padding) fit in W; W >= 256 also covers the window of ring reads ahead
     const BandShape sh = band_shape(bw, VEC);
-    const int W = std::max(256, pow2_at_least(std::max(bw + 64 + VEC * 8, sh.H * sh.P * VEC)));
-    const size_t lds = (size_t)(2 * W + 64 * 65) * 8;
+    const int W = band_ring(bw, VEC);
+    const size_t lds = band_lds(W);
     if (lds > 150 * 1024) fail(RTE_E_ARG, "band too wide for the solve window");
 #define RTE_BAND_CASE(HH, PP)                                                                             \
     if (sh.H == HH && sh.P == PP) {                                                                       \
@@ -430,6 +473,74 @@ void band_solve_launch(const FT* BL, const FT* BU, int n, int bw, int nsys, size
     RTE_BAND_CASE(17, 3) RTE_BAND_CASE(33, 3) RTE_BAND_CASE(33, 4)
 #undef RTE_BAND_CASE
     fail(RTE_E_ARG, "band too wide for the solve kernel");
+}
+
+template <typename FT, int H, int P>
+void band_group_launch_hp(const BandJob* jobs, int njobs, int nwg, size_t lds, hipStream_t s) {
+    RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_group_kernel<FT, H, P>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((band_solve_group_kernel<FT, H, P>), dim3(nwg), dim3(64), lds, s, jobs, njobs);
+    RTE_CHECK_LAUNCH();
+}
+
+void band_group_plan(std::vector<BandJob>& jobs, bool f32, BandGroupPlan& plan, hipStream_t s) {
+    const int vec = f32 ? 4 : 2;
+    for (auto& j : jobs) {
+        const BandShape sh = band_shape(j.bw, vec);
+        if (sh.H == 0) fail(RTE_E_ARG, "band too wide for the solve kernel");
+        j.W = band_ring(j.bw, vec);
+        if (band_lds(j.W) > 150 * 1024) fail(RTE_E_ARG, "band too wide for the solve window");
+        j.first = sh.H * 16 + sh.P;                 // sort key for now
+    }
+    std::stable_sort(jobs.begin(), jobs.end(), [](const BandJob& a, const BandJob& b) { return a.first < b.first; });
+    plan.launches.clear();
+    for (size_t i = 0; i < jobs.size();) {
+        const int key = jobs[i].first;
+        BandGroupPlan::Launch L{};
+        L.H = key / 16;
+        L.P = key % 16;
+        L.first_job = (int)i;
+        int wg = 0, wmax = 0;
+        size_t e = i;
+        for (; e < jobs.size() && jobs[e].first == key; ++e) {
+            wmax = std::max(wmax, jobs[e].W);
+            const int nsys = jobs[e].nsys;
+            jobs[e].first = wg;
+            wg += nsys;
+        }
+        L.njobs = (int)(e - i);
+        L.nwg = wg;
+        L.lds = band_lds(wmax);
+        if (wg > 0) plan.launches.push_back(L);
+        i = e;
+    }
+    plan.f32 = f32;
+    plan.jobs.alloc(std::max<size_t>(jobs.size(), 1));
+    if (!jobs.empty())
+        RTE_HIP(hipMemcpyAsync(plan.jobs.p, jobs.data(), jobs.size() * sizeof(BandJob), hipMemcpyHostToDevice, s));
+    RTE_HIP(hipStreamSynchronize(s));
+}
+
+void band_group_run(const BandGroupPlan& plan, hipStream_t s) {
+    for (const auto& L : plan.launches) {
+        const BandJob* jp = plan.jobs.p + L.first_job;
+#define RTE_GROUP_CASE(FT, HH, PP)                                                 \
+    if (L.H == HH && L.P == PP) {                                                  \
+        band_group_launch_hp<FT, HH, PP>(jp, L.njobs, L.nwg, L.lds, s);            \
+        continue;                                                                  \
+    }
+        if (plan.f32) {
+            RTE_GROUP_CASE(float, 9, 1) RTE_GROUP_CASE(float, 17, 1) RTE_GROUP_CASE(float, 33, 1)
+            RTE_GROUP_CASE(float, 9, 2) RTE_GROUP_CASE(float, 17, 2) RTE_GROUP_CASE(float, 33, 2)
+            RTE_GROUP_CASE(float, 17, 3) RTE_GROUP_CASE(float, 33, 3) RTE_GROUP_CASE(float, 33, 4)
+        } else {
+            RTE_GROUP_CASE(double, 9, 1) RTE_GROUP_CASE(double, 17, 1) RTE_GROUP_CASE(double, 33, 1)
+            RTE_GROUP_CASE(double, 9, 2) RTE_GROUP_CASE(double, 17, 2) RTE_GROUP_CASE(double, 33, 2)
+            RTE_GROUP_CASE(double, 17, 3) RTE_GROUP_CASE(double, 33, 3) RTE_GROUP_CASE(double, 33, 4)
+        }
+#undef RTE_GROUP_CASE
+        fail(RTE_E_ARG, "band too wide for the solve kernel");
+    }
 }
 
 void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, double* BL, double* BU,

@@ -92,6 +92,31 @@ void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys,
 // same with FP32 factors (the reduced-precision preconditioner); FP64 vectors and sums
 void band_solve_blk_f32(const float* BL, const float* BU, int n, int bw, int nsys, size_t stride_sys,
                         const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s);
+// One job of a grouped band solve: nsys systems with factors at BL/BU + stride_sys * sys (FP64 or
+// FP32 elements, per launch) and right-hand sides / solutions in band order at
+// b/x + stride_vec * sys.  W and first are filled in by band_group_plan.
+struct BandJob {
+    const void* BL;
+    const void* BU;
+    const double* b;
+    double* x;
+    size_t stride_sys, stride_vec;
+    int n, bw, nsys, W, first;
+};
+// the launches of a set of jobs, one per band shape, and the jobs in device memory
+struct BandGroupPlan {
+    struct Launch {
+        int H, P, first_job, njobs, nwg;
+        size_t lds;
+    };
+    std::vector<Launch> launches;
+    DBuf<BandJob> jobs;
+    bool f32 = false;
+};
+// sort the jobs by band shape, number their work-groups and upload them (blocking)
+void band_group_plan(std::vector<BandJob>& jobs, bool f32, BandGroupPlan& plan, hipStream_t s);
+// all jobs' solves, one launch per band shape
+void band_group_run(const BandGroupPlan& plan, hipStream_t s);
 // FP64 blocked factors -> FP32 blocked factors (their own layout, 4 entries per group)
 void band_to_f32(const double* src, float* dst, int n, int bw, int nsys, size_t stride64, size_t stride32,
                  hipStream_t s);

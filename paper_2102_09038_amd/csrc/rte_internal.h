@@ -181,6 +181,15 @@ void precond(Handle* h, const rte_solve_opts* o, int which, const double* r, dou
 rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U,
                  rte_solve_info* info, hipStream_t s);
 
+// lockstep batch of solves (solver_batch.cpp)
+struct Batch;
+Batch* batch_create(int max_slots, size_t budget);
+void batch_destroy(Batch* B);
+int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, double* U, hipStream_t s);
+int batch_step(Batch* B, int outer_iters, hipStream_t s);
+int batch_poll(Batch* B, int max_out, int32_t* slots, rte_solve_info* infos, int32_t* statuses);
+void batch_usage(const Batch* B, int32_t* n_live, int32_t* n_done, size_t* used_bytes);
+
 // ----------------------------------------------------------------------------- launchers
 namespace k {
 // Dense scattering matrices by double quadrature of the HG kernel.

@@ -6,28 +6,10 @@
 #include <chrono>
 #include <cmath>
 
-#include "ops.h"
-#include "rte_internal.h"
+#include "solver_detail.h"
 
 namespace rte {
-namespace {
-
-// device scalar slots
-enum Slot { S_BB = 0, S_PW, S_ALPHA, S_RR, S_RZ0, S_RZ1, S_BETA, S_DOT0, S_DOT1, S_DOT2 };
-
-enum WsId {
-    // odd workspace (nRm x nSm)
-    W_OB = 0, W_OZ, W_OR, W_OP, W_OW, W_OY, W_OG,
-    // thin odd workspace
-    W_CPART, W_CFIN,
-    // even workspace (nRp x nS)
-    W_EG, W_ET, W_ER, W_ES, W_ESTEP, W_EZ, W_ET2, W_CGR, W_CGP, W_CGQ,
-    // right-hand side and solution of the band solves in band order
-    W_BB, W_BX,
-    // coarse
-    W_CRHS, W_CSOL,
-    W_COUNT
-};
+namespace sv {
 
 double* ws(Handle* h, int id) {
     if (h->ws.size() < W_COUNT) h->ws.resize(W_COUNT);
@@ -297,7 +279,9 @@ void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const 
     k::richardson_update(h, step, sv, uc, s);
 }
 
-}  // namespace
+}  // namespace sv
+
+using namespace sv;
 
 void apply_E(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s, int64_t* pcg) {
     apply_E_core(h, o, X, nullptr, nullptr, Y, o->pcg_tol_resid, s, pcg, o->precision == RTE_MIXED);

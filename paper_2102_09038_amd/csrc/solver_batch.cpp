@@ -1,0 +1,265 @@
+// Lockstep preconditioned Richardson iteration over several problem instances (the batched
+// and served forms of Alg. 3).  Every live slot takes one outer step per batch iteration:
+// - the residuals of all slots are formed, and ONE host synchronisation reads every slot's
+//   residual norm and step products;
+// - in each of the l steps of P_1 (Alg. 2), the E_0^{-1} applications of all slots are one
+//   grouped band-solve launch per band shape, so that the direction systems of small
+//   instances fill the GPU together;
+// - the remaining per-slot work (ApplyE, the subspace correction) is enqueued slot after slot
+//   on the same stream.
+// Slots may be admitted while others are running and leave as soon as they converge, which
+// is what a continuous-batching server needs.  The arithmetic of a slot is the arithmetic of
+// rte_solve with the same options, so a slot's result does not depend on the other slots.
+#include <chrono>
+#include <cmath>
+
+#include "solver_detail.h"
+
+namespace rte {
+
+using namespace sv;
+
+struct BatchSlot {
+    Handle* h = nullptr;
+    double* U = nullptr;
+    rte_solve_opts o{};
+    rte_solve_info info{};
+    rte_status status = RTE_OK;
+    bool used = false, live = false, done = false;
+    int iters = 0;
+    bool have_step = false;
+    double e1 = -1.0;
+    size_t bytes = 0;
+    std::chrono::steady_clock::time_point t0;
+};
+
+struct Batch {
+    int max_slots = 0;
+    size_t budget = 0, used_bytes = 0;
+    int precision = -1;                 // of the slots (the grouped solve's factor type)
+    int l = 0;                          // P_1 steps of the slots (they advance together)
+    std::vector<BatchSlot> slots;
+    k::BandGroupPlan plan;
+    bool plan_valid = false;
+};
+
+namespace {
+
+// the workspace a batch slot uses (condensed or exact odd solve, banded E_0)
+const int kSlotWs[] = {W_OB, W_OZ, W_EG, W_ET, W_ER, W_ES, W_ESTEP, W_EZ, W_ET2, W_BB, W_BX, W_CRHS, W_CSOL};
+
+size_t ws_bytes(const Handle* h, int id) {
+    const size_t odd = (size_t)h->nRm * h->nSm, even = (size_t)h->nRp * h->nS;
+    size_t n;
+    if (id <= W_OG) n = odd;
+    else if (id <= W_BX) n = even;
+    else n = (size_t)h->nc;
+    return n * sizeof(double);
+}
+
+size_t slot_bytes(Handle* h) {
+    size_t b = h->footprint();
+    if (h->ws.size() < W_COUNT) h->ws.resize(W_COUNT);
+    for (int id : kSlotWs)
+        if (!h->ws[id].p) b += ws_bytes(h, id);
+    return b;
+}
+
+void rebuild_plan(Batch* B, hipStream_t s) {
+    std::vector<k::BandJob> jobs;
+    const bool f32 = B->precision == RTE_MIXED;
+    for (auto& sl : B->slots) {
+        if (!sl.live) continue;
+        Handle* h = sl.h;
+        k::BandJob j{};
+        j.BL = f32 ? static_cast<const void*>(h->L0f.p) : static_cast<const void*>(h->L0.p);
+        j.BU = f32 ? static_cast<const void*>(h->L0Uf.p) : static_cast<const void*>(h->L0U.p);
+        j.b = ws(h, W_BB);
+        j.x = ws(h, W_BX);
+        j.stride_sys = f32 ? h->e0_stride32 : h->e0_stride;
+        j.stride_vec = (size_t)h->nRp;
+        j.n = h->nRp;
+        j.bw = h->sbw;
+        j.nsys = h->nS;
+        jobs.push_back(j);
+    }
+    k::band_group_plan(jobs, f32, B->plan, s);
+    B->plan_valid = true;
+}
+
+// X -> Y = E_0^{-1} X for every live slot (x_of / y_of give the slot's vectors)
+template <typename XF, typename YF>
+void grouped_e0inv(Batch* B, XF x_of, YF y_of, hipStream_t s) {
+    for (auto& sl : B->slots)
+        if (sl.live) k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, x_of(sl), ws(sl.h, W_BB), true, s);
+    k::band_group_run(B->plan, s);
+    for (auto& sl : B->slots)
+        if (sl.live) k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, ws(sl.h, W_BX), y_of(sl), false, s);
+}
+
+void finish(BatchSlot& sl, rte_status st) {
+    sl.status = st;
+    sl.live = false;
+    sl.done = true;
+    sl.info.iters = sl.iters;
+    sl.info.t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - sl.t0).count();
+}
+
+}  // namespace
+
+Batch* batch_create(int max_slots, size_t budget) {
+    if (max_slots < 1 || max_slots > 4096) fail(RTE_E_ARG, "max_slots must lie in 1..4096");
+    Batch* B = new Batch;
+    B->max_slots = max_slots;
+    B->budget = budget;
+    B->slots.resize(max_slots);
+    return B;
+}
+
+void batch_destroy(Batch* B) { delete B; }
+
+int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, double* U, hipStream_t s) {
+    if (o->e0_solver != RTE_E0_BANDED || !h->have_e0_banded)
+        fail(RTE_E_ARG, "batch slots need the banded E_0 solve (assemble with e0_solver = RTE_E0_BANDED)");
+    if (o->odd_solver == RTE_ODD_PCG) fail(RTE_E_ARG, "batch slots use the exact or condensed odd solve");
+    if (o->precision == RTE_MIXED && !(h->have_mixed && h->L0f.p))
+        fail(RTE_E_ARG, "a mixed-precision slot needs a handle assembled with mixed != 0");
+    if (o->precision == RTE_FP64 && !h->L0.p) fail(RTE_E_ARG, "an FP64 slot needs the FP64 band factors");
+    bool any = false;
+    for (auto& sl : B->slots) any |= sl.used;
+    if (any && o->precision != B->precision) fail(RTE_E_ARG, "all slots of a batch share one precision");
+    if (any && o->l != B->l) fail(RTE_E_ARG, "all slots of a batch share one l");
+    for (auto& sl : B->slots)
+        if (sl.used && sl.h == h) fail(RTE_E_ARG, "a handle can hold one slot at a time");
+    int id = -1;
+    for (int i = 0; i < B->max_slots; ++i)
+        if (!B->slots[i].used) { id = i; break; }
+    if (id < 0) fail(RTE_E_ARG, "no free batch slot");
+    const size_t bytes = slot_bytes(h);
+    if (B->budget && B->used_bytes + bytes > B->budget) fail(RTE_E_NOMEM, "the batch's device-memory budget is full");
+    for (int wid : kSlotWs) ws(h, wid);
+    B->precision = o->precision;
+    B->l = o->l;
+    BatchSlot& sl = B->slots[id];
+    sl = BatchSlot{};
+    sl.h = h;
+    sl.U = U;
+    sl.o = *o;
+    sl.o.profile = 0;
+    sl.used = sl.live = true;
+    sl.bytes = bytes;
+    sl.t0 = std::chrono::steady_clock::now();
+    B->used_bytes += bytes;
+    const size_t n = (size_t)h->nRp * h->nS;
+    if (U0) k::copy(U0, U, n, s);
+    else k::fill(U, 0.0, n, s);
+    B->plan_valid = false;
+    return id;
+}
+
+int batch_step(Batch* B, int outer_iters, hipStream_t s) {
+    const bool lowp = B->precision == RTE_MIXED;
+    for (int it = 0; it < outer_iters; ++it) {
+        // ---- residuals r_n = (E - K+) u_n - q (FP64) and the scalars of the stopping tests
+        int nlive = 0;
+        for (auto& sl : B->slots) {
+            if (!sl.live) continue;
+            ++nlive;
+            Handle* h = sl.h;
+            const size_t n = (size_t)h->nRp * h->nS;
+            double* r = ws(h, W_ER);
+            residual_like(h, &sl.o, sl.U, h->q.p, r, sl.o.pcg_tol_resid, s, &sl.info.pcg_iters_total, false);
+            k::dot(r, r, n, h->red.p, s);
+            k::reduce(h->red.p, h->scal.p, S_DOT0, s);
+            if (sl.have_step) {
+                k::dot(ws(h, W_ESTEP), r, n, h->red.p, s);
+                k::reduce(h->red.p, h->scal.p, S_DOT1, s);
+            }
+            RTE_HIP(hipMemcpyAsync(h->pinned, h->scal.p, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        if (nlive == 0) return 0;
+        RTE_HIP(hipStreamSynchronize(s));
+        bool changed = false;
+        for (auto& sl : B->slots) {
+            if (!sl.live) continue;
+            const double* hp = sl.h->pinned;
+            const double rr = hp[S_DOT0];
+            if (!std::isfinite(rr)) { finish(sl, RTE_E_NONFINITE); changed = true; continue; }
+            sl.info.rel_resid = std::sqrt(rr) / sl.h->qnorm;
+            if (sl.have_step) {
+                // ||u_n - u_{n-1}||^2_{E-K} = step^T (r_n - r_{n-1}); step^T r_{n-1} was left in
+                // S_DOT2 by the previous iteration
+                const double en = std::sqrt(std::max(hp[S_DOT1] - hp[S_DOT2], 0.0));
+                if (sl.e1 < 0) sl.e1 = en;
+                sl.info.stop_quantity = sl.e1 > 0 ? en / sl.e1 : 0.0;
+            }
+            if (sl.info.rel_resid <= sl.o.tol) { finish(sl, RTE_OK); changed = true; }
+            else if (sl.iters >= sl.o.max_iter) { finish(sl, RTE_E_NOTCONV); changed = true; }
+        }
+        if (changed || !B->plan_valid) rebuild_plan(B, s);
+        bool any = false;
+        for (auto& sl : B->slots) any |= sl.live;
+        if (!any) return 0;
+        // ---- P_1^l (Alg. 2): z = E_0^{-1} r, then l - 1 steps z -= E_0^{-1} (E z - r)
+        grouped_e0inv(B, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ER); },
+                      [](BatchSlot& sl) { return ws(sl.h, W_ES); }, s);
+        for (int i = 1; i < B->l; ++i) {
+            for (auto& sl : B->slots) {
+                if (!sl.live) continue;
+                apply_E_core(sl.h, &sl.o, ws(sl.h, W_ES), nullptr, ws(sl.h, W_ER), ws(sl.h, W_ET2), sl.o.pcg_tol_inner,
+                             s, &sl.info.pcg_iters_total, lowp);
+            }
+            grouped_e0inv(B, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ET2); },
+                          [](BatchSlot& sl) { return ws(sl.h, W_EZ); }, s);
+            for (auto& sl : B->slots) {
+                if (!sl.live) continue;
+                k::axpby(-1.0, ws(sl.h, W_EZ), 1.0, ws(sl.h, W_ES), (size_t)sl.h->nRp * sl.h->nS, s);
+            }
+        }
+        // ---- subspace correction (Sec. 5.4) and the update u_{n+1} = u_n + step
+        for (auto& sl : B->slots) {
+            if (!sl.live) continue;
+            Handle* h = sl.h;
+            const size_t n = (size_t)h->nRp * h->nS;
+            double* r = ws(h, W_ER);
+            double* step = ws(h, W_ESTEP);
+            correction_step(h, &sl.o, r, ws(h, W_ES), step, s, &sl.info.pcg_iters_total, lowp);
+            k::dot(step, r, n, h->red.p, s);
+            k::reduce(h->red.p, h->scal.p, S_DOT2, s);
+            k::axpby(1.0, step, 1.0, sl.U, n, s);
+            ++sl.iters;
+            sl.have_step = true;
+        }
+    }
+    int nlive = 0;
+    for (auto& sl : B->slots) nlive += sl.live ? 1 : 0;
+    return nlive;
+}
+
+int batch_poll(Batch* B, int max_out, int32_t* slots, rte_solve_info* infos, int32_t* statuses) {
+    int n = 0;
+    for (int i = 0; i < B->max_slots && n < max_out; ++i) {
+        BatchSlot& sl = B->slots[i];
+        if (!sl.used || !sl.done) continue;
+        if (slots) slots[n] = i;
+        if (infos) infos[n] = sl.info;
+        if (statuses) statuses[n] = sl.status;
+        B->used_bytes -= sl.bytes;
+        sl = BatchSlot{};
+        ++n;
+    }
+    return n;
+}
+
+void batch_usage(const Batch* B, int32_t* n_live, int32_t* n_done, size_t* used_bytes) {
+    int live = 0, done = 0;
+    for (auto& sl : B->slots) {
+        live += sl.live ? 1 : 0;
+        done += (sl.used && sl.done) ? 1 : 0;
+    }
+    if (n_live) *n_live = live;
+    if (n_done) *n_done = done;
+    if (used_bytes) *used_bytes = B->used_bytes;
+}
+
+}  // namespace rte

@@ -1,0 +1,39 @@
+// Internal pieces of the Richardson solver shared by the single-instance solve
+// (solver.cpp) and the lockstep batch (solver_batch.cpp).
+#pragma once
+#include "ops.h"
+
+namespace rte {
+namespace sv {
+
+// device scalar slots of a handle (Handle::scal)
+enum Slot { S_BB = 0, S_PW, S_ALPHA, S_RR, S_RZ0, S_RZ1, S_BETA, S_DOT0, S_DOT1, S_DOT2 };
+
+// workspace buffers of a handle (allocated on first use)
+enum WsId {
+    // odd workspace (nRm x nSm)
+    W_OB = 0, W_OZ, W_OR, W_OP, W_OW, W_OY, W_OG,
+    // thin odd workspace
+    W_CPART, W_CFIN,
+    // even workspace (nRp x nS)
+    W_EG, W_ET, W_ER, W_ES, W_ESTEP, W_EZ, W_ET2, W_CGR, W_CGP, W_CGQ,
+    // right-hand side and solution of the band solves in band order
+    W_BB, W_BX,
+    // coarse
+    W_CRHS, W_CSOL,
+    W_COUNT
+};
+
+double* ws(Handle* h, int id);
+// Y = E X [- q0] (q0 nullable), or with G = X S+ given: Y = (E - K+) X - q0  (Alg. 1)
+void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const double* G, const double* q0, double* Y,
+                  double tol, hipStream_t s, int64_t* pcg, bool lowp);
+// Y = (E - K+) X - q0 (FP64 scatter GEMM, then apply_E_core)
+void residual_like(Handle* h, const rte_solve_opts* o, const double* X, const double* q0, double* Y, double tol,
+                   hipStream_t s, int64_t* pcg, bool lowp);
+// step = -s + W E_c^{-1} W^T ((E - K+) s - r)   (Sec. 5.4)
+void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const double* sv, double* step,
+                     hipStream_t s, int64_t* pcg, bool lowp);
+
+}  // namespace sv
+}  // namespace rte

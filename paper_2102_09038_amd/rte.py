@@ -77,6 +77,14 @@ EXPORTS = {
                             C.POINTER(rte_solve_info), C.c_void_p]),
     "rte_get_array": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "rte_destroy": (C.c_int, [C.c_void_p]),
+    "rte_batch_create": (C.c_int, [C.c_int32, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "rte_batch_admit": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.POINTER(C.c_int32)]),
+    "rte_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
+    "rte_batch_poll": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(rte_solve_info),
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "rte_batch_usage": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]),
+    "rte_batch_destroy": (C.c_int, [C.c_void_p]),
     "rte_last_error": (C.c_char_p, []),
 }
 
@@ -244,3 +252,56 @@ class Handle:
         if st != RTE_OK and (raise_on_notconv or st != RTE_E_NOTCONV):
             _check(st)
         return st, info
+
+
+class Batch:
+    """Lockstep batch of solves (rte_batch_*): admit handles with their output arrays, step
+    all live slots together, poll finished ones.  Handles and arrays must outlive their slot."""
+
+    def __init__(self, max_slots=64, hbm_budget=0):
+        self.b = C.c_void_p()
+        _check(lib.rte_batch_create(int(max_slots), int(hbm_budget), C.byref(self.b)))
+        self._keep = {}
+
+    def close(self):
+        if self.b:
+            lib.rte_batch_destroy(self.b)
+            self.b = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, handle, U, opts=None, U0=None, stream=None) -> int:
+        o = opts or default_solve_opts()
+        slot = C.c_int32(-1)
+        _check(lib.rte_batch_admit(self.b, handle.h, C.byref(o), C.c_void_p(U0.data_ptr() if U0 is not None else 0),
+                                   C.c_void_p(U.data_ptr()), _stream(stream), C.byref(slot)))
+        self._keep[slot.value] = (handle, U, U0)
+        return slot.value
+
+    def step(self, outer_iters=1, stream=None) -> int:
+        n = C.c_int32(0)
+        _check(lib.rte_batch_step(self.b, int(outer_iters), _stream(stream), C.byref(n)))
+        return n.value
+
+    def poll(self, max_out=None):
+        m = max_out if max_out is not None else 4096
+        slots = (C.c_int32 * m)()
+        infos = (rte_solve_info * m)()
+        stats = (C.c_int32 * m)()
+        n = C.c_int32(0)
+        _check(lib.rte_batch_poll(self.b, m, slots, infos, stats, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            self._keep.pop(slots[i], None)
+            out.append((slots[i], stats[i], infos[i]))
+        return out
+
+    def usage(self):
+        nl, nd, ub = C.c_int32(0), C.c_int32(0), C.c_size_t(0)
+        _check(lib.rte_batch_usage(self.b, C.byref(nl), C.byref(nd), C.byref(ub)))
+        return nl.value, nd.value, ub.value
