@@ -145,6 +145,91 @@ def kernel_passes(h, inst, torch, rte):
                                         f"device copy {COPY_BYTES} bytes x2"]}))
 
 
+def batch_bench(args, torch, rte, inputs):
+    """The batched form: count seeded instances of uneven size (N ~ U{32..128}, 128/512/2048
+    sphere triangles, g ~ U[0,0.95], ratio ~ U[0.5,0.999]).
+    - Baseline: the plain FP64 GPU solve, one instance at a time (assembled, solved and
+      released in turn; only the solves are timed).
+    - Batched: every instance assembled in mixed-only form, then solved in one lockstep batch
+      in mixed precision, with admission bounded by a device-memory budget; timed from the
+      first admission to the last completion.
+    Both run to the same relative residual.  The error of each mixed result is taken
+    against the instance's FP64 result."""
+    import numpy as np
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    insts = inputs.instance_distribution(count=args.count, seed=3, tol=args.tol)
+    base = dict(l=4, tol=args.tol, max_iter=2000, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_BANDED)
+    o64 = rte.default_solve_opts(precision=rte.RTE_FP64, **base)
+    omx = rte.default_solve_opts(precision=rte.RTE_MIXED, **base)
+    ref, t64, it64, asm64 = [], 0.0, [], []
+    for i, inst in enumerate(insts):
+        ta = time.perf_counter()
+        h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=0)
+        asm64.append(time.perf_counter() - ta)
+        U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = h.solve(U, opts=o64, raise_on_notconv=False)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t0
+        it64.append(info.iters)
+        ref.append(U.cpu())
+        h.close()
+        del U
+        log(f"[fp64 {i + 1}/{len(insts)}] {inst.name}: {info.iters} iters, {1e3 * info.t_solve:.0f} ms, "
+            f"assembly {asm64[-1]:.2f} s")
+    # batched mixed form: assemble all, admit within the budget, step until done
+    handles, asm = [], []
+    for i, inst in enumerate(insts):
+        ta = time.perf_counter()
+        handles.append(rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2))
+        asm.append(time.perf_counter() - ta)
+    log(f"[batch] assembled {len(handles)} handles in {sum(asm):.1f} s")
+    budget = int(200e9)
+    b = rte.Batch(max_slots=len(handles), hbm_budget=budget)
+    outs = [torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda") for h in handles]
+    pending = list(range(len(handles)))
+    owner, res = {}, {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    peak_live = 0
+    while pending or owner:
+        while pending:
+            try:
+                owner[b.admit(handles[pending[0]], outs[pending[0]], omx)] = pending[0]
+                pending.pop(0)
+            except rte.RteError as e:
+                if e.status != rte.RTE_E_NOMEM or not owner:
+                    raise
+                break
+        peak_live = max(peak_live, len(owner))
+        b.step(1)
+        for slot, st, info in b.poll():
+            res[owner.pop(slot)] = (st, info)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    errs = [float(torch.linalg.norm(outs[i].cpu() - ref[i]) / torch.linalg.norm(ref[i])) for i in range(len(insts))]
+    for h in handles:
+        h.close()
+    out = {
+        "workload": f"batched form: {len(insts)} seeded instances (N 32..128, 128/512/2048 sphere triangles, "
+                    f"g 0..0.95, ratio 0.5..0.999), rel. residual {args.tol:g}",
+        "fp64_one_at_a_time": {"value": len(insts) / t64, "unit": "solves/s", "seconds": t64,
+                               "iters_total": int(sum(it64))},
+        "mixed_batched": {"value": len(insts) / tb, "unit": "solves/s", "seconds": tb,
+                          "iters_total": int(sum(r[1].iters for r in res.values())),
+                          "all_converged": all(r[0] == rte.RTE_OK for r in res.values()),
+                          "peak_live_slots": peak_live, "hbm_budget": budget},
+        "speedup": t64 / tb,
+        "max_rel_err_vs_fp64": max(errs), "median_rel_err_vs_fp64": float(np.median(errs)),
+        "assembly_s": {"mixed_only_total": sum(asm), "fp64_total": sum(asm64), "max": max(asm)},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,9 +237,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["kernels"], default=None,
+    ap.add_argument("--only", choices=["kernels", "batch"], default=None,
                     help="'kernels': assemble the realistic instance, run the dominant kernels twice each "
-                         "and a plain 4 GiB device copy (the reference for HBM counter passes), then exit")
+                         "and a plain 4 GiB device copy (the reference for HBM counter passes), then exit; "
+                         "'batch': the batched form (seeded instances of uneven size, mixed precision, "
+                         "lockstep batch) against the same instances solved one at a time in FP64")
+    ap.add_argument("--count", type=int, default=64, help="instances of the batched form")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
@@ -166,6 +254,9 @@ def main():
 
     from paper_2102_09038_amd import inputs, rte
 
+    if args.only == "batch":
+        batch_bench(args, torch, rte, inputs)
+        return
     inst = inputs.config_realistic()
     ta = time.perf_counter()
     h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)

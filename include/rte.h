@@ -104,7 +104,10 @@ typedef struct rte_assemble_opts {
     int32_t n_odd;               /* N- >= 1 odd: PCG preconditioner uses the top
                                     (N+1)(N+2)/2 eigenpairs of (S-, M_S-)  (Sec. 5.1)        */
     int32_t e0_solver;           /* rte_e0_solver prepared at assembly (CG is always there)  */
-    int32_t mixed;               /* nonzero: also prepare BF16/FP32 operator copies          */
+    int32_t mixed;               /* 1: also prepare BF16/FP32 operator copies; 2: the same,  */
+                                 /*    and keep only the FP32 E_0 band factors (FP64 E_0    */
+                                 /*    solves then fail with RTE_E_ARG; halves the largest  */
+                                 /*    allocation for mixed-only use)                       */
 } rte_assemble_opts;
 
 typedef struct rte_solve_opts {

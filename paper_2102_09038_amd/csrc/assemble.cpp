@@ -279,6 +279,7 @@ size_t Handle::footprint() const {
 Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStream_t s) {
     // ------------------------------------------------------------------ validation
     if (!D || !o) fail(RTE_E_ARG, "null descriptor or options");
+    if (o->mixed < 0 || o->mixed > 2) fail(RTE_E_ARG, "mixed must be 0, 1 or 2");
     const int d = D->dim;
     if (d != 2 && d != 3) fail(RTE_E_ARG, "dim must be 2 or 3");
     if (D->n_vert < d + 1 || D->n_cell < 1 || !D->vert || !D->cell) fail(RTE_E_ARG, "empty spatial mesh");
@@ -923,8 +924,12 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             k::cvt_f64_bf16(h.Hodd.p, h.Hodd_bf.p, h.Hodd.n, s);
         }
         if (h.Gc.p) {
-            h.Gc_bf.alloc(h.Gc.n);
-            k::cvt_f64_bf16(h.Gc.p, h.Gc_bf.p, h.Gc.n, s);
+            // [G_hi; G_lo] (2 dn x dn, column-major): the BF16 transport GEMM carries the
+            // operator with 16 significant bits (its diagonal blocks are nearly singular for
+            // small sphere triangles, see kernels_mixed.hip)
+            const size_t dn = (size_t)h.d * nS;
+            h.Gc_bf.alloc(2 * dn * dn);
+            k::cvt_f64_bf16_split2(h.Gc.p, h.Gc_bf.p, dn, s);
         }
         if (h.have_e0_banded) {
             h.e0_stride32 = k::band_blk_size(nRp, h.sbw, 4);
@@ -932,6 +937,11 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             h.L0Uf.alloc(h.e0_stride32 * nS);
             k::band_to_f32(h.L0.p, h.L0f.p, nRp, h.sbw, nS, h.e0_stride, h.e0_stride32, s);
             k::band_to_f32(h.L0U.p, h.L0Uf.p, nRp, h.sbw, nS, h.e0_stride, h.e0_stride32, s);
+            if (o->mixed == 2) {
+                RTE_HIP(hipStreamSynchronize(s));
+                h.L0.release();
+                h.L0U.release();
+            }
         }
         h.have_mixed = true;
     }

@@ -123,9 +123,8 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(int M, int N, int K, 
 }
 
 // ============================================================================ glue
-// Ycb[j * dn + n nS + k] = bf16((D_n X)[j, k] / mt_j): the condensed GEMM's A operand,
-// row-major (angular index contiguous).  Threads run fastest over k so the BF16 stores
-// coalesce.
+// Ycb[j * 2 dn + n nS + k] = Ycb[j * 2 dn + dn + n nS + k] = bf16((D_n X)[j, k] / mt_j): the
+// condensed GEMM's A operand, row-major (angular index contiguous).
 template <int D>
 __global__ __launch_bounds__(256) void apply_grad_bf16_kernel(int nRm, int nRp, int nS, const int* __restrict__ cell,
                                                               const double* __restrict__ Dc,
@@ -133,7 +132,13 @@ __global__ __launch_bounds__(256) void apply_grad_bf16_kernel(int nRm, int nRp, 
                                                               const double* __restrict__ X,
                                                               uint16_t* __restrict__ Ycb) {
     // one thread per cell and 8 consecutive directions: the cell's data is loaded once, the
-    // 8 BF16 results of each component go out as one 16-byte store
+    // 8 BF16 results of each component go out as one 16-byte store.  Row j holds the d nS
+    // values twice: the GEMM multiplies [Y | Y] with [G_hi; G_lo], the operator carried as a
+    // pair of BF16 parts (16 significant bits).  The operator needs them: its d x d diagonal
+    // blocks are the odd moments 2 T_k of the sphere triangles, nearly singular for small
+    // triangles (s_x and s_y almost proportional over the triangle), and rounding them to
+    // 8 bits can make the transport term indefinite.  Rounding the data Y to BF16 only adds
+    // a small error to each product and leaves the operator positive definite.
     const int nkc = nS / 8;
     const size_t t = blockIdx.x * (size_t)256 + threadIdx.x;
     if (t >= (size_t)nRm * nkc) return;
@@ -164,14 +169,18 @@ __global__ __launch_bounds__(256) void apply_grad_bf16_kernel(int nRm, int nRp, 
         for (int n = 0; n < D; ++n) out[n][kk] = f32_to_bf16((float)(gn[n] * inv));
     }
     const size_t dn = (size_t)D * nS;
+    auto pack = [](const uint16_t* p) {
+        uint4 w;
+        w.x = p[0] | ((uint32_t)p[1] << 16);
+        w.y = p[2] | ((uint32_t)p[3] << 16);
+        w.z = p[4] | ((uint32_t)p[5] << 16);
+        w.w = p[6] | ((uint32_t)p[7] << 16);
+        return w;
+    };
 #pragma unroll
     for (int n = 0; n < D; ++n) {
-        uint4 w;
-        w.x = out[n][0] | ((uint32_t)out[n][1] << 16);
-        w.y = out[n][2] | ((uint32_t)out[n][3] << 16);
-        w.z = out[n][4] | ((uint32_t)out[n][5] << 16);
-        w.w = out[n][6] | ((uint32_t)out[n][7] << 16);
-        *reinterpret_cast<uint4*>(Ycb + (size_t)j * dn + (size_t)n * nS + k0) = w;
+        *reinterpret_cast<uint4*>(Ycb + (size_t)j * 2 * dn + (size_t)n * nS + k0) = pack(out[n]);
+        *reinterpret_cast<uint4*>(Ycb + (size_t)j * 2 * dn + dn + (size_t)n * nS + k0) = pack(out[n]);
     }
 }
 

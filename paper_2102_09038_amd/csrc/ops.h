@@ -150,7 +150,8 @@ namespace rte {
 namespace k {
 // Y = M X column by column for a matrix with the P1 pattern and values vals[nnz]
 void spmm_pattern(const Handle* h, const double* vals, const double* X, double* Y, hipStream_t s);
-// Ycb = bf16(Mt-^{-1} [D_1 X, .., D_d X]) row-major (nRm x d nS, angular index contiguous)
+// Ycb = [Y | Y] with Y = bf16(Mt-^{-1} [D_1 X, .., D_d X]), row-major nRm x 2 d nS (angular index
+// contiguous; the second copy meets the low BF16 part of the operator in the GEMM)
 void apply_grad_bf16(const Handle* h, const double* X, uint16_t* Ycb, hipStream_t s);
 // apply_At_E with FP32 condensed components Z (column-major nRm x d nS)
 void apply_At_E_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,

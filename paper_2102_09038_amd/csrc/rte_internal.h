@@ -144,7 +144,7 @@ struct Handle {
     // ---- BF16 copies (mixed precision)
     bool have_mixed = false;
     DBuf<uint16_t> Sp_bf, Sm_bf, Hodd_bf;
-    DBuf<uint16_t> Gc_bf;          // BF16 copy of the condensed transport matrix
+    DBuf<uint16_t> Gc_bf;          // condensed transport matrix as BF16 parts [G_hi; G_lo]
     size_t e0_stride32 = 0;
     DBuf<float> L0f, L0Uf;         // FP32 copies of the banded E_0 factors ([nS * e0_stride32])
 
@@ -204,6 +204,9 @@ void gemm_bf16(int M, int N, int K, float alpha, const uint16_t* A, int lda, con
 void cvt_f64_bf16(const double* x, uint16_t* y, size_t n, hipStream_t s);
 void cvt_f32_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s);
 void cvt_f64_f32(const double* x, float* y, size_t n, hipStream_t s);
+// Y (2n x n, column-major) = [X_hi; X_lo] for an n x n column-major X: X_hi = bf16(X),
+// X_lo = bf16(X - X_hi)
+void cvt_f64_bf16_split2(const double* X, uint16_t* Y, size_t n, hipStream_t s);
 void cvt_f32_f64(const float* x, double* y, size_t n, hipStream_t s);
 }  // namespace k
 

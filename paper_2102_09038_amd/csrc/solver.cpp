@@ -175,8 +175,8 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
             float* Zf = reinterpret_cast<float*>(Z);
             k::apply_grad_bf16(h, X, Ycb, s);
             {
-                Timed t(h, s, P_GEMM_BF16, 2.0 * h->nRm * (double)dn * dn);
-                k::gemm_bf16(h->nRm, dn, dn, 1.0f, Ycb, dn, h->Gc_bf.p, dn, 0.0f, Zf, h->nRm, s);
+                Timed t(h, s, P_GEMM_BF16, 2.0 * h->nRm * (double)dn * (2.0 * dn));
+                k::gemm_bf16(h->nRm, dn, 2 * dn, 1.0f, Ycb, 2 * dn, h->Gc_bf.p, 2 * dn, 0.0f, Zf, h->nRm, s);
             }
             k::apply_At_E_f32(h, Zf, X, G, q, Y, s);
             return;
@@ -211,6 +211,8 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
            int* cgmax, bool lowp) {
     if (o->e0_solver == RTE_E0_BANDED) {
         if (!h->have_e0_banded) fail(RTE_E_ARG, "banded E_0 factors were not prepared at assembly");
+        if (!(lowp && h->L0f.p) && !h->L0.p)
+            fail(RTE_E_ARG, "the FP64 band factors were dropped at assembly (mixed = 2)");
         // the factors are in band (bandwidth-reducing) order: permute the columns of X into
         // that order and the solution back in coalesced per-column passes, so that the
         // solve itself reads and writes its vectors contiguously
