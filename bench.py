@@ -160,10 +160,13 @@ def batch_bench(args, torch, rte, inputs):
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    from paper_2102_09038_amd import serve
+
     insts = inputs.instance_distribution(count=args.count, seed=3, tol=args.tol)
     base = dict(l=4, tol=args.tol, max_iter=2000, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_BANDED)
     o64 = rte.default_solve_opts(precision=rte.RTE_FP64, **base)
     omx = rte.default_solve_opts(precision=rte.RTE_MIXED, **base)
+    # ---- baseline: plain FP64, one instance at a time
     ref, t64, it64, asm64 = [], 0.0, [], []
     for i, inst in enumerate(insts):
         ta = time.perf_counter()
@@ -181,52 +184,107 @@ def batch_bench(args, torch, rte, inputs):
         del U
         log(f"[fp64 {i + 1}/{len(insts)}] {inst.name}: {info.iters} iters, {1e3 * info.t_solve:.0f} ms, "
             f"assembly {asm64[-1]:.2f} s")
-    # batched mixed form: assemble all, admit within the budget, step until done
-    handles, asm = [], []
-    for i, inst in enumerate(insts):
-        ta = time.perf_counter()
-        handles.append(rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2))
-        asm.append(time.perf_counter() - ta)
-    log(f"[batch] assembled {len(handles)} handles in {sum(asm):.1f} s")
-    budget = int(200e9)
-    b = rte.Batch(max_slots=len(handles), hbm_budget=budget)
-    outs = [torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda") for h in handles]
-    pending = list(range(len(handles)))
-    owner, res = {}, {}
-    torch.cuda.synchronize()
+    # ---- batched mixed form: every instance arrives at once; the server assembles within the
+    #      device-memory budget and runs all admitted solves in one lockstep batch
+    budget = int(240e9)
+    reqs = [serve.Request(rid=i, inst=inst, arrival=0.0) for i, inst in enumerate(insts)]
+    srv = serve.Server(budget, omx, max_slots=len(insts), workers=4, keep_results=True)
     t0 = time.perf_counter()
-    peak_live = 0
-    while pending or owner:
-        while pending:
-            try:
-                owner[b.admit(handles[pending[0]], outs[pending[0]], omx)] = pending[0]
-                pending.pop(0)
-            except rte.RteError as e:
-                if e.status != rte.RTE_E_NOMEM or not owner:
-                    raise
-                break
-        peak_live = max(peak_live, len(owner))
-        b.step(1)
-        for slot, st, info in b.poll():
-            res[owner.pop(slot)] = (st, info)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    errs = [float(torch.linalg.norm(outs[i].cpu() - ref[i]) / torch.linalg.norm(ref[i])) for i in range(len(insts))]
-    for h in handles:
-        h.close()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    srv.close()
+    errs = [float(torch.linalg.norm(r.U.cpu() - ref[r.rid]) / torch.linalg.norm(ref[r.rid])) for r in done]
+    log(f"[batch] {len(done)} solved in {wall:.1f} s ({srv.t_step:.1f} s stepping), peak {srv.peak_live} live slots")
     out = {
         "workload": f"batched form: {len(insts)} seeded instances (N 32..128, 128/512/2048 sphere triangles, "
                     f"g 0..0.95, ratio 0.5..0.999), rel. residual {args.tol:g}",
-        "fp64_one_at_a_time": {"value": len(insts) / t64, "unit": "solves/s", "seconds": t64,
+        "fp64_one_at_a_time": {"solves_per_s": len(insts) / t64, "solve_s": t64, "assembly_s": sum(asm64),
+                               "end_to_end_solves_per_s": len(insts) / (t64 + sum(asm64)),
                                "iters_total": int(sum(it64))},
-        "mixed_batched": {"value": len(insts) / tb, "unit": "solves/s", "seconds": tb,
-                          "iters_total": int(sum(r[1].iters for r in res.values())),
-                          "all_converged": all(r[0] == rte.RTE_OK for r in res.values()),
-                          "peak_live_slots": peak_live, "hbm_budget": budget},
-        "speedup": t64 / tb,
+        "mixed_batched": {"solves_per_s": len(insts) / srv.t_step, "step_s": srv.t_step, "wall_s": wall,
+                          "end_to_end_solves_per_s": len(insts) / wall,
+                          "iters_total": int(sum(r.iters for r in done)),
+                          "all_converged": all(r.status == rte.RTE_OK for r in done),
+                          "peak_live_slots": srv.peak_live, "hbm_budget": budget, "assembly_workers": 4},
+        "speedup_solve": t64 / srv.t_step, "speedup_end_to_end": (t64 + sum(asm64)) / wall,
         "max_rel_err_vs_fp64": max(errs), "median_rel_err_vs_fp64": float(np.median(errs)),
-        "assembly_s": {"mixed_only_total": sum(asm), "fp64_total": sum(asm64), "max": max(asm)},
     }
+    print(json.dumps(out))
+
+
+def serve_bench(args, torch, rte, inputs):
+    """The served form: Poisson arrivals (seed 4) of requests drawn like the batched form,
+    served by the continuous-batching loop (mixed precision, assembly on worker threads,
+    admission by predicted footprint) and, as the baseline, by plain FP64 solves one at a
+    time in arrival order.  Latency = completion - arrival; the first warm-up requests of
+    each run are not counted."""
+    import numpy as np
+
+    from paper_2102_09038_amd import serve
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    warm = 8
+    n = args.requests + warm
+    insts = inputs.instance_distribution(count=n, seed=4, tol=args.tol)
+    base = dict(l=4, tol=args.tol, max_iter=2000, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_BANDED)
+    omx = rte.default_solve_opts(precision=rte.RTE_MIXED, **base)
+    o64 = rte.default_solve_opts(precision=rte.RTE_FP64, **base)
+    rng = np.random.Generator(np.random.PCG64(4))
+    unit = np.cumsum(rng.exponential(1.0, size=n))          # arrivals at rate 1, scaled per run
+    unit -= unit[0]
+
+    def stats(reqs, t_wall):
+        m = [r for r in reqs if r.rid >= warm]
+        lat = [r.latency for r in m]
+        first = min(r.arrival for r in m)
+        last = max(r.done_at for r in m)
+        return {"p50_s": serve.percentile(lat, 50), "p99_s": serve.percentile(lat, 99),
+                "mean_s": float(np.mean(lat)), "solves_per_s": len(m) / (last - first),
+                "all_converged": all(r.status == rte.RTE_OK for r in m), "wall_s": t_wall}
+
+    def run_batched(rate):
+        reqs = [serve.Request(rid=i, inst=insts[i], arrival=float(unit[i] / rate)) for i in range(n)]
+        srv = serve.Server(int(240e9), omx, max_slots=n, workers=4)
+        t0 = time.perf_counter()
+        done = srv.run(reqs)
+        srv.close()
+        st = stats(done, time.perf_counter() - t0)
+        st["peak_live_slots"] = srv.peak_live
+        return st
+
+    def run_fp64_serial(rate):
+        reqs = [serve.Request(rid=i, inst=insts[i], arrival=float(unit[i] / rate)) for i in range(n)]
+        t0 = time.perf_counter()
+        for r in reqs:
+            wait = r.arrival - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            h = rte.Handle.from_instance(r.inst, e0_solver=rte.RTE_E0_BANDED, mixed=0)
+            U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+            st, info = h.solve(U, opts=o64, raise_on_notconv=False)
+            torch.cuda.synchronize()
+            r.status, r.iters = st, info.iters
+            r.done_at = time.perf_counter() - t0
+            h.close()
+        return stats(reqs, time.perf_counter() - t0)
+
+    rates = [x for x in args.rates.split(",") if x]
+    numeric = [float(x) for x in rates if x != "half"]
+    out = {"workload": f"served form: Poisson arrivals (seed 4), {args.requests} measured requests per rate after "
+                       f"{warm} warm-up, drawn like the batched form (2D), rel. residual {args.tol:g}",
+           "rates": {}}
+    for x in rates:
+        rate = float(x) if x != "half" else 0.5 * out["rates"][max(numeric)]["batched"]["solves_per_s"]
+        log(f"[serve] rate {rate:.2f}/s: batched")
+        b = run_batched(rate)
+        log(f"[serve] rate {rate:.2f}/s: fp64 one at a time")
+        f = run_fp64_serial(rate)
+        key = x if x != "half" else f"half capacity ({rate:.2f}/s)"
+        out["rates"][key] = {"rate": rate, "batched": b, "fp64_one_at_a_time": f}
+        log(f"[serve] rate {rate:.2f}/s: batched p50 {b['p50_s']:.2f} s p99 {b['p99_s']:.2f} s "
+            f"{b['solves_per_s']:.2f}/s | fp64 p50 {f['p50_s']:.2f} s p99 {f['p99_s']:.2f} s {f['solves_per_s']:.2f}/s")
     print(json.dumps(out))
 
 
@@ -237,12 +295,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["kernels", "batch"], default=None,
+    ap.add_argument("--only", choices=["kernels", "batch", "serve"], default=None,
                     help="'kernels': assemble the realistic instance, run the dominant kernels twice each "
                          "and a plain 4 GiB device copy (the reference for HBM counter passes), then exit; "
                          "'batch': the batched form (seeded instances of uneven size, mixed precision, "
                          "lockstep batch) against the same instances solved one at a time in FP64")
     ap.add_argument("--count", type=int, default=64, help="instances of the batched form")
+    ap.add_argument("--rates", default="50,200,1000,half",
+                    help="served form: Poisson arrival rates in requests/s ('half' = half the capacity "
+                         "measured at the highest listed rate)")
+    ap.add_argument("--requests", type=int, default=64, help="served form: measured requests per rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
@@ -256,6 +318,9 @@ def main():
 
     if args.only == "batch":
         batch_bench(args, torch, rte, inputs)
+        return
+    if args.only == "serve":
+        serve_bench(args, torch, rte, inputs)
         return
     inst = inputs.config_realistic()
     ta = time.perf_counter()

@@ -175,6 +175,14 @@ rte_status rte_query_band(const rte_handle* h, int32_t* e0_bw, int32_t* coarse_n
 /* Device bytes the handle holds (operators and solver workspace at full size). */
 rte_status rte_footprint(const rte_handle* h, size_t* bytes);
 
+/* Before assembly: the device bytes a handle of this problem will hold once assembled with
+ * opts and given the workspace of a solve (or batch slot), and the peak during assembly
+ * (*peak_bytes, nullable; larger when mixed = 2 drops the FP64 factors at the end).  Host
+ * work only (the P1 pattern and its bandwidth); used to admit requests by memory footprint
+ * before they are assembled. */
+rte_status rte_estimate_footprint(const rte_problem_desc* desc, const rte_assemble_opts* opts, size_t* bytes,
+                                  size_t* peak_bytes);
+
 /* Y = K+ X = Ms+ X S+ (parity +1, X and Y n_R+ x n_S+) or Y = K- X = Ms- X S-
  * (parity -1, n_R- x n_S-); Sec. 4 with the Kronecker identity of Sec. 5.1.
  * X and Y are device arrays of dtype_in / dtype_out (F64 or F32; BF16 input only

@@ -6,6 +6,9 @@
 // Host FP64 for the geometry (cheap, O(mesh size)); the O(n_S^2 Q^2) double quadrature
 // of the HG kernel runs on the GPU (kernels_dense.hip); the symmetric eigensolves use
 // rocSOLVER on the GPU.
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -276,7 +279,24 @@ size_t Handle::footprint() const {
     return b;
 }
 
+// Phase timing of the assembly, printed to stderr when the environment sets RTE_TRACE
+// (each phase is closed with a stream synchronisation so that GPU work is attributed to it).
+struct PhaseTrace {
+    bool on = std::getenv("RTE_TRACE") != nullptr;
+    hipStream_t s;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    explicit PhaseTrace(hipStream_t s_) : s(s_) {}
+    void operator()(const char* name) {
+        if (!on) return;
+        (void)hipStreamSynchronize(s);
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[rte assemble] %-28s %9.3f s\n", name, std::chrono::duration<double>(now - t).count());
+        t = now;
+    }
+};
+
 Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStream_t s) {
+    PhaseTrace trace(s);
     // ------------------------------------------------------------------ validation
     if (!D || !o) fail(RTE_E_ARG, "null descriptor or options");
     if (o->mixed < 0 || o->mixed > 2) fail(RTE_E_ARG, "mixed must be 0, 1 or 2");
@@ -322,6 +342,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     h.dNp = (o->n_even + 1) * (o->n_even + 2) / 2;
     h.dNm = (o->n_odd + 1) * (o->n_odd + 2) / 2;
 
+    trace("validation");
     // ------------------------------------------------------------------ sphere: upper half, antipodes
     const int nt = D->n_stri;
     auto vkey = [](const double* v) {
@@ -363,6 +384,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     h.nSm = 3 * nS;
     if (h.dNm > h.nSm || h.dNp > nS) fail(RTE_E_ARG, "eigen-basis larger than the angular space");
 
+    trace("sphere pairing");
     // ------------------------------------------------------------------ angular quadrature and moments
     const Rule R = composite_rule(o->quad_level);
     const int Q = (int)R.w.size();
@@ -399,6 +421,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         inv_lower3(L, &LkInv[9 * k]);
     }
 
+    trace("angular quadrature");
     // ------------------------------------------------------------------ spatial geometry
     const int nv = d + 1;
     Vec vol(nRm), Dc((size_t)nRm * nv * d);
@@ -438,6 +461,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         if (hi - lo > 1e-13 * std::max(hi, 1e-300)) h.uniform_delta = false;
     }
 
+    trace("spatial geometry");
     // ------------------------------------------------------------------ P1 pattern
     std::vector<std::vector<int>> adj(nRp);
     for (int j = 0; j < nRm; ++j)
@@ -462,6 +486,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     std::vector<int> diagpos(nRp);
     for (int i = 0; i < nRp; ++i) diagpos[i] = find(i, i);
 
+    trace("P1 pattern");
     // ------------------------------------------------------------------ boundary facets
     struct Facet { std::array<int, 3> v; int cell, opp; };
     std::map<std::array<int, 3>, std::pair<int, int>> owner;   // sorted verts -> (count, cell*8+opp)
@@ -512,6 +537,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         fail(RTE_E_ARG, "boundary has too many distinct facet normals (" + std::to_string(nb) +
                             "); at most " + std::to_string(kMaxClasses - nstiff - 1) + " are supported");
 
+    trace("boundary facets");
     // ------------------------------------------------------------------ value classes of the pattern
     // stiffness classes (n <= m): sum_j D_n(j,a) D_m(j,b) / mt_j (+ the (m,n) term when n < m)
     const int ncls = h.ncls;
@@ -605,6 +631,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         }
     h.qnorm = std::sqrt(qn2);
 
+    trace("value classes");
     // ------------------------------------------------------------------ uploads
     h.m.upload(h.h_m, s);
     h.T.upload(h.h_T, s);
@@ -643,6 +670,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     }
     h.q.upload(qv, s);
 
+    trace("uploads");
     // ------------------------------------------------------------------ scattering matrices (GPU)
     {
         DBuf<double> dp, dw;
@@ -656,6 +684,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     h.h_Sp = h.Sp.download(s);
     h.h_Sm = h.Sm.download(s);
 
+    trace("scattering matrices");
     // ------------------------------------------------------------------ eigen-bases (rocSOLVER)
     RocblasCtx rb(s);
     const int nSm = h.nSm;
@@ -779,6 +808,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         }
         h.Wp.upload(h.h_Wp, s);
 
+        trace("eigen-bases");
         // ------------------------------------------------------------------ coarse matrix E_c
         const int dN = h.dNp;
         // P_n = W_full^T (A_n W+)  [nSm x dN], (A_n W+)[(k,m), a] = 2 T_k(n, m) W+[k, a]
@@ -894,6 +924,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     h.h_Sp.clear();
     h.h_Sp.shrink_to_fit();
 
+    trace("coarse matrix");
     // ------------------------------------------------------------------ banded E_0 factors
     if (o->e0_solver == RTE_E0_BANDED) {
         if (k::band_groups(h.sbw, 2) == 0 || k::band_groups(h.sbw, 4) == 0)
@@ -913,6 +944,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         fail(RTE_E_ARG, "unknown e0_solver");
     }
 
+    trace("E_0 band factors");
     // ------------------------------------------------------------------ BF16 copies
     if (o->mixed) {
         h.Sp_bf.alloc(h.Sp.n);
@@ -945,11 +977,73 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         }
         h.have_mixed = true;
     }
+    trace("reduced-precision copies");
     h.red.alloc(k::kRedBlocks);
     h.scal.alloc(64);
     RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&h.pinned), 64 * sizeof(double), hipHostMallocDefault));
     RTE_HIP(hipStreamSynchronize(s));
     return H.release();
+}
+
+
+// Device bytes a handle will hold after assemble() (operators, factors and the workspace of a
+// solve or batch slot) and the peak during assembly, from the problem's sizes alone: the P1
+// pattern's bandwidth is computed (natural and reverse Cuthill-McKee orders, as assemble()
+// chooses), nothing is allocated on the GPU.  Small per-cell and per-pattern arrays are
+// bounded from above.
+size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o, size_t* peak) {
+    if (!D || !o) fail(RTE_E_ARG, "null descriptor or options");
+    const int d = D->dim;
+    if (d != 2 && d != 3) fail(RTE_E_ARG, "dim must be 2 or 3");
+    if (D->n_vert < d + 1 || D->n_cell < 1 || !D->cell || D->n_stri < 2) fail(RTE_E_ARG, "empty mesh");
+    const int nv = d + 1, nRp = D->n_vert, nRm = D->n_cell;
+    const size_t nS = (size_t)D->n_stri / 2, nSm = 3 * nS;
+    const size_t dN = (size_t)(o->n_even + 1) * (o->n_even + 2) / 2;
+    const size_t dNm = (size_t)(o->n_odd + 1) * (o->n_odd + 2) / 2;
+    std::vector<std::vector<int>> adj(nRp);
+    for (int j = 0; j < nRm; ++j)
+        for (int a = 0; a < nv; ++a)
+            for (int b = 0; b < nv; ++b) {
+                const int va = D->cell[nv * j + a], vb = D->cell[nv * j + b];
+                if (va < 0 || va >= nRp || vb < 0 || vb >= nRp) fail(RTE_E_MESH, "cell vertex out of range");
+                adj[va].push_back(vb);
+            }
+    std::vector<int> rp(nRp + 1, 0), ci;
+    for (int i = 0; i < nRp; ++i) {
+        auto& v = adj[i];
+        v.push_back(i);
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        rp[i + 1] = rp[i] + (int)v.size();
+        ci.insert(ci.end(), v.begin(), v.end());
+    }
+    std::vector<int> ident(nRp);
+    std::iota(ident.begin(), ident.end(), 0);
+    const int sbw = std::min(band_width(rcm(nRp, rp, ci), rp, ci), band_width(ident, rp, ci));
+    const size_t nnz = (size_t)rp[nRp], nc = dN * nRp, even = (size_t)nRp * nS;
+    const size_t cbw = dN * sbw + dN - 1;
+    size_t b = 0;
+    // angular operators: S+, S-, eigenbases (full odd basis twice), H, condensed G, moments
+    b += (nS * nS + 4 * nSm * nSm + nSm * dNm + nS * dN + 4 * nSm + 16 * nS) * 8;
+    b += (size_t)d * nS * d * nS * 8;
+    // spatial data: cells, gradients, pattern values per class, incidence, source
+    b += (size_t)nRm * (nv * 4 + nv * d * 8 + 4 * 8) + nnz * (4 + 8 * (kMaxClasses + 4)) + (size_t)nRp * 16;
+    b += (size_t)nRm * nv * (4 + 4 + d * 8) + nS * kMaxClasses * 8 * 3 + even * 8;
+    // coarse solve: explicit inverse or band factors
+    if ((double)nc * nc * 8 <= kEcinvMaxBytes) b += nc * nc * 8;
+    else b += 2 * k::band_blk_size((int)nc, (int)cbw, 2) * 8;
+    size_t transient = 0;
+    if (o->e0_solver == RTE_E0_BANDED) {
+        const size_t f64 = 2 * k::band_blk_size(nRp, sbw, 2) * nS * 8;
+        if (o->mixed != 2) b += f64;
+        else transient = f64;
+        if (o->mixed) b += 2 * k::band_blk_size(nRp, sbw, 4) * nS * 4;
+    }
+    if (o->mixed) b += (nS * nS + 2 * nSm * nSm + 2 * (size_t)d * nS * d * nS) * 2;
+    // solver workspace: two odd-sized buffers, eleven even vectors, coarse vectors, reductions
+    b += 2 * (size_t)nRm * nSm * 8 + 11 * even * 8 + 2 * nc * 8 + (1 << 16);
+    if (peak) *peak = b + transient;
+    return b;
 }
 
 }  // namespace rte

@@ -172,6 +172,15 @@ rte_status rte_solve(rte_handle* hh, const rte_solve_opts* o, const double* U0, 
     });
 }
 
+rte_status rte_estimate_footprint(const rte_problem_desc* desc, const rte_assemble_opts* opts, size_t* bytes,
+                                  size_t* peak_bytes) {
+    return guarded([&] {
+        if (!bytes) rte::fail(RTE_E_ARG, "null output");
+        *bytes = rte::estimate_footprint(desc, opts, peak_bytes);
+        return RTE_OK;
+    });
+}
+
 rte_status rte_batch_create(int32_t max_slots, size_t hbm_budget, rte_batch** out) {
     return guarded([&] {
         if (!out) rte::fail(RTE_E_ARG, "null output");

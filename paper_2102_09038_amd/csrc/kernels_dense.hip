@@ -16,12 +16,29 @@ namespace {
 constexpr int QT = 16;     // pairs per tile side
 constexpr int QC = 32;     // points per LDS chunk
 
+// S+ / S- from the split partial sums, added in split order
+__global__ void sum_parts_kernel(const double* __restrict__ part, int nsplit, int nS, double* __restrict__ Sp,
+                                 double* __restrict__ Sm) {
+    const size_t n1 = (size_t)nS * nS, n = 10 * n1;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp) v += part[(size_t)sp * n + i];
+        if (i < n1) Sp[i] = v;
+        else Sm[i - n1] = v;
+    }
+}
+
 __global__ __launch_bounds__(256) void hg_scatter_kernel(const double* __restrict__ pts,
                                                          const double* __restrict__ wts,
                                                          int nS, int Q, double g,
                                                          double* __restrict__ Sp,
-                                                         double* __restrict__ Sm) {
+                                                         double* __restrict__ Sm, double* __restrict__ part) {
     const int nt = (nS + QT - 1) / QT;
+    // the row points are split over gridDim.y parts (few sphere pairs: more work-groups);
+    // a split's sums go to its slice of part and are added up in a fixed order afterwards
+    const int nchunk = (Q + QC - 1) / QC;
+    const int c_lo = (int)((long long)nchunk * blockIdx.y / gridDim.y);
+    const int c_hi = (int)((long long)nchunk * (blockIdx.y + 1) / gridDim.y);
     const int bi = blockIdx.x % nt, bj = blockIdx.x / nt;
     if (bi > bj) return;
     __shared__ double rowp[QT][QC][4];
@@ -32,7 +49,7 @@ __global__ __launch_bounds__(256) void hg_scatter_kernel(const double* __restric
     const double cn = (1.0 - g * g) / (4.0 * M_PI);
     double sp = 0.0;
     double sm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int p0 = 0; p0 < Q; p0 += QC) {
+    for (int p0 = c_lo * QC; p0 < c_hi * QC; p0 += QC) {
         const int pc = min(QC, Q - p0);
         for (int q0 = 0; q0 < Q; q0 += QC) {
             const int qc = min(QC, Q - q0);
@@ -87,6 +104,10 @@ __global__ __launch_bounds__(256) void hg_scatter_kernel(const double* __restric
     }
     if (k < nS && kp < nS) {
         const double f = 2.0 * cn;
+        if (gridDim.y > 1) {
+            Sp = part + (size_t)blockIdx.y * 10 * nS * nS;
+            Sm = Sp + (size_t)nS * nS;
+        }
         Sp[k + (size_t)nS * kp] = f * sp;
         if (bi < bj) Sp[kp + (size_t)nS * k] = f * sp;
         const size_t nSm = 3 * (size_t)nS;
@@ -243,8 +264,20 @@ namespace k {
 void hg_scatter(const double* pts, const double* wts, int nS, int Q, double g, double* Sp,
                 double* Sm, hipStream_t s) {
     const int nt = (nS + QT - 1) / QT;
-    hipLaunchKernelGGL(hg_scatter_kernel, dim3(nt * nt), dim3(256), 0, s, pts, wts, nS, Q, g, Sp, Sm);
+    const int tiles = nt * (nt + 1) / 2, nchunk = (Q + QC - 1) / QC;
+    const int nsplit = std::max(1, std::min(nchunk, (2048 + tiles - 1) / tiles));
+    DBuf<double> part;
+    if (nsplit > 1) part.alloc((size_t)nsplit * 10 * nS * nS);
+    hipLaunchKernelGGL(hg_scatter_kernel, dim3(nt * nt, nsplit), dim3(256), 0, s, pts, wts, nS, Q, g, Sp, Sm,
+                       part.p);
     RTE_CHECK_LAUNCH();
+    if (nsplit > 1) {
+        const size_t n = (size_t)10 * nS * nS;
+        hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)std::min<size_t>((n + 255) / 256, 65536)), dim3(256), 0,
+                           s, part.p, nsplit, nS, Sp, Sm);
+        RTE_CHECK_LAUNCH();
+        RTE_HIP(hipStreamSynchronize(s));     // part is freed on return
+    }
 }
 
 void gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, const double* B,

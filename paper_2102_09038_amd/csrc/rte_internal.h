@@ -181,6 +181,8 @@ void precond(Handle* h, const rte_solve_opts* o, int which, const double* r, dou
 rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U,
                  rte_solve_info* info, hipStream_t s);
 
+size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o, size_t* peak);
+
 // lockstep batch of solves (solver_batch.cpp)
 struct Batch;
 Batch* batch_create(int max_slots, size_t budget);

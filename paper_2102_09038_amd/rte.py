@@ -77,6 +77,8 @@ EXPORTS = {
                             C.POINTER(rte_solve_info), C.c_void_p]),
     "rte_get_array": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t]),
     "rte_destroy": (C.c_int, [C.c_void_p]),
+    "rte_estimate_footprint": (C.c_int, [C.POINTER(rte_problem_desc), C.POINTER(rte_assemble_opts),
+                                         C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "rte_batch_create": (C.c_int, [C.c_int32, C.c_size_t, C.POINTER(C.c_void_p)]),
     "rte_batch_admit": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.POINTER(C.c_int32)]),
@@ -154,31 +156,49 @@ class Dims:
     nSm: int
 
 
+def _make_desc(vert, cell, sigma_t, sigma_s, g, svert, stri, q_nodal):
+    keep = [np.ascontiguousarray(vert, np.float64), np.ascontiguousarray(cell, np.int32),
+            np.ascontiguousarray(sigma_t, np.float64), np.ascontiguousarray(sigma_s, np.float64),
+            np.ascontiguousarray(svert, np.float64), np.ascontiguousarray(stri, np.int32),
+            np.ascontiguousarray(q_nodal, np.float64)]
+    v, c, st, ss, sv, stt, q = keep
+    d = rte_problem_desc()
+    d.dim = v.shape[1]
+    d.n_vert = v.shape[0]
+    d.vert = _dptr(v)
+    d.n_cell = c.shape[0]
+    d.cell = _iptr(c)
+    d.sigma_t = _dptr(st)
+    d.sigma_s = _dptr(ss)
+    d.g = float(g)
+    d.n_svert = sv.shape[0]
+    d.svert = _dptr(sv)
+    d.n_stri = stt.shape[0]
+    d.stri = _iptr(stt)
+    d.q_nodal = _dptr(q)
+    d.g_inflow = None
+    return keep, d
+
+
+def estimate_footprint(inst, **opt_kw):
+    """(bytes, peak_bytes) a handle of this instance will hold once assembled with these
+    options (rte_estimate_footprint; host work only, no GPU needed)."""
+    kw = dict(quad_level=inst.quad_level, n_even=inst.n_even, n_odd=inst.n_odd)
+    kw.update(opt_kw)
+    keep, d = _make_desc(inst.vert, inst.cell, inst.sigma_t, inst.sigma_s, inst.g, inst.svert, inst.stri,
+                         inst.q_nodal)
+    o = default_assemble_opts(**kw)
+    b, p = C.c_size_t(0), C.c_size_t(0)
+    _check(lib.rte_estimate_footprint(C.byref(d), C.byref(o), C.byref(b), C.byref(p)))
+    return b.value, p.value
+
+
 class Handle:
     """Owns an rte_handle; thin wrapper over the C entry points."""
 
     def __init__(self, vert, cell, sigma_t, sigma_s, g, svert, stri, q_nodal, opts=None, stream=None,
                  **opt_kw):
-        self._keep = [np.ascontiguousarray(vert, np.float64), np.ascontiguousarray(cell, np.int32),
-                      np.ascontiguousarray(sigma_t, np.float64), np.ascontiguousarray(sigma_s, np.float64),
-                      np.ascontiguousarray(svert, np.float64), np.ascontiguousarray(stri, np.int32),
-                      np.ascontiguousarray(q_nodal, np.float64)]
-        v, c, st, ss, sv, stt, q = self._keep
-        d = rte_problem_desc()
-        d.dim = v.shape[1]
-        d.n_vert = v.shape[0]
-        d.vert = _dptr(v)
-        d.n_cell = c.shape[0]
-        d.cell = _iptr(c)
-        d.sigma_t = _dptr(st)
-        d.sigma_s = _dptr(ss)
-        d.g = float(g)
-        d.n_svert = sv.shape[0]
-        d.svert = _dptr(sv)
-        d.n_stri = stt.shape[0]
-        d.stri = _iptr(stt)
-        d.q_nodal = _dptr(q)
-        d.g_inflow = None
+        self._keep, d = _make_desc(vert, cell, sigma_t, sigma_s, g, svert, stri, q_nodal)
         self.desc = d
         self.opts = opts if opts is not None else default_assemble_opts(**opt_kw)
         h = C.c_void_p()

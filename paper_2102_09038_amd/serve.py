@@ -1,0 +1,184 @@
+"""Continuous-batching request loop over librte's lockstep batch (rte_batch_*).
+
+Requests (problem instances with an arrival time) are assembled on worker threads, each on
+its own HIP stream, as soon as they have arrived and their predicted peak device footprint
+(rte_estimate_footprint) fits into what the budget leaves.  Assembled requests are admitted
+into the running batch between its steps; the batch advances every admitted solve by one
+outer iteration per step; finished solves are polled, their handles freed, and their
+latency (completion - arrival) recorded.  A request's result is the result rte_solve
+computes for it alone: the batch runs the same arithmetic per slot.
+
+The loop runs in real time: a request is not touched before its arrival time.
+"""
+from __future__ import annotations
+
+import dataclasses
+import queue
+import threading
+import time
+from typing import Callable, List, Optional
+
+from . import rte
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    inst: object                     # an inputs.Instance
+    arrival: float                   # seconds after the start of the run
+    # filled in by the server
+    assembled_at: float = float("nan")
+    admitted_at: float = float("nan")
+    done_at: float = float("nan")
+    status: int = -1
+    iters: int = 0
+    rel_resid: float = float("nan")
+    U: object = None                 # the solution (torch tensor on the device), if kept
+
+    @property
+    def latency(self) -> float:
+        return self.done_at - self.arrival
+
+
+class Server:
+    """One lockstep batch plus assembly workers.
+
+    budget: device bytes the requests' handles (operators + solver workspace) may hold
+    together, counted from admission of a request's assembly to the release of its slot.
+    """
+
+    def __init__(self, budget: int, solve_opts, max_slots: int = 256, workers: int = 4, mixed_assembly: int = 2,
+                 keep_results: bool = False, on_done: Optional[Callable[[Request], None]] = None):
+        import torch
+        self.torch = torch
+        self.budget = int(budget)
+        self.opts = solve_opts
+        self.batch = rte.Batch(max_slots=max_slots, hbm_budget=0)
+        self.workers = workers
+        self.mixed_assembly = mixed_assembly
+        self.keep = keep_results
+        self.on_done = on_done
+        self.reserved = 0                          # bytes promised to requests being assembled or in slots
+        self.stream = torch.cuda.Stream()
+        self.slot_of = {}                          # slot -> (request, handle, reserved bytes, U)
+        self.t_step = 0.0                          # seconds inside batch steps
+        self.peak_live = 0
+
+    # ---------------------------------------------------------------------------- helpers
+    def _estimate(self, req):
+        if not hasattr(req, "_est"):
+            b, p = rte.estimate_footprint(req.inst, e0_solver=rte.RTE_E0_BANDED, mixed=self.mixed_assembly)
+            req._est = (b, max(b, p))
+        return req._est
+
+    def _assemble(self, req: Request, stream):
+        h = rte.Handle.from_instance(req.inst, stream=stream.cuda_stream, e0_solver=rte.RTE_E0_BANDED,
+                                     mixed=self.mixed_assembly)
+        return h
+
+    # ---------------------------------------------------------------------------- main loop
+    def run(self, requests: List[Request], step_iters: int = 1) -> List[Request]:
+        torch = self.torch
+        pending = sorted(requests, key=lambda r: r.arrival)
+        ready: "queue.Queue" = queue.Queue()
+        todo: "queue.Queue" = queue.Queue()
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+
+        def worker():
+            stream = torch.cuda.Stream()
+            while True:
+                item = todo.get()
+                if item is None:
+                    return
+                req, est = item
+                try:
+                    h = self._assemble(req, stream)
+                    req.assembled_at = now()
+                    ready.put((req, h, est))
+                except BaseException as e:            # reported by the main loop
+                    ready.put((req, e, est))
+
+        threads = [threading.Thread(target=worker, daemon=True) for _ in range(self.workers)]
+        for t in threads:
+            t.start()
+        waiting = []                                  # arrived, not yet handed to a worker
+        in_flight = 0                                 # handed to a worker, not yet admitted
+        finished: List[Request] = []
+        try:
+            while len(finished) < len(requests):
+                t = now()
+                while pending and pending[0].arrival <= t:
+                    waiting.append(pending.pop(0))
+                # hand arrived requests to the workers while their predicted peak fits
+                while waiting:
+                    req = waiting[0]
+                    b, peak = self._estimate(req)
+                    if peak > self.budget:
+                        raise RuntimeError(f"request {req.rid} needs {peak} bytes, more than the whole budget")
+                    if self.reserved + peak > self.budget:
+                        break
+                    waiting.pop(0)
+                    self.reserved += peak
+                    todo.put((req, (b, peak)))
+                    in_flight += 1
+                # admit what the workers have assembled
+                while True:
+                    try:
+                        req, h, (b, peak) = ready.get_nowait()
+                    except queue.Empty:
+                        break
+                    in_flight -= 1
+                    if isinstance(h, BaseException):
+                        raise h
+                    self.reserved -= peak - b          # the assembly peak is over
+                    U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+                    slot = self.batch.admit(h, U, self.opts, stream=self.stream.cuda_stream)
+                    req.admitted_at = now()
+                    self.slot_of[slot] = (req, h, b, U)
+                if self.slot_of:
+                    self.peak_live = max(self.peak_live, len(self.slot_of))
+                    ts = time.perf_counter()
+                    self.batch.step(step_iters, stream=self.stream.cuda_stream)
+                    self.t_step += time.perf_counter() - ts
+                    for slot, st, info in self.batch.poll():
+                        req, h, b, U = self.slot_of.pop(slot)
+                        req.done_at = now()
+                        req.status, req.iters, req.rel_resid = st, info.iters, info.rel_resid
+                        if self.keep:
+                            req.U = U
+                        h.close()
+                        self.reserved -= b
+                        finished.append(req)
+                        if self.on_done:
+                            self.on_done(req)
+                else:
+                    # nothing to step: wait for an arrival or an assembly
+                    if pending and not waiting and in_flight == 0:
+                        time.sleep(max(0.0, min(0.01, pending[0].arrival - now())))
+                    else:
+                        try:
+                            item = ready.get(timeout=0.01)
+                            ready.put(item)
+                        except queue.Empty:
+                            pass
+        finally:
+            for _ in threads:
+                todo.put(None)
+            for t in threads:
+                t.join(timeout=60)
+            torch.cuda.synchronize()
+        return finished
+
+    def close(self):
+        self.batch.close()
+
+
+def percentile(values, q):
+    v = sorted(values)
+    if not v:
+        return float("nan")
+    k = (len(v) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(v) - 1)
+    return v[lo] + (v[hi] - v[lo]) * (k - lo)

@@ -71,3 +71,24 @@ def test_validation_errors_before_device_work():
     assert _bad(svert=inst.svert * 2) == rte.RTE_E_MESH                    # not unit vectors
     q = inst.q_nodal.copy(); q[0] = np.inf
     assert _bad(q_nodal=q) == rte.RTE_E_ARG
+
+
+def test_estimate_footprint_host_only():
+    """rte_estimate_footprint needs no GPU and orders the variants as the allocations do."""
+    from paper_2102_09038_amd import inputs, rte
+    real = inputs.config_realistic()
+    b2, p2 = rte.estimate_footprint(real, e0_solver=rte.RTE_E0_BANDED, mixed=2)
+    b1, p1 = rte.estimate_footprint(real, e0_solver=rte.RTE_E0_BANDED, mixed=1)
+    b0, _ = rte.estimate_footprint(real, e0_solver=rte.RTE_E0_BANDED, mixed=0)
+    bc, _ = rte.estimate_footprint(real, e0_solver=rte.RTE_E0_CG, mixed=0)
+    assert bc < b2 < b0 < b1 and p1 == b1 and p2 > b2
+    # the FP64 band factors (bandwidth 129 in band order: 261 row blocks x 66 groups x 64 x 2
+    # doubles per direction, L and L^T, 1024 directions) are what mixed = 2 drops
+    assert p2 - b2 == 2 * 261 * 66 * 64 * 2 * 8 * 1024
+    small = inputs.config_small()
+    bs, _ = rte.estimate_footprint(small, e0_solver=rte.RTE_E0_BANDED, mixed=1)
+    assert 0 < bs < b2
+    with pytest.raises(rte.RteError) as e:
+        bad = rte.default_assemble_opts()
+        rte._check(rte.lib.rte_estimate_footprint(None, rte.C.byref(bad), rte.C.byref(rte.C.c_size_t()), None))
+    assert e.value.status == rte.RTE_E_ARG

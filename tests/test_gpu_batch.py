@@ -158,3 +158,20 @@ def test_budget_and_requirements(handles):
         b.admit(hs[0], U1, bad)
     assert e.value.status == rte.RTE_E_ARG
     b.close()
+
+
+def test_estimated_footprint_matches_admitted_slot(handles):
+    """rte_estimate_footprint (host only, before assembly) against the bytes a slot holds."""
+    from paper_2102_09038_amd import rte
+    insts, hs = handles
+    for inst, h in zip(insts, hs):
+        est, _ = rte.estimate_footprint(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)
+        b = rte.Batch(max_slots=1)
+        U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+        b.admit(h, U, opts_for(rte.RTE_MIXED))
+        actual = b.usage()[2]
+        print(f"{inst.name}: estimated {est} bytes, slot holds {actual}")
+        assert 0.8 * actual <= est <= 1.5 * actual + (1 << 20)
+        b.step(1000)
+        b.poll()
+        b.close()

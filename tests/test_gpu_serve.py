@@ -1,0 +1,67 @@
+"""GPU tests of the continuous-batching loop (serve.Server): requests that arrive while
+others are being solved are assembled, admitted and finished, and every result is exactly
+the result of solving that request alone (rte_solve, same options); a budget that fits
+one request at a time still serves them all."""
+import pytest
+
+from paper_2102_09038_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def trace():
+    insts = [
+        inputs.tiny_instance(n=4, sphere_level=1, g=0.5, ratio=0.9, n_even=0, n_odd=3, l=4),
+        inputs.config_small(),
+        inputs.tiny_instance(n=6, sphere_level=1, g=0.7, ratio=0.95, n_even=0, n_odd=3, l=4),
+        inputs.make_instance("mid", 2, 24, 2, 0.8, 0.97, seed=7, n_even=0, n_odd=5, l=4),
+        inputs.tiny_instance(n=2, sphere_level=1, g=0.6, ratio=0.9, dim=3, n_even=0, n_odd=1, l=4),
+    ]
+    for inst in insts:
+        inst.n_even = 0
+        inst.l = 4
+    return insts, [0.0, 0.02, 0.05, 0.05, 0.2]
+
+
+def opts():
+    from paper_2102_09038_amd import rte
+    return rte.default_solve_opts(l=4, tol=1e-9, max_iter=500, precision=rte.RTE_MIXED, odd_solver=rte.RTE_ODD_CONDENSED,
+                                  e0_solver=rte.RTE_E0_BANDED)
+
+
+def solo(inst):
+    from paper_2102_09038_amd import rte
+    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2)
+    U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+    st, info = h.solve(U, opts=opts())
+    torch.cuda.synchronize()
+    h.close()
+    return U, info
+
+
+@pytest.mark.parametrize("budget_kind", ["ample", "one-at-a-time"])
+def test_serve_results_equal_solo(budget_kind):
+    from paper_2102_09038_amd import rte, serve
+    insts, arrivals = trace()
+    refs = [solo(i) for i in insts]
+    if budget_kind == "ample":
+        budget = int(64e9)
+    else:
+        # just above the largest single request: requests are served one after another
+        budget = max(max(rte.estimate_footprint(i, e0_solver=rte.RTE_E0_BANDED, mixed=2)) for i in insts) + 1
+    reqs = [serve.Request(rid=k, inst=inst, arrival=a) for k, (inst, a) in enumerate(zip(insts, arrivals))]
+    srv = serve.Server(budget, opts(), max_slots=8, workers=2, keep_results=True)
+    done = srv.run(reqs)
+    srv.close()
+    assert sorted(r.rid for r in done) == list(range(len(insts)))
+    for r in done:
+        U, info = refs[r.rid]
+        print(f"[{budget_kind}] request {r.rid}: arrival {r.arrival:.2f} done {r.done_at:.3f} "
+              f"latency {r.latency:.3f} s, {r.iters} iters (solo {info.iters})")
+        assert r.status == rte.RTE_OK
+        assert r.iters == info.iters
+        assert r.done_at >= r.arrival
+        assert torch.equal(r.U, U)
+    if budget_kind == "one-at-a-time":
+        assert srv.peak_live == 1
