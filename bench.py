@@ -212,23 +212,21 @@ def batch_bench(args, torch, rte, inputs):
     print(json.dumps(out))
 
 
-def serve_bench(args, torch, rte, inputs):
+def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None):
     """The served form: Poisson arrivals (seed 4) of requests drawn like the batched form,
     served by the continuous-batching loop (mixed precision, assembly on worker threads,
     admission by predicted footprint) and, as the baseline, by plain FP64 solves one at a
     time in arrival order.  Latency = completion - arrival; the first warm-up requests of
-    each run are not counted."""
+    each run are not counted.  rates: list of requests/s or 'half' (half the capacity the
+    batched loop reached at the highest numeric rate)."""
     import numpy as np
 
     from paper_2102_09038_amd import serve
 
-    def log(msg):
-        print(msg, file=sys.stderr, flush=True)
-
-    warm = 8
-    n = args.requests + warm
-    insts = inputs.instance_distribution(count=n, seed=4, tol=args.tol)
-    base = dict(l=4, tol=args.tol, max_iter=2000, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_BANDED)
+    log = log or (lambda msg: None)
+    n = requests + warm
+    insts = inputs.instance_distribution(count=n, seed=4, tol=tol)
+    base = dict(l=4, tol=tol, max_iter=2000, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_BANDED)
     omx = rte.default_solve_opts(precision=rte.RTE_MIXED, **base)
     o64 = rte.default_solve_opts(precision=rte.RTE_FP64, **base)
     rng = np.random.Generator(np.random.PCG64(4))
@@ -270,22 +268,33 @@ def serve_bench(args, torch, rte, inputs):
             h.close()
         return stats(reqs, time.perf_counter() - t0)
 
-    rates = [x for x in args.rates.split(",") if x]
     numeric = [float(x) for x in rates if x != "half"]
-    out = {"workload": f"served form: Poisson arrivals (seed 4), {args.requests} measured requests per rate after "
-                       f"{warm} warm-up, drawn like the batched form (2D), rel. residual {args.tol:g}",
+    out = {"workload": f"served form: Poisson arrivals (seed 4), {requests} measured requests per rate after "
+                       f"{warm} warm-up, drawn like the batched form (2D), rel. residual {tol:g}",
            "rates": {}}
     for x in rates:
-        rate = float(x) if x != "half" else 0.5 * out["rates"][max(numeric)]["batched"]["solves_per_s"]
+        rate = float(x) if x != "half" else 0.5 * out["rates"][str(x_max(numeric))]["batched"]["solves_per_s"]
         log(f"[serve] rate {rate:.2f}/s: batched")
         b = run_batched(rate)
         log(f"[serve] rate {rate:.2f}/s: fp64 one at a time")
         f = run_fp64_serial(rate)
-        key = x if x != "half" else f"half capacity ({rate:.2f}/s)"
+        key = str(x) if x != "half" else f"half capacity ({rate:.2f}/s)"
         out["rates"][key] = {"rate": rate, "batched": b, "fp64_one_at_a_time": f}
         log(f"[serve] rate {rate:.2f}/s: batched p50 {b['p50_s']:.2f} s p99 {b['p99_s']:.2f} s "
             f"{b['solves_per_s']:.2f}/s | fp64 p50 {f['p50_s']:.2f} s p99 {f['p99_s']:.2f} s {f['solves_per_s']:.2f}/s")
-    print(json.dumps(out))
+    return out
+
+
+def x_max(v):
+    m = max(v)
+    return int(m) if float(m).is_integer() else m
+
+
+def serve_bench(args, torch, rte, inputs):
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+    rates = [x for x in args.rates.split(",") if x]
+    print(json.dumps(serving_runs(torch, rte, inputs, rates, args.requests, args.tol, log=log)))
 
 
 def main():
@@ -295,6 +304,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the short served-form run")
     ap.add_argument("--only", choices=["kernels", "batch", "serve"], default=None,
                     help="'kernels': assemble the realistic instance, run the dominant kernels twice each "
                          "and a plain 4 GiB device copy (the reference for HBM counter passes), then exit; "
@@ -427,9 +437,21 @@ def main():
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "avg_launch_ms": 1e3 * t_e0m / max(n_e0m, 1),
                        "bytes_per_launch": e0m_bytes, "traffic": measured_traffic("band_solve_f32")},
     }
+    h.close()
+    if not args.no_serving:
+        # the served form at one arrival rate, reduced to a short run (the full study is
+        # bench.py --only serve)
+        sv = serving_runs(torch, rte, inputs, ["50"], 24, args.tol, warm=4)
+        r = sv["rates"]["50"]
+        out["serving"] = {"workload": sv["workload"], "rate_per_s": 50,
+                          "p50_latency_s": r["batched"]["p50_s"], "p99_latency_s": r["batched"]["p99_s"],
+                          "solves_per_s": r["batched"]["solves_per_s"],
+                          "fp64_one_at_a_time": {"p50_latency_s": r["fp64_one_at_a_time"]["p50_s"],
+                                                 "p99_latency_s": r["fp64_one_at_a_time"]["p99_s"],
+                                                 "solves_per_s": r["fp64_one_at_a_time"]["solves_per_s"]},
+                          "all_converged": r["batched"]["all_converged"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, infos[-1].iters, inst.l)
-    h.close()
     print(json.dumps(out))
 
 
