@@ -149,6 +149,73 @@ __global__ __launch_bounds__(TPB) void at_e_kernel(
     }
 }
 
+// Y = A^T Z + (M+ + R) X [- Ms+ G] [- q] with the condensed components in row-major layout,
+// Z[j (d nS) + n nS + k] (cell j, component n, direction k), FP64 or FP32.  A work-group
+// takes a tile of 32 vertices x 64 directions: first each wave gathers A^T Z for its vertices
+// with the lanes along the directions (the vertex's incidence data is wave-uniform and each
+// cell's 64 directions are one contiguous read), into an LDS tile; then the threads turn to
+// run along the vertices for the mass, boundary and source terms, whose vectors are
+// column-major, and write Y coalesced.
+template <int D, typename ZT>
+__global__ __launch_bounds__(256) void at_e_rm_kernel(
+    int nRp, int nS, int nnz, int ncls, int nstiff, int nb, const int* __restrict__ vc_ptr,
+    const int* __restrict__ vc_cell, const double* __restrict__ vcD, const int* __restrict__ rowptr,
+    const int* __restrict__ col, const double* __restrict__ MtMs, const double* __restrict__ cls,
+    const int* __restrict__ bnd_row, const double* __restrict__ coefE, const ZT* __restrict__ Z,
+    const double* __restrict__ X, const double* __restrict__ G, const double* __restrict__ q,
+    double* __restrict__ Y) {
+    constexpr int TI = 32, TK = 64;
+    __shared__ double T[TI][TK + 1];
+    const int i0 = blockIdx.x * TI, k0 = blockIdx.y * TK;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t dn = (size_t)D * nS;
+    {
+        const int k = k0 + lane;
+        const bool kin = k < nS;
+        for (int il = wave; il < TI; il += 4) {
+            const int i = i0 + il;
+            double acc = 0.0;
+            if (i < nRp && kin) {
+                for (int e = vc_ptr[i]; e < vc_ptr[i + 1]; ++e) {
+                    const ZT* zr = Z + (size_t)vc_cell[e] * dn + k;
+#pragma unroll
+                    for (int n = 0; n < D; ++n) acc = fma(vcD[(size_t)e * D + n], (double)zr[(size_t)n * nS], acc);
+                }
+            }
+            T[il][lane] = acc;
+        }
+    }
+    __syncthreads();
+    const int il = threadIdx.x & (TI - 1);
+    const int i = i0 + il;
+    if (i >= nRp) return;
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    const bool bnd = bnd_row[i] != 0;
+    for (int kl = threadIdx.x / TI; kl < TK; kl += 256 / TI) {
+        const int k = k0 + kl;
+        if (k >= nS) break;
+        const double* cf = coefE + (size_t)k * ncls;
+        const double mk = cf[nstiff];
+        const double* xk = X + (size_t)nRp * k;
+        double acc = T[il][kl];
+        for (int e = e0; e < e1; ++e) {
+            const int c = col[e];
+            acc = fma(mk * MtMs[2 * (size_t)e], xk[c], acc);
+            if (G) acc = fma(-MtMs[2 * (size_t)e + 1], G[c + (size_t)nRp * k], acc);
+        }
+        if (bnd) {
+            for (int e = e0; e < e1; ++e) {
+                double val = 0.0;
+                for (int b2 = 0; b2 < nb; ++b2)
+                    val = fma(cf[nstiff + 1 + b2], cls[(size_t)(nstiff + 1 + b2) * nnz + e], val);
+                acc = fma(val, xk[col[e]], acc);
+            }
+        }
+        const size_t o = i + (size_t)nRp * k;
+        Y[o] = q ? acc - q[o] : acc;
+    }
+}
+
 // Yc[j + nRm (n nS + k)] = (D_n X)[j, k] / mt_j   (input of the condensed transport GEMM).
 // One thread per cell and KC consecutive directions (cell data loaded once).
 template <int D, int KC>
@@ -590,15 +657,25 @@ void apply_At_E(const Handle* h, const double* Z, const double* X, const double*
     RTE_CHECK_LAUNCH();
 }
 
-void apply_At_E_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,
+template <typename ZT>
+void at_e_rm_launch(const Handle* h, const ZT* Z, const double* X, const double* G, const double* q, double* Y,
                     hipStream_t s) {
-    const size_t n = (size_t)h->nRp * ((h->nS + kAtEK - 1) / kAtEK);
-    const dim3 g((unsigned)((n + TPB - 1) / TPB));
-    auto* f = h->d == 2 ? at_e_kernel<2, true, float, kAtEK> : at_e_kernel<3, true, float, kAtEK>;
-    hipLaunchKernelGGL(f, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->nnz, h->ncls, h->ncls_stiff, h->nbcls,
-                       h->vc_ptr.p, h->vc_cell.p, h->vcD.p, h->T.p, h->rowptr.p, h->col.p, h->MtMs.p, h->cls.p,
-                       h->bnd_row.p, h->coefE.p, Z, X, G, q, Y);
+    const dim3 g((unsigned)((h->nRp + 31) / 32), (unsigned)((h->nS + 63) / 64));
+    auto* f = h->d == 2 ? at_e_rm_kernel<2, ZT> : at_e_rm_kernel<3, ZT>;
+    hipLaunchKernelGGL(f, g, dim3(256), 0, s, h->nRp, h->nS, h->nnz, h->ncls, h->ncls_stiff, h->nbcls, h->vc_ptr.p,
+                       h->vc_cell.p, h->vcD.p, h->rowptr.p, h->col.p, h->MtMs.p, h->cls.p, h->bnd_row.p, h->coefE.p,
+                       Z, X, G, q, Y);
     RTE_CHECK_LAUNCH();
+}
+
+void apply_At_E_rm(const Handle* h, const double* Z, const double* X, const double* G, const double* q, double* Y,
+                   hipStream_t s) {
+    at_e_rm_launch<double>(h, Z, X, G, q, Y, s);
+}
+
+void apply_At_E_rm_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,
+                       hipStream_t s) {
+    at_e_rm_launch<float>(h, Z, X, G, q, Y, s);
 }
 
 void apply_grad(const Handle* h, const double* X, double* Yc, hipStream_t s) {

@@ -153,9 +153,11 @@ void spmm_pattern(const Handle* h, const double* vals, const double* X, double* 
 // Ycb = [Y | Y] with Y = bf16(Mt-^{-1} [D_1 X, .., D_d X]), row-major nRm x 2 d nS (angular index
 // contiguous; the second copy meets the low BF16 part of the operator in the GEMM)
 void apply_grad_bf16(const Handle* h, const double* X, uint16_t* Ycb, hipStream_t s);
-// apply_At_E with FP32 condensed components Z (column-major nRm x d nS)
-void apply_At_E_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,
-                    hipStream_t s);
+// apply_At_E with the condensed components Z row-major (Z[j (d nS) + n nS + k]), FP64 or FP32
+void apply_At_E_rm(const Handle* h, const double* Z, const double* X, const double* G, const double* q, double* Y,
+                   hipStream_t s);
+void apply_At_E_rm_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,
+                       hipStream_t s);
 // Y[j, c] = v[j] X[j, c]   (nrow x ncol, col-major)
 void row_scale(const double* v, int nrow, int ncol, const double* X, double* Y, hipStream_t s);
 }  // namespace k

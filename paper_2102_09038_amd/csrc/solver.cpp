@@ -176,14 +176,16 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
             k::apply_grad_bf16(h, X, Ycb, s);
             {
                 Timed t(h, s, P_GEMM_BF16, 2.0 * h->nRm * (double)dn * (2.0 * dn));
-                k::gemm_bf16(h->nRm, dn, 2 * dn, 1.0f, Ycb, 2 * dn, h->Gc_bf.p, 2 * dn, 0.0f, Zf, h->nRm, s);
+                // Z^T = [G_hi | G_lo] [Y | Y]^T: Z comes out row-major (cell-major, directions contiguous)
+                k::gemm_bf16(dn, h->nRm, 2 * dn, 1.0f, h->Gc_bf.p, 2 * dn, Ycb, 2 * dn, 0.0f, Zf, dn, s);
             }
-            k::apply_At_E_f32(h, Zf, X, G, q, Y, s);
+            k::apply_At_E_rm_f32(h, Zf, X, G, q, Y, s);
             return;
         }
         k::apply_grad(h, X, B, s);
-        gemm(h, h->nRm, dn, dn, B, h->nRm, h->Gc.p, dn, Z, h->nRm, s);
-        k::apply_At_E(h, Z, X, G, q, Y, s, true);
+        // Z^T = G Yc^T (G symmetric): Z comes out row-major (cell-major, directions contiguous)
+        gemm(h, dn, h->nRm, dn, h->Gc.p, dn, B, h->nRm, Z, dn, s);
+        k::apply_At_E_rm(h, Z, X, G, q, Y, s);
         return;
     }
     k::apply_A(h, X, B, s);
