@@ -263,3 +263,33 @@ def test_mixed_solve_fine_sphere_low_scattering():
     assert its["mixed"] <= its["fp64"] + 1
     assert err < 1e-6
     h.close()
+
+
+# ----------------------------------------------------------------------------- degenerate cases
+DEGENERATE = {
+    # sigma_s = 0: E_0 = E, the even problem decouples per direction and P_1 is exact
+    "pure-absorber": lambda: inputs.tiny_instance(n=5, sphere_level=1, g=0.6, ratio=0.0, n_even=0, n_odd=3, l=3),
+    # g = 0: isotropic scattering (S- = 0)
+    "isotropic": lambda: inputs.tiny_instance(n=4, sphere_level=1, g=0.0, ratio=0.9, n_even=2, n_odd=3, l=3),
+    # one square: 4 vertices, 2 cells, every kernel with a single ragged tile
+    "one-square": lambda: inputs.tiny_instance(n=1, sphere_level=1, g=0.5, ratio=0.8, n_even=0, n_odd=3, l=2),
+}
+
+
+@pytest.mark.parametrize("name", list(DEGENERATE))
+def test_degenerate_solves(name):
+    from paper_2102_09038_amd import rte
+    inst = DEGENERATE[name]()
+    D, ops, h = make(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)
+    uref, rinfo = richardson(ops, l=inst.l, tol=1e-12, max_iter=200)
+    for odd in (rte.RTE_ODD_EXACT, rte.RTE_ODD_CONDENSED):
+        o = rte.default_solve_opts(l=inst.l, tol=1e-12, max_iter=200, odd_solver=odd, e0_solver=rte.RTE_E0_BANDED,
+                                   pcg_tol_resid=1e-14)
+        U = torch.empty((D.nS, D.nRp), dtype=torch.float64, device="cuda")
+        st, info = h.solve(U, opts=o)
+        err = rel(from_dev(U), uref)
+        print(f"[{name} odd={odd}] {info.iters} iters (oracle {rinfo['iters']}), rel err {err:.2e}")
+        assert err < 1e-10
+        if name == "pure-absorber":
+            assert info.iters <= 1
+    h.close()
