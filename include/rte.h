@@ -210,7 +210,10 @@ rte_status rte_precond(rte_handle* h, const rte_solve_opts* opts, int32_t which,
 
 /* Preconditioned Richardson iteration (Sec. 5, Alg. 3) from U0 (device, NULL = 0)
  * until ||r_n|| <= tol ||q||.  U_even (device FP64 n_R+ x n_S+) receives the iterate.
- * U_odd must be NULL (reserved).  info may be NULL.  Blocking.  Returns
+ * U_odd (device FP64 n_R- x n_S-, column-major, odd index 3k + m; NULL = not wanted)
+ * receives the odd part of the final iterate from the second row of the mixed system
+ * (eq. mixed_discrete with l- = 0): u- = -(M- - K-)^{-1} A u+, by the exact per-cell odd
+ * inverse.  info may be NULL.  Blocking.  Returns
  * RTE_E_NOTCONV at the iteration cap (U_even still holds the last iterate) and
  * RTE_E_NONFINITE if the residual is not finite. */
 rte_status rte_solve(rte_handle* h, const rte_solve_opts* opts, const double* U0, double* U_even,

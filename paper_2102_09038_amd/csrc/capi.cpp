@@ -164,8 +164,8 @@ rte_status rte_solve(rte_handle* hh, const rte_solve_opts* o, const double* U0, 
         rte::Handle* h = as_handle(hh);
         check_opts(o);
         if (!U_even) rte::fail(RTE_E_ARG, "null U_even");
-        if (U_odd) rte::fail(RTE_E_ARG, "U_odd output is reserved and must be NULL");
-        const rte_status st = rte::solve(h, o, U0, U_even, info, as_stream(hip_stream));
+        if (U_odd && !h->have_exact) rte::fail(RTE_E_ARG, "the odd part needs the exact odd inverse of the handle");
+        const rte_status st = rte::solve(h, o, U0, U_even, U_odd, info, as_stream(hip_stream));
         if (st == RTE_E_NOTCONV) g_last_error = "iteration cap reached before the tolerance";
         if (st == RTE_E_NONFINITE) g_last_error = "residual is not finite";
         return st;

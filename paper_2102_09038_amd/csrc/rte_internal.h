@@ -178,7 +178,7 @@ void apply_E0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y,
                  int64_t* cg_total, int* cg_max);
 void precond(Handle* h, const rte_solve_opts* o, int which, const double* r, double* out,
              hipStream_t s);
-rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U,
+rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U, double* U_odd,
                  rte_solve_info* info, hipStream_t s);
 
 size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o, size_t* peak);

@@ -308,8 +308,8 @@ void precond(Handle* h, const rte_solve_opts* o, int which, const double* r, dou
     k::axpby(0.0, out, -1.0, out, n, s);             // P2 P1 r = s - W uc
 }
 
-rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U, rte_solve_info* info,
-                 hipStream_t s) {
+rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U, double* U_odd,
+                 rte_solve_info* info, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     const size_t n = (size_t)h->nRp * h->nS;
     rte_solve_info inf{};
@@ -345,6 +345,15 @@ rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U
         have_step = true;
         k::axpby(1.0, step, 1.0, U, n, s);
         ++it;
+    }
+    if (U_odd) {
+        // the odd part from the second row of the mixed system (Sec. 2.6, eq. mixed_discrete):
+        // A u+ + (M- - K-) u- = l- = 0 for an isotropic source, so u- = -(M- - K-)^{-1} A u+
+        double* B = ws(h, W_OB);
+        k::apply_A(h, U, B, s);
+        odd_exact(h, B, U_odd, s);
+        const size_t nodd = (size_t)h->nRm * h->nSm;
+        k::axpby(0.0, U_odd, -1.0, U_odd, nodd, s);
     }
     RTE_HIP(hipStreamSynchronize(s));
     collect_profile(h, &inf);

@@ -264,11 +264,12 @@ class Handle:
         _check(lib.rte_precond(self.h, C.byref(o), which, C.c_void_p(r.data_ptr()), C.c_void_p(s.data_ptr()),
                                _stream(stream)))
 
-    def solve(self, U, U0=None, opts=None, stream=None, raise_on_notconv=True):
+    def solve(self, U, U0=None, opts=None, stream=None, raise_on_notconv=True, U_odd=None):
         o = opts or default_solve_opts()
         info = rte_solve_info()
         st = lib.rte_solve(self.h, C.byref(o), C.c_void_p(U0.data_ptr() if U0 is not None else 0),
-                           C.c_void_p(U.data_ptr()), None, C.byref(info), _stream(stream))
+                           C.c_void_p(U.data_ptr()), C.c_void_p(U_odd.data_ptr() if U_odd is not None else 0),
+                           C.byref(info), _stream(stream))
         if st != RTE_OK and (raise_on_notconv or st != RTE_E_NOTCONV):
             _check(st)
         return st, info

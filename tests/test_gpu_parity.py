@@ -293,3 +293,23 @@ def test_degenerate_solves(name):
         if name == "pure-absorber":
             assert info.iters <= 1
     h.close()
+
+
+def test_odd_part_matches_mixed_direct_solve(case):
+    """u- returned by rte_solve against the odd block of the oracle's direct solve of the full
+    mixed system (eq. mixed_discrete)."""
+    from oracle.mixed import solve_mixed
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    if D.nRp * D.nS + D.nRm * 3 * D.nS > 30_000:
+        pytest.skip("direct solve of the mixed system too large for this case")
+    up_ref, um_ref = solve_mixed(D)
+    o = rte.default_solve_opts(l=inst.l, tol=1e-12, max_iter=300, odd_solver=rte.RTE_ODD_EXACT,
+                               e0_solver=rte.RTE_E0_BANDED)
+    U = torch.empty((D.nS, D.nRp), dtype=torch.float64, device="cuda")
+    Um = torch.full((3 * D.nS, D.nRm), float("nan"), dtype=torch.float64, device="cuda")
+    h.solve(U, opts=o, U_odd=Um)
+    eu = rel(from_dev(U), up_ref)
+    em = rel(from_dev(Um), um_ref)
+    print(f"[{name}] even {eu:.2e} odd {em:.2e}")
+    assert eu < 1e-10 and em < 1e-10
