@@ -224,6 +224,14 @@ rte_status rte_batch_poll(rte_batch* b, int32_t max_out, int32_t* slots, rte_sol
     });
 }
 
+rte_status rte_batch_set_graphs(rte_batch* b, int32_t use_graphs) {
+    return guarded([&] {
+        if (!b) rte::fail(RTE_E_ARG, "null batch");
+        rte::batch_set_graphs(reinterpret_cast<rte::Batch*>(b), use_graphs != 0);
+        return RTE_OK;
+    });
+}
+
 rte_status rte_batch_usage(const rte_batch* b, int32_t* n_live, int32_t* n_done, size_t* used_bytes) {
     return guarded([&] {
         if (!b) rte::fail(RTE_E_ARG, "null batch");

@@ -406,6 +406,8 @@ __global__ __launch_bounds__(256) void gemv_rows_kernel(int n, const double* __r
     if (lane == 0) Y[i] = v;
 }
 
+constexpr int kBandMaxLds = 150 * 1024;   // largest dynamic LDS window of a band solve
+
 int pow2_at_least(int v) {
     int w = 64;
     while (w < v) w <<= 1;
@@ -439,8 +441,14 @@ namespace k {
 template <typename FT, int H, int P>
 void band_launch_hp(const FT* BL, const FT* BU, int n, int bw, int nsys, size_t stride_sys, const double* b,
                     double* x, size_t stride_vec, const int* iperm, int W, size_t lds, hipStream_t s) {
-    RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_kernel<FT, H, P>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    // the window limit is raised once per kernel to the largest window any band may use
+    // (so that no attribute call happens while a caller captures a graph)
+    static const bool attr = [] {
+        RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_kernel<FT, H, P>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kBandMaxLds));
+        return true;
+    }();
+    (void)attr;
     hipLaunchKernelGGL((band_solve_kernel<FT, H, P>), dim3(nsys), dim3(64), lds, s, BL, BU, n, bw, stride_sys, b, x,
                        stride_vec, iperm, W);
     RTE_CHECK_LAUNCH();
@@ -462,7 +470,7 @@ void band_solve_launch(const FT* BL, const FT* BU, int n, int bw, int nsys, size
     const BandShape sh = band_shape(bw, VEC);
     const int W = band_ring(bw, VEC);
     const size_t lds = band_lds(W);
-    if (lds > 150 * 1024) fail(RTE_E_ARG, "band too wide for the solve window");
+    if (lds > (size_t)kBandMaxLds) fail(RTE_E_ARG, "band too wide for the solve window");
 #define RTE_BAND_CASE(HH, PP)                                                                             \
     if (sh.H == HH && sh.P == PP) {                                                                       \
         band_launch_hp<FT, HH, PP>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, W, lds, s); \
@@ -477,8 +485,12 @@ void band_solve_launch(const FT* BL, const FT* BU, int n, int bw, int nsys, size
 
 template <typename FT, int H, int P>
 void band_group_launch_hp(const BandJob* jobs, int njobs, int nwg, size_t lds, hipStream_t s) {
-    RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_group_kernel<FT, H, P>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    static const bool attr = [] {
+        RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_group_kernel<FT, H, P>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kBandMaxLds));
+        return true;
+    }();
+    (void)attr;
     hipLaunchKernelGGL((band_solve_group_kernel<FT, H, P>), dim3(nwg), dim3(64), lds, s, jobs, njobs);
     RTE_CHECK_LAUNCH();
 }
@@ -489,7 +501,7 @@ void band_group_plan(std::vector<BandJob>& jobs, bool f32, BandGroupPlan& plan, 
         const BandShape sh = band_shape(j.bw, vec);
         if (sh.H == 0) fail(RTE_E_ARG, "band too wide for the solve kernel");
         j.W = band_ring(j.bw, vec);
-        if (band_lds(j.W) > 150 * 1024) fail(RTE_E_ARG, "band too wide for the solve window");
+        if (band_lds(j.W) > (size_t)kBandMaxLds) fail(RTE_E_ARG, "band too wide for the solve window");
         j.first = sh.H * 16 + sh.P;                 // sort key for now
     }
     std::stable_sort(jobs.begin(), jobs.end(), [](const BandJob& a, const BandJob& b) { return a.first < b.first; });

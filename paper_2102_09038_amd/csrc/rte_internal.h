@@ -189,6 +189,7 @@ Batch* batch_create(int max_slots, size_t budget);
 void batch_destroy(Batch* B);
 int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, double* U, hipStream_t s);
 int batch_step(Batch* B, int outer_iters, hipStream_t s);
+void batch_set_graphs(Batch* B, bool on);
 int batch_poll(Batch* B, int max_out, int32_t* slots, rte_solve_info* infos, int32_t* statuses);
 void batch_usage(const Batch* B, int32_t* n_live, int32_t* n_done, size_t* used_bytes);
 

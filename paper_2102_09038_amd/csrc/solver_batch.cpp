@@ -41,12 +41,26 @@ struct Batch {
     std::vector<BatchSlot> slots;
     k::BandGroupPlan plan;
     bool plan_valid = false;
+    // graph mode: the two launch sequences of an iteration (residuals; preconditioner and
+    // update) are captured once per set of live slots and replayed, on the batch's own stream
+    bool use_graphs = true;
+    hipStream_t gs = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t g_res = nullptr, g_prec = nullptr;
+    bool graphs_valid = false;
+    ~Batch() {
+        if (g_res) (void)hipGraphExecDestroy(g_res);
+        if (g_prec) (void)hipGraphExecDestroy(g_prec);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (gs) (void)hipStreamDestroy(gs);
+    }
 };
 
 namespace {
 
 // the workspace a batch slot uses (condensed or exact odd solve, banded E_0)
-const int kSlotWs[] = {W_OB, W_OZ, W_EG, W_ET, W_ER, W_ES, W_ESTEP, W_EZ, W_ET2, W_BB, W_BX, W_CRHS, W_CSOL};
+const int kSlotWs[] = {W_OB, W_OZ, W_OG, W_EG, W_ET, W_ER, W_ES, W_ESTEP, W_EZ, W_ET2, W_BB, W_BX, W_CRHS, W_CSOL};
 
 size_t ws_bytes(const Handle* h, int id) {
     const size_t odd = (size_t)h->nRm * h->nSm, even = (size_t)h->nRp * h->nS;
@@ -95,6 +109,83 @@ void grouped_e0inv(Batch* B, XF x_of, YF y_of, hipStream_t s) {
     k::band_group_run(B->plan, s);
     for (auto& sl : B->slots)
         if (sl.live) k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, ws(sl.h, W_BX), y_of(sl), false, s);
+}
+
+// residuals r_n = (E - K+) u_n - q (FP64) of every live slot and the scalars of its
+// stopping tests (r.r in S_DOT0, step.r_n in S_DOT1; the latter is unused before a slot's
+// first step)
+void enqueue_residuals(Batch* B, hipStream_t s) {
+    for (auto& sl : B->slots) {
+        if (!sl.live) continue;
+        Handle* h = sl.h;
+        const size_t n = (size_t)h->nRp * h->nS;
+        double* r = ws(h, W_ER);
+        residual_like(h, &sl.o, sl.U, h->q.p, r, sl.o.pcg_tol_resid, s, nullptr, false);
+        k::dot(r, r, n, h->red.p, s);
+        k::reduce(h->red.p, h->scal.p, S_DOT0, s);
+        k::dot(ws(h, W_ESTEP), r, n, h->red.p, s);
+        k::reduce(h->red.p, h->scal.p, S_DOT1, s);
+    }
+}
+
+// P_1^l (Alg. 2) with grouped E_0 solves, the subspace correction (Sec. 5.4), step.r_n into
+// S_DOT2 and the update u_{n+1} = u_n + step, for every live slot
+void enqueue_precond_update(Batch* B, hipStream_t s) {
+    const bool lowp = B->precision == RTE_MIXED;
+    grouped_e0inv(B, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ER); },
+                  [](BatchSlot& sl) { return ws(sl.h, W_ES); }, s);
+    for (int i = 1; i < B->l; ++i) {
+        for (auto& sl : B->slots) {
+            if (!sl.live) continue;
+            apply_E_core(sl.h, &sl.o, ws(sl.h, W_ES), nullptr, ws(sl.h, W_ER), ws(sl.h, W_ET2), sl.o.pcg_tol_inner,
+                         s, nullptr, lowp);
+        }
+        grouped_e0inv(B, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ET2); },
+                      [](BatchSlot& sl) { return ws(sl.h, W_EZ); }, s);
+        for (auto& sl : B->slots) {
+            if (!sl.live) continue;
+            k::axpby(-1.0, ws(sl.h, W_EZ), 1.0, ws(sl.h, W_ES), (size_t)sl.h->nRp * sl.h->nS, s);
+        }
+    }
+    for (auto& sl : B->slots) {
+        if (!sl.live) continue;
+        Handle* h = sl.h;
+        const size_t n = (size_t)h->nRp * h->nS;
+        double* r = ws(h, W_ER);
+        double* step = ws(h, W_ESTEP);
+        correction_step(h, &sl.o, r, ws(h, W_ES), step, s, nullptr, lowp);
+        k::dot(step, r, n, h->red.p, s);
+        k::reduce(h->red.p, h->scal.p, S_DOT2, s);
+        k::axpby(1.0, step, 1.0, sl.U, n, s);
+    }
+}
+
+template <typename F>
+hipGraphExec_t capture(hipStream_t s, F&& enqueue) {
+    RTE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue();
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(s, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    hipGraph_t g = nullptr;
+    RTE_HIP(hipStreamEndCapture(s, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    RTE_HIP(e);
+    return ex;
+}
+
+void recapture(Batch* B) {
+    if (B->g_res) { RTE_HIP(hipGraphExecDestroy(B->g_res)); B->g_res = nullptr; }
+    if (B->g_prec) { RTE_HIP(hipGraphExecDestroy(B->g_prec)); B->g_prec = nullptr; }
+    B->g_res = capture(B->gs, [&] { enqueue_residuals(B, B->gs); });
+    B->g_prec = capture(B->gs, [&] { enqueue_precond_update(B, B->gs); });
+    B->graphs_valid = true;
 }
 
 void finish(BatchSlot& sl, rte_status st) {
@@ -154,30 +245,40 @@ int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, 
     if (U0) k::copy(U0, U, n, s);
     else k::fill(U, 0.0, n, s);
     B->plan_valid = false;
+    B->graphs_valid = false;
     return id;
 }
 
-int batch_step(Batch* B, int outer_iters, hipStream_t s) {
-    const bool lowp = B->precision == RTE_MIXED;
-    for (int it = 0; it < outer_iters; ++it) {
-        // ---- residuals r_n = (E - K+) u_n - q (FP64) and the scalars of the stopping tests
-        int nlive = 0;
-        for (auto& sl : B->slots) {
-            if (!sl.live) continue;
-            ++nlive;
-            Handle* h = sl.h;
-            const size_t n = (size_t)h->nRp * h->nS;
-            double* r = ws(h, W_ER);
-            residual_like(h, &sl.o, sl.U, h->q.p, r, sl.o.pcg_tol_resid, s, &sl.info.pcg_iters_total, false);
-            k::dot(r, r, n, h->red.p, s);
-            k::reduce(h->red.p, h->scal.p, S_DOT0, s);
-            if (sl.have_step) {
-                k::dot(ws(h, W_ESTEP), r, n, h->red.p, s);
-                k::reduce(h->red.p, h->scal.p, S_DOT1, s);
-            }
-            RTE_HIP(hipMemcpyAsync(h->pinned, h->scal.p, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
+int batch_step(Batch* B, int outer_iters, hipStream_t caller) {
+    hipStream_t s = caller;
+    if (B->use_graphs) {
+        // a captured sequence needs a stream other than the null stream: run on the batch's
+        // own stream, ordered after the caller's earlier work and before its later work
+        if (!B->gs) {
+            RTE_HIP(hipStreamCreateWithFlags(&B->gs, hipStreamNonBlocking));
+            RTE_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+            RTE_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
         }
-        if (nlive == 0) return 0;
+        s = B->gs;
+        RTE_HIP(hipEventRecord(B->ev_in, caller));
+        RTE_HIP(hipStreamWaitEvent(s, B->ev_in, 0));
+    }
+    int nlive = 0;
+    for (int it = 0; it < outer_iters; ++it) {
+        nlive = 0;
+        for (auto& sl : B->slots) nlive += sl.live ? 1 : 0;
+        if (nlive == 0) break;
+        if (!B->plan_valid) {
+            rebuild_plan(B, s);
+            B->graphs_valid = false;
+        }
+        if (B->use_graphs && !B->graphs_valid) recapture(B);
+        // ---- residuals and the scalars of the stopping tests; one synchronisation
+        if (B->use_graphs) RTE_HIP(hipGraphLaunch(B->g_res, s));
+        else enqueue_residuals(B, s);
+        for (auto& sl : B->slots)
+            if (sl.live)
+                RTE_HIP(hipMemcpyAsync(sl.h->pinned, sl.h->scal.p, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
         RTE_HIP(hipStreamSynchronize(s));
         bool changed = false;
         for (auto& sl : B->slots) {
@@ -196,44 +297,33 @@ int batch_step(Batch* B, int outer_iters, hipStream_t s) {
             if (sl.info.rel_resid <= sl.o.tol) { finish(sl, RTE_OK); changed = true; }
             else if (sl.iters >= sl.o.max_iter) { finish(sl, RTE_E_NOTCONV); changed = true; }
         }
-        if (changed || !B->plan_valid) rebuild_plan(B, s);
-        bool any = false;
-        for (auto& sl : B->slots) any |= sl.live;
-        if (!any) return 0;
-        // ---- P_1^l (Alg. 2): z = E_0^{-1} r, then l - 1 steps z -= E_0^{-1} (E z - r)
-        grouped_e0inv(B, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ER); },
-                      [](BatchSlot& sl) { return ws(sl.h, W_ES); }, s);
-        for (int i = 1; i < B->l; ++i) {
-            for (auto& sl : B->slots) {
-                if (!sl.live) continue;
-                apply_E_core(sl.h, &sl.o, ws(sl.h, W_ES), nullptr, ws(sl.h, W_ER), ws(sl.h, W_ET2), sl.o.pcg_tol_inner,
-                             s, &sl.info.pcg_iters_total, lowp);
-            }
-            grouped_e0inv(B, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ET2); },
-                          [](BatchSlot& sl) { return ws(sl.h, W_EZ); }, s);
-            for (auto& sl : B->slots) {
-                if (!sl.live) continue;
-                k::axpby(-1.0, ws(sl.h, W_EZ), 1.0, ws(sl.h, W_ES), (size_t)sl.h->nRp * sl.h->nS, s);
-            }
+        if (changed) {
+            rebuild_plan(B, s);
+            B->graphs_valid = false;
         }
-        // ---- subspace correction (Sec. 5.4) and the update u_{n+1} = u_n + step
-        for (auto& sl : B->slots) {
-            if (!sl.live) continue;
-            Handle* h = sl.h;
-            const size_t n = (size_t)h->nRp * h->nS;
-            double* r = ws(h, W_ER);
-            double* step = ws(h, W_ESTEP);
-            correction_step(h, &sl.o, r, ws(h, W_ES), step, s, &sl.info.pcg_iters_total, lowp);
-            k::dot(step, r, n, h->red.p, s);
-            k::reduce(h->red.p, h->scal.p, S_DOT2, s);
-            k::axpby(1.0, step, 1.0, sl.U, n, s);
-            ++sl.iters;
-            sl.have_step = true;
-        }
+        nlive = 0;
+        for (auto& sl : B->slots) nlive += sl.live ? 1 : 0;
+        if (nlive == 0) break;
+        if (B->use_graphs && !B->graphs_valid) recapture(B);
+        // ---- P_1^l, the subspace correction and the update
+        if (B->use_graphs) RTE_HIP(hipGraphLaunch(B->g_prec, s));
+        else enqueue_precond_update(B, s);
+        for (auto& sl : B->slots)
+            if (sl.live) {
+                ++sl.iters;
+                sl.have_step = true;
+            }
     }
-    int nlive = 0;
-    for (auto& sl : B->slots) nlive += sl.live ? 1 : 0;
+    if (B->use_graphs) {
+        RTE_HIP(hipEventRecord(B->ev_out, s));
+        RTE_HIP(hipStreamWaitEvent(caller, B->ev_out, 0));
+    }
     return nlive;
+}
+
+void batch_set_graphs(Batch* B, bool on) {
+    B->use_graphs = on;
+    B->graphs_valid = false;
 }
 
 int batch_poll(Batch* B, int max_out, int32_t* slots, rte_solve_info* infos, int32_t* statuses) {

@@ -85,6 +85,7 @@ EXPORTS = {
     "rte_batch_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     "rte_batch_poll": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(rte_solve_info),
                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "rte_batch_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "rte_batch_usage": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]),
     "rte_batch_destroy": (C.c_int, [C.c_void_p]),
     "rte_last_error": (C.c_char_p, []),
@@ -279,10 +280,11 @@ class Batch:
     """Lockstep batch of solves (rte_batch_*): admit handles with their output arrays, step
     all live slots together, poll finished ones.  Handles and arrays must outlive their slot."""
 
-    def __init__(self, max_slots=64, hbm_budget=0):
+    def __init__(self, max_slots=64, hbm_budget=0, use_graphs=True):
         self.b = C.c_void_p()
         _check(lib.rte_batch_create(int(max_slots), int(hbm_budget), C.byref(self.b)))
         self._keep = {}
+        _check(lib.rte_batch_set_graphs(self.b, 1 if use_graphs else 0))
 
     def close(self):
         if self.b:

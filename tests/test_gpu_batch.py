@@ -53,13 +53,17 @@ def alone(h, o):
     return U, info
 
 
+@pytest.mark.parametrize("graphs", [True, False])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batch_equals_single_solves(handles, prec):
+def test_batch_equals_single_solves(handles, prec, graphs):
+    """Graph mode replays the captured iteration many times, with host synchronisations and
+    eager work (admission, polling) in between; every replay feeds the next, and the final
+    results must equal the eager solo solves bit for bit."""
     from paper_2102_09038_amd import rte
     insts, hs = handles
     o = opts_for(rte.RTE_FP64 if prec == "fp64" else rte.RTE_MIXED)
     ref = [alone(h, o) for h in hs]
-    b = rte.Batch(max_slots=8)
+    b = rte.Batch(max_slots=8, use_graphs=graphs)
     outs = [torch.full((h.dims.nSp, h.dims.nRp), np.nan, dtype=torch.float64, device="cuda") for h in hs]
     slots = [b.admit(h, U, o) for h, U in zip(hs, outs)]
     left = b.step(1000)
@@ -70,7 +74,7 @@ def test_batch_equals_single_solves(handles, prec):
     for k, (s, U) in enumerate(zip(slots, outs)):
         st, info = done[s]
         Ur, ir = ref[k]
-        print(f"[{prec} slot {s}] iters {info.iters} (alone {ir.iters}) rel_resid {info.rel_resid:.2e}")
+        print(f"[{prec} graphs={graphs} slot {s}] iters {info.iters} (alone {ir.iters}) rel_resid {info.rel_resid:.2e}")
         assert st == rte.RTE_OK
         assert info.iters == ir.iters
         assert info.rel_resid == ir.rel_resid
