@@ -195,6 +195,37 @@ def batch_bench(args, torch, rte, inputs):
     srv.close()
     errs = [float(torch.linalg.norm(r.U.cpu() - ref[r.rid]) / torch.linalg.norm(ref[r.rid])) for r in done]
     log(f"[batch] {len(done)} solved in {wall:.1f} s ({srv.t_step:.1f} s stepping), peak {srv.peak_live} live slots")
+    # ---- the lockstep stepping alone: every instance assembled beforehand (mixed-only form),
+    #      all admitted at once, stepped to completion with and without the captured graphs;
+    #      instances are taken in order while their handles fit the budget together
+    hs, held = [], 0
+    for inst in insts:
+        b_est, p_est = rte.estimate_footprint(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2)
+        if held + max(b_est, p_est) > budget:
+            continue
+        hs.append(rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2))
+        held += b_est
+    lockstep = {}
+    for graphs in (True, False):
+        b = rte.Batch(max_slots=len(hs), use_graphs=graphs)
+        Us = [torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda") for h in hs]
+        for h, U in zip(hs, Us):
+            b.admit(h, U, omx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        left = b.step(100000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = b.poll()
+        assert left == 0 and len(res) == len(hs)
+        lockstep["graphs" if graphs else "direct"] = {
+            "instances": len(hs), "solves_per_s": len(hs) / dt, "step_s": dt,
+            "lockstep_iters": max(i.iters for _, _, i in res)}
+        log(f"[lockstep graphs={graphs}] {len(hs)} solves in {dt:.2f} s")
+        b.close()
+        del Us
+    for h in hs:
+        h.close()
     out = {
         "workload": f"batched form: {len(insts)} seeded instances (N 32..128, 128/512/2048 sphere triangles, "
                     f"g 0..0.95, ratio 0.5..0.999), rel. residual {args.tol:g}",
@@ -206,6 +237,7 @@ def batch_bench(args, torch, rte, inputs):
                           "iters_total": int(sum(r.iters for r in done)),
                           "all_converged": all(r.status == rte.RTE_OK for r in done),
                           "peak_live_slots": srv.peak_live, "hbm_budget": budget, "assembly_workers": 4},
+        "mixed_lockstep_preassembled": lockstep,
         "speedup_solve": t64 / srv.t_step, "speedup_end_to_end": (t64 + sum(asm64)) / wall,
         "max_rel_err_vs_fp64": max(errs), "median_rel_err_vs_fp64": float(np.median(errs)),
     }

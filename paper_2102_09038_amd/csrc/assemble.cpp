@@ -206,13 +206,19 @@ std::vector<int> rcm(int n, const std::vector<int>& rp, const std::vector<int>& 
     return perm;
 }
 
+// rocBLAS handle on the assembly stream; creation, destruction and every library call hold
+// the capture lock shared
 struct RocblasCtx {
     rocblas_handle h = nullptr;
     explicit RocblasCtx(hipStream_t s) {
+        std::shared_lock<std::shared_mutex> lk(capture_mutex());
         if (rocblas_create_handle(&h) != rocblas_status_success) fail(RTE_E_HIP, "rocblas_create_handle failed");
         rocblas_set_stream(h, s);
     }
-    ~RocblasCtx() { if (h) rocblas_destroy_handle(h); }
+    ~RocblasCtx() {
+        std::shared_lock<std::shared_mutex> lk(capture_mutex());
+        if (h) rocblas_destroy_handle(h);
+    }
 };
 
 // eigenpairs of the symmetric n x n matrix A (col-major host); ascending eigenvalues
@@ -226,13 +232,20 @@ void dense_spd_inverse(RocblasCtx& rb, hipStream_t s, const Vec& band, int n, in
     k::band_to_dense(dband.p, n, bw, Inv.p, s);
     DBuf<int> info(1);
     int hinfo = 0;
-    if (rocsolver_dpotrf(rb.h, rocblas_fill_lower, n, Inv.p, n, info.p) != rocblas_status_success)
-        fail(RTE_E_HIP, "rocsolver_dpotrf failed");
+    rocblas_status st;
+    {
+        std::shared_lock<std::shared_mutex> lk(capture_mutex());
+        st = rocsolver_dpotrf(rb.h, rocblas_fill_lower, n, Inv.p, n, info.p);
+    }
+    if (st != rocblas_status_success) fail(RTE_E_HIP, "rocsolver_dpotrf failed");
     RTE_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
     RTE_HIP(hipStreamSynchronize(s));
     if (hinfo != 0) fail(RTE_E_ARG, "the coarse matrix E_c is not positive definite");
-    if (rocsolver_dpotri(rb.h, rocblas_fill_lower, n, Inv.p, n, info.p) != rocblas_status_success)
-        fail(RTE_E_HIP, "rocsolver_dpotri failed");
+    {
+        std::shared_lock<std::shared_mutex> lk(capture_mutex());
+        st = rocsolver_dpotri(rb.h, rocblas_fill_lower, n, Inv.p, n, info.p);
+    }
+    if (st != rocblas_status_success) fail(RTE_E_HIP, "rocsolver_dpotri failed");
     RTE_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
     RTE_HIP(hipStreamSynchronize(s));
     if (hinfo != 0) fail(RTE_E_HIP, "rocsolver_dpotri failed on the coarse matrix");
@@ -244,8 +257,11 @@ void syevd(RocblasCtx& rb, hipStream_t s, int n, Vec& A, Vec& lam) {
     DBuf<double> dA(A.size()), dD(n), dE(n);
     DBuf<int> info(1);
     RTE_HIP(hipMemcpyAsync(dA.p, A.data(), A.size() * 8, hipMemcpyHostToDevice, s));
-    const rocblas_status st = rocsolver_dsyevd(rb.h, rocblas_evect_original, rocblas_fill_lower, n, dA.p,
-                                               n, dD.p, dE.p, info.p);
+    rocblas_status st;
+    {
+        std::shared_lock<std::shared_mutex> lk(capture_mutex());
+        st = rocsolver_dsyevd(rb.h, rocblas_evect_original, rocblas_fill_lower, n, dA.p, n, dD.p, dE.p, info.p);
+    }
     if (st != rocblas_status_success) fail(RTE_E_HIP, "rocsolver_dsyevd failed");
     int hinfo = 0;
     RTE_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <mutex>
+#include <shared_mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -31,6 +33,17 @@ struct Error : std::runtime_error {
     } while (0)
 
 #define RTE_CHECK_LAUNCH() RTE_HIP(hipGetLastError())
+
+// ----------------------------------------------------------------------------- capture
+// Stream capture (the batch's graphs) and rocBLAS / rocSOLVER calls exclude each other
+// across threads: the libraries touch the legacy null stream (handle set-up, workspace),
+// which HIP rejects while a stream of the process is being captured.  Library calls take
+// the lock shared, a capture takes it exclusively; neither holds it across a wait for
+// device work.
+inline std::shared_mutex& capture_mutex() {
+    static std::shared_mutex m;
+    return m;
+}
 
 // ----------------------------------------------------------------------------- buffers
 // Owning device buffer (hipMalloc / hipFree); movable, not copyable.

@@ -162,6 +162,7 @@ void enqueue_precond_update(Batch* B, hipStream_t s) {
 
 template <typename F>
 hipGraphExec_t capture(hipStream_t s, F&& enqueue) {
+    std::unique_lock<std::shared_mutex> lk(capture_mutex());
     RTE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
         enqueue();
