@@ -23,6 +23,7 @@ import time
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TFLOPS = 78.6    # MI355X dense FP64 matrix
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
+FP32_MFMA_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix
 
 
 def cores_used():
@@ -411,7 +412,7 @@ def main():
                "bytes_per_launch": e0_bytes, "time_share": t_e0 / dt}
     gemm_roof = {"bound": "mfma", "achieved": gemm_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": measured_traffic("gemm_f64_transport"),
-                 "kernel": "gemm_f64_kernel (condensed transport term of E)",
+                 "kernel": "gemm_mfma_kernel<double> (condensed transport term of E)",
                  "avg_launch_ms": 1e3 * t_gm / max(n_gm, 1), "launches": n_gm,
                  "flops_per_launch": fl_gm / max(n_gm, 1), "time_share": t_gm / dt}
     dominant, other = (e0_roof, gemm_roof) if t_e0 >= t_gm else (gemm_roof, e0_roof)
@@ -428,7 +429,7 @@ def main():
         "t_assemble_s": t_assemble,
         "roofline": dominant, "roofline_other": other,
         "scatter_gemm": {"bound": "mfma", "achieved": scatter_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": scatter_tf / FP64_MFMA_PEAK_TFLOPS, "kernel": "gemm_f64_kernel (U S+, eq. tpmv)",
+                         "frac": scatter_tf / FP64_MFMA_PEAK_TFLOPS, "kernel": "gemm_mfma_kernel<double> (U S+, eq. tpmv; last round split over K)",
                          "avg_launch_ms": 1e3 * t_sc / max(n_sc, 1), "launches": n_sc,
                          "flops_per_launch": fl_sc / max(n_sc, 1)},
     }
@@ -456,12 +457,21 @@ def main():
     t_e0m = sum(i.t_e0inv for i in minfos)
     n_e0m = sum(i.n_e0inv for i in minfos)
     e0m_bytes = d.nSp * (2 * factor_entries * 4 + 2 * n * 8)
+    ts32 = sum(i.t_scatter_f32 for i in minfos)
+    fs32 = sum(i.scatter_f32_flops for i in minfos)
+    ns32 = sum(i.n_scatter_f32 for i in minfos)
+    s32_tf = fs32 / ts32 / 1e12 if ts32 else 0.0
     out["mixed"] = {
         "value": args.steps / mdt, "unit": "solves/s", "ms_per_step": 1e3 * mdt / args.steps,
         "speedup_vs_fp64": (args.steps / mdt) / value, "iters": [i.iters for i in minfos],
         "rel_resid": [i.rel_resid for i in minfos],
         "rel_err_vs_fp64_solution": float(torch.linalg.norm(Um - U64) / torch.linalg.norm(U64)),
-        "dtype": "bf16 GEMM (fp32 acc), fp32 E_0 factors, fp64 residual/dots/coarse",
+        "dtype": "bf16 transport GEMM (fp32 acc), fp32 MFMA scatter GEMM in the preconditioner, fp32 E_0 factors, "
+                 "fp64 residual/dots/coarse",
+        "scatter_gemm_fp32": {"bound": "mfma", "achieved": s32_tf, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": s32_tf / FP32_MFMA_PEAK_TFLOPS, "kernel": "gemm_mfma_kernel<float> (U S+)",
+                              "avg_launch_ms": 1e3 * ts32 / max(ns32, 1), "launches": ns32,
+                              "flops_per_launch": fs32 / max(ns32, 1)},
         "gemm_bf16": {"bound": "mfma", "achieved": bf16_tf, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": bf16_tf / BF16_MFMA_PEAK_TFLOPS, "avg_launch_ms": 1e3 * tb / max(nb, 1),
                       "launches": nb, "flops_per_launch": fb / max(nb, 1)},

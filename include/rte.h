@@ -142,9 +142,12 @@ typedef struct rte_solve_info {
     double t_gemm_bf16;          /*   seconds inside BF16 (mixed-precision) GEMM kernels     */
     int64_t n_gemm_bf16;         /*   number of those launches                               */
     double gemm_bf16_flops;      /*   their algorithmic flops                                */
-    double t_scatter;            /*   seconds inside the even scatter GEMMs U S+ (eq. tpmv)  */
-    int64_t n_scatter;           /*   number of those launches                               */
-    double scatter_flops;        /*   their algorithmic flops                                */
+    double t_scatter;            /*   seconds inside the FP64 even scatter GEMMs U S+        */
+    int64_t n_scatter;           /*   (eq. tpmv), their launches                             */
+    double scatter_flops;        /*   and their algorithmic flops                            */
+    double t_scatter_f32;        /*   seconds inside the FP32 MFMA even scatter GEMMs of the */
+    int64_t n_scatter_f32;       /*   mixed-precision preconditioner, their launches         */
+    double scatter_f32_flops;    /*   and their algorithmic flops                            */
 } rte_solve_info;
 
 /* Fill opts with the defaults: quad_level 2, N+ 0, N- 5, CG E_0, no mixed copies. */
@@ -185,8 +188,11 @@ rte_status rte_estimate_footprint(const rte_problem_desc* desc, const rte_assemb
 
 /* Y = K+ X = Ms+ X S+ (parity +1, X and Y n_R+ x n_S+) or Y = K- X = Ms- X S-
  * (parity -1, n_R- x n_S-); Sec. 4 with the Kronecker identity of Sec. 5.1.
- * X and Y are device arrays of dtype_in / dtype_out (F64 or F32; BF16 input only
- * with dtype_out F32 and a handle assembled with mixed != 0).  Enqueue only. */
+ * X and Y are column-major device arrays of dtype_in / dtype_out, each RTE_DT_F64 or
+ * RTE_DT_F32 (other codes: RTE_E_ARG).  The GEMM's arithmetic follows dtype_in: FP64
+ * MFMA, or FP32 MFMA (FP32 products and sums) on the FP32 copy of S, which needs a handle
+ * assembled with mixed != 0 (else RTE_E_ARG); an FP32 Y is rounded from the FP64 epilogue.
+ * Uses the handle's workspace: calls on one handle must not overlap.  Enqueue only. */
 rte_status rte_apply_scatter(rte_handle* h, int32_t parity, int32_t dtype_in, const void* X,
                              int32_t dtype_out, void* Y, void* hip_stream);
 

@@ -289,7 +289,7 @@ size_t Handle::footprint() const {
                q.bytes() + Lc.bytes() + LcU.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() + L0U.bytes() + Ecinv.bytes() +
                Gc.bytes() + vcD.bytes() +
                MtMs.bytes() + bnd_row.bytes() + cg_iters.bytes() +
-               Sp_bf.bytes() + Sm_bf.bytes() + Hodd_bf.bytes() + Gc_bf.bytes() + L0f.bytes() + L0Uf.bytes() + red.bytes() +
+               Sp_f.bytes() + Sm_f.bytes() + Gc_bf.bytes() + L0f.bytes() + L0Uf.bytes() + red.bytes() +
                scal.bytes();
     for (auto& w : ws) b += w.bytes();
     return b;
@@ -961,16 +961,13 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     }
 
     trace("E_0 band factors");
-    // ------------------------------------------------------------------ BF16 copies
+    // ------------------------------------------------------------------ reduced-precision copies
     if (o->mixed) {
-        h.Sp_bf.alloc(h.Sp.n);
-        h.Sm_bf.alloc(h.Sm.n);
-        k::cvt_f64_bf16(h.Sp.p, h.Sp_bf.p, h.Sp.n, s);
-        k::cvt_f64_bf16(h.Sm.p, h.Sm_bf.p, h.Sm.n, s);
-        if (h.Hodd.p) {
-            h.Hodd_bf.alloc(h.Hodd.n);
-            k::cvt_f64_bf16(h.Hodd.p, h.Hodd_bf.p, h.Hodd.n, s);
-        }
+        // FP32 scattering matrices for the FP32 MFMA scatter GEMMs of the preconditioner
+        h.Sp_f.alloc(h.Sp.n);
+        h.Sm_f.alloc(h.Sm.n);
+        k::cvt_f64_f32(h.Sp.p, h.Sp_f.p, h.Sp.n, s);
+        k::cvt_f64_f32(h.Sm.p, h.Sm_f.p, h.Sm.n, s);
         if (h.Gc.p) {
             // [G_hi; G_lo] (2 dn x dn, column-major): the BF16 transport GEMM carries the
             // operator with 16 significant bits (its diagonal blocks are nearly singular for
@@ -1055,7 +1052,7 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
         else transient = f64;
         if (o->mixed) b += 2 * k::band_blk_size(nRp, sbw, 4) * nS * 4;
     }
-    if (o->mixed) b += (nS * nS + 2 * nSm * nSm + 2 * (size_t)d * nS * d * nS) * 2;
+    if (o->mixed) b += (nS * nS + nSm * nSm) * 4 + 2 * (size_t)d * nS * d * nS * 2;
     // solver workspace: two odd-sized buffers, eleven even vectors, coarse vectors, reductions
     b += 2 * (size_t)nRm * nSm * 8 + 11 * even * 8 + 2 * nc * 8 + (1 << 16);
     if (peak) *peak = b + transient;

@@ -4,6 +4,7 @@
 
 #include "ops.h"
 #include "rte_internal.h"
+#include "solver_detail.h"
 
 namespace {
 thread_local std::string g_last_error;
@@ -288,17 +289,28 @@ const char* rte_last_error(void) { return g_last_error.c_str(); }
 
 namespace rte {
 void apply_scatter(Handle* h, int parity, int dtin, const void* X, int dtout, void* Y, hipStream_t s) {
-    if (dtin != RTE_DT_F64 || dtout != RTE_DT_F64) fail(RTE_E_ARG, "only FP64 operands are supported here");
-    const double* x = static_cast<const double*>(X);
-    double* y = static_cast<double*>(Y);
+    if ((dtin != RTE_DT_F64 && dtin != RTE_DT_F32) || (dtout != RTE_DT_F64 && dtout != RTE_DT_F32))
+        fail(RTE_E_ARG, "scatter operands are FP64 or FP32");
+    const bool f32 = dtin == RTE_DT_F32;
+    if (f32 && !(parity == 1 ? h->Sp_f.p : h->Sm_f.p))
+        fail(RTE_E_ARG, "FP32 scatter operands need a handle assembled with mixed != 0");
+    // the GEMM and the mass/diagonal epilogue run on FP64 intermediates in the handle's
+    // workspace; an FP32 result is rounded at the end
     if (parity == 1) {
-        DBuf<double> G((size_t)h->nRp * h->nS);
-        k::gemm_f64(h->nRp, h->nS, h->nS, 1.0, x, h->nRp, h->Sp.p, h->nS, 0.0, G.p, h->nRp, s);
-        k::spmm_pattern(h, h->Msv.p, G.p, y, s);
-        RTE_HIP(hipStreamSynchronize(s));
+        const int n = h->nRp, m = h->nS;
+        double* G = sv::ws(h, sv::W_EG);
+        double* T = dtout == RTE_DT_F64 ? static_cast<double*>(Y) : sv::ws(h, sv::W_ET);
+        if (f32) k::gemm_f32(n, m, m, 1.0f, static_cast<const float*>(X), n, h->Sp_f.p, m, 0.0f, G, n, s);
+        else k::gemm_f64(n, m, m, 1.0, static_cast<const double*>(X), n, h->Sp.p, m, 0.0, G, n, s);
+        k::spmm_pattern(h, h->Msv.p, G, T, s);
+        if (dtout == RTE_DT_F32) k::cvt_f64_f32(T, static_cast<float*>(Y), (size_t)n * m, s);
     } else {
-        k::gemm_f64(h->nRm, h->nSm, h->nSm, 1.0, x, h->nRm, h->Sm.p, h->nSm, 0.0, y, h->nRm, s);
-        k::row_scale(h->ms.p, h->nRm, h->nSm, y, y, s);
+        const int n = h->nRm, m = h->nSm;
+        double* T = dtout == RTE_DT_F64 ? static_cast<double*>(Y) : sv::ws(h, sv::W_OB);
+        if (f32) k::gemm_f32(n, m, m, 1.0f, static_cast<const float*>(X), n, h->Sm_f.p, m, 0.0f, T, n, s);
+        else k::gemm_f64(n, m, m, 1.0, static_cast<const double*>(X), n, h->Sm.p, m, 0.0, T, n, s);
+        k::row_scale(h->ms.p, n, m, T, T, s);
+        if (dtout == RTE_DT_F32) k::cvt_f64_f32(T, static_cast<float*>(Y), (size_t)n * m, s);
     }
 }
 }  // namespace rte

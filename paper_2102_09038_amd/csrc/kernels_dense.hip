@@ -3,6 +3,9 @@
 // (B (x) C) vec X = vec(C X B^T), which turns K+ and K- into GEMMs).
 #include "rte_internal.h"
 
+#include <map>
+#include <mutex>
+
 namespace rte {
 namespace {
 
@@ -119,15 +122,23 @@ __global__ __launch_bounds__(256) void hg_scatter_kernel(const double* __restric
     }
 }
 
-// ============================================================================ FP64 MFMA GEMM
+// ============================================================================ MFMA GEMM
 // C = alpha A B + beta C.  A: M x K col-major (lda); B: K x N row-major (ldb); C: col-major.
 // Work-group tile 128 x 128, K step 16, 4 waves in 2 x 2, each wave 64 x 64 as 4 x 4
-// v_mfma_f64_16x16x4 blocks.  The MFMA "row" operand is the B fragment and the "column"
-// operand the A fragment, so the accumulator's lane-fast index runs along M and the
-// column-major stores of C are 128-byte contiguous.  Register-prefetched global loads,
-// double-buffered LDS, one barrier per K step.
+// 16 x 16 x 4 MFMA blocks, in FP64 (v_mfma_f64_16x16x4f64) or FP32 (v_mfma_f32_16x16x4f32;
+// A may then be FP64, rounded to FP32 as it is staged).  The MFMA "row" operand is the B
+// fragment and the "column" operand the A fragment, so the accumulator's lane-fast index
+// runs along M and the column-major stores of C are contiguous.  Register-prefetched global
+// loads, double-buffered LDS, one barrier per K step.
+//
+// A launch may cover a range of K steps only (blockIdx.y selects the range): that is the
+// split-K form used for a lightly loaded last round of tiles, whose partial products go to
+// a workspace and are summed in split order by gemm_sum_parts_kernel.
 typedef double d4v __attribute__((ext_vector_type(4)));
-constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 4;
+typedef float f4v __attribute__((ext_vector_type(4)));
+// rows padded by 16 elements: the four 16-lane row groups of an operand read fall in
+// disjoint LDS banks
+constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 16;
 
 __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
     // consecutive work-group ids land on different XCDs (round-robin over 8); give every
@@ -138,32 +149,50 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
     return x * per + i;
 }
 
-__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int M, int N, int K, double alpha,
-                                                          const double* __restrict__ A, int lda,
-                                                          const double* __restrict__ B, int ldb,
-                                                          double beta, double* __restrict__ C,
-                                                          int ldc) {
-    __shared__ double As[2][GBK][GBM + GPAD];
-    __shared__ double Bs[2][GBK][GBN + GPAD];
-    const int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
-    const int nb = tm * tn;
-    const int b = xcd_swizzle(blockIdx.x, nb);
-    const int bm = b / tn, bn = b % tn;      // n fastest: one A panel stays hot in L2
-    const int m0 = bm * GBM, n0 = bn * GBN;
+template <typename TM> struct Mfma16;
+template <> struct Mfma16<double> {
+    typedef d4v acc_t;
+    static __device__ __forceinline__ acc_t mma(double b, double a, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c, 0, 0, 0);
+    }
+    // result element v of a lane: row (along the B operand) lane/16 + 4 v
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct Mfma16<float> {
+    typedef f4v acc_t;
+    static __device__ __forceinline__ acc_t mma(float b, float a, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(b, a, c, 0, 0, 0);
+    }
+    // result element v of a lane: row 4 (lane/16) + v
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// One work-group's tile over K steps [kt_begin, kt_end) into acc.  CHECK: guard every load
+// (edge tiles, or K not a multiple of the step); interior tiles load unconditionally.
+template <bool CHECK, typename TM, typename TA>
+__device__ __forceinline__ void gemm_tile(int M, int N, int K, int m0, int n0, int kt_begin, int kt_end,
+                                          const TA* __restrict__ A, int lda, const TM* __restrict__ B, int ldb,
+                                          TM (&As)[2][GBK][GBM + GPAD], TM (&Bs)[2][GBK][GBN + GPAD],
+                                          typename Mfma16<TM>::acc_t (&acc)[4][4]) {
+    typedef Mfma16<TM> F;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-
-    double ra[8], rb[8];
+    TM ra[8], rb[8];
     auto gload = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int f = tid + 256 * i;
             const int ka = f / GBM, ma = f % GBM;
             const int gm = m0 + ma, gk = k0 + ka;
-            ra[i] = (gm < M && gk < K) ? A[gm + (size_t)lda * gk] : 0.0;
             const int kb = f / GBN, nbx = f % GBN;
             const int gn = n0 + nbx, gk2 = k0 + kb;
-            rb[i] = (gn < N && gk2 < K) ? B[(size_t)ldb * gk2 + gn] : 0.0;
+            if (CHECK) {
+                ra[i] = (gm < M && gk < K) ? (TM)A[gm + (size_t)lda * gk] : (TM)0;
+                rb[i] = (gn < N && gk2 < K) ? B[(size_t)ldb * gk2 + gn] : (TM)0;
+            } else {
+                ra[i] = (TM)A[gm + (size_t)lda * gk];
+                rb[i] = B[(size_t)ldb * gk2 + gn];
+            }
         }
     };
     auto sstore = [&](int buf) {
@@ -174,24 +203,18 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int M, int N, int K, d
             Bs[buf][f / GBN][f % GBN] = rb[i];
         }
     };
-
-    d4v acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = d4v{0, 0, 0, 0};
-
-    const int nk = (K + GBK - 1) / GBK;
-    gload(0);
-    sstore(0);
+    if (kt_begin < kt_end) {
+        gload(kt_begin * GBK);
+        sstore(0);
+    }
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * GBK);
+    for (int kt = kt_begin; kt < kt_end; ++kt) {
+        const int cur = (kt - kt_begin) & 1;
+        if (kt + 1 < kt_end) gload((kt + 1) * GBK);
 #pragma unroll
         for (int kk = 0; kk < GBK / 4; ++kk) {
             const int kr = kk * 4 + (lane >> 4);
-            double af[4], bf[4];
+            TM af[4], bf[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) af[i] = As[cur][kr][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
@@ -199,13 +222,44 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int M, int N, int K, d
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    acc[j][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[j][i], 0, 0, 0);
+                for (int i = 0; i < 4; ++i) acc[j][i] = F::mma(bf[j], af[i], acc[j][i]);
         }
-        if (kt + 1 < nk) sstore(cur ^ 1);
+        if (kt + 1 < kt_end) sstore(cur ^ 1);
         __syncthreads();
     }
-    // acc[j][i][v] = C(m = m0 + wm*64 + i*16 + lane%16, n = n0 + wn*64 + j*16 + lane/16 + 4*v)
+}
+
+// TM: MFMA and LDS type; TA: A's storage type; TC: C's storage type.  kps: K steps per
+// split (blockIdx.y); the split's result goes to C + blockIdx.y * split_stride.
+template <typename TM, typename TA, typename TC>
+__global__ __launch_bounds__(256, 2) void gemm_mfma_kernel(int M, int N, int K, int kps, TM alpha,
+                                                           const TA* __restrict__ A, int lda,
+                                                           const TM* __restrict__ B, int ldb, TM beta,
+                                                           TC* __restrict__ C, int ldc, size_t split_stride) {
+    typedef Mfma16<TM> F;
+    __shared__ TM As[2][GBK][GBM + GPAD];
+    __shared__ TM Bs[2][GBK][GBN + GPAD];
+    const int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
+    const int nb = tm * tn;
+    const int b = xcd_swizzle(blockIdx.x, nb);
+    const int bm = b / tn, bn = b % tn;      // n fastest: one A panel stays hot in L2
+    const int m0 = bm * GBM, n0 = bn * GBN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int kt_begin = blockIdx.y * kps;
+    const int kt_end = min((K + GBK - 1) / GBK, kt_begin + kps);
+    C += blockIdx.y * split_stride;
+
+    typename F::acc_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = typename F::acc_t{0, 0, 0, 0};
+    if (m0 + GBM <= M && n0 + GBN <= N && K % GBK == 0)
+        gemm_tile<false>(M, N, K, m0, n0, kt_begin, kt_end, A, lda, B, ldb, As, Bs, acc);
+    else
+        gemm_tile<true>(M, N, K, m0, n0, kt_begin, kt_end, A, lda, B, ldb, As, Bs, acc);
+    // acc[j][i][v] = C(m = m0 + wm*64 + i*16 + lane%16, n = n0 + wn*64 + j*16 + F::row(lane, v))
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -213,14 +267,29 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int M, int N, int K, d
             const int gm = m0 + wm * 64 + i * 16 + (lane & 15);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int gn = n0 + wn * 64 + j * 16 + (lane >> 4) + 4 * v;
+                const int gn = n0 + wn * 64 + j * 16 + F::row(lane, v);
                 if (gm < M && gn < N) {
-                    double* cp = C + gm + (size_t)ldc * gn;
-                    const double val = alpha * acc[j][i][v];
-                    *cp = (beta == 0.0) ? val : fma(beta, *cp, val);
+                    TC* cp = C + gm + (size_t)ldc * gn;
+                    const TM val = alpha * acc[j][i][v];
+                    *cp = (TC)((beta == (TM)0) ? val : beta * (TM)*cp + val);
                 }
             }
         }
+}
+
+// C[m, n] = alpha sum_p P[p][m + M n] + beta C[m + ldc n], the parts added in order
+template <typename TM, typename TC>
+__global__ void gemm_sum_parts_kernel(int M, int N, int nsplit, const TM* __restrict__ P, TM alpha, TM beta,
+                                      TC* __restrict__ C, int ldc) {
+    const size_t total = (size_t)M * N;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        TM acc = P[i];
+        for (int p = 1; p < nsplit; ++p) acc += P[(size_t)p * total + i];
+        const size_t m = i % M, n = i / M;
+        TC* cp = C + m + (size_t)ldc * n;
+        const TM val = alpha * acc;
+        *cp = (TC)((beta == (TM)0) ? val : beta * (TM)*cp + val);
+    }
 }
 
 // ============================================================================ conversions
@@ -280,13 +349,77 @@ void hg_scatter(const double* pts, const double* wts, int nS, int Q, double g, d
     }
 }
 
-void gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, const double* B,
-              int ldb, double beta, double* C, int ldc, hipStream_t s) {
+namespace {
+// work-groups of a kernel resident on the whole current device (compute units x occupancy)
+template <typename Kern>
+int resident_groups(Kern kern) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
+    int dev = 0;
+    RTE_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(reinterpret_cast<const void*>(kern), dev);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int cus = 0, occ = 0;
+    RTE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    RTE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, 0));
+    const int n = std::max(1, cus) * std::max(1, occ);
+    cache[key] = n;
+    return n;
+}
+
+template <typename TM, typename TA, typename TC>
+void gemm_mfma(int M, int N, int K, TM alpha, const TA* A, int lda, const TM* B, int ldb, TM beta, TC* C,
+               int ldc, TM* ws, size_t ws_elems, hipStream_t s) {
     if (M <= 0 || N <= 0) return;
-    const int nb = ((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
-    hipLaunchKernelGGL(gemm_f64_kernel, dim3(nb), dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                       beta, C, ldc);
+    const int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN, nk = (K + GBK - 1) / GBK;
+    const int tiles = tm * tn;
+    const int slots = resident_groups(gemm_mfma_kernel<TM, TA, TC>);
+    const int rounds = tiles / slots, tail = tiles % slots;
+    // A last round filled to a quarter or less leaves most of the device idle: its whole row
+    // blocks are split over K instead (partial products in ws, summed in split order).
+    const int trb = (tail + tn - 1) / tn;
+    if (ws && rounds >= 1 && tail > 0 && 4 * tail <= slots && trb < tm && nk >= 2) {
+        const int units = trb * tn;
+        int nsplit = std::min(nk, std::max(1, slots / units));
+        const int kps = (nk + nsplit - 1) / nsplit;
+        nsplit = (nk + kps - 1) / kps;
+        const int Mm = (tm - trb) * GBM, Mt = M - Mm;
+        const size_t part = (size_t)Mt * N;
+        if (nsplit >= 2 && (size_t)nsplit * part <= ws_elems) {
+            hipLaunchKernelGGL((gemm_mfma_kernel<TM, TA, TC>), dim3((tm - trb) * tn, 1), dim3(256), 0, s, Mm, N, K,
+                               nk, alpha, A, lda, B, ldb, beta, C, ldc, (size_t)0);
+            RTE_CHECK_LAUNCH();
+            hipLaunchKernelGGL((gemm_mfma_kernel<TM, TA, TM>), dim3(units, nsplit), dim3(256), 0, s, Mt, N, K, kps,
+                               (TM)1, A + Mm, lda, B, ldb, (TM)0, ws, Mt, part);
+            RTE_CHECK_LAUNCH();
+            const int g = (int)std::min<size_t>((part + 255) / 256, 4096);
+            hipLaunchKernelGGL((gemm_sum_parts_kernel<TM, TC>), dim3(g), dim3(256), 0, s, Mt, N, nsplit,
+                               (const TM*)ws, alpha, beta, C + Mm, ldc);
+            RTE_CHECK_LAUNCH();
+            return;
+        }
+    }
+    hipLaunchKernelGGL((gemm_mfma_kernel<TM, TA, TC>), dim3(tiles, 1), dim3(256), 0, s, M, N, K, nk, alpha, A, lda,
+                       B, ldb, beta, C, ldc, (size_t)0);
     RTE_CHECK_LAUNCH();
+}
+}  // namespace
+
+void gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, const double* B, int ldb, double beta,
+              double* C, int ldc, hipStream_t s, double* ws, size_t ws_elems) {
+    gemm_mfma<double, double, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems, s);
+}
+
+void gemm_f32(int M, int N, int K, float alpha, const double* A, int lda, const float* B, int ldb, float beta,
+              double* C, int ldc, hipStream_t s, float* ws, size_t ws_elems) {
+    gemm_mfma<float, double, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems, s);
+}
+
+void gemm_f32(int M, int N, int K, float alpha, const float* A, int lda, const float* B, int ldb, float beta,
+              double* C, int ldc, hipStream_t s, float* ws, size_t ws_elems) {
+    gemm_mfma<float, float, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems, s);
 }
 
 void cvt_f64_bf16(const double* x, uint16_t* y, size_t n, hipStream_t s) {

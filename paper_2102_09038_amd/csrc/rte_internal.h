@@ -156,7 +156,7 @@ struct Handle {
 
     // ---- BF16 copies (mixed precision)
     bool have_mixed = false;
-    DBuf<uint16_t> Sp_bf, Sm_bf, Hodd_bf;
+    DBuf<float> Sp_f, Sm_f;        // FP32 S+ and S- (mixed-precision scatter GEMMs)
     DBuf<uint16_t> Gc_bf;          // condensed transport matrix as BF16 parts [G_hi; G_lo]
     size_t e0_stride32 = 0;
     DBuf<float> L0f, L0Uf;         // FP32 copies of the banded E_0 factors ([nS * e0_stride32])
@@ -212,9 +212,19 @@ namespace k {
 void hg_scatter(const double* pts, const double* wts, int nS, int Q, double g, double* Sp,
                 double* Sm, hipStream_t s);
 // C[MxN] = alpha * A[MxK] (col-major, lda) * B (row-major KxN, ldb) + beta * C (col-major).
+// ws (nullable, ws_elems elements, contents overwritten): scratch that lets a lightly loaded
+// last round of tiles be split over K.
 void gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, const double* B,
-              int ldb, double beta, double* C, int ldc, hipStream_t s);
-// BF16 inputs, FP32 accumulate; A col-major bf16, B row-major bf16, C col-major f32.
+              int ldb, double beta, double* C, int ldc, hipStream_t s, double* ws = nullptr,
+              size_t ws_elems = 0);
+// The same in FP32 MFMA arithmetic (FP32 products, FP32 accumulation); an FP64 A is rounded
+// to FP32 as it is loaded, an FP64 C receives the FP32 result.
+void gemm_f32(int M, int N, int K, float alpha, const double* A, int lda, const float* B, int ldb,
+              float beta, double* C, int ldc, hipStream_t s, float* ws = nullptr, size_t ws_elems = 0);
+void gemm_f32(int M, int N, int K, float alpha, const float* A, int lda, const float* B, int ldb,
+              float beta, double* C, int ldc, hipStream_t s, float* ws = nullptr, size_t ws_elems = 0);
+// BF16 inputs, FP32 accumulate; A row-major bf16 (k contiguous, lda), B column-major bf16
+// (k contiguous, ldb), C col-major f32.
 void gemm_bf16(int M, int N, int K, float alpha, const uint16_t* A, int lda, const uint16_t* B,
                int ldb, float beta, float* C, int ldc, hipStream_t s);
 void cvt_f64_bf16(const double* x, uint16_t* y, size_t n, hipStream_t s);

@@ -28,7 +28,7 @@ double* ws(Handle* h, int id) {
 }
 
 // ----------------------------------------------------------------------------- timers
-enum ProfKind { P_E0 = 0, P_GEMM = 1, P_GEMM_BF16 = 2, P_GEMM_SCATTER = 3 };
+enum ProfKind { P_E0 = 0, P_GEMM = 1, P_GEMM_BF16 = 2, P_GEMM_SCATTER = 3, P_GEMM_SCATTER_F32 = 4 };
 
 hipEvent_t take_event(Handle* h) {
     if (h->evpool.empty()) {
@@ -80,6 +80,11 @@ void collect_profile(Handle* h, rte_solve_info* inf) {
             inf->t_scatter += ms * 1e-3;
             inf->n_scatter += 1;
             inf->scatter_flops += r.flops;
+        }
+        else if (r.kind == P_GEMM_SCATTER_F32) {
+            inf->t_scatter_f32 += ms * 1e-3;
+            inf->n_scatter_f32 += 1;
+            inf->scatter_f32_flops += r.flops;
         }
         else { inf->t_gemm_bf16 += ms * 1e-3; inf->n_gemm_bf16 += 1; inf->gemm_bf16_flops += r.flops; }
         h->evpool.push_back(r.a);
@@ -202,9 +207,19 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
 void residual_like(Handle* h, const rte_solve_opts* o, const double* X, const double* q0, double* Y,
                    double tol, hipStream_t s, int64_t* pcg, bool lowp) {
     double* G = ws(h, W_EG);
-    {
-        Timed t(h, s, P_GEMM_SCATTER, 2.0 * h->nRp * (double)h->nS * h->nS);
-        k::gemm_f64(h->nRp, h->nS, h->nS, 1.0, X, h->nRp, h->Sp.p, h->nS, 0.0, G, h->nRp, s);
+    // the odd workspace is free until apply_E_core: scratch for the GEMM's split last round
+    double* scratch = ws(h, W_OZ);
+    const size_t nscratch = (size_t)h->nRm * h->nSm;
+    const double flops = 2.0 * h->nRp * (double)h->nS * h->nS;
+    if (lowp) {
+        // inside the preconditioner: FP32 MFMA arithmetic on the FP32 copy of S+
+        if (!h->Sp_f.p) fail(RTE_E_ARG, "mixed precision needs a handle assembled with mixed != 0");
+        Timed t(h, s, P_GEMM_SCATTER_F32, flops);
+        k::gemm_f32(h->nRp, h->nS, h->nS, 1.0f, X, h->nRp, h->Sp_f.p, h->nS, 0.0f, G, h->nRp, s,
+                    reinterpret_cast<float*>(scratch), 2 * nscratch);
+    } else {
+        Timed t(h, s, P_GEMM_SCATTER, flops);
+        k::gemm_f64(h->nRp, h->nS, h->nS, 1.0, X, h->nRp, h->Sp.p, h->nS, 0.0, G, h->nRp, s, scratch, nscratch);
     }
     apply_E_core(h, o, X, G, q0, Y, tol, s, pcg, lowp);
 }

@@ -53,7 +53,8 @@ class rte_solve_info(C.Structure):
                 ("n_e0inv", C.c_int64), ("t_gemm", C.c_double), ("n_gemm", C.c_int64),
                 ("gemm_flops", C.c_double), ("t_gemm_bf16", C.c_double), ("n_gemm_bf16", C.c_int64),
                 ("gemm_bf16_flops", C.c_double), ("t_scatter", C.c_double), ("n_scatter", C.c_int64),
-                ("scatter_flops", C.c_double)]
+                ("scatter_flops", C.c_double), ("t_scatter_f32", C.c_double), ("n_scatter_f32", C.c_int64),
+                ("scatter_f32_flops", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

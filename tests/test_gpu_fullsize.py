@@ -102,3 +102,41 @@ def test_solves_full_size(realistic):
     assert res["mixed"][1] <= 1e-6
     Uf, Um = res["fp64"][0], res["mixed"][0]
     assert float(torch.linalg.norm(Um - Uf) / torch.linalg.norm(Uf)) < 1e-6
+
+
+def test_scatter_gemm_full_size(realistic):
+    """K+ X = Ms+ X S+ and K- X = Ms- X S- at full size, in FP64 and FP32 MFMA arithmetic, on
+    sampled output rows (the first and last rows included: at this size the last, lightly
+    loaded round of GEMM tiles runs split over K).  S+ and S- are the handle's own matrices,
+    whose rows test_scattering_rows checks against the oracle; the reference products are
+    numpy FP64.  FP32 bound: inputs rounded to FP32 (2^-24 relative) and sums of n_S terms
+    accumulated in FP32 give about sqrt(n_S) 2^-24 ~ 2e-6 relative; 2e-5 is asserted."""
+    from paper_2102_09038_amd import rte
+    inst, D, h = realistic
+    nS, nSm = D.nS, 3 * D.nS
+    rng = np.random.default_rng(41)
+    Sp = h.get_array(rte.ARRAY_SP, (nS, nS))
+    Sm = h.get_array(rte.ARRAY_SM, (nSm, nSm))
+    for parity, nR, S in ((1, D.nRp, Sp), (-1, D.nRm, Sm)):
+        n = S.shape[0]
+        X = rng.standard_normal((nR, n))
+        rows = np.r_[0:100, nR // 2:nR // 2 + 100, nR - 300:nR]
+        if parity == 1:
+            ref = (D.Ms[rows] @ X) @ S
+        else:
+            ref = D.ms[rows, None] * (X[rows] @ S)
+        Xd = to_dev(X)
+        Y = torch.empty_like(Xd)
+        h.apply_scatter(parity, Xd, Y)
+        Y32 = torch.empty_like(Xd)
+        h.apply_scatter(parity, Xd.float().contiguous(), Y32, dtype_in=rte.RTE_DT_F32, dtype_out=rte.RTE_DT_F64)
+        torch.cuda.synchronize()
+        got = Y.cpu().numpy().T[rows]
+        got32 = Y32.cpu().numpy().T[rows]
+        e64 = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        e32 = np.linalg.norm(got32 - ref) / np.linalg.norm(ref)
+        tail = slice(len(rows) - 300, len(rows))
+        et = np.linalg.norm(got[tail] - ref[tail]) / np.linalg.norm(ref[tail])
+        print(f"K{'+' if parity == 1 else '-'} on sampled rows: FP64 {e64:.2e} (last rows {et:.2e}), FP32 MFMA {e32:.2e}")
+        assert e64 < 1e-12 and et < 1e-12
+        assert e32 < 2e-5

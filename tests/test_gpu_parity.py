@@ -111,6 +111,29 @@ def test_scatter(case):
     assert rel(from_dev(Yv), ops.K_odd(V)) < 1e-12
 
 
+def test_scatter_fp32(case):
+    """FP32 MFMA scatter GEMMs (the preconditioner's K+ in mixed precision) against the
+    oracle's FP64 products: inputs rounded to FP32 and FP32 sums of n_S terms stay within
+    about sqrt(n_S) 2^-24 relative; 2e-5 is asserted.  Both output dtypes are checked."""
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    rng = np.random.default_rng(12)
+    for parity, X, ref in ((1, rng.standard_normal((D.nRp, D.nS)), None),
+                           (-1, rng.standard_normal((D.nRm, 3 * D.nS)), None)):
+        ref = ops.K_even(X) if parity == 1 else ops.K_odd(X)
+        Xf = to_dev(X).float().contiguous()
+        Y64 = torch.empty(Xf.shape, dtype=torch.float64, device="cuda")
+        Y32 = torch.empty(Xf.shape, dtype=torch.float32, device="cuda")
+        h.apply_scatter(parity, Xf, Y64, dtype_in=rte.RTE_DT_F32, dtype_out=rte.RTE_DT_F64)
+        h.apply_scatter(parity, Xf, Y32, dtype_in=rte.RTE_DT_F32, dtype_out=rte.RTE_DT_F32)
+        e64 = rel(from_dev(Y64), ref)
+        e32 = rel(from_dev(Y32.double()), ref)
+        print(f"[{name}] K{'+' if parity == 1 else '-'} FP32 MFMA: {e64:.2e} (FP32 out {e32:.2e})")
+        assert e64 < 2e-5 and e32 < 2e-5
+    with pytest.raises(rte.RteError):
+        h.apply_scatter(1, Xf, Y64, dtype_in=rte.RTE_DT_BF16, dtype_out=rte.RTE_DT_F32)
+
+
 ODD = {"pcg": 0, "exact": 1, "condensed": 2}
 
 
