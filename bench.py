@@ -370,6 +370,14 @@ def main():
     h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)
     t_assemble = time.perf_counter() - ta
     d = h.dims
+    # band layout of the E_0 factors: every shape that holds the band timed on the device,
+    # the fastest kept (setup, outside the timed solves)
+    ta = time.perf_counter()
+    tune = h.autotune()
+    t_tune = time.perf_counter() - ta
+    print(f"[autotune] {t_tune:.2f} s: " + "; ".join(
+        f"{k} default {v['default']} chosen {v['chosen']} timed " +
+        ", ".join(f"{hp}:{ms:.3f}ms" for hp, ms in v["timed"]) for k, v in tune.items()), file=sys.stderr, flush=True)
     if args.only == "kernels":
         kernel_passes(h, inst, torch, rte)
         return
@@ -427,6 +435,10 @@ def main():
                    "odd_solver": "condensed", "e0_solver": "banded", "e0_band": e0_bw, "precision": "fp64"},
         "iters": [i.iters for i in infos], "rel_resid": [i.rel_resid for i in infos],
         "t_assemble_s": t_assemble,
+        "band_layout": {k: {"default": v["default"], "chosen": v["chosen"],
+                            "timed_ms": {f"{hp[0]}x{hp[1]}": ms for hp, ms in v["timed"]}}
+                        for k, v in tune.items()},
+        "t_autotune_s": t_tune,
         "roofline": dominant, "roofline_other": other,
         "scatter_gemm": {"bound": "mfma", "achieved": scatter_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": scatter_tf / FP64_MFMA_PEAK_TFLOPS, "kernel": "gemm_mfma_kernel<double> (U S+, eq. tpmv; last round split over K)",

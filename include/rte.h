@@ -47,8 +47,10 @@ typedef enum rte_status {
 
 typedef enum rte_precision {
     RTE_FP64 = 0,         /* every step in FP64                                        */
-    RTE_MIXED = 1         /* scattering GEMMs BF16 in / FP32 accumulate, CG vectors FP32;
-                             outer residual, all dot products and the coarse solve FP64 */
+    RTE_MIXED = 1         /* inside the preconditioner: condensed transport GEMM with BF16
+                             inputs and FP32 accumulation, scatter GEMM in FP32 MFMA, E_0
+                             factors FP32; outer residual, all dot products and the coarse
+                             solve FP64                                                  */
 } rte_precision;
 
 typedef enum rte_dtype { RTE_DT_F64 = 0, RTE_DT_F32 = 1, RTE_DT_BF16 = 2 } rte_dtype;
@@ -286,6 +288,39 @@ rte_status rte_batch_set_graphs(rte_batch* b, int32_t use_graphs);
 rte_status rte_batch_usage(const rte_batch* b, int32_t* n_live, int32_t* n_done, size_t* used_bytes);
 
 rte_status rte_batch_destroy(rte_batch* b);
+
+/* ------------------------------------------------------------------ autotuning
+ * Layouts of the banded E_0 factors: a factor row block holds G = H P groups of 16 bytes,
+ * H the register ring depth of the band solve and P its phase count, over the menu of shapes
+ * the solve kernel is built for (H, P) in {(9,1) (17,1) (33,1) (9,2) (17,2) (33,2) (17,3)
+ * (33,3) (33,4)}.  Assembly lays them out in the shape with the least padding; the
+ * autotuner times the E_0^{-1} launch (all n_S+ directions, HIP events on hip_stream) in
+ * every shape that holds the band, re-laying the factors out on the device, and keeps the
+ * fastest.  The results do not depend on the layout (padding entries are zero and every
+ * product is summed in the same order).
+ *
+ * Choices are cached per process by (n_R+, band width, n_S+, element size): a handle whose
+ * key is cached takes the cached shape without timing unless flags has RTE_TUNE_FORCE.
+ * Both precisions present in the handle are tuned (the FP64 factors are absent after
+ * assembly with mixed = 2).  While a candidate is timed the device holds one more copy of
+ * the factors of that precision.  The handle must not be in use (no solve, no batch slot)
+ * during the call.  Blocking.  RTE_E_ARG if the handle has no banded E_0 factors. */
+#define RTE_TUNE_FORCE 1
+typedef struct rte_tune_report {
+    int32_t n_cand[2];           /* candidates timed: [0] FP64 factors, [1] FP32 factors    */
+    int32_t H[2][9], P[2][9];    /* their shapes                                            */
+    double ms[2][9];             /* average E_0^{-1} launch time of each candidate          */
+    int32_t chosen_H[2], chosen_P[2];  /* the shape in place on return (0: precision absent) */
+    int32_t default_H[2], default_P[2];/* the shape assembly chose                           */
+    int32_t from_cache[2];       /* 1: taken from the per-process cache, nothing timed      */
+} rte_tune_report;
+rte_status rte_autotune(rte_handle* h, int32_t flags, void* hip_stream, rte_tune_report* report);
+
+/* Lay the banded E_0 factors of one precision (RTE_FP64: the FP64 factors, RTE_MIXED: the
+ * FP32 ones) out in the shape (H, P) of the menu above, without timing.  RTE_E_ARG if the
+ * shape is not in the menu, cannot hold the band, or the factors are absent.  Same
+ * conditions as rte_autotune; blocking. */
+rte_status rte_set_band_layout(rte_handle* h, int32_t precision, int32_t H, int32_t P, void* hip_stream);
 
 /* Thread-local text of the last non-OK status ("" if none). */
 const char* rte_last_error(void);

@@ -946,6 +946,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         if (k::band_groups(h.sbw, 2) == 0 || k::band_groups(h.sbw, 4) == 0)
             fail(RTE_E_ARG, "E_0 band too wide for the band solve");
         h.e0_stride = k::band_blk_size(nRp, h.sbw, 2);
+        h.e0_g64 = (int)k::band_groups(h.sbw, 2);
         h.L0.alloc(h.e0_stride * nS);
         h.L0U.alloc(h.e0_stride * nS);
         DBuf<int> bad(1);
@@ -978,10 +979,11 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         }
         if (h.have_e0_banded) {
             h.e0_stride32 = k::band_blk_size(nRp, h.sbw, 4);
+            h.e0_g32 = (int)k::band_groups(h.sbw, 4);
             h.L0f.alloc(h.e0_stride32 * nS);
             h.L0Uf.alloc(h.e0_stride32 * nS);
-            k::band_to_f32(h.L0.p, h.L0f.p, nRp, h.sbw, nS, h.e0_stride, h.e0_stride32, s);
-            k::band_to_f32(h.L0U.p, h.L0Uf.p, nRp, h.sbw, nS, h.e0_stride, h.e0_stride32, s);
+            k::band_to_f32(h.L0.p, h.L0f.p, nRp, h.sbw, nS, h.e0_stride, h.e0_stride32, s, h.e0_g64, h.e0_g32);
+            k::band_to_f32(h.L0U.p, h.L0Uf.p, nRp, h.sbw, nS, h.e0_stride, h.e0_stride32, s, h.e0_g64, h.e0_g32);
             if (o->mixed == 2) {
                 RTE_HIP(hipStreamSynchronize(s));
                 h.L0.release();

@@ -233,6 +233,22 @@ rte_status rte_batch_set_graphs(rte_batch* b, int32_t use_graphs) {
     });
 }
 
+rte_status rte_autotune(rte_handle* hh, int32_t flags, void* hip_stream, rte_tune_report* report) {
+    return guarded([&] {
+        if (!hh) rte::fail(RTE_E_ARG, "null handle");
+        rte::autotune(reinterpret_cast<rte::Handle*>(hh), flags, static_cast<hipStream_t>(hip_stream), report);
+        return RTE_OK;
+    });
+}
+
+rte_status rte_set_band_layout(rte_handle* hh, int32_t precision, int32_t H, int32_t P, void* hip_stream) {
+    return guarded([&] {
+        if (!hh) rte::fail(RTE_E_ARG, "null handle");
+        rte::set_band_layout(reinterpret_cast<rte::Handle*>(hh), precision, H, P, static_cast<hipStream_t>(hip_stream));
+        return RTE_OK;
+    });
+}
+
 rte_status rte_batch_usage(const rte_batch* b, int32_t* n_live, int32_t* n_done, size_t* used_bytes) {
     return guarded([&] {
         if (!b) rte::fail(RTE_E_ARG, "null batch");

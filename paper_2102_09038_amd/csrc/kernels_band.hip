@@ -414,23 +414,43 @@ int pow2_at_least(int v) {
     return w;
 }
 
-// FP64 blocked factor (VEC 2) -> FP32 blocked factor (VEC 4) of the same band
+// FP64 blocked factor (VEC 2, G64 groups) -> FP32 blocked factor (VEC 4, G32 groups) of
+// the same band
 __global__ void band_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst, int n, int bw,
-                                   int nsys, size_t stride64, size_t stride32) {
-    const size_t per = k::band_blk_size(n, bw, 4);
+                                   int nsys, size_t stride64, size_t stride32, int G64, int G32) {
+    const size_t per = k::band_blk_size_g(n, G32, 4);
     const size_t total = per * nsys;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
         const size_t sys = e / per, q = e % per;
-        // q = ((B G4 + g) 64 + lane) 4 + k
+        // q = ((B G32 + g) 64 + lane) 4 + k
         const int k = (int)(q & 3), lane = (int)((q >> 2) & 63);
         const size_t bg = q >> 8;
-        const int G4 = (int)k::band_groups(bw, 4);
-        const int B = (int)(bg / G4), g = (int)(bg % G4);
+        const int B = (int)(bg / G32), g = (int)(bg % G32);
         const int t = 4 * g + k;
         const int r = 64 * B + lane;
         float v = 0.0f;
-        if (t <= bw && r < n) v = (float)src[stride64 * sys + k::band_blk_index(r, t, bw, 2)];
+        if (t <= bw && r < n) v = (float)src[stride64 * sys + k::band_blk_index_g(r, t, G64, 2)];
         dst[stride32 * sys + q] = v;
+    }
+}
+
+// the same band from a layout of Gs groups to one of Gd groups, VEC entries per group
+template <typename T, int VEC>
+__global__ void band_relayout_kernel(const T* __restrict__ src, int Gs, T* __restrict__ dst, int Gd, int n, int bw,
+                                     int nsys, size_t stride_src, size_t stride_dst) {
+    const size_t per = k::band_blk_size_g(n, Gd, VEC);
+    const size_t total = per * nsys;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t sys = e / per, q = e % per;
+        // q = ((B Gd + g) 64 + lane) VEC + k
+        const int k = (int)(q % VEC), lane = (int)((q / VEC) & 63);
+        const size_t bg = q / (64 * VEC);
+        const int B = (int)(bg / Gd), g = (int)(bg % Gd);
+        const int t = VEC * g + k;
+        const int r = 64 * B + lane;
+        T v = (T)0;
+        if (t <= bw && r < n) v = src[stride_src * sys + k::band_blk_index_g(r, t, Gs, VEC)];
+        dst[stride_dst * sys + q] = v;
     }
 }
 
@@ -456,21 +476,26 @@ void band_launch_hp(const FT* BL, const FT* BU, int n, int bw, int nsys, size_t 
 
 // ring: the rows a block reads (bw before it, or after it, its own 64 and up to a group of
 // padding) fit in W; W >= 256 also covers the window of ring reads ahead
-int band_ring(int bw, int vec) {
-    const BandShape sh = band_shape(bw, vec);
-    return std::max(256, pow2_at_least(std::max(bw + 64 + vec * 8, sh.H * sh.P * vec)));
+int band_ring(int bw, int vec, int G) {
+    return std::max(256, pow2_at_least(std::max(bw + 64 + vec * 8, G * vec)));
 }
 size_t band_lds(int W) { return (size_t)(2 * W + 64 * 65) * 8; }
 
+bool band_layout_ok(int bw, int vec, int G) {
+    const BandShape sh = band_shape_of_groups(G);
+    return sh.H > 0 && G >= (bw + vec) / vec && band_lds(band_ring(bw, vec, G)) <= (size_t)kBandMaxLds;
+}
+
 template <typename FT>
 void band_solve_launch(const FT* BL, const FT* BU, int n, int bw, int nsys, size_t stride_sys, const double* b,
-                       double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
+                       double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G) {
     if (nsys <= 0 || n <= 0) return;
     constexpr int VEC = 16 / (int)sizeof(FT);
-    const BandShape sh = band_shape(bw, VEC);
-    const int W = band_ring(bw, VEC);
+    if (G == 0) G = (int)band_groups(bw, VEC);
+    if (!band_layout_ok(bw, VEC, G)) fail(RTE_E_ARG, "band too wide for the solve kernel");
+    const BandShape sh = band_shape_of_groups(G);
+    const int W = band_ring(bw, VEC, G);
     const size_t lds = band_lds(W);
-    if (lds > (size_t)kBandMaxLds) fail(RTE_E_ARG, "band too wide for the solve window");
 #define RTE_BAND_CASE(HH, PP)                                                                             \
     if (sh.H == HH && sh.P == PP) {                                                                       \
         band_launch_hp<FT, HH, PP>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, W, lds, s); \
@@ -498,10 +523,10 @@ void band_group_launch_hp(const BandJob* jobs, int njobs, int nwg, size_t lds, h
 void band_group_plan(std::vector<BandJob>& jobs, bool f32, BandGroupPlan& plan, hipStream_t s) {
     const int vec = f32 ? 4 : 2;
     for (auto& j : jobs) {
-        const BandShape sh = band_shape(j.bw, vec);
-        if (sh.H == 0) fail(RTE_E_ARG, "band too wide for the solve kernel");
-        j.W = band_ring(j.bw, vec);
-        if (band_lds(j.W) > (size_t)kBandMaxLds) fail(RTE_E_ARG, "band too wide for the solve window");
+        if (j.G == 0) j.G = (int)band_groups(j.bw, vec);
+        if (!band_layout_ok(j.bw, vec, j.G)) fail(RTE_E_ARG, "band too wide for the solve kernel");
+        const BandShape sh = band_shape_of_groups(j.G);
+        j.W = band_ring(j.bw, vec, j.G);
         j.first = sh.H * 16 + sh.P;                 // sort key for now
     }
     std::stable_sort(jobs.begin(), jobs.end(), [](const BandJob& a, const BandJob& b) { return a.first < b.first; });
@@ -567,20 +592,39 @@ void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, 
 }
 
 void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
-                    const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
-    band_solve_launch<double>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, s);
+                    const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G) {
+    band_solve_launch<double>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, s, G);
 }
 
 void band_solve_blk_f32(const float* BL, const float* BU, int n, int bw, int nsys, size_t stride_sys,
-                        const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s) {
-    band_solve_launch<float>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, s);
+                        const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G) {
+    band_solve_launch<float>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, s, G);
 }
 
 void band_to_f32(const double* src, float* dst, int n, int bw, int nsys, size_t stride64, size_t stride32,
-                 hipStream_t s) {
-    const size_t total = band_blk_size(n, bw, 4) * nsys;
+                 hipStream_t s, int G64, int G32) {
+    const size_t total = band_blk_size_g(n, G32, 4) * nsys;
     const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(band_to_f32_kernel, dim3(blocks), dim3(256), 0, s, src, dst, n, bw, nsys, stride64, stride32);
+    hipLaunchKernelGGL(band_to_f32_kernel, dim3(blocks), dim3(256), 0, s, src, dst, n, bw, nsys, stride64, stride32,
+                       G64, G32);
+    RTE_CHECK_LAUNCH();
+}
+
+void band_relayout(const double* src, int Gsrc, double* dst, int Gdst, int n, int bw, int nsys, size_t stride_src,
+                   size_t stride_dst, hipStream_t s) {
+    const size_t total = band_blk_size_g(n, Gdst, 2) * nsys;
+    const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL((band_relayout_kernel<double, 2>), dim3(blocks), dim3(256), 0, s, src, Gsrc, dst, Gdst, n, bw,
+                       nsys, stride_src, stride_dst);
+    RTE_CHECK_LAUNCH();
+}
+
+void band_relayout(const float* src, int Gsrc, float* dst, int Gdst, int n, int bw, int nsys, size_t stride_src,
+                   size_t stride_dst, hipStream_t s) {
+    const size_t total = band_blk_size_g(n, Gdst, 4) * nsys;
+    const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL((band_relayout_kernel<float, 4>), dim3(blocks), dim3(256), 0, s, src, Gsrc, dst, Gdst, n, bw,
+                       nsys, stride_src, stride_dst);
     RTE_CHECK_LAUNCH();
 }
 

@@ -53,55 +53,79 @@ void scale_eigbasis(const Handle* h, double* C, hipStream_t s);
 void coarse_project(const Handle* h, const double* T, double* rhs, hipStream_t s);
 // Blocked band layout of a factor with band width bw (kernels_band.hip): rows in blocks of
 // 64, band offsets t = 0..bw in groups of vec consecutive entries (vec = 16 bytes / element);
-// a row block holds H P groups (the solve kernel's ring depth H times its phase count P,
-// chosen here so that H P >= ceil((bw+1)/vec) with little padding), zero past t = bw.
+// a row block holds G = H P groups (the solve kernel's ring depth H times its phase count P,
+// with H P >= ceil((bw+1)/vec)), zero past t = bw.  The shapes the solve kernel is built for
+// have distinct H P, so a layout's group count G names its shape.  band_shape picks the
+// default (little padding, then a deeper ring); the autotuner may choose another.
 struct BandShape {
     int H, P;
 };
+constexpr int kBandShapes = 9;
+__host__ __device__ inline BandShape band_shape_at(int k) {
+    const int hs[kBandShapes] = {9, 17, 33, 9, 17, 33, 17, 33, 33};
+    const int ps[kBandShapes] = {1, 1, 1, 2, 2, 2, 3, 3, 4};
+    return BandShape{hs[k], ps[k]};
+}
 __host__ __device__ inline BandShape band_shape(int bw, int vec) {
     const int g = (bw + vec) / vec;
-    const int hs[9] = {9, 17, 33, 9, 17, 33, 17, 33, 33};
-    const int ps[9] = {1, 1, 1, 2, 2, 2, 3, 3, 4};
     BandShape best{0, 0};
     int waste = 1 << 30;
-    for (int k = 0; k < 9; ++k) {
-        const int cap = hs[k] * ps[k];
+    for (int k = 0; k < kBandShapes; ++k) {
+        const BandShape sh = band_shape_at(k);
+        const int cap = sh.H * sh.P;
         if (cap < g) continue;
         // prefer little padding, then a deeper ring
-        const int w = (cap - g) * 4 - hs[k];
-        if (w < waste) { waste = w; best = BandShape{hs[k], ps[k]}; }
+        const int w = (cap - g) * 4 - sh.H;
+        if (w < waste) { waste = w; best = sh; }
     }
     return best;
 }
+// the shape of a layout with G groups per row block ({0, 0}: none)
+__host__ __device__ inline BandShape band_shape_of_groups(int G) {
+    for (int k = 0; k < kBandShapes; ++k) {
+        const BandShape sh = band_shape_at(k);
+        if (sh.H * sh.P == G) return sh;
+    }
+    return BandShape{0, 0};
+}
+// default group count (0 if the band is too wide for every shape)
 __host__ __device__ inline size_t band_groups(int bw, int vec) {
     const BandShape sh = band_shape(bw, vec);
     return (size_t)sh.H * sh.P;
 }
-__host__ __device__ inline size_t band_blk_index(int r, int t, int bw, int vec) {
-    return (((size_t)(r >> 6) * band_groups(bw, vec) + t / vec) * 64 + (r & 63)) * vec + t % vec;
+__host__ __device__ inline size_t band_blk_index_g(int r, int t, int G, int vec) {
+    return (((size_t)(r >> 6) * G + t / vec) * 64 + (r & 63)) * vec + t % vec;
 }
-// number of elements of one system's factor in that layout (0 if the band is too wide)
+__host__ __device__ inline size_t band_blk_size_g(int n, int G, int vec) {
+    return (size_t)((n + 63) / 64) * G * 64 * vec;
+}
+// the same in the default layout
+__host__ __device__ inline size_t band_blk_index(int r, int t, int bw, int vec) {
+    return band_blk_index_g(r, t, (int)band_groups(bw, vec), vec);
+}
+// number of elements of one system's factor in the default layout (0 if the band is too wide)
 __host__ __device__ inline size_t band_blk_size(int n, int bw, int vec) {
-    return (size_t)((n + 63) / 64) * band_groups(bw, vec) * 64 * vec;
+    return band_blk_size_g(n, (int)band_groups(bw, vec), vec);
 }
 // x = L^{-T} L^{-1} b for nsys systems with blocked band factors BL (rows of L) and BU
-// (rows of L^T) (kernels_band.hip); b and x are read / written at iperm[band row] when
-// iperm is given
+// (rows of L^T) in the layout of G groups per row block (G = 0: the default layout)
+// (kernels_band.hip); b and x are read / written at iperm[band row] when iperm is given
 void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
-                    const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s);
+                    const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G = 0);
 // same with FP32 factors (the reduced-precision preconditioner); FP64 vectors and sums
 void band_solve_blk_f32(const float* BL, const float* BU, int n, int bw, int nsys, size_t stride_sys,
-                        const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s);
+                        const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G = 0);
 // One job of a grouped band solve: nsys systems with factors at BL/BU + stride_sys * sys (FP64 or
-// FP32 elements, per launch) and right-hand sides / solutions in band order at
-// b/x + stride_vec * sys.  W and first are filled in by band_group_plan.
+// FP32 elements, per launch) in the layout of G groups per row block (0: default) and
+// right-hand sides / solutions in band order at b/x + stride_vec * sys.  W and first are
+// filled in by band_group_plan.
 struct BandJob {
     const void* BL;
     const void* BU;
     const double* b;
     double* x;
     size_t stride_sys, stride_vec;
-    int n, bw, nsys, W, first;
+    int n, bw, nsys, W, first, G;
 };
 // the launches of a set of jobs, one per band shape, and the jobs in device memory
 struct BandGroupPlan {
@@ -117,9 +141,16 @@ struct BandGroupPlan {
 void band_group_plan(std::vector<BandJob>& jobs, bool f32, BandGroupPlan& plan, hipStream_t s);
 // all jobs' solves, one launch per band shape
 void band_group_run(const BandGroupPlan& plan, hipStream_t s);
-// FP64 blocked factors -> FP32 blocked factors (their own layout, 4 entries per group)
+// FP64 blocked factors (G64 groups per row block) -> FP32 blocked factors (G32 groups of 4)
 void band_to_f32(const double* src, float* dst, int n, int bw, int nsys, size_t stride64, size_t stride32,
-                 hipStream_t s);
+                 hipStream_t s, int G64, int G32);
+// the same factors from a layout of Gsrc groups to one of Gdst groups (same element type)
+void band_relayout(const double* src, int Gsrc, double* dst, int Gdst, int n, int bw, int nsys,
+                   size_t stride_src, size_t stride_dst, hipStream_t s);
+void band_relayout(const float* src, int Gsrc, float* dst, int Gdst, int n, int bw, int nsys,
+                   size_t stride_src, size_t stride_dst, hipStream_t s);
+// whether the solve kernel can run a band of width bw in the layout of G groups of vec
+bool band_layout_ok(int bw, int vec, int G);
 // lower band (row-major, band[r (bw+1) + bw + c - r]) -> lower triangle of a dense
 // column-major n x n matrix; and the copy of that lower triangle to the upper one
 void band_to_dense(const double* band, int n, int bw, double* A, hipStream_t s);

@@ -152,6 +152,7 @@ struct Handle {
     // ---- banded E_0 (RTE_E0_BANDED): one blocked band factor per direction
     bool have_e0_banded = false;
     size_t e0_stride = 0;
+    int e0_g64 = 0;                // groups per row block of the FP64 factors' layout
     DBuf<double> L0, L0U;          // [nS * e0_stride], rows of L and of L^T
 
     // ---- BF16 copies (mixed precision)
@@ -159,6 +160,7 @@ struct Handle {
     DBuf<float> Sp_f, Sm_f;        // FP32 S+ and S- (mixed-precision scatter GEMMs)
     DBuf<uint16_t> Gc_bf;          // condensed transport matrix as BF16 parts [G_hi; G_lo]
     size_t e0_stride32 = 0;
+    int e0_g32 = 0;                // groups per row block of the FP32 factors' layout
     DBuf<float> L0f, L0Uf;         // FP32 copies of the banded E_0 factors ([nS * e0_stride32])
 
     // ---- workspace (allocated lazily, sized for one solve)
@@ -203,6 +205,9 @@ void batch_destroy(Batch* B);
 int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, double* U, hipStream_t s);
 int batch_step(Batch* B, int outer_iters, hipStream_t s);
 void batch_set_graphs(Batch* B, bool on);
+// band layout autotuning of the E_0 factors (autotune.cpp)
+void autotune(Handle* h, int flags, hipStream_t s, rte_tune_report* rep);
+void set_band_layout(Handle* h, int precision, int H, int P, hipStream_t s);
 int batch_poll(Batch* B, int max_out, int32_t* slots, rte_solve_info* infos, int32_t* statuses);
 void batch_usage(const Batch* B, int32_t* n_live, int32_t* n_done, size_t* used_bytes);
 

@@ -240,10 +240,10 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
             Timed t(h, s, P_E0);
             if (lowp && h->L0f.p)
                 k::band_solve_blk_f32(h->L0f.p, h->L0Uf.p, h->nRp, h->sbw, h->nS, h->e0_stride32, Xb, Yb,
-                                      (size_t)h->nRp, nullptr, s);
+                                      (size_t)h->nRp, nullptr, s, h->e0_g32);
             else
                 k::band_solve_blk(h->L0.p, h->L0U.p, h->nRp, h->sbw, h->nS, h->e0_stride, Xb, Yb, (size_t)h->nRp,
-                                  nullptr, s);
+                                  nullptr, s, h->e0_g64);
         }
         k::permute_cols(h->iperm.p, h->nRp, h->nS, Yb, Y, false, s);
         return;

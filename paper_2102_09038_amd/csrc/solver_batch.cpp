@@ -91,6 +91,7 @@ void rebuild_plan(Batch* B, hipStream_t s) {
         j.b = ws(h, W_BB);
         j.x = ws(h, W_BX);
         j.stride_sys = f32 ? h->e0_stride32 : h->e0_stride;
+        j.G = f32 ? h->e0_g32 : h->e0_g64;
         j.stride_vec = (size_t)h->nRp;
         j.n = h->nRp;
         j.bw = h->sbw;

@@ -46,6 +46,17 @@ class rte_solve_opts(C.Structure):
                 ("profile", C.c_int32)]
 
 
+RTE_TUNE_FORCE = 1
+# the (ring depth H, phase count P) shapes the band solve kernel is built for
+BAND_SHAPES = [(9, 1), (17, 1), (33, 1), (9, 2), (17, 2), (33, 2), (17, 3), (33, 3), (33, 4)]
+
+
+class rte_tune_report(C.Structure):
+    _fields_ = [("n_cand", C.c_int32 * 2), ("H", (C.c_int32 * 9) * 2), ("P", (C.c_int32 * 9) * 2),
+                ("ms", (C.c_double * 9) * 2), ("chosen_H", C.c_int32 * 2), ("chosen_P", C.c_int32 * 2),
+                ("default_H", C.c_int32 * 2), ("default_P", C.c_int32 * 2), ("from_cache", C.c_int32 * 2)]
+
+
 class rte_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("rel_resid", C.c_double), ("stop_quantity", C.c_double),
                 ("pcg_iters_total", C.c_int64), ("cg_iters_total", C.c_int64),
@@ -89,6 +100,8 @@ EXPORTS = {
     "rte_batch_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "rte_batch_usage": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]),
     "rte_batch_destroy": (C.c_int, [C.c_void_p]),
+    "rte_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "rte_set_band_layout": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
     "rte_last_error": (C.c_char_p, []),
 }
 
@@ -232,6 +245,25 @@ class Handle:
         b = C.c_size_t()
         _check(lib.rte_footprint(self.h, C.byref(b)))
         return b.value
+
+    def autotune(self, force=False, stream=None) -> dict:
+        """Time the E_0 band solve in every factor layout that holds the band and keep the
+        fastest (rte_autotune).  Returns, per precision present, the shapes timed with
+        their milliseconds per E_0^{-1}, the default and the chosen shape."""
+        r = rte_tune_report()
+        _check(lib.rte_autotune(self.h, RTE_TUNE_FORCE if force else 0, _stream(stream), C.byref(r)))
+        out = {}
+        for i, name in ((0, "fp64"), (1, "fp32")):
+            if r.chosen_H[i] == 0:
+                continue
+            out[name] = {"timed": [((r.H[i][c], r.P[i][c]), r.ms[i][c]) for c in range(r.n_cand[i])],
+                         "default": (r.default_H[i], r.default_P[i]), "chosen": (r.chosen_H[i], r.chosen_P[i]),
+                         "from_cache": bool(r.from_cache[i])}
+        return out
+
+    def set_band_layout(self, precision, H, P, stream=None):
+        """Lay the E_0 factors of one precision out in the band solve shape (H, P)."""
+        _check(lib.rte_set_band_layout(self.h, int(precision), int(H), int(P), _stream(stream)))
 
     def band(self):
         """(E_0 band width, coarse unknowns, coarse band width)."""

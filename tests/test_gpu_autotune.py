@@ -1,0 +1,110 @@
+"""GPU tests of the band layout autotuner (rte_autotune, rte_set_band_layout): every factor
+layout that holds the band gives bitwise the same E_0^{-1} (padding groups are zero and each
+row's products are summed in the same order), the tuner times every such layout, keeps one
+of them and caches its choice, and the lockstep batch runs handles in non-default layouts."""
+import numpy as np
+import pytest
+
+from paper_2102_09038_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def instances():
+    return [inputs.config_small(),
+            inputs.tiny_instance(n=6, sphere_level=1, g=0.7, ratio=0.95, n_even=0, n_odd=3, l=4)]
+
+
+def e0inv(h, X, prec):
+    from paper_2102_09038_amd import rte
+    Y = torch.empty_like(X)
+    h.apply_E0inv(X, Y, rte.default_solve_opts(e0_solver=rte.RTE_E0_BANDED, precision=prec))
+    torch.cuda.synchronize()
+    return Y
+
+
+def holds(H, P, bw, vec):
+    return H * P >= (bw + vec) // vec
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_every_layout_same_result(k):
+    from paper_2102_09038_amd import rte
+    inst = instances()[k]
+    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)
+    bw = h.band()[0]
+    X = torch.from_numpy(np.random.default_rng(5).standard_normal((h.dims.nSp, h.dims.nRp))).cuda()
+    ref = {p: e0inv(h, X, p) for p in (rte.RTE_FP64, rte.RTE_MIXED)}
+    for prec, vec in ((rte.RTE_FP64, 2), (rte.RTE_MIXED, 4)):
+        tried = 0
+        for H, P in rte.BAND_SHAPES:
+            if not holds(H, P, bw, vec):
+                with pytest.raises(rte.RteError):
+                    h.set_band_layout(prec, H, P)
+                continue
+            h.set_band_layout(prec, H, P)
+            assert torch.equal(e0inv(h, X, prec), ref[prec]), (prec, H, P)
+            tried += 1
+        print(f"{inst.name} bw {bw} precision {prec}: {tried} layouts, identical results")
+        assert tried >= 2
+    h.close()
+
+
+def test_autotune_report_and_cache():
+    from paper_2102_09038_amd import rte
+    inst = instances()[0]
+    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)
+    bw = h.band()[0]
+    X = torch.from_numpy(np.random.default_rng(6).standard_normal((h.dims.nSp, h.dims.nRp))).cuda()
+    ref64 = e0inv(h, X, rte.RTE_FP64)
+    rep = h.autotune(force=True)
+    for name, vec in (("fp64", 2), ("fp32", 4)):
+        r = rep[name]
+        shapes = [s for s, _ in r["timed"]]
+        print(name, r)
+        assert not r["from_cache"]
+        assert shapes[0] == r["default"]
+        assert sorted(shapes) == sorted(s for s in rte.BAND_SHAPES if holds(*s, bw, vec))
+        assert r["chosen"] in shapes
+        assert all(ms > 0 for _, ms in r["timed"])
+    assert torch.equal(e0inv(h, X, rte.RTE_FP64), ref64)
+    # a second handle of the same shape takes the cached choice without timing
+    h2 = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)
+    rep2 = h2.autotune()
+    for name in ("fp64", "fp32"):
+        assert rep2[name]["from_cache"] and rep2[name]["timed"] == []
+        assert rep2[name]["chosen"] == rep[name]["chosen"]
+    assert torch.equal(e0inv(h2, X, rte.RTE_FP64), ref64)
+    h.close()
+    h2.close()
+
+
+def test_batch_with_non_default_layouts():
+    """The grouped band solve of the lockstep batch reads each job's own layout."""
+    from paper_2102_09038_amd import rte
+    insts = instances()
+    o = rte.default_solve_opts(l=4, tol=1e-10, max_iter=300, precision=rte.RTE_MIXED, e0_solver=rte.RTE_E0_BANDED,
+                               odd_solver=rte.RTE_ODD_CONDENSED)
+    hs = [rte.Handle.from_instance(i, e0_solver=rte.RTE_E0_BANDED, mixed=1) for i in insts]
+    ref = []
+    for h in hs:
+        U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+        h.solve(U, opts=o)
+        ref.append(U)
+    for h in hs:   # the widest shape that holds each band, unlike the default
+        bw = h.band()[0]
+        H, P = [s for s in rte.BAND_SHAPES if holds(*s, bw, 4)][-1]
+        h.set_band_layout(rte.RTE_MIXED, H, P)
+    b = rte.Batch(max_slots=4)
+    outs = [torch.empty_like(U) for U in ref]
+    for h, U in zip(hs, outs):
+        b.admit(h, U, o)
+    assert b.step(1000) == 0
+    res = b.poll()
+    assert len(res) == len(hs) and all(st == rte.RTE_OK for _, st, _ in res)
+    for U, Ur in zip(outs, ref):
+        assert torch.equal(U, Ur)
+    b.close()
+    for h in hs:
+        h.close()
