@@ -124,25 +124,34 @@ def measured_traffic(key):
 
 
 def kernel_passes(h, inst, torch, rte):
-    """The launches the HBM counter passes read: the condensed FP64 ApplyE (its GEMM),
-    E_0^{-1} with FP64 and FP32 band factors, and a plain device copy of COPY_BYTES."""
+    """The launches the HBM counter passes read, in this order: the condensed ApplyE in FP64
+    (transport GEMM, A^T kernel) and in mixed precision (BF16 GEMM, FP32 A^T kernel), each
+    twice; E_0^{-1} with FP64 and with FP32 band factors, twice each; the scatter GEMM U S+
+    in FP64 and in FP32 MFMA, twice each; a plain device copy of COPY_BYTES, twice."""
     d = h.dims
     gen = torch.Generator(device="cuda").manual_seed(0)
     X = torch.randn((d.nSp, d.nRp), dtype=torch.float64, device="cuda", generator=gen)
     Y = torch.empty_like(X)
-    e_opts = rte.default_solve_opts(odd_solver=rte.RTE_ODD_CONDENSED)
-    for _ in range(2):
-        h.apply_E(X, Y, e_opts)
+    for prec in (rte.RTE_FP64, rte.RTE_MIXED):
+        e_opts = rte.default_solve_opts(odd_solver=rte.RTE_ODD_CONDENSED, precision=prec)
+        for _ in range(2):
+            h.apply_E(X, Y, e_opts)
     for prec in (rte.RTE_FP64, rte.RTE_MIXED):
         o = rte.default_solve_opts(e0_solver=rte.RTE_E0_BANDED, precision=prec)
         for _ in range(2):
             h.apply_E0inv(X, Y, o)
+    Xf = X.float()
+    for _ in range(2):
+        h.apply_scatter(1, X, Y)
+    for _ in range(2):
+        h.apply_scatter(1, Xf, Y, dtype_in=rte.RTE_DT_F32, dtype_out=rte.RTE_DT_F64)
     a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(2):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"kernel_passes": ["apply_E condensed fp64 x2", "E0inv banded fp64 x2", "E0inv banded fp32 x2",
+    print(json.dumps({"kernel_passes": ["apply_E condensed fp64 x2", "apply_E condensed mixed x2",
+                                        "E0inv banded fp64 x2", "E0inv banded fp32 x2", "K+ fp64 x2", "K+ fp32 x2",
                                         f"device copy {COPY_BYTES} bytes x2"]}))
 
 
@@ -443,7 +452,7 @@ def main():
         "scatter_gemm": {"bound": "mfma", "achieved": scatter_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": scatter_tf / FP64_MFMA_PEAK_TFLOPS, "kernel": "gemm_mfma_kernel<double> (U S+, eq. tpmv; last round split over K)",
                          "avg_launch_ms": 1e3 * t_sc / max(n_sc, 1), "launches": n_sc,
-                         "flops_per_launch": fl_sc / max(n_sc, 1)},
+                         "flops_per_launch": fl_sc / max(n_sc, 1), "traffic": measured_traffic("gemm_f64_scatter")},
     }
     # ---- the mixed-precision form of the same solve: BF16/FP32 preconditioner (condensed
     #      transport GEMM in BF16 with FP32 accumulation, FP32 E_0 band factors), FP64
@@ -483,10 +492,11 @@ def main():
         "scatter_gemm_fp32": {"bound": "mfma", "achieved": s32_tf, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                               "frac": s32_tf / FP32_MFMA_PEAK_TFLOPS, "kernel": "gemm_mfma_kernel<float> (U S+)",
                               "avg_launch_ms": 1e3 * ts32 / max(ns32, 1), "launches": ns32,
-                              "flops_per_launch": fs32 / max(ns32, 1)},
+                              "flops_per_launch": fs32 / max(ns32, 1), "traffic": measured_traffic("gemm_f32_scatter")},
         "gemm_bf16": {"bound": "mfma", "achieved": bf16_tf, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": bf16_tf / BF16_MFMA_PEAK_TFLOPS, "avg_launch_ms": 1e3 * tb / max(nb, 1),
-                      "launches": nb, "flops_per_launch": fb / max(nb, 1)},
+                      "launches": nb, "flops_per_launch": fb / max(nb, 1),
+                      "traffic": measured_traffic("gemm_bf16_transport")},
         "e0inv_fp32": {"bound": "hbm", "achieved": e0m_bytes / (t_e0m / max(n_e0m, 1)) / 1e9 if n_e0m else 0.0,
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "avg_launch_ms": 1e3 * t_e0m / max(n_e0m, 1),
                        "bytes_per_launch": e0m_bytes, "traffic": measured_traffic("band_solve_f32")},

@@ -316,8 +316,14 @@ void apply_scatter(Handle* h, int parity, int dtin, const void* X, int dtout, vo
         const int n = h->nRp, m = h->nS;
         double* G = sv::ws(h, sv::W_EG);
         double* T = dtout == RTE_DT_F64 ? static_cast<double*>(Y) : sv::ws(h, sv::W_ET);
-        if (f32) k::gemm_f32(n, m, m, 1.0f, static_cast<const float*>(X), n, h->Sp_f.p, m, 0.0f, G, n, s);
-        else k::gemm_f64(n, m, m, 1.0, static_cast<const double*>(X), n, h->Sp.p, m, 0.0, G, n, s);
+        // the odd workspace is scratch for the split last round of GEMM tiles, as in the solve
+        double* scratch = sv::ws(h, sv::W_OZ);
+        const size_t nscr = (size_t)h->nRm * h->nSm;
+        if (f32)
+            k::gemm_f32(n, m, m, 1.0f, static_cast<const float*>(X), n, h->Sp_f.p, m, 0.0f, G, n, s,
+                        reinterpret_cast<float*>(scratch), 2 * nscr);
+        else
+            k::gemm_f64(n, m, m, 1.0, static_cast<const double*>(X), n, h->Sp.p, m, 0.0, G, n, s, scratch, nscr);
         k::spmm_pattern(h, h->Msv.p, G, T, s);
         if (dtout == RTE_DT_F32) k::cvt_f64_f32(T, static_cast<float*>(Y), (size_t)n * m, s);
     } else {

@@ -372,17 +372,16 @@ __global__ __launch_bounds__(256) void symmetrize_lower_kernel(double* __restric
 // column-wise permutation of an n x ncols column-major matrix: gather (dst[r] = src[iperm[r]])
 // or scatter (dst[iperm[r]] = src[r]); one work-group per column, so the scattered side of a
 // column is touched by one work-group in a short time and its cache lines are reused
+// one thread per element: column blockIdx.y, rows of the 256-row chunk blockIdx.x
 __global__ __launch_bounds__(256) void permute_cols_kernel(const int* __restrict__ iperm, int n,
                                                            const double* __restrict__ src,
                                                            double* __restrict__ dst, int gather) {
-    const size_t off = (size_t)blockIdx.x * n;
-    const double* sc = src + off;
-    double* dc = dst + off;
-    if (gather) {
-        for (int r = threadIdx.x; r < n; r += blockDim.x) dc[r] = sc[iperm[r]];
-    } else {
-        for (int r = threadIdx.x; r < n; r += blockDim.x) dc[iperm[r]] = sc[r];
-    }
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    const size_t off = (size_t)blockIdx.y * n;
+    const int p = iperm[r];
+    if (gather) dst[off + r] = src[off + p];
+    else dst[off + p] = src[off + r];
 }
 
 // Y[i] = sum_j A[i * n + j] X[j] for a dense n x n matrix stored by rows (one wave per row,
@@ -643,7 +642,8 @@ void symmetrize_lower(double* A, int n, hipStream_t s) {
 
 void permute_cols(const int* iperm, int n, int ncols, const double* src, double* dst, bool gather, hipStream_t s) {
     if (n <= 0 || ncols <= 0) return;
-    hipLaunchKernelGGL(permute_cols_kernel, dim3(ncols), dim3(256), 0, s, iperm, n, src, dst, gather ? 1 : 0);
+    hipLaunchKernelGGL(permute_cols_kernel, dim3((n + 255) / 256, ncols), dim3(256), 0, s, iperm, n, src, dst,
+                       gather ? 1 : 0);
     RTE_CHECK_LAUNCH();
 }
 

@@ -242,7 +242,11 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_kernel(int M, int N, int K, 
     const int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
     const int nb = tm * tn;
     const int b = xcd_swizzle(blockIdx.x, nb);
-    const int bm = b / tn, bn = b % tn;      // n fastest: one A panel stays hot in L2
+    // tile order: along the shorter tile dimension fastest, so that the panel of the other
+    // operand is shared by the few consecutive tiles that need it while it is in L2 and the
+    // operand re-read across the long dimension is the small one (HBM reads it once)
+    const bool mfast = tm < tn;
+    const int bm = mfast ? b % tm : b / tn, bn = mfast ? b / tm : b % tn;
     const int m0 = bm * GBM, n0 = bn * GBN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave & 1, wn = wave >> 1;

@@ -28,6 +28,13 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 // operand the A fragment (m), so the result's lane-fast index runs along m and the
 // column-major stores of C are contiguous.  16-byte global loads, double-buffered LDS
 // with rows padded by 16 bytes, one barrier per K step.
+//
+// A K step is short (32 MFMAs per wave), shorter than a global load's latency, so interior
+// tiles run the loads two steps ahead of the MFMAs (two register sets) in a loop without
+// branches: the loads past the last step re-read the last step (in bounds, unused) and the
+// store after the last step fills a buffer nobody reads, so the compiler's waits for a
+// register set never cover the younger set's loads.  Edge tiles, and K not a multiple of
+// two steps, take a guarded loop with one step of prefetch.
 constexpr int HBM_ = 128, HBN = 128, HBK = 64, HPAD = 8;
 
 __device__ __forceinline__ int xcd_swz(int b, int nb) {
@@ -36,73 +43,131 @@ __device__ __forceinline__ int xcd_swz(int b, int nb) {
     return x * per + i;
 }
 
+typedef uint16_t BTile[HBM_][HBK + HPAD];
+
+// the MFMAs of one K step from LDS buffers As / Bs
+__device__ __forceinline__ void bf16_step_mfma(const BTile& As, const BTile& Bs, int lane, int wm, int wn,
+                                               f4v (&acc)[4][4]) {
+#pragma unroll
+    for (int kk = 0; kk < HBK / 32; ++kk) {
+        const int kc = kk * 32 + 8 * (lane >> 4);
+        bf8v af[4], bfr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf8v*>(&As[wm * 64 + i * 16 + (lane & 15)][kc]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bfr[j] = *reinterpret_cast<const bf8v*>(&Bs[wn * 64 + j * 16 + (lane & 15)][kc]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[j][i], 0, 0, 0);
+    }
+}
+
 __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(int M, int N, int K, float alpha,
                                                            const uint16_t* __restrict__ A, int lda,
                                                            const uint16_t* __restrict__ B, int ldb, float beta,
                                                            float* __restrict__ C, int ldc) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][HBM_][HBK + HPAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][HBN][HBK + HPAD];
+    __shared__ __attribute__((aligned(16))) BTile As[2];
+    __shared__ __attribute__((aligned(16))) BTile Bs[2];
     const int tm = (M + HBM_ - 1) / HBM_, tn = (N + HBN - 1) / HBN;
     const int b = xcd_swz(blockIdx.x, tm * tn);
-    const int bm = b / tn, bn = b % tn;
+    // the shorter tile dimension fastest: consecutive tiles share the other operand's panel
+    // (in L2), and the operand re-read across the long dimension is the small one
+    const bool mfast = tm < tn;
+    const int bm = mfast ? b % tm : b / tn, bn = mfast ? b / tm : b % tn;
     const int m0 = bm * HBM_, n0 = bn * HBN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
+    const int nk = (K + HBK - 1) / HBK;
+    // thread tid moves 16-byte chunk ch of rows r = tid / 8 + 32 i of both tiles
+    const int r0 = tid >> 3, ch = tid & 7;
 
-    uint4 ra[4], rb[4];
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = tid + 256 * i;
-            const int r = f >> 3, ch = f & 7;
-            const int gk = k0 + ch * 8;
-            const int gm = m0 + r, gn = n0 + r;
-            ra[i] = (gm < M && gk < K) ? *reinterpret_cast<const uint4*>(A + (size_t)gm * lda + gk)
-                                       : make_uint4(0, 0, 0, 0);
-            rb[i] = (gn < N && gk < K) ? *reinterpret_cast<const uint4*>(B + (size_t)gn * ldb + gk)
-                                       : make_uint4(0, 0, 0, 0);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int f = tid + 256 * i;
-            const int r = f >> 3, ch = f & 7;
-            *reinterpret_cast<uint4*>(&As[buf][r][ch * 8]) = ra[i];
-            *reinterpret_cast<uint4*>(&Bs[buf][r][ch * 8]) = rb[i];
-        }
-    };
     f4v acc[4][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[j][i] = f4v{0, 0, 0, 0};
 
-    const int nk = (K + HBK - 1) / HBK;
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * HBK);
-#pragma unroll
-        for (int kk = 0; kk < HBK / 32; ++kk) {
-            const int kc = kk * 32 + 8 * (lane >> 4);
-            bf8v af[4], bfr[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                af[i] = *reinterpret_cast<const bf8v*>(&As[cur][wm * 64 + i * 16 + (lane & 15)][kc]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                bfr[j] = *reinterpret_cast<const bf8v*>(&Bs[cur][wn * 64 + j * 16 + (lane & 15)][kc]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[j][i], 0, 0, 0);
-        }
-        if (kt + 1 < nk) sstore(cur ^ 1);
+    if (m0 + HBM_ <= M && n0 + HBN <= N && K % (2 * HBK) == 0) {
+        const uint16_t* Ab = A + (size_t)(m0 + r0) * lda + ch * 8;
+        const uint16_t* Bb = B + (size_t)(n0 + r0) * ldb + ch * 8;
+        // one K step's share of this thread: 4 chunks of A and 4 of B (kept as named values:
+        // arrays passed to the helpers would be placed in scratch memory)
+        struct Stage { uint4 a0, a1, a2, a3, b0, b1, b2, b3; };
+        auto load = [&](int kt) {
+            const size_t ko = (size_t)kt * HBK;
+            const size_t la = (size_t)32 * lda, lb = (size_t)32 * ldb;
+            Stage t;
+            t.a0 = *reinterpret_cast<const uint4*>(Ab + ko);
+            t.a1 = *reinterpret_cast<const uint4*>(Ab + la + ko);
+            t.a2 = *reinterpret_cast<const uint4*>(Ab + 2 * la + ko);
+            t.a3 = *reinterpret_cast<const uint4*>(Ab + 3 * la + ko);
+            t.b0 = *reinterpret_cast<const uint4*>(Bb + ko);
+            t.b1 = *reinterpret_cast<const uint4*>(Bb + lb + ko);
+            t.b2 = *reinterpret_cast<const uint4*>(Bb + 2 * lb + ko);
+            t.b3 = *reinterpret_cast<const uint4*>(Bb + 3 * lb + ko);
+            return t;
+        };
+        auto store = [&](const Stage& t, BTile& as, BTile& bs) {
+            *reinterpret_cast<uint4*>(&as[r0][ch * 8]) = t.a0;
+            *reinterpret_cast<uint4*>(&as[r0 + 32][ch * 8]) = t.a1;
+            *reinterpret_cast<uint4*>(&as[r0 + 64][ch * 8]) = t.a2;
+            *reinterpret_cast<uint4*>(&as[r0 + 96][ch * 8]) = t.a3;
+            *reinterpret_cast<uint4*>(&bs[r0][ch * 8]) = t.b0;
+            *reinterpret_cast<uint4*>(&bs[r0 + 32][ch * 8]) = t.b1;
+            *reinterpret_cast<uint4*>(&bs[r0 + 64][ch * 8]) = t.b2;
+            *reinterpret_cast<uint4*>(&bs[r0 + 96][ch * 8]) = t.b3;
+        };
+        Stage s0 = load(0);
+        store(s0, As[0], Bs[0]);
+        Stage s1 = load(1);
         __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            // step kt from buffer 0; step kt + 1's data (s1) goes to buffer 1
+            s0 = load(min(kt + 2, nk - 1));
+            __builtin_amdgcn_sched_barrier(0);     // the loads stay ahead of the MFMAs
+            bf16_step_mfma(As[0], Bs[0], lane, wm, wn, acc);
+            store(s1, As[1], Bs[1]);
+            __syncthreads();
+            // step kt + 1 from buffer 1; step kt + 2's data (s0) goes to buffer 0
+            s1 = load(min(kt + 3, nk - 1));
+            __builtin_amdgcn_sched_barrier(0);
+            bf16_step_mfma(As[1], Bs[1], lane, wm, wn, acc);
+            store(s0, As[0], Bs[0]);
+            __syncthreads();
+        }
+    } else {
+        uint4 ra[4], rb[4];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + 32 * i;
+                const int gk = k0 + ch * 8;
+                const int gm = m0 + r, gn = n0 + r;
+                ra[i] = (gm < M && gk < K) ? *reinterpret_cast<const uint4*>(A + (size_t)gm * lda + gk)
+                                           : make_uint4(0, 0, 0, 0);
+                rb[i] = (gn < N && gk < K) ? *reinterpret_cast<const uint4*>(B + (size_t)gn * ldb + gk)
+                                           : make_uint4(0, 0, 0, 0);
+            }
+        };
+        auto sstore = [&](int buf) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                *reinterpret_cast<uint4*>(&As[buf][r0 + 32 * i][ch * 8]) = ra[i];
+                *reinterpret_cast<uint4*>(&Bs[buf][r0 + 32 * i][ch * 8]) = rb[i];
+            }
+        };
+        gload(0);
+        sstore(0);
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            if (kt + 1 < nk) gload((kt + 1) * HBK);
+            bf16_step_mfma(As[cur], Bs[cur], lane, wm, wn, acc);
+            if (kt + 1 < nk) sstore(cur ^ 1);
+            __syncthreads();
+        }
     }
     // acc[j][i][v] = C(m = m0 + wm*64 + i*16 + lane%16, n = n0 + wn*64 + j*16 + 4*(lane/16) + v)
 #pragma unroll
