@@ -180,7 +180,7 @@ def batch_bench(args, torch, rte, inputs):
     ref, t64, it64, asm64 = [], 0.0, [], []
     for i, inst in enumerate(insts):
         ta = time.perf_counter()
-        h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=0)
+        h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0)
         asm64.append(time.perf_counter() - ta)
         U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
@@ -210,10 +210,10 @@ def batch_bench(args, torch, rte, inputs):
     #      instances are taken in order while their handles fit the budget together
     hs, held = [], 0
     for inst in insts:
-        b_est, p_est = rte.estimate_footprint(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2)
+        b_est, p_est = rte.estimate_footprint(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0)
         if held + max(b_est, p_est) > budget:
             continue
-        hs.append(rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2))
+        hs.append(rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0))
         held += b_est
     lockstep = {}
     for graphs in (True, False):
@@ -301,7 +301,7 @@ def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None):
             wait = r.arrival - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
-            h = rte.Handle.from_instance(r.inst, e0_solver=rte.RTE_E0_BANDED, mixed=0)
+            h = rte.Handle.from_instance(r.inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0)
             U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
             st, info = h.solve(U, opts=o64, raise_on_notconv=False)
             torch.cuda.synchronize()
@@ -376,7 +376,8 @@ def main():
         return
     inst = inputs.config_realistic()
     ta = time.perf_counter()
-    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1)
+    # the condensed odd solve only: no odd eigendecomposition at assembly
+    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1, odd_eig=0)
     t_assemble = time.perf_counter() - ta
     d = h.dims
     # band layout of the E_0 factors: every shape that holds the band timed on the device,

@@ -110,6 +110,12 @@ typedef struct rte_assemble_opts {
                                  /*    and keep only the FP32 E_0 band factors (FP64 E_0    */
                                  /*    solves then fail with RTE_E_ARG; halves the largest  */
                                  /*    allocation for mixed-only use)                       */
+    int32_t odd_eig;             /* 1 (default): eigendecomposition of (S-, M_S-) at assembly
+                                    (every odd solver); 0: skipped when sigma_s / sigma_t is
+                                    uniform, H = (M_S- - delta S-)^{-1} then comes from a dense
+                                    Cholesky inverse (the exact and condensed odd solves work,
+                                    the PCG odd solve fails with RTE_E_ARG); ignored (the
+                                    decomposition is done) when the ratio varies             */
 } rte_assemble_opts;
 
 typedef struct rte_solve_opts {

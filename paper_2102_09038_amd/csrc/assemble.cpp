@@ -316,6 +316,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     // ------------------------------------------------------------------ validation
     if (!D || !o) fail(RTE_E_ARG, "null descriptor or options");
     if (o->mixed < 0 || o->mixed > 2) fail(RTE_E_ARG, "mixed must be 0, 1 or 2");
+    if (o->odd_eig != 0 && o->odd_eig != 1) fail(RTE_E_ARG, "odd_eig must be 0 or 1");
     const int d = D->dim;
     if (d != 2 && d != 3) fail(RTE_E_ARG, "dim must be 2 or 3");
     if (D->n_vert < d + 1 || D->n_cell < 1 || !D->vert || !D->cell) fail(RTE_E_ARG, "empty spatial mesh");
@@ -704,7 +705,37 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     // ------------------------------------------------------------------ eigen-bases (rocSOLVER)
     RocblasCtx rb(s);
     const int nSm = h.nSm;
-    {   // odd: S- W = M_S- W Lambda; with M_S- = L L^T blockwise: (L^-1 S- L^-T) V = V Lambda, W = L^-T V
+    // The odd eigendecomposition of (S-, M_S-) serves the PCG preconditioner (its top pairs),
+    // the exact odd inverse for a per-cell ratio (all pairs) and the transport term of E_c.
+    // With a uniform ratio delta and opts->odd_eig == 0 it is skipped: the exact and condensed
+    // forms only need H = (M_S- - delta S-)^{-1}, which a dense Cholesky inverse on the GPU gives
+    // directly, and the E_c term is (A_n W+)^T H (A_m W+).
+    const bool odd_eig = o->odd_eig != 0 || !h.uniform_delta;
+    h.have_odd_eig = odd_eig;
+    Vec Wfull;                    // host full odd eigenbasis (odd_eig only)
+    Vec Hh;                       // host H (uniform delta only)
+    // condensed transport matrix G from H: block (n, n') = A_n^T H A_n', i.e.
+    // G[(n,k),(n',k')] = sum_{m,m'} 2 T_k(n,m) H[3k+m, 3k'+m'] 2 T_k'(n',m')
+    auto condensed_from_H = [&]() {
+        const int dn = d * nS;
+        Vec G((size_t)dn * dn);
+        for (int k2 = 0; k2 < nS; ++k2)
+            for (int k1 = 0; k1 < nS; ++k1) {
+                double Hb[9];
+                for (int m = 0; m < 3; ++m)
+                    for (int m2 = 0; m2 < 3; ++m2) Hb[3 * m + m2] = Hh[(3 * k1 + m) + (size_t)nSm * (3 * k2 + m2)];
+                for (int n = 0; n < d; ++n)
+                    for (int n2 = 0; n2 < d; ++n2) {
+                        double v = 0;
+                        for (int m = 0; m < 3; ++m)
+                            for (int m2 = 0; m2 < 3; ++m2)
+                                v += 2.0 * h.h_T[9 * k1 + 3 * n + m] * Hb[3 * m + m2] * 2.0 * h.h_T[9 * k2 + 3 * n2 + m2];
+                        G[(n * nS + k1) + (size_t)dn * (n2 * nS + k2)] = v;
+                    }
+            }
+        h.Gc.upload(G, s);
+    };
+    if (odd_eig) {   // odd: S- W = M_S- W Lambda; with M_S- = L L^T blockwise: (L^-1 S- L^-T) V = V Lambda, W = L^-T V
         Vec A((size_t)nSm * nSm);
         for (int kb = 0; kb < nS; ++kb)
             for (int kc = 0; kc < nS; ++kc) {
@@ -733,7 +764,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         Vec lam;
         syevd(rb, s, nSm, A, lam);
         // W = L^-T V, reorder to non-increasing eigenvalues
-        Vec Wfull((size_t)nSm * nSm);
+        Wfull.assign((size_t)nSm * nSm, 0.0);
         h.h_lamm_full.resize(nSm);
         for (int c = 0; c < nSm; ++c) {
             const int src = nSm - 1 - c;
@@ -767,7 +798,6 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             h.WfullT.upload(WT, s);
             h.lam_full.upload(h.h_lamm_full, s);
             if (h.uniform_delta) {
-                DBuf<double> Ws(Wfull.size());
                 Vec Wsc(Wfull);
                 for (int c = 0; c < nSm; ++c) {
                     const double f = 1.0 / (1.0 - h.delta0 * h.h_lamm_full[c]);
@@ -779,29 +809,29 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
                 h.Hodd.alloc((size_t)nSm * nSm);
                 k::gemm_f64(nSm, nSm, nSm, 1.0, dWsc.p, nSm, h.WfullT.p, nSm, 0.0, h.Hodd.p, nSm, s);
                 RTE_HIP(hipStreamSynchronize(s));
-                // condensed transport matrix: block (n, n') = A_n^T H A_n', i.e.
-                // G[(n,k),(n',k')] = sum_{m,m'} 2 T_k(n,m) H[3k+m, 3k'+m'] 2 T_k'(n',m')
-                const Vec Hh = h.Hodd.download(s);
-                const int dn = d * nS;
-                Vec G((size_t)dn * dn);
-                for (int k2 = 0; k2 < nS; ++k2)
-                    for (int k1 = 0; k1 < nS; ++k1) {
-                        double Hb[9];
-                        for (int m = 0; m < 3; ++m)
-                            for (int m2 = 0; m2 < 3; ++m2) Hb[3 * m + m2] = Hh[(3 * k1 + m) + (size_t)nSm * (3 * k2 + m2)];
-                        for (int n = 0; n < d; ++n)
-                            for (int n2 = 0; n2 < d; ++n2) {
-                                double v = 0;
-                                for (int m = 0; m < 3; ++m)
-                                    for (int m2 = 0; m2 < 3; ++m2)
-                                        v += 2.0 * h.h_T[9 * k1 + 3 * n + m] * Hb[3 * m + m2] * 2.0 * h.h_T[9 * k2 + 3 * n2 + m2];
-                                G[(n * nS + k1) + (size_t)dn * (n2 * nS + k2)] = v;
-                            }
-                    }
-                h.Gc.upload(G, s);
+                Hh = h.Hodd.download(s);
+                condensed_from_H();
             }
             h.have_exact = true;
         }
+    } else {
+        // H = (M_S- - delta S-)^{-1}: M_S- is block diagonal (2 T_k), S- symmetrised as above;
+        // dense lower band of width nSm - 1, Cholesky inverse on the GPU
+        const size_t w = (size_t)nSm;
+        Vec band((size_t)nSm * w, 0.0);
+        for (int r = 0; r < nSm; ++r)
+            for (int c = 0; c <= r; ++c) {
+                const double sm = 0.5 * (h.h_Sm[r + (size_t)nSm * c] + h.h_Sm[c + (size_t)nSm * r]);
+                double v = -h.delta0 * sm;
+                if (r / 3 == c / 3) v += 2.0 * h.h_T[9 * (r / 3) + 3 * (r % 3) + (c % 3)];
+                band[(size_t)r * w + (nSm - 1) + c - r] = v;
+            }
+        dense_spd_inverse(rb, s, band, nSm, nSm - 1, h.Hodd);
+        Hh = h.Hodd.download(s);
+        condensed_from_H();
+        h.have_exact = true;
+    }
+    {
         // ---- coarse needs P_n = W_full^T (A_n W+) later; keep Wfull on the host until then
         h.h_Sm.clear();
         h.h_Sm.shrink_to_fit();
@@ -827,14 +857,17 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         trace("eigen-bases");
         // ------------------------------------------------------------------ coarse matrix E_c
         const int dN = h.dNp;
-        // P_n = W_full^T (A_n W+)  [nSm x dN], (A_n W+)[(k,m), a] = 2 T_k(n, m) W+[k, a]
-        std::vector<Vec> Pn(d, Vec((size_t)nSm * dN, 0.0));
+        // (A_n W+)[(k,m), a] = 2 T_k(n, m) W+[k, a]  [nSm x dN], and with the odd eigenbasis
+        // P_n = W_full^T (A_n W+)
+        std::vector<Vec> AWn(d, Vec((size_t)nSm * dN));
+        std::vector<Vec> Pn(odd_eig ? d : 0, Vec((size_t)nSm * dN, 0.0));
         for (int n = 0; n < d; ++n) {
-            Vec AW((size_t)nSm * dN);
+            Vec& AW = AWn[n];
             for (int k = 0; k < nS; ++k)
                 for (int m = 0; m < 3; ++m)
                     for (int a = 0; a < dN; ++a)
                         AW[(3 * k + m) + (size_t)nSm * a] = 2.0 * h.h_T[9 * k + 3 * n + m] * h.h_Wp[k + (size_t)nS * a];
+            if (!odd_eig) continue;
             for (int c = 0; c < nSm; ++c)
                 for (int a = 0; a < dN; ++a) {
                     double v = 0;
@@ -844,23 +877,46 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
                     Pn[n][c + (size_t)nSm * a] = v;
                 }
         }
-        // G_nm(delta) = P_n^T diag(1/(1 - delta lam)) P_m for each distinct delta
+        // G_nm(delta) = (A_n W+)^T (M_S- - delta S-)^{-1} (A_m W+) for each distinct delta:
+        // P_n^T diag(1/(1 - delta lam)) P_m with the eigenbasis, else (uniform delta) through H
         std::map<double, Vec> Gcache;     // key delta -> [d*d*dN*dN]
         auto Gfor = [&](double delta) -> const Vec& {
             auto it = Gcache.find(delta);
             if (it != Gcache.end()) return it->second;
             Vec G((size_t)d * d * dN * dN, 0.0);
-            Vec f(nSm);
-            for (int c = 0; c < nSm; ++c) f[c] = 1.0 / (1.0 - delta * h.h_lamm_full[c]);
-            for (int n = 0; n < d; ++n)
-                for (int m = 0; m < d; ++m)
-                    for (int a = 0; a < dN; ++a)
-                        for (int b = 0; b < dN; ++b) {
+            if (odd_eig) {
+                Vec f(nSm);
+                for (int c = 0; c < nSm; ++c) f[c] = 1.0 / (1.0 - delta * h.h_lamm_full[c]);
+                for (int n = 0; n < d; ++n)
+                    for (int m = 0; m < d; ++m)
+                        for (int a = 0; a < dN; ++a)
+                            for (int b = 0; b < dN; ++b) {
+                                double v = 0;
+                                for (int c = 0; c < nSm; ++c)
+                                    v += Pn[n][c + (size_t)nSm * a] * f[c] * Pn[m][c + (size_t)nSm * b];
+                                G[((size_t)(n * d + m) * dN + a) * dN + b] = v;
+                            }
+            } else {
+                Vec HA((size_t)nSm * dN);
+                for (int m = 0; m < d; ++m) {
+                    for (int b = 0; b < dN; ++b)       // HA = H (A_m W+), H symmetric
+                        for (int r = 0; r < nSm; ++r) {
                             double v = 0;
-                            for (int c = 0; c < nSm; ++c)
-                                v += Pn[n][c + (size_t)nSm * a] * f[c] * Pn[m][c + (size_t)nSm * b];
-                            G[((size_t)(n * d + m) * dN + a) * dN + b] = v;
+                            const double* hr = &Hh[(size_t)nSm * r];
+                            const double* aw = &AWn[m][(size_t)nSm * b];
+                            for (int c = 0; c < nSm; ++c) v += hr[c] * aw[c];
+                            HA[r + (size_t)nSm * b] = v;
                         }
+                    for (int n = 0; n < d; ++n)
+                        for (int a = 0; a < dN; ++a)
+                            for (int b = 0; b < dN; ++b) {
+                                double v = 0;
+                                for (int r = 0; r < nSm; ++r)
+                                    v += AWn[n][r + (size_t)nSm * a] * HA[r + (size_t)nSm * b];
+                                G[((size_t)(n * d + m) * dN + a) * dN + b] = v;
+                            }
+                }
+            }
             return Gcache.emplace(delta, std::move(G)).first->second;
         };
         // ordering: reverse Cuthill-McKee or the given vertex order, whichever is narrower
@@ -1038,8 +1094,20 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
     const size_t nnz = (size_t)rp[nRp], nc = dN * nRp, even = (size_t)nRp * nS;
     const size_t cbw = dN * sbw + dN - 1;
     size_t b = 0;
-    // angular operators: S+, S-, eigenbases (full odd basis twice), H, condensed G, moments
-    b += (nS * nS + 4 * nSm * nSm + nSm * dNm + nS * dN + 4 * nSm + 16 * nS) * 8;
+    // angular operators: S+, S-, eigenbases (full odd basis twice), H, condensed G, moments;
+    // without the odd eigendecomposition (uniform ratio, odd_eig = 0) neither odd basis
+    bool uniform = true;
+    if (D->sigma_t && D->sigma_s) {
+        double lo = 1e300, hi = -1e300;
+        for (int j = 0; j < nRm; ++j) {
+            const double r = D->sigma_s[j] / D->sigma_t[j];
+            lo = std::min(lo, r);
+            hi = std::max(hi, r);
+        }
+        uniform = hi - lo <= 1e-13 * std::max(hi, 1e-300);
+    }
+    if (o->odd_eig == 0 && uniform) b += (nS * nS + 2 * nSm * nSm + nS * dN + 4 * nSm + 16 * nS) * 8;
+    else b += (nS * nS + 4 * nSm * nSm + nSm * dNm + nS * dN + 4 * nSm + 16 * nS) * 8;
     b += (size_t)d * nS * d * nS * 8;
     // spatial data: cells, gradients, pattern values per class, incidence, source
     b += (size_t)nRm * (nv * 4 + nv * d * 8 + 4 * 8) + nnz * (4 + 8 * (kMaxClasses + 4)) + (size_t)nRp * 16;

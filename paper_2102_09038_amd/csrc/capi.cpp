@@ -56,6 +56,7 @@ void rte_default_assemble_opts(rte_assemble_opts* o) {
     o->n_odd = 5;
     o->e0_solver = RTE_E0_CG;
     o->mixed = 0;
+    o->odd_eig = 1;
 }
 
 void rte_default_solve_opts(rte_solve_opts* o) {

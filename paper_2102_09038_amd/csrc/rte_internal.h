@@ -115,6 +115,7 @@ struct Handle {
 
     // ---- exact odd inverse (RTE_ODD_EXACT)
     bool have_exact = false;
+    bool have_odd_eig = false;     // odd eigenpairs present (PCG odd solve, per-cell exact)
     DBuf<double> Hodd;             // [nSm x nSm] (M_S- - delta0 S-)^{-1} when uniform_delta
     DBuf<double> Wfull, WfullT;    // full odd eigenvectors and transpose (both row-major K x N)
     DBuf<double> lam_full;         // [nSm]

@@ -197,6 +197,7 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
     if (o->odd_solver == RTE_ODD_EXACT) {
         odd_exact(h, B, Z, s);
     } else {
+        if (!h->have_odd_eig) fail(RTE_E_ARG, "the PCG odd solve needs the odd eigenpairs (assembly with odd_eig = 1)");
         const int it = odd_pcg(h, B, Z, tol, o->pcg_max_iter, s);
         if (pcg) *pcg += it;
     }

@@ -35,7 +35,7 @@ class rte_problem_desc(C.Structure):
 
 class rte_assemble_opts(C.Structure):
     _fields_ = [("quad_level", C.c_int32), ("n_even", C.c_int32), ("n_odd", C.c_int32),
-                ("e0_solver", C.c_int32), ("mixed", C.c_int32)]
+                ("e0_solver", C.c_int32), ("mixed", C.c_int32), ("odd_eig", C.c_int32)]
 
 
 class rte_solve_opts(C.Structure):

@@ -48,7 +48,8 @@ class Server:
     """
 
     def __init__(self, budget: int, solve_opts, max_slots: int = 256, workers: int = 4, mixed_assembly: int = 2,
-                 keep_results: bool = False, on_done: Optional[Callable[[Request], None]] = None):
+                 keep_results: bool = False, on_done: Optional[Callable[[Request], None]] = None,
+                 odd_eig: int = 0):
         import torch
         self.torch = torch
         self.budget = int(budget)
@@ -56,6 +57,9 @@ class Server:
         self.batch = rte.Batch(max_slots=max_slots, hbm_budget=0)
         self.workers = workers
         self.mixed_assembly = mixed_assembly
+        # the batch runs the condensed odd solve only: no odd eigendecomposition at assembly
+        # (uniform sigma_s / sigma_t; ignored otherwise)
+        self.odd_eig = odd_eig
         self.keep = keep_results
         self.on_done = on_done
         self.reserved = 0                          # bytes promised to requests being assembled or in slots
@@ -67,13 +71,14 @@ class Server:
     # ---------------------------------------------------------------------------- helpers
     def _estimate(self, req):
         if not hasattr(req, "_est"):
-            b, p = rte.estimate_footprint(req.inst, e0_solver=rte.RTE_E0_BANDED, mixed=self.mixed_assembly)
+            b, p = rte.estimate_footprint(req.inst, e0_solver=rte.RTE_E0_BANDED, mixed=self.mixed_assembly,
+                                          odd_eig=self.odd_eig)
             req._est = (b, max(b, p))
         return req._est
 
     def _assemble(self, req: Request, stream):
         h = rte.Handle.from_instance(req.inst, stream=stream.cuda_stream, e0_solver=rte.RTE_E0_BANDED,
-                                     mixed=self.mixed_assembly)
+                                     mixed=self.mixed_assembly, odd_eig=self.odd_eig)
         return h
 
     # ---------------------------------------------------------------------------- main loop

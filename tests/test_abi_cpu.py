@@ -85,6 +85,10 @@ def test_estimate_footprint_host_only():
     # the FP64 band factors (bandwidth 129 in band order: 261 row blocks x 66 groups x 64 x 2
     # doubles per direction, L and L^T, 1024 directions) are what mixed = 2 drops
     assert p2 - b2 == 2 * 261 * 66 * 64 * 2 * 8 * 1024
+    # without the odd eigendecomposition: no full odd basis and its transpose (3072^2 doubles
+    # each) and no truncated basis (3072 x 21)
+    be, _ = rte.estimate_footprint(real, e0_solver=rte.RTE_E0_BANDED, mixed=1, odd_eig=0)
+    assert b1 - be == (2 * 3072 * 3072 + 3072 * 21) * 8
     small = inputs.config_small()
     bs, _ = rte.estimate_footprint(small, e0_solver=rte.RTE_E0_BANDED, mixed=1)
     assert 0 < bs < b2
