@@ -221,10 +221,19 @@ struct RocblasCtx {
     }
 };
 
-// eigenpairs of the symmetric n x n matrix A (col-major host); ascending eigenvalues
+// The rocSOLVER factorisations of concurrent assemblies (worker threads of the server) run
+// one at a time: each holds this lock from upload to read-back.
+std::mutex& solver_library_mutex() {
+    static std::mutex m;
+    return m;
+}
+
 // Inv = A^{-1} for the SPD matrix given by its lower band (row-major, band[r (bw+1) + bw + c - r]):
-// dense Cholesky factorisation and inverse on the GPU, both triangles filled
-void dense_spd_inverse(RocblasCtx& rb, hipStream_t s, const Vec& band, int n, int bw, DBuf<double>& Inv) {
+// dense Cholesky factorisation and inverse on the GPU, both triangles filled; what names the
+// matrix in errors
+void dense_spd_inverse(RocblasCtx& rb, hipStream_t s, const Vec& band, int n, int bw, DBuf<double>& Inv,
+                       const char* what) {
+    std::lock_guard<std::mutex> serial(solver_library_mutex());
     DBuf<double> dband;
     dband.upload(band, s);
     Inv.alloc((size_t)n * n);
@@ -240,7 +249,8 @@ void dense_spd_inverse(RocblasCtx& rb, hipStream_t s, const Vec& band, int n, in
     if (st != rocblas_status_success) fail(RTE_E_HIP, "rocsolver_dpotrf failed");
     RTE_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
     RTE_HIP(hipStreamSynchronize(s));
-    if (hinfo != 0) fail(RTE_E_ARG, "the coarse matrix E_c is not positive definite");
+    if (hinfo != 0)
+        fail(RTE_E_ARG, std::string(what) + " is not positive definite (Cholesky pivot " + std::to_string(hinfo) + ")");
     {
         std::shared_lock<std::shared_mutex> lk(capture_mutex());
         st = rocsolver_dpotri(rb.h, rocblas_fill_lower, n, Inv.p, n, info.p);
@@ -248,12 +258,14 @@ void dense_spd_inverse(RocblasCtx& rb, hipStream_t s, const Vec& band, int n, in
     if (st != rocblas_status_success) fail(RTE_E_HIP, "rocsolver_dpotri failed");
     RTE_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
     RTE_HIP(hipStreamSynchronize(s));
-    if (hinfo != 0) fail(RTE_E_HIP, "rocsolver_dpotri failed on the coarse matrix");
+    if (hinfo != 0) fail(RTE_E_HIP, std::string("rocsolver_dpotri failed on ") + what);
     k::symmetrize_lower(Inv.p, n, s);
     RTE_HIP(hipStreamSynchronize(s));
 }
 
+// eigenpairs of the symmetric n x n matrix A (col-major host); ascending eigenvalues
 void syevd(RocblasCtx& rb, hipStream_t s, int n, Vec& A, Vec& lam) {
+    std::lock_guard<std::mutex> serial(solver_library_mutex());
     DBuf<double> dA(A.size()), dD(n), dE(n);
     DBuf<int> info(1);
     RTE_HIP(hipMemcpyAsync(dA.p, A.data(), A.size() * 8, hipMemcpyHostToDevice, s));
@@ -826,7 +838,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
                 if (r / 3 == c / 3) v += 2.0 * h.h_T[9 * (r / 3) + 3 * (r % 3) + (c % 3)];
                 band[(size_t)r * w + (nSm - 1) + c - r] = v;
             }
-        dense_spd_inverse(rb, s, band, nSm, nSm - 1, h.Hodd);
+        dense_spd_inverse(rb, s, band, nSm, nSm - 1, h.Hodd, "M_S- - delta S-");
         Hh = h.Hodd.download(s);
         condensed_from_H();
         h.have_exact = true;
@@ -983,7 +995,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             // A single band solve is one wave walking nc rows in sequence, so the coarse
             // solve uses the explicit inverse instead (dense Cholesky and inverse on the GPU,
             // once), applied as a bandwidth-bound matrix-vector product.
-            dense_spd_inverse(rb, s, band, nc, bw, h.Ecinv);
+            dense_spd_inverse(rb, s, band, nc, bw, h.Ecinv, "the coarse matrix E_c");
         } else {
             if (k::band_groups(bw, 2) == 0) fail(RTE_E_ARG, "coarse band too wide for the band solve");
             band_cholesky(band, nc, bw);

@@ -25,48 +25,78 @@ namespace {
 __device__ __forceinline__ size_t blk_idx(int row, int t, int bw) { return k::band_blk_index(row, t, bw, 2); }
 
 // ----------------------------------------------------------------------------- factor
-// One 256-thread work-group per direction.  A (bw+1) x (bw+1) window of the active
-// trailing matrix lives in LDS with circular row/column indices (mod bw+1).
-// Step j: pivot; scale column j; write row j of L (final now) to BL and BU; rank-one
-// update of the window's lower triangle; load row j+bw+1 into the slot row j vacated.
-__global__ __launch_bounds__(256) void e0_band_factor_kernel(
-    int n, int bw, int nnz, int ncls, const int* __restrict__ rowptr, const int* __restrict__ col,
-    const double* __restrict__ cls, const double* __restrict__ coefE0, const int* __restrict__ perm,
-    const int* __restrict__ iperm, double* __restrict__ BLall, double* __restrict__ BUall, size_t stride_sys,
-    int* __restrict__ bad) {
+// The lower band of every direction's E_0 block, in band order, is first written into the
+// blocked layout of BL by a fully parallel pass (e0_band_fill_kernel: one thread per row,
+// BL and BU zeroed around it).  The factorisation then streams its input rows from there
+// with plain coalesced loads, ahead of use, instead of walking the sparse pattern row by row.
+__global__ __launch_bounds__(256) void e0_band_fill_kernel(int n, int bw, int nnz, int ncls,
+                                                           const int* __restrict__ rowptr,
+                                                           const int* __restrict__ col,
+                                                           const double* __restrict__ cls,
+                                                           const double* __restrict__ coefE0,
+                                                           const int* __restrict__ perm,
+                                                           const int* __restrict__ iperm, double* __restrict__ BLall,
+                                                           double* __restrict__ BUall, size_t stride_sys) {
+    const int kk = blockIdx.y;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int rows = (n + 63) / 64 * 64;             // the layout's rows, padding included
+    if (r >= rows) return;
+    double* BL = BLall + stride_sys * kk;
+    double* BU = BUall + stride_sys * kk;
+    const int G2 = (int)k::band_groups(bw, 2) * 2;   // offsets per row in the layout
+    for (int t = 0; t < G2; ++t) {
+        BL[blk_idx(r, t, bw)] = 0.0;
+        BU[blk_idx(r, t, bw)] = 0.0;
+    }
+    if (r >= n) return;
+    const double* cf = coefE0 + (size_t)kk * ncls;
+    const int v = iperm[r];
+    for (int e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+        const int pc = perm[col[e]];
+        if (pc <= r && pc >= r - bw) {
+            double val = 0.0;
+            for (int c = 0; c < ncls; ++c) val = fma(cf[c], cls[(size_t)c * nnz + e], val);
+            BL[blk_idx(r, pc - (r - bw), bw)] = val;
+        }
+    }
+}
+
+// One work-group of 512 or 1024 threads (wide bands) per direction.  A (bw+1) x (bw+1) window of the active
+// trailing matrix lives in LDS with circular row and column indices (mod bw+1).  Step j:
+// pivot and scale column j; write row j of L (final now) to BL and BU; rank-one update of
+// the window's lower triangle; store row j+bw+1 of the input (read from BL one step ahead)
+// into the slot row j vacated.  Thread t owns offset t of the row leaving and of the row
+// arriving: column j-bw+t and column j+1+t share one window position (mod bw+1), so the
+// thread reads the old entry before it writes the new one and no other thread touches it.
+constexpr int kFacCols = 9;     // columns per thread of the trailing update: 16 x 9 >= bw + 1
+
+// Work-group barrier for LDS traffic only: this thread's LDS operations complete
+// (lgkmcnt(0)), then s_barrier.  __syncthreads would also wait for every global load and
+// store in flight, which here are the prefetched input row and the output rows of L.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);       // vmcnt and expcnt at their maxima, lgkmcnt 0
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+__global__ __launch_bounds__(1024) void e0_band_factor_kernel(int n, int bw, double* __restrict__ BLall,
+                                                             double* __restrict__ BUall, size_t stride_sys,
+                                                             int* __restrict__ bad) {
     extern __shared__ double win[];
-    __shared__ double cf[kMaxClasses];
     const int kk = blockIdx.x;
     const int w1 = bw + 1;
     double* BL = BLall + stride_sys * kk;
     double* BU = BUall + stride_sys * kk;
-    if (threadIdx.x < ncls) cf[threadIdx.x] = coefE0[(size_t)kk * ncls + threadIdx.x];
-    for (int e = threadIdx.x; e < w1 * w1; e += blockDim.x) win[e] = 0.0;
-    // BU entries pointing past the last row, and the padding of both, stay zero
-    const int nb = (n + 63) / 64;
-    const size_t used = k::band_blk_size(n, bw, 2);
-    for (size_t e = threadIdx.x; e < used; e += blockDim.x) {
-        BU[e] = 0.0;
-        BL[e] = 0.0;
-    }
+    const int t = threadIdx.x;                       // offset owned (t <= bw)
+    const bool own = t <= bw;
+    // rows 0 .. min(n, w1) - 1 of the input into the window: row r, offset t is column
+    // r - bw + t, at position (r + 1 + t) mod w1
+    for (int r = 0; r < min(n, w1); ++r)
+        if (own) win[(r % w1) * w1 + (r + 1 + t) % w1] = BL[blk_idx(r, t, bw)];
+    // the input row that arrives at step j is row j + w1, loaded one step ahead
+    double next = (own && w1 < n) ? BL[blk_idx(w1, t, bw)] : 0.0;
     __syncthreads();
-    auto load_row = [&](int r) {      // lower-triangle entries of band row r, columns [r-bw, r]
-        const int slot = r % w1;
-        for (int c = threadIdx.x; c < w1; c += blockDim.x) win[slot * w1 + c] = 0.0;
-        __syncthreads();
-        const int v = iperm[r];
-        for (int e = rowptr[v] + threadIdx.x; e < rowptr[v + 1]; e += blockDim.x) {
-            const int pc = perm[col[e]];
-            if (pc <= r && pc >= r - bw) {
-                double val = 0.0;
-                for (int c = 0; c < ncls; ++c) val = fma(cf[c], cls[(size_t)c * nnz + e], val);
-                win[slot * w1 + pc % w1] = val;
-            }
-        }
-    };
-    for (int r = 0; r < min(n, w1); ++r) load_row(r);
-    __syncthreads();
-    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15, nty = blockDim.x >> 4;
     int failed = 0;
     for (int j = 0; j < n; ++j) {
         const int sj = j % w1;
@@ -75,39 +105,51 @@ __global__ __launch_bounds__(256) void e0_band_factor_kernel(
         if (!(djj > 0.0)) { failed = 1; djj = 1.0; }
         const double d = sqrt(djj), id = 1.0 / d;
         const int m = min(n - 1, j + bw) - j;               // rows below the pivot in the window
-        __syncthreads();
-        for (int a = threadIdx.x; a < m; a += blockDim.x) {
-            int si = s1 + a; if (si >= w1) si -= w1;
+        const double arriving = next;
+        if (own && j + w1 + 1 < n) next = BL[blk_idx(j + w1 + 1, t, bw)];
+        if (t < m) {
+            int si = s1 + t; if (si >= w1) si -= w1;
             win[si * w1 + sj] *= id;
         }
-        if (threadIdx.x == 0) win[sj * w1 + sj] = d;
-        __syncthreads();
-        // row j of L is final: write it out (columns j-bw .. j)
-        for (int t = threadIdx.x; t <= bw; t += blockDim.x) {
+        lds_barrier();
+        // row j of L is final: offset t is column c = j - bw + t (t = bw: 1 / L(j,j))
+        const int pos = (j + 1 + t) % w1;
+        if (own) {
             const int c = j - bw + t;
-            double v = 0.0;
+            const double v = (t == bw) ? id : win[sj * w1 + pos];
             if (c >= 0) {
-                int sc = sj - bw + t; if (sc < 0) sc += w1;  // c mod w1
-                v = (t == bw) ? id : win[sj * w1 + sc];
                 BU[blk_idx(c, bw - t, bw)] = v;              // L(j, c): row c of L^T at offset j - c
+                BL[blk_idx(j, t, bw)] = v;
             }
-            BL[blk_idx(j, t, bw)] = v;
+            // the arriving row j + w1 takes the slot (offset t: column j + 1 + t, same position)
+            if (j + w1 < n) win[sj * w1 + pos] = arriving;
         }
-        // trailing update of the lower triangle (j, j+m] x (j, j+m]
-        for (int a = ty; a < m; a += 16) {
+        // trailing update of the lower triangle (j, j+m] x (j, j+m]: this thread's columns
+        // b = tx + 16 k (their column-j entries held in registers) of rows a = ty + (blockDim.x / 16) i; a
+        // row's entries are read together, then written, so the LDS reads overlap
+        int scol[kFacCols];
+        double lb[kFacCols];
+#pragma unroll
+        for (int q = 0; q < kFacCols; ++q) {
+            const int b = tx + 16 * q;
+            int sc = s1 + b; if (sc >= w1) sc -= w1;
+            scol[q] = b < w1 ? sc : 0;
+            lb[q] = b < m ? win[sc * w1 + sj] : 0.0;
+        }
+        for (int a = ty; a < m; a += nty) {
             int si = s1 + a; if (si >= w1) si -= w1;
             const double lij = win[si * w1 + sj];
             double* rowp = win + si * w1;
-            for (int b = tx; b <= a; b += 16) {
-                int sc = s1 + b; if (sc >= w1) sc -= w1;
-                rowp[sc] = fma(-lij, win[sc * w1 + sj], rowp[sc]);
-            }
+            double val[kFacCols];
+#pragma unroll
+            for (int q = 0; q < kFacCols; ++q)
+                if (tx + 16 * q <= a) val[q] = rowp[scol[q]];
+#pragma unroll
+            for (int q = 0; q < kFacCols; ++q)
+                if (tx + 16 * q <= a) rowp[scol[q]] = fma(-lij, lb[q], val[q]);
         }
-        __syncthreads();
-        if (j + w1 < n) load_row(j + w1);
-        __syncthreads();
+        lds_barrier();
     }
-    (void)nb;
     if (failed && threadIdx.x == 0) atomicOr(bad, 1);
 }
 
@@ -582,11 +624,16 @@ void band_group_run(const BandGroupPlan& plan, hipStream_t s) {
 void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, double* BL, double* BU,
                     size_t stride_sys, int* bad, hipStream_t s) {
     const size_t lds = (size_t)(bw + 1) * (bw + 1) * sizeof(double);
-    if (lds > 150 * 1024) fail(RTE_E_ARG, "E_0 band too wide for the LDS factorisation window");
+    if (lds > 150 * 1024 || bw + 1 > 16 * kFacCols)
+        fail(RTE_E_ARG, "E_0 band too wide for the LDS factorisation window");
+    const int rows = (h->nRp + 63) / 64 * 64;
+    hipLaunchKernelGGL(e0_band_fill_kernel, dim3((rows + 255) / 256, h->nS), dim3(256), 0, s, h->nRp, bw, h->nnz,
+                       h->ncls, h->rowptr.p, h->col.p, h->cls.p, h->coefE0.p, perm, iperm, BL, BU, stride_sys);
+    RTE_CHECK_LAUNCH();
     RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&e0_band_factor_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(e0_band_factor_kernel, dim3(h->nS), dim3(256), lds, s, h->nRp, bw, h->nnz, h->ncls,
-                       h->rowptr.p, h->col.p, h->cls.p, h->coefE0.p, perm, iperm, BL, BU, stride_sys, bad);
+    hipLaunchKernelGGL(e0_band_factor_kernel, dim3(h->nS), dim3(bw >= 120 ? 1024 : 512), lds, s, h->nRp, bw, BL, BU,
+                       stride_sys, bad);
     RTE_CHECK_LAUNCH();
 }
 

@@ -102,6 +102,7 @@ class Server:
                     req.assembled_at = now()
                     ready.put((req, h, est))
                 except BaseException as e:            # reported by the main loop
+                    e.args = (f"request {req.rid} ({getattr(req.inst, 'name', '?')}): {e}",)
                     ready.put((req, e, est))
 
         threads = [threading.Thread(target=worker, daemon=True) for _ in range(self.workers)]
