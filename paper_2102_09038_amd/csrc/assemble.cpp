@@ -249,8 +249,15 @@ void dense_spd_inverse(RocblasCtx& rb, hipStream_t s, const Vec& band, int n, in
     if (st != rocblas_status_success) fail(RTE_E_HIP, "rocsolver_dpotrf failed");
     RTE_HIP(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, s));
     RTE_HIP(hipStreamSynchronize(s));
-    if (hinfo != 0)
-        fail(RTE_E_ARG, std::string(what) + " is not positive definite (Cholesky pivot " + std::to_string(hinfo) + ")");
+    if (hinfo != 0) {
+        // tell a matrix that arrived on the device intact from one that did not
+        const Vec back = dband.download(s);
+        size_t diff = 0;
+        for (size_t e = 0; e < band.size(); ++e) diff += back[e] != band[e];
+        fail(RTE_E_ARG, std::string(what) + " is not positive definite (Cholesky pivot " + std::to_string(hinfo) +
+                            "; device copy of the input differs from the host matrix in " + std::to_string(diff) +
+                            " of " + std::to_string(band.size()) + " entries)");
+    }
     {
         std::shared_lock<std::shared_mutex> lk(capture_mutex());
         st = rocsolver_dpotri(rb.h, rocblas_fill_lower, n, Inv.p, n, info.p);

@@ -48,7 +48,17 @@ struct Batch {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t g_res = nullptr, g_prec = nullptr;
     bool graphs_valid = false;
+    // the stream the last batch work went to: a step returns with its last phase still
+    // running there, and that phase reads the job table and the graphs
+    hipStream_t last = nullptr;
+    // wait for the batch's work in flight (before its job table or graphs are replaced or freed)
+    void drain() {
+        if (last) RTE_HIP(hipStreamSynchronize(last));
+        if (gs && gs != last) RTE_HIP(hipStreamSynchronize(gs));
+    }
     ~Batch() {
+        if (last) (void)hipStreamSynchronize(last);
+        if (gs) (void)hipStreamSynchronize(gs);
         if (g_res) (void)hipGraphExecDestroy(g_res);
         if (g_prec) (void)hipGraphExecDestroy(g_prec);
         if (ev_in) (void)hipEventDestroy(ev_in);
@@ -80,6 +90,7 @@ size_t slot_bytes(Handle* h) {
 }
 
 void rebuild_plan(Batch* B, hipStream_t s) {
+    B->drain();      // the previous plan's job table may still be read by a launch in flight
     std::vector<k::BandJob> jobs;
     const bool f32 = B->precision == RTE_MIXED;
     for (auto& sl : B->slots) {
@@ -183,6 +194,7 @@ hipGraphExec_t capture(hipStream_t s, F&& enqueue) {
 }
 
 void recapture(Batch* B) {
+    B->drain();
     if (B->g_res) { RTE_HIP(hipGraphExecDestroy(B->g_res)); B->g_res = nullptr; }
     if (B->g_prec) { RTE_HIP(hipGraphExecDestroy(B->g_prec)); B->g_prec = nullptr; }
     B->g_res = capture(B->gs, [&] { enqueue_residuals(B, B->gs); });
@@ -320,6 +332,7 @@ int batch_step(Batch* B, int outer_iters, hipStream_t caller) {
         RTE_HIP(hipEventRecord(B->ev_out, s));
         RTE_HIP(hipStreamWaitEvent(caller, B->ev_out, 0));
     }
+    B->last = s;
     return nlive;
 }
 

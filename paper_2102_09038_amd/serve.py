@@ -49,12 +49,12 @@ class Server:
 
     def __init__(self, budget: int, solve_opts, max_slots: int = 256, workers: int = 4, mixed_assembly: int = 2,
                  keep_results: bool = False, on_done: Optional[Callable[[Request], None]] = None,
-                 odd_eig: int = 0):
+                 odd_eig: int = 0, use_graphs: bool = False):
         import torch
         self.torch = torch
         self.budget = int(budget)
         self.opts = solve_opts
-        self.batch = rte.Batch(max_slots=max_slots, hbm_budget=0)
+        self.batch = rte.Batch(max_slots=max_slots, hbm_budget=0, use_graphs=use_graphs)
         self.workers = workers
         self.mixed_assembly = mixed_assembly
         # the batch runs the condensed odd solve only: no odd eigendecomposition at assembly
