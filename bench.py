@@ -177,7 +177,7 @@ def batch_bench(args, torch, rte, inputs):
     o64 = rte.default_solve_opts(precision=rte.RTE_FP64, **base)
     omx = rte.default_solve_opts(precision=rte.RTE_MIXED, **base)
     # ---- baseline: plain FP64, one instance at a time
-    ref, t64, it64, asm64 = [], 0.0, [], []
+    ref, t64, it64, asm64, res64 = [], 0.0, [], [], []
     for i, inst in enumerate(insts):
         ta = time.perf_counter()
         h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0)
@@ -189,6 +189,7 @@ def batch_bench(args, torch, rte, inputs):
         torch.cuda.synchronize()
         t64 += time.perf_counter() - t0
         it64.append(info.iters)
+        res64.append(info.rel_resid)
         ref.append(U.cpu())
         h.close()
         del U
@@ -248,8 +249,13 @@ def batch_bench(args, torch, rte, inputs):
                           "all_converged": all(r.status == rte.RTE_OK for r in done),
                           "peak_live_slots": srv.peak_live, "hbm_budget": budget, "assembly_workers": 4},
         "mixed_lockstep_preassembled": lockstep,
-        "speedup_solve": t64 / srv.t_step, "speedup_end_to_end": (t64 + sum(asm64)) / wall,
+        # solve-only rates: the lockstep stepping of pre-assembled instances against the FP64
+        # solves one at a time (assembly excluded from both)
+        "speedup_solve": max(v["solves_per_s"] for v in lockstep.values()) / (len(insts) / t64), "speedup_end_to_end": (t64 + sum(asm64)) / wall,
+        # both forms stop at the same FP64 relative residual; their solutions then differ by up
+        # to about (condition number) x tol, most for instances whose iteration counts differ
         "max_rel_err_vs_fp64": max(errs), "median_rel_err_vs_fp64": float(np.median(errs)),
+        "max_rel_resid": {"fp64": max(res64), "mixed": max(r.rel_resid for r in done)},
     }
     print(json.dumps(out))
 
