@@ -288,7 +288,8 @@ def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None):
         last = max(r.done_at for r in m)
         return {"p50_s": serve.percentile(lat, 50), "p99_s": serve.percentile(lat, 99),
                 "mean_s": float(np.mean(lat)), "solves_per_s": len(m) / (last - first),
-                "all_converged": all(r.status == rte.RTE_OK for r in m), "wall_s": t_wall}
+                "all_converged": all(r.status == rte.RTE_OK for r in m),
+                "n_failed": sum(r.status not in (rte.RTE_OK, rte.RTE_E_NOTCONV) for r in m), "wall_s": t_wall}
 
     def run_batched(rate):
         reqs = [serve.Request(rid=i, inst=insts[i], arrival=float(unit[i] / rate)) for i in range(n)]

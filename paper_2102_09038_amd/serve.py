@@ -33,6 +33,7 @@ class Request:
     status: int = -1
     iters: int = 0
     rel_resid: float = float("nan")
+    error: str = ""                  # the library's message when the request failed
     U: object = None                 # the solution (torch tensor on the device), if kept
 
     @property
@@ -135,6 +136,15 @@ class Server:
                     except queue.Empty:
                         break
                     in_flight -= 1
+                    if isinstance(h, rte.RteError):
+                        # the request fails alone (its status is the library's); the loop goes on
+                        self.reserved -= peak
+                        req.done_at = now()
+                        req.status, req.error = h.status, str(h)
+                        finished.append(req)
+                        if self.on_done:
+                            self.on_done(req)
+                        continue
                     if isinstance(h, BaseException):
                         raise h
                     self.reserved -= peak - b          # the assembly peak is over
