@@ -67,3 +67,21 @@ def test_serve_results_equal_solo(budget_kind):
         assert torch.equal(r.U, U)
     if budget_kind == "one-at-a-time":
         assert srv.peak_live == 1
+
+
+def test_failed_request_does_not_stop_the_loop():
+    """A request the library rejects at assembly (sigma_s > sigma_t: RTE_E_PHYS, found before
+    any device work) is reported with that status; the other requests are served as usual."""
+    from paper_2102_09038_amd import rte, serve
+    insts, arrivals = trace()
+    bad = inputs.tiny_instance(n=4, sphere_level=1, g=0.5, ratio=0.9, n_even=0, n_odd=3, l=4)
+    bad.sigma_s = bad.sigma_t * 1.5
+    reqs = [serve.Request(rid=k, inst=inst, arrival=a) for k, (inst, a) in enumerate(zip(insts, arrivals))]
+    reqs.append(serve.Request(rid=len(reqs), inst=bad, arrival=0.0))
+    srv = serve.Server(int(64e9), opts(), max_slots=8, workers=2)
+    done = srv.run(reqs)
+    srv.close()
+    by_id = {r.rid: r for r in done}
+    assert sorted(by_id) == list(range(len(reqs)))
+    assert by_id[len(reqs) - 1].status == rte.RTE_E_PHYS and "E_PHYS" in by_id[len(reqs) - 1].error
+    assert all(by_id[k].status == rte.RTE_OK for k in range(len(insts)))
