@@ -156,7 +156,7 @@ struct Handle {
     int e0_g64 = 0;                // groups per row block of the FP64 factors' layout
     DBuf<double> L0, L0U;          // [nS * e0_stride], rows of L and of L^T
 
-    // ---- BF16 copies (mixed precision)
+    // ---- reduced-precision copies (mixed precision)
     bool have_mixed = false;
     DBuf<float> Sp_f, Sm_f;        // FP32 S+ and S- (mixed-precision scatter GEMMs)
     DBuf<uint16_t> Gc_bf;          // condensed transport matrix as BF16 parts [G_hi; G_lo]
