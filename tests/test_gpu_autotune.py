@@ -108,3 +108,26 @@ def test_batch_with_non_default_layouts():
     b.close()
     for h in hs:
         h.close()
+
+
+def test_autotune_fp32_only_handle():
+    """mixed = 2 keeps only the FP32 factors: the tuner reports that precision alone, FP64
+    layouts are refused, and the mixed solve is unchanged by any layout."""
+    from paper_2102_09038_amd import rte
+    inst = instances()[1]
+    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2)
+    o = rte.default_solve_opts(l=4, tol=1e-10, max_iter=300, precision=rte.RTE_MIXED, e0_solver=rte.RTE_E0_BANDED,
+                               odd_solver=rte.RTE_ODD_CONDENSED)
+    U0 = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+    h.solve(U0, opts=o)
+    rep = h.autotune(force=True)
+    assert set(rep) == {"fp32"}
+    with pytest.raises(rte.RteError):
+        h.set_band_layout(rte.RTE_FP64, 33, 1)
+    with pytest.raises(rte.RteError):
+        h.set_band_layout(rte.RTE_MIXED, 10, 1)       # not a shape of the menu
+    h.set_band_layout(rte.RTE_MIXED, 33, 4)
+    U1 = torch.empty_like(U0)
+    h.solve(U1, opts=o)
+    assert torch.equal(U0, U1)
+    h.close()

@@ -104,6 +104,26 @@ def test_solves_full_size(realistic):
     assert float(torch.linalg.norm(Um - Uf) / torch.linalg.norm(Uf)) < 1e-6
 
 
+def test_mixed_apply_E_full_size(realistic):
+    """The mixed-precision E U (BF16 MFMA transport GEMM at its full 4096 x 32768 x 8192 shape)
+    against the FP64 condensed E U on the same U: globally within the BF16 input rounding
+    (2^-9 relative per element), and per direction, so that a misplaced tile (an O(1) error
+    confined to some directions) cannot hide in the global norm."""
+    from paper_2102_09038_amd import rte
+    inst, D, h = realistic
+    d = h.dims
+    U = torch.from_numpy(np.random.default_rng(43).standard_normal((d.nSp, d.nRp))).cuda()
+    Yf = torch.empty_like(U)
+    Ym = torch.empty_like(U)
+    h.apply_E(U, Yf, rte.default_solve_opts(odd_solver=rte.RTE_ODD_CONDENSED))
+    h.apply_E(U, Ym, rte.default_solve_opts(odd_solver=rte.RTE_ODD_CONDENSED, precision=rte.RTE_MIXED))
+    err = float(torch.linalg.norm(Ym - Yf) / torch.linalg.norm(Yf))
+    per_dir = torch.linalg.norm(Ym - Yf, dim=1) / torch.linalg.norm(Yf, dim=1)
+    print(f"mixed vs FP64 E U: {err:.2e}, worst direction {float(per_dir.max()):.2e}")
+    assert 1e-12 < err < 1e-2
+    assert float(per_dir.max()) < 5e-2
+
+
 def test_scatter_gemm_full_size(realistic):
     """K+ X = Ms+ X S+ and K- X = Ms- X S- at full size, in FP64 and FP32 MFMA arithmetic, on
     sampled output rows (the first and last rows included: at this size the last, lightly
