@@ -105,7 +105,7 @@ def test_solves_full_size(realistic):
 
 
 def test_mixed_apply_E_full_size(realistic):
-    """The mixed-precision E U (BF16 MFMA transport GEMM at its full 4096 x 32768 x 8192 shape)
+    """The mixed-precision E U (BF16 MFMA transport GEMM at its full 2048 x 32768 x 4096 shape)
     against the FP64 condensed E U on the same U: globally within the BF16 input rounding
     (2^-9 relative per element), and per direction, so that a misplaced tile (an O(1) error
     confined to some directions) cannot hide in the global norm."""
