@@ -509,6 +509,26 @@ def main():
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "avg_launch_ms": 1e3 * t_e0m / max(n_e0m, 1),
                        "bytes_per_launch": e0m_bytes, "traffic": measured_traffic("band_solve_f32")},
     }
+    # ---- P_1 as l steps of E_0-preconditioned CG (the non-stationary inner iteration of
+    #      Sec. 5.3) instead of P_1^l, in both precisions; same workload and residual
+    out["inner_pcg"] = {}
+    for name, base_opts, base_value in (("fp64", opts, value), ("mixed", mopts, out["mixed"]["value"])):
+        po = rte.default_solve_opts(l=base_opts.l, tol=base_opts.tol, max_iter=base_opts.max_iter,
+                                    odd_solver=base_opts.odd_solver, e0_solver=base_opts.e0_solver,
+                                    precision=base_opts.precision, inner=rte.RTE_INNER_PCG)
+        Up = torch.empty_like(U)
+        for _ in range(args.warmup):
+            h.solve(Up, opts=po)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pinfos = [h.solve(Up, opts=po)[1] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        out["inner_pcg"][name] = {
+            "value": args.steps / pdt, "unit": "solves/s", "ms_per_step": 1e3 * pdt / args.steps,
+            "speedup_vs_richardson_inner": (args.steps / pdt) / base_value,
+            "iters": [i.iters for i in pinfos], "rel_resid": [i.rel_resid for i in pinfos],
+            "rel_diff_vs_fp64_solution": float(torch.linalg.norm(Up - U64) / torch.linalg.norm(U64))}
     h.close()
     if not args.no_serving:
         # the served form at one arrival rate, reduced to a short run (the full study is

@@ -75,6 +75,24 @@ typedef enum rte_e0_solver {
     RTE_E0_BANDED = 1     /* banded Cholesky factors per direction, factored once      */
 } rte_e0_solver;
 
+/* How P_1 approximates E^{-1} (Sec. 5.3).  The paper takes l steps of the preconditioned
+ * Richardson iteration with E_0 and remarks that a non-stationary preconditioned conjugate
+ * gradient method with the same E_0 does better. */
+typedef enum rte_inner {
+    RTE_INNER_RICHARDSON = 0, /* P_1^l (eq. applyP1, Alg. 2): z_0 = 0, z_{i+1} = z_i -
+                                 E_0^{-1} (E z_i - r), l steps; a fixed SPD matrix (Lemma
+                                 preconditioner_pl); l - 1 E and l E_0^{-1} applications */
+    RTE_INNER_PCG = 1         /* l steps of CG on E z = r preconditioned by E_0, z_0 = 0:
+                                 z_l is the E-orthogonal projection of E^{-1} r onto the
+                                 Krylov space span{(E_0^{-1} E)^j E_0^{-1} r, j < l}, so
+                                 its E-norm error is never larger than P_1^l r's; it
+                                 depends on r nonlinearly.  l E and l E_0^{-1}
+                                 applications; the step sizes stay on the device (no
+                                 host synchronisation).  Four more even-sized FP64
+                                 work vectors are allocated on first use.  Single
+                                 solves only (the batch refuses it with RTE_E_ARG)    */
+} rte_inner;
+
 typedef struct rte_handle rte_handle;   /* opaque; owns all device memory it allocates */
 
 /* Problem statement (Sec. 1, RTE with Henyey-Greenstein scattering and vacuum or
@@ -132,6 +150,7 @@ typedef struct rte_solve_opts {
     int32_t cg_max_iter;         /* CG iteration cap per E_0 block                           */
     int32_t profile;             /* nonzero: time the E_0 solves and the scattering GEMMs with
                                     HIP events on hip_stream (rte_solve_info.t_*)            */
+    int32_t inner;               /* rte_inner: how P_1 is applied                            */
 } rte_solve_opts;
 
 typedef struct rte_solve_info {
@@ -162,7 +181,7 @@ typedef struct rte_solve_info {
 void rte_default_assemble_opts(rte_assemble_opts* opts);
 /* Defaults: l 4, tol 1e-8, max_iter 200, FP64, PCG odd solve, CG E_0, PCG tolerances
  * 1e-12 (residual) / 1e-10 (inner), pcg_max_iter 200, cg_tol 1e-10, cg_max_iter 20000,
- * profile 0. */
+ * profile 0, Richardson inner iteration. */
 void rte_default_solve_opts(rte_solve_opts* opts);
 
 /* Validate the problem and assemble every operator of the mixed system (Sec. 4) on

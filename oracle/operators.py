@@ -130,6 +130,53 @@ class Operators:
             z = z - self.E0_solve(self.E(z) - r)
         return z
 
+    def P1_pcg(self, r, l):
+        """l steps of the conjugate gradient method on E z = r preconditioned by E_0, from
+        z_0 = 0: the non-stationary inner iteration Sec. 5.3 names as the better choice.
+        Inner products are those of the vectorised matrices (sum of elementwise products)."""
+        z = np.zeros_like(r)
+        res = r.copy()
+        y = self.E0_solve(res)
+        p = y.copy()
+        gamma = float(np.sum(res * y))
+        for i in range(l):
+            q = self.E(p)
+            pq = float(np.sum(p * q))
+            alpha = gamma / pq if pq != 0.0 else 0.0
+            z = z + alpha * p
+            if i + 1 == l:
+                break
+            res = res - alpha * q
+            y = self.E0_solve(res)
+            gamma_new = float(np.sum(res * y))
+            beta = gamma_new / gamma if gamma != 0.0 else 0.0
+            p = y + beta * p
+            gamma = gamma_new
+        return z
+
+    def P1_krylov(self, r, l):
+        """The result P1_pcg must reach in exact arithmetic, from its definition rather than the
+        recurrence: the E-orthogonal projection of E^{-1} r onto the Krylov space
+        span{(E_0^{-1} E)^j E_0^{-1} r : j < l}, i.e. z = V (V^T E V)^{-1} V^T r for a basis V.
+        The basis is orthonormalised (Gram-Schmidt, twice) for a stable small solve."""
+        shape = r.shape
+        v = self.E0_solve(r)
+        basis = []
+        for j in range(l):
+            w = v.reshape(-1).copy()
+            for _ in range(2):
+                for b in basis:
+                    w -= np.dot(b, w) * b
+            nw = np.linalg.norm(w)
+            if nw == 0.0:
+                break
+            basis.append(w / nw)
+            v = self.E0_solve(self.E(basis[-1].reshape(shape)))
+        V = np.stack(basis, axis=1)
+        EV = np.stack([self.E(V[:, j].reshape(shape)).reshape(-1) for j in range(V.shape[1])], axis=1)
+        c = np.linalg.solve(V.T @ EV, V.T @ r.reshape(-1))
+        return (V @ c).reshape(shape)
+
     # ------------------------------------------------------------------ subspace correction
     def even_eig(self):
         """W_N+ [nS, d_N] (M_S+-orthonormal) and Lambda_N+ for the d_N = (N+1)(N+2)/2
@@ -190,10 +237,10 @@ class Operators:
         v = self._Ec.solve(Qc.reshape(-1, order="F"))
         return v.reshape(Qc.shape, order="F")
 
-    def P2P1(self, r, l):
+    def P2P1(self, r, l, inner="richardson"):
         """P_2 P_1 r = s + W E_c^{-1} W^T (r - (E - K+) s), s = P_1^l r (product preconditioner,
-        Sec. 5)."""
-        s = self.P1(r, l)
+        Sec. 5); inner="pcg" takes s from P1_pcg instead."""
+        s = self.P1(r, l) if inner == "richardson" else self.P1_pcg(r, l)
         W, _ = self.even_eig()
         qc = (self.EmK(s) - r) @ W
         uc = self.Ec_solve(qc)

@@ -27,8 +27,9 @@ from .operators import Operators
 
 
 def richardson(ops: Operators, l: int = 4, tol: float = 1e-8, max_iter: int = 200, u0=None,
-               callback=None):
-    """Run Alg. 3 from u0 (default 0). Returns (u, info dict)."""
+               callback=None, inner: str = "richardson"):
+    """Run Alg. 3 from u0 (default 0). Returns (u, info dict).  inner="pcg" applies P_1 as
+    l steps of E_0-preconditioned CG (Sec. 5.3's non-stationary alternative)."""
     D = ops.D
     q = D.q
     u = np.zeros_like(q) if u0 is None else np.array(u0, dtype=float)
@@ -52,7 +53,7 @@ def richardson(ops: Operators, l: int = 4, tol: float = 1e-8, max_iter: int = 20
             callback(it, u, r)
         if rel <= tol or it >= max_iter:
             break
-        s = ops.P1(r, l)
+        s = ops.P1(r, l) if inner == "richardson" else ops.P1_pcg(r, l)
         uc = ops.Ec_solve((ops.EmK(s) - r) @ W)
         step = -s + uc @ W.T
         u = u + step

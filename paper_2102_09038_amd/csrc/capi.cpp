@@ -36,6 +36,7 @@ void check_opts(const rte_solve_opts* o) {
     if (o->odd_solver != RTE_ODD_PCG && o->odd_solver != RTE_ODD_EXACT && o->odd_solver != RTE_ODD_CONDENSED)
         rte::fail(RTE_E_ARG, "unknown odd solver");
     if (o->e0_solver != RTE_E0_CG && o->e0_solver != RTE_E0_BANDED) rte::fail(RTE_E_ARG, "unknown E_0 solver");
+    if (o->inner != RTE_INNER_RICHARDSON && o->inner != RTE_INNER_PCG) rte::fail(RTE_E_ARG, "unknown inner iteration");
     if (!(o->pcg_tol_resid > 0) || !(o->pcg_tol_inner > 0) || !(o->cg_tol > 0) || o->pcg_max_iter < 1 ||
         o->cg_max_iter < 1)
         rte::fail(RTE_E_ARG, "inner tolerances must be > 0 and iteration caps >= 1");
@@ -73,6 +74,7 @@ void rte_default_solve_opts(rte_solve_opts* o) {
     o->cg_tol = 1e-10;
     o->cg_max_iter = 20000;
     o->profile = 0;
+    o->inner = RTE_INNER_RICHARDSON;
 }
 
 rte_status rte_assemble(const rte_problem_desc* desc, const rte_assemble_opts* opts, void* hip_stream,

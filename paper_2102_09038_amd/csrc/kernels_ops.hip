@@ -395,9 +395,9 @@ __global__ void xpby_kernel(const double* __restrict__ y, double* __restrict__ p
     for (size_t i = blockIdx.x * (size_t)TPB + threadIdx.x; i < n; i += (size_t)gridDim.x * TPB)
         p[i] = ib >= 0 ? fma(b, p[i], y[i]) : y[i];
 }
-__global__ void axpy_s_kernel(double* __restrict__ y, const double* __restrict__ x,
-                              const double* __restrict__ z, const double* __restrict__ scal, int ia,
-                              double sign, size_t n) {
+// y may be x (in-place update): no restrict on those two
+__global__ void axpy_s_kernel(double* y, const double* x, const double* __restrict__ z,
+                              const double* __restrict__ scal, int ia, double sign, size_t n) {
     const double a = sign * scal[ia];
     for (size_t i = blockIdx.x * (size_t)TPB + threadIdx.x; i < n; i += (size_t)gridDim.x * TPB)
         y[i] = fma(a, z[i], x[i]);

@@ -269,9 +269,52 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
     }
 }
 
-// z = P_1^l r  (Alg. 2 with l steps; z_0 = 0 so the first step is E_0^{-1} r)
+// z = l steps of CG on E z = r preconditioned by E_0, from z_0 = 0 (the non-stationary
+// alternative to P_1^l named in Sec. 5.3).  Inner products are FP64 fixed-order
+// reductions into device scalars; alpha = gamma / p.Ep and beta = gamma' / gamma are formed
+// on the device (0 when the denominator is 0, so r = 0 gives z = 0), so the l steps run
+// without a host synchronisation.  The last step's residual update and E_0 solve are not
+// needed for z and are skipped.
+void apply_P1_pcg(Handle* h, const rte_solve_opts* o, const double* r, double* z, hipStream_t s,
+                  int64_t* pcg, int64_t* cgt, int* cgmax, bool lowp) {
+    const size_t n = (size_t)h->nRp * h->nS;
+    double* res = ws(h, W_IR);
+    double* y = ws(h, W_IY);
+    double* p = ws(h, W_IP);
+    double* q = ws(h, W_IQ);
+    double* scal = h->scal.p;
+    k::fill(z, 0.0, n, s);
+    k::copy(r, res, n, s);
+    e0inv(h, o, res, y, s, cgt, cgmax, lowp);
+    int g = S_IG0, gn = S_IG1;
+    k::dot(res, y, n, h->red.p, s);
+    k::reduce(h->red.p, scal, g, s);
+    k::xpby(y, p, scal, -1, n, s);                                  // p = y
+    for (int i = 0; i < o->l; ++i) {
+        apply_E_core(h, o, p, nullptr, nullptr, q, o->pcg_tol_inner, s, pcg, lowp);   // q = E p
+        k::dot(p, q, n, h->red.p, s);
+        k::reduce(h->red.p, scal, S_IPQ, s);
+        k::sdiv(scal, S_IALPHA, g, S_IPQ, s);
+        k::axpy_s(z, z, p, scal, S_IALPHA, 1.0, n, s);              // z += alpha p
+        if (i + 1 == o->l) break;
+        k::axpy_s(res, res, q, scal, S_IALPHA, -1.0, n, s);         // res -= alpha q
+        e0inv(h, o, res, y, s, cgt, cgmax, lowp);
+        k::dot(res, y, n, h->red.p, s);
+        k::reduce(h->red.p, scal, gn, s);
+        k::sdiv(scal, S_IBETA, gn, g, s);
+        k::xpby(y, p, scal, S_IBETA, n, s);                         // p = y + beta p
+        std::swap(g, gn);
+    }
+}
+
+// z = P_1^l r  (Alg. 2 with l steps; z_0 = 0 so the first step is E_0^{-1} r), or the inner
+// PCG above
 void apply_P1(Handle* h, const rte_solve_opts* o, const double* r, double* z, hipStream_t s,
               int64_t* pcg, int64_t* cgt, int* cgmax, bool lowp) {
+    if (o->inner == RTE_INNER_PCG) {
+        apply_P1_pcg(h, o, r, z, s, pcg, cgt, cgmax, lowp);
+        return;
+    }
     const size_t n = (size_t)h->nRp * h->nS;
     double* t = ws(h, W_ET2);
     double* t2 = ws(h, W_EZ);

@@ -7,7 +7,9 @@ namespace rte {
 namespace sv {
 
 // device scalar slots of a handle (Handle::scal)
-enum Slot { S_BB = 0, S_PW, S_ALPHA, S_RR, S_RZ0, S_RZ1, S_BETA, S_DOT0, S_DOT1, S_DOT2 };
+enum Slot { S_BB = 0, S_PW, S_ALPHA, S_RR, S_RZ0, S_RZ1, S_BETA, S_DOT0, S_DOT1, S_DOT2,
+            // the inner PCG of P_1: two alternating gammas, p.Ep, alpha, beta
+            S_IG0, S_IG1, S_IPQ, S_IALPHA, S_IBETA };
 
 // workspace buffers of a handle (allocated on first use)
 enum WsId {
@@ -17,6 +19,8 @@ enum WsId {
     W_CPART, W_CFIN,
     // even workspace (nRp x nS)
     W_EG, W_ET, W_ER, W_ES, W_ESTEP, W_EZ, W_ET2, W_CGR, W_CGP, W_CGQ,
+    // the inner PCG of P_1: residual, preconditioned residual, direction, E times direction
+    W_IR, W_IY, W_IP, W_IQ,
     // right-hand side and solution of the band solves in band order
     W_BB, W_BX,
     // coarse

@@ -20,6 +20,7 @@ RTE_FP64, RTE_MIXED = 0, 1
 RTE_DT_F64, RTE_DT_F32, RTE_DT_BF16 = 0, 1, 2
 RTE_ODD_PCG, RTE_ODD_EXACT, RTE_ODD_CONDENSED = 0, 1, 2
 RTE_E0_CG, RTE_E0_BANDED = 0, 1
+RTE_INNER_RICHARDSON, RTE_INNER_PCG = 0, 1
 ARRAY_SP, ARRAY_SM, ARRAY_M, ARRAY_T, ARRAY_Q, ARRAY_LAMP, ARRAY_WP, ARRAY_LAMM = range(8)
 STATUS_NAMES = ["OK", "E_ARG", "E_PHYS", "E_MESH", "E_NOMEM", "E_HIP", "E_NOTCONV", "E_NONFINITE"]
 
@@ -43,7 +44,7 @@ class rte_solve_opts(C.Structure):
                 ("precision", C.c_int32), ("odd_solver", C.c_int32), ("e0_solver", C.c_int32),
                 ("pcg_tol_resid", C.c_double), ("pcg_tol_inner", C.c_double),
                 ("pcg_max_iter", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32),
-                ("profile", C.c_int32)]
+                ("profile", C.c_int32), ("inner", C.c_int32)]
 
 
 RTE_TUNE_FORCE = 1

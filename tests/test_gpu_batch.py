@@ -161,6 +161,11 @@ def test_budget_and_requirements(handles):
     with pytest.raises(rte.RteError) as e:        # the PCG odd solve is not batched
         b.admit(hs[0], U1, bad)
     assert e.value.status == rte.RTE_E_ARG
+    bad = opts_for(rte.RTE_MIXED)
+    bad.inner = rte.RTE_INNER_PCG
+    with pytest.raises(rte.RteError) as e:        # nor the inner PCG of P_1
+        b.admit(hs[0], U1, bad)
+    assert e.value.status == rte.RTE_E_ARG
     b.close()
 
 

@@ -211,6 +211,43 @@ def test_deterministic(case):
     assert torch.equal(Y1, Y2)
 
 
+# ----------------------------------------------------------------------------- inner PCG
+@pytest.mark.parametrize("which", [0, 1])
+def test_inner_pcg_precond(case, which):
+    """P_1 as l steps of E_0-preconditioned CG (and P_2 after it) against the oracle's CG."""
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    o = rte.default_solve_opts(l=inst.l + 1, cg_tol=1e-14, cg_max_iter=50000, pcg_tol_resid=1e-14,
+                               pcg_tol_inner=1e-14, pcg_max_iter=500, inner=rte.RTE_INNER_PCG)
+    r = np.random.default_rng(16).standard_normal((D.nRp, D.nS))
+    S = torch.empty_like(to_dev(r))
+    h.precond(which, to_dev(r), S, o)
+    ref = ops.P1_pcg(r, inst.l + 1) if which == 0 else ops.P2P1(r, inst.l + 1, inner="pcg")
+    err = rel(from_dev(S), ref)
+    print(f"[{name}] inner PCG precond {which}: {err:.2e}")
+    assert err < 1e-10
+    Z = torch.empty_like(S)
+    h.precond(which, torch.zeros_like(S), Z, o)
+    assert torch.count_nonzero(Z) == 0          # r = 0: every step size is 0, nothing non-finite
+
+
+def test_inner_pcg_solve(case):
+    """The outer iteration with the inner PCG, on the production path (banded E_0, exact or
+    condensed odd solve), reaches the oracle's iterate with the same inner method."""
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    odd = rte.RTE_ODD_CONDENSED if np.ptp(D.sigma_s / D.sigma_t) == 0 else rte.RTE_ODD_EXACT
+    o = rte.default_solve_opts(l=inst.l, tol=1e-12, odd_solver=odd, e0_solver=rte.RTE_E0_BANDED,
+                               inner=rte.RTE_INNER_PCG)
+    U = torch.empty((D.nS, D.nRp), dtype=torch.float64, device="cuda")
+    st, info = h.solve(U, opts=o)
+    uref, rinfo = richardson(ops, l=inst.l, tol=1e-12, max_iter=200, inner="pcg")
+    print(f"[{name}] inner PCG: gpu iters {info.iters} rel_resid {info.rel_resid:.2e}  oracle iters {rinfo['iters']}")
+    assert info.rel_resid <= 1e-12
+    assert rel(from_dev(U), uref) < 1e-10
+    assert abs(info.iters - rinfo["iters"]) <= 1
+
+
 # ----------------------------------------------------------------------------- mixed precision
 # Bars: one application of the reduced-precision operators carries BF16 / FP32 rounding
 # (BF16 keeps 8 significant bits: relative error ~ 2^-9 per product, averaged over the
@@ -260,6 +297,12 @@ def test_mixed_solve(case):
     uref, rinfo = richardson(ops, l=inst.l, tol=1e-12, max_iter=200)
     err = rel(from_dev(U), uref)
     print(f"[{name}] mixed solve iters {info.iters} (fp64 oracle {rinfo['iters']}) rel err {err:.2e}")
+    assert info.rel_resid <= 1e-10
+    assert err < 1e-6
+    o.inner = rte.RTE_INNER_PCG
+    st, info = h.solve(U, opts=o)
+    err = rel(from_dev(U), uref)
+    print(f"[{name}] mixed solve with inner PCG: iters {info.iters}, rel err {err:.2e}")
     assert info.rel_resid <= 1e-10
     assert err < 1e-6
 

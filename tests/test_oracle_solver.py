@@ -141,3 +141,59 @@ def test_contraction_and_factorisation(g, l):
     eta = np.sqrt(sla.eigh(it.T @ EmK @ it, EmK, eigvals_only=True).max())
     assert eta <= D.c + 1e-9
     assert np.allclose(P1, P1.T, atol=1e-9 * np.abs(P1).max())
+
+
+# ---------------------------------------------------------------- non-stationary inner iteration
+@pytest.mark.parametrize("l", [1, 2, 3, 5])
+def test_inner_pcg_is_the_krylov_projection(l):
+    """l steps of E_0-preconditioned CG from 0 reach the E-orthogonal projection of E^{-1} r
+    onto span{(E_0^{-1} E)^j E_0^{-1} r, j < l}, which P1_krylov forms from an explicit basis
+    and a small dense solve (no recurrence in common with P1_pcg)."""
+    inst, D, ops = build(n=4, sphere_level=1, g=0.8, ratio=0.95)
+    r = np.random.default_rng(50 + l).standard_normal((D.nRp, D.nS))
+    z = ops.P1_pcg(r, l)
+    zk = ops.P1_krylov(r, l)
+    assert np.linalg.norm(z - zk) <= 1e-10 * np.linalg.norm(zk)
+    # Galerkin: the residual r - E z is l2-orthogonal to the Krylov space
+    basis = [ops.E0_solve(r)]
+    for _ in range(l - 1):
+        basis.append(ops.E0_solve(ops.E(basis[-1])))
+    res = r - ops.E(z)
+    for b in basis:
+        assert abs(np.sum(b * res)) <= 1e-10 * np.linalg.norm(b) * np.linalg.norm(r)
+
+
+def test_inner_pcg_beats_richardson_in_energy_and_terminates():
+    """Its E-norm error is never above that of P_1^l r (the Richardson iterate lies in the same
+    Krylov space), and with l at the system's dimension it is E^{-1} r."""
+    inst, D, ops = build(n=2, sphere_level=0, g=0.9, ratio=0.99)
+    n = D.nRp * D.nS
+    E = dense(ops.E, D.nRp, D.nS)
+    r = np.random.default_rng(60).standard_normal((D.nRp, D.nS))
+    x = np.linalg.solve(E, r.reshape(-1, order="F")).reshape(r.shape, order="F")
+
+    def enorm(v):
+        f = v.reshape(-1, order="F")
+        return float(np.sqrt(f @ E @ f))
+    for l in (1, 2, 3, 4, 6):
+        e_pcg = enorm(x - ops.P1_pcg(r, l))
+        e_rich = enorm(x - ops.P1(r, l))
+        assert e_pcg <= e_rich * (1 + 1e-12)
+    assert np.linalg.norm(ops.P1_pcg(r, n) - x) <= 1e-10 * np.linalg.norm(x)
+    assert np.array_equal(ops.P1_pcg(np.zeros_like(r), 3), np.zeros_like(r))
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n=4, sphere_level=1, g=0.5, ratio=0.9),
+    dict(n=3, sphere_level=1, g=0.9, ratio=0.99, n_even=0, l=2),
+])
+def test_richardson_with_inner_pcg_matches_mixed_lu(kw):
+    """The outer iteration keeps its fixed point with the nonlinear inner iteration: it reaches
+    the even block of the direct solve of the mixed system."""
+    inst, D, ops = build(**kw)
+    u, info = richardson(ops, l=inst.l, tol=1e-13, max_iter=200, inner="pcg")
+    up, _ = solve_mixed(D)
+    assert info["rel_resid"] <= 1e-13
+    assert np.linalg.norm(u - up) <= 1e-11 * np.linalg.norm(up)
+    u_r, info_r = richardson(ops, l=inst.l, tol=1e-13, max_iter=200)
+    assert info["iters"] <= info_r["iters"]
