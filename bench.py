@@ -462,6 +462,8 @@ def main():
                          "avg_launch_ms": 1e3 * t_sc / max(n_sc, 1), "launches": n_sc,
                          "flops_per_launch": fl_sc / max(n_sc, 1), "traffic": measured_traffic("gemm_f64_scatter")},
     }
+    # particle balance of the FP64 solution (source = absorption + leakage up to the residual)
+    out["balance"] = h.derived_outputs(U)
     # ---- the mixed-precision form of the same solve: BF16/FP32 preconditioner (condensed
     #      transport GEMM in BF16 with FP32 accumulation, FP32 E_0 band factors), FP64
     #      outer residual, dots and coarse solve

@@ -252,6 +252,21 @@ rte_status rte_precond(rte_handle* h, const rte_solve_opts* opts, int32_t which,
 rte_status rte_solve(rte_handle* h, const rte_solve_opts* opts, const double* U0, double* U_even,
                      double* U_odd, rte_solve_info* info, void* hip_stream);
 
+/* Derived outputs of an even solution U_even (device FP64 n_R+ x n_S+, column-major), e.g.
+ * the iterate rte_solve returns.
+ * phi (device FP64 [n_R+], NULL = not wanted): the scalar flux at the vertices, the integral
+ *   of the intensity over the sphere, phi = U m with m_k = 2|K_k| (the odd part integrates
+ *   to zero).
+ * balance (host FP64 [4], NULL = not wanted): the particle balance obtained by testing
+ *   (E - K+) u = q with the constant 1, whose transport term vanishes (Sec. 2, eq.
+ *   mixed_discrete; A 1 = 0):  [0] source 1^T q,  [1] absorption 1^T (M+ - K+) U,
+ *   [2] leakage 1^T R U (the outflow through the vacuum boundary),  [3] source -
+ *   absorption - leakage, which equals -1^T r for the residual r = (E - K+) U - q.
+ * Sums are FP64 with a fixed order.  Blocking when balance is requested (it allocates a
+ * few small device buffers and reads back per-direction sums); otherwise enqueue only. */
+rte_status rte_derived_outputs(rte_handle* h, const double* U_even, double* phi, double* balance,
+                               void* hip_stream);
+
 /* Copy an assembled array to host memory, for inspection and tests.
  * which: 0 S+ [n_S+ x n_S+], 1 S- [n_S- x n_S-], 2 m_k [n_S+], 3 T_k [n_S+ x 9],
  * 4 q = l+ [n_R+ x n_S+], 5 even eigenvalues [d_N+], 6 even eigenvectors

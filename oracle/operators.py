@@ -177,6 +177,19 @@ class Operators:
         c = np.linalg.solve(V.T @ EV, V.T @ r.reshape(-1))
         return (V @ c).reshape(shape)
 
+    # ------------------------------------------------------------------ derived outputs
+    def derived(self, U):
+        """Scalar flux phi = U m (the integral of the intensity over the sphere: the odd part
+        integrates to zero and the even basis function of direction k has integral m_k), and
+        the balance terms from testing the even equation with the constant 1: source 1^T q,
+        absorption 1^T (M+ - K+) U, leakage 1^T R U (the outflow through the vacuum boundary)."""
+        D = self.D
+        source = float(np.sum(D.q))
+        absorption = float(np.sum(self.M_even(U) - self.K_even(U)))
+        leakage = float(np.sum(self.R(U)))
+        return U @ D.m, {"source": source, "absorption": absorption, "leakage": leakage,
+                         "imbalance": source - absorption - leakage}
+
     # ------------------------------------------------------------------ subspace correction
     def even_eig(self):
         """W_N+ [nS, d_N] (M_S+-orthonormal) and Lambda_N+ for the d_N = (N+1)(N+2)/2

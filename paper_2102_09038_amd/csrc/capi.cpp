@@ -267,6 +267,15 @@ rte_status rte_batch_destroy(rte_batch* b) {
     });
 }
 
+rte_status rte_derived_outputs(rte_handle* hh, const double* U, double* phi, double* balance, void* hip_stream) {
+    return guarded([&] {
+        rte::Handle* h = as_handle(hh);
+        if (!U) rte::fail(RTE_E_ARG, "null U_even");
+        rte::derived_outputs(h, U, phi, balance, as_stream(hip_stream));
+        return RTE_OK;
+    });
+}
+
 rte_status rte_get_array(rte_handle* hh, int32_t which, void* host_dst, size_t host_bytes) {
     return guarded([&] {
         rte::Handle* h = as_handle(hh);

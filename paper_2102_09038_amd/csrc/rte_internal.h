@@ -207,6 +207,7 @@ int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, 
 int batch_step(Batch* B, int outer_iters, hipStream_t s);
 void batch_set_graphs(Batch* B, bool on);
 // band layout autotuning of the E_0 factors (autotune.cpp)
+void derived_outputs(Handle* h, const double* U, double* phi, double* balance, hipStream_t s);
 void autotune(Handle* h, int flags, hipStream_t s, rte_tune_report* rep);
 void set_band_layout(Handle* h, int precision, int H, int P, hipStream_t s);
 int batch_poll(Batch* B, int max_out, int32_t* slots, rte_solve_info* infos, int32_t* statuses);

@@ -103,6 +103,7 @@ EXPORTS = {
     "rte_batch_destroy": (C.c_int, [C.c_void_p]),
     "rte_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "rte_set_band_layout": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]),
+    "rte_derived_outputs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_last_error": (C.c_char_p, []),
 }
 
@@ -308,6 +309,15 @@ class Handle:
         if st != RTE_OK and (raise_on_notconv or st != RTE_E_NOTCONV):
             _check(st)
         return st, info
+
+
+    def derived_outputs(self, U, phi=None, stream=None) -> dict:
+        """Scalar flux into phi (device, n_R+; optional) and the particle balance of U."""
+        bal = np.zeros(4)
+        _check(lib.rte_derived_outputs(self.h, C.c_void_p(U.data_ptr()),
+                                       C.c_void_p(phi.data_ptr() if phi is not None else 0),
+                                       C.c_void_p(bal.ctypes.data), _stream(stream)))
+        return {"source": bal[0], "absorption": bal[1], "leakage": bal[2], "imbalance": bal[3]}
 
 
 class Batch:

@@ -102,6 +102,15 @@ def test_solves_full_size(realistic):
     assert res["mixed"][1] <= 1e-6
     Uf, Um = res["fp64"][0], res["mixed"][0]
     assert float(torch.linalg.norm(Um - Uf) / torch.linalg.norm(Uf)) < 1e-6
+    # derived outputs: the scalar flux is U m; the balance closes to within what the residual
+    # bound allows (|1^T r| <= sqrt(n) ||r|| <= sqrt(n) tol ||q|| and 1^T q >= ||q|| for q >= 0)
+    phi = torch.empty(d.nRp, dtype=torch.float64, device="cuda")
+    b = h.derived_outputs(Uf, phi)
+    m = torch.from_numpy(h.get_array(rte.ARRAY_M, (d.nSp,))).cuda()
+    assert float(torch.linalg.norm(phi - m @ Uf) / torch.linalg.norm(phi)) < 1e-13
+    print(f"balance: source {b['source']:.6e} absorption {b['absorption']:.6e} leakage {b['leakage']:.6e} "
+          f"imbalance {b['imbalance']:.1e}")
+    assert abs(b["imbalance"]) <= np.sqrt(d.nRp * d.nSp) * 1e-10 * b["source"]
 
 
 def test_mixed_apply_E_full_size(realistic):

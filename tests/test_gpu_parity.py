@@ -248,6 +248,29 @@ def test_inner_pcg_solve(case):
     assert abs(info.iters - rinfo["iters"]) <= 1
 
 
+def test_derived_outputs(case):
+    """Scalar flux and balance terms of a random U against the oracle's plain definitions, and
+    the closed balance at a converged solution."""
+    from paper_2102_09038_amd import rte
+    name, inst, D, ops, h = case
+    V = np.random.default_rng(17).standard_normal((D.nRp, D.nS))
+    phi = torch.empty(D.nRp, dtype=torch.float64, device="cuda")
+    b = h.derived_outputs(to_dev(V), phi)
+    phi_ref, b_ref = ops.derived(V)
+    assert rel(phi.cpu().numpy(), phi_ref) < 1e-13
+    scale = abs(b_ref["absorption"]) + abs(b_ref["leakage"]) + abs(b_ref["source"])
+    for key in ("source", "absorption", "leakage", "imbalance"):
+        assert abs(b[key] - b_ref[key]) <= 1e-12 * scale, key
+    odd = rte.RTE_ODD_CONDENSED if np.ptp(D.sigma_s / D.sigma_t) == 0 else rte.RTE_ODD_EXACT
+    U = torch.empty((D.nS, D.nRp), dtype=torch.float64, device="cuda")
+    h.solve(U, opts=rte.default_solve_opts(l=inst.l, tol=1e-12, odd_solver=odd, e0_solver=rte.RTE_E0_BANDED))
+    bs = h.derived_outputs(U)
+    print(f"[{name}] source {bs['source']:.6e} absorption {bs['absorption']:.6e} leakage {bs['leakage']:.6e} "
+          f"imbalance {bs['imbalance']:.1e}")
+    assert abs(bs["imbalance"]) <= 1e-10 * bs["source"]
+    assert h.derived_outputs(U, phi) == bs      # repeatable (fixed-order sums)
+
+
 # ----------------------------------------------------------------------------- mixed precision
 # Bars: one application of the reduced-precision operators carries BF16 / FP32 rounding
 # (BF16 keeps 8 significant bits: relative error ~ 2^-9 per product, averaged over the
