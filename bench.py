@@ -346,6 +346,47 @@ def serve_bench(args, torch, rte, inputs):
     print(json.dumps(serving_runs(torch, rte, inputs, rates, args.requests, args.tol, log=log)))
 
 
+def rates_study(args, torch, rte, inputs):
+    """Convergence rates rho and eta of the iteration matrix (Sec. 6.2) on the lattice
+    stand-in (56 x 56 squares on (0,7)^2, c = 10/10.01): g = 0 over angular grids of
+    16..1024 even directions (N+ = 0, P_1 = E^{-1}), and g in {0.1, 0.5, 0.9} over
+    d_N in {1, 6, 15} and l = 1..4 at 64 even directions (d_N = 15 on 42 x 42 squares)."""
+    from paper_2102_09038_amd.rates import iteration_rates
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    def one(inst, ls):
+        t0 = time.perf_counter()
+        h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED)
+        res = {}
+        for l in ls:
+            o = rte.default_solve_opts(l=l, odd_solver=rte.RTE_ODD_EXACT, e0_solver=rte.RTE_E0_BANDED)
+            r = iteration_rates(h, o, m=80, tol=1e-5)
+            res[l] = {"rho": r["rho"], "eta": r["eta"], "steps": [r["rho_steps"], r["eta_steps"]]}
+            log(f"[rates] {inst.name} N+={inst.n_even} l={l}: rho {r['rho']:.3f} eta {r['eta']:.3f} "
+                f"({time.perf_counter() - t0:.1f} s)")
+        h.close()
+        return res
+
+    out = {"study": "convergence rates rho, eta of (I - P_G)(I - P_1^l (E - K+))",
+           "workload": "lattice stand-in 56x56 on (0,7)^2, sigma_s/sigma_a 10/0.01 and 0/1, c = 0.999",
+           "isotropic": {}, "anisotropic": {}}
+    for lev in (1, 2, 3, 4):
+        inst = inputs.lattice_standin(sphere_level=lev, g=0.0, n_even=0)
+        out["isotropic"][4 ** (lev + 1)] = one(inst, [1])[1]
+    for g in (0.1, 0.5, 0.9):
+        for n_even in (0, 2, 4):
+            # d_N = 15 on the 56 x 56 mesh makes a coarse system of 48735 unknowns whose
+            # explicit inverse (19 GB) exceeds its budget and whose band (885) exceeds the
+            # band solve: that row runs on 42 x 42 squares (the rates are mesh-independent)
+            inst = inputs.lattice_standin(cells_per_unit=8 if n_even < 4 else 6, sphere_level=2, g=g,
+                                          n_even=n_even)
+            d_n = (n_even + 1) * (n_even + 2) // 2
+            out["anisotropic"][f"g={g} d_N={d_n}"] = one(inst, [1, 2, 3, 4])
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,11 +395,12 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the short served-form run")
-    ap.add_argument("--only", choices=["kernels", "batch", "serve"], default=None,
+    ap.add_argument("--only", choices=["kernels", "batch", "serve", "rates"], default=None,
                     help="'kernels': assemble the realistic instance, run the dominant kernels twice each "
                          "and a plain 4 GiB device copy (the reference for HBM counter passes), then exit; "
                          "'batch': the batched form (seeded instances of uneven size, mixed precision, "
-                         "lockstep batch) against the same instances solved one at a time in FP64")
+                         "lockstep batch) against the same instances solved one at a time in FP64; "
+                         "'rates': the convergence-rate study on the lattice stand-in")
     ap.add_argument("--count", type=int, default=64, help="instances of the batched form")
     ap.add_argument("--rates", default="50,200,1000,half",
                     help="served form: Poisson arrival rates in requests/s ('half' = half the capacity "
@@ -380,6 +422,9 @@ def main():
         return
     if args.only == "serve":
         serve_bench(args, torch, rte, inputs)
+        return
+    if args.only == "rates":
+        rates_study(args, torch, rte, inputs)
         return
     inst = inputs.config_realistic()
     ta = time.perf_counter()

@@ -221,6 +221,36 @@ def make_instance(name, dim, n, sphere_level, g, ratio, sigma_t=None, block=8, s
                     svert=svert, stri=stri, q_nodal=q, quad_level=int(quad_level), **kw)
 
 
+def lattice_standin(cells_per_unit: int = 8, sphere_level: int = 2, g: float = 0.5, n_even: int = 4,
+                    l: int = 4, n_odd: int = 5, seed: int = 11, n_absorbers: int = 12,
+                    quad_level=None) -> Instance:
+    """Stand-in for the lattice problem of the paper's numerical section (its block layout is
+    in a figure that is not available): R = (0,7)^2 as 7 x 7 unit blocks, each cut into
+    cells_per_unit^2 squares ("/" diagonal).  n_absorbers blocks (sigma_s = 0, sigma_a = 1),
+    drawn with the seed from the 24 interior blocks other than the centre; the centre block
+    holds the source q = 1 (nodal values on its closed square, 0 elsewhere); every other
+    block scatters (sigma_s = 10, sigma_a = 0.01, so c = 10 / 10.01).  cells_per_unit = 8
+    gives the paper's coarsest n_R+ = 57^2 = 3249."""
+    n = 7 * cells_per_unit
+    vert, cell, sq = grid2d(n)
+    vert = 7.0 * vert
+    blk = sq // cells_per_unit
+    interior = [(i, j) for j in range(1, 6) for i in range(1, 6) if (i, j) != (3, 3)]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pick = rng.choice(len(interior), size=n_absorbers, replace=False)
+    absorbing = {interior[int(t)] for t in pick}
+    is_abs = np.array([(int(a), int(b)) in absorbing for a, b in blk])
+    sigma_s = np.where(is_abs, 0.0, 10.0)
+    sigma_t = np.where(is_abs, 1.0, 10.01)
+    q = ((vert[:, 0] >= 3.0) & (vert[:, 0] <= 4.0) & (vert[:, 1] >= 3.0) & (vert[:, 1] <= 4.0)).astype(np.float64)
+    svert, stri = octahedral_sphere(sphere_level)
+    if quad_level is None:
+        quad_level = default_quad_level(svert, stri, g)
+    return Instance(name=f"lattice-standin-{n}x{n}-s{8 * 4 ** sphere_level}-g{g}", vert=vert, cell=cell,
+                    sigma_t=sigma_t, sigma_s=sigma_s, g=float(g), svert=svert, stri=stri, q_nodal=q,
+                    quad_level=int(quad_level), n_even=n_even, n_odd=n_odd, l=l, tol=1e-8)
+
+
 def config_small() -> Instance:
     """16x16 grid, 128 sphere triangles, g=0.5, sigma_t=1, sigma_s=0.9, disk source,
     l=4, N+=4, N-=5, tol 1e-8 (the paper's benchmark method settings, Sec. 6.4)."""
