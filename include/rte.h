@@ -93,6 +93,22 @@ typedef enum rte_inner {
                                  solves only (the batch refuses it with RTE_E_ARG)    */
 } rte_inner;
 
+/* How the coarse system E_c u_c = q_c of the subspace correction is solved (Sec. 5.4). */
+typedef enum rte_coarse_solver {
+    RTE_COARSE_AUTO = 0,      /* the first of the three below that fits                      */
+    RTE_COARSE_INVERSE = 1,   /* explicit E_c^{-1} (dense Cholesky and inverse on the device,
+                                 once), applied as a matrix-vector product; needs n_c^2 * 8
+                                 bytes <= 12 GiB                                             */
+    RTE_COARSE_BAND = 2,      /* banded Cholesky (host), the band solve on the device; needs
+                                 the half-bandwidth d_N (b + 1) - 1 within the band solve's
+                                 reach (b: spatial bandwidth)                                */
+    RTE_COARSE_BLOCK = 3      /* block-tridiagonal Cholesky on the device (blocks of one
+                                 half-bandwidth: dense factor, triangular solve and rank
+                                 update per block, then inverses of the diagonal factors);
+                                 a solve is a chain of 4 n_c / bw matrix-vector products.
+                                 Single solves only (the batch refuses such a handle)   */
+} rte_coarse_solver;
+
 typedef struct rte_handle rte_handle;   /* opaque; owns all device memory it allocates */
 
 /* Problem statement (Sec. 1, RTE with Henyey-Greenstein scattering and vacuum or
@@ -134,6 +150,8 @@ typedef struct rte_assemble_opts {
                                     Cholesky inverse (the exact and condensed odd solves work,
                                     the PCG odd solve fails with RTE_E_ARG); ignored (the
                                     decomposition is done) when the ratio varies             */
+    int32_t coarse_solver;       /* rte_coarse_solver (default RTE_COARSE_AUTO); RTE_E_ARG if
+                                    the chosen one does not fit                              */
 } rte_assemble_opts;
 
 typedef struct rte_solve_opts {

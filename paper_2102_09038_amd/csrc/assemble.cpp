@@ -221,12 +221,6 @@ struct RocblasCtx {
     }
 };
 
-// The rocSOLVER factorisations of concurrent assemblies (worker threads of the server) run
-// one at a time: each holds this lock from upload to read-back.
-std::mutex& solver_library_mutex() {
-    static std::mutex m;
-    return m;
-}
 
 // Inv = A^{-1} for the SPD matrix given by its lower band (row-major, band[r (bw+1) + bw + c - r]):
 // dense Cholesky factorisation and inverse on the GPU, both triangles filled; what names the
@@ -295,6 +289,7 @@ void syevd(RocblasCtx& rb, hipStream_t s, int n, Vec& A, Vec& lam) {
 
 Handle::~Handle() {
     if (stream) (void)hipStreamSynchronize(stream);
+    coarse_block_release(*this);
     if (pinned) (void)hipHostFree(pinned);
     for (auto& r : prof) { evpool.push_back(r.a); evpool.push_back(r.b); }
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
@@ -305,7 +300,7 @@ size_t Handle::footprint() const {
                Wp.bytes() + Hodd.bytes() + Wfull.bytes() + WfullT.bytes() + lam_full.bytes() + cell.bytes() +
                Dc.bytes() + mt.bytes() + ms.bytes() + rowptr.bytes() + col.bytes() + Msv.bytes() + cls.bytes() +
                coefE0.bytes() + coefE.bytes() + diagE0.bytes() + vc_ptr.bytes() + vc_cell.bytes() + vc_loc.bytes() +
-               q.bytes() + Lc.bytes() + LcU.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() + L0U.bytes() + Ecinv.bytes() +
+               q.bytes() + Lc.bytes() + LcU.bytes() + CLinv.bytes() + CB.bytes() + cwork.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() + L0U.bytes() + Ecinv.bytes() +
                Gc.bytes() + vcD.bytes() +
                MtMs.bytes() + bnd_row.bytes() + cg_iters.bytes() +
                Sp_f.bytes() + Sm_f.bytes() + Gc_bf.bytes() + L0f.bytes() + L0Uf.bytes() + red.bytes() +
@@ -336,6 +331,8 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     if (!D || !o) fail(RTE_E_ARG, "null descriptor or options");
     if (o->mixed < 0 || o->mixed > 2) fail(RTE_E_ARG, "mixed must be 0, 1 or 2");
     if (o->odd_eig != 0 && o->odd_eig != 1) fail(RTE_E_ARG, "odd_eig must be 0 or 1");
+    if (o->coarse_solver < RTE_COARSE_AUTO || o->coarse_solver > RTE_COARSE_BLOCK)
+        fail(RTE_E_ARG, "unknown coarse solver");
     const int d = D->dim;
     if (d != 2 && d != 3) fail(RTE_E_ARG, "dim must be 2 or 3");
     if (D->n_vert < d + 1 || D->n_cell < 1 || !D->vert || !D->cell) fail(RTE_E_ARG, "empty spatial mesh");
@@ -998,16 +995,27 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         }
         h.nc = nc;
         h.cbw = bw;
-        if ((double)nc * nc * sizeof(double) <= kEcinvMaxBytes) {
-            // A single band solve is one wave walking nc rows in sequence, so the coarse
-            // solve uses the explicit inverse instead (dense Cholesky and inverse on the GPU,
-            // once), applied as a bandwidth-bound matrix-vector product.
+        // A single band solve is one wave walking nc rows in sequence, so the coarse solve
+        // uses the explicit inverse where it fits (dense Cholesky and inverse on the GPU, once),
+        // applied as a bandwidth-bound matrix-vector product; else the band solve where the
+        // band fits it; else the block-tridiagonal Cholesky on the device.
+        const bool inv_fits = (double)nc * nc * sizeof(double) <= kEcinvMaxBytes;
+        const bool band_fits = k::band_groups(bw, 2) != 0;
+        int how = o->coarse_solver;
+        if (how == RTE_COARSE_AUTO) how = inv_fits ? RTE_COARSE_INVERSE : band_fits ? RTE_COARSE_BAND : RTE_COARSE_BLOCK;
+        if (how == RTE_COARSE_INVERSE) {
+            if (!inv_fits) fail(RTE_E_ARG, "the explicit coarse inverse exceeds its memory budget");
             dense_spd_inverse(rb, s, band, nc, bw, h.Ecinv, "the coarse matrix E_c");
-        } else {
-            if (k::band_groups(bw, 2) == 0) fail(RTE_E_ARG, "coarse band too wide for the band solve");
+        } else if (how == RTE_COARSE_BAND) {
+            if (!band_fits) fail(RTE_E_ARG, "coarse band too wide for the band solve");
             band_cholesky(band, nc, bw);
             h.Lc.upload(band_to_blocked(band, nc, bw, false), s);
             h.LcU.upload(band_to_blocked(band, nc, bw, true), s);
+        } else {
+            DBuf<double> dband;
+            dband.upload(band, s);
+            coarse_block_factor(h, dband.p, nc, bw, s);
+            RTE_HIP(hipStreamSynchronize(s));
         }
         h.perm.upload(perm, s);
         h.iperm.upload(iperm, s);
@@ -1132,9 +1140,21 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
     b += (size_t)nRm * (nv * 4 + nv * d * 8 + 4 * 8) + nnz * (4 + 8 * (kMaxClasses + 4)) + (size_t)nRp * 16;
     b += (size_t)nRm * nv * (4 + 4 + d * 8) + nS * kMaxClasses * 8 * 3 + even * 8;
     // coarse solve: explicit inverse or band factors
-    if ((double)nc * nc * 8 <= kEcinvMaxBytes) b += nc * nc * 8;
-    else b += 2 * k::band_blk_size((int)nc, (int)cbw, 2) * 8;
     size_t transient = 0;
+    {
+        const bool inv_fits = (double)nc * nc * 8 <= kEcinvMaxBytes, band_fits = k::band_groups((int)cbw, 2) != 0;
+        int how = o->coarse_solver;
+        if (how == RTE_COARSE_AUTO) how = inv_fits ? RTE_COARSE_INVERSE : band_fits ? RTE_COARSE_BAND : RTE_COARSE_BLOCK;
+        if (how == RTE_COARSE_INVERSE) {
+            b += nc * nc * 8;
+        } else if (how == RTE_COARSE_BAND) {
+            b += 2 * k::band_blk_size((int)nc, (int)cbw, 2) * 8;
+        } else {
+            const size_t bs = std::max<size_t>(cbw, 1), nbk = (nc + bs - 1) / bs;
+            b += (2 * nbk - 1) * bs * bs * 8 + nbk * bs * 8;
+            transient = std::max(transient, nc * (cbw + 1) * 8);   // the band on its way to the blocks
+        }
+    }
     if (o->e0_solver == RTE_E0_BANDED) {
         const size_t f64 = 2 * k::band_blk_size(nRp, sbw, 2) * nS * 8;
         if (o->mixed != 2) b += f64;

@@ -58,6 +58,7 @@ void rte_default_assemble_opts(rte_assemble_opts* o) {
     o->e0_solver = RTE_E0_CG;
     o->mixed = 0;
     o->odd_eig = 1;
+    o->coarse_solver = RTE_COARSE_AUTO;
 }
 
 void rte_default_solve_opts(rte_solve_opts* o) {

@@ -1,0 +1,158 @@
+// Coarse solve of the subspace correction (Sec. 5.4, eq. corr_discrete) for coarse systems
+// whose explicit inverse does not fit its memory budget and whose band is wider than the
+// band solve takes (a large correction space d_N on a large mesh: N+ = 4 on 128 x 128 squares
+// gives 249615 unknowns with half-bandwidth 1949).
+//
+// In the band (vertex-major) order the coarse matrix E_c has half-bandwidth bw, so cut into
+// blocks of bs = bw rows it is block tridiagonal: block row k couples to blocks k-1, k, k+1
+// only.  Its Cholesky factor is block lower bidiagonal,
+//     E_c = L L^T,  L = [L_0; C_0 L_1; C_1 L_2; ...],
+// computed on the device block by block with library dense kernels:
+//     L_k = chol(D_k),  C_k = B_k L_k^{-T},  D_{k+1} -= C_k C_k^T,
+// where D_k is the k-th diagonal block and B_k the block below it.  The diagonal factors are
+// then inverted (triangular inverse), so that a solve is a chain of matrix-vector products:
+//     forward   z_k = L_k^{-1} (b_k - C_{k-1} z_{k-1})
+//     backward  x_k = L_k^{-T} (z_k - C_k^T x_{k+1}).
+// Rows past n (the last block's padding) are an identity block decoupled from the rest.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <mutex>
+#include <shared_mutex>
+#include <string>
+
+#include "ops.h"
+
+namespace rte {
+namespace {
+
+constexpr int TPB = 256;
+
+// D_k (column-major bs x bs, lower triangle) and B_k (rows of block k+1, columns of block k)
+// from the row-major lower band band[r (bw+1) + bw + c - r]
+__global__ __launch_bounds__(TPB) void band_to_blocks_kernel(const double* __restrict__ band, int n, int bw, int bs,
+                                                             int nb, double* __restrict__ D, double* __restrict__ B) {
+    const size_t w1 = (size_t)bw + 1, blk = (size_t)bs * bs;
+    const size_t nD = (size_t)nb * blk, nB = (size_t)(nb - 1) * blk;
+    for (size_t t = blockIdx.x * (size_t)TPB + threadIdx.x; t < nD + nB; t += (size_t)gridDim.x * TPB) {
+        const bool isD = t < nD;
+        const size_t u = isD ? t : t - nD;
+        const int k = (int)(u / blk);
+        const int i = (int)(u % blk % bs), j = (int)(u % blk / bs);
+        const long r = (long)(isD ? k : k + 1) * bs + i, c = (long)k * bs + j;
+        double v = 0.0;
+        if (r >= c && r - c <= bw) {
+            if (r < n) v = band[(size_t)r * w1 + (size_t)(bw + c - r)];
+            else if (r == c) v = 1.0;
+        }
+        (isD ? D : B)[u] = v;
+    }
+}
+
+struct LibLock {
+    std::lock_guard<std::mutex> serial{solver_library_mutex()};
+    std::shared_lock<std::shared_mutex> capture{capture_mutex()};
+};
+
+void check_rb(rocblas_status st, const char* what) {
+    if (st != rocblas_status_success) fail(RTE_E_HIP, std::string(what) + " failed");
+}
+
+}  // namespace
+
+void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStream_t s) {
+    if (bw < 1) fail(RTE_E_ARG, "the block coarse factorisation needs a band half-width >= 1");
+    const int bs = bw, nb = (n + bs - 1) / bs;
+    const size_t blk = (size_t)bs * bs;
+    h.cbs = bs;
+    h.cnb = nb;
+    h.CLinv.alloc((size_t)nb * blk);
+    h.CB.alloc((size_t)(nb > 1 ? nb - 1 : 0) * blk);
+    h.cwork.alloc((size_t)nb * bs);
+    {
+        const size_t tot = (size_t)(2 * nb - 1) * blk;
+        const int grid = (int)std::min<size_t>((tot + TPB - 1) / TPB, 65535u * 8);
+        hipLaunchKernelGGL(band_to_blocks_kernel, dim3(grid), dim3(TPB), 0, s, dband, n, bw, bs, nb, h.CLinv.p,
+                           h.CB.p);
+        RTE_CHECK_LAUNCH();
+    }
+    LibLock lk;
+    rocblas_handle rb = nullptr;
+    check_rb(rocblas_create_handle(&rb), "rocblas_create_handle");
+    rocblas_set_stream(rb, s);
+    DBuf<int> info((size_t)2 * nb);
+    try {
+        const double one = 1.0, minus_one = -1.0;
+        for (int k = 0; k < nb; ++k) {
+            double* Dk = h.CLinv.p + (size_t)k * blk;
+            check_rb(rocsolver_dpotrf(rb, rocblas_fill_lower, bs, Dk, bs, info.p + k), "rocsolver_dpotrf");
+            if (k + 1 < nb) {
+                double* Bk = h.CB.p + (size_t)k * blk;
+                check_rb(rocblas_dtrsm(rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                                       rocblas_diagonal_non_unit, bs, bs, &one, Dk, bs, Bk, bs),
+                         "rocblas_dtrsm");
+                check_rb(rocblas_dsyrk(rb, rocblas_fill_lower, rocblas_operation_none, bs, bs, &minus_one, Bk, bs,
+                                       &one, Dk + blk, bs),
+                         "rocblas_dsyrk");
+            }
+        }
+        for (int k = 0; k < nb; ++k)
+            check_rb(rocsolver_dtrtri(rb, rocblas_fill_lower, rocblas_diagonal_non_unit, bs,
+                                      h.CLinv.p + (size_t)k * blk, bs, info.p + nb + k),
+                     "rocsolver_dtrtri");
+        const std::vector<int> hinfo = info.download(s);
+        for (int k = 0; k < nb; ++k)
+            if (hinfo[k] != 0)
+                fail(RTE_E_ARG, "the coarse matrix E_c is not positive definite (block " + std::to_string(k) +
+                                    ", pivot " + std::to_string(hinfo[k]) + ")");
+        for (int k = 0; k < nb; ++k)
+            if (hinfo[nb + k] != 0) fail(RTE_E_HIP, "rocsolver_dtrtri: singular coarse Cholesky block");
+    } catch (...) {
+        rocblas_destroy_handle(rb);
+        throw;
+    }
+    h.coarse_rb = rb;
+}
+
+void coarse_block_release(Handle& h) {
+    if (h.coarse_rb) {
+        std::shared_lock<std::shared_mutex> lk(capture_mutex());
+        rocblas_destroy_handle(static_cast<rocblas_handle>(h.coarse_rb));
+        h.coarse_rb = nullptr;
+    }
+}
+
+void coarse_block_solve(Handle* h, const double* rhs, double* x, hipStream_t s) {
+    const int bs = h->cbs, nb = h->cnb, n = h->nc;
+    const size_t blk = (size_t)bs * bs;
+    auto rb = static_cast<rocblas_handle>(h->coarse_rb);
+    double* y = h->cwork.p;
+    k::fill(y, 0.0, (size_t)nb * bs, s);
+    k::copy(rhs, y, (size_t)n, s);
+    std::shared_lock<std::shared_mutex> lk(capture_mutex());
+    check_rb(rocblas_set_stream(rb, s), "rocblas_set_stream");
+    const double one = 1.0, minus_one = -1.0;
+    for (int k = 0; k < nb; ++k) {
+        double* yk = y + (size_t)k * bs;
+        if (k > 0)
+            check_rb(rocblas_dgemv(rb, rocblas_operation_none, bs, bs, &minus_one, h->CB.p + (size_t)(k - 1) * blk,
+                                   bs, yk - bs, 1, &one, yk, 1),
+                     "rocblas_dgemv");
+        check_rb(rocblas_dtrmv(rb, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, bs,
+                               h->CLinv.p + (size_t)k * blk, bs, yk, 1),
+                 "rocblas_dtrmv");
+    }
+    for (int k = nb - 1; k >= 0; --k) {
+        double* yk = y + (size_t)k * bs;
+        if (k + 1 < nb)
+            check_rb(rocblas_dgemv(rb, rocblas_operation_transpose, bs, bs, &minus_one, h->CB.p + (size_t)k * blk, bs,
+                                   yk + bs, 1, &one, yk, 1),
+                     "rocblas_dgemv");
+        check_rb(rocblas_dtrmv(rb, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit, bs,
+                               h->CLinv.p + (size_t)k * blk, bs, yk, 1),
+                 "rocblas_dtrmv");
+    }
+    k::copy(y, x, (size_t)n, s);
+}
+
+}  // namespace rte

@@ -45,6 +45,13 @@ inline std::shared_mutex& capture_mutex() {
     return m;
 }
 
+// The rocSOLVER factorisations of concurrent assemblies (worker threads of the server) run
+// one at a time: each holds this lock from upload to read-back.
+inline std::mutex& solver_library_mutex() {
+    static std::mutex m;
+    return m;
+}
+
 // ----------------------------------------------------------------------------- buffers
 // Owning device buffer (hipMalloc / hipFree); movable, not copyable.
 template <typename T>
@@ -147,6 +154,12 @@ struct Handle {
     int nc = 0, cbw = 0;
     DBuf<double> Lc, LcU;          // blocked band factor, rows of L and of L^T (kernels_band.hip)
     DBuf<double> Ecinv;            // explicit E_c^{-1} (nc x nc, band order) when it fits its budget
+    // block-tridiagonal Cholesky of E_c (coarse_block.hip) for wide coarse bands: cnb blocks
+    // of cbs rows; inverses of the diagonal factors, the scaled sub-diagonal blocks, a work
+    // vector and the rocBLAS handle of the solve
+    int cbs = 0, cnb = 0;
+    DBuf<double> CLinv, CB, cwork;
+    void* coarse_rb = nullptr;
     DBuf<int> perm, iperm;         // [nRp] spatial reordering (reverse Cuthill-McKee) and inverse
     int sbw = 0;                   // spatial band width in that order
 
@@ -208,6 +221,9 @@ int batch_step(Batch* B, int outer_iters, hipStream_t s);
 void batch_set_graphs(Batch* B, bool on);
 // band layout autotuning of the E_0 factors (autotune.cpp)
 void derived_outputs(Handle* h, const double* U, double* phi, double* balance, hipStream_t s);
+void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStream_t s);
+void coarse_block_release(Handle& h);
+void coarse_block_solve(Handle* h, const double* rhs, double* x, hipStream_t s);
 void autotune(Handle* h, int flags, hipStream_t s, rte_tune_report* rep);
 void set_band_layout(Handle* h, int precision, int H, int P, hipStream_t s);
 int batch_poll(Batch* B, int max_out, int32_t* slots, rte_solve_info* infos, int32_t* statuses);

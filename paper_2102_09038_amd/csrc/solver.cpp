@@ -337,6 +337,7 @@ void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const 
     double* uc = ws(h, W_CSOL);
     k::coarse_project(h, t, rhs, s);
     if (h->Ecinv.p) k::gemv_rows(h->nc, h->Ecinv.p, rhs, uc, s);
+    else if (h->cnb) coarse_block_solve(h, rhs, uc, s);
     else k::band_solve_blk(h->Lc.p, h->LcU.p, h->nc, h->cbw, 1, 0, rhs, uc, 0, nullptr, s);
     k::fill(step, 0.0, n, s);
     k::richardson_update(h, step, sv, uc, s);

@@ -228,6 +228,7 @@ int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, 
         fail(RTE_E_ARG, "batch slots need the banded E_0 solve (assemble with e0_solver = RTE_E0_BANDED)");
     if (o->odd_solver == RTE_ODD_PCG) fail(RTE_E_ARG, "batch slots use the exact or condensed odd solve");
     if (o->inner != RTE_INNER_RICHARDSON) fail(RTE_E_ARG, "batch slots use the Richardson inner iteration");
+    if (h->cnb) fail(RTE_E_ARG, "batch slots need a coarse solve without library calls (not RTE_COARSE_BLOCK)");
     if (o->precision == RTE_MIXED && !(h->have_mixed && h->L0f.p))
         fail(RTE_E_ARG, "a mixed-precision slot needs a handle assembled with mixed != 0");
     if (o->precision == RTE_FP64 && !h->L0.p) fail(RTE_E_ARG, "an FP64 slot needs the FP64 band factors");

@@ -271,6 +271,37 @@ def test_derived_outputs(case):
     assert h.derived_outputs(U, phi) == bs      # repeatable (fixed-order sums)
 
 
+@pytest.mark.parametrize("name,coarse", [("tiny2d", "band"), ("tiny2d", "block"), ("small", "block")])
+def test_coarse_solvers(name, coarse):
+    """The correction's coarse system solved by the band solve or by the block-tridiagonal
+    Cholesky instead of the explicit inverse: P_2 P_1 r and the converged iterate against the
+    oracle (sparse LU of E_c).  The small instance has 4335 coarse unknowns in blocks of one
+    half-bandwidth, the last one ragged."""
+    from paper_2102_09038_amd import rte
+    inst = CASES[name]()
+    how = {"band": rte.RTE_COARSE_BAND, "block": rte.RTE_COARSE_BLOCK}[coarse]
+    print(f"[{name}] coarse solver {coarse}", flush=True)
+    D, ops, h = make(inst, e0_solver=rte.RTE_E0_BANDED, coarse_solver=how)
+    o = rte.default_solve_opts(l=inst.l, tol=1e-12, odd_solver=rte.RTE_ODD_EXACT, e0_solver=rte.RTE_E0_BANDED)
+    r = np.random.default_rng(18).standard_normal((D.nRp, D.nS))
+    S = torch.empty_like(to_dev(r))
+    h.precond(1, to_dev(r), S, o)
+    err = rel(from_dev(S), ops.P2P1(r, inst.l))
+    U = torch.empty((D.nS, D.nRp), dtype=torch.float64, device="cuda")
+    st, info = h.solve(U, opts=o)
+    uref, rinfo = richardson(ops, l=inst.l, tol=1e-12, max_iter=200)
+    eu = rel(from_dev(U), uref)
+    print(f"[{name} {coarse}] P2P1 {err:.2e}; solve {info.iters} iters (oracle {rinfo['iters']}), {eu:.2e}")
+    assert err < 1e-10 and eu < 1e-10
+    if coarse == "block":
+        b = rte.Batch(max_slots=2)
+        with pytest.raises(rte.RteError) as e:
+            b.admit(h, U, o)
+        assert e.value.status == rte.RTE_E_ARG
+        b.close()
+    h.close()
+
+
 # ----------------------------------------------------------------------------- mixed precision
 # Bars: one application of the reduced-precision operators carries BF16 / FP32 rounding
 # (BF16 keeps 8 significant bits: relative error ~ 2^-9 per product, averaged over the
