@@ -556,6 +556,26 @@ def main():
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "avg_launch_ms": 1e3 * t_e0m / max(n_e0m, 1),
                        "bytes_per_launch": e0m_bytes, "traffic": measured_traffic("band_solve_f32")},
     }
+    # ---- the same workload with the larger correction space N+ = 4 (d_N = 15, 249615 coarse
+    #      unknowns solved by the block-tridiagonal Cholesky)
+    h4 = rte.Handle.from_instance(inputs.config_realistic(n_even=4), e0_solver=rte.RTE_E0_BANDED, mixed=1, odd_eig=0)
+    out["n_even_4"] = {}
+    for name, base_opts in (("fp64", opts), ("mixed", mopts)):
+        o4 = rte.default_solve_opts(l=base_opts.l, tol=base_opts.tol, max_iter=base_opts.max_iter,
+                                    odd_solver=base_opts.odd_solver, e0_solver=base_opts.e0_solver,
+                                    precision=base_opts.precision)
+        U4 = torch.empty_like(U)
+        for _ in range(args.warmup):
+            h4.solve(U4, opts=o4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        i4 = [h4.solve(U4, opts=o4)[1] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        dt4 = time.perf_counter() - t0
+        out["n_even_4"][name] = {"value": args.steps / dt4, "unit": "solves/s", "ms_per_step": 1e3 * dt4 / args.steps,
+                                 "iters": [i.iters for i in i4], "rel_resid": [i.rel_resid for i in i4],
+                                 "rel_diff_vs_fp64_solution": float(torch.linalg.norm(U4 - U64) / torch.linalg.norm(U64))}
+    h4.close()
     # ---- P_1 as l steps of E_0-preconditioned CG (the non-stationary inner iteration of
     #      Sec. 5.3) instead of P_1^l, in both precisions; same workload and residual
     out["inner_pcg"] = {}

@@ -104,8 +104,10 @@ typedef enum rte_coarse_solver {
                                  reach (b: spatial bandwidth)                                */
     RTE_COARSE_BLOCK = 3      /* block-tridiagonal Cholesky on the device (blocks of one
                                  half-bandwidth: dense factor, triangular solve and rank
-                                 update per block, then inverses of the diagonal factors);
-                                 a solve is a chain of 4 n_c / bw matrix-vector products.
+                                 update per block, then inverses of the diagonal factors
+                                 folded into the coupling blocks); a solve is two
+                                 block-diagonal products and two chains of n_c / bw
+                                 matrix-vector products.
                                  Single solves only (the batch refuses such a handle)   */
 } rte_coarse_solver;
 

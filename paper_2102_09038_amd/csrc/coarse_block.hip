@@ -10,9 +10,12 @@
 // computed on the device block by block with library dense kernels:
 //     L_k = chol(D_k),  C_k = B_k L_k^{-T},  D_{k+1} -= C_k C_k^T,
 // where D_k is the k-th diagonal block and B_k the block below it.  The diagonal factors are
-// then inverted (triangular inverse), so that a solve is a chain of matrix-vector products:
-//     forward   z_k = L_k^{-1} (b_k - C_{k-1} z_{k-1})
-//     backward  x_k = L_k^{-T} (z_k - C_k^T x_{k+1}).
+// then inverted (triangular inverse) and folded into the coupling blocks,
+//     F_k = L_k^{-1} C_{k-1},   G_k = C_k L_k^{-1},
+// so that a solve is one block-diagonal product and one chain of matrix-vector products per
+// sweep:
+//     forward   w = diag(L_k^{-1}) b,     z_k = w_k - F_k z_{k-1}
+//     backward  v = diag(L_k^{-T}) z,     x_k = v_k - G_k^T x_{k+1}.
 // Rows past n (the last block's padding) are an identity block decoupled from the rest.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -68,7 +71,8 @@ void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStrea
     h.cnb = nb;
     h.CLinv.alloc((size_t)nb * blk);
     h.CB.alloc((size_t)(nb > 1 ? nb - 1 : 0) * blk);
-    h.cwork.alloc((size_t)nb * bs);
+    h.CG.alloc((size_t)(nb > 1 ? nb - 1 : 0) * blk);
+    h.cwork.alloc((size_t)2 * nb * bs);
     {
         const size_t tot = (size_t)(2 * nb - 1) * blk;
         const int grid = (int)std::min<size_t>((tot + TPB - 1) / TPB, 65535u * 8);
@@ -100,6 +104,24 @@ void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStrea
             check_rb(rocsolver_dtrtri(rb, rocblas_fill_lower, rocblas_diagonal_non_unit, bs,
                                       h.CLinv.p + (size_t)k * blk, bs, info.p + nb + k),
                      "rocsolver_dtrtri");
+        // G_k = C_k L_k^{-1} into CG, then F_k = L_k^{-1} C_{k-1} over C_{k-1} in CB (the strictly
+        // upper triangles of the L_k^{-1} blocks are zero)
+        const double zero = 0.0;
+        for (int k = 0; k + 1 < nb; ++k)
+            check_rb(rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, bs, bs, bs, &one,
+                                   h.CB.p + (size_t)k * blk, bs, h.CLinv.p + (size_t)k * blk, bs, &zero,
+                                   h.CG.p + (size_t)k * blk, bs),
+                     "rocblas_dgemm");
+        DBuf<double> tmp(nb > 1 ? blk : 0);
+        for (int k = 1; k < nb; ++k) {
+            check_rb(rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, bs, bs, bs, &one,
+                                   h.CLinv.p + (size_t)k * blk, bs, h.CB.p + (size_t)(k - 1) * blk, bs, &zero,
+                                   tmp.p, bs),
+                     "rocblas_dgemm");
+            RTE_HIP(hipMemcpyAsync(h.CB.p + (size_t)(k - 1) * blk, tmp.p, blk * sizeof(double),
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        RTE_HIP(hipStreamSynchronize(s));
         const std::vector<int> hinfo = info.download(s);
         for (int k = 0; k < nb; ++k)
             if (hinfo[k] != 0)
@@ -124,34 +146,31 @@ void coarse_block_release(Handle& h) {
 
 void coarse_block_solve(Handle* h, const double* rhs, double* x, hipStream_t s) {
     const int bs = h->cbs, nb = h->cnb, n = h->nc;
-    const size_t blk = (size_t)bs * bs;
+    const size_t blk = (size_t)bs * bs, np = (size_t)nb * bs;
     auto rb = static_cast<rocblas_handle>(h->coarse_rb);
     double* y = h->cwork.p;
-    k::fill(y, 0.0, (size_t)nb * bs, s);
+    double* z = h->cwork.p + np;
+    k::fill(y, 0.0, np, s);
     k::copy(rhs, y, (size_t)n, s);
     std::shared_lock<std::shared_mutex> lk(capture_mutex());
     check_rb(rocblas_set_stream(rb, s), "rocblas_set_stream");
-    const double one = 1.0, minus_one = -1.0;
-    for (int k = 0; k < nb; ++k) {
-        double* yk = y + (size_t)k * bs;
-        if (k > 0)
-            check_rb(rocblas_dgemv(rb, rocblas_operation_none, bs, bs, &minus_one, h->CB.p + (size_t)(k - 1) * blk,
-                                   bs, yk - bs, 1, &one, yk, 1),
-                     "rocblas_dgemv");
-        check_rb(rocblas_dtrmv(rb, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, bs,
-                               h->CLinv.p + (size_t)k * blk, bs, yk, 1),
-                 "rocblas_dtrmv");
-    }
-    for (int k = nb - 1; k >= 0; --k) {
-        double* yk = y + (size_t)k * bs;
-        if (k + 1 < nb)
-            check_rb(rocblas_dgemv(rb, rocblas_operation_transpose, bs, bs, &minus_one, h->CB.p + (size_t)k * blk, bs,
-                                   yk + bs, 1, &one, yk, 1),
-                     "rocblas_dgemv");
-        check_rb(rocblas_dtrmv(rb, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit, bs,
-                               h->CLinv.p + (size_t)k * blk, bs, yk, 1),
-                 "rocblas_dtrmv");
-    }
+    const double one = 1.0, minus_one = -1.0, zero = 0.0;
+    // forward: z = diag(L_k^{-1}) y, then z_k -= F_k z_{k-1}
+    check_rb(rocblas_dgemv_strided_batched(rb, rocblas_operation_none, bs, bs, &one, h->CLinv.p, bs, blk, y, 1, bs,
+                                           &zero, z, 1, bs, nb),
+             "rocblas_dgemv_strided_batched");
+    for (int k = 1; k < nb; ++k)
+        check_rb(rocblas_dgemv(rb, rocblas_operation_none, bs, bs, &minus_one, h->CB.p + (size_t)(k - 1) * blk, bs,
+                               z + (size_t)(k - 1) * bs, 1, &one, z + (size_t)k * bs, 1),
+                 "rocblas_dgemv");
+    // backward: y = diag(L_k^{-T}) z, then y_k -= G_k^T y_{k+1}
+    check_rb(rocblas_dgemv_strided_batched(rb, rocblas_operation_transpose, bs, bs, &one, h->CLinv.p, bs, blk, z, 1,
+                                           bs, &zero, y, 1, bs, nb),
+             "rocblas_dgemv_strided_batched");
+    for (int k = nb - 2; k >= 0; --k)
+        check_rb(rocblas_dgemv(rb, rocblas_operation_transpose, bs, bs, &minus_one, h->CG.p + (size_t)k * blk, bs,
+                               y + (size_t)(k + 1) * bs, 1, &one, y + (size_t)k * bs, 1),
+                 "rocblas_dgemv");
     k::copy(y, x, (size_t)n, s);
 }
 
