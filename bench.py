@@ -350,7 +350,7 @@ def rates_study(args, torch, rte, inputs):
     """Convergence rates rho and eta of the iteration matrix (Sec. 6.2) on the lattice
     stand-in (56 x 56 squares on (0,7)^2, c = 10/10.01): g = 0 over angular grids of
     16..1024 even directions (N+ = 0, P_1 = E^{-1}), and g in {0.1, 0.5, 0.9} over
-    d_N in {1, 6, 15} and l = 1..4 at 64 even directions (d_N = 15 on 42 x 42 squares)."""
+    d_N in {1, 6, 15} and l = 1..4 at 64 even directions."""
     from paper_2102_09038_amd.rates import iteration_rates
 
     def log(msg):
@@ -377,11 +377,8 @@ def rates_study(args, torch, rte, inputs):
         out["isotropic"][4 ** (lev + 1)] = one(inst, [1])[1]
     for g in (0.1, 0.5, 0.9):
         for n_even in (0, 2, 4):
-            # d_N = 15 on the 56 x 56 mesh makes a coarse system of 48735 unknowns whose
-            # explicit inverse (19 GB) exceeds its budget and whose band (885) exceeds the
-            # band solve: that row runs on 42 x 42 squares (the rates are mesh-independent)
-            inst = inputs.lattice_standin(cells_per_unit=8 if n_even < 4 else 6, sphere_level=2, g=g,
-                                          n_even=n_even)
+            # d_N = 15 makes a coarse system of 48735 unknowns: block-tridiagonal Cholesky
+            inst = inputs.lattice_standin(sphere_level=2, g=g, n_even=n_even)
             d_n = (n_even + 1) * (n_even + 2) // 2
             out["anisotropic"][f"g={g} d_N={d_n}"] = one(inst, [1, 2, 3, 4])
     print(json.dumps(out))

@@ -68,7 +68,7 @@ def test_rates_on_lattice_standin_match_paper_tables():
                 rho_p, eta_p = float(f[2]), float(f[3])
             else:
                 g, d_n, l = float(f[1]), int(f[2]), int(f[3])
-                h, tol = handle(2, g, {1: 0, 6: 2}[d_n]), 0.015
+                h, tol = handle(2, g, {1: 0, 6: 2, 15: 4}[d_n]), 0.015
                 rho_p, eta_p = float(f[4]), float(f[5])
             o = rte.default_solve_opts(l=l, odd_solver=rte.RTE_ODD_EXACT, e0_solver=rte.RTE_E0_BANDED)
             r = iteration_rates(h, o, m=80, tol=1e-6)
