@@ -156,6 +156,11 @@ __global__ __launch_bounds__(TPB) void at_e_kernel(
 // cell's 64 directions are one contiguous read), into an LDS tile; then the threads turn to
 // run along the vertices for the mass, boundary and source terms, whose vectors are
 // column-major, and write Y coalesced.
+//
+// Both phases load their index data first and then issue all the dependent loads of a
+// batch at once (KI incidences of a vertex; the RMAX entries of a pattern row, kept in
+// registers for all of the thread's directions), so that a vertex costs one or two memory
+// round trips instead of one per entry.  The sums run in the same order as entry by entry.
 template <int D, typename ZT>
 __global__ __launch_bounds__(256) void at_e_rm_kernel(
     int nRp, int nS, int nnz, int ncls, int nstiff, int nb, const int* __restrict__ vc_ptr,
@@ -165,21 +170,48 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
     const double* __restrict__ X, const double* __restrict__ G, const double* __restrict__ q,
     double* __restrict__ Y) {
     constexpr int TI = 32, TK = 64;
+    constexpr int KI = 8;                    // incidences per batch
+    constexpr int RMAX = D == 2 ? 8 : 16;    // pattern entries held in registers
     __shared__ double T[TI][TK + 1];
     const int i0 = blockIdx.x * TI, k0 = blockIdx.y * TK;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const size_t dn = (size_t)D * nS;
     {
-        const int k = k0 + lane;
-        const bool kin = k < nS;
+        // lanes past the last direction read direction nS - 1 (in bounds) and their sums are
+        // never used; a batch's missing incidences re-read the vertex's last one and are
+        // skipped in the sum, so every load is unconditional and the batch's loads are in
+        // flight together
+        const int k = min(k0 + lane, nS - 1);
         for (int il = wave; il < TI; il += 4) {
             const int i = i0 + il;
             double acc = 0.0;
-            if (i < nRp && kin) {
-                for (int e = vc_ptr[i]; e < vc_ptr[i + 1]; ++e) {
-                    const ZT* zr = Z + (size_t)vc_cell[e] * dn + k;
+            if (i < nRp) {
+                const int e0 = vc_ptr[i], e1 = vc_ptr[i + 1];
+                for (int eb = e0; eb < e1; eb += KI) {
+                    int cj[KI];
+                    double w[KI][D];
+                    ZT z[KI][D];        // converted only when summed
 #pragma unroll
-                    for (int n = 0; n < D; ++n) acc = fma(vcD[(size_t)e * D + n], (double)zr[(size_t)n * nS], acc);
+                    for (int t = 0; t < KI; ++t) {
+                        const int e = min(eb + t, e1 - 1);
+                        cj[t] = vc_cell[e];
+#pragma unroll
+                        for (int n = 0; n < D; ++n) w[t][n] = vcD[(size_t)e * D + n];
+                    }
+#pragma unroll
+                    for (int t = 0; t < KI; ++t) {
+                        const ZT* zr = Z + (size_t)cj[t] * dn + k;
+#pragma unroll
+                        for (int n = 0; n < D; ++n) z[t][n] = zr[(size_t)n * nS];
+                    }
+#pragma unroll
+                    for (int t = 0; t < KI; ++t) {
+                        if (eb + t < e1) {
+#pragma unroll
+                            for (int n = 0; n < D; ++n) acc = fma(w[t][n], (double)z[t][n], acc);
+                        }
+                    }
                 }
             }
             T[il][lane] = acc;
@@ -191,6 +223,16 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
     if (i >= nRp) return;
     const int e0 = rowptr[i], e1 = rowptr[i + 1];
     const bool bnd = bnd_row[i] != 0;
+    const bool inreg = e1 - e0 <= RMAX;
+    int rc[RMAX];
+    double ra[RMAX], rb[RMAX];
+#pragma unroll
+    for (int t = 0; t < RMAX; ++t) {
+        const bool ok = inreg && e0 + t < e1;
+        rc[t] = ok ? col[e0 + t] : 0;
+        ra[t] = ok ? MtMs[2 * (size_t)(e0 + t)] : 0.0;
+        rb[t] = ok ? MtMs[2 * (size_t)(e0 + t) + 1] : 0.0;
+    }
     for (int kl = threadIdx.x / TI; kl < TK; kl += 256 / TI) {
         const int k = k0 + kl;
         if (k >= nS) break;
@@ -198,10 +240,27 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
         const double mk = cf[nstiff];
         const double* xk = X + (size_t)nRp * k;
         double acc = T[il][kl];
-        for (int e = e0; e < e1; ++e) {
-            const int c = col[e];
-            acc = fma(mk * MtMs[2 * (size_t)e], xk[c], acc);
-            if (G) acc = fma(-MtMs[2 * (size_t)e + 1], G[c + (size_t)nRp * k], acc);
+        if (inreg) {
+            double xv[RMAX], gv[RMAX];
+#pragma unroll
+            for (int t = 0; t < RMAX; ++t) {
+                const bool ok = e0 + t < e1;
+                xv[t] = ok ? xk[rc[t]] : 0.0;
+                gv[t] = (ok && G) ? G[rc[t] + (size_t)nRp * k] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < RMAX; ++t) {
+                if (e0 + t < e1) {
+                    acc = fma(mk * ra[t], xv[t], acc);
+                    if (G) acc = fma(-rb[t], gv[t], acc);
+                }
+            }
+        } else {
+            for (int e = e0; e < e1; ++e) {
+                const int c = col[e];
+                acc = fma(mk * MtMs[2 * (size_t)e], xk[c], acc);
+                if (G) acc = fma(-MtMs[2 * (size_t)e + 1], G[c + (size_t)nRp * k], acc);
+            }
         }
         if (bnd) {
             for (int e = e0; e < e1; ++e) {
