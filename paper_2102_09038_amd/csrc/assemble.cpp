@@ -300,7 +300,7 @@ size_t Handle::footprint() const {
                Wp.bytes() + Hodd.bytes() + Wfull.bytes() + WfullT.bytes() + lam_full.bytes() + cell.bytes() +
                Dc.bytes() + mt.bytes() + ms.bytes() + rowptr.bytes() + col.bytes() + Msv.bytes() + cls.bytes() +
                coefE0.bytes() + coefE.bytes() + diagE0.bytes() + vc_ptr.bytes() + vc_cell.bytes() + vc_loc.bytes() +
-               q.bytes() + Lc.bytes() + LcU.bytes() + CLinv.bytes() + CB.bytes() + CG.bytes() + cwork.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() + L0U.bytes() + Ecinv.bytes() +
+               q.bytes() + Lc.bytes() + LcU.bytes() + CLinv.bytes() + CLinvT.bytes() + CB.bytes() + CG.bytes() + cwork.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() + L0U.bytes() + Ecinv.bytes() +
                Gc.bytes() + vcD.bytes() +
                MtMs.bytes() + bnd_row.bytes() + cg_iters.bytes() +
                Sp_f.bytes() + Sm_f.bytes() + Gc_bf.bytes() + L0f.bytes() + L0Uf.bytes() + red.bytes() +
@@ -1151,7 +1151,7 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
             b += 2 * k::band_blk_size((int)nc, (int)cbw, 2) * 8;
         } else {
             const size_t bs = std::max<size_t>(cbw, 1), nbk = (nc + bs - 1) / bs;
-            b += (3 * nbk - 2) * bs * bs * 8 + 2 * nbk * bs * 8;
+            b += (4 * nbk - 2) * bs * bs * 8 + 2 * nbk * bs * 8;
             transient = std::max(transient, nc * (cbw + 1) * 8);   // the band on its way to the blocks
         }
     }

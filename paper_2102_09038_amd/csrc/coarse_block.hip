@@ -16,6 +16,9 @@
 // sweep:
 //     forward   w = diag(L_k^{-1}) b,     z_k = w_k - F_k z_{k-1}
 //     backward  v = diag(L_k^{-T}) z,     x_k = v_k - G_k^T x_{k+1}.
+// Every product is taken as a transposed one (y = A^T x reads A's columns, contiguous in the
+// column-major blocks, and runs several times faster than y = A x here), so the forward
+// sweep keeps L_k^{-T} and F_k^T.
 // Rows past n (the last block's padding) are an identity block decoupled from the rest.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -70,6 +73,7 @@ void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStrea
     h.cbs = bs;
     h.cnb = nb;
     h.CLinv.alloc((size_t)nb * blk);
+    h.CLinvT.alloc((size_t)nb * blk);
     h.CB.alloc((size_t)(nb > 1 ? nb - 1 : 0) * blk);
     h.CG.alloc((size_t)(nb > 1 ? nb - 1 : 0) * blk);
     h.cwork.alloc((size_t)2 * nb * bs);
@@ -104,9 +108,14 @@ void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStrea
             check_rb(rocsolver_dtrtri(rb, rocblas_fill_lower, rocblas_diagonal_non_unit, bs,
                                       h.CLinv.p + (size_t)k * blk, bs, info.p + nb + k),
                      "rocsolver_dtrtri");
-        // G_k = C_k L_k^{-1} into CG, then F_k = L_k^{-1} C_{k-1} over C_{k-1} in CB (the strictly
-        // upper triangles of the L_k^{-1} blocks are zero)
+        // L_k^{-T} into CLinvT; G_k = C_k L_k^{-1} into CG; then F_k^T = C_{k-1}^T L_k^{-T} over
+        // C_{k-1} in CB (the strictly upper triangles of the L_k^{-1} blocks are zero)
         const double zero = 0.0;
+        for (int k = 0; k < nb; ++k)
+            check_rb(rocblas_dgeam(rb, rocblas_operation_transpose, rocblas_operation_transpose, bs, bs, &one,
+                                   h.CLinv.p + (size_t)k * blk, bs, &zero, h.CLinv.p + (size_t)k * blk, bs,
+                                   h.CLinvT.p + (size_t)k * blk, bs),
+                     "rocblas_dgeam");
         for (int k = 0; k + 1 < nb; ++k)
             check_rb(rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, bs, bs, bs, &one,
                                    h.CB.p + (size_t)k * blk, bs, h.CLinv.p + (size_t)k * blk, bs, &zero,
@@ -114,8 +123,8 @@ void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStrea
                      "rocblas_dgemm");
         DBuf<double> tmp(nb > 1 ? blk : 0);
         for (int k = 1; k < nb; ++k) {
-            check_rb(rocblas_dgemm(rb, rocblas_operation_none, rocblas_operation_none, bs, bs, bs, &one,
-                                   h.CLinv.p + (size_t)k * blk, bs, h.CB.p + (size_t)(k - 1) * blk, bs, &zero,
+            check_rb(rocblas_dgemm(rb, rocblas_operation_transpose, rocblas_operation_transpose, bs, bs, bs, &one,
+                                   h.CB.p + (size_t)(k - 1) * blk, bs, h.CLinv.p + (size_t)k * blk, bs, &zero,
                                    tmp.p, bs),
                      "rocblas_dgemm");
             RTE_HIP(hipMemcpyAsync(h.CB.p + (size_t)(k - 1) * blk, tmp.p, blk * sizeof(double),
@@ -155,13 +164,13 @@ void coarse_block_solve(Handle* h, const double* rhs, double* x, hipStream_t s) 
     std::shared_lock<std::shared_mutex> lk(capture_mutex());
     check_rb(rocblas_set_stream(rb, s), "rocblas_set_stream");
     const double one = 1.0, minus_one = -1.0, zero = 0.0;
-    // forward: z = diag(L_k^{-1}) y, then z_k -= F_k z_{k-1}
-    check_rb(rocblas_dgemv_strided_batched(rb, rocblas_operation_none, bs, bs, &one, h->CLinv.p, bs, blk, y, 1, bs,
-                                           &zero, z, 1, bs, nb),
+    // forward: z = diag(L_k^{-1}) y, then z_k -= F_k z_{k-1}  (from L_k^{-T} and F_k^T)
+    check_rb(rocblas_dgemv_strided_batched(rb, rocblas_operation_transpose, bs, bs, &one, h->CLinvT.p, bs, blk, y,
+                                           1, bs, &zero, z, 1, bs, nb),
              "rocblas_dgemv_strided_batched");
     for (int k = 1; k < nb; ++k)
-        check_rb(rocblas_dgemv(rb, rocblas_operation_none, bs, bs, &minus_one, h->CB.p + (size_t)(k - 1) * blk, bs,
-                               z + (size_t)(k - 1) * bs, 1, &one, z + (size_t)k * bs, 1),
+        check_rb(rocblas_dgemv(rb, rocblas_operation_transpose, bs, bs, &minus_one, h->CB.p + (size_t)(k - 1) * blk,
+                               bs, z + (size_t)(k - 1) * bs, 1, &one, z + (size_t)k * bs, 1),
                  "rocblas_dgemv");
     // backward: y = diag(L_k^{-T}) z, then y_k -= G_k^T y_{k+1}
     check_rb(rocblas_dgemv_strided_batched(rb, rocblas_operation_transpose, bs, bs, &one, h->CLinv.p, bs, blk, z, 1,

@@ -155,10 +155,10 @@ struct Handle {
     DBuf<double> Lc, LcU;          // blocked band factor, rows of L and of L^T (kernels_band.hip)
     DBuf<double> Ecinv;            // explicit E_c^{-1} (nc x nc, band order) when it fits its budget
     // block-tridiagonal Cholesky of E_c (coarse_block.hip) for wide coarse bands: cnb blocks
-    // of cbs rows; inverses of the diagonal factors, the two folded coupling blocks per block
-    // boundary, two work vectors and the rocBLAS handle of the solve
+    // of cbs rows; inverses of the diagonal factors and their transposes, the two folded
+    // coupling blocks per block boundary, two work vectors and the rocBLAS handle of the solve
     int cbs = 0, cnb = 0;
-    DBuf<double> CLinv, CB, CG, cwork;
+    DBuf<double> CLinv, CLinvT, CB, CG, cwork;
     void* coarse_rb = nullptr;
     DBuf<int> perm, iperm;         // [nRp] spatial reordering (reverse Cuthill-McKee) and inverse
     int sbw = 0;                   // spatial band width in that order
