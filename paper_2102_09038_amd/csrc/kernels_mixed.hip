@@ -26,8 +26,10 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 // v_mfma_f32_16x16x32_bf16 (operand lanes: row l%16, k = 8 (l/16) + e; result rows
 // 4 (l/16) + v, column l%16).  The MFMA row operand is the B fragment (n) and the column
 // operand the A fragment (m), so the result's lane-fast index runs along m and the
-// column-major stores of C are contiguous.  16-byte global loads, double-buffered LDS
-// with rows padded by 16 bytes, one barrier per K step.
+// column-major stores of C are contiguous.  16-byte global loads, double-buffered LDS, one
+// barrier per K step.  LDS rows are not padded: the 16-byte chunk c of tile row r sits at
+// chunk c ^ ((r / 2) % 8) of the row, so that the 16 lanes of a 16-byte access, which read
+// one chunk of 16 consecutive rows or write two whole rows, cover all 64 banks once.
 //
 // A K step is short (32 MFMAs per wave), shorter than a global load's latency, so interior
 // tiles run the loads two steps ahead of the MFMAs (two register sets) in a loop without
@@ -35,7 +37,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 // store after the last step fills a buffer nobody reads, so the compiler's waits for a
 // register set never cover the younger set's loads.  Edge tiles, and K not a multiple of
 // two steps, take a guarded loop with one step of prefetch.
-constexpr int HBM_ = 128, HBN = 128, HBK = 64, HPAD = 8;
+constexpr int HBM_ = 128, HBN = 128, HBK = 64;
 
 __device__ __forceinline__ int xcd_swz(int b, int nb) {
     const int per = nb / 8, x = b % 8, i = b / 8;
@@ -43,19 +45,28 @@ __device__ __forceinline__ int xcd_swz(int b, int nb) {
     return x * per + i;
 }
 
-typedef uint16_t BTile[HBM_][HBK + HPAD];
+typedef uint16_t BTile[HBM_][HBK];
+
+// element offset of 16-byte chunk c of tile row r within that row (the bank swizzle)
+__device__ __forceinline__ int swz(int r, int c) { return (c ^ ((r >> 1) & 7)) * 8; }
 
 // the MFMAs of one K step from LDS buffers As / Bs
 __device__ __forceinline__ void bf16_step_mfma(const BTile& As, const BTile& Bs, int lane, int wm, int wn,
                                                f4v (&acc)[4][4]) {
 #pragma unroll
     for (int kk = 0; kk < HBK / 32; ++kk) {
-        const int kc = kk * 32 + 8 * (lane >> 4);
+        const int c = kk * 4 + (lane >> 4);           // 16-byte chunk: k = 8 c .. 8 c + 7
         bf8v af[4], bfr[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf8v*>(&As[wm * 64 + i * 16 + (lane & 15)][kc]);
+        for (int i = 0; i < 4; ++i) {
+            const int r = wm * 64 + i * 16 + (lane & 15);
+            af[i] = *reinterpret_cast<const bf8v*>(&As[r][swz(r, c)]);
+        }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bfr[j] = *reinterpret_cast<const bf8v*>(&Bs[wn * 64 + j * 16 + (lane & 15)][kc]);
+        for (int j = 0; j < 4; ++j) {
+            const int r = wn * 64 + j * 16 + (lane & 15);
+            bfr[j] = *reinterpret_cast<const bf8v*>(&Bs[r][swz(r, c)]);
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -109,15 +120,17 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(int M, int N, int K, 
             t.b3 = *reinterpret_cast<const uint4*>(Bb + 3 * lb + ko);
             return t;
         };
+        // rows r0 + 32 i share (r / 2) % 8, hence the chunk position
+        const int cs = swz(r0, ch);
         auto store = [&](const Stage& t, BTile& as, BTile& bs) {
-            *reinterpret_cast<uint4*>(&as[r0][ch * 8]) = t.a0;
-            *reinterpret_cast<uint4*>(&as[r0 + 32][ch * 8]) = t.a1;
-            *reinterpret_cast<uint4*>(&as[r0 + 64][ch * 8]) = t.a2;
-            *reinterpret_cast<uint4*>(&as[r0 + 96][ch * 8]) = t.a3;
-            *reinterpret_cast<uint4*>(&bs[r0][ch * 8]) = t.b0;
-            *reinterpret_cast<uint4*>(&bs[r0 + 32][ch * 8]) = t.b1;
-            *reinterpret_cast<uint4*>(&bs[r0 + 64][ch * 8]) = t.b2;
-            *reinterpret_cast<uint4*>(&bs[r0 + 96][ch * 8]) = t.b3;
+            *reinterpret_cast<uint4*>(&as[r0][cs]) = t.a0;
+            *reinterpret_cast<uint4*>(&as[r0 + 32][cs]) = t.a1;
+            *reinterpret_cast<uint4*>(&as[r0 + 64][cs]) = t.a2;
+            *reinterpret_cast<uint4*>(&as[r0 + 96][cs]) = t.a3;
+            *reinterpret_cast<uint4*>(&bs[r0][cs]) = t.b0;
+            *reinterpret_cast<uint4*>(&bs[r0 + 32][cs]) = t.b1;
+            *reinterpret_cast<uint4*>(&bs[r0 + 64][cs]) = t.b2;
+            *reinterpret_cast<uint4*>(&bs[r0 + 96][cs]) = t.b3;
         };
         Stage s0 = load(0);
         store(s0, As[0], Bs[0]);
@@ -151,11 +164,12 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(int M, int N, int K, 
                                            : make_uint4(0, 0, 0, 0);
             }
         };
+        const int cs = swz(r0, ch);
         auto sstore = [&](int buf) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                *reinterpret_cast<uint4*>(&As[buf][r0 + 32 * i][ch * 8]) = ra[i];
-                *reinterpret_cast<uint4*>(&Bs[buf][r0 + 32 * i][ch * 8]) = rb[i];
+                *reinterpret_cast<uint4*>(&As[buf][r0 + 32 * i][cs]) = ra[i];
+                *reinterpret_cast<uint4*>(&Bs[buf][r0 + 32 * i][cs]) = rb[i];
             }
         };
         gload(0);
