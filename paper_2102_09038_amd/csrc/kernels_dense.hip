@@ -223,10 +223,11 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, int m0, int n0, i
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) acc[j][i] = F::mma(bf[j], af[i], acc[j][i]);
-            // the next step's tile goes to the other buffer half-way through this step's
+            // FP64: the next step's tile goes to the other buffer half-way through this step's
             // MFMAs (every wave finished reading that buffer before the last barrier), so the
-            // stores overlap the matrix pipe instead of following it
-            if (kk == 2 && kt + 1 < kt_end) sstore(cur ^ 1);
+            // stores overlap the matrix pipe instead of following it.  FP32 MFMAs are twice as
+            // fast, the loads would not have landed by then: its stores follow the MFMAs.
+            if (kk == (sizeof(TM) == 8 ? 2 : GBK / 4 - 1) && kt + 1 < kt_end) sstore(cur ^ 1);
         }
         __syncthreads();
     }
