@@ -180,7 +180,8 @@ def batch_bench(args, torch, rte, inputs):
     ref, t64, it64, asm64, res64 = [], 0.0, [], [], []
     for i, inst in enumerate(insts):
         ta = time.perf_counter()
-        h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0)
+        h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0,
+                                     coarse_solver=rte.RTE_COARSE_QUICK)
         asm64.append(time.perf_counter() - ta)
         U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
@@ -214,7 +215,8 @@ def batch_bench(args, torch, rte, inputs):
         b_est, p_est = rte.estimate_footprint(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0)
         if held + max(b_est, p_est) > budget:
             continue
-        hs.append(rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0))
+        hs.append(rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0,
+                                              coarse_solver=rte.RTE_COARSE_QUICK))
         held += b_est
     lockstep = {}
     for graphs in (True, False):
@@ -308,7 +310,8 @@ def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None):
             wait = r.arrival - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
-            h = rte.Handle.from_instance(r.inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0)
+            h = rte.Handle.from_instance(r.inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0,
+                                         coarse_solver=rte.RTE_COARSE_QUICK)
             U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
             st, info = h.solve(U, opts=o64, raise_on_notconv=False)
             torch.cuda.synchronize()

@@ -99,9 +99,15 @@ typedef enum rte_coarse_solver {
     RTE_COARSE_INVERSE = 1,   /* explicit E_c^{-1} (dense Cholesky and inverse on the device,
                                  once), applied as a matrix-vector product; needs n_c^2 * 8
                                  bytes <= 12 GiB                                             */
-    RTE_COARSE_BAND = 2,      /* banded Cholesky (host), the band solve on the device; needs
-                                 the half-bandwidth d_N (b + 1) - 1 within the band solve's
-                                 reach (b: spatial bandwidth)                                */
+    RTE_COARSE_BAND = 2,      /* banded Cholesky (on the device when the half-bandwidth is
+                                 <= 143, else on the host), the band solve on the device;
+                                 needs the half-bandwidth d_N (b + 1) - 1 within the band
+                                 solve's reach (b: spatial bandwidth)                        */
+    RTE_COARSE_QUICK = 4,     /* for a short set-up (served requests): the band solve when its
+                                 band fits the device band factorisation (half-bandwidth
+                                 <= 143; set-up in milliseconds, about 3 ms per solve at
+                                 16641 unknowns against 0.5 ms for the explicit inverse),
+                                 else as RTE_COARSE_AUTO                                 */
     RTE_COARSE_BLOCK = 3      /* block-tridiagonal Cholesky on the device (blocks of one
                                  half-bandwidth: dense factor, triangular solve and rank
                                  update per block, then inverses of the diagonal factors

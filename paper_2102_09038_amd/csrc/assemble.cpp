@@ -19,6 +19,7 @@
 #include <map>
 #include <memory>
 #include <numeric>
+#include <thread>
 #include <unordered_map>
 
 #include "ops.h"
@@ -127,6 +128,24 @@ double invd(const double* J, double* Ji, int d) {
                        J[2] * (J[3] * J[7] - J[4] * J[6]);
     inv3(J, Ji);
     return det;
+}
+
+// f(k) for k in [0, n) over up to 16 host threads (contiguous ranges; f must touch disjoint
+// data per k)
+template <typename F>
+void parallel_for(int n, F f) {
+    const int nt = std::max(1, std::min<int>({16, (int)std::thread::hardware_concurrency(), n / 8}));
+    if (nt == 1) {
+        for (int k = 0; k < n; ++k) f(k);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            for (int k = (int)((long)n * t / nt); k < (int)((long)n * (t + 1) / nt); ++k) f(k);
+        });
+    for (auto& x : th) x.join();
 }
 
 // ----------------------------------------------------------------------------- banded Cholesky
@@ -331,7 +350,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     if (!D || !o) fail(RTE_E_ARG, "null descriptor or options");
     if (o->mixed < 0 || o->mixed > 2) fail(RTE_E_ARG, "mixed must be 0, 1 or 2");
     if (o->odd_eig != 0 && o->odd_eig != 1) fail(RTE_E_ARG, "odd_eig must be 0 or 1");
-    if (o->coarse_solver < RTE_COARSE_AUTO || o->coarse_solver > RTE_COARSE_BLOCK)
+    if (o->coarse_solver < RTE_COARSE_AUTO || o->coarse_solver > RTE_COARSE_QUICK)
         fail(RTE_E_ARG, "unknown coarse solver");
     const int d = D->dim;
     if (d != 2 && d != 3) fail(RTE_E_ARG, "dim must be 2 or 3");
@@ -630,11 +649,18 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         for (int c = 0; c < nb; ++c)
             coefE0[(size_t)k * ncls + nstiff + 1 + c] = coefE[(size_t)k * ncls + nstiff + 1 + c] =
                 omega[(size_t)c * nS + k];
-        for (int i = 0; i < nRp; ++i) {
-            double v = 0;
-            for (int c = 0; c < ncls; ++c) v += coefE0[(size_t)k * ncls + c] * cls[(size_t)c * nnz + diagpos[i]];
-            diagE0[i + (size_t)nRp * k] = v;
-        }
+    }
+    {   // the diagonal of every E_0 block (Jacobi), directions split over host threads
+        Vec cd((size_t)ncls * nRp);
+        for (int c = 0; c < ncls; ++c)
+            for (int i = 0; i < nRp; ++i) cd[(size_t)c * nRp + i] = cls[(size_t)c * nnz + diagpos[i]];
+        parallel_for(nS, [&](int k) {
+            for (int i = 0; i < nRp; ++i) {
+                double v = 0;
+                for (int c = 0; c < ncls; ++c) v += coefE0[(size_t)k * ncls + c] * cd[(size_t)c * nRp + i];
+                diagE0[i + (size_t)nRp * k] = v;
+            }
+        });
     }
     // vertex -> incident cells
     std::vector<int> vcp(nRp + 1, 0), vcc((size_t)nRm * nv), vcl((size_t)nRm * nv);
@@ -654,14 +680,18 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     Vec Mq(nRp, 0.0);
     for (int i = 0; i < nRp; ++i)
         for (int e = rp[i]; e < rp[i + 1]; ++e) Mq[i] += M1v[e] * D->q_nodal[ci[e]];
-    Vec qv((size_t)nRp * nS);
-    double qn2 = 0;
-    for (int k = 0; k < nS; ++k)
+    Vec qv((size_t)nRp * nS), qk2(nS);
+    parallel_for(nS, [&](int k) {
+        double a = 0;
         for (int i = 0; i < nRp; ++i) {
             const double v = h.h_m[k] * Mq[i];
             qv[i + (size_t)nRp * k] = v;
-            qn2 += v * v;
+            a += v * v;
         }
+        qk2[k] = a;
+    });
+    double qn2 = 0;
+    for (int k = 0; k < nS; ++k) qn2 += qk2[k];   // fixed order
     h.qnorm = std::sqrt(qn2);
 
     trace("value classes");
@@ -1002,15 +1032,29 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         const bool inv_fits = (double)nc * nc * sizeof(double) <= kEcinvMaxBytes;
         const bool band_fits = k::band_groups(bw, 2) != 0;
         int how = o->coarse_solver;
+        if (how == RTE_COARSE_QUICK) how = (band_fits && k::band_factor_fits(bw)) ? RTE_COARSE_BAND : RTE_COARSE_AUTO;
         if (how == RTE_COARSE_AUTO) how = inv_fits ? RTE_COARSE_INVERSE : band_fits ? RTE_COARSE_BAND : RTE_COARSE_BLOCK;
         if (how == RTE_COARSE_INVERSE) {
             if (!inv_fits) fail(RTE_E_ARG, "the explicit coarse inverse exceeds its memory budget");
             dense_spd_inverse(rb, s, band, nc, bw, h.Ecinv, "the coarse matrix E_c");
         } else if (how == RTE_COARSE_BAND) {
             if (!band_fits) fail(RTE_E_ARG, "coarse band too wide for the band solve");
-            band_cholesky(band, nc, bw);
-            h.Lc.upload(band_to_blocked(band, nc, bw, false), s);
-            h.LcU.upload(band_to_blocked(band, nc, bw, true), s);
+            if (k::band_factor_fits(bw)) {
+                // factored on the device, in place, by the E_0 factor kernel
+                h.Lc.upload(band_to_blocked(band, nc, bw, false), s);
+                h.LcU.upload(Vec(h.Lc.n, 0.0), s);
+                DBuf<int> bad(1);
+                RTE_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+                k::band_factor_one(nc, bw, h.Lc.p, h.LcU.p, bad.p, s);
+                int hb = 0;
+                RTE_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+                RTE_HIP(hipStreamSynchronize(s));
+                if (hb) fail(RTE_E_ARG, "coarse matrix is not positive definite");
+            } else {
+                band_cholesky(band, nc, bw);
+                h.Lc.upload(band_to_blocked(band, nc, bw, false), s);
+                h.LcU.upload(band_to_blocked(band, nc, bw, true), s);
+            }
         } else {
             DBuf<double> dband;
             dband.upload(band, s);
@@ -1144,6 +1188,8 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
     {
         const bool inv_fits = (double)nc * nc * 8 <= kEcinvMaxBytes, band_fits = k::band_groups((int)cbw, 2) != 0;
         int how = o->coarse_solver;
+        if (how == RTE_COARSE_QUICK)
+            how = (band_fits && k::band_factor_fits((int)cbw)) ? RTE_COARSE_BAND : RTE_COARSE_AUTO;
         if (how == RTE_COARSE_AUTO) how = inv_fits ? RTE_COARSE_INVERSE : band_fits ? RTE_COARSE_BAND : RTE_COARSE_BLOCK;
         if (how == RTE_COARSE_INVERSE) {
             b += nc * nc * 8;

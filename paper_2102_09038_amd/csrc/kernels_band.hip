@@ -637,6 +637,20 @@ void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, 
     RTE_CHECK_LAUNCH();
 }
 
+void band_factor_one(int n, int bw, double* BL, double* BU, int* bad, hipStream_t s) {
+    const size_t lds = (size_t)(bw + 1) * (bw + 1) * sizeof(double);
+    if (lds > 150 * 1024 || bw + 1 > 16 * kFacCols) fail(RTE_E_ARG, "band too wide for the LDS factorisation window");
+    RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&e0_band_factor_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(e0_band_factor_kernel, dim3(1), dim3(bw >= 120 ? 1024 : 512), lds, s, n, bw, BL, BU,
+                       (size_t)0, bad);
+    RTE_CHECK_LAUNCH();
+}
+
+bool band_factor_fits(int bw) {
+    return (size_t)(bw + 1) * (bw + 1) * sizeof(double) <= 150 * 1024 && bw + 1 <= 16 * kFacCols;
+}
+
 void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
                     const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G) {
     band_solve_launch<double>(BL, BU, n, bw, nsys, stride_sys, b, x, stride_vec, iperm, s, G);

@@ -112,6 +112,13 @@ __host__ __device__ inline size_t band_blk_size(int n, int bw, int vec) {
 // (kernels_band.hip); b and x are read / written at iperm[band row] when iperm is given
 void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
                     const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G = 0);
+// Cholesky factorisation of one SPD band matrix on the device (the E_0 factor kernel with one
+// work-group): BL holds the lower band in the blocked layout on entry (offset t = c - r + bw),
+// and L on exit, BU (zeroed by the caller) rows of L^T; the diagonal entries become
+// 1 / L(i,i).  *bad (zeroed by the caller) is set if a pivot is not positive.
+void band_factor_one(int n, int bw, double* BL, double* BU, int* bad, hipStream_t s);
+// whether band_factor_one takes half-bandwidth bw
+bool band_factor_fits(int bw);
 // same with FP32 factors (the reduced-precision preconditioner); FP64 vectors and sums
 void band_solve_blk_f32(const float* BL, const float* BU, int n, int bw, int nsys, size_t stride_sys,
                         const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G = 0);

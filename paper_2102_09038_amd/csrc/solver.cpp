@@ -326,21 +326,36 @@ void apply_P1(Handle* h, const rte_solve_opts* o, const double* r, double* z, hi
     }
 }
 
-// step = -s + W E_c^{-1} W^T ((E - K+) s - r)   (Sec. 5.4; the correction right-hand side
-// without Alg. 3's extra "-q", which would move the fixed point)
-void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const double* sv, double* step,
-                     hipStream_t s, int64_t* pcg, bool lowp) {
-    const size_t n = (size_t)h->nRp * h->nS;
+// the correction's right-hand side q_c = W^T ((E - K+) s - r) into W_CRHS (Sec. 5.4; without
+// Alg. 3's extra "-q", which would move the fixed point)
+void correction_rhs(Handle* h, const rte_solve_opts* o, const double* r, const double* sv, hipStream_t s,
+                    int64_t* pcg, bool lowp) {
     double* t = ws(h, W_ET);
     residual_like(h, o, sv, r, t, o->pcg_tol_inner, s, pcg, lowp);
-    double* rhs = ws(h, W_CRHS);
+    k::coarse_project(h, t, ws(h, W_CRHS), s);
+}
+
+// u_c = E_c^{-1} q_c: W_CRHS -> W_CSOL by the handle's coarse solver
+void coarse_solve(Handle* h, hipStream_t s) {
+    const double* rhs = ws(h, W_CRHS);
     double* uc = ws(h, W_CSOL);
-    k::coarse_project(h, t, rhs, s);
     if (h->Ecinv.p) k::gemv_rows(h->nc, h->Ecinv.p, rhs, uc, s);
     else if (h->cnb) coarse_block_solve(h, rhs, uc, s);
     else k::band_solve_blk(h->Lc.p, h->LcU.p, h->nc, h->cbw, 1, 0, rhs, uc, 0, nullptr, s);
-    k::fill(step, 0.0, n, s);
-    k::richardson_update(h, step, sv, uc, s);
+}
+
+// step = -s + W u_c
+void correction_finish(Handle* h, const double* sv, double* step, hipStream_t s) {
+    k::fill(step, 0.0, (size_t)h->nRp * h->nS, s);
+    k::richardson_update(h, step, sv, ws(h, W_CSOL), s);
+}
+
+// step = -s + W E_c^{-1} W^T ((E - K+) s - r)   (Sec. 5.4)
+void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const double* sv, double* step,
+                     hipStream_t s, int64_t* pcg, bool lowp) {
+    correction_rhs(h, o, r, sv, s, pcg, lowp);
+    coarse_solve(h, s);
+    correction_finish(h, sv, step, s);
 }
 
 }  // namespace sv

@@ -40,6 +40,9 @@ struct Batch {
     int l = 0;                          // P_1 steps of the slots (they advance together)
     std::vector<BatchSlot> slots;
     k::BandGroupPlan plan;
+    // the coarse band solves (one system each) of the slots whose handle solves E_c by band
+    // factors, one grouped launch
+    k::BandGroupPlan cplan;
     bool plan_valid = false;
     // graph mode: the two launch sequences of an iteration (residuals; preconditioner and
     // update) are captured once per set of live slots and replayed, on the batch's own stream
@@ -110,6 +113,26 @@ void rebuild_plan(Batch* B, hipStream_t s) {
         jobs.push_back(j);
     }
     k::band_group_plan(jobs, f32, B->plan, s);
+    std::vector<k::BandJob> cjobs;
+    for (auto& sl : B->slots) {
+        if (!sl.live) continue;
+        Handle* h = sl.h;
+        if (h->Ecinv.p || h->cnb || !h->Lc.p) continue;
+        k::BandJob j{};
+        j.BL = h->Lc.p;
+        j.BU = h->LcU.p;
+        j.b = ws(h, W_CRHS);
+        j.x = ws(h, W_CSOL);
+        j.stride_sys = 0;
+        j.G = 0;
+        j.stride_vec = (size_t)h->nc;
+        j.n = h->nc;
+        j.bw = h->cbw;
+        j.nsys = 1;
+        cjobs.push_back(j);
+    }
+    B->cplan = k::BandGroupPlan{};
+    if (!cjobs.empty()) k::band_group_plan(cjobs, false, B->cplan, s);
     B->plan_valid = true;
 }
 
@@ -159,13 +182,20 @@ void enqueue_precond_update(Batch* B, hipStream_t s) {
             k::axpby(-1.0, ws(sl.h, W_EZ), 1.0, ws(sl.h, W_ES), (size_t)sl.h->nRp * sl.h->nS, s);
         }
     }
+    // the subspace correction: right-hand sides, then the coarse solves (explicit inverses
+    // one by one, band factors in one grouped launch), then the steps and updates
+    for (auto& sl : B->slots)
+        if (sl.live) correction_rhs(sl.h, &sl.o, ws(sl.h, W_ER), ws(sl.h, W_ES), s, nullptr, lowp);
+    for (auto& sl : B->slots)
+        if (sl.live && sl.h->Ecinv.p) coarse_solve(sl.h, s);
+    if (!B->cplan.launches.empty()) k::band_group_run(B->cplan, s);
     for (auto& sl : B->slots) {
         if (!sl.live) continue;
         Handle* h = sl.h;
         const size_t n = (size_t)h->nRp * h->nS;
         double* r = ws(h, W_ER);
         double* step = ws(h, W_ESTEP);
-        correction_step(h, &sl.o, r, ws(h, W_ES), step, s, nullptr, lowp);
+        correction_finish(h, ws(h, W_ES), step, s);
         k::dot(step, r, n, h->red.p, s);
         k::reduce(h->red.p, h->scal.p, S_DOT2, s);
         k::axpby(1.0, step, 1.0, sl.U, n, s);

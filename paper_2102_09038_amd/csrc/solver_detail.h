@@ -35,6 +35,12 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
 // Y = (E - K+) X - q0 (FP64 scatter GEMM, then apply_E_core)
 void residual_like(Handle* h, const rte_solve_opts* o, const double* X, const double* q0, double* Y, double tol,
                    hipStream_t s, int64_t* pcg, bool lowp);
+// the correction in three parts (a batch groups the coarse band solves of its slots):
+// q_c = W^T ((E - K+) s - r) into W_CRHS; u_c = E_c^{-1} q_c into W_CSOL; step = -s + W u_c
+void correction_rhs(Handle* h, const rte_solve_opts* o, const double* r, const double* sv, hipStream_t s,
+                    int64_t* pcg, bool lowp);
+void coarse_solve(Handle* h, hipStream_t s);
+void correction_finish(Handle* h, const double* sv, double* step, hipStream_t s);
 // step = -s + W E_c^{-1} W^T ((E - K+) s - r)   (Sec. 5.4)
 void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const double* sv, double* step,
                      hipStream_t s, int64_t* pcg, bool lowp);

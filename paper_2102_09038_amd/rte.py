@@ -21,7 +21,7 @@ RTE_DT_F64, RTE_DT_F32, RTE_DT_BF16 = 0, 1, 2
 RTE_ODD_PCG, RTE_ODD_EXACT, RTE_ODD_CONDENSED = 0, 1, 2
 RTE_E0_CG, RTE_E0_BANDED = 0, 1
 RTE_INNER_RICHARDSON, RTE_INNER_PCG = 0, 1
-RTE_COARSE_AUTO, RTE_COARSE_INVERSE, RTE_COARSE_BAND, RTE_COARSE_BLOCK = 0, 1, 2, 3
+RTE_COARSE_AUTO, RTE_COARSE_INVERSE, RTE_COARSE_BAND, RTE_COARSE_BLOCK, RTE_COARSE_QUICK = 0, 1, 2, 3, 4
 ARRAY_SP, ARRAY_SM, ARRAY_M, ARRAY_T, ARRAY_Q, ARRAY_LAMP, ARRAY_WP, ARRAY_LAMM = range(8)
 STATUS_NAMES = ["OK", "E_ARG", "E_PHYS", "E_MESH", "E_NOMEM", "E_HIP", "E_NOTCONV", "E_NONFINITE"]
 

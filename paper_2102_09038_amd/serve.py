@@ -50,7 +50,7 @@ class Server:
 
     def __init__(self, budget: int, solve_opts, max_slots: int = 256, workers: int = 4, mixed_assembly: int = 2,
                  keep_results: bool = False, on_done: Optional[Callable[[Request], None]] = None,
-                 odd_eig: int = 0, use_graphs: bool = False):
+                 odd_eig: int = 0, use_graphs: bool = False, coarse_solver: int = rte.RTE_COARSE_QUICK):
         import torch
         self.torch = torch
         self.budget = int(budget)
@@ -61,6 +61,9 @@ class Server:
         # the batch runs the condensed odd solve only: no odd eigendecomposition at assembly
         # (uniform sigma_s / sigma_t; ignored otherwise)
         self.odd_eig = odd_eig
+        # short set-up first: the coarse system by the device band factorisation where it
+        # applies (assembly bounds the served rate)
+        self.coarse_solver = coarse_solver
         self.keep = keep_results
         self.on_done = on_done
         self.reserved = 0                          # bytes promised to requests being assembled or in slots
@@ -73,13 +76,14 @@ class Server:
     def _estimate(self, req):
         if not hasattr(req, "_est"):
             b, p = rte.estimate_footprint(req.inst, e0_solver=rte.RTE_E0_BANDED, mixed=self.mixed_assembly,
-                                          odd_eig=self.odd_eig)
+                                          odd_eig=self.odd_eig, coarse_solver=self.coarse_solver)
             req._est = (b, max(b, p))
         return req._est
 
     def _assemble(self, req: Request, stream):
         h = rte.Handle.from_instance(req.inst, stream=stream.cuda_stream, e0_solver=rte.RTE_E0_BANDED,
-                                     mixed=self.mixed_assembly, odd_eig=self.odd_eig)
+                                     mixed=self.mixed_assembly, odd_eig=self.odd_eig,
+                                     coarse_solver=self.coarse_solver)
         return h
 
     # ---------------------------------------------------------------------------- main loop

@@ -89,6 +89,10 @@ def test_estimate_footprint_host_only():
     # each) and no truncated basis (3072 x 21)
     be, _ = rte.estimate_footprint(real, e0_solver=rte.RTE_E0_BANDED, mixed=1, odd_eig=0)
     assert b1 - be == (2 * 3072 * 3072 + 3072 * 21) * 8
+    # the quick coarse choice: band factors (261 row blocks x 66 groups x 64 x 2 doubles, L and
+    # L^T) in place of the explicit 16641^2 inverse
+    bq, _ = rte.estimate_footprint(real, e0_solver=rte.RTE_E0_BANDED, mixed=1, coarse_solver=rte.RTE_COARSE_QUICK)
+    assert b1 - bq == 16641 * 16641 * 8 - 2 * 261 * 66 * 64 * 2 * 8
     small = inputs.config_small()
     bs, _ = rte.estimate_footprint(small, e0_solver=rte.RTE_E0_BANDED, mixed=1)
     assert 0 < bs < b2

@@ -53,6 +53,30 @@ def alone(h, o):
     return U, info
 
 
+def test_batch_with_band_coarse_solve_equals_single_solves():
+    """Handles assembled with the quick coarse set-up (E_c by the device band factorisation and
+    the band solve, as the server assembles): captured and replayed, bitwise the solo solves."""
+    from paper_2102_09038_amd import rte
+    insts = [i for i in instances() if i.n_even == 0]
+    hs = [rte.Handle.from_instance(i, e0_solver=rte.RTE_E0_BANDED, mixed=1, coarse_solver=rte.RTE_COARSE_QUICK)
+          for i in insts]
+    o = opts_for(rte.RTE_MIXED)
+    ref = [alone(h, o) for h in hs]
+    b = rte.Batch(max_slots=8, use_graphs=True)
+    outs = [torch.full((h.dims.nSp, h.dims.nRp), np.nan, dtype=torch.float64, device="cuda") for h in hs]
+    slots = [b.admit(h, U, o) for h, U in zip(hs, outs)]
+    assert b.step(1000) == 0
+    torch.cuda.synchronize()
+    done = {s: (st, info) for s, st, info in b.poll()}
+    for k, (s, U) in enumerate(zip(slots, outs)):
+        st, info = done[s]
+        assert st == rte.RTE_OK and info.iters == ref[k][1].iters
+        assert torch.equal(U, ref[k][0])
+    b.close()
+    for h in hs:
+        h.close()
+
+
 @pytest.mark.parametrize("graphs", [True, False])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_equals_single_solves(handles, prec, graphs):

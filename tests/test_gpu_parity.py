@@ -271,15 +271,16 @@ def test_derived_outputs(case):
     assert h.derived_outputs(U, phi) == bs      # repeatable (fixed-order sums)
 
 
-@pytest.mark.parametrize("name,coarse", [("tiny2d", "band"), ("tiny2d", "block"), ("small", "block")])
+@pytest.mark.parametrize("name,coarse", [("tiny2d", "band"), ("tiny2d", "block"), ("small", "block"),
+                                        ("tiny2d-hetero", "quick")])
 def test_coarse_solvers(name, coarse):
-    """The correction's coarse system solved by the band solve or by the block-tridiagonal
-    Cholesky instead of the explicit inverse: P_2 P_1 r and the converged iterate against the
-    oracle (sparse LU of E_c).  The small instance has 4335 coarse unknowns in blocks of one
-    half-bandwidth, the last one ragged."""
+    """The correction's coarse system solved by the band solve (factored on the device) or by
+    the block-tridiagonal Cholesky instead of the explicit inverse: P_2 P_1 r and the converged
+    iterate against the oracle (sparse LU of E_c).  The small instance has 4335 coarse unknowns
+    in blocks of one half-bandwidth, the last one ragged."""
     from paper_2102_09038_amd import rte
     inst = CASES[name]()
-    how = {"band": rte.RTE_COARSE_BAND, "block": rte.RTE_COARSE_BLOCK}[coarse]
+    how = {"band": rte.RTE_COARSE_BAND, "block": rte.RTE_COARSE_BLOCK, "quick": rte.RTE_COARSE_QUICK}[coarse]
     print(f"[{name}] coarse solver {coarse}", flush=True)
     D, ops, h = make(inst, e0_solver=rte.RTE_E0_BANDED, coarse_solver=how)
     o = rte.default_solve_opts(l=inst.l, tol=1e-12, odd_solver=rte.RTE_ODD_EXACT, e0_solver=rte.RTE_E0_BANDED)

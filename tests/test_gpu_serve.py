@@ -32,8 +32,10 @@ def opts():
 
 def solo(inst):
     from paper_2102_09038_amd import rte
-    # assembled as the server assembles (FP32 factors only, no odd eigendecomposition)
-    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0)
+    # assembled as the server assembles (FP32 factors only, no odd eigendecomposition, the
+    # quick coarse set-up)
+    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0,
+                                 coarse_solver=rte.RTE_COARSE_QUICK)
     U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
     st, info = h.solve(U, opts=opts())
     torch.cuda.synchronize()
@@ -50,7 +52,8 @@ def test_serve_results_equal_solo(budget_kind):
         budget = int(64e9)
     else:
         # just above the largest single request: requests are served one after another
-        budget = max(max(rte.estimate_footprint(i, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0))
+        budget = max(max(rte.estimate_footprint(i, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0,
+                                                coarse_solver=rte.RTE_COARSE_QUICK))
                      for i in insts) + 1
     reqs = [serve.Request(rid=k, inst=inst, arrival=a) for k, (inst, a) in enumerate(zip(insts, arrivals))]
     srv = serve.Server(budget, opts(), max_slots=8, workers=2, keep_results=True)
