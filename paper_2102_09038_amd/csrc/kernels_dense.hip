@@ -5,6 +5,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 namespace rte {
 namespace {
@@ -285,6 +286,80 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_kernel(int M, int N, int K, 
         }
 }
 
+// FP64 form for shapes made of whole tiles (M, N multiples of 128, K of 16) with 16-byte
+// aligned operand rows: the tiles go from global memory straight into LDS
+// (global_load_lds_dwordx4: a wave moves one 128-element K row of a tile, 16 bytes a lane),
+// so no registers stage them and no LDS stores follow the MFMAs.  The next step's loads are
+// issued into the other buffer at the start of a step; the barrier at its end (which waits
+// for them) makes them visible.  Same tile order, fragments and summation order as above.
+__global__ __launch_bounds__(256, 2) void gemm_f64_dtl_kernel(int M, int N, int K, double alpha,
+                                                              const double* __restrict__ A, int lda,
+                                                              const double* __restrict__ B, int ldb, double beta,
+                                                              double* __restrict__ C, int ldc) {
+    typedef Mfma16<double> F;
+    __shared__ __attribute__((aligned(16))) double As[2][GBK][GBM + GPAD];
+    __shared__ __attribute__((aligned(16))) double Bs[2][GBK][GBN + GPAD];
+    const int tm = M / GBM, tn = N / GBN;
+    const int b = xcd_swizzle(blockIdx.x, tm * tn);
+    const bool mfast = tm < tn;
+    const int bm = mfast ? b % tm : b / tn, bn = mfast ? b / tm : b % tn;
+    const int m0 = bm * GBM, n0 = bn * GBN;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave & 1, wn = wave >> 1;
+    const int nk = K / GBK;
+    // wave w moves K rows w, w + 4, w + 8, w + 12 of both tiles
+    auto issue = [&](int kt, int buf) {
+#pragma unroll
+        for (int i = 0; i < GBK / 4; ++i) {
+            const int kr = wave + 4 * i;
+            const size_t gk = (size_t)kt * GBK + kr;
+            __builtin_amdgcn_global_load_lds(A + m0 + lda * gk + 2 * lane, &As[buf][kr][0], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(B + ldb * gk + n0 + 2 * lane, &Bs[buf][kr][0], 16, 0, 0);
+        }
+    };
+    typename F::acc_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = typename F::acc_t{0, 0, 0, 0};
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) issue(kt + 1, cur ^ 1);
+#pragma unroll
+        for (int kk = 0; kk < GBK / 4; ++kk) {
+            const int kr = kk * 4 + (lane >> 4);
+            double af[4], bf[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) af[i] = As[cur][kr][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bf[j] = Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[j][i] = F::mma(bf[j], af[i], acc[j][i]);
+        }
+        __builtin_amdgcn_s_waitcnt(0);       // this wave's tile loads have landed in LDS
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int gm = m0 + wm * 64 + i * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gn = n0 + wn * 64 + j * 16 + F::row(lane, v);
+                double* cp = C + gm + (size_t)ldc * gn;
+                const double val = alpha * acc[j][i][v];
+                *cp = (beta == 0.0) ? val : fma(beta, *cp, val);
+            }
+        }
+}
+
 // C[m, n] = alpha sum_p P[p][m + M n] + beta C[m + ldc n], the parts added in order
 template <typename TM, typename TC>
 __global__ void gemm_sum_parts_kernel(int M, int N, int nsplit, const TM* __restrict__ P, TM alpha, TM beta,
@@ -405,6 +480,17 @@ void gemm_mfma(int M, int N, int K, TM alpha, const TA* A, int lda, const TM* B,
             const int g = (int)std::min<size_t>((part + 255) / 256, 4096);
             hipLaunchKernelGGL((gemm_sum_parts_kernel<TM, TC>), dim3(g), dim3(256), 0, s, Mt, N, nsplit,
                                (const TM*)ws, alpha, beta, C + Mm, ldc);
+            RTE_CHECK_LAUNCH();
+            return;
+        }
+    }
+    if constexpr (std::is_same<TM, double>::value && std::is_same<TA, double>::value &&
+                  std::is_same<TC, double>::value) {
+        const bool aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(B) % 16 == 0) &&
+                             lda % 2 == 0 && ldb % 2 == 0;
+        if (aligned && M % GBM == 0 && N % GBN == 0 && K % GBK == 0 && K > 0) {
+            hipLaunchKernelGGL(gemm_f64_dtl_kernel, dim3(tiles), dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                               beta, C, ldc);
             RTE_CHECK_LAUNCH();
             return;
         }
