@@ -482,7 +482,7 @@ def main():
                "bytes_per_launch": e0_bytes, "time_share": t_e0 / dt}
     gemm_roof = {"bound": "mfma", "achieved": gemm_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": gemm_tf / FP64_MFMA_PEAK_TFLOPS, "traffic": measured_traffic("gemm_f64_transport"),
-                 "kernel": "gemm_mfma_kernel<double> (condensed transport term of E)",
+                 "kernel": "gemm_f64_dtl_kernel (condensed transport term of E; direct-to-LDS tiles)",
                  "avg_launch_ms": 1e3 * t_gm / max(n_gm, 1), "launches": n_gm,
                  "flops_per_launch": fl_gm / max(n_gm, 1), "time_share": t_gm / dt}
     dominant, other = (e0_roof, gemm_roof) if t_e0 >= t_gm else (gemm_roof, e0_roof)
