@@ -154,6 +154,24 @@ def test_apply_E(case, odd):
     assert rel(from_dev(Y), ops.E(U)) < 1e-10
 
 
+def test_apply_E_many_tiles():
+    """Condensed E U where the FP64 transport GEMM takes the direct-to-LDS kernel over many
+    whole tiles (48 x 48 squares, 128 sphere triangles: 128 x 4608 x 128, 36 tiles, so the
+    work-group to XCD map also takes its leftover branch), against the oracle."""
+    from paper_2102_09038_amd import rte
+    inst = inputs.make_instance("tiles-48x48-s128", 2, 48, 2, 0.5, 0.95, seed=9, n_even=0, n_odd=5, l=4,
+                                quad_level=2)
+    D, ops, h = make(inst)
+    o = rte.default_solve_opts(odd_solver=rte.RTE_ODD_CONDENSED)
+    U = np.random.default_rng(19).standard_normal((D.nRp, D.nS))
+    Y = torch.empty_like(to_dev(U))
+    h.apply_E(to_dev(U), Y, o)
+    err = rel(from_dev(Y), ops.E(U))
+    print(f"[tiles] E U rel err {err:.2e}")
+    assert err < 1e-10
+    h.close()
+
+
 @pytest.mark.parametrize("e0", ["cg", "banded"])
 def test_apply_E0inv(case, e0):
     from paper_2102_09038_amd import rte
