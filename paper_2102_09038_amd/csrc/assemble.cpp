@@ -304,6 +304,55 @@ void syevd(RocblasCtx& rb, hipStream_t s, int n, Vec& A, Vec& lam) {
     if (hinfo != 0) fail(RTE_E_HIP, "rocsolver_dsyevd did not converge");
 }
 
+// The dominant eigenpair of the symmetric n x n matrix A (col-major host) by power iteration on
+// the device from v0, for a correction space of one mode (N+ = 0), where a full
+// eigendecomposition is not needed.  The spectrum of the scaled S+ is the HG spectrum
+// 1 > g^2 > ... (one per even degree, up to the quadrature defect) and v0 = M^{1/2} 1 is the
+// discrete constant, already within the defect of the top eigenvector, so the iteration
+// contracts by about g^2 per step from a small start.  Converged when the vector moves by at
+// most 4e-16 (max norm) over 8 steps; false (the caller falls back to the full
+// eigendecomposition) if that takes more than 4000 steps.
+bool top_eigenpair(RocblasCtx& rb, hipStream_t s, int n, const Vec& A, const Vec& v0, Vec& v, double& lam) {
+    DBuf<double> dA(A.size()), x(n), y(n);
+    RTE_HIP(hipMemcpyAsync(dA.p, A.data(), A.size() * 8, hipMemcpyHostToDevice, s));
+    RTE_HIP(hipMemcpyAsync(x.p, v0.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+    Vec prev(v0), cur(n);
+    bool ok = false;
+    {
+        std::shared_lock<std::shared_mutex> lk(capture_mutex());
+        const double one = 1.0, zero = 0.0;
+        for (int it = 1; it <= 4000 && !ok; ++it) {
+            if (rocblas_dgemv(rb.h, rocblas_operation_none, n, n, &one, dA.p, n, x.p, 1, &zero, y.p, 1) !=
+                rocblas_status_success)
+                fail(RTE_E_HIP, "rocblas_dgemv failed");
+            double nrm = 0.0;
+            if (rocblas_dnrm2(rb.h, n, y.p, 1, &nrm) != rocblas_status_success) fail(RTE_E_HIP, "rocblas_dnrm2 failed");
+            if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
+            const double inv = 1.0 / nrm;
+            if (rocblas_dscal(rb.h, n, &inv, y.p, 1) != rocblas_status_success) fail(RTE_E_HIP, "rocblas_dscal failed");
+            std::swap(x.p, y.p);
+            if (it % 8 == 0) {
+                RTE_HIP(hipMemcpyAsync(cur.data(), x.p, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+                RTE_HIP(hipStreamSynchronize(s));
+                double d = 0.0;
+                for (int i = 0; i < n; ++i) d = std::max(d, std::fabs(cur[i] - prev[i]));
+                ok = d <= 4e-16;
+                prev.swap(cur);
+            }
+        }
+    }
+    if (!ok) return false;
+    v = prev;
+    // Rayleigh quotient on the host, in a fixed order
+    lam = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double t = 0.0;
+        for (int i = 0; i < n; ++i) t += A[i + (size_t)n * j] * v[i];
+        lam += v[j] * t;
+    }
+    return true;
+}
+
 }  // namespace
 
 Handle::~Handle() {
@@ -889,14 +938,29 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             for (int b = 0; b < nS; ++b)
                 Ap[a + (size_t)nS * b] =
                     0.5 * (h.h_Sp[a + (size_t)nS * b] + h.h_Sp[b + (size_t)nS * a]) * isq[a] * isq[b];
-        Vec lp;
-        syevd(rb, s, nS, Ap, lp);
         h.h_lamp.resize(h.dNp);
         h.h_Wp.resize((size_t)nS * h.dNp);
-        for (int c = 0; c < h.dNp; ++c) {
-            const int src = nS - 1 - c;
-            h.h_lamp[c] = lp[src];
-            for (int k = 0; k < nS; ++k) h.h_Wp[k + (size_t)nS * c] = Ap[k + (size_t)nS * src] * isq[k];
+        bool done = false;
+        if (h.dNp == 1) {
+            Vec v0(nS), v;
+            double nv = 0.0;
+            for (int k = 0; k < nS; ++k) { v0[k] = std::sqrt(h.h_m[k]); nv += h.h_m[k]; }
+            for (int k = 0; k < nS; ++k) v0[k] /= std::sqrt(nv);
+            double lam = 0.0;
+            if (top_eigenpair(rb, s, nS, Ap, v0, v, lam)) {
+                h.h_lamp[0] = lam;
+                for (int k = 0; k < nS; ++k) h.h_Wp[k] = v[k] * isq[k];
+                done = true;
+            }
+        }
+        if (!done) {
+            Vec lp;
+            syevd(rb, s, nS, Ap, lp);
+            for (int c = 0; c < h.dNp; ++c) {
+                const int src = nS - 1 - c;
+                h.h_lamp[c] = lp[src];
+                for (int k = 0; k < nS; ++k) h.h_Wp[k + (size_t)nS * c] = Ap[k + (size_t)nS * src] * isq[k];
+            }
         }
         h.Wp.upload(h.h_Wp, s);
 
