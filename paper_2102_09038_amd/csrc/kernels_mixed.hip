@@ -210,56 +210,61 @@ __global__ __launch_bounds__(256) void apply_grad_bf16_kernel(int nRm, int nRp, 
                                                               const double* __restrict__ mt,
                                                               const double* __restrict__ X,
                                                               uint16_t* __restrict__ Ycb) {
-    // one thread per cell and 8 consecutive directions: the cell's data is loaded once, the
-    // 8 BF16 results of each component go out as one 16-byte store.  Row j holds the d nS
-    // values twice: the GEMM multiplies [Y | Y] with [G_hi; G_lo], the operator carried as a
-    // pair of BF16 parts (16 significant bits).  The operator needs them: its d x d diagonal
-    // blocks are the odd moments 2 T_k of the sphere triangles, nearly singular for small
-    // triangles (s_x and s_y almost proportional over the triangle), and rounding them to
-    // 8 bits can make the transport term indefinite.  Rounding the data Y to BF16 only adds
-    // a small error to each product and leaves the operator positive definite.
-    const int nkc = nS / 8;
-    const size_t t = blockIdx.x * (size_t)256 + threadIdx.x;
-    if (t >= (size_t)nRm * nkc) return;
-    const int j = (int)(t % nRm);
-    const int k0 = (int)(t / nRm) * 8;
-    int cv[D + 1];
-    double dc[D + 1][D];
+    // Row j holds the d nS values twice: the GEMM multiplies [Y | Y] with [G_hi; G_lo], the
+    // operator carried as a pair of BF16 parts (16 significant bits).  The operator needs
+    // them: its d x d diagonal blocks are the odd moments 2 T_k of the sphere triangles,
+    // nearly singular for small triangles (s_x and s_y almost proportional over the
+    // triangle), and rounding them to 8 bits can make the transport term indefinite.
+    // Rounding the data Y to BF16 only adds a small error to each product and leaves the
+    // operator positive definite.
+    //
+    // A work-group takes 32 cells x 64 directions.  First each thread computes 8 directions
+    // of one cell (consecutive threads on consecutive cells, so the reads of X run along its
+    // columns) into an LDS tile; then the threads turn to write the tile's rows, 128
+    // contiguous bytes per cell and component, instead of one 16-byte piece per cell.
+    constexpr int TC = 32, TKD = 64;
+    __shared__ __attribute__((aligned(16))) uint16_t T[TC][D][TKD + 8];
+    const int j0 = blockIdx.x * TC, k0 = blockIdx.y * TKD;
+    {
+        const int c = threadIdx.x % TC, kg = threadIdx.x / TC;       // 8 groups of 8 directions
+        const int j = j0 + c, kb = k0 + 8 * kg;
+        if (j < nRm && kb < nS) {
+            int cv[D + 1];
+            double dc[D + 1][D];
 #pragma unroll
-    for (int v = 0; v < D + 1; ++v) {
-        cv[v] = cell[j * (D + 1) + v];
+            for (int v = 0; v < D + 1; ++v) {
+                cv[v] = cell[j * (D + 1) + v];
 #pragma unroll
-        for (int n = 0; n < D; ++n) dc[v][n] = Dc[(j * (D + 1) + v) * D + n];
-    }
-    const double inv = 1.0 / mt[j];
-    uint16_t out[D][8];
+                for (int n = 0; n < D; ++n) dc[v][n] = Dc[(j * (D + 1) + v) * D + n];
+            }
+            const double inv = 1.0 / mt[j];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-        double gn[D];
+            for (int kk = 0; kk < 8; ++kk) {
+                double gn[D];
 #pragma unroll
-        for (int n = 0; n < D; ++n) gn[n] = 0.0;
+                for (int n = 0; n < D; ++n) gn[n] = 0.0;
 #pragma unroll
-        for (int v = 0; v < D + 1; ++v) {
-            const double xv = X[cv[v] + (size_t)nRp * (k0 + kk)];
+                for (int v = 0; v < D + 1; ++v) {
+                    const double xv = X[cv[v] + (size_t)nRp * (kb + kk)];
 #pragma unroll
-            for (int n = 0; n < D; ++n) gn[n] = fma(dc[v][n], xv, gn[n]);
+                    for (int n = 0; n < D; ++n) gn[n] = fma(dc[v][n], xv, gn[n]);
+                }
+#pragma unroll
+                for (int n = 0; n < D; ++n) T[c][n][8 * kg + kk] = f32_to_bf16((float)(gn[n] * inv));
+            }
         }
-#pragma unroll
-        for (int n = 0; n < D; ++n) out[n][kk] = f32_to_bf16((float)(gn[n] * inv));
     }
+    __syncthreads();
+    // rows out: (cell, component) pairs, 8 chunks of 16 bytes each, both copies
     const size_t dn = (size_t)D * nS;
-    auto pack = [](const uint16_t* p) {
-        uint4 w;
-        w.x = p[0] | ((uint32_t)p[1] << 16);
-        w.y = p[2] | ((uint32_t)p[3] << 16);
-        w.z = p[4] | ((uint32_t)p[5] << 16);
-        w.w = p[6] | ((uint32_t)p[7] << 16);
-        return w;
-    };
-#pragma unroll
-    for (int n = 0; n < D; ++n) {
-        *reinterpret_cast<uint4*>(Ycb + (size_t)j * 2 * dn + (size_t)n * nS + k0) = pack(out[n]);
-        *reinterpret_cast<uint4*>(Ycb + (size_t)j * 2 * dn + dn + (size_t)n * nS + k0) = pack(out[n]);
+    for (int e = threadIdx.x; e < TC * D * 8; e += 256) {
+        const int ch = e % 8, row = e / 8;
+        const int c = row / D, n = row % D;
+        const int j = j0 + c, k = k0 + 8 * ch;
+        if (j >= nRm || k >= nS) continue;
+        const uint4 w = *reinterpret_cast<const uint4*>(&T[c][n][8 * ch]);
+        *reinterpret_cast<uint4*>(Ycb + (size_t)j * 2 * dn + (size_t)n * nS + k) = w;
+        *reinterpret_cast<uint4*>(Ycb + (size_t)j * 2 * dn + dn + (size_t)n * nS + k) = w;
     }
 }
 
@@ -278,8 +283,7 @@ void gemm_bf16(int M, int N, int K, float alpha, const uint16_t* A, int lda, con
 
 void apply_grad_bf16(const Handle* h, const double* X, uint16_t* Ycb, hipStream_t s) {
     if (h->nS % 8) fail(RTE_E_ARG, "the BF16 transport path needs a multiple of 8 sphere pairs");
-    const size_t n = (size_t)h->nRm * (h->nS / 8);
-    const dim3 g((unsigned)((n + 255) / 256));
+    const dim3 g((unsigned)((h->nRm + 31) / 32), (unsigned)((h->nS + 63) / 64));
     auto* f = h->d == 2 ? apply_grad_bf16_kernel<2> : apply_grad_bf16_kernel<3>;
     hipLaunchKernelGGL(f, g, dim3(256), 0, s, h->nRm, h->nRp, h->nS, h->cell.p, h->Dc.p, h->mt.p, X, Ycb);
     RTE_CHECK_LAUNCH();
