@@ -498,24 +498,41 @@ __global__ void scale_eigbasis_kernel(int nRm, int nSm, const double* __restrict
 }
 
 // ----------------------------------------------------------------------------- coarse
+// rhs[a + DN perm[i]] = sum_k T[i, k] W+[k, a].  A work-group takes 32 vertices; its 8
+// groups of 32 threads sum interleaved eighths of the directions (k = g, g + 8, ...), and the
+// eight partial sums are added in group order, so each vertex's long sum is split over 8
+// threads instead of walked by one.
 template <int DN>
 __global__ __launch_bounds__(TPB) void coarse_project_kernel(int nRp, int nS, const double* __restrict__ T,
                                                              const double* __restrict__ Wp,
                                                              const int* __restrict__ perm,
                                                              double* __restrict__ rhs) {
-    const int i = blockIdx.x * TPB + threadIdx.x;
-    if (i >= nRp) return;
+    constexpr int VB = 32, NG = TPB / VB;
+    __shared__ double part[NG][DN][VB];
+    const int v = threadIdx.x % VB, grp = threadIdx.x / VB;
+    const int i = blockIdx.x * VB + v;
     double acc[DN];
 #pragma unroll
     for (int a = 0; a < DN; ++a) acc[a] = 0.0;
-    for (int kk = 0; kk < nS; ++kk) {
-        const double t = T[i + (size_t)nRp * kk];
+    if (i < nRp) {
+        for (int kk = grp; kk < nS; kk += NG) {
+            const double t = T[i + (size_t)nRp * kk];
 #pragma unroll
-        for (int a = 0; a < DN; ++a) acc[a] = fma(t, Wp[kk + (size_t)nS * a], acc[a]);
+            for (int a = 0; a < DN; ++a) acc[a] = fma(t, Wp[kk + (size_t)nS * a], acc[a]);
+        }
     }
-    const int pi = perm[i];
 #pragma unroll
-    for (int a = 0; a < DN; ++a) rhs[a + (size_t)DN * pi] = acc[a];
+    for (int a = 0; a < DN; ++a) part[grp][a][v] = acc[a];
+    __syncthreads();
+    if (grp == 0 && i < nRp) {
+        const int pi = perm[i];
+#pragma unroll
+        for (int a = 0; a < DN; ++a) {
+            double sum = part[0][a][v];
+            for (int g2 = 1; g2 < NG; ++g2) sum += part[g2][a][v];
+            rhs[a + (size_t)DN * pi] = sum;
+        }
+    }
 }
 
 template <int DN>
@@ -675,7 +692,7 @@ template <int DN> struct OddPrecondL {
 };
 template <int DN> struct CoarseProjectL {
     static void run(const Handle* h, const double* T, double* rhs, hipStream_t s) {
-        hipLaunchKernelGGL(coarse_project_kernel<DN>, dim3((h->nRp + TPB - 1) / TPB), dim3(TPB), 0, s,
+        hipLaunchKernelGGL(coarse_project_kernel<DN>, dim3((h->nRp + 31) / 32), dim3(TPB), 0, s,
                            h->nRp, h->nS, T, h->Wp.p, h->perm.p, rhs);
     }
 };
