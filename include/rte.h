@@ -113,8 +113,8 @@ typedef enum rte_coarse_solver {
                                  update per block, then inverses of the diagonal factors
                                  folded into the coupling blocks); a solve is two
                                  block-diagonal products and two chains of n_c / bw
-                                 matrix-vector products.
-                                 Single solves only (the batch refuses such a handle)   */
+                                 matrix-vector products (kernels of this library
+                                 only, so a batch may capture them)                       */
 } rte_coarse_solver;
 
 typedef struct rte_handle rte_handle;   /* opaque; owns all device memory it allocates */

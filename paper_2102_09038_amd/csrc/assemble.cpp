@@ -357,7 +357,6 @@ bool top_eigenpair(RocblasCtx& rb, hipStream_t s, int n, const Vec& A, const Vec
 
 Handle::~Handle() {
     if (stream) (void)hipStreamSynchronize(stream);
-    coarse_block_release(*this);
     if (pinned) (void)hipHostFree(pinned);
     for (auto& r : prof) { evpool.push_back(r.a); evpool.push_back(r.b); }
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);

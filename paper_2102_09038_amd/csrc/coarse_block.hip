@@ -16,8 +16,8 @@
 // sweep:
 //     forward   w = diag(L_k^{-1}) b,     z_k = w_k - F_k z_{k-1}
 //     backward  v = diag(L_k^{-T}) z,     x_k = v_k - G_k^T x_{k+1}.
-// Every product is taken as a transposed one (y = A^T x reads A's columns, contiguous in the
-// column-major blocks, and runs several times faster than y = A x here), so the forward
+// Every product of the solve is taken as a transposed one, y = A^T x, which reads A's
+// columns, contiguous in the column-major blocks (one work-group per column), so the forward
 // sweep keeps L_k^{-T} and F_k^T.
 // Rows past n (the last block's padding) are an identity block decoupled from the rest.
 #include <rocblas/rocblas.h>
@@ -55,6 +55,55 @@ __global__ __launch_bounds__(TPB) void band_to_blocks_kernel(const double* __res
     }
 }
 
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// y_j = alpha sum_i A[i + lda j] x_i (+ y_j when accumulate) for the n columns of each of
+// blockIdx.y blocks (block b at A + b sa, x + b sx, y + b sy).  One work-group per column:
+// the threads run down the column 8 entries at a time, all 8 loads issued before the first
+// is used (past the column's end a load is skipped and reads as zero), into four partial
+// sums; the sums are combined in a fixed order.
+__global__ __launch_bounds__(TPB) void gemv_t_kernel(int n, double alpha, const double* __restrict__ A, size_t lda,
+                                                     size_t sa, const double* __restrict__ x, size_t sx,
+                                                     int accumulate, double* y, size_t sy) {
+    constexpr int U = 8;
+    __shared__ double sh[4];
+    const int j = blockIdx.x;
+    const size_t b = blockIdx.y;
+    const double* a = A + b * sa + (size_t)j * lda;
+    const double* xb = x + b * sx;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i0 = threadIdx.x; i0 < n; i0 += U * TPB) {
+        double av[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * TPB;
+            av[u] = i < n ? a[i] : 0.0;
+            xv[u] = i < n ? xb[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u % 4] = fma(av[u], xv[u], acc[u % 4]);
+    }
+    const double v = block_sum256((acc[0] + acc[1]) + (acc[2] + acc[3]), sh);
+    if (threadIdx.x == 0) {
+        double* yj = y + b * sy + j;
+        *yj = accumulate ? fma(alpha, v, *yj) : alpha * v;
+    }
+}
+
+void gemv_t(int n, double alpha, const double* A, size_t sa, const double* x, size_t sx, bool accumulate, double* y,
+            size_t sy, int nbat, hipStream_t s) {
+    hipLaunchKernelGGL(gemv_t_kernel, dim3(n, nbat), dim3(TPB), 0, s, n, alpha, A, (size_t)n, sa, x, sx,
+                       accumulate ? 1 : 0, y, sy);
+    RTE_CHECK_LAUNCH();
+}
+
 struct LibLock {
     std::lock_guard<std::mutex> serial{solver_library_mutex()};
     std::shared_lock<std::shared_mutex> capture{capture_mutex()};
@@ -69,6 +118,7 @@ void check_rb(rocblas_status st, const char* what) {
 void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStream_t s) {
     if (bw < 1) fail(RTE_E_ARG, "the block coarse factorisation needs a band half-width >= 1");
     const int bs = bw, nb = (n + bs - 1) / bs;
+    if (nb > 65535) fail(RTE_E_ARG, "the block coarse factorisation takes at most 65535 blocks");
     const size_t blk = (size_t)bs * bs;
     h.cbs = bs;
     h.cnb = nb;
@@ -142,44 +192,26 @@ void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStrea
         rocblas_destroy_handle(rb);
         throw;
     }
-    h.coarse_rb = rb;
-}
-
-void coarse_block_release(Handle& h) {
-    if (h.coarse_rb) {
-        std::shared_lock<std::shared_mutex> lk(capture_mutex());
-        rocblas_destroy_handle(static_cast<rocblas_handle>(h.coarse_rb));
-        h.coarse_rb = nullptr;
-    }
+    rocblas_destroy_handle(rb);
 }
 
 void coarse_block_solve(Handle* h, const double* rhs, double* x, hipStream_t s) {
     const int bs = h->cbs, nb = h->cnb, n = h->nc;
     const size_t blk = (size_t)bs * bs, np = (size_t)nb * bs;
-    auto rb = static_cast<rocblas_handle>(h->coarse_rb);
     double* y = h->cwork.p;
     double* z = h->cwork.p + np;
     k::fill(y, 0.0, np, s);
     k::copy(rhs, y, (size_t)n, s);
-    std::shared_lock<std::shared_mutex> lk(capture_mutex());
-    check_rb(rocblas_set_stream(rb, s), "rocblas_set_stream");
-    const double one = 1.0, minus_one = -1.0, zero = 0.0;
     // forward: z = diag(L_k^{-1}) y, then z_k -= F_k z_{k-1}  (from L_k^{-T} and F_k^T)
-    check_rb(rocblas_dgemv_strided_batched(rb, rocblas_operation_transpose, bs, bs, &one, h->CLinvT.p, bs, blk, y,
-                                           1, bs, &zero, z, 1, bs, nb),
-             "rocblas_dgemv_strided_batched");
+    gemv_t(bs, 1.0, h->CLinvT.p, blk, y, bs, false, z, bs, nb, s);
     for (int k = 1; k < nb; ++k)
-        check_rb(rocblas_dgemv(rb, rocblas_operation_transpose, bs, bs, &minus_one, h->CB.p + (size_t)(k - 1) * blk,
-                               bs, z + (size_t)(k - 1) * bs, 1, &one, z + (size_t)k * bs, 1),
-                 "rocblas_dgemv");
+        gemv_t(bs, -1.0, h->CB.p + (size_t)(k - 1) * blk, 0, z + (size_t)(k - 1) * bs, 0, true, z + (size_t)k * bs,
+               0, 1, s);
     // backward: y = diag(L_k^{-T}) z, then y_k -= G_k^T y_{k+1}
-    check_rb(rocblas_dgemv_strided_batched(rb, rocblas_operation_transpose, bs, bs, &one, h->CLinv.p, bs, blk, z, 1,
-                                           bs, &zero, y, 1, bs, nb),
-             "rocblas_dgemv_strided_batched");
+    gemv_t(bs, 1.0, h->CLinv.p, blk, z, bs, false, y, bs, nb, s);
     for (int k = nb - 2; k >= 0; --k)
-        check_rb(rocblas_dgemv(rb, rocblas_operation_transpose, bs, bs, &minus_one, h->CG.p + (size_t)k * blk, bs,
-                               y + (size_t)(k + 1) * bs, 1, &one, y + (size_t)k * bs, 1),
-                 "rocblas_dgemv");
+        gemv_t(bs, -1.0, h->CG.p + (size_t)k * blk, 0, y + (size_t)(k + 1) * bs, 0, true, y + (size_t)k * bs, 0, 1,
+               s);
     k::copy(y, x, (size_t)n, s);
 }
 

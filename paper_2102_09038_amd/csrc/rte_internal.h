@@ -156,10 +156,9 @@ struct Handle {
     DBuf<double> Ecinv;            // explicit E_c^{-1} (nc x nc, band order) when it fits its budget
     // block-tridiagonal Cholesky of E_c (coarse_block.hip) for wide coarse bands: cnb blocks
     // of cbs rows; inverses of the diagonal factors and their transposes, the two folded
-    // coupling blocks per block boundary, two work vectors and the rocBLAS handle of the solve
+    // coupling blocks per block boundary and two work vectors of the solve
     int cbs = 0, cnb = 0;
     DBuf<double> CLinv, CLinvT, CB, CG, cwork;
-    void* coarse_rb = nullptr;
     DBuf<int> perm, iperm;         // [nRp] spatial reordering (reverse Cuthill-McKee) and inverse
     int sbw = 0;                   // spatial band width in that order
 
@@ -222,7 +221,6 @@ void batch_set_graphs(Batch* B, bool on);
 // band layout autotuning of the E_0 factors (autotune.cpp)
 void derived_outputs(Handle* h, const double* U, double* phi, double* balance, hipStream_t s);
 void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStream_t s);
-void coarse_block_release(Handle& h);
 void coarse_block_solve(Handle* h, const double* rhs, double* x, hipStream_t s);
 void autotune(Handle* h, int flags, hipStream_t s, rte_tune_report* rep);
 void set_band_layout(Handle* h, int precision, int H, int P, hipStream_t s);

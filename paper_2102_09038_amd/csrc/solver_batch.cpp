@@ -183,11 +183,12 @@ void enqueue_precond_update(Batch* B, hipStream_t s) {
         }
     }
     // the subspace correction: right-hand sides, then the coarse solves (explicit inverses
-    // one by one, band factors in one grouped launch), then the steps and updates
+    // and block factorisations one by one, band factors in one grouped launch), then the
+    // steps and updates
     for (auto& sl : B->slots)
         if (sl.live) correction_rhs(sl.h, &sl.o, ws(sl.h, W_ER), ws(sl.h, W_ES), s, nullptr, lowp);
     for (auto& sl : B->slots)
-        if (sl.live && sl.h->Ecinv.p) coarse_solve(sl.h, s);
+        if (sl.live && (sl.h->Ecinv.p || sl.h->cnb)) coarse_solve(sl.h, s);
     if (!B->cplan.launches.empty()) k::band_group_run(B->cplan, s);
     for (auto& sl : B->slots) {
         if (!sl.live) continue;
@@ -258,7 +259,6 @@ int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, 
         fail(RTE_E_ARG, "batch slots need the banded E_0 solve (assemble with e0_solver = RTE_E0_BANDED)");
     if (o->odd_solver == RTE_ODD_PCG) fail(RTE_E_ARG, "batch slots use the exact or condensed odd solve");
     if (o->inner != RTE_INNER_RICHARDSON) fail(RTE_E_ARG, "batch slots use the Richardson inner iteration");
-    if (h->cnb) fail(RTE_E_ARG, "batch slots need a coarse solve without library calls (not RTE_COARSE_BLOCK)");
     if (o->precision == RTE_MIXED && !(h->have_mixed && h->L0f.p))
         fail(RTE_E_ARG, "a mixed-precision slot needs a handle assembled with mixed != 0");
     if (o->precision == RTE_FP64 && !h->L0.p) fail(RTE_E_ARG, "an FP64 slot needs the FP64 band factors");

@@ -78,6 +78,32 @@ def test_batch_with_band_coarse_solve_equals_single_solves():
 
 
 @pytest.mark.parametrize("graphs", [True, False])
+def test_batch_with_block_coarse_solve_equals_single_solves(graphs):
+    """Handles whose coarse system takes the block-tridiagonal Cholesky (forced here on small
+    instances): the batch runs their block solves slot by slot, inside the captured graphs or
+    eagerly, and matches the solo solves bit for bit."""
+    from paper_2102_09038_amd import rte
+    insts = instances()[:3]
+    hs = [rte.Handle.from_instance(i, e0_solver=rte.RTE_E0_BANDED, mixed=1, coarse_solver=rte.RTE_COARSE_BLOCK)
+          for i in insts]
+    o = opts_for(rte.RTE_FP64)
+    ref = [alone(h, o) for h in hs]
+    b = rte.Batch(max_slots=8, use_graphs=graphs)
+    outs = [torch.full((h.dims.nSp, h.dims.nRp), np.nan, dtype=torch.float64, device="cuda") for h in hs]
+    slots = [b.admit(h, U, o) for h, U in zip(hs, outs)]
+    assert b.step(1000) == 0
+    torch.cuda.synchronize()
+    done = {s: (st, info) for s, st, info in b.poll()}
+    for k, (s, U) in enumerate(zip(slots, outs)):
+        st, info = done[s]
+        assert st == rte.RTE_OK and info.iters == ref[k][1].iters
+        assert torch.equal(U, ref[k][0])
+    b.close()
+    for h in hs:
+        h.close()
+
+
+@pytest.mark.parametrize("graphs", [True, False])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_equals_single_solves(handles, prec, graphs):
     """Graph mode replays the captured iteration many times, with host synchronisations and
