@@ -170,7 +170,8 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
     const double* __restrict__ X, const double* __restrict__ G, const double* __restrict__ q,
     double* __restrict__ Y) {
     constexpr int TI = 32, TK = 64;
-    constexpr int KI = 8;                    // incidences per batch
+    constexpr int KI = D == 2 ? 6 : 8;       // incidences per batch (six triangles meet at an
+                                             // interior vertex of the 2D meshes)
     constexpr int RMAX = D == 2 ? 8 : 16;    // pattern entries held in registers
     __shared__ double T[TI][TK + 1];
     const int i0 = blockIdx.x * TI, k0 = blockIdx.y * TK;
