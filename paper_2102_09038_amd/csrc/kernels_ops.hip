@@ -756,9 +756,10 @@ void apply_At_E_rm_f32(const Handle* h, const float* Z, const double* X, const d
 }
 
 void apply_grad(const Handle* h, const double* X, double* Yc, hipStream_t s) {
-    const size_t n = (size_t)h->nRm * ((h->nS + kAtEK - 1) / kAtEK);
+    constexpr int KC = 16;   // directions per thread
+    const size_t n = (size_t)h->nRm * ((h->nS + KC - 1) / KC);
     const dim3 g((unsigned)((n + TPB - 1) / TPB));
-    auto* f = h->d == 2 ? apply_grad_kernel<2, kAtEK> : apply_grad_kernel<3, kAtEK>;
+    auto* f = h->d == 2 ? apply_grad_kernel<2, KC> : apply_grad_kernel<3, KC>;
     hipLaunchKernelGGL(f, g, dim3(TPB), 0, s, h->nRm, h->nRp, h->nS, h->cell.p, h->Dc.p, h->mt.p, X, Yc);
     RTE_CHECK_LAUNCH();
 }
