@@ -172,7 +172,8 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
     constexpr int TI = 32, TK = 64;
     constexpr int KI = D == 2 ? 6 : 8;       // incidences per batch (six triangles meet at an
                                              // interior vertex of the 2D meshes)
-    constexpr int RMAX = D == 2 ? 8 : 16;    // pattern entries held in registers
+    constexpr int RMAX = D == 2 ? 7 : 16;    // pattern entries held in registers (a vertex and
+                                             // its six neighbours in 2D; longer rows loop)
     __shared__ double T[TI][TK + 1];
     const int i0 = blockIdx.x * TI, k0 = blockIdx.y * TK;
     const int lane = threadIdx.x & 63;
