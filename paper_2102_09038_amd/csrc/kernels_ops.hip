@@ -185,38 +185,54 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
         // skipped in the sum, so every load is unconditional and the batch's loads are in
         // flight together
         const int k = min(k0 + lane, nS - 1);
-        for (int il = wave; il < TI; il += 4) {
-            const int i = i0 + il;
-            double acc = 0.0;
-            if (i < nRp) {
-                const int e0 = vc_ptr[i], e1 = vc_ptr[i + 1];
-                for (int eb = e0; eb < e1; eb += KI) {
-                    int cj[KI];
-                    double w[KI][D];
-                    ZT z[KI][D];        // converted only when summed
+        // two vertices per pass (il and il + 4), so that both vertices' loads are in flight
+        for (int il = wave; il < TI; il += 8) {
+            int e0[2], e1[2];
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int i = i0 + il + 4 * v;
+                e0[v] = i < nRp ? vc_ptr[i] : 0;
+                e1[v] = i < nRp ? vc_ptr[i + 1] : 0;
+            }
+            double acc[2] = {0.0, 0.0};
+            const int nbat = max((e1[0] - e0[0] + KI - 1) / KI, (e1[1] - e0[1] + KI - 1) / KI);
+            for (int bt = 0; bt < nbat; ++bt) {
+                int cj[2][KI];
+                double w[2][KI][D];
+                ZT z[2][KI][D];        // converted only when summed
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    // a vertex whose incidences are used up re-reads its last one (skipped in
+                    // the sum); a vertex past the end reads incidence 0 of the mesh
+                    const int last = e1[v] > e0[v] ? e1[v] - 1 : 0;
 #pragma unroll
                     for (int t = 0; t < KI; ++t) {
-                        const int e = min(eb + t, e1 - 1);
-                        cj[t] = vc_cell[e];
+                        const int e = min(e0[v] + bt * KI + t, last);
+                        cj[v][t] = vc_cell[e];
 #pragma unroll
-                        for (int n = 0; n < D; ++n) w[t][n] = vcD[(size_t)e * D + n];
-                    }
-#pragma unroll
-                    for (int t = 0; t < KI; ++t) {
-                        const ZT* zr = Z + (size_t)cj[t] * dn + k;
-#pragma unroll
-                        for (int n = 0; n < D; ++n) z[t][n] = zr[(size_t)n * nS];
-                    }
-#pragma unroll
-                    for (int t = 0; t < KI; ++t) {
-                        if (eb + t < e1) {
-#pragma unroll
-                            for (int n = 0; n < D; ++n) acc = fma(w[t][n], (double)z[t][n], acc);
-                        }
+                        for (int n = 0; n < D; ++n) w[v][t][n] = vcD[(size_t)e * D + n];
                     }
                 }
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+#pragma unroll
+                    for (int t = 0; t < KI; ++t) {
+                        const ZT* zr = Z + (size_t)cj[v][t] * dn + k;
+#pragma unroll
+                        for (int n = 0; n < D; ++n) z[v][t][n] = zr[(size_t)n * nS];
+                    }
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+#pragma unroll
+                    for (int t = 0; t < KI; ++t) {
+                        if (e0[v] + bt * KI + t < e1[v]) {
+#pragma unroll
+                            for (int n = 0; n < D; ++n) acc[v] = fma(w[v][t][n], (double)z[v][t][n], acc[v]);
+                        }
+                    }
             }
-            T[il][lane] = acc;
+            T[il][lane] = acc[0];
+            T[il + 4][lane] = acc[1];
         }
     }
     __syncthreads();
