@@ -82,23 +82,30 @@ def angular_quadrature(svert, stri, r_q: int) -> AngularQuadrature:
     return AngularQuadrature(np.array(P), np.array(W))
 
 
-def scattering_rows(q: AngularQuadrature, g: float, rows):
+def scattering_rows(q: AngularQuadrature, g: float, rows, max_pairs: int = 1 << 23):
     """Rows ``rows`` (pair indices k) of S+ [len(rows), nS] and of S- as
-    [len(rows), 3, nS, 3] (entry [r, n, k', m] = S-_{(k_r,n),(k',m)})."""
+    [len(rows), 3, nS, 3] (entry [r, n, k', m] = S-_{(k_r,n),(k',m)}).
+
+    The double sum over the points p of K_k and q of every K_k' is taken over slices of p
+    holding at most ``max_pairs`` point pairs, so that the temporaries stay bounded at high
+    quadrature levels; every entry is the same double sum, added slice by slice."""
     P, W = q.pts, q.wts
-    nS = P.shape[0]
+    nS, Q = P.shape[0], P.shape[1]
     Sp = np.zeros((len(rows), nS))
     Sm = np.zeros((len(rows), 3, nS, 3))
+    step = max(1, max_pairs // (nS * Q))
     for r, k in enumerate(rows):
-        diff = P[k][:, None, None, :] - P[None, :, :, :]       # [Q, nS, Q', 3]
-        summ = P[k][:, None, None, :] + P[None, :, :, :]
-        d2 = np.einsum("ijkl,ijkl->ijk", diff, diff)
-        e2 = np.einsum("ijkl,ijkl->ijk", summ, summ)
-        kp, km = hg_pm(d2, e2, g)
-        ww = W[k][:, None, None] * W[None, :, :]               # [Q, nS, Q']
-        Sp[r] = 2.0 * np.einsum("pkq->k", ww * (kp + km))
-        F = ww * (kp - km)
-        Sm[r] = 2.0 * np.einsum("pn,pkq,kqm->nkm", P[k], F, P)
+        for p0 in range(0, Q, step):
+            Pk, Wk = P[k, p0:p0 + step], W[k, p0:p0 + step]
+            diff = Pk[:, None, None, :] - P[None, :, :, :]         # [p, nS, Q', 3]
+            summ = Pk[:, None, None, :] + P[None, :, :, :]
+            d2 = np.einsum("ijkl,ijkl->ijk", diff, diff)
+            e2 = np.einsum("ijkl,ijkl->ijk", summ, summ)
+            kp, km = hg_pm(d2, e2, g)
+            ww = Wk[:, None, None] * W[None, :, :]                 # [p, nS, Q']
+            Sp[r] += 2.0 * np.einsum("pkq->k", ww * (kp + km))
+            F = ww * (kp - km)
+            Sm[r] += 2.0 * np.einsum("pn,pkq,kqm->nkm", Pk, F, P)
     return Sp, Sm
 
 
