@@ -343,11 +343,14 @@ rte_status rte_batch_step(rte_batch* b, int32_t outer_iters, void* hip_stream, i
 rte_status rte_batch_poll(rte_batch* b, int32_t max_out, int32_t* slots, rte_solve_info* infos,
                           int32_t* statuses, int32_t* n_done);
 
-/* use_graphs != 0 (the default): each lockstep iteration replays two captured HIP graphs
- * (the residuals; the preconditioner, correction and update), recaptured whenever the set
- * of live slots changes, on a stream the batch owns (ordered after the caller's stream's
- * earlier work, and the caller's later work after it).  0: the same launches are issued one
- * by one on the caller's stream.  The results are identical. */
+/* use_graphs != 0: each lockstep iteration replays two captured HIP graphs (the residuals;
+ * the preconditioner, correction and update), recaptured whenever the set of live slots
+ * changes, on a stream the batch owns (ordered after the caller's stream's earlier work, and
+ * the caller's later work after it).  0 (the default): the same launches are issued one by
+ * one on the caller's stream.  The results are identical.  Graph mode must not run while
+ * other threads of the process assemble handles (rte_assemble): that combination has
+ * produced assembly inputs that were not positive definite, with no cause shown, so it is
+ * not supported. */
 rte_status rte_batch_set_graphs(rte_batch* b, int32_t use_graphs);
 
 /* Slots still iterating, finished slots not yet polled, device bytes held by admitted slots. */

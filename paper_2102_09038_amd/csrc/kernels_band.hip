@@ -621,6 +621,19 @@ void band_group_run(const BandGroupPlan& plan, hipStream_t s) {
     }
 }
 
+// The factorisation's LDS window limit is raised once per process, to the largest window any
+// band may use (150 KiB), and never per call: concurrent assemblies on other threads launch
+// the same kernel with windows of their own size, and a per-call attribute write by one of
+// them could lower the limit under another's launch (or land inside a graph capture).
+void raise_factor_window() {
+    static const bool attr = [] {
+        RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&e0_band_factor_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+        return true;
+    }();
+    (void)attr;
+}
+
 void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, double* BL, double* BU,
                     size_t stride_sys, int* bad, hipStream_t s) {
     const size_t lds = (size_t)(bw + 1) * (bw + 1) * sizeof(double);
@@ -630,8 +643,7 @@ void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, 
     hipLaunchKernelGGL(e0_band_fill_kernel, dim3((rows + 255) / 256, h->nS), dim3(256), 0, s, h->nRp, bw, h->nnz,
                        h->ncls, h->rowptr.p, h->col.p, h->cls.p, h->coefE0.p, perm, iperm, BL, BU, stride_sys);
     RTE_CHECK_LAUNCH();
-    RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&e0_band_factor_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    raise_factor_window();
     hipLaunchKernelGGL(e0_band_factor_kernel, dim3(h->nS), dim3(bw >= 120 ? 1024 : 512), lds, s, h->nRp, bw, BL, BU,
                        stride_sys, bad);
     RTE_CHECK_LAUNCH();
@@ -640,8 +652,7 @@ void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, 
 void band_factor_one(int n, int bw, double* BL, double* BU, int* bad, hipStream_t s) {
     const size_t lds = (size_t)(bw + 1) * (bw + 1) * sizeof(double);
     if (lds > 150 * 1024 || bw + 1 > 16 * kFacCols) fail(RTE_E_ARG, "band too wide for the LDS factorisation window");
-    RTE_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&e0_band_factor_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    raise_factor_window();
     hipLaunchKernelGGL(e0_band_factor_kernel, dim3(1), dim3(bw >= 120 ? 1024 : 512), lds, s, n, bw, BL, BU,
                        (size_t)0, bad);
     RTE_CHECK_LAUNCH();

@@ -44,9 +44,10 @@ struct Batch {
     // factors, one grouped launch
     k::BandGroupPlan cplan;
     bool plan_valid = false;
-    // graph mode: the two launch sequences of an iteration (residuals; preconditioner and
-    // update) are captured once per set of live slots and replayed, on the batch's own stream
-    bool use_graphs = true;
+    // graph mode (off unless asked for): the two launch sequences of an iteration (residuals;
+    // preconditioner and update) are captured once per set of live slots and replayed, on the
+    // batch's own stream
+    bool use_graphs = false;
     hipStream_t gs = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraphExec_t g_res = nullptr, g_prec = nullptr;

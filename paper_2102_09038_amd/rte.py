@@ -326,7 +326,7 @@ class Batch:
     """Lockstep batch of solves (rte_batch_*): admit handles with their output arrays, step
     all live slots together, poll finished ones.  Handles and arrays must outlive their slot."""
 
-    def __init__(self, max_slots=64, hbm_budget=0, use_graphs=True):
+    def __init__(self, max_slots=64, hbm_budget=0, use_graphs=False):
         self.b = C.c_void_p()
         _check(lib.rte_batch_create(int(max_slots), int(hbm_budget), C.byref(self.b)))
         self._keep = {}

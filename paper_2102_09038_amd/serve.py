@@ -52,6 +52,11 @@ class Server:
                  keep_results: bool = False, on_done: Optional[Callable[[Request], None]] = None,
                  odd_eig: int = 0, use_graphs: bool = False, coarse_solver: int = rte.RTE_COARSE_QUICK):
         import torch
+        if use_graphs and workers > 0:
+            # graph replay beside concurrent assembly has reported assembly matrices that were
+            # not positive definite for requests that assemble correctly alone, and no cause
+            # has been shown; the combination is refused until one is
+            raise ValueError("graph mode is not supported while assembly workers run (use_graphs=False)")
         self.torch = torch
         self.budget = int(budget)
         self.opts = solve_opts
