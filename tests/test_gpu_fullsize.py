@@ -51,6 +51,35 @@ def test_scattering_rows(realistic):
         assert e1 < 1e-12 and e2 < 1e-12
 
 
+def test_apply_E_rows_against_stored_oracle(realistic):
+    """E U and K+ U at the full size for the seeded U of tests/golden/make_fullsize_golden.py,
+    on the rows of sampled vertices (each row spans all 1024 directions, so it carries the
+    whole odd scattering inverse), against the oracle's values stored by that script: the
+    condensed transport GEMM (the form the solve runs) and the exact per-cell inverse, 1e-10;
+    K+ U 1e-12."""
+    import os
+    from paper_2102_09038_amd import rte
+    inst, D, h = realistic
+    z = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_realistic.npz"))
+    verts = list(z["verts"])
+    U = np.random.Generator(np.random.PCG64(int(z["seed_U"]))).standard_normal((D.nRp, D.nS))
+    Ud = to_dev(U)
+    del U
+    Y = torch.empty_like(Ud)
+    idx = torch.tensor(verts, device="cuda")
+    for odd in (rte.RTE_ODD_CONDENSED, rte.RTE_ODD_EXACT):
+        h.apply_E(Ud, Y, rte.default_solve_opts(odd_solver=odd))
+        got = Y[:, idx].cpu().numpy().T
+        err = float(np.linalg.norm(got - z["EU_rows"]) / np.linalg.norm(z["EU_rows"]))
+        print(f"E U rows ({'condensed' if odd == rte.RTE_ODD_CONDENSED else 'exact'}) vs oracle: {err:.2e}")
+        assert err < 1e-10
+    h.apply_scatter(1, Ud, Y)
+    got = Y[:, idx].cpu().numpy().T
+    err = float(np.linalg.norm(got - z["KU_rows"]) / np.linalg.norm(z["KU_rows"]))
+    print(f"K+ U rows vs oracle: {err:.2e}")
+    assert err < 1e-12
+
+
 def test_e0inv_sampled_directions(realistic):
     import scipy.sparse.linalg as spla
     from paper_2102_09038_amd import rte
