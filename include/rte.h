@@ -71,7 +71,10 @@ typedef enum rte_odd_solver {
 
 /* How each block of E_0^{-1} is applied (Sec. 5.3). */
 typedef enum rte_e0_solver {
-    RTE_E0_CG = 0,        /* Jacobi-preconditioned CG per direction                    */
+    RTE_E0_CG = 0,        /* Jacobi-preconditioned CG on every direction block at once
+                             (sliced-ELL storage, per-direction early exit); with
+                             precision RTE_MIXED its vectors and values are FP32 (dot
+                             products FP64) and it stops at max(cg_tol, 1e-6)          */
     RTE_E0_BANDED = 1     /* banded Cholesky factors per direction, factored once      */
 } rte_e0_solver;
 
@@ -194,7 +197,9 @@ typedef struct rte_solve_info {
     double gemm_flops;           /*   and their algorithmic flops (2 M N K summed)           */
     double t_gemm_bf16;          /*   seconds inside BF16 (mixed-precision) GEMM kernels     */
     int64_t n_gemm_bf16;         /*   number of those launches                               */
-    double gemm_bf16_flops;      /*   their algorithmic flops                                */
+    double gemm_bf16_flops;      /*   their algorithmic flops (the method's contraction,     */
+                                 /*   2 n_R- (d n_S+)^2; the kernel runs twice that on the  */
+                                 /*   hi/lo operator pair)                                   */
     double t_scatter;            /*   seconds inside the FP64 even scatter GEMMs U S+        */
     int64_t n_scatter;           /*   (eq. tpmv), their launches                             */
     double scatter_flops;        /*   and their algorithmic flops                            */

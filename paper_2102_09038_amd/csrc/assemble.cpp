@@ -24,6 +24,7 @@
 
 #include "ops.h"
 #include "rte_internal.h"
+#include "solver_detail.h"
 
 namespace rte {
 namespace {
@@ -225,6 +226,41 @@ std::vector<int> rcm(int n, const std::vector<int>& rp, const std::vector<int>& 
     return perm;
 }
 
+// The P1 pattern (CSR rp / ci) in sliced ELL form for the CG solve of E_0: slices of 64 rows,
+// as many slots as the slice's longest row, slot j of a slice one contiguous group of 64
+// entries (lane = row).  sptr[s] = first slot group of slice s; col = column of every entry (the
+// row itself on padding, whose value is zero); epos = the entry's CSR position (-1 on padding).
+// Returns the number of entries; the arrays are filled when non-null.
+size_t sliced_ell(int n, const std::vector<int>& rp, const std::vector<int>& ci, std::vector<int>* sptr,
+                  std::vector<int>* col, std::vector<int>* epos) {
+    const int nslice = (n + 63) / 64;
+    std::vector<int> sp(nslice + 1, 0);
+    for (int sl = 0; sl < nslice; ++sl) {
+        int w = 0;
+        for (int i = 64 * sl; i < std::min(n, 64 * sl + 64); ++i) w = std::max(w, rp[i + 1] - rp[i]);
+        sp[sl + 1] = sp[sl] + w;
+    }
+    const size_t len = (size_t)sp[nslice] * 64;
+    if (col && epos) {
+        col->assign(len, 0);
+        epos->assign(len, -1);
+        for (int sl = 0; sl < nslice; ++sl)
+            for (int j = 0; j < sp[sl + 1] - sp[sl]; ++j)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int i = 64 * sl + lane;
+                    const size_t q = ((size_t)sp[sl] + j) * 64 + lane;
+                    if (i < n && j < rp[i + 1] - rp[i]) {
+                        (*epos)[q] = rp[i] + j;
+                        (*col)[q] = ci[rp[i] + j];
+                    } else {
+                        (*col)[q] = i < n ? i : 0;
+                    }
+                }
+    }
+    if (sptr) *sptr = sp;
+    return len;
+}
+
 // rocBLAS handle on the assembly stream; creation, destruction and every library call hold
 // the capture lock shared
 struct RocblasCtx {
@@ -369,7 +405,9 @@ size_t Handle::footprint() const {
                coefE0.bytes() + coefE.bytes() + diagE0.bytes() + vc_ptr.bytes() + vc_cell.bytes() + vc_loc.bytes() +
                q.bytes() + Lc.bytes() + LcU.bytes() + CLinv.bytes() + CLinvT.bytes() + CB.bytes() + CG.bytes() + cwork.bytes() + perm.bytes() + iperm.bytes() + L0.bytes() + L0U.bytes() + Ecinv.bytes() +
                Gc.bytes() + vcD.bytes() +
-               MtMs.bytes() + bnd_row.bytes() + cg_iters.bytes() +
+               MtMs.bytes() + bnd_row.bytes() + cg_iters.bytes() + ell_sptr.bytes() + ell_col.bytes() + ell_e.bytes() +
+               ell_v64.bytes() + ell_dinv64.bytes() + ell_v32.bytes() + ell_dinv32.bytes() + cg_part.bytes() +
+               cg_scal.bytes() + cg_state.bytes() +
                Sp_f.bytes() + Sm_f.bytes() + Gc_bf.bytes() + L0f.bytes() + L0Uf.bytes() + red.bytes() +
                scal.bytes();
     for (auto& w : ws) b += w.bytes();
@@ -753,6 +791,14 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     h.ms.upload(ms, s);
     h.rowptr.upload(rp, s);
     h.col.upload(ci, s);
+    {
+        std::vector<int> sptr, ecol, epos;
+        h.ell_len = sliced_ell(nRp, rp, ci, &sptr, &ecol, &epos);
+        h.ell_nslice = (nRp + 63) / 64;
+        h.ell_sptr.upload(sptr, s);
+        h.ell_col.upload(ecol, s);
+        h.ell_e.upload(epos, s);
+    }
     h.Msv.upload(Msv, s);
     h.cls.upload(cls, s);
     h.coefE0.upload(coefE0, s);
@@ -1147,7 +1193,10 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         RTE_HIP(hipStreamSynchronize(s));
         if (hb) fail(RTE_E_ARG, "an E_0 block lost positive definiteness in the band factorisation");
         h.have_e0_banded = true;
-    } else if (o->e0_solver != RTE_E0_CG) {
+    } else if (o->e0_solver == RTE_E0_CG) {
+        sv::cg_prepare(&h, false, s);
+        if (o->mixed) sv::cg_prepare(&h, true, s);
+    } else {
         fail(RTE_E_ARG, "unknown e0_solver");
     }
 
@@ -1271,6 +1320,15 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
         if (o->mixed) b += 2 * k::band_blk_size(nRp, sbw, 4) * nS * 4;
     }
     if (o->mixed) b += (nS * nS + nSm * nSm) * 4 + 2 * (size_t)d * nS * d * nS * 2;
+    // the sliced ELL pattern; with the CG solver the explicit values (FP64, and FP32 when mixed),
+    // inverse diagonals, three CG vectors and the per-tile partials
+    const size_t ell = sliced_ell(nRp, rp, ci, nullptr, nullptr, nullptr);
+    b += ell * 8 + ((size_t)nRp / 64 + 2) * 4;
+    if (o->e0_solver == RTE_E0_CG) {
+        const size_t ntiles = ((size_t)nRp + 255) / 256;
+        b += nS * ell * 8 + even * 8 + 3 * even * 8 + 4 * nS * ntiles * 8 + 3 * nS * 8 + (nS + 1) * 4;
+        if (o->mixed) b += nS * ell * 4 + even * 4;
+    }
     // solver workspace: two odd-sized buffers, eleven even vectors, coarse vectors, reductions
     b += 2 * (size_t)nRm * nSm * 8 + 11 * even * 8 + 2 * nc * 8 + (1 << 16);
     if (peak) *peak = b + transient;

@@ -1,0 +1,328 @@
+// E_0^{-1} by conjugate gradients on every direction block at once (Sec. 5.3: E_0 is block
+// diagonal over the directions, each block an SPD anisotropic diffusion-reaction matrix on
+// the P1 space).  Jacobi preconditioning; all directions iterate in the same launches and a
+// direction that has converged stops doing work (per-direction early exit).
+//
+// Storage: the P1 pattern in sliced ELL form.  Rows are cut into slices of 64 (one wave, lane
+// = row); a slice holds as many entry slots as its longest row, and entry j of the slice's
+// rows sits in one contiguous group of 64, so a wave's loads of values and columns are single
+// 256- or 512-byte transactions.  The column pattern is shared by every direction; each
+// direction has its own explicit values (formed once from the pattern's value classes).
+//
+// One CG iteration is three launches over (row tile, direction) work-groups of 256 rows:
+//   spmv    q = E_0 p, partial sums of p.q per tile;
+//   update  alpha = rz / p.q (the tile partials summed in a fixed order by every work-group of
+//           the direction, so all of them get the same bits), x += alpha p, r -= alpha q,
+//           partials of r.z and r.r (z = D^{-1} r);
+//   dir     beta = r.z / rz_old; stop if r.r <= tol^2 b.b; p = z + beta p.
+// The two rz of consecutive iterations alternate between two slots, so the work-group that
+// stores the new one never overwrites the value the others still read.  Dot products are
+// accumulated in FP64 whatever the vector type.  Work-group b runs on XCD b mod 8; the tiles
+// of one direction are all given to one XCD, so the neighbour rows their SpMV gathers are in
+// that XCD's L2.
+#include <climits>
+
+#include "ops.h"
+
+namespace rte {
+namespace {
+
+constexpr int CTB = 256;                 // threads (rows) per work-group: 4 slices of 64
+
+__device__ __forceinline__ bool cg_tile(int ntiles, int nS, int& k, int& t) {
+    const int b = blockIdx.x;
+    const int xcd = b & 7, local = b >> 3;
+    k = xcd + 8 * (local / ntiles);
+    t = local % ntiles;
+    return k < nS;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// sum over the work-group in a fixed order; the result is returned to every thread
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+// sum of n partials in a fixed order (lane l takes l, l + 64, ...; then a fixed butterfly),
+// computed by every thread of the work-group, identical bits in every work-group
+__device__ __forceinline__ double partial_sum(const double* __restrict__ part, int n, double* sh) {
+    double v = 0.0;
+    if (threadIdx.x < 64)
+        for (int i = threadIdx.x; i < n; i += 64) v += part[i];
+    if (threadIdx.x < 64) v = wave_sum(v);
+    __syncthreads();
+    if (threadIdx.x == 0) sh[4] = v;
+    __syncthreads();
+    const double r = sh[4];
+    __syncthreads();
+    return r;
+}
+
+// explicit values of every direction's block in the sliced ELL layout:
+// val[k * len + q] = sum_c coef[k, c] cls[c, e(q)] (0 on padding), dinv = 1 / diag
+template <typename T>
+__global__ void cg_fill_kernel(int nS, size_t len, int nnz, int ncls, const int* __restrict__ ell_e,
+                               const double* __restrict__ cls, const double* __restrict__ coef,
+                               T* __restrict__ val) {
+    const size_t total = len * nS;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(q / len);
+        const int e = ell_e[q % len];
+        double v = 0.0;
+        if (e >= 0)
+            for (int c = 0; c < ncls; ++c) v = fma(coef[(size_t)k * ncls + c], cls[(size_t)c * nnz + e], v);
+        val[q] = (T)v;
+    }
+}
+
+template <typename T>
+__global__ void cg_dinv_kernel(size_t n, const double* __restrict__ diag, T* __restrict__ dinv) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dinv[i] = (T)(1.0 / diag[i]);
+}
+
+// x = 0, r = b, p = z = D^{-1} r; partials of b.b and r.z
+template <typename T>
+__global__ __launch_bounds__(CTB) void cg_init_kernel(int n, int nS, int ntiles, const double* __restrict__ B,
+                                                      double* __restrict__ X, T* __restrict__ R, T* __restrict__ P,
+                                                      const T* __restrict__ dinv, double* __restrict__ part) {
+    __shared__ double sh[8];
+    int k, t;
+    if (!cg_tile(ntiles, nS, k, t)) return;
+    const int i = t * CTB + threadIdx.x;
+    double bb = 0.0, rz = 0.0;
+    if (i < n) {
+        const size_t o = (size_t)n * k + i;
+        const double b = B[o];
+        X[o] = 0.0;
+        const T r = (T)b;
+        const T z = r * dinv[o];
+        R[o] = r;
+        P[o] = z;
+        bb = b * b;
+        rz = (double)r * (double)z;
+    }
+    bb = block_sum(bb, sh);
+    rz = block_sum(rz, sh);
+    if (threadIdx.x == 0) {
+        part[(size_t)k * ntiles + t] = bb;
+        part[(size_t)(nS + k) * ntiles + t] = rz;
+    }
+}
+
+// per direction: rz_0, the stopping threshold tol^2 b.b and the state (converged at
+// iteration done[k]; INT_MAX while running, -1 for a zero right-hand side)
+__global__ __launch_bounds__(CTB) void cg_setup_kernel(int nS, int ntiles, const double* __restrict__ part, double tol,
+                                                       double* __restrict__ rz, double* __restrict__ stop,
+                                                       int* __restrict__ done, int* __restrict__ iters) {
+    __shared__ double sh[8];
+    const int k = blockIdx.x;
+    const double bb = partial_sum(part + (size_t)k * ntiles, ntiles, sh);
+    const double r0 = partial_sum(part + (size_t)(nS + k) * ntiles, ntiles, sh);
+    if (threadIdx.x == 0) {
+        rz[k] = r0;                      // slot 0 (iteration 0 reads slot 0)
+        stop[k] = tol * tol * bb;
+        done[k] = bb > 0.0 ? INT_MAX : -1;
+        iters[k] = 0;
+    }
+}
+
+// q = E_0 p on one row tile of one direction; partial p.q
+template <typename T>
+__global__ __launch_bounds__(CTB) void cg_spmv_kernel(int n, int nS, int ntiles, int nslice, int it,
+                                                      const int* __restrict__ sptr, const int* __restrict__ col,
+                                                      const T* __restrict__ val, size_t len,
+                                                      const T* __restrict__ P, T* __restrict__ Q,
+                                                      const int* __restrict__ done, double* __restrict__ part) {
+    __shared__ double sh[8];
+    int k, t;
+    if (!cg_tile(ntiles, nS, k, t)) return;
+    if (done && done[k] < it) return;
+    const int slice = t * (CTB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int i = slice * 64 + lane;
+    const T* pk = P + (size_t)n * k;
+    double pq = 0.0;
+    if (slice < nslice) {
+        const int g0 = sptr[slice], w = sptr[slice + 1] - g0;
+        const size_t base = (size_t)g0 * 64 + lane;
+        const T* vk = val + len * k + base;
+        const int* ck = col + base;
+        T acc = (T)0;
+        for (int j = 0; j < w; ++j) acc += vk[64 * j] * pk[ck[64 * j]];
+        if (i < n) {
+            Q[(size_t)n * k + i] = acc;
+            pq = (double)pk[i] * (double)acc;
+        }
+    }
+    pq = block_sum(pq, sh);
+    if (threadIdx.x == 0) part[(size_t)k * ntiles + t] = pq;
+}
+
+// alpha = rz / p.q; x += alpha p; r -= alpha q; partials of r.z and r.r
+template <typename T>
+__global__ __launch_bounds__(CTB) void cg_update_kernel(int n, int nS, int ntiles, int it, const T* __restrict__ P,
+                                                        const T* __restrict__ Q, T* __restrict__ R,
+                                                        double* __restrict__ X, const T* __restrict__ dinv,
+                                                        const double* __restrict__ rz, const int* __restrict__ done,
+                                                        const double* __restrict__ part_pq,
+                                                        double* __restrict__ part) {
+    __shared__ double sh[8];
+    int k, t;
+    if (!cg_tile(ntiles, nS, k, t)) return;
+    if (done[k] < it) return;
+    const double pq = partial_sum(part_pq + (size_t)k * ntiles, ntiles, sh);
+    const double a = pq != 0.0 ? rz[(size_t)(it & 1) * nS + k] / pq : 0.0;
+    const int i = t * CTB + threadIdx.x;
+    double rzn = 0.0, rr = 0.0;
+    if (i < n) {
+        const size_t o = (size_t)n * k + i;
+        const T p = P[o];
+        X[o] = fma(a, (double)p, X[o]);
+        const T r = R[o] - (T)a * Q[o];
+        R[o] = r;
+        const T z = r * dinv[o];
+        rzn = (double)r * (double)z;
+        rr = (double)r * (double)r;
+    }
+    rzn = block_sum(rzn, sh);
+    rr = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        part[(size_t)k * ntiles + t] = rzn;
+        part[(size_t)(nS + k) * ntiles + t] = rr;
+    }
+}
+
+// convergence test and p = z + beta p
+template <typename T>
+__global__ __launch_bounds__(CTB) void cg_dir_kernel(int n, int nS, int ntiles, int it, T* __restrict__ P,
+                                                     const T* __restrict__ R, const T* __restrict__ dinv,
+                                                     double* __restrict__ rz, const double* __restrict__ stop,
+                                                     int* __restrict__ done, int* __restrict__ iters,
+                                                     const double* __restrict__ part) {
+    __shared__ double sh[8];
+    int k, t;
+    if (!cg_tile(ntiles, nS, k, t)) return;
+    if (done[k] < it) return;
+    const double rzn = partial_sum(part + (size_t)k * ntiles, ntiles, sh);
+    const double rr = partial_sum(part + (size_t)(nS + k) * ntiles, ntiles, sh);
+    if (rr <= stop[k]) {
+        if (t == 0 && threadIdx.x == 0) {
+            done[k] = it;
+            iters[k] = it + 1;
+        }
+        return;
+    }
+    const double rzo = rz[(size_t)(it & 1) * nS + k];
+    const double b = rzo != 0.0 ? rzn / rzo : 0.0;
+    const int i = t * CTB + threadIdx.x;
+    if (i < n) {
+        const size_t o = (size_t)n * k + i;
+        P[o] = R[o] * dinv[o] + (T)b * P[o];
+    }
+    if (t == 0 && threadIdx.x == 0) rz[(size_t)((it + 1) & 1) * nS + k] = rzn;
+}
+
+// number of directions still iterating; the directions that ran out of iterations get maxit
+__global__ __launch_bounds__(CTB) void cg_count_kernel(int nS, int maxit, int final_pass, int* __restrict__ done,
+                                                       int* __restrict__ iters, int* __restrict__ active) {
+    __shared__ double sh[8];
+    double c = 0.0;
+    for (int k = threadIdx.x; k < nS; k += CTB) {
+        const bool run = done[k] == INT_MAX;
+        c += run ? 1.0 : 0.0;
+        if (final_pass && run) iters[k] = maxit;
+    }
+    c = block_sum(c, sh);
+    if (threadIdx.x == 0) *active = (int)c;
+}
+
+inline int grid_of(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 65536); }
+
+}  // namespace
+
+namespace k {
+
+void cg_fill_values(const Handle* h, const int* ell_e, size_t len, double* val, hipStream_t s) {
+    hipLaunchKernelGGL(cg_fill_kernel<double>, dim3(grid_of(len * h->nS)), dim3(256), 0, s, h->nS, len, h->nnz, h->ncls,
+                       ell_e, h->cls.p, h->coefE0.p, val);
+    RTE_CHECK_LAUNCH();
+}
+void cg_fill_values(const Handle* h, const int* ell_e, size_t len, float* val, hipStream_t s) {
+    hipLaunchKernelGGL(cg_fill_kernel<float>, dim3(grid_of(len * h->nS)), dim3(256), 0, s, h->nS, len, h->nnz, h->ncls,
+                       ell_e, h->cls.p, h->coefE0.p, val);
+    RTE_CHECK_LAUNCH();
+}
+void cg_fill_dinv(const double* diag, size_t n, double* dinv, hipStream_t s) {
+    hipLaunchKernelGGL(cg_dinv_kernel<double>, dim3(grid_of(n)), dim3(256), 0, s, n, diag, dinv);
+    RTE_CHECK_LAUNCH();
+}
+void cg_fill_dinv(const double* diag, size_t n, float* dinv, hipStream_t s) {
+    hipLaunchKernelGGL(cg_dinv_kernel<float>, dim3(grid_of(n)), dim3(256), 0, s, n, diag, dinv);
+    RTE_CHECK_LAUNCH();
+}
+
+template <typename T>
+void cg_solve_t(const CgArgs& a, const T* val, const T* dinv, T* R, T* P, T* Q, hipStream_t s) {
+    const int n = a.n, nS = a.nS;
+    const int ntiles = (n + CTB - 1) / CTB;
+    const unsigned grid = (unsigned)ntiles * 8u * (unsigned)((nS + 7) / 8);
+    double* part_a = a.part;                              // [2 nS ntiles]
+    double* part_b = a.part + (size_t)2 * nS * ntiles;    // [2 nS ntiles]
+    hipLaunchKernelGGL(cg_init_kernel<T>, dim3(grid), dim3(CTB), 0, s, n, nS, ntiles, a.B, a.X, R, P, dinv, part_a);
+    RTE_CHECK_LAUNCH();
+    hipLaunchKernelGGL(cg_setup_kernel, dim3(nS), dim3(CTB), 0, s, nS, ntiles, part_a, a.tol, a.rz, a.stop, a.done,
+                       a.iters);
+    RTE_CHECK_LAUNCH();
+    for (int it = 0; it < a.maxit; ++it) {
+        hipLaunchKernelGGL(cg_spmv_kernel<T>, dim3(grid), dim3(CTB), 0, s, n, nS, ntiles, a.nslice, it, a.sptr, a.col,
+                           val, a.len, (const T*)P, Q, a.done, part_a);
+        RTE_CHECK_LAUNCH();
+        hipLaunchKernelGGL(cg_update_kernel<T>, dim3(grid), dim3(CTB), 0, s, n, nS, ntiles, it, (const T*)P,
+                           (const T*)Q, R, a.X, dinv, (const double*)a.rz, (const int*)a.done, (const double*)part_a,
+                           part_b);
+        RTE_CHECK_LAUNCH();
+        hipLaunchKernelGGL(cg_dir_kernel<T>, dim3(grid), dim3(CTB), 0, s, n, nS, ntiles, it, P, (const T*)R, dinv,
+                           a.rz, (const double*)a.stop, a.done, a.iters, (const double*)part_b);
+        RTE_CHECK_LAUNCH();
+        const bool last = it + 1 == a.maxit;
+        if ((it + 1) % a.check_every == 0 || last) {
+            hipLaunchKernelGGL(cg_count_kernel, dim3(1), dim3(CTB), 0, s, nS, a.maxit, last ? 1 : 0, a.done, a.iters,
+                               a.active);
+            RTE_CHECK_LAUNCH();
+            RTE_HIP(hipMemcpyAsync(a.host_active, a.active, sizeof(int), hipMemcpyDeviceToHost, s));
+            RTE_HIP(hipStreamSynchronize(s));
+            if (*a.host_active == 0) break;
+        }
+    }
+}
+
+void cg_solve(const CgArgs& a, const double* val, const double* dinv, double* R, double* P, double* Q, hipStream_t s) {
+    cg_solve_t<double>(a, val, dinv, R, P, Q, s);
+}
+void cg_solve(const CgArgs& a, const float* val, const float* dinv, float* R, float* P, float* Q, hipStream_t s) {
+    cg_solve_t<float>(a, val, dinv, R, P, Q, s);
+}
+
+void cg_spmv(const CgArgs& a, const double* val, const double* X, double* Y, hipStream_t s) {
+    const int ntiles = (a.n + CTB - 1) / CTB;
+    const unsigned grid = (unsigned)ntiles * 8u * (unsigned)((a.nS + 7) / 8);
+    hipLaunchKernelGGL(cg_spmv_kernel<double>, dim3(grid), dim3(CTB), 0, s, a.n, a.nS, ntiles, a.nslice, 0, a.sptr,
+                       a.col, val, a.len, X, Y, (const int*)nullptr, a.part);
+    RTE_CHECK_LAUNCH();
+}
+
+}  // namespace k
+}  // namespace rte

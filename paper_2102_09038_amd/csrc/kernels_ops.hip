@@ -569,115 +569,6 @@ __global__ __launch_bounds__(TPB) void richardson_update_kernel(int nRp, int nS,
     U[t] = v;
 }
 
-// ----------------------------------------------------------------------------- E_0
-// Jacobi-preconditioned CG, one 256-thread work-group per direction, all iterations in
-// one launch (no grid-wide synchronisation: directions are independent).  Vectors live
-// in global memory; the block values are formed on the fly from the shared pattern
-// classes and the direction's coefficients.
-__device__ __forceinline__ double e0_row(int i, const int* __restrict__ rowptr, const int* __restrict__ col,
-                                         const double* __restrict__ cls, int nnz, int ncls,
-                                         const double* cf, const double* __restrict__ xk) {
-    double acc = 0.0;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        double val = 0.0;
-        for (int c = 0; c < ncls; ++c) val = fma(cf[c], cls[(size_t)c * nnz + e], val);
-        acc = fma(val, xk[col[e]], acc);
-    }
-    return acc;
-}
-
-__global__ __launch_bounds__(TPB) void e0_cg_kernel(int nRp, int nnz, int ncls,
-                                                    const int* __restrict__ rowptr,
-                                                    const int* __restrict__ col,
-                                                    const double* __restrict__ cls,
-                                                    const double* __restrict__ coefE0,
-                                                    const double* __restrict__ diag,
-                                                    const double* __restrict__ B, double* __restrict__ X,
-                                                    double* __restrict__ R, double* __restrict__ P,
-                                                    double* __restrict__ Q, double tol, int maxit,
-                                                    int* __restrict__ iters) {
-    __shared__ double sh[4];
-    __shared__ double bc[3];
-    __shared__ double cf[kMaxClasses];
-    const int kk = blockIdx.x;
-    const size_t off = (size_t)nRp * kk;
-    const double* b = B + off;
-    double* x = X + off;
-    double* r = R + off;
-    double* p = P + off;
-    double* q = Q + off;
-    const double* dg = diag + off;
-    if (threadIdx.x < ncls) cf[threadIdx.x] = coefE0[(size_t)kk * ncls + threadIdx.x];
-    double bb = 0.0, rz = 0.0;
-    for (int i = threadIdx.x; i < nRp; i += TPB) {
-        const double bi = b[i];
-        x[i] = 0.0;
-        r[i] = bi;
-        const double zi = bi / dg[i];
-        p[i] = zi;
-        bb = fma(bi, bi, bb);
-        rz = fma(bi, zi, rz);
-    }
-    bb = block_sum(bb, sh);
-    rz = block_sum(rz, sh);
-    if (threadIdx.x == 0) { bc[0] = bb; bc[1] = rz; }
-    __syncthreads();
-    bb = bc[0];
-    rz = bc[1];
-    __syncthreads();
-    int it = 0;
-    const double stop = tol * tol * bb;
-    if (bb > 0.0) {
-        while (it < maxit) {
-            double pq = 0.0;
-            for (int i = threadIdx.x; i < nRp; i += TPB) {
-                const double qi = e0_row(i, rowptr, col, cls, nnz, ncls, cf, p);
-                q[i] = qi;
-                pq = fma(p[i], qi, pq);
-            }
-            pq = block_sum(pq, sh);
-            if (threadIdx.x == 0) bc[0] = pq;
-            __syncthreads();
-            const double alpha = rz / bc[0];
-            double rzn = 0.0, rr = 0.0;
-            for (int i = threadIdx.x; i < nRp; i += TPB) {
-                x[i] = fma(alpha, p[i], x[i]);
-                const double ri = fma(-alpha, q[i], r[i]);
-                r[i] = ri;
-                rzn = fma(ri, ri / dg[i], rzn);
-                rr = fma(ri, ri, rr);
-            }
-            rzn = block_sum(rzn, sh);
-            rr = block_sum(rr, sh);
-            if (threadIdx.x == 0) { bc[1] = rzn; bc[2] = rr; }
-            __syncthreads();
-            rzn = bc[1];
-            rr = bc[2];
-            ++it;
-            if (rr <= stop) break;
-            const double beta = rzn / rz;
-            rz = rzn;
-            for (int i = threadIdx.x; i < nRp; i += TPB) p[i] = fma(beta, p[i], r[i] / dg[i]);
-            __syncthreads();
-        }
-    } else {
-        for (int i = threadIdx.x; i < nRp; i += TPB) x[i] = 0.0;
-    }
-    if (threadIdx.x == 0) iters[kk] = it;
-}
-
-__global__ __launch_bounds__(TPB) void e0_apply_kernel(int nRp, int nS, int nnz, int ncls,
-                                                       const int* __restrict__ rowptr,
-                                                       const int* __restrict__ col,
-                                                       const double* __restrict__ cls,
-                                                       const double* __restrict__ coefE0,
-                                                       const double* __restrict__ X, double* __restrict__ Y) {
-    const size_t t = blockIdx.x * (size_t)TPB + threadIdx.x;
-    if (t >= (size_t)nRp * nS) return;
-    const int i = (int)(t % nRp), kk = (int)(t / nRp);
-    Y[t] = e0_row(i, rowptr, col, cls, nnz, ncls, coefE0 + (size_t)kk * ncls, X + (size_t)nRp * kk);
-}
-
 // compile-time dispatch over the eigen-basis sizes d_N = (N+1)(N+2)/2, N = 0..8
 template <template <int> class F, typename... Args>
 void dispatch_dn(int dn, Args&&... args) {
@@ -860,20 +751,6 @@ void coarse_project(const Handle* h, const double* T, double* rhs, hipStream_t s
 
 void richardson_update(const Handle* h, double* U, const double* S, const double* uc, hipStream_t s) {
     dispatch_dn<RichUpdateL>(h->dNp, h, U, S, uc, s);
-    RTE_CHECK_LAUNCH();
-}
-
-void e0_cg(const Handle* h, const double* B, double* X, double* r, double* p, double* q, double tol,
-           int maxit, int* iters, hipStream_t s) {
-    hipLaunchKernelGGL(e0_cg_kernel, dim3(h->nS), dim3(TPB), 0, s, h->nRp, h->nnz, h->ncls, h->rowptr.p,
-                       h->col.p, h->cls.p, h->coefE0.p, h->diagE0.p, B, X, r, p, q, tol, maxit, iters);
-    RTE_CHECK_LAUNCH();
-}
-
-void e0_apply(const Handle* h, const double* X, double* Y, hipStream_t s) {
-    const size_t n = (size_t)h->nRp * h->nS;
-    hipLaunchKernelGGL(e0_apply_kernel, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, h->nRp,
-                       h->nS, h->nnz, h->ncls, h->rowptr.p, h->col.p, h->cls.p, h->coefE0.p, X, Y);
     RTE_CHECK_LAUNCH();
 }
 

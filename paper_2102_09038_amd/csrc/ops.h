@@ -174,12 +174,35 @@ void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, 
 void richardson_update(const Handle* h, double* U, const double* S, const double* uc,
                        hipStream_t s);
 
-// ---- E_0 (Sec. 5.3)
-// X = E_0^{-1} B by Jacobi-preconditioned CG per direction; iters[k] <- count
-void e0_cg(const Handle* h, const double* B, double* X, double* r, double* p, double* q,
-           double tol, int maxit, int* iters, hipStream_t s);
-// Y = E_0 X (all directions)
-void e0_apply(const Handle* h, const double* X, double* Y, hipStream_t s);
+// ---- E_0 by CG over a sliced-ELL layout (kernels_cg.hip, Sec. 5.3)
+struct CgArgs {
+    int n = 0, nS = 0, nslice = 0;   // rows per block, directions, slices of 64 rows
+    size_t len = 0;                  // ELL entries per direction (64 per slot of every slice)
+    const int* sptr = nullptr;       // [nslice + 1] first slot group of each slice
+    const int* col = nullptr;        // [len] column of every entry (shared by the directions)
+    const double* B = nullptr;       // right-hand sides, n x nS column-major
+    double* X = nullptr;             // solutions (FP64 whatever the vector type)
+    double tol = 1e-10;              // stop direction k once ||r_k|| <= tol ||b_k||
+    int maxit = 1000, check_every = 16;   // host reads the live count every check_every iterations
+    double* part = nullptr;          // [4 nS ntiles] per-tile partial sums
+    double* rz = nullptr;            // [2 nS] r.z of consecutive iterations
+    double* stop = nullptr;          // [nS] tol^2 b.b
+    int* done = nullptr;             // [nS] iteration of convergence (INT_MAX while running)
+    int* iters = nullptr;            // [nS] iterations taken
+    int* active = nullptr;           // [1] directions still running
+    int* host_active = nullptr;      // pinned host copy of *active
+};
+// val[k len + q] = explicit value of entry q of block k from the pattern classes; dinv = 1/diag
+void cg_fill_values(const Handle* h, const int* ell_e, size_t len, double* val, hipStream_t s);
+void cg_fill_values(const Handle* h, const int* ell_e, size_t len, float* val, hipStream_t s);
+void cg_fill_dinv(const double* diag, size_t n, double* dinv, hipStream_t s);
+void cg_fill_dinv(const double* diag, size_t n, float* dinv, hipStream_t s);
+// X = E_0^{-1} B, Jacobi-preconditioned CG on every direction block at once (vectors R, P, Q
+// of the value type, n x nS); blocking (reads the live count every check_every iterations)
+void cg_solve(const CgArgs& a, const double* val, const double* dinv, double* R, double* P, double* Q, hipStream_t s);
+void cg_solve(const CgArgs& a, const float* val, const float* dinv, float* R, float* P, float* Q, hipStream_t s);
+// Y = E_0 X on every direction (FP64), the CG's own SpMV kernel
+void cg_spmv(const CgArgs& a, const double* val, const double* X, double* Y, hipStream_t s);
 
 }  // namespace k
 }  // namespace rte

@@ -147,6 +147,17 @@ struct Handle {
     DBuf<double> coefE;            // [nS*ncls] (M+ + R) block k = sum_c coefE[k,c] cls_c
     DBuf<double> diagE0;           // [nRp*nS] diagonal of every E_0 block (Jacobi)
     DBuf<int> vc_ptr, vc_cell, vc_loc;   // vertex -> incident cells (for A^T)
+    // E_0 by CG (kernels_cg.hip): the pattern in sliced ELL form (slices of 64 rows, as many
+    // slots as the slice's longest row), its entries' positions in the CSR pattern (-1 on
+    // padding), and the explicit values of every direction's block with the inverse diagonal,
+    // in FP64 and (mixed) FP32, built at assembly for e0_solver = RTE_E0_CG, else on first use
+    int ell_nslice = 0;
+    size_t ell_len = 0;
+    DBuf<int> ell_sptr, ell_col, ell_e;
+    DBuf<double> ell_v64, ell_dinv64;
+    DBuf<float> ell_v32, ell_dinv32;
+    DBuf<double> cg_part, cg_scal;   // per-tile partials [4 nS ntiles]; rz [2 nS] and stop [nS]
+    DBuf<int> cg_state;             // done [nS], active [1]
     DBuf<double> q;                // [nRp*nS] even load l+
     double qnorm = 0;
 

@@ -27,6 +27,30 @@ double* ws(Handle* h, int id) {
     return b.p;
 }
 
+void cg_prepare(Handle* h, bool f32, hipStream_t s) {
+    const size_t even = (size_t)h->nRp * h->nS;
+    if (f32 ? !h->ell_v32.p : !h->ell_v64.p) {
+        if (f32) {
+            h->ell_v32.alloc(h->ell_len * h->nS);
+            h->ell_dinv32.alloc(even);
+            k::cg_fill_values(h, h->ell_e.p, h->ell_len, h->ell_v32.p, s);
+            k::cg_fill_dinv(h->diagE0.p, even, h->ell_dinv32.p, s);
+        } else {
+            h->ell_v64.alloc(h->ell_len * h->nS);
+            h->ell_dinv64.alloc(even);
+            k::cg_fill_values(h, h->ell_e.p, h->ell_len, h->ell_v64.p, s);
+            k::cg_fill_dinv(h->diagE0.p, even, h->ell_dinv64.p, s);
+        }
+    }
+    const size_t ntiles = ((size_t)h->nRp + 255) / 256;
+    if (!h->cg_part.p) {
+        h->cg_part.alloc(4 * (size_t)h->nS * ntiles);
+        h->cg_scal.alloc(3 * (size_t)h->nS);
+        h->cg_state.alloc((size_t)h->nS + 1);
+    }
+    if (h->cg_iters.n < (size_t)h->nS) h->cg_iters.alloc(h->nS);
+}
+
 // ----------------------------------------------------------------------------- timers
 enum ProfKind { P_E0 = 0, P_GEMM = 1, P_GEMM_BF16 = 2, P_GEMM_SCATTER = 3, P_GEMM_SCATTER_F32 = 4 };
 
@@ -180,7 +204,9 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
             float* Zf = reinterpret_cast<float*>(Z);
             k::apply_grad_bf16(h, X, Ycb, s);
             {
-                Timed t(h, s, P_GEMM_BF16, 2.0 * h->nRm * (double)dn * (2.0 * dn));
+                // the method's flops, 2 n_R- (d n_S+)^2: the hi/lo operator pair doubles the
+                // GEMM's K but not the contraction the method asks for
+                Timed t(h, s, P_GEMM_BF16, 2.0 * h->nRm * (double)dn * dn);
                 // Z^T = [G_hi | G_lo] [Y | Y]^T: Z comes out row-major (cell-major, directions contiguous)
                 k::gemm_bf16(dn, h->nRm, 2 * dn, 1.0f, h->Gc_bf.p, 2 * dn, Ycb, 2 * dn, 0.0f, Zf, dn, s);
             }
@@ -249,14 +275,40 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
         k::permute_cols(h->iperm.p, h->nRp, h->nS, Yb, Y, false, s);
         return;
     }
+    // CG on every direction block at once (kernels_cg.hip); in mixed precision its vectors and
+    // block values are FP32 (dot products FP64) and it stops at a relative residual of
+    // max(cg_tol, 1e-6), the FP32 floor of a preconditioner solve
+    const bool f32 = lowp;
+    cg_prepare(h, f32, s);
     double* r = ws(h, W_CGR);
     double* p = ws(h, W_CGP);
     double* q = ws(h, W_CGQ);
     DBuf<int>& iters = h->cg_iters;
-    if (iters.n < (size_t)h->nS) iters.alloc(h->nS);
+    k::CgArgs a;
+    a.n = h->nRp;
+    a.nS = h->nS;
+    a.nslice = h->ell_nslice;
+    a.len = h->ell_len;
+    a.sptr = h->ell_sptr.p;
+    a.col = h->ell_col.p;
+    a.B = X;
+    a.X = Y;
+    a.tol = f32 ? std::max(o->cg_tol, 1e-6) : o->cg_tol;
+    a.maxit = o->cg_max_iter;
+    a.part = h->cg_part.p;
+    a.rz = h->cg_scal.p;
+    a.stop = h->cg_scal.p + 2 * (size_t)h->nS;
+    a.done = h->cg_state.p;
+    a.active = h->cg_state.p + h->nS;
+    a.iters = iters.p;
+    a.host_active = reinterpret_cast<int*>(h->pinned + 32);
     {
         Timed t(h, s, P_E0);
-        k::e0_cg(h, X, Y, r, p, q, o->cg_tol, o->cg_max_iter, iters.p, s);
+        if (f32)
+            k::cg_solve(a, h->ell_v32.p, h->ell_dinv32.p, reinterpret_cast<float*>(r), reinterpret_cast<float*>(p),
+                        reinterpret_cast<float*>(q), s);
+        else
+            k::cg_solve(a, h->ell_v64.p, h->ell_dinv64.p, r, p, q, s);
     }
     if (cgt || cgmax) {
         std::vector<int> hi(h->nS);

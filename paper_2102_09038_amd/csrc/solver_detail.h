@@ -29,6 +29,8 @@ enum WsId {
 };
 
 double* ws(Handle* h, int id);
+// the explicit E_0 block values and inverse diagonals of the CG solve, FP64 or FP32 (built once)
+void cg_prepare(Handle* h, bool f32, hipStream_t s);
 // Y = E X [- q0] (q0 nullable), or with G = X S+ given: Y = (E - K+) X - q0  (Alg. 1)
 void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const double* G, const double* q0, double* Y,
                   double tol, hipStream_t s, int64_t* pcg, bool lowp);
