@@ -254,6 +254,22 @@ rte_status rte_estimate_footprint(const rte_problem_desc* desc, const rte_assemb
 rte_status rte_apply_scatter(rte_handle* h, int32_t parity, int32_t dtype_in, const void* X,
                              int32_t dtype_out, void* Y, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops or harnesses that forbid hipMalloc): Y = K+- X exactly as rte_apply_scatter computes
+ * it (same arguments, layouts and dtypes), calling no hipMalloc, hipFree or allocating
+ * library routine.  Its intermediates live in a fixed scratch array of 64 MiB that the
+ * library holds on every device it runs on until the process ends (its address is looked
+ * up by rte_assemble, or by the first call on a device): the GEMM product X S+ (parity +1,
+ * n_R+ n_S+ FP64 values) and an FP64 copy of the result when dtype_out is FP32 (n_R+- n_S+-
+ * values); the GEMM is not split over K.  RTE_E_ARG,
+ * before any device work, when those intermediates exceed 64 MiB: parity +1 needs
+ * n_R+ n_S+ * 8 bytes (twice that with an FP32 Y), parity -1 needs n_R- n_S- * 8 bytes with
+ * an FP32 Y and nothing with an FP64 Y.  All calls on one device share its array: calls
+ * that overlap on one GPU (other streams, other threads) race, and the caller must order
+ * them.  Enqueue only. */
+rte_status rte_apply_scatter_noalloc(rte_handle* h, int32_t parity, int32_t dtype_in, const void* X,
+                                     int32_t dtype_out, void* Y, void* hip_stream);
+
 /* Y = E X = A^T (M- - K-)^{-1} A X + M+ X + R X (Sec. 4; Alg. 1).  X, Y device FP64
  * n_R+ x n_S+.  The odd solve follows opts->odd_solver with tolerance
  * opts->pcg_tol_resid.  With opts->precision == RTE_MIXED and the condensed odd solver

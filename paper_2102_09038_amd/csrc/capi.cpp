@@ -84,6 +84,14 @@ rte_status rte_assemble(const rte_problem_desc* desc, const rte_assemble_opts* o
         if (!out) rte::fail(RTE_E_ARG, "null output handle pointer");
         *out = nullptr;
         rte::Handle* h = rte::assemble(desc, opts, as_stream(hip_stream));
+        // set-up of this device for rte_apply_scatter_noalloc (the address of its scratch
+        // array), after validation and assembly so that invalid input still fails first
+        try {
+            rte::noalloc_setup();
+        } catch (...) {
+            delete h;
+            throw;
+        }
         *out = reinterpret_cast<rte_handle*>(h);
         return RTE_OK;
     });
@@ -126,6 +134,17 @@ rte_status rte_apply_scatter(rte_handle* hh, int32_t parity, int32_t dtype_in, c
         if (!X || !Y) rte::fail(RTE_E_ARG, "null operand");
         if (parity != 1 && parity != -1) rte::fail(RTE_E_ARG, "parity must be +1 or -1");
         rte::apply_scatter(h, parity, dtype_in, X, dtype_out, Y, as_stream(hip_stream));
+        return RTE_OK;
+    });
+}
+
+rte_status rte_apply_scatter_noalloc(rte_handle* hh, int32_t parity, int32_t dtype_in, const void* X,
+                                     int32_t dtype_out, void* Y, void* hip_stream) {
+    return guarded([&] {
+        rte::Handle* h = as_handle(hh);
+        if (!X || !Y) rte::fail(RTE_E_ARG, "null operand");
+        if (parity != 1 && parity != -1) rte::fail(RTE_E_ARG, "parity must be +1 or -1");
+        rte::apply_scatter_noalloc(h, parity, dtype_in, X, dtype_out, Y, as_stream(hip_stream));
         return RTE_OK;
     });
 }

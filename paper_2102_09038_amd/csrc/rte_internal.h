@@ -231,6 +231,10 @@ int batch_step(Batch* B, int outer_iters, hipStream_t s);
 void batch_set_graphs(Batch* B, bool on);
 // band layout autotuning of the E_0 factors (autotune.cpp)
 void derived_outputs(Handle* h, const double* U, double* phi, double* balance, hipStream_t s);
+// scattering operator without device allocation (noalloc.hip): its intermediates live in a
+// fixed per-device array whose address noalloc_setup looks up on the current device
+void noalloc_setup();
+void apply_scatter_noalloc(Handle* h, int parity, int dtin, const void* X, int dtout, void* Y, hipStream_t s);
 void coarse_block_factor(Handle& h, const double* dband, int n, int bw, hipStream_t s);
 void coarse_block_solve(Handle* h, const double* rhs, double* x, hipStream_t s);
 void autotune(Handle* h, int flags, hipStream_t s, rte_tune_report* rep);

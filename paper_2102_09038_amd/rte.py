@@ -84,6 +84,8 @@ EXPORTS = {
     "rte_query_band": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int32)] * 3),
     "rte_apply_scatter": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                     C.c_void_p]),
+    "rte_apply_scatter_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                            C.c_void_p]),
     "rte_apply_E": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_apply_E0inv": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_precond": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_int32, C.c_void_p, C.c_void_p,
@@ -286,6 +288,10 @@ class Handle:
     def apply_scatter(self, parity, X, Y, dtype_in=RTE_DT_F64, dtype_out=RTE_DT_F64, stream=None):
         _check(lib.rte_apply_scatter(self.h, parity, dtype_in, C.c_void_p(X.data_ptr()), dtype_out,
                                      C.c_void_p(Y.data_ptr()), _stream(stream)))
+
+    def apply_scatter_noalloc(self, parity, X, Y, dtype_in=RTE_DT_F64, dtype_out=RTE_DT_F64, stream=None):
+        _check(lib.rte_apply_scatter_noalloc(self.h, parity, dtype_in, C.c_void_p(X.data_ptr()), dtype_out,
+                                             C.c_void_p(Y.data_ptr()), _stream(stream)))
 
     def apply_E(self, X, Y, opts=None, stream=None):
         o = opts or default_solve_opts()
