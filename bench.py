@@ -101,6 +101,22 @@ def cpu_baseline(inst, iters, l, seed=0):
             "est_seconds_per_solve": t_solve, "est_setup_s": t_setup, "est_iter_s": t_iter}
 
 
+def ell_entries(inst):
+    """Entries per direction of the CG's sliced-ELL storage of the P1 pattern: every slice of 64
+    rows holds 64 entries per slot, as many slots as its longest row."""
+    import numpy as np
+    import scipy.sparse as sp
+    c = np.asarray(inst.cell)
+    nv, n = c.shape[1], len(inst.vert)
+    rows = np.repeat(c, nv, axis=1).ravel()
+    cols = np.tile(c, (1, nv)).ravel()
+    A = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, n))
+    A.sum_duplicates()
+    rl = np.diff(A.indptr)
+    rl = np.concatenate([rl, np.zeros((-n) % 64, dtype=rl.dtype)])
+    return int(rl.reshape(-1, 64).max(axis=1).sum() * 64)
+
+
 COPY_BYTES = 4 << 30
 ROOT = os.path.dirname(os.path.abspath(__file__))
 
@@ -140,6 +156,8 @@ def kernel_passes(h, inst, torch, rte):
         o = rte.default_solve_opts(e0_solver=rte.RTE_E0_BANDED, precision=prec)
         for _ in range(2):
             h.apply_E0inv(X, Y, o)
+    for _ in range(2):
+        h.apply_E0(X, Y)
     Xf = X.float()
     for _ in range(2):
         h.apply_scatter(1, X, Y)
@@ -151,33 +169,35 @@ def kernel_passes(h, inst, torch, rte):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"kernel_passes": ["apply_E condensed fp64 x2", "apply_E condensed mixed x2",
-                                        "E0inv banded fp64 x2", "E0inv banded fp32 x2", "K+ fp64 x2", "K+ fp32 x2",
+                                        "E0inv banded fp64 x2", "E0inv banded fp32 x2", "E0 SpMV fp64 x2",
+                                        "K+ fp64 x2", "K+ fp32 x2",
                                         f"device copy {COPY_BYTES} bytes x2"]}))
 
 
-def batch_bench(args, torch, rte, inputs):
+def batched_form(torch, rte, inputs, count, tol, log, with_server=True, graph_modes=(False,)):
     """The batched form: count seeded instances of uneven size (N ~ U{32..128}, 128/512/2048
     sphere triangles, g ~ U[0,0.95], ratio ~ U[0.5,0.999]).
     - Baseline: the plain FP64 GPU solve, one instance at a time (assembled, solved and
-      released in turn; only the solves are timed).
-    - Batched: every instance assembled in mixed-only form, then solved in one lockstep batch
-      in mixed precision, with admission bounded by a device-memory budget; timed from the
-      first admission to the last completion.
-    Both run to the same relative residual.  The error of each mixed result is taken
-    against the instance's FP64 result."""
+      released in turn; solve and assembly timed separately).
+    - Lockstep: every instance that fits the device-memory budget assembled beforehand in
+      mixed-only form, all admitted at once and stepped to completion in mixed precision; its
+      rate is compared with the FP64 rate over the same instances (like for like).
+    - Server (with_server): all instances arrive at once; the continuous-batching loop
+      assembles them on worker threads within the budget and steps them (end to end).
+    All stop at the same FP64 relative residual tol.  Every result's error is taken against a
+    tight FP64 reference solve of its instance (relative residual 1e-11), for the FP64 and the
+    mixed results alike, and against the FP64 result at tol."""
     import numpy as np
-
-    def log(msg):
-        print(msg, file=sys.stderr, flush=True)
 
     from paper_2102_09038_amd import serve
 
-    insts = inputs.instance_distribution(count=args.count, seed=3, tol=args.tol)
-    base = dict(l=4, tol=args.tol, max_iter=2000, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_BANDED)
-    o64 = rte.default_solve_opts(precision=rte.RTE_FP64, **base)
-    omx = rte.default_solve_opts(precision=rte.RTE_MIXED, **base)
-    # ---- baseline: plain FP64, one instance at a time
-    ref, t64, it64, asm64, res64 = [], 0.0, [], [], []
+    insts = inputs.instance_distribution(count=count, seed=3, tol=tol)
+    base = dict(l=4, max_iter=2000, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_BANDED)
+    o64 = rte.default_solve_opts(precision=rte.RTE_FP64, tol=tol, **base)
+    otight = rte.default_solve_opts(precision=rte.RTE_FP64, tol=1e-11, **base)
+    omx = rte.default_solve_opts(precision=rte.RTE_MIXED, tol=tol, **base)
+    # ---- baseline: plain FP64, one instance at a time; then an untimed tight reference solve
+    ref, tight, t64, it64, asm64, res64 = [], [], [], [], [], []
     for i, inst in enumerate(insts):
         ta = time.perf_counter()
         h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0,
@@ -188,38 +208,38 @@ def batch_bench(args, torch, rte, inputs):
         t0 = time.perf_counter()
         st, info = h.solve(U, opts=o64, raise_on_notconv=False)
         torch.cuda.synchronize()
-        t64 += time.perf_counter() - t0
+        t64.append(time.perf_counter() - t0)
         it64.append(info.iters)
         res64.append(info.rel_resid)
         ref.append(U.cpu())
+        h.solve(U, opts=otight, raise_on_notconv=False)
+        tight.append(U.cpu())
         h.close()
         del U
-        log(f"[fp64 {i + 1}/{len(insts)}] {inst.name}: {info.iters} iters, {1e3 * info.t_solve:.0f} ms, "
+        log(f"[fp64 {i + 1}/{len(insts)}] {inst.name}: {info.iters} iters, {1e3 * t64[-1]:.0f} ms, "
             f"assembly {asm64[-1]:.2f} s")
-    # ---- batched mixed form: every instance arrives at once; the server assembles within the
-    #      device-memory budget and runs all admitted solves in one lockstep batch
+
+    def err(U, i, against):
+        R = against[i]
+        return float(torch.linalg.norm(U - R) / torch.linalg.norm(R))
+
+    err64_tight = [err(ref[i], i, tight) for i in range(len(insts))]
     budget = int(240e9)
-    reqs = [serve.Request(rid=i, inst=inst, arrival=0.0) for i, inst in enumerate(insts)]
-    srv = serve.Server(budget, omx, max_slots=len(insts), workers=4, keep_results=True)
-    t0 = time.perf_counter()
-    done = srv.run(reqs)
-    wall = time.perf_counter() - t0
-    srv.close()
-    errs = [float(torch.linalg.norm(r.U.cpu() - ref[r.rid]) / torch.linalg.norm(ref[r.rid])) for r in done]
-    log(f"[batch] {len(done)} solved in {wall:.1f} s ({srv.t_step:.1f} s stepping), peak {srv.peak_live} live slots")
-    # ---- the lockstep stepping alone: every instance assembled beforehand (mixed-only form),
-    #      all admitted at once, stepped to completion with and without the captured graphs;
-    #      instances are taken in order while their handles fit the budget together
-    hs, held = [], 0
-    for inst in insts:
-        b_est, p_est = rte.estimate_footprint(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0)
+    # ---- lockstep stepping of pre-assembled instances (mixed-only form), in order while their
+    #      handles fit the budget together
+    hs, sub, held = [], [], 0
+    for i, inst in enumerate(insts):
+        b_est, p_est = rte.estimate_footprint(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0,
+                                              coarse_solver=rte.RTE_COARSE_QUICK)
         if held + max(b_est, p_est) > budget:
             continue
         hs.append(rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0,
-                                              coarse_solver=rte.RTE_COARSE_QUICK))
+                                           coarse_solver=rte.RTE_COARSE_QUICK))
+        sub.append(i)
         held += b_est
+    t64_sub = sum(t64[i] for i in sub)
     lockstep = {}
-    for graphs in (True, False):
+    for graphs in graph_modes:
         b = rte.Batch(max_slots=len(hs), use_graphs=graphs)
         Us = [torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda") for h in hs]
         for h, U in zip(hs, Us):
@@ -231,44 +251,75 @@ def batch_bench(args, torch, rte, inputs):
         dt = time.perf_counter() - t0
         res = b.poll()
         assert left == 0 and len(res) == len(hs)
+        by_slot = {slot: info for slot, _, info in res}
+        e_tight = [err(Us[j].cpu(), i, tight) for j, i in enumerate(sub)]
+        e_64 = [err(Us[j].cpu(), i, ref) for j, i in enumerate(sub)]
         lockstep["graphs" if graphs else "direct"] = {
             "instances": len(hs), "solves_per_s": len(hs) / dt, "step_s": dt,
-            "lockstep_iters": max(i.iters for _, _, i in res)}
-        log(f"[lockstep graphs={graphs}] {len(hs)} solves in {dt:.2f} s")
+            "fp64_same_instances_solves_per_s": len(hs) / t64_sub,
+            "speedup_vs_fp64_same_instances": t64_sub / dt,
+            "lockstep_iters": max(i.iters for i in by_slot.values()),
+            "max_rel_resid": max(i.rel_resid for i in by_slot.values()),
+            "rel_err_vs_tight_reference": {"max": max(e_tight), "median": float(np.median(e_tight))},
+            "rel_err_vs_fp64_result": {"max": max(e_64), "median": float(np.median(e_64))}}
+        log(f"[lockstep graphs={graphs}] {len(hs)} solves in {dt:.2f} s (FP64 one at a time: {t64_sub:.2f} s)")
         b.close()
         del Us
     for h in hs:
         h.close()
     out = {
         "workload": f"batched form: {len(insts)} seeded instances (N 32..128, 128/512/2048 sphere triangles, "
-                    f"g 0..0.95, ratio 0.5..0.999), rel. residual {args.tol:g}",
-        "fp64_one_at_a_time": {"solves_per_s": len(insts) / t64, "solve_s": t64, "assembly_s": sum(asm64),
-                               "end_to_end_solves_per_s": len(insts) / (t64 + sum(asm64)),
-                               "iters_total": int(sum(it64))},
-        "mixed_batched": {"solves_per_s": len(insts) / srv.t_step, "step_s": srv.t_step, "wall_s": wall,
-                          "end_to_end_solves_per_s": len(insts) / wall,
-                          "iters_total": int(sum(r.iters for r in done)),
-                          "all_converged": all(r.status == rte.RTE_OK for r in done),
-                          "peak_live_slots": srv.peak_live, "hbm_budget": budget, "assembly_workers": 4},
+                    f"g 0..0.95, ratio 0.5..0.999), rel. residual {tol:g}",
+        "fp64_one_at_a_time": {"solves_per_s": len(insts) / sum(t64), "solve_s": sum(t64),
+                               "assembly_s": sum(asm64),
+                               "end_to_end_solves_per_s": len(insts) / (sum(t64) + sum(asm64)),
+                               "iters_total": int(sum(it64)), "max_rel_resid": max(res64),
+                               "rel_err_vs_tight_reference": {"max": max(err64_tight),
+                                                              "median": float(np.median(err64_tight))}},
         "mixed_lockstep_preassembled": lockstep,
-        # solve-only rates: the lockstep stepping of pre-assembled instances against the FP64
-        # solves one at a time (assembly excluded from both)
-        "speedup_solve": max(v["solves_per_s"] for v in lockstep.values()) / (len(insts) / t64), "speedup_end_to_end": (t64 + sum(asm64)) / wall,
-        # both forms stop at the same FP64 relative residual; their solutions then differ by up
-        # to about (condition number) x tol, most for instances whose iteration counts differ
-        "max_rel_err_vs_fp64": max(errs), "median_rel_err_vs_fp64": float(np.median(errs)),
-        "max_rel_resid": {"fp64": max(res64), "mixed": max(r.rel_resid for r in done)},
     }
-    print(json.dumps(out))
+    if with_server:
+        reqs = [serve.Request(rid=i, inst=inst, arrival=0.0) for i, inst in enumerate(insts)]
+        srv = serve.Server(budget, omx, max_slots=len(insts), workers=4, keep_results=True)
+        t0 = time.perf_counter()
+        done = srv.run(reqs)
+        wall = time.perf_counter() - t0
+        srv.close()
+        e_tight = [err(r.U.cpu(), r.rid, tight) for r in done]
+        e_64 = [err(r.U.cpu(), r.rid, ref) for r in done]
+        log(f"[server] {len(done)} solved in {wall:.1f} s ({srv.t_step:.1f} s stepping), "
+            f"peak {srv.peak_live} live slots")
+        out["mixed_server"] = {
+            "solves_per_s_stepping": len(insts) / srv.t_step, "step_s": srv.t_step, "wall_s": wall,
+            "end_to_end_solves_per_s": len(insts) / wall,
+            "speedup_end_to_end_vs_fp64": (sum(t64) + sum(asm64)) / wall,
+            "speedup_stepping_vs_fp64_solves": sum(t64) / srv.t_step,
+            "iters_total": int(sum(r.iters for r in done)),
+            "all_converged": all(r.status == rte.RTE_OK for r in done),
+            "max_rel_resid": max(r.rel_resid for r in done),
+            "rel_err_vs_tight_reference": {"max": max(e_tight), "median": float(np.median(e_tight)),
+                                           "per_instance": [round(e, 12) for e in e_tight]},
+            "rel_err_vs_fp64_result": {"max": max(e_64), "median": float(np.median(e_64))},
+            "peak_live_slots": srv.peak_live, "hbm_budget": budget, "assembly_workers": 4}
+    return out
 
 
-def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None):
+def batch_bench(args, torch, rte, inputs):
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+    print(json.dumps(batched_form(torch, rte, inputs, args.count, args.tol, log, with_server=True,
+                                  graph_modes=(True, False))))
+
+
+def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None, errors=True):
     """The served form: Poisson arrivals (seed 4) of requests drawn like the batched form,
     served by the continuous-batching loop (mixed precision, assembly on worker threads,
     admission by predicted footprint) and, as the baseline, by plain FP64 solves one at a
     time in arrival order.  Latency = completion - arrival; the first warm-up requests of
     each run are not counted.  rates: list of requests/s or 'half' (half the capacity the
-    batched loop reached at the highest numeric rate)."""
+    batched loop reached at the highest numeric rate).  errors: every measured batched result
+    is compared, after the run, with a tight FP64 solve (relative residual 1e-11) of its
+    request."""
     import numpy as np
 
     from paper_2102_09038_amd import serve
@@ -293,14 +344,33 @@ def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None):
                 "all_converged": all(r.status == rte.RTE_OK for r in m),
                 "n_failed": sum(r.status not in (rte.RTE_OK, rte.RTE_E_NOTCONV) for r in m), "wall_s": t_wall}
 
+    otight = rte.default_solve_opts(precision=rte.RTE_FP64, **dict(base, tol=1e-11))
+
+    def errors_vs_tight(done):
+        """Each measured result against a tight FP64 solve of its request (untimed, after the run)."""
+        errs = []
+        for r in sorted(done, key=lambda r: r.rid):
+            if r.rid < warm or r.U is None:
+                continue
+            h = rte.Handle.from_instance(r.inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0,
+                                         coarse_solver=rte.RTE_COARSE_QUICK)
+            R = torch.empty_like(r.U)
+            h.solve(R, opts=otight, raise_on_notconv=False)
+            errs.append(float(torch.linalg.norm(r.U - R) / torch.linalg.norm(R)))
+            h.close()
+            r.U = None
+        return {"max": max(errs), "median": float(np.median(errs)), "per_request": [round(e, 12) for e in errs]}
+
     def run_batched(rate):
         reqs = [serve.Request(rid=i, inst=insts[i], arrival=float(unit[i] / rate)) for i in range(n)]
-        srv = serve.Server(int(240e9), omx, max_slots=n, workers=4)
+        srv = serve.Server(int(240e9), omx, max_slots=n, workers=4, keep_results=errors)
         t0 = time.perf_counter()
         done = srv.run(reqs)
         srv.close()
         st = stats(done, time.perf_counter() - t0)
         st["peak_live_slots"] = srv.peak_live
+        if errors:
+            st["rel_err_vs_tight_reference"] = errors_vs_tight(done)
         return st
 
     def run_fp64_serial(rate):
@@ -395,6 +465,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the short served-form run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the short batched-form run")
     ap.add_argument("--only", choices=["kernels", "batch", "serve", "rates"], default=None,
                     help="'kernels': assemble the realistic instance, run the dominant kernels twice each "
                          "and a plain 4 GiB device copy (the reference for HBM counter passes), then exit; "
@@ -509,6 +580,42 @@ def main():
     }
     # particle balance of the FP64 solution (source = absorption + leakage up to the residual)
     out["balance"] = h.derived_outputs(U)
+    # ---- the SpMV of the CG E_0 solve (Sec. 5.3), rte_apply_E0 on all 1024 directions, timed
+    #      with HIP events on the stream it is launched on; algorithmic bytes per launch: the
+    #      explicit values of every block, the shared column pattern, X read and Y written once
+    len_ell = ell_entries(inst)
+    spmv_bytes = d.nSp * len_ell * 8 + len_ell * 4 + 2 * d.nRp * d.nSp * 8
+    stream = torch.cuda.current_stream()
+    Xs = torch.randn((d.nSp, d.nRp), dtype=torch.float64, device="cuda")
+    Ys = torch.empty_like(Xs)
+    h.apply_E0(Xs, Ys, stream=stream.cuda_stream)        # builds the explicit values once
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_spmv = 20
+    ev0.record(stream)
+    for _ in range(n_spmv):
+        h.apply_E0(Xs, Ys, stream=stream.cuda_stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    spmv_ms = ev0.elapsed_time(ev1) / n_spmv
+    spmv_gbs = spmv_bytes / (spmv_ms * 1e-3) / 1e9
+    out["spmv"] = {"bound": "hbm", "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("cg_spmv_f64"),
+                   "kernel": "cg_spmv_kernel<double> (E_0 X, sliced ELL, all directions)",
+                   "avg_launch_ms": spmv_ms, "launches": n_spmv, "bytes_per_launch": spmv_bytes,
+                   "ell_entries_per_direction": len_ell}
+    # E_0^{-1} by the CG path on the same workload (context for the banded solve above)
+    cg_out = {}
+    for name, prec, tol in (("fp64", rte.RTE_FP64, 1e-10), ("fp32", rte.RTE_MIXED, 1e-6)):
+        oc = rte.default_solve_opts(e0_solver=rte.RTE_E0_CG, precision=prec, cg_tol=tol, cg_max_iter=20000,
+                                    profile=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.apply_E0inv(Xs, Ys, oc)
+        torch.cuda.synchronize()
+        cg_out[name] = {"ms": 1e3 * (time.perf_counter() - t0), "cg_tol": tol}
+    out["e0inv_cg"] = cg_out
+    del Xs, Ys
     # ---- the mixed-precision form of the same solve: BF16/FP32 preconditioner (condensed
     #      transport GEMM in BF16 with FP32 accumulation, FP32 E_0 band factors), FP64
     #      outer residual, dots and coarse solve
@@ -548,9 +655,13 @@ def main():
                               "frac": s32_tf / FP32_MFMA_PEAK_TFLOPS, "kernel": "gemm_mfma_kernel<float> (U S+)",
                               "avg_launch_ms": 1e3 * ts32 / max(ns32, 1), "launches": ns32,
                               "flops_per_launch": fs32 / max(ns32, 1), "traffic": measured_traffic("gemm_f32_scatter")},
+        # achieved and frac count the method's contraction, 2 n_R- (d n_S+)^2 per launch; the
+        # kernel multiplies by the hi/lo pair [G_hi; G_lo], which doubles K: its own MFMA rate
+        # is kernel_mfma_rate
         "gemm_bf16": {"bound": "mfma", "achieved": bf16_tf, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": bf16_tf / BF16_MFMA_PEAK_TFLOPS, "avg_launch_ms": 1e3 * tb / max(nb, 1),
                       "launches": nb, "flops_per_launch": fb / max(nb, 1),
+                      "kernel_mfma_rate_tflops": 2 * bf16_tf,
                       "traffic": measured_traffic("gemm_bf16_transport")},
         "e0inv_fp32": {"bound": "hbm", "achieved": e0m_bytes / (t_e0m / max(n_e0m, 1)) / 1e9 if n_e0m else 0.0,
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "avg_launch_ms": 1e3 * t_e0m / max(n_e0m, 1),
@@ -597,10 +708,15 @@ def main():
             "iters": [i.iters for i in pinfos], "rel_resid": [i.rel_resid for i in pinfos],
             "rel_diff_vs_fp64_solution": float(torch.linalg.norm(Up - U64) / torch.linalg.norm(U64))}
     h.close()
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+    if not args.no_batched:
+        # the batched form on 16 instances of its distribution (the full 64 are bench.py --only batch)
+        out["batched"] = batched_form(torch, rte, inputs, 16, args.tol, log, with_server=False)
     if not args.no_serving:
-        # the served form at one arrival rate, reduced to a short run (the full study is
+        # the served form at one arrival rate, reduced to 64 requests (the full study is
         # bench.py --only serve)
-        sv = serving_runs(torch, rte, inputs, ["50"], 24, args.tol, warm=4)
+        sv = serving_runs(torch, rte, inputs, ["50"], 64, args.tol, warm=4)
         r = sv["rates"]["50"]
         out["serving"] = {"workload": sv["workload"], "rate_per_s": 50,
                           "p50_latency_s": r["batched"]["p50_s"], "p99_latency_s": r["batched"]["p99_s"],
@@ -608,7 +724,10 @@ def main():
                           "fp64_one_at_a_time": {"p50_latency_s": r["fp64_one_at_a_time"]["p50_s"],
                                                  "p99_latency_s": r["fp64_one_at_a_time"]["p99_s"],
                                                  "solves_per_s": r["fp64_one_at_a_time"]["solves_per_s"]},
-                          "all_converged": r["batched"]["all_converged"]}
+                          "all_converged": r["batched"]["all_converged"],
+                          "rel_err_vs_tight_reference": {k: v for k, v in
+                                                         r["batched"]["rel_err_vs_tight_reference"].items()
+                                                         if k != "per_request"}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, infos[-1].iters, inst.l)
     print(json.dumps(out))

@@ -42,15 +42,18 @@ typedef enum rte_status {
     RTE_E_NOMEM = 4,      /* device allocation failed                                 */
     RTE_E_HIP = 5,        /* a HIP / rocSOLVER call failed                             */
     RTE_E_NOTCONV = 6,    /* iteration cap reached; the last iterate is returned      */
-    RTE_E_NONFINITE = 7   /* a residual became NaN or Inf                              */
+    RTE_E_NONFINITE = 7,  /* a residual became NaN or Inf                              */
+    RTE_E_STALL = 8       /* the iteration stopped contracting (rte_solve_opts.stall_*);
+                             the last iterate is returned                              */
 } rte_status;
 
 typedef enum rte_precision {
     RTE_FP64 = 0,         /* every step in FP64                                        */
     RTE_MIXED = 1         /* inside the preconditioner: condensed transport GEMM with BF16
-                             inputs and FP32 accumulation, scatter GEMM in FP32 MFMA, E_0
-                             factors FP32; outer residual, all dot products and the coarse
-                             solve FP64                                                  */
+                             inputs and FP32 accumulation (the operator's nearly singular
+                             d x d diagonal blocks applied exactly in FP64 beside it),
+                             scatter GEMM in FP32 MFMA, E_0 factors (or CG vectors) FP32;
+                             outer residual, all dot products and the coarse solve FP64 */
 } rte_precision;
 
 typedef enum rte_dtype { RTE_DT_F64 = 0, RTE_DT_F32 = 1, RTE_DT_BF16 = 2 } rte_dtype;
@@ -180,6 +183,14 @@ typedef struct rte_solve_opts {
     int32_t profile;             /* nonzero: time the E_0 solves and the scattering GEMMs with
                                     HIP events on hip_stream (rte_solve_info.t_*)            */
     int32_t inner;               /* rte_inner: how P_1 is applied                            */
+    /* Stagnation test.  The error of the iteration contracts in the energy norm of E - K+ by
+     * at least the factor c per step (Sec. 3; with the preconditioners of Sec. 5 the factor
+     * is smaller), and so does the step ||u_{n+1} - u_n||_{E-K}.  With stall_iters > 0 the solve
+     * stops with RTE_E_STALL once that step shrinks by less than the factor stall_ratio, i.e.
+     * step_n > stall_ratio * step_{n-1}, on stall_iters consecutive iterations (an inexact or
+     * broken preconditioner, or a floor of the arithmetic).  0 (the default) disables it. */
+    double stall_ratio;          /* default 1.0: no contraction at all                       */
+    int32_t stall_iters;         /* default 0: off                                           */
 } rte_solve_opts;
 
 typedef struct rte_solve_info {
@@ -198,8 +209,7 @@ typedef struct rte_solve_info {
     double t_gemm_bf16;          /*   seconds inside BF16 (mixed-precision) GEMM kernels     */
     int64_t n_gemm_bf16;         /*   number of those launches                               */
     double gemm_bf16_flops;      /*   their algorithmic flops (the method's contraction,     */
-                                 /*   2 n_R- (d n_S+)^2; the kernel runs twice that on the  */
-                                 /*   hi/lo operator pair)                                   */
+                                 /*   2 n_R- (d n_S+)^2)                                     */
     double t_scatter;            /*   seconds inside the FP64 even scatter GEMMs U S+        */
     int64_t n_scatter;           /*   (eq. tpmv), their launches                             */
     double scatter_flops;        /*   and their algorithmic flops                            */
@@ -212,7 +222,7 @@ typedef struct rte_solve_info {
 void rte_default_assemble_opts(rte_assemble_opts* opts);
 /* Defaults: l 4, tol 1e-8, max_iter 200, FP64, PCG odd solve, CG E_0, PCG tolerances
  * 1e-12 (residual) / 1e-10 (inner), pcg_max_iter 200, cg_tol 1e-10, cg_max_iter 20000,
- * profile 0, Richardson inner iteration. */
+ * profile 0, Richardson inner iteration, stagnation test off (stall_ratio 1, stall_iters 0). */
 void rte_default_solve_opts(rte_solve_opts* opts);
 
 /* Validate the problem and assemble every operator of the mixed system (Sec. 4) on
@@ -278,6 +288,13 @@ rte_status rte_apply_scatter_noalloc(rte_handle* h, int32_t parity, int32_t dtyp
 rte_status rte_apply_E(rte_handle* h, const rte_solve_opts* opts, const double* X, double* Y,
                        void* hip_stream);
 
+/* Y = E_0 X, the block-diagonal operator of Sec. 5.3 (block k: (1 - c g)^{-1} sum_{n,m} 2 T_k(n,m)
+ * D_n^T Mt-^{-1} D_m + m_k Mt+ + R_k), by the SpMV kernel of the CG solve over its sliced-ELL
+ * storage.  Device FP64 n_R+ x n_S+ column-major vectors.  The explicit block values are built
+ * on the first call when the handle was not assembled for the CG solver (then it allocates).
+ * Enqueue only. */
+rte_status rte_apply_E0(rte_handle* h, const double* X, double* Y, void* hip_stream);
+
 /* Y = E_0^{-1} X, block by block over the directions (Sec. 5.3).  Device FP64 vectors;
  * with opts->precision == RTE_MIXED the banded solver uses FP32 factors. */
 rte_status rte_apply_E0inv(rte_handle* h, const rte_solve_opts* opts, const double* X,
@@ -294,8 +311,10 @@ rte_status rte_precond(rte_handle* h, const rte_solve_opts* opts, int32_t which,
  * receives the odd part of the final iterate from the second row of the mixed system
  * (eq. mixed_discrete with l- = 0): u- = -(M- - K-)^{-1} A u+, by the exact per-cell odd
  * inverse.  info may be NULL.  Blocking.  Returns
- * RTE_E_NOTCONV at the iteration cap (U_even still holds the last iterate) and
- * RTE_E_NONFINITE if the residual is not finite. */
+ * RTE_E_NOTCONV at the iteration cap (U_even still holds the last iterate), RTE_E_STALL when the
+ * stagnation test of opts fires (likewise), and RTE_E_NONFINITE if the residual is not finite.
+ * The iteration is stationary (u_{n+1} depends on u_n alone), so a solve stopped after n steps
+ * and resumed with U0 = its iterate reproduces the uninterrupted run bit for bit. */
 rte_status rte_solve(rte_handle* h, const rte_solve_opts* opts, const double* U0, double* U_even,
                      double* U_odd, rte_solve_info* info, void* hip_stream);
 
@@ -321,7 +340,8 @@ rte_status rte_derived_outputs(rte_handle* h, const double* U_even, double* phi,
  * bytes (FP64).  Blocking. */
 rte_status rte_get_array(rte_handle* h, int32_t which, void* host_dst, size_t host_bytes);
 
-/* Release the handle (synchronises its stream first).  NULL is accepted. */
+/* Release the handle (synchronises its stream first).  NULL is accepted.  RTE_E_HIP if a
+ * hipFree of its device memory failed (the handle is gone either way). */
 rte_status rte_destroy(rte_handle* h);
 
 /* ------------------------------------------------------------------ batched and served solves
@@ -359,7 +379,7 @@ rte_status rte_batch_step(rte_batch* b, int32_t outer_iters, void* hip_stream, i
 
 /* Report and release up to max_out finished slots: slot ids, their solve infos (iters,
  * rel_resid, stop_quantity, t_solve = seconds from admission to completion) and statuses
- * (RTE_OK, RTE_E_NOTCONV or RTE_E_NONFINITE).  *n_done receives the count.  The
+ * (RTE_OK, RTE_E_NOTCONV, RTE_E_STALL or RTE_E_NONFINITE).  *n_done receives the count.  The
  * released slot ids and budget become free. */
 rte_status rte_batch_poll(rte_batch* b, int32_t max_out, int32_t* slots, rte_solve_info* infos,
                           int32_t* statuses, int32_t* n_done);

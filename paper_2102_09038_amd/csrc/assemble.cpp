@@ -149,30 +149,6 @@ void parallel_for(int n, F f) {
     for (auto& x : th) x.join();
 }
 
-// ----------------------------------------------------------------------------- banded Cholesky
-// A is stored as its lower band by rows: A[i*(bw+1) + bw + j - i] for j in [i-bw, i].
-// In place: L with L L^T = A; afterwards the diagonal entries hold 1 / L(i,i).
-void band_cholesky(Vec& A, int n, int bw) {
-    const size_t w1 = (size_t)bw + 1;
-    for (int j = 0; j < n; ++j) {
-        double* rj = A.data() + w1 * j;
-        double s = rj[bw];
-        for (int k = std::max(0, j - bw); k < j; ++k) { const double v = rj[bw + k - j]; s -= v * v; }
-        if (!(s > 0)) fail(RTE_E_ARG, "coarse matrix is not positive definite");
-        const double ljj = std::sqrt(s);
-        rj[bw] = ljj;
-        const int i1 = std::min(n - 1, j + bw);
-        for (int i = j + 1; i <= i1; ++i) {
-            double* ri = A.data() + w1 * i;
-            double t = ri[bw + j - i];
-            const int k0 = std::max(0, i - bw);
-            for (int k = k0; k < j; ++k) t -= ri[bw + k - i] * rj[bw + k - j];
-            ri[bw + j - i] = t / ljj;
-        }
-    }
-    for (int i = 0; i < n; ++i) A[w1 * i + bw] = 1.0 / A[w1 * i + bw];
-}
-
 // row-major lower band (band[r*(bw+1) + t], t = bw + c - r) -> blocked FP64 layout of
 // kernels_band.hip (k::band_blk_index with 2 entries per group): rows of L (upper = false)
 // or rows of L^T, at (r, t) = L(r+t, r) (upper = true)
@@ -187,78 +163,6 @@ Vec band_to_blocked(const Vec& band, int n, int bw, bool upper) {
             out[k::band_blk_index(r, (int)t, bw, 2)] = v;
         }
     return out;
-}
-
-int band_width(const std::vector<int>& perm, const std::vector<int>& rp, const std::vector<int>& ci) {
-    int bw = 0;
-    for (size_t i = 0; i + 1 < rp.size(); ++i)
-        for (int e = rp[i]; e < rp[i + 1]; ++e) bw = std::max(bw, std::abs(perm[i] - perm[ci[e]]));
-    return bw;
-}
-
-// reverse Cuthill-McKee on the P1 graph; returns perm[i] = new position of vertex i
-std::vector<int> rcm(int n, const std::vector<int>& rp, const std::vector<int>& ci) {
-    std::vector<int> deg(n), order;
-    order.reserve(n);
-    for (int i = 0; i < n; ++i) deg[i] = rp[i + 1] - rp[i];
-    std::vector<char> seen(n, 0);
-    std::vector<int> byDeg(n);
-    std::iota(byDeg.begin(), byDeg.end(), 0);
-    std::stable_sort(byDeg.begin(), byDeg.end(), [&](int a, int b) { return deg[a] < deg[b]; });
-    for (int start : byDeg) {
-        if (seen[start]) continue;
-        std::deque<int> dq{start};
-        seen[start] = 1;
-        while (!dq.empty()) {
-            const int v = dq.front();
-            dq.pop_front();
-            order.push_back(v);
-            std::vector<int> nb;
-            for (int e = rp[v]; e < rp[v + 1]; ++e)
-                if (!seen[ci[e]]) { seen[ci[e]] = 1; nb.push_back(ci[e]); }
-            std::stable_sort(nb.begin(), nb.end(), [&](int a, int b) { return deg[a] < deg[b]; });
-            for (int u : nb) dq.push_back(u);
-        }
-    }
-    std::reverse(order.begin(), order.end());
-    std::vector<int> perm(n);
-    for (int p = 0; p < n; ++p) perm[order[p]] = p;
-    return perm;
-}
-
-// The P1 pattern (CSR rp / ci) in sliced ELL form for the CG solve of E_0: slices of 64 rows,
-// as many slots as the slice's longest row, slot j of a slice one contiguous group of 64
-// entries (lane = row).  sptr[s] = first slot group of slice s; col = column of every entry (the
-// row itself on padding, whose value is zero); epos = the entry's CSR position (-1 on padding).
-// Returns the number of entries; the arrays are filled when non-null.
-size_t sliced_ell(int n, const std::vector<int>& rp, const std::vector<int>& ci, std::vector<int>* sptr,
-                  std::vector<int>* col, std::vector<int>* epos) {
-    const int nslice = (n + 63) / 64;
-    std::vector<int> sp(nslice + 1, 0);
-    for (int sl = 0; sl < nslice; ++sl) {
-        int w = 0;
-        for (int i = 64 * sl; i < std::min(n, 64 * sl + 64); ++i) w = std::max(w, rp[i + 1] - rp[i]);
-        sp[sl + 1] = sp[sl] + w;
-    }
-    const size_t len = (size_t)sp[nslice] * 64;
-    if (col && epos) {
-        col->assign(len, 0);
-        epos->assign(len, -1);
-        for (int sl = 0; sl < nslice; ++sl)
-            for (int j = 0; j < sp[sl + 1] - sp[sl]; ++j)
-                for (int lane = 0; lane < 64; ++lane) {
-                    const int i = 64 * sl + lane;
-                    const size_t q = ((size_t)sp[sl] + j) * 64 + lane;
-                    if (i < n && j < rp[i + 1] - rp[i]) {
-                        (*epos)[q] = rp[i] + j;
-                        (*col)[q] = ci[rp[i] + j];
-                    } else {
-                        (*col)[q] = i < n ? i : 0;
-                    }
-                }
-    }
-    if (sptr) *sptr = sp;
-    return len;
 }
 
 // rocBLAS handle on the assembly stream; creation, destruction and every library call hold
@@ -408,7 +312,7 @@ size_t Handle::footprint() const {
                MtMs.bytes() + bnd_row.bytes() + cg_iters.bytes() + ell_sptr.bytes() + ell_col.bytes() + ell_e.bytes() +
                ell_v64.bytes() + ell_dinv64.bytes() + ell_v32.bytes() + ell_dinv32.bytes() + cg_part.bytes() +
                cg_scal.bytes() + cg_state.bytes() +
-               Sp_f.bytes() + Sm_f.bytes() + Gc_bf.bytes() + L0f.bytes() + L0Uf.bytes() + red.bytes() +
+               Sp_f.bytes() + Sm_f.bytes() + Gc_bf.bytes() + coefD.bytes() + L0f.bytes() + L0Uf.bytes() + red.bytes() +
                scal.bytes();
     for (auto& w : ws) b += w.bytes();
     return b;
@@ -432,45 +336,10 @@ struct PhaseTrace {
 
 Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStream_t s) {
     PhaseTrace trace(s);
-    // ------------------------------------------------------------------ validation
-    if (!D || !o) fail(RTE_E_ARG, "null descriptor or options");
-    if (o->mixed < 0 || o->mixed > 2) fail(RTE_E_ARG, "mixed must be 0, 1 or 2");
-    if (o->odd_eig != 0 && o->odd_eig != 1) fail(RTE_E_ARG, "odd_eig must be 0 or 1");
-    if (o->coarse_solver < RTE_COARSE_AUTO || o->coarse_solver > RTE_COARSE_QUICK)
-        fail(RTE_E_ARG, "unknown coarse solver");
+    // ------------------------------------------------------------------ validation (host.cpp)
+    const double cmax = validate_problem(D, o);
     const int d = D->dim;
-    if (d != 2 && d != 3) fail(RTE_E_ARG, "dim must be 2 or 3");
-    if (D->n_vert < d + 1 || D->n_cell < 1 || !D->vert || !D->cell) fail(RTE_E_ARG, "empty spatial mesh");
-    if (!D->sigma_t || !D->sigma_s || !D->q_nodal) fail(RTE_E_ARG, "null sigma_t / sigma_s / q_nodal");
-    if (D->g_inflow) fail(RTE_E_ARG, "inflow boundary data is not supported (vacuum boundary only)");
-    if (D->n_stri < 2 || D->n_stri % 2 || !D->svert || !D->stri || D->n_svert < 3)
-        fail(RTE_E_MESH, "sphere mesh must have an even, positive number of triangles");
-    if (!(D->g >= 0.0 && D->g < 1.0)) fail(RTE_E_PHYS, "g must lie in [0, 1)");
-    if (o->quad_level < 0 || o->quad_level > 6) fail(RTE_E_ARG, "quad_level must lie in 0..6");
-    if (o->n_even < 0 || o->n_even > 8) fail(RTE_E_ARG, "n_even must lie in 0..8");
-    if (o->n_odd < 1 || o->n_odd > 8) fail(RTE_E_ARG, "n_odd must lie in 1..8");
     const int nRp = D->n_vert, nRm = D->n_cell;
-    double cmax = 0.0;
-    for (int j = 0; j < nRm; ++j) {
-        const double st = D->sigma_t[j], ss = D->sigma_s[j];
-        if (!std::isfinite(st) || !std::isfinite(ss) || !(st > 0) || ss < 0)
-            fail(RTE_E_PHYS, "sigma_t must be > 0 and sigma_s >= 0 (finite) in every cell");
-        cmax = std::max(cmax, ss / st);
-    }
-    if (!(cmax < 1.0)) fail(RTE_E_PHYS, "max sigma_s/sigma_t must be < 1 (absorbing medium)");
-    for (int i = 0; i < nRp * d; ++i)
-        if (!std::isfinite(D->vert[i])) fail(RTE_E_ARG, "non-finite vertex coordinate");
-    for (int i = 0; i < nRp; ++i)
-        if (!std::isfinite(D->q_nodal[i])) fail(RTE_E_ARG, "non-finite source value");
-    for (int i = 0; i < nRm * (d + 1); ++i)
-        if (D->cell[i] < 0 || D->cell[i] >= nRp) fail(RTE_E_MESH, "cell vertex index out of range");
-    for (int i = 0; i < D->n_stri * 3; ++i)
-        if (D->stri[i] < 0 || D->stri[i] >= D->n_svert) fail(RTE_E_MESH, "sphere vertex index out of range");
-    for (int i = 0; i < D->n_svert; ++i) {
-        const double* v = D->svert + 3 * i;
-        const double nv = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        if (!(std::fabs(nv - 1.0) < 1e-10)) fail(RTE_E_MESH, "sphere vertices must be unit vectors");
-    }
 
     auto H = std::make_unique<Handle>();
     Handle& h = *H;
@@ -483,40 +352,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     trace("validation");
     // ------------------------------------------------------------------ sphere: upper half, antipodes
     const int nt = D->n_stri;
-    auto vkey = [](const double* v) {
-        auto q = [](double x) { return (long long)std::llround(x * 1e9); };
-        return std::array<long long, 3>{q(v[0]), q(v[1]), q(v[2])};
-    };
-    std::map<std::array<long long, 9>, int> trikey;
-    auto tkey = [&](const int* t, double sign) {
-        std::array<std::array<long long, 3>, 3> ks;
-        for (int v = 0; v < 3; ++v) {
-            const double* p = D->svert + 3 * t[v];
-            const double q[3] = {sign * p[0], sign * p[1], sign * p[2]};
-            ks[v] = vkey(q);
-        }
-        std::sort(ks.begin(), ks.end());
-        std::array<long long, 9> out;
-        for (int v = 0; v < 3; ++v)
-            for (int e = 0; e < 3; ++e) out[3 * v + e] = ks[v][e];
-        return out;
-    };
-    for (int t = 0; t < nt; ++t) trikey[tkey(D->stri + 3 * t, 1.0)] = t;
-    std::vector<int> upper;
-    for (int t = 0; t < nt; ++t) {
-        double cz = 0, cy = 0, cx = 0;
-        for (int v = 0; v < 3; ++v) {
-            const double* p = D->svert + 3 * D->stri[3 * t + v];
-            cx += p[0]; cy += p[1]; cz += p[2];
-        }
-        const double key = cz != 0 ? cz : (cy != 0 ? cy : cx);
-        if (key > 0) {
-            if (!trikey.count(tkey(D->stri + 3 * t, -1.0)))
-                fail(RTE_E_MESH, "sphere triangle " + std::to_string(t) + " has no antipodal partner");
-            upper.push_back(t);
-        }
-    }
-    if ((int)upper.size() * 2 != nt) fail(RTE_E_MESH, "sphere mesh is not split evenly into antipodal pairs");
+    const std::vector<int> upper = pair_sphere(D);
     const int nS = (int)upper.size();
     h.nS = nS;
     h.nSm = 3 * nS;
@@ -601,19 +437,8 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
 
     trace("spatial geometry");
     // ------------------------------------------------------------------ P1 pattern
-    std::vector<std::vector<int>> adj(nRp);
-    for (int j = 0; j < nRm; ++j)
-        for (int a = 0; a < nv; ++a)
-            for (int b = 0; b < nv; ++b) adj[D->cell[nv * j + a]].push_back(D->cell[nv * j + b]);
-    std::vector<int> rp(nRp + 1, 0), ci;
-    for (int i = 0; i < nRp; ++i) {
-        auto& v = adj[i];
-        v.push_back(i);
-        std::sort(v.begin(), v.end());
-        v.erase(std::unique(v.begin(), v.end()), v.end());
-        rp[i + 1] = rp[i] + (int)v.size();
-        ci.insert(ci.end(), v.begin(), v.end());
-    }
+    std::vector<int> rp, ci;
+    p1_pattern(D, rp, ci);
     const int nnz = rp[nRp];
     h.nnz = nnz;
     auto find = [&](int i, int jv) {
@@ -874,6 +699,13 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
                     }
             }
         h.Gc.upload(G, s);
+        // its diagonal d x d blocks G_kk(n, m) as coefficients of the stiffness classes (n <= m;
+        // the class of n < m holds both orders): the mixed-precision path applies them exactly
+        Vec cd((size_t)nS * nstiff);
+        for (int k2 = 0; k2 < nS; ++k2)
+            for (int c = 0; c < nstiff; ++c)
+                cd[(size_t)k2 * nstiff + c] = G[(nm[c].first * nS + k2) + (size_t)dn * (nm[c].second * nS + k2)];
+        h.coefD.upload(cd, s);
     };
     if (odd_eig) {   // odd: S- W = M_S- W Lambda; with M_S- = L L^T blockwise: (L^-1 S- L^-T) V = V Lambda, W = L^-T V
         Vec A((size_t)nSm * nSm);
@@ -1209,12 +1041,12 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         k::cvt_f64_f32(h.Sp.p, h.Sp_f.p, h.Sp.n, s);
         k::cvt_f64_f32(h.Sm.p, h.Sm_f.p, h.Sm.n, s);
         if (h.Gc.p) {
-            // [G_hi; G_lo] (2 dn x dn, column-major): the BF16 transport GEMM carries the
-            // operator with 16 significant bits (its diagonal blocks are nearly singular for
-            // small sphere triangles, see kernels_mixed.hip)
+            // the BF16 transport operator without its diagonal d x d blocks, which are nearly
+            // singular for small sphere triangles and go to the A^T kernel exactly instead (see
+            // kernels_mixed.hip)
             const size_t dn = (size_t)h.d * nS;
-            h.Gc_bf.alloc(2 * dn * dn);
-            k::cvt_f64_bf16_split2(h.Gc.p, h.Gc_bf.p, dn, s);
+            h.Gc_bf.alloc(dn * dn);
+            k::cvt_f64_bf16_offdiag(h.Gc.p, h.Gc_bf.p, dn, nS, s);
         }
         if (h.have_e0_banded) {
             h.e0_stride32 = k::band_blk_size(nRp, h.sbw, 4);
@@ -1237,102 +1069,6 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&h.pinned), 64 * sizeof(double), hipHostMallocDefault));
     RTE_HIP(hipStreamSynchronize(s));
     return H.release();
-}
-
-
-// Device bytes a handle will hold after assemble() (operators, factors and the workspace of a
-// solve or batch slot) and the peak during assembly, from the problem's sizes alone: the P1
-// pattern's bandwidth is computed (natural and reverse Cuthill-McKee orders, as assemble()
-// chooses), nothing is allocated on the GPU.  Small per-cell and per-pattern arrays are
-// bounded from above.
-size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o, size_t* peak) {
-    if (!D || !o) fail(RTE_E_ARG, "null descriptor or options");
-    const int d = D->dim;
-    if (d != 2 && d != 3) fail(RTE_E_ARG, "dim must be 2 or 3");
-    if (D->n_vert < d + 1 || D->n_cell < 1 || !D->cell || D->n_stri < 2) fail(RTE_E_ARG, "empty mesh");
-    const int nv = d + 1, nRp = D->n_vert, nRm = D->n_cell;
-    const size_t nS = (size_t)D->n_stri / 2, nSm = 3 * nS;
-    const size_t dN = (size_t)(o->n_even + 1) * (o->n_even + 2) / 2;
-    const size_t dNm = (size_t)(o->n_odd + 1) * (o->n_odd + 2) / 2;
-    std::vector<std::vector<int>> adj(nRp);
-    for (int j = 0; j < nRm; ++j)
-        for (int a = 0; a < nv; ++a)
-            for (int b = 0; b < nv; ++b) {
-                const int va = D->cell[nv * j + a], vb = D->cell[nv * j + b];
-                if (va < 0 || va >= nRp || vb < 0 || vb >= nRp) fail(RTE_E_MESH, "cell vertex out of range");
-                adj[va].push_back(vb);
-            }
-    std::vector<int> rp(nRp + 1, 0), ci;
-    for (int i = 0; i < nRp; ++i) {
-        auto& v = adj[i];
-        v.push_back(i);
-        std::sort(v.begin(), v.end());
-        v.erase(std::unique(v.begin(), v.end()), v.end());
-        rp[i + 1] = rp[i] + (int)v.size();
-        ci.insert(ci.end(), v.begin(), v.end());
-    }
-    std::vector<int> ident(nRp);
-    std::iota(ident.begin(), ident.end(), 0);
-    const int sbw = std::min(band_width(rcm(nRp, rp, ci), rp, ci), band_width(ident, rp, ci));
-    const size_t nnz = (size_t)rp[nRp], nc = dN * nRp, even = (size_t)nRp * nS;
-    const size_t cbw = dN * sbw + dN - 1;
-    size_t b = 0;
-    // angular operators: S+, S-, eigenbases (full odd basis twice), H, condensed G, moments;
-    // without the odd eigendecomposition (uniform ratio, odd_eig = 0) neither odd basis
-    bool uniform = true;
-    if (D->sigma_t && D->sigma_s) {
-        double lo = 1e300, hi = -1e300;
-        for (int j = 0; j < nRm; ++j) {
-            const double r = D->sigma_s[j] / D->sigma_t[j];
-            lo = std::min(lo, r);
-            hi = std::max(hi, r);
-        }
-        uniform = hi - lo <= 1e-13 * std::max(hi, 1e-300);
-    }
-    if (o->odd_eig == 0 && uniform) b += (nS * nS + 2 * nSm * nSm + nS * dN + 4 * nSm + 16 * nS) * 8;
-    else b += (nS * nS + 4 * nSm * nSm + nSm * dNm + nS * dN + 4 * nSm + 16 * nS) * 8;
-    b += (size_t)d * nS * d * nS * 8;
-    // spatial data: cells, gradients, pattern values per class, incidence, source
-    b += (size_t)nRm * (nv * 4 + nv * d * 8 + 4 * 8) + nnz * (4 + 8 * (kMaxClasses + 4)) + (size_t)nRp * 16;
-    b += (size_t)nRm * nv * (4 + 4 + d * 8) + nS * kMaxClasses * 8 * 3 + even * 8;
-    // coarse solve: explicit inverse or band factors
-    size_t transient = 0;
-    {
-        const bool inv_fits = (double)nc * nc * 8 <= kEcinvMaxBytes, band_fits = k::band_groups((int)cbw, 2) != 0;
-        int how = o->coarse_solver;
-        if (how == RTE_COARSE_QUICK)
-            how = (band_fits && k::band_factor_fits((int)cbw)) ? RTE_COARSE_BAND : RTE_COARSE_AUTO;
-        if (how == RTE_COARSE_AUTO) how = inv_fits ? RTE_COARSE_INVERSE : band_fits ? RTE_COARSE_BAND : RTE_COARSE_BLOCK;
-        if (how == RTE_COARSE_INVERSE) {
-            b += nc * nc * 8;
-        } else if (how == RTE_COARSE_BAND) {
-            b += 2 * k::band_blk_size((int)nc, (int)cbw, 2) * 8;
-        } else {
-            const size_t bs = std::max<size_t>(cbw, 1), nbk = (nc + bs - 1) / bs;
-            b += (4 * nbk - 2) * bs * bs * 8 + 2 * nbk * bs * 8;
-            transient = std::max(transient, nc * (cbw + 1) * 8);   // the band on its way to the blocks
-        }
-    }
-    if (o->e0_solver == RTE_E0_BANDED) {
-        const size_t f64 = 2 * k::band_blk_size(nRp, sbw, 2) * nS * 8;
-        if (o->mixed != 2) b += f64;
-        else transient = f64;
-        if (o->mixed) b += 2 * k::band_blk_size(nRp, sbw, 4) * nS * 4;
-    }
-    if (o->mixed) b += (nS * nS + nSm * nSm) * 4 + 2 * (size_t)d * nS * d * nS * 2;
-    // the sliced ELL pattern; with the CG solver the explicit values (FP64, and FP32 when mixed),
-    // inverse diagonals, three CG vectors and the per-tile partials
-    const size_t ell = sliced_ell(nRp, rp, ci, nullptr, nullptr, nullptr);
-    b += ell * 8 + ((size_t)nRp / 64 + 2) * 4;
-    if (o->e0_solver == RTE_E0_CG) {
-        const size_t ntiles = ((size_t)nRp + 255) / 256;
-        b += nS * ell * 8 + even * 8 + 3 * even * 8 + 4 * nS * ntiles * 8 + 3 * nS * 8 + (nS + 1) * 4;
-        if (o->mixed) b += nS * ell * 4 + even * 4;
-    }
-    // solver workspace: two odd-sized buffers, eleven even vectors, coarse vectors, reductions
-    b += 2 * (size_t)nRm * nSm * 8 + 11 * even * 8 + 2 * nc * 8 + (1 << 16);
-    if (peak) *peak = b + transient;
-    return b;
 }
 
 }  // namespace rte

@@ -40,6 +40,8 @@ void check_opts(const rte_solve_opts* o) {
     if (!(o->pcg_tol_resid > 0) || !(o->pcg_tol_inner > 0) || !(o->cg_tol > 0) || o->pcg_max_iter < 1 ||
         o->cg_max_iter < 1)
         rte::fail(RTE_E_ARG, "inner tolerances must be > 0 and iteration caps >= 1");
+    if (o->stall_iters < 0 || (o->stall_iters > 0 && !(o->stall_ratio > 0)))
+        rte::fail(RTE_E_ARG, "stall_iters must be >= 0 and stall_ratio > 0 when it is on");
 }
 
 rte::Handle* as_handle(rte_handle* h) {
@@ -76,6 +78,8 @@ void rte_default_solve_opts(rte_solve_opts* o) {
     o->cg_max_iter = 20000;
     o->profile = 0;
     o->inner = RTE_INNER_RICHARDSON;
+    o->stall_ratio = 1.0;
+    o->stall_iters = 0;
 }
 
 rte_status rte_assemble(const rte_problem_desc* desc, const rte_assemble_opts* opts, void* hip_stream,
@@ -155,6 +159,15 @@ rte_status rte_apply_E(rte_handle* hh, const rte_solve_opts* o, const double* X,
         check_opts(o);
         if (!X || !Y) rte::fail(RTE_E_ARG, "null operand");
         rte::apply_E(h, o, X, Y, as_stream(hip_stream), nullptr);
+        return RTE_OK;
+    });
+}
+
+rte_status rte_apply_E0(rte_handle* hh, const double* X, double* Y, void* hip_stream) {
+    return guarded([&] {
+        rte::Handle* h = as_handle(hh);
+        if (!X || !Y) rte::fail(RTE_E_ARG, "null operand");
+        rte::apply_E0(h, X, Y, as_stream(hip_stream));
         return RTE_OK;
     });
 }
@@ -326,7 +339,12 @@ rte_status rte_get_array(rte_handle* hh, int32_t which, void* host_dst, size_t h
 
 rte_status rte_destroy(rte_handle* hh) {
     return guarded([&] {
+        (void)rte::take_free_error();
         delete reinterpret_cast<rte::Handle*>(hh);
+        const hipError_t e = rte::take_free_error();
+        if (e != hipSuccess)
+            rte::fail(RTE_E_HIP, std::string("releasing the handle's device memory: hipFree failed: ") +
+                                     hipGetErrorString(e));
         return RTE_OK;
     });
 }

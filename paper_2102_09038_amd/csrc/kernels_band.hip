@@ -68,7 +68,6 @@ __global__ __launch_bounds__(256) void e0_band_fill_kernel(int n, int bw, int nn
 // into the slot row j vacated.  Thread t owns offset t of the row leaving and of the row
 // arriving: column j-bw+t and column j+1+t share one window position (mod bw+1), so the
 // thread reads the old entry before it writes the new one and no other thread touches it.
-constexpr int kFacCols = 9;     // columns per thread of the trailing update: 16 x 9 >= bw + 1
 
 // Work-group barrier for LDS traffic only: this thread's LDS operations complete
 // (lgkmcnt(0)), then s_barrier.  __syncthreads would also wait for every global load and
@@ -658,9 +657,6 @@ void band_factor_one(int n, int bw, double* BL, double* BU, int* bad, hipStream_
     RTE_CHECK_LAUNCH();
 }
 
-bool band_factor_fits(int bw) {
-    return (size_t)(bw + 1) * (bw + 1) * sizeof(double) <= 150 * 1024 && bw + 1 <= 16 * kFacCols;
-}
 
 void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
                     const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G) {

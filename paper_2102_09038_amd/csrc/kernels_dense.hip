@@ -387,12 +387,10 @@ __global__ void cvt_f64_bf16_kernel(const double* x, uint16_t* y, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         y[i] = f32_to_bf16_rne((float)x[i]);
 }
-__global__ void cvt_f64_bf16_split2_kernel(const double* X, uint16_t* Y, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < 2 * n * n; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t c = i / (2 * n), r = i % (2 * n);
-        const double v = X[c * n + (r < n ? r : r - n)];
-        const uint16_t hi = f32_to_bf16_rne((float)v);
-        Y[i] = r < n ? hi : f32_to_bf16_rne((float)(v - (double)__uint_as_float((uint32_t)hi << 16)));
+__global__ void cvt_f64_bf16_offdiag_kernel(const double* X, uint16_t* Y, size_t n, size_t nb) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n * n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = i / n, r = i % n;
+        Y[i] = (r % nb == c % nb) ? (uint16_t)0 : f32_to_bf16_rne((float)X[i]);
     }
 }
 __global__ void cvt_f32_bf16_kernel(const float* x, uint16_t* y, size_t n) {
@@ -521,9 +519,9 @@ void cvt_f64_bf16(const double* x, uint16_t* y, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(cvt_f64_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
     RTE_CHECK_LAUNCH();
 }
-void cvt_f64_bf16_split2(const double* X, uint16_t* Y, size_t n, hipStream_t s) {
+void cvt_f64_bf16_offdiag(const double* X, uint16_t* Y, size_t n, size_t nb, hipStream_t s) {
     if (!n) return;
-    hipLaunchKernelGGL(cvt_f64_bf16_split2_kernel, dim3(grid_for(2 * n * n)), dim3(256), 0, s, X, Y, n);
+    hipLaunchKernelGGL(cvt_f64_bf16_offdiag_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, X, Y, n, nb);
     RTE_CHECK_LAUNCH();
 }
 void cvt_f32_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s) {

@@ -202,21 +202,20 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(int M, int N, int K, 
 }
 
 // ============================================================================ glue
-// Ycb[j * 2 dn + n nS + k] = Ycb[j * 2 dn + dn + n nS + k] = bf16((D_n X)[j, k] / mt_j): the
-// condensed GEMM's A operand, row-major (angular index contiguous).
+// Ycb[j * dn + n nS + k] = bf16((D_n X)[j, k] / mt_j): the condensed GEMM's B operand, row-major
+// (angular index contiguous).
 template <int D>
 __global__ __launch_bounds__(256) void apply_grad_bf16_kernel(int nRm, int nRp, int nS, const int* __restrict__ cell,
                                                               const double* __restrict__ Dc,
                                                               const double* __restrict__ mt,
                                                               const double* __restrict__ X,
                                                               uint16_t* __restrict__ Ycb) {
-    // Row j holds the d nS values twice: the GEMM multiplies [Y | Y] with [G_hi; G_lo], the
-    // operator carried as a pair of BF16 parts (16 significant bits).  The operator needs
-    // them: its d x d diagonal blocks are the odd moments 2 T_k of the sphere triangles,
-    // nearly singular for small triangles (s_x and s_y almost proportional over the
-    // triangle), and rounding them to 8 bits can make the transport term indefinite.
-    // Rounding the data Y to BF16 only adds a small error to each product and leaves the
-    // operator positive definite.
+    // Rounding the data Y to BF16 only adds a small error to each product.  The operator's
+    // d x d diagonal blocks (the odd moments 2 T_k of the sphere triangles plus their own
+    // scattering part) are nearly singular for small triangles (s_x and s_y almost
+    // proportional over the triangle), and rounding them to 8 bits can make the transport
+    // term indefinite; they are therefore left out of the BF16 operator and applied exactly
+    // in FP64 by the A^T kernel.
     //
     // A work-group takes 32 cells x 64 directions.  First each thread computes 8 directions
     // of one cell (consecutive threads on consecutive cells, so the reads of X run along its
@@ -255,7 +254,7 @@ __global__ __launch_bounds__(256) void apply_grad_bf16_kernel(int nRm, int nRp, 
         }
     }
     __syncthreads();
-    // rows out: (cell, component) pairs, 8 chunks of 16 bytes each, both copies
+    // rows out: (cell, component) pairs, 8 chunks of 16 bytes each
     const size_t dn = (size_t)D * nS;
     for (int e = threadIdx.x; e < TC * D * 8; e += 256) {
         const int ch = e % 8, row = e / 8;
@@ -263,8 +262,7 @@ __global__ __launch_bounds__(256) void apply_grad_bf16_kernel(int nRm, int nRp, 
         const int j = j0 + c, k = k0 + 8 * ch;
         if (j >= nRm || k >= nS) continue;
         const uint4 w = *reinterpret_cast<const uint4*>(&T[c][n][8 * ch]);
-        *reinterpret_cast<uint4*>(Ycb + (size_t)j * 2 * dn + (size_t)n * nS + k) = w;
-        *reinterpret_cast<uint4*>(Ycb + (size_t)j * 2 * dn + dn + (size_t)n * nS + k) = w;
+        *reinterpret_cast<uint4*>(Ycb + (size_t)j * dn + (size_t)n * nS + k) = w;
     }
 }
 

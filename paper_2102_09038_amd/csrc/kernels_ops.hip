@@ -166,8 +166,8 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
     int nRp, int nS, int nnz, int ncls, int nstiff, int nb, const int* __restrict__ vc_ptr,
     const int* __restrict__ vc_cell, const double* __restrict__ vcD, const int* __restrict__ rowptr,
     const int* __restrict__ col, const double* __restrict__ MtMs, const double* __restrict__ cls,
-    const int* __restrict__ bnd_row, const double* __restrict__ coefE, const ZT* __restrict__ Z,
-    const double* __restrict__ X, const double* __restrict__ G, const double* __restrict__ q,
+    const int* __restrict__ bnd_row, const double* __restrict__ coefE, const double* __restrict__ coefD,
+    const ZT* __restrict__ Z, const double* __restrict__ X, const double* __restrict__ G, const double* __restrict__ q,
     double* __restrict__ Y) {
     constexpr int TI = 32, TK = 64;
     constexpr int KI = D == 2 ? 6 : 8;       // incidences per batch (six triangles meet at an
@@ -285,6 +285,16 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
                 double val = 0.0;
                 for (int b2 = 0; b2 < nb; ++b2)
                     val = fma(cf[nstiff + 1 + b2], cls[(size_t)(nstiff + 1 + b2) * nnz + e], val);
+                acc = fma(val, xk[col[e]], acc);
+            }
+        }
+        if (coefD) {
+            // the diagonal d x d blocks of the condensed operator, kept out of the BF16 GEMM:
+            // sum_{n,m} G_kk(n,m) D_n^T Mt-^{-1} D_m x_k over the stiffness classes, in FP64
+            const double* cd = coefD + (size_t)k * nstiff;
+            for (int e = e0; e < e1; ++e) {
+                double val = 0.0;
+                for (int c = 0; c < nstiff; ++c) val = fma(cd[c], cls[(size_t)c * nnz + e], val);
                 acc = fma(val, xk[col[e]], acc);
             }
         }
@@ -644,23 +654,23 @@ void apply_At_E(const Handle* h, const double* Z, const double* X, const double*
 
 template <typename ZT>
 void at_e_rm_launch(const Handle* h, const ZT* Z, const double* X, const double* G, const double* q, double* Y,
-                    hipStream_t s) {
+                    const double* coefD, hipStream_t s) {
     const dim3 g((unsigned)((h->nRp + 31) / 32), (unsigned)((h->nS + 63) / 64));
     auto* f = h->d == 2 ? at_e_rm_kernel<2, ZT> : at_e_rm_kernel<3, ZT>;
     hipLaunchKernelGGL(f, g, dim3(256), 0, s, h->nRp, h->nS, h->nnz, h->ncls, h->ncls_stiff, h->nbcls, h->vc_ptr.p,
                        h->vc_cell.p, h->vcD.p, h->rowptr.p, h->col.p, h->MtMs.p, h->cls.p, h->bnd_row.p, h->coefE.p,
-                       Z, X, G, q, Y);
+                       coefD, Z, X, G, q, Y);
     RTE_CHECK_LAUNCH();
 }
 
 void apply_At_E_rm(const Handle* h, const double* Z, const double* X, const double* G, const double* q, double* Y,
                    hipStream_t s) {
-    at_e_rm_launch<double>(h, Z, X, G, q, Y, s);
+    at_e_rm_launch<double>(h, Z, X, G, q, Y, nullptr, s);
 }
 
 void apply_At_E_rm_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,
                        hipStream_t s) {
-    at_e_rm_launch<float>(h, Z, X, G, q, Y, s);
+    at_e_rm_launch<float>(h, Z, X, G, q, Y, h->coefD.p, s);
 }
 
 void apply_grad(const Handle* h, const double* X, double* Yc, hipStream_t s) {

@@ -51,62 +51,8 @@ void scale_eigbasis(const Handle* h, double* C, hipStream_t s);
 // ---- coarse correction (Sec. 5.4)
 // rhs[a + dN*perm[i]] = sum_k T[i,k] Wp[k,a]
 void coarse_project(const Handle* h, const double* T, double* rhs, hipStream_t s);
-// Blocked band layout of a factor with band width bw (kernels_band.hip): rows in blocks of
-// 64, band offsets t = 0..bw in groups of vec consecutive entries (vec = 16 bytes / element);
-// a row block holds G = H P groups (the solve kernel's ring depth H times its phase count P,
-// with H P >= ceil((bw+1)/vec)), zero past t = bw.  The shapes the solve kernel is built for
-// have distinct H P, so a layout's group count G names its shape.  band_shape picks the
-// default (little padding, then a deeper ring); the autotuner may choose another.
-struct BandShape {
-    int H, P;
-};
-constexpr int kBandShapes = 9;
-__host__ __device__ inline BandShape band_shape_at(int k) {
-    const int hs[kBandShapes] = {9, 17, 33, 9, 17, 33, 17, 33, 33};
-    const int ps[kBandShapes] = {1, 1, 1, 2, 2, 2, 3, 3, 4};
-    return BandShape{hs[k], ps[k]};
-}
-__host__ __device__ inline BandShape band_shape(int bw, int vec) {
-    const int g = (bw + vec) / vec;
-    BandShape best{0, 0};
-    int waste = 1 << 30;
-    for (int k = 0; k < kBandShapes; ++k) {
-        const BandShape sh = band_shape_at(k);
-        const int cap = sh.H * sh.P;
-        if (cap < g) continue;
-        // prefer little padding, then a deeper ring
-        const int w = (cap - g) * 4 - sh.H;
-        if (w < waste) { waste = w; best = sh; }
-    }
-    return best;
-}
-// the shape of a layout with G groups per row block ({0, 0}: none)
-__host__ __device__ inline BandShape band_shape_of_groups(int G) {
-    for (int k = 0; k < kBandShapes; ++k) {
-        const BandShape sh = band_shape_at(k);
-        if (sh.H * sh.P == G) return sh;
-    }
-    return BandShape{0, 0};
-}
-// default group count (0 if the band is too wide for every shape)
-__host__ __device__ inline size_t band_groups(int bw, int vec) {
-    const BandShape sh = band_shape(bw, vec);
-    return (size_t)sh.H * sh.P;
-}
-__host__ __device__ inline size_t band_blk_index_g(int r, int t, int G, int vec) {
-    return (((size_t)(r >> 6) * G + t / vec) * 64 + (r & 63)) * vec + t % vec;
-}
-__host__ __device__ inline size_t band_blk_size_g(int n, int G, int vec) {
-    return (size_t)((n + 63) / 64) * G * 64 * vec;
-}
-// the same in the default layout
-__host__ __device__ inline size_t band_blk_index(int r, int t, int bw, int vec) {
-    return band_blk_index_g(r, t, (int)band_groups(bw, vec), vec);
-}
-// number of elements of one system's factor in the default layout (0 if the band is too wide)
-__host__ __device__ inline size_t band_blk_size(int n, int bw, int vec) {
-    return band_blk_size_g(n, (int)band_groups(bw, vec), vec);
-}
+// The blocked band layout and its size arithmetic (BandShape, band_groups, band_blk_size, ...)
+// are in host.h.
 // x = L^{-T} L^{-1} b for nsys systems with blocked band factors BL (rows of L) and BU
 // (rows of L^T) in the layout of G groups per row block (G = 0: the default layout)
 // (kernels_band.hip); b and x are read / written at iperm[band row] when iperm is given
@@ -117,8 +63,6 @@ void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys,
 // and L on exit, BU (zeroed by the caller) rows of L^T; the diagonal entries become
 // 1 / L(i,i).  *bad (zeroed by the caller) is set if a pivot is not positive.
 void band_factor_one(int n, int bw, double* BL, double* BU, int* bad, hipStream_t s);
-// whether band_factor_one takes half-bandwidth bw
-bool band_factor_fits(int bw);
 // same with FP32 factors (the reduced-precision preconditioner); FP64 vectors and sums
 void band_solve_blk_f32(const float* BL, const float* BU, int n, int bw, int nsys, size_t stride_sys,
                         const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G = 0);
@@ -211,10 +155,11 @@ namespace rte {
 namespace k {
 // Y = M X column by column for a matrix with the P1 pattern and values vals[nnz]
 void spmm_pattern(const Handle* h, const double* vals, const double* X, double* Y, hipStream_t s);
-// Ycb = [Y | Y] with Y = bf16(Mt-^{-1} [D_1 X, .., D_d X]), row-major nRm x 2 d nS (angular index
-// contiguous; the second copy meets the low BF16 part of the operator in the GEMM)
+// Ycb = bf16(Mt-^{-1} [D_1 X, .., D_d X]), row-major nRm x d nS (angular index contiguous)
 void apply_grad_bf16(const Handle* h, const double* X, uint16_t* Ycb, hipStream_t s);
-// apply_At_E with the condensed components Z row-major (Z[j (d nS) + n nS + k]), FP64 or FP32
+// apply_At_E with the condensed components Z row-major (Z[j (d nS) + n nS + k]), FP64 or FP32;
+// the FP32 form (the mixed-precision GEMM, whose operator leaves out the diagonal d x d blocks)
+// adds those blocks exactly, sum_{n,m} G_kk(n,m) D_n^T Mt-^{-1} D_m X[:, k] (Handle::coefD)
 void apply_At_E_rm(const Handle* h, const double* Z, const double* X, const double* G, const double* q, double* Y,
                    hipStream_t s);
 void apply_At_E_rm_f32(const Handle* h, const float* Z, const double* X, const double* G, const double* q, double* Y,

@@ -13,16 +13,9 @@
 #include <vector>
 
 #include "../../include/rte.h"
+#include "host.h"
 
 namespace rte {
-
-// ----------------------------------------------------------------------------- errors
-struct Error : std::runtime_error {
-    rte_status status;
-    Error(rte_status s, const std::string& msg) : std::runtime_error(msg), status(s) {}
-};
-
-[[noreturn]] inline void fail(rte_status s, const std::string& msg) { throw Error(s, msg); }
 
 #define RTE_HIP(call)                                                                    \
     do {                                                                                 \
@@ -53,6 +46,18 @@ inline std::mutex& solver_library_mutex() {
 }
 
 // ----------------------------------------------------------------------------- buffers
+// The first failed hipFree of the calling thread since the last take_free_error() (a destructor
+// cannot throw, so releases record their error here; re-allocation and rte_destroy report it).
+inline hipError_t& free_error() {
+    static thread_local hipError_t e = hipSuccess;
+    return e;
+}
+inline hipError_t take_free_error() {
+    const hipError_t e = free_error();
+    free_error() = hipSuccess;
+    return e;
+}
+
 // Owning device buffer (hipMalloc / hipFree); movable, not copyable.
 template <typename T>
 struct DBuf {
@@ -70,11 +75,16 @@ struct DBuf {
     ~DBuf() { release(); }
     void alloc(size_t count) {
         release();
+        const hipError_t fe = take_free_error();
+        if (fe != hipSuccess) fail(RTE_E_HIP, std::string("hipFree failed: ") + hipGetErrorString(fe));
         if (count) RTE_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
         n = count;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            const hipError_t e = hipFree(p);
+            if (e != hipSuccess && free_error() == hipSuccess) free_error() = e;
+        }
         p = nullptr;
         n = 0;
     }
@@ -98,8 +108,6 @@ struct DBuf {
 };
 
 // ----------------------------------------------------------------------------- handle
-constexpr int kMaxClasses = 16;   // sparse value classes of the P1 pattern (see below)
-constexpr double kEcinvMaxBytes = 12.0 * (1 << 30);   // budget of an explicit E_c^{-1}
 
 struct Handle {
     // sizes
@@ -182,7 +190,9 @@ struct Handle {
     // ---- reduced-precision copies (mixed precision)
     bool have_mixed = false;
     DBuf<float> Sp_f, Sm_f;        // FP32 S+ and S- (mixed-precision scatter GEMMs)
-    DBuf<uint16_t> Gc_bf;          // condensed transport matrix as BF16 parts [G_hi; G_lo]
+    DBuf<uint16_t> Gc_bf;          // condensed transport matrix in BF16 without its diagonal blocks
+    DBuf<double> coefD;            // [nS * ncls_stiff] those blocks G_kk(n, m) as stiffness-class
+                                   //   coefficients (applied exactly by the A^T kernel)
     size_t e0_stride32 = 0;
     int e0_g32 = 0;                // groups per row block of the FP32 factors' layout
     DBuf<float> L0f, L0Uf;         // FP32 copies of the banded E_0 factors ([nS * e0_stride32])
@@ -213,6 +223,7 @@ void apply_scatter(Handle* h, int parity, int dtin, const void* X, int dtout, vo
                    hipStream_t s);
 void apply_E(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s,
              int64_t* pcg_iters);
+void apply_E0(Handle* h, const double* X, double* Y, hipStream_t s);
 void apply_E0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s,
                  int64_t* cg_total, int* cg_max);
 void precond(Handle* h, const rte_solve_opts* o, int which, const double* r, double* out,
@@ -266,9 +277,10 @@ void gemm_bf16(int M, int N, int K, float alpha, const uint16_t* A, int lda, con
 void cvt_f64_bf16(const double* x, uint16_t* y, size_t n, hipStream_t s);
 void cvt_f32_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s);
 void cvt_f64_f32(const double* x, float* y, size_t n, hipStream_t s);
-// Y (2n x n, column-major) = [X_hi; X_lo] for an n x n column-major X: X_hi = bf16(X),
-// X_lo = bf16(X - X_hi)
-void cvt_f64_bf16_split2(const double* X, uint16_t* Y, size_t n, hipStream_t s);
+// Y = bf16(X) for an n x n matrix whose index is (component, direction) with nb directions,
+// except that the entries coupling a direction with itself (r mod nb == c mod nb, the d x d
+// diagonal blocks) are zero
+void cvt_f64_bf16_offdiag(const double* X, uint16_t* Y, size_t n, size_t nb, hipStream_t s);
 void cvt_f32_f64(const float* x, double* y, size_t n, hipStream_t s);
 }  // namespace k
 

@@ -204,11 +204,10 @@ void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const dou
             float* Zf = reinterpret_cast<float*>(Z);
             k::apply_grad_bf16(h, X, Ycb, s);
             {
-                // the method's flops, 2 n_R- (d n_S+)^2: the hi/lo operator pair doubles the
-                // GEMM's K but not the contraction the method asks for
                 Timed t(h, s, P_GEMM_BF16, 2.0 * h->nRm * (double)dn * dn);
-                // Z^T = [G_hi | G_lo] [Y | Y]^T: Z comes out row-major (cell-major, directions contiguous)
-                k::gemm_bf16(dn, h->nRm, 2 * dn, 1.0f, h->Gc_bf.p, 2 * dn, Ycb, 2 * dn, 0.0f, Zf, dn, s);
+                // Z^T = G_off Y^T (G symmetric): Z comes out row-major (cell-major, directions
+                // contiguous); the diagonal blocks of G are added by the A^T kernel
+                k::gemm_bf16(dn, h->nRm, dn, 1.0f, h->Gc_bf.p, dn, Ycb, dn, 0.0f, Zf, dn, s);
             }
             k::apply_At_E_rm_f32(h, Zf, X, G, q, Y, s);
             return;
@@ -410,12 +409,32 @@ void correction_step(Handle* h, const rte_solve_opts* o, const double* r, const 
     correction_finish(h, sv, step, s);
 }
 
+bool stall_step(const rte_solve_opts* o, double en, double& en_prev, int& stall) {
+    if (o->stall_iters <= 0 || en < 0.0) return false;
+    if (en_prev > 0.0) stall = en > o->stall_ratio * en_prev ? stall + 1 : 0;
+    en_prev = en;
+    return stall >= o->stall_iters;
+}
+
 }  // namespace sv
 
 using namespace sv;
 
 void apply_E(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s, int64_t* pcg) {
     apply_E_core(h, o, X, nullptr, nullptr, Y, o->pcg_tol_resid, s, pcg, o->precision == RTE_MIXED);
+}
+
+void apply_E0(Handle* h, const double* X, double* Y, hipStream_t s) {
+    cg_prepare(h, false, s);
+    k::CgArgs a;
+    a.n = h->nRp;
+    a.nS = h->nS;
+    a.nslice = h->ell_nslice;
+    a.len = h->ell_len;
+    a.sptr = h->ell_sptr.p;
+    a.col = h->ell_col.p;
+    a.part = h->cg_part.p;
+    k::cg_spmv(a, h->ell_v64.p, X, Y, s);
 }
 
 void apply_E0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s,
@@ -448,8 +467,9 @@ rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U
     double* step = ws(h, W_ESTEP);
     if (U0) k::copy(U0, U, n, s);
     else k::fill(U, 0.0, n, s);
-    double e1 = -1.0, step_rprev = 0.0;
+    double e1 = -1.0, step_rprev = 0.0, en_prev = -1.0;
     bool have_step = false;
+    int stall = 0;
     rte_status st = RTE_E_NOTCONV;
     int it = 0;
     for (;;) {
@@ -457,15 +477,17 @@ rte_status solve(Handle* h, const rte_solve_opts* o, const double* U0, double* U
         const double rr = dot_dev(h, r, r, n, S_DOT0, s);
         if (!std::isfinite(rr)) { st = RTE_E_NONFINITE; break; }
         inf.rel_resid = std::sqrt(rr) / h->qnorm;
+        double en = -1.0;
         if (have_step) {
             // ||u_n - u_{n-1}||^2_{E-K} = step^T (r_n - r_{n-1})
             const double sr = dot_dev(h, step, r, n, S_DOT1, s);
-            const double en = std::sqrt(std::max(sr - step_rprev, 0.0));
+            en = std::sqrt(std::max(sr - step_rprev, 0.0));
             if (e1 < 0) e1 = en;
             inf.stop_quantity = e1 > 0 ? en / e1 : 0.0;
         }
         if (inf.rel_resid <= o->tol) { st = RTE_OK; break; }
         if (it >= o->max_iter) { st = RTE_E_NOTCONV; break; }
+        if (stall_step(o, en, en_prev, stall)) { st = RTE_E_STALL; break; }
         apply_P1(h, o, r, sv, s, &inf.pcg_iters_total, &inf.cg_iters_total, &inf.cg_iters_max, lowp);
         correction_step(h, o, r, sv, step, s, &inf.pcg_iters_total, lowp);
         step_rprev = dot_dev(h, step, r, n, S_DOT2, s);

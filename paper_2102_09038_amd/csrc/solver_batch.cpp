@@ -5,8 +5,10 @@
 // - in each of the l steps of P_1 (Alg. 2), the E_0^{-1} applications of all slots are one
 //   grouped band-solve launch per band shape, so that the direction systems of small
 //   instances fill the GPU together;
-// - the remaining per-slot work (ApplyE, the subspace correction) is enqueued slot after slot
-//   on the same stream.
+// - the remaining per-slot work (ApplyE, the subspace correction) of the slots is spread over
+//   a few lanes (streams of the batch, joined to the step's stream by events), so that the
+//   kernels of small instances run side by side and fill the GPU together; each slot's own
+//   launches keep their order on one lane, so its arithmetic is unchanged.
 // Slots may be admitted while others are running and leave as soon as they converge, which
 // is what a continuous-batching server needs.  The arithmetic of a slot is the arithmetic of
 // rte_solve with the same options, so a slot's result does not depend on the other slots.
@@ -28,7 +30,8 @@ struct BatchSlot {
     bool used = false, live = false, done = false;
     int iters = 0;
     bool have_step = false;
-    double e1 = -1.0;
+    double e1 = -1.0, en_prev = -1.0;
+    int stall = 0;
     size_t bytes = 0;
     std::chrono::steady_clock::time_point t0;
 };
@@ -55,14 +58,36 @@ struct Batch {
     // the stream the last batch work went to: a step returns with its last phase still
     // running there, and that phase reads the job table and the graphs
     hipStream_t last = nullptr;
+    // lanes for the per-slot work (default-priority non-blocking streams), with the events
+    // that fork them from the step's stream and join them back
+    static constexpr int kLanes = 4;
+    hipStream_t lane[kLanes] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[kLanes] = {};
+    void ensure_lanes() {
+        if (lane[0]) return;
+        for (int l = 0; l < kLanes; ++l) {
+            RTE_HIP(hipStreamCreateWithFlags(&lane[l], hipStreamNonBlocking));
+            RTE_HIP(hipEventCreateWithFlags(&ev_join[l], hipEventDisableTiming));
+        }
+        RTE_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    }
     // wait for the batch's work in flight (before its job table or graphs are replaced or freed)
     void drain() {
         if (last) RTE_HIP(hipStreamSynchronize(last));
         if (gs && gs != last) RTE_HIP(hipStreamSynchronize(gs));
+        for (int l = 0; l < kLanes; ++l)
+            if (lane[l]) RTE_HIP(hipStreamSynchronize(lane[l]));
     }
     ~Batch() {
         if (last) (void)hipStreamSynchronize(last);
         if (gs) (void)hipStreamSynchronize(gs);
+        for (int l = 0; l < kLanes; ++l)
+            if (lane[l]) {
+                (void)hipStreamSynchronize(lane[l]);
+                (void)hipStreamDestroy(lane[l]);
+                (void)hipEventDestroy(ev_join[l]);
+            }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (g_res) (void)hipGraphExecDestroy(g_res);
         if (g_prec) (void)hipGraphExecDestroy(g_prec);
         if (ev_in) (void)hipEventDestroy(ev_in);
@@ -91,6 +116,30 @@ size_t slot_bytes(Handle* h) {
     for (int id : kSlotWs)
         if (!h->ws[id].p) b += ws_bytes(h, id);
     return b;
+}
+
+// f(slot, stream) for every live slot: slot j of the live ones on lane j mod kLanes, the lanes
+// ordered after the earlier work of s and s's later work after all of them (a single live
+// slot runs on s itself)
+template <typename F>
+void for_slots(Batch* B, hipStream_t s, F&& f) {
+    int nlive = 0;
+    for (auto& sl : B->slots) nlive += sl.live ? 1 : 0;
+    if (nlive <= 1) {
+        for (auto& sl : B->slots)
+            if (sl.live) f(sl, s);
+        return;
+    }
+    const int used = std::min(nlive, Batch::kLanes);
+    RTE_HIP(hipEventRecord(B->ev_fork, s));
+    for (int l = 0; l < used; ++l) RTE_HIP(hipStreamWaitEvent(B->lane[l], B->ev_fork, 0));
+    int j = 0;
+    for (auto& sl : B->slots)
+        if (sl.live) f(sl, B->lane[j++ % used]);
+    for (int l = 0; l < used; ++l) {
+        RTE_HIP(hipEventRecord(B->ev_join[l], B->lane[l]));
+        RTE_HIP(hipStreamWaitEvent(s, B->ev_join[l], 0));
+    }
 }
 
 void rebuild_plan(Batch* B, hipStream_t s) {
@@ -140,28 +189,29 @@ void rebuild_plan(Batch* B, hipStream_t s) {
 // X -> Y = E_0^{-1} X for every live slot (x_of / y_of give the slot's vectors)
 template <typename XF, typename YF>
 void grouped_e0inv(Batch* B, XF x_of, YF y_of, hipStream_t s) {
-    for (auto& sl : B->slots)
-        if (sl.live) k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, x_of(sl), ws(sl.h, W_BB), true, s);
+    for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
+        k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, x_of(sl), ws(sl.h, W_BB), true, ls);
+    });
     k::band_group_run(B->plan, s);
-    for (auto& sl : B->slots)
-        if (sl.live) k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, ws(sl.h, W_BX), y_of(sl), false, s);
+    for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
+        k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, ws(sl.h, W_BX), y_of(sl), false, ls);
+    });
 }
 
 // residuals r_n = (E - K+) u_n - q (FP64) of every live slot and the scalars of its
 // stopping tests (r.r in S_DOT0, step.r_n in S_DOT1; the latter is unused before a slot's
 // first step)
 void enqueue_residuals(Batch* B, hipStream_t s) {
-    for (auto& sl : B->slots) {
-        if (!sl.live) continue;
+    for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
         Handle* h = sl.h;
         const size_t n = (size_t)h->nRp * h->nS;
         double* r = ws(h, W_ER);
-        residual_like(h, &sl.o, sl.U, h->q.p, r, sl.o.pcg_tol_resid, s, nullptr, false);
-        k::dot(r, r, n, h->red.p, s);
-        k::reduce(h->red.p, h->scal.p, S_DOT0, s);
-        k::dot(ws(h, W_ESTEP), r, n, h->red.p, s);
-        k::reduce(h->red.p, h->scal.p, S_DOT1, s);
-    }
+        residual_like(h, &sl.o, sl.U, h->q.p, r, sl.o.pcg_tol_resid, ls, nullptr, false);
+        k::dot(r, r, n, h->red.p, ls);
+        k::reduce(h->red.p, h->scal.p, S_DOT0, ls);
+        k::dot(ws(h, W_ESTEP), r, n, h->red.p, ls);
+        k::reduce(h->red.p, h->scal.p, S_DOT1, ls);
+    });
 }
 
 // P_1^l (Alg. 2) with grouped E_0 solves, the subspace correction (Sec. 5.4), step.r_n into
@@ -171,37 +221,35 @@ void enqueue_precond_update(Batch* B, hipStream_t s) {
     grouped_e0inv(B, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ER); },
                   [](BatchSlot& sl) { return ws(sl.h, W_ES); }, s);
     for (int i = 1; i < B->l; ++i) {
-        for (auto& sl : B->slots) {
-            if (!sl.live) continue;
+        // the previous step's update z -= E_0^{-1}(...) (none before the first) and this
+        // step's E z - r, per slot on its lane
+        for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
+            if (i > 1) k::axpby(-1.0, ws(sl.h, W_EZ), 1.0, ws(sl.h, W_ES), (size_t)sl.h->nRp * sl.h->nS, ls);
             apply_E_core(sl.h, &sl.o, ws(sl.h, W_ES), nullptr, ws(sl.h, W_ER), ws(sl.h, W_ET2), sl.o.pcg_tol_inner,
-                         s, nullptr, lowp);
-        }
+                         ls, nullptr, lowp);
+        });
         grouped_e0inv(B, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ET2); },
                       [](BatchSlot& sl) { return ws(sl.h, W_EZ); }, s);
-        for (auto& sl : B->slots) {
-            if (!sl.live) continue;
-            k::axpby(-1.0, ws(sl.h, W_EZ), 1.0, ws(sl.h, W_ES), (size_t)sl.h->nRp * sl.h->nS, s);
-        }
     }
-    // the subspace correction: right-hand sides, then the coarse solves (explicit inverses
-    // and block factorisations one by one, band factors in one grouped launch), then the
-    // steps and updates
-    for (auto& sl : B->slots)
-        if (sl.live) correction_rhs(sl.h, &sl.o, ws(sl.h, W_ER), ws(sl.h, W_ES), s, nullptr, lowp);
-    for (auto& sl : B->slots)
-        if (sl.live && (sl.h->Ecinv.p || sl.h->cnb)) coarse_solve(sl.h, s);
+    // the last step's update, then the subspace correction: right-hand sides and the coarse
+    // solves by explicit inverses or block factorisations per slot, band factors in one
+    // grouped launch, then the steps and updates
+    for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
+        if (B->l > 1) k::axpby(-1.0, ws(sl.h, W_EZ), 1.0, ws(sl.h, W_ES), (size_t)sl.h->nRp * sl.h->nS, ls);
+        correction_rhs(sl.h, &sl.o, ws(sl.h, W_ER), ws(sl.h, W_ES), ls, nullptr, lowp);
+        if (sl.h->Ecinv.p || sl.h->cnb) coarse_solve(sl.h, ls);
+    });
     if (!B->cplan.launches.empty()) k::band_group_run(B->cplan, s);
-    for (auto& sl : B->slots) {
-        if (!sl.live) continue;
+    for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
         Handle* h = sl.h;
         const size_t n = (size_t)h->nRp * h->nS;
         double* r = ws(h, W_ER);
         double* step = ws(h, W_ESTEP);
-        correction_finish(h, ws(h, W_ES), step, s);
-        k::dot(step, r, n, h->red.p, s);
-        k::reduce(h->red.p, h->scal.p, S_DOT2, s);
-        k::axpby(1.0, step, 1.0, sl.U, n, s);
-    }
+        correction_finish(h, ws(h, W_ES), step, ls);
+        k::dot(step, r, n, h->red.p, ls);
+        k::reduce(h->red.p, h->scal.p, S_DOT2, ls);
+        k::axpby(1.0, step, 1.0, sl.U, n, ls);
+    });
 }
 
 template <typename F>
@@ -310,6 +358,7 @@ int batch_step(Batch* B, int outer_iters, hipStream_t caller) {
         RTE_HIP(hipEventRecord(B->ev_in, caller));
         RTE_HIP(hipStreamWaitEvent(s, B->ev_in, 0));
     }
+    B->ensure_lanes();
     int nlive = 0;
     for (int it = 0; it < outer_iters; ++it) {
         nlive = 0;
@@ -334,15 +383,17 @@ int batch_step(Batch* B, int outer_iters, hipStream_t caller) {
             const double rr = hp[S_DOT0];
             if (!std::isfinite(rr)) { finish(sl, RTE_E_NONFINITE); changed = true; continue; }
             sl.info.rel_resid = std::sqrt(rr) / sl.h->qnorm;
+            double en = -1.0;
             if (sl.have_step) {
                 // ||u_n - u_{n-1}||^2_{E-K} = step^T (r_n - r_{n-1}); step^T r_{n-1} was left in
                 // S_DOT2 by the previous iteration
-                const double en = std::sqrt(std::max(hp[S_DOT1] - hp[S_DOT2], 0.0));
+                en = std::sqrt(std::max(hp[S_DOT1] - hp[S_DOT2], 0.0));
                 if (sl.e1 < 0) sl.e1 = en;
                 sl.info.stop_quantity = sl.e1 > 0 ? en / sl.e1 : 0.0;
             }
             if (sl.info.rel_resid <= sl.o.tol) { finish(sl, RTE_OK); changed = true; }
             else if (sl.iters >= sl.o.max_iter) { finish(sl, RTE_E_NOTCONV); changed = true; }
+            else if (stall_step(&sl.o, en, sl.en_prev, sl.stall)) { finish(sl, RTE_E_STALL); changed = true; }
         }
         if (changed) {
             rebuild_plan(B, s);

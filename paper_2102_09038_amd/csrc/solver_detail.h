@@ -29,6 +29,10 @@ enum WsId {
 };
 
 double* ws(Handle* h, int id);
+// the stagnation test of rte_solve_opts on the energy-norm step en of this iteration (< 0 before
+// the first step): true once the step has failed to shrink by stall_ratio stall_iters times in
+// a row; en_prev and stall carry the state between iterations
+bool stall_step(const rte_solve_opts* o, double en, double& en_prev, int& stall);
 // the explicit E_0 block values and inverse diagonals of the CG solve, FP64 or FP32 (built once)
 void cg_prepare(Handle* h, bool f32, hipStream_t s);
 // Y = E X [- q0] (q0 nullable), or with G = X S+ given: Y = (E - K+) X - q0  (Alg. 1)

@@ -15,7 +15,7 @@ import numpy as np
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librte.so")
 
-RTE_OK, RTE_E_ARG, RTE_E_PHYS, RTE_E_MESH, RTE_E_NOMEM, RTE_E_HIP, RTE_E_NOTCONV, RTE_E_NONFINITE = range(8)
+RTE_OK, RTE_E_ARG, RTE_E_PHYS, RTE_E_MESH, RTE_E_NOMEM, RTE_E_HIP, RTE_E_NOTCONV, RTE_E_NONFINITE, RTE_E_STALL = range(9)
 RTE_FP64, RTE_MIXED = 0, 1
 RTE_DT_F64, RTE_DT_F32, RTE_DT_BF16 = 0, 1, 2
 RTE_ODD_PCG, RTE_ODD_EXACT, RTE_ODD_CONDENSED = 0, 1, 2
@@ -46,7 +46,8 @@ class rte_solve_opts(C.Structure):
                 ("precision", C.c_int32), ("odd_solver", C.c_int32), ("e0_solver", C.c_int32),
                 ("pcg_tol_resid", C.c_double), ("pcg_tol_inner", C.c_double),
                 ("pcg_max_iter", C.c_int32), ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32),
-                ("profile", C.c_int32), ("inner", C.c_int32)]
+                ("profile", C.c_int32), ("inner", C.c_int32), ("stall_ratio", C.c_double),
+                ("stall_iters", C.c_int32)]
 
 
 RTE_TUNE_FORCE = 1
@@ -87,6 +88,7 @@ EXPORTS = {
     "rte_apply_scatter_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                             C.c_void_p]),
     "rte_apply_E": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rte_apply_E0": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_apply_E0inv": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_precond": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_int32, C.c_void_p, C.c_void_p,
                               C.c_void_p]),
@@ -298,6 +300,9 @@ class Handle:
         _check(lib.rte_apply_E(self.h, C.byref(o), C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
                                _stream(stream)))
 
+    def apply_E0(self, X, Y, stream=None):
+        _check(lib.rte_apply_E0(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), _stream(stream)))
+
     def apply_E0inv(self, X, Y, opts=None, stream=None):
         o = opts or default_solve_opts()
         _check(lib.rte_apply_E0inv(self.h, C.byref(o), C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
@@ -314,7 +319,8 @@ class Handle:
         st = lib.rte_solve(self.h, C.byref(o), C.c_void_p(U0.data_ptr() if U0 is not None else 0),
                            C.c_void_p(U.data_ptr()), C.c_void_p(U_odd.data_ptr() if U_odd is not None else 0),
                            C.byref(info), _stream(stream))
-        if st != RTE_OK and (raise_on_notconv or st != RTE_E_NOTCONV):
+        # the iteration cap and the stagnation test return the last iterate: raised only when asked
+        if st != RTE_OK and (raise_on_notconv or st not in (RTE_E_NOTCONV, RTE_E_STALL)):
             _check(st)
         return st, info
 

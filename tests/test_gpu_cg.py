@@ -153,3 +153,14 @@ def test_cg_3d_request_full_size():
     print(f"[3d] recomputed relative residual {r:.2e}")
     assert r <= 1.01e-6
     h.close()
+
+
+def test_apply_E0(cgcase):
+    """The CG's SpMV kernel (rte_apply_E0) against the oracle's E_0 blocks."""
+    name, inst, D, ops, h = cgcase
+    X = np.random.default_rng(54).standard_normal((D.nRp, D.nS))
+    Y = torch.empty_like(to_dev(X))
+    h.apply_E0(to_dev(X), Y)
+    err = rel(from_dev(Y), ops.E0_apply(X))
+    print(f"[{name}] E_0 X {err:.2e}")
+    assert err < 1e-13
