@@ -311,7 +311,7 @@ def batch_bench(args, torch, rte, inputs):
                                   graph_modes=(True, False))))
 
 
-def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None, errors=True):
+def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None, errors=True, fraction_3d=0.0):
     """The served form: Poisson arrivals (seed 4) of requests drawn like the batched form,
     served by the continuous-batching loop (mixed precision, assembly on worker threads,
     admission by predicted footprint) and, as the baseline, by plain FP64 solves one at a
@@ -319,14 +319,16 @@ def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None, err
     each run are not counted.  rates: list of requests/s or 'half' (half the capacity the
     batched loop reached at the highest numeric rate).  errors: every measured batched result
     is compared, after the run, with a tight FP64 solve (relative residual 1e-11) of its
-    request."""
+    request.  fraction_3d: that share of the requests are the 3D ones (32^3 Kuhn tetrahedra, 512
+    sphere triangles, g = 0.8), solved with the CG E_0 (cg_tol 1e-8 in FP64, 1e-6 in FP32; the
+    tight reference 1e-12) in both forms."""
     import numpy as np
 
     from paper_2102_09038_amd import serve
 
     log = log or (lambda msg: None)
     n = requests + warm
-    insts = inputs.instance_distribution(count=n, seed=4, tol=tol)
+    insts = inputs.instance_distribution(count=n, seed=4, tol=tol, large_3d_fraction=fraction_3d)
     base = dict(l=4, tol=tol, max_iter=2000, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_BANDED)
     omx = rte.default_solve_opts(precision=rte.RTE_MIXED, **base)
     o64 = rte.default_solve_opts(precision=rte.RTE_FP64, **base)
@@ -346,60 +348,101 @@ def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None, err
 
     otight = rte.default_solve_opts(precision=rte.RTE_FP64, **dict(base, tol=1e-11))
 
-    def errors_vs_tight(done):
-        """Each measured result against a tight FP64 solve of its request (untimed, after the run)."""
-        errs = []
-        for r in sorted(done, key=lambda r: r.rid):
+    def with_e0(o, inst, cg_tol):
+        """o with the E_0 solver the server uses for inst (CG for 3D meshes)."""
+        e0 = serve.Server.e0_solver_for(inst)
+        if e0 == rte.RTE_E0_BANDED:
+            return o, e0
+        oc = rte.rte_solve_opts.from_buffer_copy(o)
+        oc.e0_solver, oc.cg_tol, oc.cg_max_iter = e0, cg_tol, 20000
+        return oc, e0
+
+    def errors_vs_tight(done_mixed, done_fp64):
+        """Each measured result of both forms against a tight FP64 solve of its request (untimed,
+        after the runs)."""
+        by_rid = {r.rid: r for r in done_fp64}
+        em, ef = [], []
+        tick = progress("tight reference")
+        for r in sorted(done_mixed, key=lambda r: r.rid):
+            tick()
             if r.rid < warm or r.U is None:
                 continue
-            h = rte.Handle.from_instance(r.inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0,
+            ot, e0 = with_e0(otight, r.inst, 1e-12)
+            h = rte.Handle.from_instance(r.inst, e0_solver=e0, mixed=0, odd_eig=0,
                                          coarse_solver=rte.RTE_COARSE_QUICK)
             R = torch.empty_like(r.U)
-            h.solve(R, opts=otight, raise_on_notconv=False)
-            errs.append(float(torch.linalg.norm(r.U - R) / torch.linalg.norm(R)))
+            h.solve(R, opts=ot, raise_on_notconv=False)
+            nr = torch.linalg.norm(R)
+            em.append(float(torch.linalg.norm(r.U - R) / nr))
+            f = by_rid.get(r.rid)
+            if f is not None and f.U is not None:
+                ef.append(float(torch.linalg.norm(f.U - R) / nr))
+                f.U = None
             h.close()
             r.U = None
-        return {"max": max(errs), "median": float(np.median(errs)), "per_request": [round(e, 12) for e in errs]}
+
+        def summ(v):
+            return {"max": max(v), "median": float(np.median(v)), "per_request": [round(e, 12) for e in v]} if v else None
+        return summ(em), summ(ef)
+
+    def progress(what):
+        """a callback that logs every 16th completed request (long runs print as they go)"""
+        count = [0]
+
+        def tick(*_):
+            count[0] += 1
+            if count[0] % 16 == 0 or count[0] == n:
+                log(f"[serve]   {what}: {count[0]}/{n}")
+        return tick
 
     def run_batched(rate):
         reqs = [serve.Request(rid=i, inst=insts[i], arrival=float(unit[i] / rate)) for i in range(n)]
-        srv = serve.Server(int(240e9), omx, max_slots=n, workers=4, keep_results=errors)
+        srv = serve.Server(int(240e9), omx, max_slots=n, workers=4, keep_results=errors,
+                           on_done=progress("batched done"))
         t0 = time.perf_counter()
         done = srv.run(reqs)
         srv.close()
         st = stats(done, time.perf_counter() - t0)
         st["peak_live_slots"] = srv.peak_live
-        if errors:
-            st["rel_err_vs_tight_reference"] = errors_vs_tight(done)
-        return st
+        return st, done
 
     def run_fp64_serial(rate):
         reqs = [serve.Request(rid=i, inst=insts[i], arrival=float(unit[i] / rate)) for i in range(n)]
         t0 = time.perf_counter()
+        tick = progress("fp64 done")
         for r in reqs:
             wait = r.arrival - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
-            h = rte.Handle.from_instance(r.inst, e0_solver=rte.RTE_E0_BANDED, mixed=0, odd_eig=0,
+            o, e0 = with_e0(o64, r.inst, 1e-8)
+            h = rte.Handle.from_instance(r.inst, e0_solver=e0, mixed=0, odd_eig=0,
                                          coarse_solver=rte.RTE_COARSE_QUICK)
             U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
-            st, info = h.solve(U, opts=o64, raise_on_notconv=False)
+            st, info = h.solve(U, opts=o, raise_on_notconv=False)
             torch.cuda.synchronize()
             r.status, r.iters = st, info.iters
             r.done_at = time.perf_counter() - t0
+            if errors and r.rid >= warm:
+                r.U = U
             h.close()
-        return stats(reqs, time.perf_counter() - t0)
+            tick()
+        return stats(reqs, time.perf_counter() - t0), reqs
 
     numeric = [float(x) for x in rates if x != "half"]
+    n3 = sum(1 for i in insts[warm:] if i.dim == 3)
     out = {"workload": f"served form: Poisson arrivals (seed 4), {requests} measured requests per rate after "
-                       f"{warm} warm-up, drawn like the batched form (2D), rel. residual {tol:g}",
+                       f"{warm} warm-up, drawn like the batched form"
+                       + (f" plus {n3} 3D requests (32^3, 512 sphere triangles, g = 0.8)" if n3 else " (2D)")
+                       + f", rel. residual {tol:g}",
            "rates": {}}
     for x in rates:
         rate = float(x) if x != "half" else 0.5 * out["rates"][str(x_max(numeric))]["batched"]["solves_per_s"]
         log(f"[serve] rate {rate:.2f}/s: batched")
-        b = run_batched(rate)
+        b, done_b = run_batched(rate)
         log(f"[serve] rate {rate:.2f}/s: fp64 one at a time")
-        f = run_fp64_serial(rate)
+        f, done_f = run_fp64_serial(rate)
+        if errors:
+            b["rel_err_vs_tight_reference"], f["rel_err_vs_tight_reference"] = errors_vs_tight(done_b, done_f)
         key = str(x) if x != "half" else f"half capacity ({rate:.2f}/s)"
         out["rates"][key] = {"rate": rate, "batched": b, "fp64_one_at_a_time": f}
         log(f"[serve] rate {rate:.2f}/s: batched p50 {b['p50_s']:.2f} s p99 {b['p99_s']:.2f} s "
@@ -416,7 +459,8 @@ def serve_bench(args, torch, rte, inputs):
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
     rates = [x for x in args.rates.split(",") if x]
-    print(json.dumps(serving_runs(torch, rte, inputs, rates, args.requests, args.tol, log=log)))
+    print(json.dumps(serving_runs(torch, rte, inputs, rates, args.requests, args.tol, log=log,
+                                  fraction_3d=args.fraction_3d)))
 
 
 def rates_study(args, torch, rte, inputs):
@@ -445,10 +489,10 @@ def rates_study(args, torch, rte, inputs):
     out = {"study": "convergence rates rho, eta of (I - P_G)(I - P_1^l (E - K+))",
            "workload": "lattice stand-in 56x56 on (0,7)^2, sigma_s/sigma_a 10/0.01 and 0/1, c = 0.999",
            "isotropic": {}, "anisotropic": {}}
-    for lev in (1, 2, 3, 4):
+    for lev in ((1, 2, 3, 4) if args.rates_isotropic else ()):
         inst = inputs.lattice_standin(sphere_level=lev, g=0.0, n_even=0)
         out["isotropic"][4 ** (lev + 1)] = one(inst, [1])[1]
-    for g in (0.1, 0.5, 0.9):
+    for g in [float(x) for x in args.rates_g.split(",") if x]:
         for n_even in (0, 2, 4):
             # d_N = 15 makes a coarse system of 48735 unknowns: block-tridiagonal Cholesky
             inst = inputs.lattice_standin(sphere_level=2, g=g, n_even=n_even)
@@ -477,6 +521,10 @@ def main():
                     help="served form: Poisson arrival rates in requests/s ('half' = half the capacity "
                          "measured at the highest listed rate)")
     ap.add_argument("--requests", type=int, default=64, help="served form: measured requests per rate")
+    ap.add_argument("--rates-isotropic", type=int, default=1, help="rates study: include the g = 0 table (0/1)")
+    ap.add_argument("--rates-g", default="0.1,0.5,0.9", help="rates study: anisotropy factors g of the d_N x l tables")
+    ap.add_argument("--fraction-3d", type=float, default=0.0,
+                    help="served form: share of 3D requests (32^3 Kuhn tetrahedra, 512 sphere triangles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
@@ -503,14 +551,18 @@ def main():
     h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=1, odd_eig=0)
     t_assemble = time.perf_counter() - ta
     d = h.dims
-    # band layout of the E_0 factors: every shape that holds the band timed on the device,
-    # the fastest kept (setup, outside the timed solves)
+    # band layout of the E_0 factors (every shape that holds the band) and the tile map of each
+    # GEMM shape, timed on the device, the fastest kept (setup, outside the timed solves)
     ta = time.perf_counter()
     tune = h.autotune()
     t_tune = time.perf_counter() - ta
+    gemm_tune = tune.pop("gemm")
     print(f"[autotune] {t_tune:.2f} s: " + "; ".join(
         f"{k} default {v['default']} chosen {v['chosen']} timed " +
-        ", ".join(f"{hp}:{ms:.3f}ms" for hp, ms in v["timed"]) for k, v in tune.items()), file=sys.stderr, flush=True)
+        ", ".join(f"{hp}:{ms:.3f}ms" for hp, ms in v["timed"]) for k, v in tune.items()) + "; gemm " + ", ".join(
+        f"{g['kind']} {g['m']}x{g['n']}x{g['k']} map {g['map']}" +
+        ("" if g["from_cache"] else " (" + "/".join(f"{ms:.3f}" for ms in g["ms"]) + " ms)") for g in gemm_tune),
+        file=sys.stderr, flush=True)
     if args.only == "kernels":
         kernel_passes(h, inst, torch, rte)
         return
@@ -571,6 +623,8 @@ def main():
         "band_layout": {k: {"default": v["default"], "chosen": v["chosen"],
                             "timed_ms": {f"{hp[0]}x{hp[1]}": ms for hp, ms in v["timed"]}}
                         for k, v in tune.items()},
+        "gemm_tile_map": [{"kind": g["kind"], "mnk": [g["m"], g["n"], g["k"]], "map": g["map"],
+                           "timed_ms": g["ms"] if not g["from_cache"] else None} for g in gemm_tune],
         "t_autotune_s": t_tune,
         "roofline": dominant, "roofline_other": other,
         "scatter_gemm": {"bound": "mfma", "achieved": scatter_tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -644,6 +698,7 @@ def main():
     fs32 = sum(i.scatter_f32_flops for i in minfos)
     ns32 = sum(i.n_scatter_f32 for i in minfos)
     s32_tf = fs32 / ts32 / 1e12 if ts32 else 0.0
+    e0m_gbs = e0m_bytes / (t_e0m / max(n_e0m, 1)) / 1e9 if n_e0m else 0.0
     out["mixed"] = {
         "value": args.steps / mdt, "unit": "solves/s", "ms_per_step": 1e3 * mdt / args.steps,
         "speedup_vs_fp64": (args.steps / mdt) / value, "iters": [i.iters for i in minfos],
@@ -655,16 +710,14 @@ def main():
                               "frac": s32_tf / FP32_MFMA_PEAK_TFLOPS, "kernel": "gemm_mfma_kernel<float> (U S+)",
                               "avg_launch_ms": 1e3 * ts32 / max(ns32, 1), "launches": ns32,
                               "flops_per_launch": fs32 / max(ns32, 1), "traffic": measured_traffic("gemm_f32_scatter")},
-        # achieved and frac count the method's contraction, 2 n_R- (d n_S+)^2 per launch; the
-        # kernel multiplies by the hi/lo pair [G_hi; G_lo], which doubles K: its own MFMA rate
-        # is kernel_mfma_rate
+        # the method's contraction, 2 n_R- (d n_S+)^2 per launch (the operator's diagonal blocks
+        # are zero in the BF16 copy and applied by the A^T kernel; K is the full d n_S+)
         "gemm_bf16": {"bound": "mfma", "achieved": bf16_tf, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": bf16_tf / BF16_MFMA_PEAK_TFLOPS, "avg_launch_ms": 1e3 * tb / max(nb, 1),
                       "launches": nb, "flops_per_launch": fb / max(nb, 1),
-                      "kernel_mfma_rate_tflops": 2 * bf16_tf,
                       "traffic": measured_traffic("gemm_bf16_transport")},
-        "e0inv_fp32": {"bound": "hbm", "achieved": e0m_bytes / (t_e0m / max(n_e0m, 1)) / 1e9 if n_e0m else 0.0,
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "avg_launch_ms": 1e3 * t_e0m / max(n_e0m, 1),
+        "e0inv_fp32": {"bound": "hbm", "achieved": e0m_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": e0m_gbs / HBM_PEAK_GBS, "avg_launch_ms": 1e3 * t_e0m / max(n_e0m, 1),
                        "bytes_per_launch": e0m_bytes, "traffic": measured_traffic("band_solve_f32")},
     }
     # ---- the same workload with the larger correction space N+ = 4 (d_N = 15, 249615 coarse
@@ -727,7 +780,10 @@ def main():
                           "all_converged": r["batched"]["all_converged"],
                           "rel_err_vs_tight_reference": {k: v for k, v in
                                                          r["batched"]["rel_err_vs_tight_reference"].items()
-                                                         if k != "per_request"}}
+                                                         if k != "per_request"},
+                          "fp64_rel_err_vs_tight_reference": {k: v for k, v in
+                                                              r["fp64_one_at_a_time"]["rel_err_vs_tight_reference"].items()
+                                                              if k != "per_request"}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, infos[-1].iters, inst.l)
     print(json.dumps(out))

@@ -155,9 +155,10 @@ typedef struct rte_assemble_opts {
                                     (N+1)(N+2)/2 eigenpairs of (S-, M_S-)  (Sec. 5.1)        */
     int32_t e0_solver;           /* rte_e0_solver prepared at assembly (CG is always there)  */
     int32_t mixed;               /* 1: also prepare BF16/FP32 operator copies; 2: the same,  */
-                                 /*    and keep only the FP32 E_0 band factors (FP64 E_0    */
-                                 /*    solves then fail with RTE_E_ARG; halves the largest  */
-                                 /*    allocation for mixed-only use)                       */
+                                 /*    and keep only the FP32 E_0 band factors (FP64 banded */
+                                 /*    E_0 solves then fail with RTE_E_ARG; halves the      */
+                                 /*    largest allocation for mixed-only use); with the CG  */
+                                 /*    E_0 solver only the FP32 block values are built      */
     int32_t odd_eig;             /* 1 (default): eigendecomposition of (S-, M_S-) at assembly
                                     (every odd solver); 0: skipped when sigma_s / sigma_t is
                                     uniform, H = (M_S- - delta S-)^{-1} then comes from a dense
@@ -409,12 +410,24 @@ rte_status rte_batch_destroy(rte_batch* b);
  * fastest.  The results do not depend on the layout (padding entries are zero and every
  * product is summed in the same order).
  *
- * Choices are cached per process by (n_R+, band width, n_S+, element size): a handle whose
- * key is cached takes the cached shape without timing unless flags has RTE_TUNE_FORCE.
- * Both precisions present in the handle are tuned (the FP64 factors are absent after
- * assembly with mixed = 2).  While a candidate is timed the device holds one more copy of
- * the factors of that precision.  The handle must not be in use (no solve, no batch slot)
- * during the call.  Blocking.  RTE_E_ARG if the handle has no banded E_0 factors. */
+ * The tile map of every GEMM shape the handle launches (the scatter GEMM U S+ of Sec. 5.2 in
+ * FP64 and, with mixed precision, FP32; the condensed transport GEMM of Sec. 5.1 in FP64 and,
+ * with mixed precision, BF16) is tuned the same way: the four combinations of {XCD swizzle
+ * of the work-group ids on, off} x {row-major, column-major traversal of the output tile
+ * grid} are timed (three launches each, HIP events) and the fastest kept when it beats the
+ * default map 0 by 1%.  A map only reorders whole output tiles: results are bitwise the same.
+ * The maps are process-wide by (kind, M, N, K) and apply to every handle.
+ *
+ * Choices are cached per process by (n_R+, band width, n_S+, element size) and (GEMM kind,
+ * M, N, K), and in a text file read on the first call and appended to on each new choice:
+ * the path in the environment variable RTE_TUNE_CACHE, else $HOME/.cache/rte/tune.txt
+ * (lines for another device architecture or compute-unit count are ignored; an unwritable
+ * file only costs the timing in later processes).  A cached key takes the cached choice
+ * without timing unless flags has RTE_TUNE_FORCE.  Both precisions of banded factors present
+ * in the handle are tuned (the FP64 factors are absent after assembly with mixed = 2).
+ * While a candidate layout is timed the device holds one more copy of the factors of that
+ * precision.  The handle must not be in use (no solve, no batch slot) during the call, and
+ * no other handle may solve during it (the GEMM maps are shared).  Blocking. */
 #define RTE_TUNE_FORCE 1
 typedef struct rte_tune_report {
     int32_t n_cand[2];           /* candidates timed: [0] FP64 factors, [1] FP32 factors    */
@@ -422,7 +435,13 @@ typedef struct rte_tune_report {
     double ms[2][9];             /* average E_0^{-1} launch time of each candidate          */
     int32_t chosen_H[2], chosen_P[2];  /* the shape in place on return (0: precision absent) */
     int32_t default_H[2], default_P[2];/* the shape assembly chose                           */
-    int32_t from_cache[2];       /* 1: taken from the per-process cache, nothing timed      */
+    int32_t from_cache[2];       /* 1: taken from the cache, nothing timed                  */
+    int32_t n_gemm;              /* GEMM shapes tuned (at most 4), in the order above        */
+    int32_t gemm_kind[4];        /* 1 FP64, 2 FP32 (FP64 operand A), 4 BF16                  */
+    int32_t gemm_m[4], gemm_n[4], gemm_k[4];
+    double gemm_ms[4][4];        /* average launch time of maps 0..3 (0 if from the cache)   */
+    int32_t gemm_map[4];         /* the map chosen                                           */
+    int32_t gemm_from_cache[4];  /* 1: taken from the cache, nothing timed                  */
 } rte_tune_report;
 rte_status rte_autotune(rte_handle* h, int32_t flags, void* hip_stream, rte_tune_report* report);
 

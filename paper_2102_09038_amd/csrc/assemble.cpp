@@ -318,6 +318,8 @@ size_t Handle::footprint() const {
     return b;
 }
 
+namespace {
+
 // Phase timing of the assembly, printed to stderr when the environment sets RTE_TRACE
 // (each phase is closed with a stream synchronisation so that GPU work is attributed to it).
 struct PhaseTrace {
@@ -334,35 +336,105 @@ struct PhaseTrace {
     }
 };
 
-Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStream_t s) {
-    PhaseTrace trace(s);
-    // ------------------------------------------------------------------ validation (host.cpp)
-    const double cmax = validate_problem(D, o);
-    const int d = D->dim;
-    const int nRp = D->n_vert, nRm = D->n_cell;
+// A boundary facet: its vertices (d of them, sorted), the cell it closes and that cell's
+// vertex opposite it.
+struct Facet {
+    std::array<int, 3> v;
+    int cell, opp;
+};
 
-    auto H = std::make_unique<Handle>();
-    Handle& h = *H;
+// The state of one assembly, shared by its phases: the problem, the handle being filled and
+// the host-side intermediates that later phases read.  assemble() runs the phases in order.
+struct Asm {
+    const rte_problem_desc* D;
+    const rte_assemble_opts* o;
+    hipStream_t s;
+    Handle& h;
+    PhaseTrace trace;
+    std::unique_ptr<RocblasCtx> rb;            // from the eigen-bases on
+    double cmax = 0;                           // max sigma_s / sigma_t
+    int d = 0, nv = 0, nRp = 0, nRm = 0;       // dimension, vertices per cell, P1 / P0 unknowns
+    int nS = 0, nSm = 0, Q = 0;                // directions, odd unknowns per cell, points per direction
+    std::vector<int> upper;                    // sphere triangle of each upper-half direction
+    Vec pts, wts;                              // quadrature points (unit vectors) and weights
+    Vec MSinv, LkInv;                          // inverses of the blocks 2 T_k and of their Cholesky factors
+    Vec vol, Dc, mt, ms;                       // cell volumes, |K| grad(lambda), sigma_t |K|, sigma_s |K|
+    std::vector<int> rp, ci, diagpos;          // P1 pattern (CSR, sorted rows) and its diagonal entries
+    int nnz = 0;
+    std::vector<Facet> facets;                 // boundary facets
+    std::vector<std::array<double, 3>> ncls_dir;   // distinct boundary normals (up to sign)
+    std::vector<int> fcls;                     // normal class of each facet
+    Vec fmeas;                                 // facet measures
+    int nb = 0, nstiff = 0;                    // boundary normal classes, stiffness classes
+    std::vector<std::pair<int, int>> nm;       // (n, m) of each stiffness class, n <= m
+    Vec cls, Msv, M1v;                         // class values on the pattern; sigma_s and unit mass matrices
+    Vec omega, coefE0, coefE, diagE0;          // omega_k(nu_c); per-direction class coefficients; diag E_0
+    std::vector<int> vcp, vcc, vcl;            // vertex -> incident (cell, local vertex index)
+    Vec qv;                                    // the source l+ (nRp x nS)
+    bool odd_eig = false;                      // the odd eigenbasis is computed
+    Vec Wfull;                                 // host full odd eigenbasis (odd_eig only)
+    Vec Hh;                                    // host H = (M_S- - delta S-)^{-1} (uniform delta only)
+
+    Asm(const rte_problem_desc* D_, const rte_assemble_opts* o_, hipStream_t s_, Handle& h_)
+        : D(D_), o(o_), s(s_), h(h_), trace(s_) {}
+
+    // position of the entry (i, jv) in the pattern
+    int find(int i, int jv) const {
+        const int* b = ci.data() + rp[i];
+        const int* e = ci.data() + rp[i + 1];
+        return (int)(std::lower_bound(b, e, jv) - ci.data());
+    }
+
+    void init();
+    void sphere();
+    void quadrature();
+    void geometry();
+    void pattern();
+    void boundary();
+    void classes();
+    void incidence_and_source();
+    void upload();
+    void scattering();
+    void odd_basis();
+    void condensed_from_H();
+    void odd_eigenbasis();
+    void odd_inverse();
+    void even_basis();
+    void coarse();
+    void e0_data();
+    void reduced_precision();
+};
+
+// validation (host.cpp) and the handle's sizes
+void Asm::init() {
+    cmax = validate_problem(D, o);
+    d = D->dim;
+    nv = d + 1;
+    nRp = D->n_vert;
+    nRm = D->n_cell;
     h.stream = s;
     h.d = d; h.nRp = nRp; h.nRm = nRm; h.g = D->g; h.c = cmax;
     h.n_even = o->n_even; h.n_odd = o->n_odd;
     h.dNp = (o->n_even + 1) * (o->n_even + 2) / 2;
     h.dNm = (o->n_odd + 1) * (o->n_odd + 2) / 2;
+}
 
-    trace("validation");
-    // ------------------------------------------------------------------ sphere: upper half, antipodes
-    const int nt = D->n_stri;
-    const std::vector<int> upper = pair_sphere(D);
-    const int nS = (int)upper.size();
+// sphere: the upper half of the directions, paired with their antipodes (host.cpp)
+void Asm::sphere() {
+    upper = pair_sphere(D);
+    nS = (int)upper.size();
     h.nS = nS;
-    h.nSm = 3 * nS;
+    h.nSm = nSm = 3 * nS;
     if (h.dNm > h.nSm || h.dNp > nS) fail(RTE_E_ARG, "eigen-basis larger than the angular space");
+}
 
-    trace("sphere pairing");
-    // ------------------------------------------------------------------ angular quadrature and moments
+// angular quadrature: points and weights of every direction, the moments m_k and T_k, and the
+// inverses of the 3x3 blocks 2 T_k of M_S- and of their Cholesky factors
+void Asm::quadrature() {
     const Rule R = composite_rule(o->quad_level);
-    const int Q = (int)R.w.size();
-    Vec pts((size_t)nS * Q * 3), wts((size_t)nS * Q);
+    Q = (int)R.w.size();
+    pts.assign((size_t)nS * Q * 3, 0.0);
+    wts.assign((size_t)nS * Q, 0.0);
     h.h_m.assign(nS, 0.0);
     h.h_T.assign((size_t)nS * 9, 0.0);
     for (int k = 0; k < nS; ++k) {
@@ -387,18 +459,21 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         }
     }
     // inverse of the 3x3 blocks 2 T_k of M_S-
-    Vec MSinv((size_t)nS * 9), LkInv((size_t)nS * 9);
+    MSinv.assign((size_t)nS * 9, 0.0);
+    LkInv.assign((size_t)nS * 9, 0.0);
     for (int k = 0; k < nS; ++k) {
         double B[9], L[9];
         for (int e = 0; e < 9; ++e) B[e] = 2.0 * h.h_T[9 * k + e];
         if (!inv3(B, &MSinv[9 * k]) || !chol3(B, L)) fail(RTE_E_MESH, "singular odd mass block");
         inv_lower3(L, &LkInv[9 * k]);
     }
+}
 
-    trace("angular quadrature");
-    // ------------------------------------------------------------------ spatial geometry
-    const int nv = d + 1;
-    Vec vol(nRm), Dc((size_t)nRm * nv * d);
+// spatial geometry: cell volumes, scaled barycentric gradients, the sigma_t and sigma_s cell
+// masses, and whether sigma_s / sigma_t is uniform
+void Asm::geometry() {
+    vol.assign(nRm, 0.0);
+    Dc.assign((size_t)nRm * nv * d, 0.0);
     for (int j = 0; j < nRm; ++j) {
         const int* cj = D->cell + nv * j;
         double J[9], Ji[9];
@@ -419,7 +494,8 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             Dc[((size_t)j * nv) * d + n] = -v * s0;
         }
     }
-    Vec mt(nRm), ms(nRm);
+    mt.assign(nRm, 0.0);
+    ms.assign(nRm, 0.0);
     for (int j = 0; j < nRm; ++j) { mt[j] = D->sigma_t[j] * vol[j]; ms[j] = D->sigma_s[j] * vol[j]; }
     // the ratio sigma_s / sigma_t counts as uniform when every cell's ratio agrees to a few
     // ulps (sigma_s = 0.99 sigma_t rounds differently cell by cell); the single inverse then
@@ -434,24 +510,19 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         h.delta0 = sum / nRm;
         if (hi - lo > 1e-13 * std::max(hi, 1e-300)) h.uniform_delta = false;
     }
+}
 
-    trace("spatial geometry");
-    // ------------------------------------------------------------------ P1 pattern
-    std::vector<int> rp, ci;
+// the P1 pattern (host.cpp) and its diagonal entries
+void Asm::pattern() {
     p1_pattern(D, rp, ci);
-    const int nnz = rp[nRp];
+    nnz = rp[nRp];
     h.nnz = nnz;
-    auto find = [&](int i, int jv) {
-        const int* b = ci.data() + rp[i];
-        const int* e = ci.data() + rp[i + 1];
-        return (int)(std::lower_bound(b, e, jv) - ci.data());
-    };
-    std::vector<int> diagpos(nRp);
+    diagpos.assign(nRp, 0);
     for (int i = 0; i < nRp; ++i) diagpos[i] = find(i, i);
+}
 
-    trace("P1 pattern");
-    // ------------------------------------------------------------------ boundary facets
-    struct Facet { std::array<int, 3> v; int cell, opp; };
+// boundary facets, their measures and their normal classes
+void Asm::boundary() {
     std::map<std::array<int, 3>, std::pair<int, int>> owner;   // sorted verts -> (count, cell*8+opp)
     for (int j = 0; j < nRm; ++j)
         for (int o_ = 0; o_ < nv; ++o_) {
@@ -464,13 +535,11 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             if (it == owner.end()) owner[f] = {1, j * 8 + o_};
             else it->second.first++;
         }
-    std::vector<Facet> facets;
     for (auto& kv : owner)
         if (kv.second.first == 1) facets.push_back({kv.first, kv.second.second / 8, kv.second.second % 8});
     // normals, measures, normal classes (normals equal up to sign share omega)
-    std::vector<std::array<double, 3>> ncls_dir;
-    std::vector<int> fcls(facets.size());
-    Vec fmeas(facets.size());
+    fcls.assign(facets.size(), 0);
+    fmeas.assign(facets.size(), 0.0);
     for (size_t f = 0; f < facets.size(); ++f) {
         const int j = facets[f].cell, op = facets[f].opp;
         double g3[3] = {0, 0, 0}, gn = 0;
@@ -491,21 +560,24 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         if (cid < 0) { cid = (int)ncls_dir.size(); ncls_dir.push_back(nu); }
         fcls[f] = cid;
     }
-    const int nb = (int)ncls_dir.size();
-    const int nstiff = d * (d + 1) / 2;
+    nb = (int)ncls_dir.size();
+    nstiff = d * (d + 1) / 2;
     h.ncls_stiff = nstiff;
     h.nbcls = nb;
     h.ncls = nstiff + 1 + nb;
     if (h.ncls > kMaxClasses)
         fail(RTE_E_ARG, "boundary has too many distinct facet normals (" + std::to_string(nb) +
                             "); at most " + std::to_string(kMaxClasses - nstiff - 1) + " are supported");
+}
 
-    trace("boundary facets");
-    // ------------------------------------------------------------------ value classes of the pattern
+// value classes of the pattern, omega_k of each boundary normal class, and the per-direction
+// class coefficients of E_0 and of M+ + R with the diagonal of every E_0 block
+void Asm::classes() {
     // stiffness classes (n <= m): sum_j D_n(j,a) D_m(j,b) / mt_j (+ the (m,n) term when n < m)
     const int ncls = h.ncls;
-    Vec cls((size_t)ncls * nnz, 0.0), Msv(nnz, 0.0), M1v(nnz, 0.0);
-    std::vector<std::pair<int, int>> nm;
+    cls.assign((size_t)ncls * nnz, 0.0);
+    Msv.assign(nnz, 0.0);
+    M1v.assign(nnz, 0.0);
     for (int n = 0; n < d; ++n) nm.push_back({n, n});
     for (int n = 0; n < d; ++n)
         for (int m = n + 1; m < d; ++m) nm.push_back({n, m});
@@ -539,7 +611,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             }
     }
     // omega_k(nu_c) = 2 sum_p w_p |s_p . nu_c|
-    Vec omega((size_t)nb * nS, 0.0);
+    omega.assign((size_t)nb * nS, 0.0);
     for (int c = 0; c < nb; ++c)
         for (int k = 0; k < nS; ++k) {
             double acc = 0;
@@ -552,7 +624,9 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         }
     // per-direction coefficients: E_0 block k and (M+ + R) block k
     const double alpha = 2.0 / (1.0 - cmax * D->g);
-    Vec coefE0((size_t)nS * ncls, 0.0), coefE((size_t)nS * ncls, 0.0), diagE0((size_t)nRp * nS);
+    coefE0.assign((size_t)nS * ncls, 0.0);
+    coefE.assign((size_t)nS * ncls, 0.0);
+    diagE0.assign((size_t)nRp * nS, 0.0);
     for (int k = 0; k < nS; ++k) {
         for (int c = 0; c < nstiff; ++c)
             coefE0[(size_t)k * ncls + c] = alpha * h.h_T[9 * k + 3 * nm[c].first + nm[c].second];
@@ -573,8 +647,13 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             }
         });
     }
-    // vertex -> incident cells
-    std::vector<int> vcp(nRp + 1, 0), vcc((size_t)nRm * nv), vcl((size_t)nRm * nv);
+}
+
+// vertex -> incident cells, and the source l+ with its norm
+void Asm::incidence_and_source() {
+    vcp.assign(nRp + 1, 0);
+    vcc.assign((size_t)nRm * nv, 0);
+    vcl.assign((size_t)nRm * nv, 0);
     for (int j = 0; j < nRm; ++j)
         for (int a = 0; a < nv; ++a) vcp[D->cell[nv * j + a] + 1]++;
     for (int i = 0; i < nRp; ++i) vcp[i + 1] += vcp[i];
@@ -591,7 +670,8 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     Vec Mq(nRp, 0.0);
     for (int i = 0; i < nRp; ++i)
         for (int e = rp[i]; e < rp[i + 1]; ++e) Mq[i] += M1v[e] * D->q_nodal[ci[e]];
-    Vec qv((size_t)nRp * nS), qk2(nS);
+    qv.assign((size_t)nRp * nS, 0.0);
+    Vec qk2(nS);
     parallel_for(nS, [&](int k) {
         double a = 0;
         for (int i = 0; i < nRp; ++i) {
@@ -604,9 +684,10 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     double qn2 = 0;
     for (int k = 0; k < nS; ++k) qn2 += qk2[k];   // fixed order
     h.qnorm = std::sqrt(qn2);
+}
 
-    trace("value classes");
-    // ------------------------------------------------------------------ uploads
+// uploads of the mesh, pattern and class data, and the sliced-ELL layout of the E_0 blocks
+void Asm::upload() {
     h.m.upload(h.h_m, s);
     h.T.upload(h.h_T, s);
     h.MSinv.upload(MSinv, s);
@@ -620,6 +701,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         std::vector<int> sptr, ecol, epos;
         h.ell_len = sliced_ell(nRp, rp, ci, &sptr, &ecol, &epos);
         h.ell_nslice = (nRp + 63) / 64;
+        for (int sl = 0; sl < h.ell_nslice; ++sl) h.ell_wmax = std::max(h.ell_wmax, sptr[sl + 1] - sptr[sl]);
         h.ell_sptr.upload(sptr, s);
         h.ell_col.upload(ecol, s);
         h.ell_e.upload(epos, s);
@@ -651,9 +733,10 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         h.bnd_row.upload(br, s);
     }
     h.q.upload(qv, s);
+}
 
-    trace("uploads");
-    // ------------------------------------------------------------------ scattering matrices (GPU)
+// scattering matrices S+ and S- (quadrature of the HG kernel on the GPU)
+void Asm::scattering() {
     {
         DBuf<double> dp, dw;
         dp.upload(pts, s);
@@ -665,184 +748,195 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     }
     h.h_Sp = h.Sp.download(s);
     h.h_Sm = h.Sm.download(s);
+}
 
-    trace("scattering matrices");
-    // ------------------------------------------------------------------ eigen-bases (rocSOLVER)
-    RocblasCtx rb(s);
-    const int nSm = h.nSm;
+// eigen-bases (rocSOLVER), odd part
+void Asm::odd_basis() {
     // The odd eigendecomposition of (S-, M_S-) serves the PCG preconditioner (its top pairs),
     // the exact odd inverse for a per-cell ratio (all pairs) and the transport term of E_c.
     // With a uniform ratio delta and opts->odd_eig == 0 it is skipped: the exact and condensed
     // forms only need H = (M_S- - delta S-)^{-1}, which a dense Cholesky inverse on the GPU gives
     // directly, and the E_c term is (A_n W+)^T H (A_m W+).
-    const bool odd_eig = o->odd_eig != 0 || !h.uniform_delta;
+    odd_eig = o->odd_eig != 0 || !h.uniform_delta;
     h.have_odd_eig = odd_eig;
-    Vec Wfull;                    // host full odd eigenbasis (odd_eig only)
-    Vec Hh;                       // host H (uniform delta only)
-    // condensed transport matrix G from H: block (n, n') = A_n^T H A_n', i.e.
-    // G[(n,k),(n',k')] = sum_{m,m'} 2 T_k(n,m) H[3k+m, 3k'+m'] 2 T_k'(n',m')
-    auto condensed_from_H = [&]() {
-        const int dn = d * nS;
-        Vec G((size_t)dn * dn);
-        for (int k2 = 0; k2 < nS; ++k2)
-            for (int k1 = 0; k1 < nS; ++k1) {
-                double Hb[9];
-                for (int m = 0; m < 3; ++m)
-                    for (int m2 = 0; m2 < 3; ++m2) Hb[3 * m + m2] = Hh[(3 * k1 + m) + (size_t)nSm * (3 * k2 + m2)];
-                for (int n = 0; n < d; ++n)
-                    for (int n2 = 0; n2 < d; ++n2) {
-                        double v = 0;
-                        for (int m = 0; m < 3; ++m)
-                            for (int m2 = 0; m2 < 3; ++m2)
-                                v += 2.0 * h.h_T[9 * k1 + 3 * n + m] * Hb[3 * m + m2] * 2.0 * h.h_T[9 * k2 + 3 * n2 + m2];
-                        G[(n * nS + k1) + (size_t)dn * (n2 * nS + k2)] = v;
-                    }
-            }
-        h.Gc.upload(G, s);
-        // its diagonal d x d blocks G_kk(n, m) as coefficients of the stiffness classes (n <= m;
-        // the class of n < m holds both orders): the mixed-precision path applies them exactly
-        Vec cd((size_t)nS * nstiff);
-        for (int k2 = 0; k2 < nS; ++k2)
-            for (int c = 0; c < nstiff; ++c)
-                cd[(size_t)k2 * nstiff + c] = G[(nm[c].first * nS + k2) + (size_t)dn * (nm[c].second * nS + k2)];
-        h.coefD.upload(cd, s);
-    };
-    if (odd_eig) {   // odd: S- W = M_S- W Lambda; with M_S- = L L^T blockwise: (L^-1 S- L^-T) V = V Lambda, W = L^-T V
-        Vec A((size_t)nSm * nSm);
-        for (int kb = 0; kb < nS; ++kb)
-            for (int kc = 0; kc < nS; ++kc) {
-                const double* Li = &LkInv[9 * kb];
-                const double* Lj = &LkInv[9 * kc];
-                double blk[9], tmp[9];
-                for (int n = 0; n < 3; ++n)
-                    for (int m = 0; m < 3; ++m) {
-                        const double a1 = h.h_Sm[(3 * kb + n) + (size_t)nSm * (3 * kc + m)];
-                        const double a2 = h.h_Sm[(3 * kc + m) + (size_t)nSm * (3 * kb + n)];
-                        blk[3 * n + m] = 0.5 * (a1 + a2);
-                    }
-                for (int n = 0; n < 3; ++n)          // tmp = Li * blk
-                    for (int m = 0; m < 3; ++m) {
-                        double v = 0;
-                        for (int e = 0; e < 3; ++e) v += Li[3 * n + e] * blk[3 * e + m];
-                        tmp[3 * n + m] = v;
-                    }
-                for (int n = 0; n < 3; ++n)          // A = tmp * Lj^T
-                    for (int m = 0; m < 3; ++m) {
-                        double v = 0;
-                        for (int e = 0; e < 3; ++e) v += tmp[3 * n + e] * Lj[3 * m + e];
-                        A[(3 * kb + n) + (size_t)nSm * (3 * kc + m)] = v;
-                    }
-            }
-        Vec lam;
-        syevd(rb, s, nSm, A, lam);
-        // W = L^-T V, reorder to non-increasing eigenvalues
-        Wfull.assign((size_t)nSm * nSm, 0.0);
-        h.h_lamm_full.resize(nSm);
-        for (int c = 0; c < nSm; ++c) {
-            const int src = nSm - 1 - c;
-            h.h_lamm_full[c] = lam[src];
-            for (int kb = 0; kb < nS; ++kb) {
-                const double* Li = &LkInv[9 * kb];
-                for (int n = 0; n < 3; ++n) {
-                    double v = 0;     // (L^-T)(n, e) = Li(e, n)
-                    for (int e = 0; e < 3; ++e) v += Li[3 * e + n] * A[(3 * kb + e) + (size_t)nSm * src];
-                    Wfull[(3 * kb + n) + (size_t)nSm * c] = v;
+    if (odd_eig) odd_eigenbasis();
+    else odd_inverse();
+}
+
+// condensed transport matrix G from H: block (n, n') = A_n^T H A_n', i.e.
+// G[(n,k),(n',k')] = sum_{m,m'} 2 T_k(n,m) H[3k+m, 3k'+m'] 2 T_k'(n',m'), and its diagonal
+// blocks as stiffness-class coefficients
+void Asm::condensed_from_H() {
+    const int dn = d * nS;
+    Vec G((size_t)dn * dn);
+    for (int k2 = 0; k2 < nS; ++k2)
+        for (int k1 = 0; k1 < nS; ++k1) {
+            double Hb[9];
+            for (int m = 0; m < 3; ++m)
+                for (int m2 = 0; m2 < 3; ++m2) Hb[3 * m + m2] = Hh[(3 * k1 + m) + (size_t)nSm * (3 * k2 + m2)];
+            for (int n = 0; n < d; ++n)
+                for (int n2 = 0; n2 < d; ++n2) {
+                    double v = 0;
+                    for (int m = 0; m < 3; ++m)
+                        for (int m2 = 0; m2 < 3; ++m2)
+                            v += 2.0 * h.h_T[9 * k1 + 3 * n + m] * Hb[3 * m + m2] * 2.0 * h.h_T[9 * k2 + 3 * n2 + m2];
+                    G[(n * nS + k1) + (size_t)dn * (n2 * nS + k2)] = v;
                 }
+        }
+    h.Gc.upload(G, s);
+    // its diagonal d x d blocks G_kk(n, m) as coefficients of the stiffness classes (n <= m;
+    // the class of n < m holds both orders): the mixed-precision path applies them exactly
+    Vec cd((size_t)nS * nstiff);
+    for (int k2 = 0; k2 < nS; ++k2)
+        for (int c = 0; c < nstiff; ++c)
+            cd[(size_t)k2 * nstiff + c] = G[(nm[c].first * nS + k2) + (size_t)dn * (nm[c].second * nS + k2)];
+    h.coefD.upload(cd, s);
+}
+
+// odd: S- W = M_S- W Lambda; with M_S- = L L^T blockwise: (L^-1 S- L^-T) V = V Lambda, W = L^-T V
+void Asm::odd_eigenbasis() {
+    Vec A((size_t)nSm * nSm);
+    for (int kb = 0; kb < nS; ++kb)
+        for (int kc = 0; kc < nS; ++kc) {
+            const double* Li = &LkInv[9 * kb];
+            const double* Lj = &LkInv[9 * kc];
+            double blk[9], tmp[9];
+            for (int n = 0; n < 3; ++n)
+                for (int m = 0; m < 3; ++m) {
+                    const double a1 = h.h_Sm[(3 * kb + n) + (size_t)nSm * (3 * kc + m)];
+                    const double a2 = h.h_Sm[(3 * kc + m) + (size_t)nSm * (3 * kb + n)];
+                    blk[3 * n + m] = 0.5 * (a1 + a2);
+                }
+            for (int n = 0; n < 3; ++n)          // tmp = Li * blk
+                for (int m = 0; m < 3; ++m) {
+                    double v = 0;
+                    for (int e = 0; e < 3; ++e) v += Li[3 * n + e] * blk[3 * e + m];
+                    tmp[3 * n + m] = v;
+                }
+            for (int n = 0; n < 3; ++n)          // A = tmp * Lj^T
+                for (int m = 0; m < 3; ++m) {
+                    double v = 0;
+                    for (int e = 0; e < 3; ++e) v += tmp[3 * n + e] * Lj[3 * m + e];
+                    A[(3 * kb + n) + (size_t)nSm * (3 * kc + m)] = v;
+                }
+        }
+    Vec lam;
+    syevd(*rb, s, nSm, A, lam);
+    // W = L^-T V, reorder to non-increasing eigenvalues
+    Wfull.assign((size_t)nSm * nSm, 0.0);
+    h.h_lamm_full.resize(nSm);
+    for (int c = 0; c < nSm; ++c) {
+        const int src = nSm - 1 - c;
+        h.h_lamm_full[c] = lam[src];
+        for (int kb = 0; kb < nS; ++kb) {
+            const double* Li = &LkInv[9 * kb];
+            for (int n = 0; n < 3; ++n) {
+                double v = 0;     // (L^-T)(n, e) = Li(e, n)
+                for (int e = 0; e < 3; ++e) v += Li[3 * e + n] * A[(3 * kb + e) + (size_t)nSm * src];
+                Wfull[(3 * kb + n) + (size_t)nSm * c] = v;
             }
         }
-        Vec Wm((size_t)nSm * h.dNm), lm(h.dNm);
-        for (int c = 0; c < h.dNm; ++c) {
-            lm[c] = h.h_lamm_full[c];
-            std::copy(Wfull.begin() + (size_t)nSm * c, Wfull.begin() + (size_t)nSm * (c + 1), Wm.begin() + (size_t)nSm * c);
-        }
-        h.Wm.upload(Wm, s);
-        h.lamm.upload(lm, s);
-        // exact odd inverse: full basis (row-major K x N views for the GEMM) and, when the
-        // ratio sigma_s / sigma_t is uniform, H = (M_S- - delta S-)^{-1} = W diag(1/(1-delta lam)) W^T
-        {
-            Vec WT((size_t)nSm * nSm), Wrm((size_t)nSm * nSm);
-            for (int r = 0; r < nSm; ++r)
-                for (int c = 0; c < nSm; ++c) {
-                    Wrm[(size_t)r * nSm + c] = Wfull[r + (size_t)nSm * c];   // B(k=r, n=c) = W[r, c]
-                    WT[(size_t)c * nSm + r] = Wfull[r + (size_t)nSm * c];    // B(k=c, n=r) = W[r, c]
-                }
-            h.Wfull.upload(Wrm, s);
-            h.WfullT.upload(WT, s);
-            h.lam_full.upload(h.h_lamm_full, s);
-            if (h.uniform_delta) {
-                Vec Wsc(Wfull);
-                for (int c = 0; c < nSm; ++c) {
-                    const double f = 1.0 / (1.0 - h.delta0 * h.h_lamm_full[c]);
-                    for (int r = 0; r < nSm; ++r) Wsc[r + (size_t)nSm * c] *= f;
-                }
-                // H = Wsc W^T : as GEMM with A = Wsc (col-major), B = W^T (row-major K x N: B(k=c, n=r) = W[r,c])
-                DBuf<double> dWsc;
-                dWsc.upload(Wsc, s);
-                h.Hodd.alloc((size_t)nSm * nSm);
-                k::gemm_f64(nSm, nSm, nSm, 1.0, dWsc.p, nSm, h.WfullT.p, nSm, 0.0, h.Hodd.p, nSm, s);
-                RTE_HIP(hipStreamSynchronize(s));
-                Hh = h.Hodd.download(s);
-                condensed_from_H();
-            }
-            h.have_exact = true;
-        }
-    } else {
-        // H = (M_S- - delta S-)^{-1}: M_S- is block diagonal (2 T_k), S- symmetrised as above;
-        // dense lower band of width nSm - 1, Cholesky inverse on the GPU
-        const size_t w = (size_t)nSm;
-        Vec band((size_t)nSm * w, 0.0);
+    }
+    Vec Wm((size_t)nSm * h.dNm), lm(h.dNm);
+    for (int c = 0; c < h.dNm; ++c) {
+        lm[c] = h.h_lamm_full[c];
+        std::copy(Wfull.begin() + (size_t)nSm * c, Wfull.begin() + (size_t)nSm * (c + 1), Wm.begin() + (size_t)nSm * c);
+    }
+    h.Wm.upload(Wm, s);
+    h.lamm.upload(lm, s);
+    // exact odd inverse: full basis (row-major K x N views for the GEMM) and, when the
+    // ratio sigma_s / sigma_t is uniform, H = (M_S- - delta S-)^{-1} = W diag(1/(1-delta lam)) W^T
+    {
+        Vec WT((size_t)nSm * nSm), Wrm((size_t)nSm * nSm);
         for (int r = 0; r < nSm; ++r)
-            for (int c = 0; c <= r; ++c) {
-                const double sm = 0.5 * (h.h_Sm[r + (size_t)nSm * c] + h.h_Sm[c + (size_t)nSm * r]);
-                double v = -h.delta0 * sm;
-                if (r / 3 == c / 3) v += 2.0 * h.h_T[9 * (r / 3) + 3 * (r % 3) + (c % 3)];
-                band[(size_t)r * w + (nSm - 1) + c - r] = v;
+            for (int c = 0; c < nSm; ++c) {
+                Wrm[(size_t)r * nSm + c] = Wfull[r + (size_t)nSm * c];   // B(k=r, n=c) = W[r, c]
+                WT[(size_t)c * nSm + r] = Wfull[r + (size_t)nSm * c];    // B(k=c, n=r) = W[r, c]
             }
-        dense_spd_inverse(rb, s, band, nSm, nSm - 1, h.Hodd, "M_S- - delta S-");
-        Hh = h.Hodd.download(s);
-        condensed_from_H();
+        h.Wfull.upload(Wrm, s);
+        h.WfullT.upload(WT, s);
+        h.lam_full.upload(h.h_lamm_full, s);
+        if (h.uniform_delta) {
+            Vec Wsc(Wfull);
+            for (int c = 0; c < nSm; ++c) {
+                const double f = 1.0 / (1.0 - h.delta0 * h.h_lamm_full[c]);
+                for (int r = 0; r < nSm; ++r) Wsc[r + (size_t)nSm * c] *= f;
+            }
+            // H = Wsc W^T : as GEMM with A = Wsc (col-major), B = W^T (row-major K x N: B(k=c, n=r) = W[r,c])
+            DBuf<double> dWsc;
+            dWsc.upload(Wsc, s);
+            h.Hodd.alloc((size_t)nSm * nSm);
+            k::gemm_f64(nSm, nSm, nSm, 1.0, dWsc.p, nSm, h.WfullT.p, nSm, 0.0, h.Hodd.p, nSm, s);
+            RTE_HIP(hipStreamSynchronize(s));
+            Hh = h.Hodd.download(s);
+            condensed_from_H();
+        }
         h.have_exact = true;
     }
-    {
-        // ---- coarse needs P_n = W_full^T (A_n W+) later; keep Wfull on the host until then
-        h.h_Sm.clear();
-        h.h_Sm.shrink_to_fit();
-        // even
-        Vec Ap((size_t)nS * nS);
-        Vec isq(nS);
-        for (int k = 0; k < nS; ++k) isq[k] = 1.0 / std::sqrt(h.h_m[k]);
-        for (int a = 0; a < nS; ++a)
-            for (int b = 0; b < nS; ++b)
-                Ap[a + (size_t)nS * b] =
-                    0.5 * (h.h_Sp[a + (size_t)nS * b] + h.h_Sp[b + (size_t)nS * a]) * isq[a] * isq[b];
-        h.h_lamp.resize(h.dNp);
-        h.h_Wp.resize((size_t)nS * h.dNp);
-        bool done = false;
-        if (h.dNp == 1) {
-            Vec v0(nS), v;
-            double nv = 0.0;
-            for (int k = 0; k < nS; ++k) { v0[k] = std::sqrt(h.h_m[k]); nv += h.h_m[k]; }
-            for (int k = 0; k < nS; ++k) v0[k] /= std::sqrt(nv);
-            double lam = 0.0;
-            if (top_eigenpair(rb, s, nS, Ap, v0, v, lam)) {
-                h.h_lamp[0] = lam;
-                for (int k = 0; k < nS; ++k) h.h_Wp[k] = v[k] * isq[k];
-                done = true;
-            }
-        }
-        if (!done) {
-            Vec lp;
-            syevd(rb, s, nS, Ap, lp);
-            for (int c = 0; c < h.dNp; ++c) {
-                const int src = nS - 1 - c;
-                h.h_lamp[c] = lp[src];
-                for (int k = 0; k < nS; ++k) h.h_Wp[k + (size_t)nS * c] = Ap[k + (size_t)nS * src] * isq[k];
-            }
-        }
-        h.Wp.upload(h.h_Wp, s);
+}
 
-        trace("eigen-bases");
-        // ------------------------------------------------------------------ coarse matrix E_c
+// H = (M_S- - delta S-)^{-1}: M_S- is block diagonal (2 T_k), S- symmetrised as above;
+// dense lower band of width nSm - 1, Cholesky inverse on the GPU
+void Asm::odd_inverse() {
+    const size_t w = (size_t)nSm;
+    Vec band((size_t)nSm * w, 0.0);
+    for (int r = 0; r < nSm; ++r)
+        for (int c = 0; c <= r; ++c) {
+            const double sm = 0.5 * (h.h_Sm[r + (size_t)nSm * c] + h.h_Sm[c + (size_t)nSm * r]);
+            double v = -h.delta0 * sm;
+            if (r / 3 == c / 3) v += 2.0 * h.h_T[9 * (r / 3) + 3 * (r % 3) + (c % 3)];
+            band[(size_t)r * w + (nSm - 1) + c - r] = v;
+        }
+    dense_spd_inverse(*rb, s, band, nSm, nSm - 1, h.Hodd, "M_S- - delta S-");
+    Hh = h.Hodd.download(s);
+    condensed_from_H();
+    h.have_exact = true;
+}
+
+// eigen-bases, even part: the top dN+ eigenpairs of (S+, M+) (Sec. 5.4)
+void Asm::even_basis() {
+    // ---- coarse needs P_n = W_full^T (A_n W+) later; keep Wfull on the host until then
+    h.h_Sm.clear();
+    h.h_Sm.shrink_to_fit();
+    // even
+    Vec Ap((size_t)nS * nS);
+    Vec isq(nS);
+    for (int k = 0; k < nS; ++k) isq[k] = 1.0 / std::sqrt(h.h_m[k]);
+    for (int a = 0; a < nS; ++a)
+        for (int b = 0; b < nS; ++b)
+            Ap[a + (size_t)nS * b] =
+                0.5 * (h.h_Sp[a + (size_t)nS * b] + h.h_Sp[b + (size_t)nS * a]) * isq[a] * isq[b];
+    h.h_lamp.resize(h.dNp);
+    h.h_Wp.resize((size_t)nS * h.dNp);
+    bool done = false;
+    if (h.dNp == 1) {
+        Vec v0(nS), v;
+        double msum = 0.0;
+        for (int k = 0; k < nS; ++k) { v0[k] = std::sqrt(h.h_m[k]); msum += h.h_m[k]; }
+        for (int k = 0; k < nS; ++k) v0[k] /= std::sqrt(msum);
+        double lam = 0.0;
+        if (top_eigenpair(*rb, s, nS, Ap, v0, v, lam)) {
+            h.h_lamp[0] = lam;
+            for (int k = 0; k < nS; ++k) h.h_Wp[k] = v[k] * isq[k];
+            done = true;
+        }
+    }
+    if (!done) {
+        Vec lp;
+        syevd(*rb, s, nS, Ap, lp);
+        for (int c = 0; c < h.dNp; ++c) {
+            const int src = nS - 1 - c;
+            h.h_lamp[c] = lp[src];
+            for (int k = 0; k < nS; ++k) h.h_Wp[k + (size_t)nS * c] = Ap[k + (size_t)nS * src] * isq[k];
+        }
+    }
+    h.Wp.upload(h.h_Wp, s);
+}
+
+// the coarse matrix E_c = W^T (E - K+) W in band form, factored (Sec. 5.4), with the
+// bandwidth-reducing order of the P1 unknowns that the banded E_0 factors share
+void Asm::coarse() {
+    {
         const int dN = h.dNp;
         // (A_n W+)[(k,m), a] = 2 T_k(n, m) W+[k, a]  [nSm x dN], and with the odd eigenbasis
         // P_n = W_full^T (A_n W+)
@@ -977,7 +1071,7 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         if (how == RTE_COARSE_AUTO) how = inv_fits ? RTE_COARSE_INVERSE : band_fits ? RTE_COARSE_BAND : RTE_COARSE_BLOCK;
         if (how == RTE_COARSE_INVERSE) {
             if (!inv_fits) fail(RTE_E_ARG, "the explicit coarse inverse exceeds its memory budget");
-            dense_spd_inverse(rb, s, band, nc, bw, h.Ecinv, "the coarse matrix E_c");
+            dense_spd_inverse(*rb, s, band, nc, bw, h.Ecinv, "the coarse matrix E_c");
         } else if (how == RTE_COARSE_BAND) {
             if (!band_fits) fail(RTE_E_ARG, "coarse band too wide for the band solve");
             if (k::band_factor_fits(bw)) {
@@ -1007,9 +1101,11 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
     }
     h.h_Sp.clear();
     h.h_Sp.shrink_to_fit();
+}
 
-    trace("coarse matrix");
-    // ------------------------------------------------------------------ banded E_0 factors
+// E_0 data (Sec. 5.3): the banded Cholesky factors of every direction block, or the explicit
+// block values of the CG
+void Asm::e0_data() {
     if (o->e0_solver == RTE_E0_BANDED) {
         if (k::band_groups(h.sbw, 2) == 0 || k::band_groups(h.sbw, 4) == 0)
             fail(RTE_E_ARG, "E_0 band too wide for the band solve");
@@ -1026,14 +1122,17 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
         if (hb) fail(RTE_E_ARG, "an E_0 block lost positive definiteness in the band factorisation");
         h.have_e0_banded = true;
     } else if (o->e0_solver == RTE_E0_CG) {
-        sv::cg_prepare(&h, false, s);
+        // the explicit block values of the CG: FP64 unless only the mixed form is wanted
+        // (mixed = 2; an FP64 CG then builds them on first use), FP32 with mixed != 0
+        if (o->mixed != 2) sv::cg_prepare(&h, false, s);
         if (o->mixed) sv::cg_prepare(&h, true, s);
     } else {
         fail(RTE_E_ARG, "unknown e0_solver");
     }
+}
 
-    trace("E_0 band factors");
-    // ------------------------------------------------------------------ reduced-precision copies
+// reduced-precision copies of the mixed-precision path, and the handle's small buffers
+void Asm::reduced_precision() {
     if (o->mixed) {
         // FP32 scattering matrices for the FP32 MFMA scatter GEMMs of the preconditioner
         h.Sp_f.alloc(h.Sp.n);
@@ -1062,12 +1161,46 @@ Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStrea
             }
         }
         h.have_mixed = true;
-    }
-    trace("reduced-precision copies");
-    h.red.alloc(k::kRedBlocks);
+    }    h.red.alloc(k::kRedBlocks);
     h.scal.alloc(64);
     RTE_HIP(hipHostMalloc(reinterpret_cast<void**>(&h.pinned), 64 * sizeof(double), hipHostMallocDefault));
     RTE_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+Handle* assemble(const rte_problem_desc* D, const rte_assemble_opts* o, hipStream_t s) {
+    auto H = std::make_unique<Handle>();
+    Asm a(D, o, s, *H);
+    a.init();
+    a.trace("validation");
+    a.sphere();
+    a.trace("sphere pairing");
+    a.quadrature();
+    a.trace("angular quadrature");
+    a.geometry();
+    a.trace("spatial geometry");
+    a.pattern();
+    a.trace("P1 pattern");
+    a.boundary();
+    a.trace("boundary facets");
+    a.classes();
+    a.incidence_and_source();
+    a.trace("value classes");
+    a.upload();
+    a.trace("uploads");
+    a.scattering();
+    a.trace("scattering matrices");
+    a.rb = std::make_unique<RocblasCtx>(s);
+    a.odd_basis();
+    a.even_basis();
+    a.trace("eigen-bases");
+    a.coarse();
+    a.trace("coarse matrix");
+    a.e0_data();
+    a.trace("E_0 band factors");
+    a.reduced_precision();
+    a.trace("reduced-precision copies");
     return H.release();
 }
 

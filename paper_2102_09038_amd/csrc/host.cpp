@@ -280,7 +280,8 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
     b += ell * 8 + ((size_t)nRp / 64 + 2) * 4;
     if (o->e0_solver == RTE_E0_CG) {
         const size_t ntiles = ((size_t)nRp + 255) / 256;
-        b += nS * ell * 8 + even * 8 + 3 * even * 8 + 4 * nS * ntiles * 8 + 3 * nS * 8 + (nS + 1) * 4;
+        b += 3 * even * 8 + 4 * nS * ntiles * 8 + 3 * nS * 8 + (nS + 1) * 4;
+        if (o->mixed != 2) b += nS * ell * 8 + even * 8;
         if (o->mixed) b += nS * ell * 4 + even * 4;
     }
     // solver workspace: two odd-sized buffers, eleven even vectors, coarse vectors, reductions

@@ -139,41 +139,84 @@ __global__ __launch_bounds__(CTB) void cg_setup_kernel(int nS, int ntiles, const
     }
 }
 
-// q = E_0 p on one row tile of one direction; partial p.q
-template <typename T>
-__global__ __launch_bounds__(CTB) void cg_spmv_kernel(int n, int nS, int ntiles, int nslice, int it,
+// q = E_0 p on a tile of one direction (4 waves of SPW consecutive 64-row slices each); partial
+// p.q.  With WMAX > 0 (the widest slice has at most WMAX slots) all of a slice's value and
+// column loads are issued together, and those of the wave's next slice before the gathers of
+// the current one, so that a wave keeps two slices' loads in flight; slots past a slice's width
+// re-read its last slot (in bounds) and count zero.  WMAX = 0: a plain loop.
+constexpr int SPW = 4;             // slices per wave in the SpMV
+template <int WMAX, typename T>
+__global__ __launch_bounds__(CTB) void cg_spmv_kernel(int n, int nS, int ntiles_s, int nslice, int it,
                                                       const int* __restrict__ sptr, const int* __restrict__ col,
                                                       const T* __restrict__ val, size_t len,
                                                       const T* __restrict__ P, T* __restrict__ Q,
                                                       const int* __restrict__ done, double* __restrict__ part) {
     __shared__ double sh[8];
     int k, t;
-    if (!cg_tile(ntiles, nS, k, t)) return;
+    if (!cg_tile(ntiles_s, nS, k, t)) return;
     if (done && done[k] < it) return;
-    const int slice = t * (CTB / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int i = slice * 64 + lane;
+    const int s0 = (t * (CTB / 64) + (threadIdx.x >> 6)) * SPW;     // the wave's first slice
     const T* pk = P + (size_t)n * k;
+    const T* vk = val + len * k;
     double pq = 0.0;
-    if (slice < nslice) {
-        const int g0 = sptr[slice], w = sptr[slice + 1] - g0;
-        const size_t base = (size_t)g0 * 64 + lane;
-        const T* vk = val + len * k + base;
-        const int* ck = col + base;
-        T acc = (T)0;
-        for (int j = 0; j < w; ++j) acc += vk[64 * j] * pk[ck[64 * j]];
-        if (i < n) {
-            Q[(size_t)n * k + i] = acc;
-            pq = (double)pk[i] * (double)acc;
+    if constexpr (WMAX > 0) {
+        int c[2][WMAX], w[2];
+        T v[2][WMAX];
+        // slice sl into buffer b (a slice past the end reads slice 0's first slot and counts zero)
+        auto load = [&](int b, int sl) {
+            const bool in = sl < nslice;
+            const int g0 = in ? sptr[sl] : 0;
+            const int wd = in ? sptr[sl + 1] - g0 : 1;
+            w[b] = in ? wd : 0;
+            const size_t base = (size_t)g0 * 64 + lane;
+#pragma unroll
+            for (int j = 0; j < WMAX; ++j) {
+                const size_t q = base + 64 * (size_t)min(j, wd - 1);
+                c[b][j] = col[q];
+                v[b][j] = vk[q];
+            }
+        };
+        load(0, s0);
+#pragma unroll
+        for (int r = 0; r < SPW; ++r) {
+            const int b = r & 1;
+            if (r + 1 < SPW) load(b ^ 1, s0 + r + 1);
+            T pv[WMAX];
+#pragma unroll
+            for (int j = 0; j < WMAX; ++j) pv[j] = pk[c[b][j]];
+            T acc = (T)0;
+#pragma unroll
+            for (int j = 0; j < WMAX; ++j) acc += (j < w[b] ? v[b][j] : (T)0) * pv[j];
+            const int i = (s0 + r) * 64 + lane;
+            if (s0 + r < nslice && i < n) {
+                Q[(size_t)n * k + i] = acc;
+                pq += (double)pk[i] * (double)acc;
+            }
+        }
+    } else {
+        for (int r = 0; r < SPW; ++r) {
+            const int sl = s0 + r;
+            if (sl >= nslice) break;
+            const int g0 = sptr[sl], w = sptr[sl + 1] - g0;
+            const size_t base = (size_t)g0 * 64 + lane;
+            T acc = (T)0;
+            for (int j = 0; j < w; ++j) acc += vk[base + 64 * j] * pk[col[base + 64 * j]];
+            const int i = sl * 64 + lane;
+            if (i < n) {
+                Q[(size_t)n * k + i] = acc;
+                pq += (double)pk[i] * (double)acc;
+            }
         }
     }
     pq = block_sum(pq, sh);
-    if (threadIdx.x == 0) part[(size_t)k * ntiles + t] = pq;
+    if (threadIdx.x == 0) part[(size_t)k * ntiles_s + t] = pq;
 }
 
 // alpha = rz / p.q; x += alpha p; r -= alpha q; partials of r.z and r.r
 template <typename T>
-__global__ __launch_bounds__(CTB) void cg_update_kernel(int n, int nS, int ntiles, int it, const T* __restrict__ P,
+__global__ __launch_bounds__(CTB) void cg_update_kernel(int n, int nS, int ntiles, int ntiles_pq, int it,
+                                                        const T* __restrict__ P,
                                                         const T* __restrict__ Q, T* __restrict__ R,
                                                         double* __restrict__ X, const T* __restrict__ dinv,
                                                         const double* __restrict__ rz, const int* __restrict__ done,
@@ -183,7 +226,7 @@ __global__ __launch_bounds__(CTB) void cg_update_kernel(int n, int nS, int ntile
     int k, t;
     if (!cg_tile(ntiles, nS, k, t)) return;
     if (done[k] < it) return;
-    const double pq = partial_sum(part_pq + (size_t)k * ntiles, ntiles, sh);
+    const double pq = partial_sum(part_pq + (size_t)k * ntiles_pq, ntiles_pq, sh);
     const double a = pq != 0.0 ? rz[(size_t)(it & 1) * nS + k] / pq : 0.0;
     const int i = t * CTB + threadIdx.x;
     double rzn = 0.0, rr = 0.0;
@@ -274,6 +317,20 @@ void cg_fill_dinv(const double* diag, size_t n, float* dinv, hipStream_t s) {
     RTE_CHECK_LAUNCH();
 }
 
+// tiles of the SpMV (4 waves of SPW slices each)
+int spmv_tiles(const CgArgs& a) { return (a.nslice + 4 * SPW - 1) / (4 * SPW); }
+
+template <typename T>
+void spmv_launch(const CgArgs& a, int it, const T* val, const T* X, T* Y, const int* done, double* part,
+                 hipStream_t s) {
+    const int ntiles_s = spmv_tiles(a);
+    const unsigned grid = (unsigned)ntiles_s * 8u * (unsigned)((a.nS + 7) / 8);
+    auto f = a.wmax <= 8 ? cg_spmv_kernel<8, T> : a.wmax <= 16 ? cg_spmv_kernel<16, T> : cg_spmv_kernel<0, T>;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(CTB), 0, s, a.n, a.nS, ntiles_s, a.nslice, it, a.sptr, a.col, val, a.len,
+                       X, Y, done, part);
+    RTE_CHECK_LAUNCH();
+}
+
 template <typename T>
 void cg_solve_t(const CgArgs& a, const T* val, const T* dinv, T* R, T* P, T* Q, hipStream_t s) {
     const int n = a.n, nS = a.nS;
@@ -287,10 +344,9 @@ void cg_solve_t(const CgArgs& a, const T* val, const T* dinv, T* R, T* P, T* Q, 
                        a.iters);
     RTE_CHECK_LAUNCH();
     for (int it = 0; it < a.maxit; ++it) {
-        hipLaunchKernelGGL(cg_spmv_kernel<T>, dim3(grid), dim3(CTB), 0, s, n, nS, ntiles, a.nslice, it, a.sptr, a.col,
-                           val, a.len, (const T*)P, Q, a.done, part_a);
-        RTE_CHECK_LAUNCH();
-        hipLaunchKernelGGL(cg_update_kernel<T>, dim3(grid), dim3(CTB), 0, s, n, nS, ntiles, it, (const T*)P,
+        spmv_launch<T>(a, it, val, (const T*)P, Q, a.done, part_a, s);
+        hipLaunchKernelGGL(cg_update_kernel<T>, dim3(grid), dim3(CTB), 0, s, n, nS, ntiles, spmv_tiles(a), it,
+                           (const T*)P,
                            (const T*)Q, R, a.X, dinv, (const double*)a.rz, (const int*)a.done, (const double*)part_a,
                            part_b);
         RTE_CHECK_LAUNCH();
@@ -317,11 +373,7 @@ void cg_solve(const CgArgs& a, const float* val, const float* dinv, float* R, fl
 }
 
 void cg_spmv(const CgArgs& a, const double* val, const double* X, double* Y, hipStream_t s) {
-    const int ntiles = (a.n + CTB - 1) / CTB;
-    const unsigned grid = (unsigned)ntiles * 8u * (unsigned)((a.nS + 7) / 8);
-    hipLaunchKernelGGL(cg_spmv_kernel<double>, dim3(grid), dim3(CTB), 0, s, a.n, a.nS, ntiles, a.nslice, 0, a.sptr,
-                       a.col, val, a.len, X, Y, (const int*)nullptr, a.part);
-    RTE_CHECK_LAUNCH();
+    spmv_launch<double>(a, 0, val, X, Y, nullptr, a.part, s);
 }
 
 }  // namespace k

@@ -237,7 +237,7 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, int m0, int n0, i
 // TM: MFMA and LDS type; TA: A's storage type; TC: C's storage type.  kps: K steps per
 // split (blockIdx.y); the split's result goes to C + blockIdx.y * split_stride.
 template <typename TM, typename TA, typename TC>
-__global__ __launch_bounds__(256, 2) void gemm_mfma_kernel(int M, int N, int K, int kps, TM alpha,
+__global__ __launch_bounds__(256, 2) void gemm_mfma_kernel(int M, int N, int K, int kps, int map, TM alpha,
                                                            const TA* __restrict__ A, int lda,
                                                            const TM* __restrict__ B, int ldb, TM beta,
                                                            TC* __restrict__ C, int ldc, size_t split_stride) {
@@ -246,11 +246,11 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_kernel(int M, int N, int K, 
     __shared__ TM Bs[2][GBK][GBN + GPAD];
     const int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN;
     const int nb = tm * tn;
-    const int b = xcd_swizzle(blockIdx.x, nb);
+    const int b = (map & 1) ? (int)blockIdx.x : xcd_swizzle(blockIdx.x, nb);
     // tile order: along the shorter tile dimension fastest, so that the panel of the other
     // operand is shared by the few consecutive tiles that need it while it is in L2 and the
     // operand re-read across the long dimension is the small one (HBM reads it once)
-    const bool mfast = tm < tn;
+    const bool mfast = (tm < tn) != ((map & 2) != 0);
     const int bm = mfast ? b % tm : b / tn, bn = mfast ? b / tm : b % tn;
     const int m0 = bm * GBM, n0 = bn * GBN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void gemm_mfma_kernel(int M, int N, int K, 
 // so no registers stage them and no LDS stores follow the MFMAs.  The next step's loads are
 // issued into the other buffer at the start of a step; the barrier at its end (which waits
 // for them) makes them visible.  Same tile order, fragments and summation order as above.
-__global__ __launch_bounds__(256, 2) void gemm_f64_dtl_kernel(int M, int N, int K, double alpha,
+__global__ __launch_bounds__(256, 2) void gemm_f64_dtl_kernel(int M, int N, int K, int map, double alpha,
                                                               const double* __restrict__ A, int lda,
                                                               const double* __restrict__ B, int ldb, double beta,
                                                               double* __restrict__ C, int ldc) {
@@ -300,8 +300,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_dtl_kernel(int M, int N, int 
     __shared__ __attribute__((aligned(16))) double As[2][GBK][GBM + GPAD];
     __shared__ __attribute__((aligned(16))) double Bs[2][GBK][GBN + GPAD];
     const int tm = M / GBM, tn = N / GBN;
-    const int b = xcd_swizzle(blockIdx.x, tm * tn);
-    const bool mfast = tm < tn;
+    const int b = (map & 1) ? (int)blockIdx.x : xcd_swizzle(blockIdx.x, tm * tn);
+    const bool mfast = (tm < tn) != ((map & 2) != 0);
     const int bm = mfast ? b % tm : b / tn, bn = mfast ? b / tm : b % tn;
     const int m0 = bm * GBM, n0 = bn * GBN;
     const int lane = threadIdx.x & 63;
@@ -452,7 +452,10 @@ int resident_groups(Kern kern) {
 
 template <typename TM, typename TA, typename TC>
 void gemm_mfma(int M, int N, int K, TM alpha, const TA* A, int lda, const TM* B, int ldb, TM beta, TC* C,
-               int ldc, TM* ws, size_t ws_elems, hipStream_t s) {
+               int ldc, TM* ws, size_t ws_elems, hipStream_t s, int kind) {
+    // the tile map the autotuner chose for this shape (XCD swizzle, traversal order; both only
+    // reorder whole tiles, so the result does not depend on it)
+    const int map = gemm_map(kind, M, N, K);
     if (M <= 0 || N <= 0) return;
     const int tm = (M + GBM - 1) / GBM, tn = (N + GBN - 1) / GBN, nk = (K + GBK - 1) / GBK;
     const int tiles = tm * tn;
@@ -470,10 +473,10 @@ void gemm_mfma(int M, int N, int K, TM alpha, const TA* A, int lda, const TM* B,
         const size_t part = (size_t)Mt * N;
         if (nsplit >= 2 && (size_t)nsplit * part <= ws_elems) {
             hipLaunchKernelGGL((gemm_mfma_kernel<TM, TA, TC>), dim3((tm - trb) * tn, 1), dim3(256), 0, s, Mm, N, K,
-                               nk, alpha, A, lda, B, ldb, beta, C, ldc, (size_t)0);
+                               nk, map, alpha, A, lda, B, ldb, beta, C, ldc, (size_t)0);
             RTE_CHECK_LAUNCH();
             hipLaunchKernelGGL((gemm_mfma_kernel<TM, TA, TM>), dim3(units, nsplit), dim3(256), 0, s, Mt, N, K, kps,
-                               (TM)1, A + Mm, lda, B, ldb, (TM)0, ws, Mt, part);
+                               map, (TM)1, A + Mm, lda, B, ldb, (TM)0, ws, Mt, part);
             RTE_CHECK_LAUNCH();
             const int g = (int)std::min<size_t>((part + 255) / 256, 4096);
             hipLaunchKernelGGL((gemm_sum_parts_kernel<TM, TC>), dim3(g), dim3(256), 0, s, Mt, N, nsplit,
@@ -487,31 +490,31 @@ void gemm_mfma(int M, int N, int K, TM alpha, const TA* A, int lda, const TM* B,
         const bool aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(B) % 16 == 0) &&
                              lda % 2 == 0 && ldb % 2 == 0;
         if (aligned && M % GBM == 0 && N % GBN == 0 && K % GBK == 0 && K > 0) {
-            hipLaunchKernelGGL(gemm_f64_dtl_kernel, dim3(tiles), dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                               beta, C, ldc);
+            hipLaunchKernelGGL(gemm_f64_dtl_kernel, dim3(tiles), dim3(256), 0, s, M, N, K, map, alpha, A, lda, B,
+                               ldb, beta, C, ldc);
             RTE_CHECK_LAUNCH();
             return;
         }
     }
-    hipLaunchKernelGGL((gemm_mfma_kernel<TM, TA, TC>), dim3(tiles, 1), dim3(256), 0, s, M, N, K, nk, alpha, A, lda,
-                       B, ldb, beta, C, ldc, (size_t)0);
+    hipLaunchKernelGGL((gemm_mfma_kernel<TM, TA, TC>), dim3(tiles, 1), dim3(256), 0, s, M, N, K, nk, map, alpha, A,
+                       lda, B, ldb, beta, C, ldc, (size_t)0);
     RTE_CHECK_LAUNCH();
 }
 }  // namespace
 
 void gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, const double* B, int ldb, double beta,
               double* C, int ldc, hipStream_t s, double* ws, size_t ws_elems) {
-    gemm_mfma<double, double, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems, s);
+    gemm_mfma<double, double, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems, s, kGemmF64);
 }
 
 void gemm_f32(int M, int N, int K, float alpha, const double* A, int lda, const float* B, int ldb, float beta,
               double* C, int ldc, hipStream_t s, float* ws, size_t ws_elems) {
-    gemm_mfma<float, double, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems, s);
+    gemm_mfma<float, double, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems, s, kGemmF32);
 }
 
 void gemm_f32(int M, int N, int K, float alpha, const float* A, int lda, const float* B, int ldb, float beta,
               double* C, int ldc, hipStream_t s, float* ws, size_t ws_elems) {
-    gemm_mfma<float, float, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems, s);
+    gemm_mfma<float, float, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_elems, s, kGemmF32in);
 }
 
 void cvt_f64_bf16(const double* x, uint16_t* y, size_t n, hipStream_t s) {

@@ -78,14 +78,15 @@ __device__ __forceinline__ void bf16_step_mfma(const BTile& As, const BTile& Bs,
 __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(int M, int N, int K, float alpha,
                                                            const uint16_t* __restrict__ A, int lda,
                                                            const uint16_t* __restrict__ B, int ldb, float beta,
-                                                           float* __restrict__ C, int ldc) {
+                                                           float* __restrict__ C, int ldc, int map) {
     __shared__ __attribute__((aligned(16))) BTile As[2];
     __shared__ __attribute__((aligned(16))) BTile Bs[2];
     const int tm = (M + HBM_ - 1) / HBM_, tn = (N + HBN - 1) / HBN;
-    const int b = xcd_swz(blockIdx.x, tm * tn);
-    // the shorter tile dimension fastest: consecutive tiles share the other operand's panel
-    // (in L2), and the operand re-read across the long dimension is the small one
-    const bool mfast = tm < tn;
+    const int b = (map & 1) ? (int)blockIdx.x : xcd_swz(blockIdx.x, tm * tn);
+    // the shorter tile dimension fastest by default: consecutive tiles share the other
+    // operand's panel (in L2), and the operand re-read across the long dimension is the small
+    // one; the tuned map may flip it (map & 2) or drop the XCD swizzle (map & 1)
+    const bool mfast = (tm < tn) != ((map & 2) != 0);
     const int bm = mfast ? b % tm : b / tn, bn = mfast ? b / tm : b % tn;
     const int m0 = bm * HBM_, n0 = bn * HBN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -275,7 +276,8 @@ void gemm_bf16(int M, int N, int K, float alpha, const uint16_t* A, int lda, con
     if (M <= 0 || N <= 0) return;
     if (K % 8 || lda % 8 || ldb % 8) fail(RTE_E_ARG, "BF16 GEMM needs K, lda, ldb multiples of 8");
     const int nb = ((M + HBM_ - 1) / HBM_) * ((N + HBN - 1) / HBN);
-    hipLaunchKernelGGL(gemm_bf16_kernel, dim3(nb), dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    hipLaunchKernelGGL(gemm_bf16_kernel, dim3(nb), dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                       gemm_map(kGemmBF16, M, N, K));
     RTE_CHECK_LAUNCH();
 }
 

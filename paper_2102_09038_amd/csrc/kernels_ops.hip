@@ -4,6 +4,8 @@
 //
 // Layouts: even vectors U[i + nRp*k]; odd vectors V[j + nRm*(3k+m)]; every kernel maps
 // consecutive threads to consecutive spatial indices so global accesses coalesce.
+#include <type_traits>
+
 #include "ops.h"
 
 namespace rte {
@@ -238,10 +240,22 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
     __syncthreads();
     const int il = threadIdx.x & (TI - 1);
     const int i = i0 + il;
-    if (i >= nRp) return;
-    const int e0 = rowptr[i], e1 = rowptr[i + 1];
-    const bool bnd = bnd_row[i] != 0;
+    const bool valid = i < nRp;
+    const int e0 = valid ? rowptr[i] : 0, e1 = valid ? rowptr[i + 1] : 0;
+    const bool bnd = valid && bnd_row[i] != 0;
     const bool inreg = e1 - e0 <= RMAX;
+    // 2D with coefD: the three stiffness-class values of the row's entries, staged in LDS once
+    // per vertex (they are the same for every direction)
+    constexpr int NSR = D == 2 ? 3 : 1, RSR = D == 2 ? RMAX : 1;
+    __shared__ double Sv[NSR][RSR][TI];
+    constexpr bool DIAG = std::is_same<ZT, float>::value;   // only the mixed-precision form has coefD
+    if (DIAG && D == 2 && coefD) {
+        const int c = threadIdx.x / TI;
+        if (c < NSR && inreg)
+            for (int t = 0; t < RSR; ++t) Sv[c][t][il] = e0 + t < e1 ? cls[(size_t)c * nnz + e0 + t] : 0.0;
+        __syncthreads();
+    }
+    if (!valid) return;
     int rc[RMAX];
     double ra[RMAX], rb[RMAX];
 #pragma unroll
@@ -273,6 +287,14 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
                     if (G) acc = fma(-rb[t], gv[t], acc);
                 }
             }
+            if (DIAG && D == 2 && coefD) {
+                // the diagonal d x d blocks of the condensed operator (see below), in FP64
+                const double c0 = coefD[(size_t)k * NSR], c1 = coefD[(size_t)k * NSR + 1],
+                             c2 = coefD[(size_t)k * NSR + 2];
+#pragma unroll
+                for (int t = 0; t < RSR; ++t)
+                    if (e0 + t < e1) acc = fma(fma(c0, Sv[0][t][il], fma(c1, Sv[1][t][il], c2 * Sv[2][t][il])), xv[t], acc);
+            }
         } else {
             for (int e = e0; e < e1; ++e) {
                 const int c = col[e];
@@ -288,9 +310,10 @@ __global__ __launch_bounds__(256) void at_e_rm_kernel(
                 acc = fma(val, xk[col[e]], acc);
             }
         }
-        if (coefD) {
+        if (DIAG && coefD && !(D == 2 && inreg)) {
             // the diagonal d x d blocks of the condensed operator, kept out of the BF16 GEMM:
             // sum_{n,m} G_kk(n,m) D_n^T Mt-^{-1} D_m x_k over the stiffness classes, in FP64
+            // (2D rows held in registers take the LDS-staged form above)
             const double* cd = coefD + (size_t)k * nstiff;
             for (int e = e0; e < e1; ++e) {
                 double val = 0.0;

@@ -122,6 +122,7 @@ void richardson_update(const Handle* h, double* U, const double* S, const double
 struct CgArgs {
     int n = 0, nS = 0, nslice = 0;   // rows per block, directions, slices of 64 rows
     size_t len = 0;                  // ELL entries per direction (64 per slot of every slice)
+    int wmax = 0;                    // slots of the widest slice
     const int* sptr = nullptr;       // [nslice + 1] first slot group of each slice
     const int* col = nullptr;        // [len] column of every entry (shared by the directions)
     const double* B = nullptr;       // right-hand sides, n x nS column-major

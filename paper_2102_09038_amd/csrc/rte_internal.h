@@ -159,7 +159,7 @@ struct Handle {
     // slots as the slice's longest row), its entries' positions in the CSR pattern (-1 on
     // padding), and the explicit values of every direction's block with the inverse diagonal,
     // in FP64 and (mixed) FP32, built at assembly for e0_solver = RTE_E0_CG, else on first use
-    int ell_nslice = 0;
+    int ell_nslice = 0, ell_wmax = 0;
     size_t ell_len = 0;
     DBuf<int> ell_sptr, ell_col, ell_e;
     DBuf<double> ell_v64, ell_dinv64;
@@ -252,6 +252,15 @@ void autotune(Handle* h, int flags, hipStream_t s, rte_tune_report* rep);
 void set_band_layout(Handle* h, int precision, int H, int P, hipStream_t s);
 int batch_poll(Batch* B, int max_out, int32_t* slots, rte_solve_info* infos, int32_t* statuses);
 void batch_usage(const Batch* B, int32_t* n_live, int32_t* n_done, size_t* used_bytes);
+
+// ----------------------------------------------------------------------------- GEMM tile maps
+// The tile map of a GEMM launch: bit 0 drops the XCD swizzle of the work-group ids, bit 1 flips
+// the traversal order of the tile grid (the shorter dimension fastest by default).  Both only
+// reorder whole output tiles, so the result is the same bits.  rte_autotune times the four maps
+// of a handle's GEMM shapes and records the fastest per (kind, M, N, K) (autotune.cpp, with an
+// on-disk cache); launches look it up (0 when none was recorded).
+enum GemmKind { kGemmF64 = 1, kGemmF32 = 2, kGemmF32in = 3, kGemmBF16 = 4 };
+int gemm_map(int kind, int M, int N, int K);
 
 // ----------------------------------------------------------------------------- launchers
 namespace k {

@@ -288,6 +288,7 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
     a.nS = h->nS;
     a.nslice = h->ell_nslice;
     a.len = h->ell_len;
+    a.wmax = h->ell_wmax;
     a.sptr = h->ell_sptr.p;
     a.col = h->ell_col.p;
     a.B = X;
@@ -431,6 +432,7 @@ void apply_E0(Handle* h, const double* X, double* Y, hipStream_t s) {
     a.nS = h->nS;
     a.nslice = h->ell_nslice;
     a.len = h->ell_len;
+    a.wmax = h->ell_wmax;
     a.sptr = h->ell_sptr.p;
     a.col = h->ell_col.p;
     a.part = h->cg_part.p;

@@ -2,9 +2,10 @@
 // and served forms of Alg. 3).  Every live slot takes one outer step per batch iteration:
 // - the residuals of all slots are formed, and ONE host synchronisation reads every slot's
 //   residual norm and step products;
-// - in each of the l steps of P_1 (Alg. 2), the E_0^{-1} applications of all slots are one
-//   grouped band-solve launch per band shape, so that the direction systems of small
-//   instances fill the GPU together;
+// - in each of the l steps of P_1 (Alg. 2), the E_0^{-1} applications of all slots with banded
+//   factors are one grouped band-solve launch per band shape, so that the direction systems of
+//   small instances fill the GPU together; slots whose E_0 is solved by CG (3D meshes, whose
+//   bands are too wide to factor) run their all-direction CG one after another;
 // - the remaining per-slot work (ApplyE, the subspace correction) of the slots is spread over
 //   a few lanes (streams of the batch, joined to the step's stream by events), so that the
 //   kernels of small instances run side by side and fill the GPU together; each slot's own
@@ -110,11 +111,14 @@ size_t ws_bytes(const Handle* h, int id) {
     return n * sizeof(double);
 }
 
-size_t slot_bytes(Handle* h) {
+size_t slot_bytes(Handle* h, const rte_solve_opts* o) {
     size_t b = h->footprint();
     if (h->ws.size() < W_COUNT) h->ws.resize(W_COUNT);
     for (int id : kSlotWs)
         if (!h->ws[id].p) b += ws_bytes(h, id);
+    if (o->e0_solver == RTE_E0_CG)
+        for (int id : {W_CGR, W_CGP, W_CGQ})
+            if (!h->ws[id].p) b += ws_bytes(h, id);
     return b;
 }
 
@@ -147,7 +151,7 @@ void rebuild_plan(Batch* B, hipStream_t s) {
     std::vector<k::BandJob> jobs;
     const bool f32 = B->precision == RTE_MIXED;
     for (auto& sl : B->slots) {
-        if (!sl.live) continue;
+        if (!sl.live || sl.o.e0_solver != RTE_E0_BANDED) continue;
         Handle* h = sl.h;
         k::BandJob j{};
         j.BL = f32 ? static_cast<const void*>(h->L0f.p) : static_cast<const void*>(h->L0.p);
@@ -189,13 +193,19 @@ void rebuild_plan(Batch* B, hipStream_t s) {
 // X -> Y = E_0^{-1} X for every live slot (x_of / y_of give the slot's vectors)
 template <typename XF, typename YF>
 void grouped_e0inv(Batch* B, XF x_of, YF y_of, hipStream_t s) {
+    const bool lowp = B->precision == RTE_MIXED;
     for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
-        k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, x_of(sl), ws(sl.h, W_BB), true, ls);
+        if (sl.o.e0_solver == RTE_E0_BANDED)
+            k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, x_of(sl), ws(sl.h, W_BB), true, ls);
     });
     k::band_group_run(B->plan, s);
     for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
-        k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, ws(sl.h, W_BX), y_of(sl), false, ls);
+        if (sl.o.e0_solver == RTE_E0_BANDED)
+            k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, ws(sl.h, W_BX), y_of(sl), false, ls);
     });
+    // the CG slots on the step's stream (each CG reads its live count on the host)
+    for (auto& sl : B->slots)
+        if (sl.live && sl.o.e0_solver == RTE_E0_CG) e0inv(sl.h, &sl.o, x_of(sl), y_of(sl), s, nullptr, nullptr, lowp);
 }
 
 // residuals r_n = (E - K+) u_n - q (FP64) of every live slot and the scalars of its
@@ -274,6 +284,9 @@ hipGraphExec_t capture(hipStream_t s, F&& enqueue) {
 }
 
 void recapture(Batch* B) {
+    for (auto& sl : B->slots)
+        if (sl.live && sl.o.e0_solver != RTE_E0_BANDED)
+            fail(RTE_E_ARG, "graph mode needs banded E_0 slots (a CG solve reads its live count on the host)");
     B->drain();
     if (B->g_res) { RTE_HIP(hipGraphExecDestroy(B->g_res)); B->g_res = nullptr; }
     if (B->g_prec) { RTE_HIP(hipGraphExecDestroy(B->g_prec)); B->g_prec = nullptr; }
@@ -304,13 +317,16 @@ Batch* batch_create(int max_slots, size_t budget) {
 void batch_destroy(Batch* B) { delete B; }
 
 int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, double* U, hipStream_t s) {
-    if (o->e0_solver != RTE_E0_BANDED || !h->have_e0_banded)
-        fail(RTE_E_ARG, "batch slots need the banded E_0 solve (assemble with e0_solver = RTE_E0_BANDED)");
+    if (o->e0_solver == RTE_E0_BANDED && !h->have_e0_banded)
+        fail(RTE_E_ARG, "a banded E_0 slot needs a handle assembled with e0_solver = RTE_E0_BANDED");
+    if (o->e0_solver != RTE_E0_BANDED && o->e0_solver != RTE_E0_CG) fail(RTE_E_ARG, "unknown E_0 solver");
+    if (o->e0_solver == RTE_E0_CG && B->use_graphs) fail(RTE_E_ARG, "graph mode needs banded E_0 slots");
     if (o->odd_solver == RTE_ODD_PCG) fail(RTE_E_ARG, "batch slots use the exact or condensed odd solve");
     if (o->inner != RTE_INNER_RICHARDSON) fail(RTE_E_ARG, "batch slots use the Richardson inner iteration");
-    if (o->precision == RTE_MIXED && !(h->have_mixed && h->L0f.p))
+    if (o->precision == RTE_MIXED && !(h->have_mixed && (h->L0f.p || o->e0_solver == RTE_E0_CG)))
         fail(RTE_E_ARG, "a mixed-precision slot needs a handle assembled with mixed != 0");
-    if (o->precision == RTE_FP64 && !h->L0.p) fail(RTE_E_ARG, "an FP64 slot needs the FP64 band factors");
+    if (o->precision == RTE_FP64 && o->e0_solver == RTE_E0_BANDED && !h->L0.p)
+        fail(RTE_E_ARG, "an FP64 slot needs the FP64 band factors");
     bool any = false;
     for (auto& sl : B->slots) any |= sl.used;
     if (any && o->precision != B->precision) fail(RTE_E_ARG, "all slots of a batch share one precision");
@@ -321,9 +337,14 @@ int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, 
     for (int i = 0; i < B->max_slots; ++i)
         if (!B->slots[i].used) { id = i; break; }
     if (id < 0) fail(RTE_E_ARG, "no free batch slot");
-    const size_t bytes = slot_bytes(h);
+    const size_t bytes = slot_bytes(h, o);
     if (B->budget && B->used_bytes + bytes > B->budget) fail(RTE_E_NOMEM, "the batch's device-memory budget is full");
     for (int wid : kSlotWs) ws(h, wid);
+    if (o->e0_solver == RTE_E0_CG) {
+        // the CG's block values and vectors now, so that stepping allocates nothing
+        cg_prepare(h, o->precision == RTE_MIXED, s);
+        for (int wid : {W_CGR, W_CGP, W_CGQ}) ws(h, wid);
+    }
     B->precision = o->precision;
     B->l = o->l;
     BatchSlot& sl = B->slots[id];

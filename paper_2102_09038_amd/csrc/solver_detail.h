@@ -38,6 +38,9 @@ void cg_prepare(Handle* h, bool f32, hipStream_t s);
 // Y = E X [- q0] (q0 nullable), or with G = X S+ given: Y = (E - K+) X - q0  (Alg. 1)
 void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const double* G, const double* q0, double* Y,
                   double tol, hipStream_t s, int64_t* pcg, bool lowp);
+// Y = E_0^{-1} X by the handle's banded factors or its CG (o->e0_solver); lowp: FP32 factors / CG
+void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s, int64_t* cgt,
+           int* cgmax, bool lowp);
 // Y = (E - K+) X - q0 (FP64 scatter GEMM, then apply_E_core)
 void residual_like(Handle* h, const rte_solve_opts* o, const double* X, const double* q0, double* Y, double tol,
                    hipStream_t s, int64_t* pcg, bool lowp);

@@ -58,7 +58,10 @@ BAND_SHAPES = [(9, 1), (17, 1), (33, 1), (9, 2), (17, 2), (33, 2), (17, 3), (33,
 class rte_tune_report(C.Structure):
     _fields_ = [("n_cand", C.c_int32 * 2), ("H", (C.c_int32 * 9) * 2), ("P", (C.c_int32 * 9) * 2),
                 ("ms", (C.c_double * 9) * 2), ("chosen_H", C.c_int32 * 2), ("chosen_P", C.c_int32 * 2),
-                ("default_H", C.c_int32 * 2), ("default_P", C.c_int32 * 2), ("from_cache", C.c_int32 * 2)]
+                ("default_H", C.c_int32 * 2), ("default_P", C.c_int32 * 2), ("from_cache", C.c_int32 * 2),
+                ("n_gemm", C.c_int32), ("gemm_kind", C.c_int32 * 4), ("gemm_m", C.c_int32 * 4),
+                ("gemm_n", C.c_int32 * 4), ("gemm_k", C.c_int32 * 4), ("gemm_ms", (C.c_double * 4) * 4),
+                ("gemm_map", C.c_int32 * 4), ("gemm_from_cache", C.c_int32 * 4)]
 
 
 class rte_solve_info(C.Structure):
@@ -255,9 +258,11 @@ class Handle:
         return b.value
 
     def autotune(self, force=False, stream=None) -> dict:
-        """Time the E_0 band solve in every factor layout that holds the band and keep the
-        fastest (rte_autotune).  Returns, per precision present, the shapes timed with
-        their milliseconds per E_0^{-1}, the default and the chosen shape."""
+        """Time the E_0 band solve in every factor layout that holds the band, and each GEMM
+        shape of the handle in its four tile maps, and keep the fastest (rte_autotune).
+        Returns, per precision of banded factors present, the shapes timed with their
+        milliseconds per E_0^{-1}, the default and the chosen shape; under "gemm" a list of
+        {kind, m, n, k, ms (per map), map, from_cache}."""
         r = rte_tune_report()
         _check(lib.rte_autotune(self.h, RTE_TUNE_FORCE if force else 0, _stream(stream), C.byref(r)))
         out = {}
@@ -267,6 +272,10 @@ class Handle:
             out[name] = {"timed": [((r.H[i][c], r.P[i][c]), r.ms[i][c]) for c in range(r.n_cand[i])],
                          "default": (r.default_H[i], r.default_P[i]), "chosen": (r.chosen_H[i], r.chosen_P[i]),
                          "from_cache": bool(r.from_cache[i])}
+        kinds = {1: "fp64", 2: "fp32", 4: "bf16"}
+        out["gemm"] = [{"kind": kinds.get(r.gemm_kind[i], r.gemm_kind[i]), "m": r.gemm_m[i], "n": r.gemm_n[i],
+                        "k": r.gemm_k[i], "ms": list(r.gemm_ms[i]), "map": r.gemm_map[i],
+                        "from_cache": bool(r.gemm_from_cache[i])} for i in range(r.n_gemm)]
         return out
 
     def set_band_layout(self, precision, H, P, stream=None):

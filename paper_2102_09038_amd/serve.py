@@ -9,6 +9,11 @@ latency (completion - arrival) recorded.  A request's result is the result rte_s
 computes for it alone: the batch runs the same arithmetic per slot.
 
 The loop runs in real time: a request is not touched before its arrival time.
+
+Requests on 2D meshes solve E_0 by band factors; requests on 3D meshes, whose bands are too
+wide to factor, by the all-direction CG.  The two kinds step in two lockstep batches, one
+after the other in the same loop, so that the grouped band solves of the 2D slots never wait
+for a CG.
 """
 from __future__ import annotations
 
@@ -60,7 +65,11 @@ class Server:
         self.torch = torch
         self.budget = int(budget)
         self.opts = solve_opts
+        # the same options with the CG E_0 solve, for the requests that use it
+        self.opts_cg = rte.rte_solve_opts.from_buffer_copy(solve_opts)
+        self.opts_cg.e0_solver = rte.RTE_E0_CG
         self.batch = rte.Batch(max_slots=max_slots, hbm_budget=0, use_graphs=use_graphs)
+        self.batch_cg = rte.Batch(max_slots=max_slots, hbm_budget=0, use_graphs=False)
         self.workers = workers
         self.mixed_assembly = mixed_assembly
         # the batch runs the condensed odd solve only: no odd eigendecomposition at assembly
@@ -73,20 +82,26 @@ class Server:
         self.on_done = on_done
         self.reserved = 0                          # bytes promised to requests being assembled or in slots
         self.stream = torch.cuda.Stream()
-        self.slot_of = {}                          # slot -> (request, handle, reserved bytes, U)
+        self.slot_of = {}                          # (batch, slot) -> (request, handle, reserved bytes, U)
         self.t_step = 0.0                          # seconds inside batch steps
         self.peak_live = 0
+        self.peak_reserved = 0                     # the most bytes promised at any time (<= budget)
 
     # ---------------------------------------------------------------------------- helpers
+    @staticmethod
+    def e0_solver_for(inst) -> int:
+        """Band factors for 2D meshes, the all-direction CG for 3D ones (bands too wide)."""
+        return rte.RTE_E0_BANDED if inst.dim == 2 else rte.RTE_E0_CG
+
     def _estimate(self, req):
         if not hasattr(req, "_est"):
-            b, p = rte.estimate_footprint(req.inst, e0_solver=rte.RTE_E0_BANDED, mixed=self.mixed_assembly,
+            b, p = rte.estimate_footprint(req.inst, e0_solver=self.e0_solver_for(req.inst), mixed=self.mixed_assembly,
                                           odd_eig=self.odd_eig, coarse_solver=self.coarse_solver)
             req._est = (b, max(b, p))
         return req._est
 
     def _assemble(self, req: Request, stream):
-        h = rte.Handle.from_instance(req.inst, stream=stream.cuda_stream, e0_solver=rte.RTE_E0_BANDED,
+        h = rte.Handle.from_instance(req.inst, stream=stream.cuda_stream, e0_solver=self.e0_solver_for(req.inst),
                                      mixed=self.mixed_assembly, odd_eig=self.odd_eig,
                                      coarse_solver=self.coarse_solver)
         return h
@@ -136,6 +151,7 @@ class Server:
                         break
                     waiting.pop(0)
                     self.reserved += peak
+                    self.peak_reserved = max(self.peak_reserved, self.reserved)
                     todo.put((req, (b, peak)))
                     in_flight += 1
                 # admit what the workers have assembled
@@ -158,16 +174,22 @@ class Server:
                         raise h
                     self.reserved -= peak - b          # the assembly peak is over
                     U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
-                    slot = self.batch.admit(h, U, self.opts, stream=self.stream.cuda_stream)
+                    cg = self.e0_solver_for(req.inst) == rte.RTE_E0_CG
+                    which = self.batch_cg if cg else self.batch
+                    slot = which.admit(h, U, self.opts_cg if cg else self.opts, stream=self.stream.cuda_stream)
                     req.admitted_at = now()
-                    self.slot_of[slot] = (req, h, b, U)
+                    self.slot_of[(int(cg), slot)] = (req, h, b, U)
                 if self.slot_of:
                     self.peak_live = max(self.peak_live, len(self.slot_of))
                     ts = time.perf_counter()
-                    self.batch.step(step_iters, stream=self.stream.cuda_stream)
+                    polled = []
+                    for cg, which in ((0, self.batch), (1, self.batch_cg)):
+                        if any(key[0] == cg for key in self.slot_of):
+                            which.step(step_iters, stream=self.stream.cuda_stream)
+                            polled += [((cg, slot), st, info) for slot, st, info in which.poll()]
                     self.t_step += time.perf_counter() - ts
-                    for slot, st, info in self.batch.poll():
-                        req, h, b, U = self.slot_of.pop(slot)
+                    for key, st, info in polled:
+                        req, h, b, U = self.slot_of.pop(key)
                         req.done_at = now()
                         req.status, req.iters, req.rel_resid = st, info.iters, info.rel_resid
                         if self.keep:
@@ -197,6 +219,7 @@ class Server:
 
     def close(self):
         self.batch.close()
+        self.batch_cg.close()
 
 
 def percentile(values, q):

@@ -1,11 +1,16 @@
 import os
 import sys
+import tempfile
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+# the tuner's on-disk cache of a test session is its own (never the user's), so that every
+# session starts untuned
+os.environ["RTE_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="rte_tune_"), "tune.txt")
 
 
 def pytest_configure(config):

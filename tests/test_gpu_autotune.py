@@ -1,7 +1,14 @@
-"""GPU tests of the band layout autotuner (rte_autotune, rte_set_band_layout): every factor
-layout that holds the band gives bitwise the same E_0^{-1} (padding groups are zero and each
-row's products are summed in the same order), the tuner times every such layout, keeps one
-of them and caches its choice, and the lockstep batch runs handles in non-default layouts."""
+"""GPU tests of the autotuner (rte_autotune, rte_set_band_layout): every factor layout that
+holds the band gives bitwise the same E_0^{-1} (padding groups are zero and each row's
+products are summed in the same order), the tuner times every such layout, keeps one of them
+and caches its choice, and the lockstep batch runs handles in non-default layouts; every GEMM
+tile map gives bitwise the same solve, and the choices come back from the on-disk cache in a
+later process."""
+import json
+import os
+import subprocess
+import sys
+
 import numpy as np
 import pytest
 
@@ -121,7 +128,8 @@ def test_autotune_fp32_only_handle():
     U0 = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
     h.solve(U0, opts=o)
     rep = h.autotune(force=True)
-    assert set(rep) == {"fp32"}
+    assert set(rep) == {"fp32", "gemm"}
+    assert [g["kind"] for g in rep["gemm"]] == ["fp64", "fp32", "fp64", "bf16"]
     with pytest.raises(rte.RteError):
         h.set_band_layout(rte.RTE_FP64, 33, 1)
     with pytest.raises(rte.RteError):
@@ -131,3 +139,65 @@ def test_autotune_fp32_only_handle():
     h.solve(U1, opts=o)
     assert torch.equal(U0, U1)
     h.close()
+
+
+# one process: tune (from the cache file when it holds the shapes), then solve in FP64 and in
+# mixed precision with the condensed odd solve, whose GEMMs are the ones tuned
+_CHILD = r"""
+import json, sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+from paper_2102_09038_amd import inputs, rte
+h = rte.Handle.from_instance(inputs.config_small(), e0_solver=rte.RTE_E0_BANDED, mixed=1)
+rep = h.autotune()
+out = {}
+for prec in (rte.RTE_FP64, rte.RTE_MIXED):
+    o = rte.default_solve_opts(l=4, tol=1e-10, max_iter=300, precision=prec, e0_solver=rte.RTE_E0_BANDED,
+                               odd_solver=rte.RTE_ODD_CONDENSED)
+    U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+    h.solve(U, opts=o)
+    np.save(sys.argv[2] + f"_{prec}.npy", U.cpu().numpy())
+h.close()
+print(json.dumps(rep["gemm"]))
+"""
+
+
+def _child(tmp_path, cache, tag):
+    env = dict(os.environ, RTE_TUNE_CACHE=str(cache))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", _CHILD, root, str(tmp_path / tag)], env=env, capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    gem = json.loads(r.stdout.strip().splitlines()[-1])
+    Us = [np.load(tmp_path / f"{tag}_{p}.npy") for p in (0, 1)]
+    return gem, Us
+
+
+def test_gemm_maps_disk_cache_and_bitwise(tmp_path):
+    """A first process times the four tile maps of each GEMM shape and writes its choices; a
+    second takes them from the file; with the file set to each map in turn, the FP64 and the
+    mixed solves are bitwise the same."""
+    from paper_2102_09038_amd import rte
+    cache = tmp_path / "tune.txt"
+    gem1, U1 = _child(tmp_path, cache, "first")
+    print(gem1)
+    assert [g["kind"] for g in gem1] == ["fp64", "fp32", "fp64", "bf16"]
+    for g in gem1:
+        assert not g["from_cache"] and all(ms > 0 for ms in g["ms"]) and 0 <= g["map"] < 4
+    lines = cache.read_text().split("\n")
+    assert sum(" gemm " in ln for ln in lines) == 4 and sum(" band " in ln for ln in lines) == 2
+    gem2, U2 = _child(tmp_path, cache, "second")
+    assert [g["map"] for g in gem2] == [g["map"] for g in gem1]
+    assert all(g["from_cache"] for g in gem2)
+    for a, b in zip(U1, U2):
+        assert np.array_equal(a, b)
+    for m in range(4):
+        kept = [ln for ln in lines if ln and " gemm " not in ln]
+        tuned = [ln.rsplit(" ", 1)[0] + f" {m}" for ln in lines if " gemm " in ln]
+        cache.write_text("\n".join(kept + tuned) + "\n")
+        gem, U = _child(tmp_path, cache, f"map{m}")
+        assert [g["map"] for g in gem] == [m] * 4 and all(g["from_cache"] for g in gem)
+        for p, (a, b) in enumerate(zip(U1, U)):
+            assert np.array_equal(a, b), (m, p)
+    print("maps 0-3: FP64 and mixed solves bitwise equal")
