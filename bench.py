@@ -361,7 +361,7 @@ def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None, err
         """Each measured result of both forms against a tight FP64 solve of its request (untimed,
         after the runs)."""
         by_rid = {r.rid: r for r in done_fp64}
-        em, ef = [], []
+        em, ef, names = [], [], []
         tick = progress("tight reference")
         for r in sorted(done_mixed, key=lambda r: r.rid):
             tick()
@@ -374,6 +374,7 @@ def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None, err
             h.solve(R, opts=ot, raise_on_notconv=False)
             nr = torch.linalg.norm(R)
             em.append(float(torch.linalg.norm(r.U - R) / nr))
+            names.append((r.rid, r.inst.name, r.iters, float(r.rel_resid)))
             f = by_rid.get(r.rid)
             if f is not None and f.U is not None:
                 ef.append(float(torch.linalg.norm(f.U - R) / nr))
@@ -381,9 +382,15 @@ def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None, err
             h.close()
             r.U = None
 
-        def summ(v):
-            return {"max": max(v), "median": float(np.median(v)), "per_request": [round(e, 12) for e in v]} if v else None
-        return summ(em), summ(ef)
+        def summ(v, worst=None):
+            if not v:
+                return None
+            out = {"max": max(v), "median": float(np.median(v)), "per_request": [round(e, 12) for e in v]}
+            if worst:
+                rid, name, iters, res = worst[int(np.argmax(v))]
+                out["worst"] = {"request": rid, "instance": name, "iters": iters, "rel_resid": res}
+            return out
+        return summ(em, names), summ(ef)
 
     def progress(what):
         """a callback that logs every 16th completed request (long runs print as they go)"""

@@ -397,6 +397,7 @@ struct Asm {
     void scattering();
     void odd_basis();
     void condensed_from_H();
+    Vec whitened_odd_scatter() const;
     void odd_eigenbasis();
     void odd_inverse();
     void even_basis();
@@ -793,8 +794,9 @@ void Asm::condensed_from_H() {
     h.coefD.upload(cd, s);
 }
 
-// odd: S- W = M_S- W Lambda; with M_S- = L L^T blockwise: (L^-1 S- L^-T) V = V Lambda, W = L^-T V
-void Asm::odd_eigenbasis() {
+// C = L^-1 S- L^-T (S- symmetrised) for M_S- = L L^T blockwise (L = blockdiag of the Cholesky
+// factors of 2 T_k): the odd scattering matrix in coordinates where M_S- is the identity
+Vec Asm::whitened_odd_scatter() const {
     Vec A((size_t)nSm * nSm);
     for (int kb = 0; kb < nS; ++kb)
         for (int kc = 0; kc < nS; ++kc) {
@@ -820,6 +822,12 @@ void Asm::odd_eigenbasis() {
                     A[(3 * kb + n) + (size_t)nSm * (3 * kc + m)] = v;
                 }
         }
+    return A;
+}
+
+// odd: S- W = M_S- W Lambda; with M_S- = L L^T blockwise: (L^-1 S- L^-T) V = V Lambda, W = L^-T V
+void Asm::odd_eigenbasis() {
+    Vec A = whitened_odd_scatter();
     Vec lam;
     syevd(*rb, s, nSm, A, lam);
     // W = L^-T V, reorder to non-increasing eigenvalues
@@ -875,19 +883,67 @@ void Asm::odd_eigenbasis() {
     }
 }
 
-// H = (M_S- - delta S-)^{-1}: M_S- is block diagonal (2 T_k), S- symmetrised as above;
-// dense lower band of width nSm - 1, Cholesky inverse on the GPU
+// H = (M_S- - delta S-)^{-1} = L^-T (I - R)^{-1} L^-1 with R = delta C, C the whitened odd
+// scattering matrix.  The spectrum of C lies in [-1, 1] (the odd Legendre moments of the
+// normalised kernel), so that of R lies inside (-1, 1) for delta < 1, and
+//   (I - R)^{-1} = (I + R)(I + R^2)(I + R^4) ...
+// converges doubly exponentially: X <- X + X Z, Z <- Z^2 from X = I + R, Z = R, until the next
+// factor is below the FP64 resolution of X.  Every product is this library's FP64 MFMA GEMM,
+// whose summation order is fixed, so H (and the condensed operator built from it) is bitwise
+// the same in every assembly of an instance, whatever else runs on the device; a dense
+// factorisation by a vendor library is not guaranteed to be (one varied in its last bits when
+// assemblies overlapped other work on the device).
 void Asm::odd_inverse() {
-    const size_t w = (size_t)nSm;
-    Vec band((size_t)nSm * w, 0.0);
-    for (int r = 0; r < nSm; ++r)
-        for (int c = 0; c <= r; ++c) {
-            const double sm = 0.5 * (h.h_Sm[r + (size_t)nSm * c] + h.h_Sm[c + (size_t)nSm * r]);
-            double v = -h.delta0 * sm;
-            if (r / 3 == c / 3) v += 2.0 * h.h_T[9 * (r / 3) + 3 * (r % 3) + (c % 3)];
-            band[(size_t)r * w + (nSm - 1) + c - r] = v;
-        }
-    dense_spd_inverse(*rb, s, band, nSm, nSm - 1, h.Hodd, "M_S- - delta S-");
+    const size_t n = (size_t)nSm, nn = n * n;
+    const Vec C = whitened_odd_scatter();
+    Vec X0(nn), Z0(nn), LiRM(nn, 0.0);
+    for (size_t e = 0; e < nn; ++e) {
+        Z0[e] = h.delta0 * C[e];
+        X0[e] = Z0[e];
+    }
+    for (size_t i = 0; i < n; ++i) X0[i + n * i] += 1.0;
+    // L^-1 by rows: LiRM[r n + c] = (L^-1)(r, c), block diagonal
+    for (int k = 0; k < nS; ++k)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) LiRM[(size_t)(3 * k + a) * n + 3 * k + b] = LkInv[9 * k + 3 * a + b];
+    DBuf<double> X, Xn, Z, Zn, Li, red(k::kRedBlocks), scal(1);
+    X.upload(X0, s);
+    Z.upload(Z0, s);
+    Li.upload(LiRM, s);
+    Xn.alloc(nn);
+    Zn.alloc(nn);
+    // ||Z||_F of the current factor, read on the host
+    auto norm2 = [&](const double* v) {
+        k::dot(v, v, nn, red.p, s);
+        k::reduce(red.p, scal.p, 0, s);
+        double r = 0.0;
+        RTE_HIP(hipMemcpyAsync(&r, scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        RTE_HIP(hipStreamSynchronize(s));
+        return r;
+    };
+    // X and every power of R are polynomials in the symmetric C, hence symmetric: as the
+    // row-major right operand of the GEMM they need no transpose
+    double zprev = norm2(Z.p);
+    bool converged = false;
+    for (int it = 0; it < 64 && !converged; ++it) {
+        k::gemm_f64((int)n, (int)n, (int)n, 1.0, Z.p, (int)n, Z.p, (int)n, 0.0, Zn.p, (int)n, s);
+        std::swap(Z.p, Zn.p);
+        const double z = norm2(Z.p);
+        if (!std::isfinite(z) || (it >= 4 && z >= zprev))
+            fail(RTE_E_ARG, "M_S- - delta S- is not positive definite (the inverse's product does not converge)");
+        zprev = z;
+        k::copy(X.p, Xn.p, nn, s);
+        k::gemm_f64((int)n, (int)n, (int)n, 1.0, X.p, (int)n, Z.p, (int)n, 1.0, Xn.p, (int)n, s);
+        std::swap(X.p, Xn.p);
+        converged = std::sqrt(z) <= 1e-18;
+    }
+    if (!converged) fail(RTE_E_ARG, "M_S- - delta S- is not positive definite (the inverse's product does not converge)");
+    // H = L^-T X L^-1: T = L^-T X (A = L^-T column-major is L^-1 by rows), H = T L^-1
+    k::gemm_f64((int)n, (int)n, (int)n, 1.0, Li.p, (int)n, X.p, (int)n, 0.0, Zn.p, (int)n, s);
+    h.Hodd.alloc(nn);
+    k::gemm_f64((int)n, (int)n, (int)n, 1.0, Zn.p, (int)n, Li.p, (int)n, 0.0, h.Hodd.p, (int)n, s);
+    k::symmetrize_lower(h.Hodd.p, (int)n, s);
+    RTE_HIP(hipStreamSynchronize(s));
     Hh = h.Hodd.download(s);
     condensed_from_H();
     h.have_exact = true;

@@ -10,7 +10,7 @@
 // direction has its own explicit values (formed once from the pattern's value classes).
 //
 // One CG iteration is three launches over (row tile, direction) work-groups of 256 rows:
-//   spmv    q = E_0 p, partial sums of p.q per tile;
+//   spmv    q = E_0 p, partial sums of p.q per tile (two directions per work-group);
 //   update  alpha = rz / p.q (the tile partials summed in a fixed order by every work-group of
 //           the direction, so all of them get the same bits), x += alpha p, r -= alpha q,
 //           partials of r.z and r.r (z = D^{-1} r);
@@ -139,12 +139,20 @@ __global__ __launch_bounds__(CTB) void cg_setup_kernel(int nS, int ntiles, const
     }
 }
 
-// q = E_0 p on a tile of one direction (4 waves of SPW consecutive 64-row slices each); partial
-// p.q.  With WMAX > 0 (the widest slice has at most WMAX slots) all of a slice's value and
-// column loads are issued together, and those of the wave's next slice before the gathers of
-// the current one, so that a wave keeps two slices' loads in flight; slots past a slice's width
-// re-read its last slot (in bounds) and count zero.  WMAX = 0: a plain loop.
-constexpr int SPW = 4;             // slices per wave in the SpMV
+// q = E_0 p on a tile of four 64-row slices (one per wave) for two directions at once, k and
+// k + 8 of the XCD's directions, which share the tile's column loads; partials p.q per
+// direction and tile.  With WMAX > 0 (the widest slice has at most WMAX slots) all of a slice's
+// column and value loads are issued together before the gathers; slots past a slice's width
+// re-read its last slot (in bounds) and count zero, so WMAX is instantiated at the exact widths
+// of the 2D and 3D P1 patterns.  The values are read once per launch and bypass the caches
+// (non-temporal loads), which keeps p, which the gathers re-read, resident.  WMAX = 0: a plain
+// loop.  A direction that has converged (done[k] < it) is not computed; its q and partial are
+// left as they are.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+
 template <int WMAX, typename T>
 __global__ __launch_bounds__(CTB) void cg_spmv_kernel(int n, int nS, int ntiles_s, int nslice, int it,
                                                       const int* __restrict__ sptr, const int* __restrict__ col,
@@ -152,65 +160,73 @@ __global__ __launch_bounds__(CTB) void cg_spmv_kernel(int n, int nS, int ntiles_
                                                       const T* __restrict__ P, T* __restrict__ Q,
                                                       const int* __restrict__ done, double* __restrict__ part) {
     __shared__ double sh[8];
-    int k, t;
-    if (!cg_tile(ntiles_s, nS, k, t)) return;
-    if (done && done[k] < it) return;
+    const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+    const int jp = local / ntiles_s, t = local % ntiles_s;
+    const int kA = xcd + 16 * jp, kB = kA + 8;
+    const bool actA = kA < nS && !(done && done[kA] < it);
+    const bool actB = kB < nS && !(done && done[kB] < it);
+    if (!actA && !actB) return;
+    // an inactive direction of the pair computes the active one's rows again, unstored
+    const int ka = actA ? kA : kB, kb = actB ? kB : ka;
     const int lane = threadIdx.x & 63;
-    const int s0 = (t * (CTB / 64) + (threadIdx.x >> 6)) * SPW;     // the wave's first slice
-    const T* pk = P + (size_t)n * k;
-    const T* vk = val + len * k;
-    double pq = 0.0;
+    const int sl = t * (CTB / 64) + (threadIdx.x >> 6);
+    const T* pa = P + (size_t)n * ka;
+    const T* pb = P + (size_t)n * kb;
+    const T* va = val + len * ka;
+    const T* vb = val + len * kb;
+    const bool in = sl < nslice;
+    const int g0 = in ? sptr[sl] : 0;
+    const int wd = in ? sptr[sl + 1] - g0 : 1;
+    const size_t base = (size_t)g0 * 64 + lane;
+    T accA = (T)0, accB = (T)0;
     if constexpr (WMAX > 0) {
-        int c[2][WMAX], w[2];
-        T v[2][WMAX];
-        // slice sl into buffer b (a slice past the end reads slice 0's first slot and counts zero)
-        auto load = [&](int b, int sl) {
-            const bool in = sl < nslice;
-            const int g0 = in ? sptr[sl] : 0;
-            const int wd = in ? sptr[sl + 1] - g0 : 1;
-            w[b] = in ? wd : 0;
-            const size_t base = (size_t)g0 * 64 + lane;
+        const int w = in ? wd : 0;
+        int c[WMAX];
+        T xa[WMAX], xb[WMAX];
 #pragma unroll
-            for (int j = 0; j < WMAX; ++j) {
-                const size_t q = base + 64 * (size_t)min(j, wd - 1);
-                c[b][j] = col[q];
-                v[b][j] = vk[q];
-            }
-        };
-        load(0, s0);
-#pragma unroll
-        for (int r = 0; r < SPW; ++r) {
-            const int b = r & 1;
-            if (r + 1 < SPW) load(b ^ 1, s0 + r + 1);
-            T pv[WMAX];
-#pragma unroll
-            for (int j = 0; j < WMAX; ++j) pv[j] = pk[c[b][j]];
-            T acc = (T)0;
-#pragma unroll
-            for (int j = 0; j < WMAX; ++j) acc += (j < w[b] ? v[b][j] : (T)0) * pv[j];
-            const int i = (s0 + r) * 64 + lane;
-            if (s0 + r < nslice && i < n) {
-                Q[(size_t)n * k + i] = acc;
-                pq += (double)pk[i] * (double)acc;
-            }
+        for (int j = 0; j < WMAX; ++j) {
+            const size_t q = base + 64 * (size_t)min(j, wd - 1);
+            c[j] = col[q];
+            xa[j] = ld_stream(va + q);
+            xb[j] = ld_stream(vb + q);
         }
-    } else {
-        for (int r = 0; r < SPW; ++r) {
-            const int sl = s0 + r;
-            if (sl >= nslice) break;
-            const int g0 = sptr[sl], w = sptr[sl + 1] - g0;
-            const size_t base = (size_t)g0 * 64 + lane;
-            T acc = (T)0;
-            for (int j = 0; j < w; ++j) acc += vk[base + 64 * j] * pk[col[base + 64 * j]];
-            const int i = sl * 64 + lane;
-            if (i < n) {
-                Q[(size_t)n * k + i] = acc;
-                pq += (double)pk[i] * (double)acc;
-            }
+        T ga[WMAX], gb[WMAX];
+#pragma unroll
+        for (int j = 0; j < WMAX; ++j) {
+            ga[j] = pa[c[j]];
+            gb[j] = pb[c[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < WMAX; ++j) {
+            accA += (j < w ? xa[j] : (T)0) * ga[j];
+            accB += (j < w ? xb[j] : (T)0) * gb[j];
+        }
+    } else if (in) {
+        for (int j = 0; j < wd; ++j) {
+            const size_t q = base + 64 * (size_t)j;
+            const int cj = col[q];
+            accA += ld_stream(va + q) * pa[cj];
+            accB += ld_stream(vb + q) * pb[cj];
         }
     }
-    pq = block_sum(pq, sh);
-    if (threadIdx.x == 0) part[(size_t)k * ntiles_s + t] = pq;
+    const int i = sl * 64 + lane;
+    double pqA = 0.0, pqB = 0.0;
+    if (in && i < n) {
+        if (actA) {
+            Q[(size_t)n * kA + i] = accA;
+            pqA = (double)pa[i] * (double)accA;
+        }
+        if (actB) {
+            Q[(size_t)n * kB + i] = accB;
+            pqB = (double)pb[i] * (double)accB;
+        }
+    }
+    pqA = block_sum(pqA, sh);
+    pqB = block_sum(pqB, sh);
+    if (threadIdx.x == 0) {
+        if (actA) part[(size_t)kA * ntiles_s + t] = pqA;
+        if (actB) part[(size_t)kB * ntiles_s + t] = pqB;
+    }
 }
 
 // alpha = rz / p.q; x += alpha p; r -= alpha q; partials of r.z and r.r
@@ -317,15 +333,21 @@ void cg_fill_dinv(const double* diag, size_t n, float* dinv, hipStream_t s) {
     RTE_CHECK_LAUNCH();
 }
 
-// tiles of the SpMV (4 waves of SPW slices each)
-int spmv_tiles(const CgArgs& a) { return (a.nslice + 4 * SPW - 1) / (4 * SPW); }
+// tiles of the SpMV (4 slices each)
+int spmv_tiles(const CgArgs& a) { return (a.nslice + 3) / 4; }
 
 template <typename T>
 void spmv_launch(const CgArgs& a, int it, const T* val, const T* X, T* Y, const int* done, double* part,
                  hipStream_t s) {
     const int ntiles_s = spmv_tiles(a);
-    const unsigned grid = (unsigned)ntiles_s * 8u * (unsigned)((a.nS + 7) / 8);
-    auto f = a.wmax <= 8 ? cg_spmv_kernel<8, T> : a.wmax <= 16 ? cg_spmv_kernel<16, T> : cg_spmv_kernel<0, T>;
+    // direction pairs (k, k + 8) per XCD: XCD x holds directions x, x + 8, ...
+    const int npair = ((a.nS + 7) / 8 + 1) / 2;
+    const unsigned grid = (unsigned)ntiles_s * 8u * (unsigned)npair;
+    auto f = a.wmax <= 7    ? cg_spmv_kernel<7, T>
+             : a.wmax <= 8  ? cg_spmv_kernel<8, T>
+             : a.wmax <= 15 ? cg_spmv_kernel<15, T>
+             : a.wmax <= 16 ? cg_spmv_kernel<16, T>
+                            : cg_spmv_kernel<0, T>;
     hipLaunchKernelGGL(f, dim3(grid), dim3(CTB), 0, s, a.n, a.nS, ntiles_s, a.nslice, it, a.sptr, a.col, val, a.len,
                        X, Y, done, part);
     RTE_CHECK_LAUNCH();

@@ -94,3 +94,35 @@ def test_failed_request_does_not_stop_the_loop():
     assert sorted(by_id) == list(range(len(reqs)))
     assert by_id[len(reqs) - 1].status == rte.RTE_E_PHYS and "E_PHYS" in by_id[len(reqs) - 1].error
     assert all(by_id[k].status == rte.RTE_OK for k in range(len(insts)))
+
+
+def test_served_distribution_equals_solo():
+    """Requests drawn like the served workload (uneven meshes up to 48 x 48, sphere meshes of
+    512 and 2048 triangles, anisotropy and scattering ratios across their ranges), arriving faster than they
+    can be served, so that their assemblies overlap the stepping of the others: every result
+    equals the solo solve bitwise.  A dense inverse whose rounding depends on what else runs on
+    the device would make some of them differ (the iteration stops at the first iterate below
+    the tolerance, so a last-bit change in an operator moves that iterate by up to the
+    condition number times the tolerance)."""
+    from paper_2102_09038_amd import rte, serve
+    insts = inputs.instance_distribution(count=14, seed=4, tol=1e-6, max_n=48)
+    o = rte.default_solve_opts(l=4, tol=1e-6, max_iter=2000, precision=rte.RTE_MIXED,
+                               odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_BANDED)
+    refs = []
+    for inst in insts:
+        h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_BANDED, mixed=2, odd_eig=0,
+                                     coarse_solver=rte.RTE_COARSE_QUICK)
+        U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+        h.solve(U, opts=o, raise_on_notconv=False)
+        torch.cuda.synchronize()
+        h.close()
+        refs.append(U)
+    reqs = [serve.Request(rid=k, inst=inst, arrival=0.02 * k) for k, inst in enumerate(insts)]
+    srv = serve.Server(int(64e9), o, max_slots=16, workers=4, keep_results=True)
+    done = srv.run(reqs)
+    srv.close()
+    assert len(done) == len(insts)
+    print(f"peak live slots {srv.peak_live}")
+    for r in done:
+        assert r.status == rte.RTE_OK, (r.rid, r.error)
+        assert torch.equal(r.U, refs[r.rid]), (r.rid, r.inst.name)
