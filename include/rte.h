@@ -161,9 +161,11 @@ typedef struct rte_assemble_opts {
                                  /*    E_0 solver only the FP32 block values are built      */
     int32_t odd_eig;             /* 1 (default): eigendecomposition of (S-, M_S-) at assembly
                                     (every odd solver); 0: skipped when sigma_s / sigma_t is
-                                    uniform, H = (M_S- - delta S-)^{-1} then comes from a dense
-                                    Cholesky inverse (the exact and condensed odd solves work,
-                                    the PCG odd solve fails with RTE_E_ARG); ignored (the
+                                    uniform, H = (M_S- - delta S-)^{-1} then comes from a
+                                    product of this library's GEMMs, bitwise the same in every
+                                    assembly (the exact and condensed odd solves work, the PCG
+                                    odd solve fails with RTE_E_ARG; RTE_E_ARG at assembly if
+                                    M_S- - delta S- is not positive definite); ignored (the
                                     decomposition is done) when the ratio varies             */
     int32_t coarse_solver;       /* rte_coarse_solver (default RTE_COARSE_AUTO); RTE_E_ARG if
                                     the chosen one does not fit                              */
@@ -389,10 +391,10 @@ rte_status rte_batch_poll(rte_batch* b, int32_t max_out, int32_t* slots, rte_sol
  * the preconditioner, correction and update), recaptured whenever the set of live slots
  * changes, on a stream the batch owns (ordered after the caller's stream's earlier work, and
  * the caller's later work after it).  0 (the default): the same launches are issued one by
- * one on the caller's stream.  The results are identical.  Graph mode must not run while
- * other threads of the process assemble handles (rte_assemble): that combination has
- * produced assembly inputs that were not positive definite, with no cause shown, so it is
- * not supported. */
+ * one on the caller's stream.  The results are identical, also while other threads of the
+ * process assemble handles (rte_assemble), whose results do not depend on what else runs when
+ * they use neither of the two rocSOLVER paths (the full odd eigendecomposition, odd_eig = 1,
+ * and the explicit coarse inverse, RTE_COARSE_INVERSE or RTE_COARSE_AUTO where it fits). */
 rte_status rte_batch_set_graphs(rte_batch* b, int32_t use_graphs);
 
 /* Slots still iterating, finished slots not yet polled, device bytes held by admitted slots. */

@@ -57,11 +57,10 @@ class Server:
                  keep_results: bool = False, on_done: Optional[Callable[[Request], None]] = None,
                  odd_eig: int = 0, use_graphs: bool = False, coarse_solver: int = rte.RTE_COARSE_QUICK):
         import torch
-        if use_graphs and workers > 0:
-            # graph replay beside concurrent assembly has reported assembly matrices that were
-            # not positive definite for requests that assemble correctly alone, and no cause
-            # has been shown; the combination is refused until one is
-            raise ValueError("graph mode is not supported while assembly workers run (use_graphs=False)")
+        # graph mode beside assembly workers: served runs once reported assembly inputs that
+        # were not positive definite; the inputs that failed came from a vendor factorisation
+        # whose result varied with concurrent device work, which assembly no longer uses for
+        # the served configuration (odd_eig = 0, quick coarse set-up)
         self.torch = torch
         self.budget = int(budget)
         self.opts = solve_opts

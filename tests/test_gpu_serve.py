@@ -96,14 +96,16 @@ def test_failed_request_does_not_stop_the_loop():
     assert all(by_id[k].status == rte.RTE_OK for k in range(len(insts)))
 
 
-def test_served_distribution_equals_solo():
+@pytest.mark.parametrize("graphs", [False, True])
+def test_served_distribution_equals_solo(graphs):
     """Requests drawn like the served workload (uneven meshes up to 48 x 48, sphere meshes of
     512 and 2048 triangles, anisotropy and scattering ratios across their ranges), arriving faster than they
     can be served, so that their assemblies overlap the stepping of the others: every result
     equals the solo solve bitwise.  A dense inverse whose rounding depends on what else runs on
     the device would make some of them differ (the iteration stops at the first iterate below
     the tolerance, so a last-bit change in an operator moves that iterate by up to the
-    condition number times the tolerance)."""
+    condition number times the tolerance).  Also with the 2D batch replaying captured graphs
+    while the workers assemble."""
     from paper_2102_09038_amd import rte, serve
     insts = inputs.instance_distribution(count=14, seed=4, tol=1e-6, max_n=48)
     o = rte.default_solve_opts(l=4, tol=1e-6, max_iter=2000, precision=rte.RTE_MIXED,
@@ -118,7 +120,7 @@ def test_served_distribution_equals_solo():
         h.close()
         refs.append(U)
     reqs = [serve.Request(rid=k, inst=inst, arrival=0.02 * k) for k, inst in enumerate(insts)]
-    srv = serve.Server(int(64e9), o, max_slots=16, workers=4, keep_results=True)
+    srv = serve.Server(int(64e9), o, max_slots=16, workers=4, keep_results=True, use_graphs=graphs)
     done = srv.run(reqs)
     srv.close()
     assert len(done) == len(insts)
