@@ -1056,13 +1056,12 @@ void Asm::coarse() {
             }
             return Gcache.emplace(delta, std::move(G)).first->second;
         };
-        // ordering: reverse Cuthill-McKee or the given vertex order, whichever is narrower
-        std::vector<int> perm = rcm(nRp, rp, ci);
-        std::vector<int> ident(nRp);
-        std::iota(ident.begin(), ident.end(), 0);
-        int sbw = band_width(perm, rp, ci);
-        const int sbw_nat = band_width(ident, rp, ci);
-        if (sbw_nat <= sbw) { perm = ident; sbw = sbw_nat; }
+        // ordering: the given vertex order unless reverse Cuthill-McKee narrows the band by
+        // more than 3% (host.cpp)
+        std::vector<int> perm;
+        bool natural = false;
+        const int sbw = band_order(nRp, rp, ci, perm, &natural);
+        h.perm_identity = natural;
         std::vector<int> iperm(nRp);
         for (int i = 0; i < nRp; ++i) iperm[perm[i]] = i;
         h.sbw = sbw;

@@ -147,6 +147,19 @@ std::vector<int> rcm(int n, const std::vector<int>& rp, const std::vector<int>& 
     return perm;
 }
 
+int band_order(int n, const std::vector<int>& rp, const std::vector<int>& ci, std::vector<int>& perm,
+               bool* identity) {
+    std::vector<int> ident(n);
+    std::iota(ident.begin(), ident.end(), 0);
+    const int bw_nat = band_width(ident, rp, ci);
+    std::vector<int> r = rcm(n, rp, ci);
+    const int bw_rcm = band_width(r, rp, ci);
+    const bool nat = 100 * ((long)bw_nat + 1) <= 103 * ((long)bw_rcm + 1);
+    perm = nat ? std::move(ident) : std::move(r);
+    if (identity) *identity = nat;
+    return nat ? bw_nat : bw_rcm;
+}
+
 void band_cholesky(std::vector<double>& A, int n, int bw) {
     const size_t w1 = (size_t)bw + 1;
     for (int j = 0; j < n; ++j) {
@@ -224,9 +237,8 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
         rp[i + 1] = rp[i] + (int)v.size();
         ci.insert(ci.end(), v.begin(), v.end());
     }
-    std::vector<int> ident(nRp);
-    std::iota(ident.begin(), ident.end(), 0);
-    const int sbw = std::min(band_width(rcm(nRp, rp, ci), rp, ci), band_width(ident, rp, ci));
+    std::vector<int> order;
+    const int sbw = band_order(nRp, rp, ci, order, nullptr);
     const size_t nnz = (size_t)rp[nRp], nc = dN * nRp, even = (size_t)nRp * nS;
     const size_t cbw = dN * sbw + dN - 1;
     size_t b = 0;

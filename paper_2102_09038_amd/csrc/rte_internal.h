@@ -180,6 +180,7 @@ struct Handle {
     DBuf<double> CLinv, CLinvT, CB, CG, cwork;
     DBuf<int> perm, iperm;         // [nRp] spatial reordering (reverse Cuthill-McKee) and inverse
     int sbw = 0;                   // spatial band width in that order
+    bool perm_identity = false;    // that order is the given vertex order (perm = identity)
 
     // ---- banded E_0 (RTE_E0_BANDED): one blocked band factor per direction
     bool have_e0_banded = false;

@@ -256,9 +256,20 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
         if (!h->have_e0_banded) fail(RTE_E_ARG, "banded E_0 factors were not prepared at assembly");
         if (!(lowp && h->L0f.p) && !h->L0.p)
             fail(RTE_E_ARG, "the FP64 band factors were dropped at assembly (mixed = 2)");
-        // the factors are in band (bandwidth-reducing) order: permute the columns of X into
-        // that order and the solution back in coalesced per-column passes, so that the
-        // solve itself reads and writes its vectors contiguously
+        // the factors are in band order: unless that is the given vertex order, permute the
+        // columns of X into it and the solution back in coalesced per-column passes, so that
+        // the solve itself reads and writes its vectors contiguously (gathering through the
+        // permutation inside the solve is slower than the two passes)
+        if (h->perm_identity && X != Y) {
+            Timed t(h, s, P_E0);
+            if (lowp && h->L0f.p)
+                k::band_solve_blk_f32(h->L0f.p, h->L0Uf.p, h->nRp, h->sbw, h->nS, h->e0_stride32, X, Y,
+                                      (size_t)h->nRp, nullptr, s, h->e0_g32);
+            else
+                k::band_solve_blk(h->L0.p, h->L0U.p, h->nRp, h->sbw, h->nS, h->e0_stride, X, Y, (size_t)h->nRp,
+                                  nullptr, s, h->e0_g64);
+            return;
+        }
         double* Xb = ws(h, W_BB);
         double* Yb = ws(h, W_BX);
         k::permute_cols(h->iperm.p, h->nRp, h->nS, X, Xb, true, s);
