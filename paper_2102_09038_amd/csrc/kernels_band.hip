@@ -208,13 +208,18 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
     constexpr int G = H * P;
     constexpr size_t bs = (size_t)G * 64 * VEC;      // elements per row block
     extern __shared__ double smem[];
-    double* win = smem;            // 2 W entries
-    double* D = smem + 2 * W;
+    // the y ring and the captured diagonal block hold the factor's type: FP64 factors keep
+    // every product and sum in FP64; FP32 factors (the mixed-precision preconditioner) take
+    // the band rows' dot products in FP32 (products and four partial sums, added to the FP64
+    // right-hand side), which spares a conversion per entry, and solve the diagonal block
+    // in FP64
+    FT* win = reinterpret_cast<FT*>(smem);              // 2 W entries
+    FT* D = reinterpret_cast<FT*>(smem + 2 * W);
     const int lane = threadIdx.x;
     const int nblk = (n + 63) / 64;
     const int Wm = W - 1;
     const int nstep = 2 * nblk;
-    for (int e = lane; e < 2 * W; e += 64) win[e] = 0.0;
+    for (int e = lane; e < 2 * W; e += 64) win[e] = (FT)0;
     // step st: forward row block st (st < nblk), else backward row block 2 nblk - 1 - st
     auto block_ptr = [&](int st) -> const GLOBAL FT* {
         return st < nblk ? BLs + (size_t)st * bs : BUs + (size_t)(nstep - 1 - st) * bs;
@@ -263,8 +268,8 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
         const GLOBAL V* cur = reinterpret_cast<const GLOBAL V*>(block_ptr(st));
         const GLOBAL V* nxt = reinterpret_cast<const GLOBAL V*>(block_ptr(min(st + 1, nstep - 1)));
         // the ring entries of this block's own rows are not known yet: zero
-        win[row & Wm] = 0.0;
-        win[(row & Wm) + W] = 0.0;
+        win[row & Wm] = (FT)0;
+        win[(row & Wm) + W] = (FT)0;
         // band offset t of this row touches ring entry yoff + t; it is part of the
         // diagonal block for t in [clo, clo + span) and is then stored at D[dbase + 64 t].
         // The range includes the stored 1 / L(r,r) (t = bw forward, 0 backward), which lands
@@ -274,10 +279,10 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
         const unsigned span = fwd ? (unsigned)lane + 1 : (unsigned)(64 - lane);
         const int dbase = fwd ? lane - 64 * (bw - lane) : 65 * lane;
         const int dump = 64 * 64 + lane;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        FT acc[4] = {(FT)0, (FT)0, (FT)0, (FT)0};
         constexpr int Q = 4;   // ring entries are read Q slots before their use
-        const double* yw = win + (yoff & Wm);
-        double yq[Q][VEC];
+        const FT* yw = win + (yoff & Wm);
+        FT yq[Q][VEC];
 #pragma unroll
         for (int j = 0; j < Q; ++j)
 #pragma unroll
@@ -286,7 +291,7 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
         for (int c = 0; c < G; ++c) {
             const int i = c % H;
             const V v = ring[i];
-            double yc[VEC];
+            FT yc[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) yc[e] = yq[c % Q][e];
             if (c + Q < G) {
@@ -296,7 +301,7 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 const int t = c * VEC + e;
-                const double val = (double)v[e];
+                const FT val = v[e];
                 acc[t & 3] = fma(-val, yc[e], acc[t & 3]);
                 // branch-free capture: lanes outside the diagonal block write their dump slot
                 D[((unsigned)(t - clo) < span) ? dbase + 64 * t : dump] = val;
@@ -308,15 +313,15 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
             __builtin_amdgcn_sched_barrier(0);
             ring[i] = (c + H < G) ? cur[(size_t)(c + H) * 64 + lane] : nxt[(size_t)i * 64 + lane];
         }
-        s += (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        s += ((double)acc[0] + (double)acc[1]) + ((double)acc[2] + (double)acc[3]);
         __syncthreads();
-        const double dinv = ok ? D[65 * lane] : 0.0;
+        const double dinv = ok ? (double)D[65 * lane] : 0.0;
         if (fwd) {
 #pragma unroll 1
             for (int c = 0; c < 4; ++c) {
                 double Lc[16];
 #pragma unroll
-                for (int uu = 0; uu < 16; ++uu) Lc[uu] = D[(16 * c + uu) * 64 + lane];
+                for (int uu = 0; uu < 16; ++uu) Lc[uu] = (double)D[(16 * c + uu) * 64 + lane];
 #pragma unroll
                 for (int uu = 0; uu < 16; ++uu) {
                     const int u = 16 * c + uu;
@@ -330,7 +335,7 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
             for (int c = 3; c >= 0; --c) {
                 double Uc[16];
 #pragma unroll
-                for (int uu = 0; uu < 16; ++uu) Uc[uu] = D[(16 * c + uu) * 64 + lane];
+                for (int uu = 0; uu < 16; ++uu) Uc[uu] = (double)D[(16 * c + uu) * 64 + lane];
 #pragma unroll
                 for (int uu = 15; uu >= 0; --uu) {
                     const int u = 16 * c + uu;
@@ -343,8 +348,8 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
         const double res = s * dinv;
         ylast = res;
         if (ok) {
-            win[row & Wm] = res;
-            win[(row & Wm) + W] = res;
+            win[row & Wm] = (FT)res;
+            win[(row & Wm) + W] = (FT)res;
             x[myidx] = res;
         }
         __syncthreads();

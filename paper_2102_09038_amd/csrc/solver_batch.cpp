@@ -43,7 +43,11 @@ struct Batch {
     int precision = -1;                 // of the slots (the grouped solve's factor type)
     int l = 0;                          // P_1 steps of the slots (they advance together)
     std::vector<BatchSlot> slots;
-    k::BandGroupPlan plan;
+    // the grouped E_0 band solves, one plan per pair of vectors it maps (0: W_ER -> W_ES, the
+    // first step of P_1; 1: W_ET2 -> W_EZ, the later ones): slots whose band order is the given
+    // vertex order are solved in place of those vectors, the others through W_BB / W_BX and the
+    // permutation passes
+    k::BandGroupPlan plan[2];
     // the coarse band solves (one system each) of the slots whose handle solves E_c by band
     // factors, one grouped launch
     k::BandGroupPlan cplan;
@@ -148,25 +152,27 @@ void for_slots(Batch* B, hipStream_t s, F&& f) {
 
 void rebuild_plan(Batch* B, hipStream_t s) {
     B->drain();      // the previous plan's job table may still be read by a launch in flight
-    std::vector<k::BandJob> jobs;
     const bool f32 = B->precision == RTE_MIXED;
-    for (auto& sl : B->slots) {
-        if (!sl.live || sl.o.e0_solver != RTE_E0_BANDED) continue;
-        Handle* h = sl.h;
-        k::BandJob j{};
-        j.BL = f32 ? static_cast<const void*>(h->L0f.p) : static_cast<const void*>(h->L0.p);
-        j.BU = f32 ? static_cast<const void*>(h->L0Uf.p) : static_cast<const void*>(h->L0U.p);
-        j.b = ws(h, W_BB);
-        j.x = ws(h, W_BX);
-        j.stride_sys = f32 ? h->e0_stride32 : h->e0_stride;
-        j.G = f32 ? h->e0_g32 : h->e0_g64;
-        j.stride_vec = (size_t)h->nRp;
-        j.n = h->nRp;
-        j.bw = h->sbw;
-        j.nsys = h->nS;
-        jobs.push_back(j);
+    for (int pi = 0; pi < 2; ++pi) {
+        std::vector<k::BandJob> jobs;
+        for (auto& sl : B->slots) {
+            if (!sl.live || sl.o.e0_solver != RTE_E0_BANDED) continue;
+            Handle* h = sl.h;
+            k::BandJob j{};
+            j.BL = f32 ? static_cast<const void*>(h->L0f.p) : static_cast<const void*>(h->L0.p);
+            j.BU = f32 ? static_cast<const void*>(h->L0Uf.p) : static_cast<const void*>(h->L0U.p);
+            j.b = h->perm_identity ? ws(h, pi == 0 ? W_ER : W_ET2) : ws(h, W_BB);
+            j.x = h->perm_identity ? ws(h, pi == 0 ? W_ES : W_EZ) : ws(h, W_BX);
+            j.stride_sys = f32 ? h->e0_stride32 : h->e0_stride;
+            j.G = f32 ? h->e0_g32 : h->e0_g64;
+            j.stride_vec = (size_t)h->nRp;
+            j.n = h->nRp;
+            j.bw = h->sbw;
+            j.nsys = h->nS;
+            jobs.push_back(j);
+        }
+        k::band_group_plan(jobs, f32, B->plan[pi], s);
     }
-    k::band_group_plan(jobs, f32, B->plan, s);
     std::vector<k::BandJob> cjobs;
     for (auto& sl : B->slots) {
         if (!sl.live) continue;
@@ -190,17 +196,18 @@ void rebuild_plan(Batch* B, hipStream_t s) {
     B->plan_valid = true;
 }
 
-// X -> Y = E_0^{-1} X for every live slot (x_of / y_of give the slot's vectors)
+// X -> Y = E_0^{-1} X for every live slot (x_of / y_of give the slot's vectors, which plan pi
+// of the grouped band solve maps)
 template <typename XF, typename YF>
-void grouped_e0inv(Batch* B, XF x_of, YF y_of, hipStream_t s) {
+void grouped_e0inv(Batch* B, int pi, XF x_of, YF y_of, hipStream_t s) {
     const bool lowp = B->precision == RTE_MIXED;
     for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
-        if (sl.o.e0_solver == RTE_E0_BANDED)
+        if (sl.o.e0_solver == RTE_E0_BANDED && !sl.h->perm_identity)
             k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, x_of(sl), ws(sl.h, W_BB), true, ls);
     });
-    k::band_group_run(B->plan, s);
+    k::band_group_run(B->plan[pi], s);
     for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
-        if (sl.o.e0_solver == RTE_E0_BANDED)
+        if (sl.o.e0_solver == RTE_E0_BANDED && !sl.h->perm_identity)
             k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, ws(sl.h, W_BX), y_of(sl), false, ls);
     });
     // the CG slots on the step's stream (each CG reads its live count on the host)
@@ -228,7 +235,7 @@ void enqueue_residuals(Batch* B, hipStream_t s) {
 // S_DOT2 and the update u_{n+1} = u_n + step, for every live slot
 void enqueue_precond_update(Batch* B, hipStream_t s) {
     const bool lowp = B->precision == RTE_MIXED;
-    grouped_e0inv(B, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ER); },
+    grouped_e0inv(B, 0, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ER); },
                   [](BatchSlot& sl) { return ws(sl.h, W_ES); }, s);
     for (int i = 1; i < B->l; ++i) {
         // the previous step's update z -= E_0^{-1}(...) (none before the first) and this
@@ -238,7 +245,7 @@ void enqueue_precond_update(Batch* B, hipStream_t s) {
             apply_E_core(sl.h, &sl.o, ws(sl.h, W_ES), nullptr, ws(sl.h, W_ER), ws(sl.h, W_ET2), sl.o.pcg_tol_inner,
                          ls, nullptr, lowp);
         });
-        grouped_e0inv(B, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ET2); },
+        grouped_e0inv(B, 1, [](BatchSlot& sl) { return (const double*)ws(sl.h, W_ET2); },
                       [](BatchSlot& sl) { return ws(sl.h, W_EZ); }, s);
     }
     // the last step's update, then the subspace correction: right-hand sides and the coarse
