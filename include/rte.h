@@ -393,8 +393,9 @@ rte_status rte_batch_poll(rte_batch* b, int32_t max_out, int32_t* slots, rte_sol
  * the caller's later work after it).  0 (the default): the same launches are issued one by
  * one on the caller's stream.  The results are identical, also while other threads of the
  * process assemble handles (rte_assemble), whose results do not depend on what else runs when
- * they use neither of the two rocSOLVER paths (the full odd eigendecomposition, odd_eig = 1,
- * and the explicit coarse inverse, RTE_COARSE_INVERSE or RTE_COARSE_AUTO where it fits). */
+ * they use none of the rocSOLVER paths (the full odd eigendecomposition, odd_eig = 1; the
+ * explicit coarse inverse, RTE_COARSE_INVERSE or RTE_COARSE_AUTO where it fits; the block
+ * coarse factorisation, RTE_COARSE_BLOCK or where the band does not fit). */
 rte_status rte_batch_set_graphs(rte_batch* b, int32_t use_graphs);
 
 /* Slots still iterating, finished slots not yet polled, device bytes held by admitted slots. */
