@@ -770,7 +770,8 @@ void Asm::odd_basis() {
 void Asm::condensed_from_H() {
     const int dn = d * nS;
     Vec G((size_t)dn * dn);
-    for (int k2 = 0; k2 < nS; ++k2)
+    // the columns of direction k2 per task (host threads; every entry is computed alone)
+    parallel_for(nS, [&](int k2) {
         for (int k1 = 0; k1 < nS; ++k1) {
             double Hb[9];
             for (int m = 0; m < 3; ++m)
@@ -784,6 +785,7 @@ void Asm::condensed_from_H() {
                     G[(n * nS + k1) + (size_t)dn * (n2 * nS + k2)] = v;
                 }
         }
+    });
     h.Gc.upload(G, s);
     // its diagonal d x d blocks G_kk(n, m) as coefficients of the stiffness classes (n <= m;
     // the class of n < m holds both orders): the mixed-precision path applies them exactly
@@ -798,7 +800,8 @@ void Asm::condensed_from_H() {
 // factors of 2 T_k): the odd scattering matrix in coordinates where M_S- is the identity
 Vec Asm::whitened_odd_scatter() const {
     Vec A((size_t)nSm * nSm);
-    for (int kb = 0; kb < nS; ++kb)
+    // rows 3 kb .. 3 kb + 2 per task (host threads; every entry is computed alone)
+    parallel_for(nS, [&](int kb) {
         for (int kc = 0; kc < nS; ++kc) {
             const double* Li = &LkInv[9 * kb];
             const double* Lj = &LkInv[9 * kc];
@@ -822,6 +825,7 @@ Vec Asm::whitened_odd_scatter() const {
                     A[(3 * kb + n) + (size_t)nSm * (3 * kc + m)] = v;
                 }
         }
+    });
     return A;
 }
 
