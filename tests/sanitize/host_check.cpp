@@ -167,6 +167,17 @@ void check_mesh(const Mesh& m, const char* name) {
     }
     for (int i = 0; i < n; ++i) check(seen[i] == 1, "permutation is a bijection");
     check(rte::band_width(perm, rp, ci) <= rte::band_width(ident, rp, ci), "RCM does not widen the band");
+    // the order of the band factors: the natural one unless RCM is more than 3% narrower, and
+    // the returned width is that order's
+    {
+        std::vector<int> order;
+        bool natural = false;
+        const int bw = rte::band_order(n, rp, ci, order, &natural);
+        const int bw_nat = rte::band_width(ident, rp, ci), bw_rcm = rte::band_width(perm, rp, ci);
+        check(bw == rte::band_width(order, rp, ci), "band_order returns its order's width");
+        check(natural == (100L * (bw_nat + 1) <= 103L * (bw_rcm + 1)), "natural order chosen within 3%");
+        check(natural ? order == ident : order == perm, "band_order returns the chosen order");
+    }
     // sliced ELL
     std::vector<int> sptr, col, epos;
     const size_t len = rte::sliced_ell(n, rp, ci, &sptr, &col, &epos);
