@@ -16,6 +16,8 @@ discretize   angular matrices (S+-, M_S+-, A_n, T_k, omega_k) and spatial P1/P0 
 operators    K+-, M+-, A, A^T, R, E, E_0, E_c, P_1^l, P_2 P_1 (Secs. 4-5)
 solver       the outer Richardson iteration (Sec. 5, Alg. 3)
 mixed        direct sparse LU of the full mixed system of Sec. 4 for tiny meshes
+mg           geometric multigrid V-cycle for the E_0 blocks on lattice meshes and CG
+             preconditioned by it (a reading of the multigrid remark of Sec. 5.5)
 
 Pins: every function is checked in ``tests/test_oracle_*.py`` against closed forms,
 invariants and special cases the paper or the mathematics fix (see each test's
