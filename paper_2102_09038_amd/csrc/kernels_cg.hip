@@ -353,37 +353,116 @@ void spmv_launch(const CgArgs& a, int it, const T* val, const T* X, T* Y, const 
     RTE_CHECK_LAUNCH();
 }
 
+// the phases of one solve: set-up, one iteration, the live-count read (its copy to the host
+// is waited for by the caller)
 template <typename T>
-void cg_solve_t(const CgArgs& a, const T* val, const T* dinv, T* R, T* P, T* Q, hipStream_t s) {
-    const int n = a.n, nS = a.nS;
-    const int ntiles = (n + CTB - 1) / CTB;
-    const unsigned grid = (unsigned)ntiles * 8u * (unsigned)((nS + 7) / 8);
-    double* part_a = a.part;                              // [2 nS ntiles]
-    double* part_b = a.part + (size_t)2 * nS * ntiles;    // [2 nS ntiles]
-    hipLaunchKernelGGL(cg_init_kernel<T>, dim3(grid), dim3(CTB), 0, s, n, nS, ntiles, a.B, a.X, R, P, dinv, part_a);
-    RTE_CHECK_LAUNCH();
-    hipLaunchKernelGGL(cg_setup_kernel, dim3(nS), dim3(CTB), 0, s, nS, ntiles, part_a, a.tol, a.rz, a.stop, a.done,
-                       a.iters);
-    RTE_CHECK_LAUNCH();
-    for (int it = 0; it < a.maxit; ++it) {
-        spmv_launch<T>(a, it, val, (const T*)P, Q, a.done, part_a, s);
-        hipLaunchKernelGGL(cg_update_kernel<T>, dim3(grid), dim3(CTB), 0, s, n, nS, ntiles, spmv_tiles(a), it,
-                           (const T*)P,
-                           (const T*)Q, R, a.X, dinv, (const double*)a.rz, (const int*)a.done, (const double*)part_a,
-                           part_b);
+struct CgRun {
+    const CgArgs& a;
+    const T *val, *dinv;
+    T *R, *P, *Q;
+    hipStream_t s;
+    int ntiles;
+    unsigned grid;
+    double *part_a, *part_b;
+    CgRun(const CgArgs& a_, const T* v, const T* d, T* r, T* p, T* q, hipStream_t s_)
+        : a(a_), val(v), dinv(d), R(r), P(p), Q(q), s(s_) {
+        ntiles = (a.n + CTB - 1) / CTB;
+        grid = (unsigned)ntiles * 8u * (unsigned)((a.nS + 7) / 8);
+        part_a = a.part;                                   // [2 nS ntiles]
+        part_b = a.part + (size_t)2 * a.nS * ntiles;       // [2 nS ntiles]
+    }
+    void start() {
+        hipLaunchKernelGGL(cg_init_kernel<T>, dim3(grid), dim3(CTB), 0, s, a.n, a.nS, ntiles, a.B, a.X, R, P, dinv,
+                           part_a);
         RTE_CHECK_LAUNCH();
-        hipLaunchKernelGGL(cg_dir_kernel<T>, dim3(grid), dim3(CTB), 0, s, n, nS, ntiles, it, P, (const T*)R, dinv,
+        hipLaunchKernelGGL(cg_setup_kernel, dim3(a.nS), dim3(CTB), 0, s, a.nS, ntiles, part_a, a.tol, a.rz, a.stop,
+                           a.done, a.iters);
+        RTE_CHECK_LAUNCH();
+    }
+    void iterate(int it) {
+        spmv_launch<T>(a, it, val, (const T*)P, Q, a.done, part_a, s);
+        hipLaunchKernelGGL(cg_update_kernel<T>, dim3(grid), dim3(CTB), 0, s, a.n, a.nS, ntiles, spmv_tiles(a), it,
+                           (const T*)P, (const T*)Q, R, a.X, dinv, (const double*)a.rz, (const int*)a.done,
+                           (const double*)part_a, part_b);
+        RTE_CHECK_LAUNCH();
+        hipLaunchKernelGGL(cg_dir_kernel<T>, dim3(grid), dim3(CTB), 0, s, a.n, a.nS, ntiles, it, P, (const T*)R, dinv,
                            a.rz, (const double*)a.stop, a.done, a.iters, (const double*)part_b);
         RTE_CHECK_LAUNCH();
-        const bool last = it + 1 == a.maxit;
-        if ((it + 1) % a.check_every == 0 || last) {
-            hipLaunchKernelGGL(cg_count_kernel, dim3(1), dim3(CTB), 0, s, nS, a.maxit, last ? 1 : 0, a.done, a.iters,
-                               a.active);
-            RTE_CHECK_LAUNCH();
-            RTE_HIP(hipMemcpyAsync(a.host_active, a.active, sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    // after iteration it: is this a check point (every check_every iterations, and the last)
+    bool check_point(int it) const { return (it + 1) % a.check_every == 0 || it + 1 == a.maxit; }
+    void count(int it) {
+        hipLaunchKernelGGL(cg_count_kernel, dim3(1), dim3(CTB), 0, s, a.nS, a.maxit, it + 1 == a.maxit ? 1 : 0,
+                           a.done, a.iters, a.active);
+        RTE_CHECK_LAUNCH();
+        RTE_HIP(hipMemcpyAsync(a.host_active, a.active, sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+};
+
+template <typename T>
+void cg_solve_t(const CgArgs& a, const T* val, const T* dinv, T* R, T* P, T* Q, hipStream_t s) {
+    CgRun<T> run(a, val, dinv, R, P, Q, s);
+    run.start();
+    for (int it = 0; it < a.maxit; ++it) {
+        run.iterate(it);
+        if (run.check_point(it)) {
+            run.count(it);
             RTE_HIP(hipStreamSynchronize(s));
             if (*a.host_active == 0) break;
         }
+    }
+}
+
+// every running solve takes iteration it on its stream; at a check point of any of them the
+// host waits for those that counted and retires the finished ones
+void cg_solve_many(std::vector<CgJob>& jobs) {
+    std::vector<CgRun<double>> r64;
+    std::vector<CgRun<float>> r32;
+    r64.reserve(jobs.size());
+    r32.reserve(jobs.size());
+    struct Ref { bool f32; size_t i; bool live; };
+    std::vector<Ref> refs;
+    for (auto& j : jobs) {
+        if (j.f32) {
+            r32.emplace_back(j.a, static_cast<const float*>(j.val), static_cast<const float*>(j.dinv),
+                             static_cast<float*>(j.R), static_cast<float*>(j.P), static_cast<float*>(j.Q), j.s);
+            refs.push_back({true, r32.size() - 1, true});
+        } else {
+            r64.emplace_back(j.a, static_cast<const double*>(j.val), static_cast<const double*>(j.dinv),
+                             static_cast<double*>(j.R), static_cast<double*>(j.P), static_cast<double*>(j.Q), j.s);
+            refs.push_back({false, r64.size() - 1, true});
+        }
+    }
+    for (auto& rf : refs) {
+        if (rf.f32) r32[rf.i].start();
+        else r64[rf.i].start();
+    }
+    for (int it = 0;; ++it) {
+        bool any = false;
+        for (size_t k = 0; k < refs.size(); ++k) {
+            Ref& rf = refs[k];
+            if (!rf.live || it >= jobs[k].a.maxit) {
+                rf.live = false;
+                continue;
+            }
+            any = true;
+            if (rf.f32) r32[rf.i].iterate(it);
+            else r64[rf.i].iterate(it);
+        }
+        if (!any) break;
+        std::vector<size_t> counted;
+        for (size_t k = 0; k < refs.size(); ++k) {
+            Ref& rf = refs[k];
+            if (!rf.live) continue;
+            const bool cp = rf.f32 ? r32[rf.i].check_point(it) : r64[rf.i].check_point(it);
+            if (!cp) continue;
+            if (rf.f32) r32[rf.i].count(it);
+            else r64[rf.i].count(it);
+            counted.push_back(k);
+        }
+        for (size_t k : counted) RTE_HIP(hipStreamSynchronize(jobs[k].s));
+        for (size_t k : counted)
+            if (*jobs[k].a.host_active == 0) refs[k].live = false;
     }
 }
 

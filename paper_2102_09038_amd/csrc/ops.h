@@ -146,6 +146,18 @@ void cg_fill_dinv(const double* diag, size_t n, float* dinv, hipStream_t s);
 // of the value type, n x nS); blocking (reads the live count every check_every iterations)
 void cg_solve(const CgArgs& a, const double* val, const double* dinv, double* R, double* P, double* Q, hipStream_t s);
 void cg_solve(const CgArgs& a, const float* val, const float* dinv, float* R, float* P, float* Q, hipStream_t s);
+// Several such solves (different handles) advanced in lockstep, each on its own stream, with
+// one host synchronisation per check interval for all of them; each solve's launches and
+// arithmetic are exactly those of cg_solve on its stream
+struct CgJob {
+    CgArgs a;
+    bool f32 = false;                 // value and vector type: FP32 (else FP64)
+    const void* val = nullptr;
+    const void* dinv = nullptr;
+    void *R = nullptr, *P = nullptr, *Q = nullptr;
+    hipStream_t s = nullptr;
+};
+void cg_solve_many(std::vector<CgJob>& jobs);
 // Y = E_0 X on every direction (FP64), the CG's own SpMV kernel
 void cg_spmv(const CgArgs& a, const double* val, const double* X, double* Y, hipStream_t s);
 

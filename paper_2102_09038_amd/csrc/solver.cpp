@@ -250,6 +250,39 @@ void residual_like(Handle* h, const rte_solve_opts* o, const double* X, const do
     apply_E_core(h, o, X, G, q0, Y, tol, s, pcg, lowp);
 }
 
+k::CgJob cg_job(Handle* h, const rte_solve_opts* o, const double* X, double* Y, bool lowp, hipStream_t s) {
+    const bool f32 = lowp;
+    cg_prepare(h, f32, s);
+    k::CgJob j;
+    k::CgArgs& a = j.a;
+    a.n = h->nRp;
+    a.nS = h->nS;
+    a.nslice = h->ell_nslice;
+    a.len = h->ell_len;
+    a.wmax = h->ell_wmax;
+    a.sptr = h->ell_sptr.p;
+    a.col = h->ell_col.p;
+    a.B = X;
+    a.X = Y;
+    a.tol = f32 ? std::max(o->cg_tol, 1e-6) : o->cg_tol;
+    a.maxit = o->cg_max_iter;
+    a.part = h->cg_part.p;
+    a.rz = h->cg_scal.p;
+    a.stop = h->cg_scal.p + 2 * (size_t)h->nS;
+    a.done = h->cg_state.p;
+    a.active = h->cg_state.p + h->nS;
+    a.iters = h->cg_iters.p;
+    a.host_active = reinterpret_cast<int*>(h->pinned + 32);
+    j.f32 = f32;
+    j.val = f32 ? static_cast<const void*>(h->ell_v32.p) : static_cast<const void*>(h->ell_v64.p);
+    j.dinv = f32 ? static_cast<const void*>(h->ell_dinv32.p) : static_cast<const void*>(h->ell_dinv64.p);
+    j.R = ws(h, W_CGR);
+    j.P = ws(h, W_CGP);
+    j.Q = ws(h, W_CGQ);
+    j.s = s;
+    return j;
+}
+
 void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s, int64_t* cgt,
            int* cgmax, bool lowp) {
     if (o->e0_solver == RTE_E0_BANDED) {
@@ -288,38 +321,16 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
     // CG on every direction block at once (kernels_cg.hip); in mixed precision its vectors and
     // block values are FP32 (dot products FP64) and it stops at a relative residual of
     // max(cg_tol, 1e-6), the FP32 floor of a preconditioner solve
-    const bool f32 = lowp;
-    cg_prepare(h, f32, s);
-    double* r = ws(h, W_CGR);
-    double* p = ws(h, W_CGP);
-    double* q = ws(h, W_CGQ);
+    k::CgJob j = cg_job(h, o, X, Y, lowp, s);
     DBuf<int>& iters = h->cg_iters;
-    k::CgArgs a;
-    a.n = h->nRp;
-    a.nS = h->nS;
-    a.nslice = h->ell_nslice;
-    a.len = h->ell_len;
-    a.wmax = h->ell_wmax;
-    a.sptr = h->ell_sptr.p;
-    a.col = h->ell_col.p;
-    a.B = X;
-    a.X = Y;
-    a.tol = f32 ? std::max(o->cg_tol, 1e-6) : o->cg_tol;
-    a.maxit = o->cg_max_iter;
-    a.part = h->cg_part.p;
-    a.rz = h->cg_scal.p;
-    a.stop = h->cg_scal.p + 2 * (size_t)h->nS;
-    a.done = h->cg_state.p;
-    a.active = h->cg_state.p + h->nS;
-    a.iters = iters.p;
-    a.host_active = reinterpret_cast<int*>(h->pinned + 32);
     {
         Timed t(h, s, P_E0);
-        if (f32)
-            k::cg_solve(a, h->ell_v32.p, h->ell_dinv32.p, reinterpret_cast<float*>(r), reinterpret_cast<float*>(p),
-                        reinterpret_cast<float*>(q), s);
+        if (j.f32)
+            k::cg_solve(j.a, static_cast<const float*>(j.val), static_cast<const float*>(j.dinv),
+                        static_cast<float*>(j.R), static_cast<float*>(j.P), static_cast<float*>(j.Q), s);
         else
-            k::cg_solve(a, h->ell_v64.p, h->ell_dinv64.p, r, p, q, s);
+            k::cg_solve(j.a, static_cast<const double*>(j.val), static_cast<const double*>(j.dinv),
+                        static_cast<double*>(j.R), static_cast<double*>(j.P), static_cast<double*>(j.Q), s);
     }
     if (cgt || cgmax) {
         std::vector<int> hi(h->nS);

@@ -205,14 +205,34 @@ void grouped_e0inv(Batch* B, int pi, XF x_of, YF y_of, hipStream_t s) {
         if (sl.o.e0_solver == RTE_E0_BANDED && !sl.h->perm_identity)
             k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, x_of(sl), ws(sl.h, W_BB), true, ls);
     });
+    // the CG slots: several run in lockstep on the lanes, beside the grouped band solve on s
+    // (each solve reads its live count on the host; one host wait per check for all of them)
+    std::vector<BatchSlot*> cg;
+    for (auto& sl : B->slots)
+        if (sl.live && sl.o.e0_solver == RTE_E0_CG) cg.push_back(&sl);
+    const int used = std::min((int)cg.size(), Batch::kLanes);
+    if (cg.size() >= 2) {
+        RTE_HIP(hipEventRecord(B->ev_fork, s));
+        for (int l = 0; l < used; ++l) RTE_HIP(hipStreamWaitEvent(B->lane[l], B->ev_fork, 0));
+    }
     k::band_group_run(B->plan[pi], s);
+    if (cg.size() == 1) {
+        e0inv(cg[0]->h, &cg[0]->o, x_of(*cg[0]), y_of(*cg[0]), s, nullptr, nullptr, lowp);
+    } else if (cg.size() >= 2) {
+        std::vector<k::CgJob> jobs;
+        jobs.reserve(cg.size());
+        for (size_t j = 0; j < cg.size(); ++j)
+            jobs.push_back(cg_job(cg[j]->h, &cg[j]->o, x_of(*cg[j]), y_of(*cg[j]), lowp, B->lane[j % used]));
+        k::cg_solve_many(jobs);
+        for (int l = 0; l < used; ++l) {
+            RTE_HIP(hipEventRecord(B->ev_join[l], B->lane[l]));
+            RTE_HIP(hipStreamWaitEvent(s, B->ev_join[l], 0));
+        }
+    }
     for_slots(B, s, [&](BatchSlot& sl, hipStream_t ls) {
         if (sl.o.e0_solver == RTE_E0_BANDED && !sl.h->perm_identity)
             k::permute_cols(sl.h->iperm.p, sl.h->nRp, sl.h->nS, ws(sl.h, W_BX), y_of(sl), false, ls);
     });
-    // the CG slots on the step's stream (each CG reads its live count on the host)
-    for (auto& sl : B->slots)
-        if (sl.live && sl.o.e0_solver == RTE_E0_CG) e0inv(sl.h, &sl.o, x_of(sl), y_of(sl), s, nullptr, nullptr, lowp);
 }
 
 // residuals r_n = (E - K+) u_n - q (FP64) of every live slot and the scalars of its

@@ -38,6 +38,9 @@ void cg_prepare(Handle* h, bool f32, hipStream_t s);
 // Y = E X [- q0] (q0 nullable), or with G = X S+ given: Y = (E - K+) X - q0  (Alg. 1)
 void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const double* G, const double* q0, double* Y,
                   double tol, hipStream_t s, int64_t* pcg, bool lowp);
+// the CG solve Y = E_0^{-1} X of a handle (its arguments and buffers, on stream s); lowp: FP32
+// vectors and block values, stopping at a relative residual of max(cg_tol, 1e-6)
+k::CgJob cg_job(Handle* h, const rte_solve_opts* o, const double* X, double* Y, bool lowp, hipStream_t s);
 // Y = E_0^{-1} X by the handle's banded factors or its CG (o->e0_solver); lowp: FP32 factors / CG
 void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s, int64_t* cgt,
            int* cgmax, bool lowp);

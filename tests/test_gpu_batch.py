@@ -234,3 +234,54 @@ def test_estimated_footprint_matches_admitted_slot(handles):
         b.step(1000)
         b.poll()
         b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_cg_slots_in_lockstep_equal_single_solves(prec):
+    """Slots whose E_0 is solved by CG advance together on the batch's stream lanes (more slots
+    than lanes, so lanes are shared), beside a banded slot; one CG slot stops at a small
+    iteration cap, so the slots leave the lockstep at different check points.  Every slot must
+    equal its solo solve bit for bit."""
+    from paper_2102_09038_amd import rte
+    insts = [
+        inputs.tiny_instance(n=4, sphere_level=1, g=0.5, ratio=0.9, n_even=0, n_odd=3, l=4),
+        inputs.tiny_instance(n=6, sphere_level=1, g=0.7, ratio=0.95, n_even=0, n_odd=3, l=4),
+        inputs.tiny_instance(n=2, sphere_level=1, g=0.6, ratio=0.9, dim=3, n_even=0, n_odd=1, l=4),
+        inputs.make_instance("cg-2d-24", 2, 24, 2, 0.8, 0.95, block=8, seed=31, n_even=0, n_odd=5, l=4),
+        inputs.make_instance("cg-3d-6", 3, 6, 1, 0.8, 0.9, block=2, seed=32, n_even=0, n_odd=3, l=4),
+        inputs.tiny_instance(n=8, sphere_level=1, g=0.4, ratio=0.9, n_even=0, n_odd=3, l=4, seed=9),
+    ]
+    e0 = [rte.RTE_E0_CG] * 5 + [rte.RTE_E0_BANDED]
+    hs = [rte.Handle.from_instance(i, e0_solver=e, mixed=1) for i, e in zip(insts, e0)]
+    precision = rte.RTE_FP64 if prec == "fp64" else rte.RTE_MIXED
+    opts = []
+    for k, e in enumerate(e0):
+        o = rte.default_solve_opts(l=4, tol=1e-10, max_iter=300, precision=precision, e0_solver=e,
+                                   odd_solver=rte.RTE_ODD_CONDENSED, cg_tol=1e-13,
+                                   cg_max_iter=7 if k == 2 else 20000)
+        opts.append(o)
+    ref = []
+    for h, o in zip(hs, opts):
+        U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+        st, info = h.solve(U, opts=o, raise_on_notconv=False)
+        torch.cuda.synchronize()
+        ref.append((st, U, info))
+    b = rte.Batch(max_slots=8)
+    outs = [torch.full((h.dims.nSp, h.dims.nRp), np.nan, dtype=torch.float64, device="cuda") for h in hs]
+    slots = [b.admit(h, U, o) for h, U, o in zip(hs, outs, opts)]
+    assert b.step(1000) == 0
+    torch.cuda.synchronize()
+    done = {s: (st, info) for s, st, info in b.poll()}
+    assert sorted(done) == sorted(slots)
+    for k, (s, U) in enumerate(zip(slots, outs)):
+        st, info = done[s]
+        st0, U0, i0 = ref[k]
+        print(f"[cg lockstep {prec} slot {k}] status {st} iters {info.iters} (alone {i0.iters}) "
+              f"rel_resid {info.rel_resid:.2e}", flush=True)
+        assert st == st0
+        assert info.iters == i0.iters
+        assert np.float64(info.rel_resid).tobytes() == np.float64(i0.rel_resid).tobytes()
+        assert torch.equal(U.view(torch.int64), U0.view(torch.int64))
+    b.close()
+    for h in hs:
+        h.close()
