@@ -457,6 +457,45 @@ def serving_runs(torch, rte, inputs, rates, requests, tol, warm=8, log=None, err
     return out
 
 
+def e0inv_3d(torch, rte, inputs, log):
+    """E_0^{-1} of the served form's 3D request (32^3 cubes in Kuhn tetrahedra, 512 sphere
+    triangles, g = 0.8) by the Jacobi CG and by the multigrid-preconditioned CG, FP32 to 1e-6
+    and FP64 to 1e-10, and its mixed solve to 1e-6 with the multigrid E_0."""
+    import numpy as np
+    inst = inputs.make_instance("req-3d-32-s512", 3, 32, 3, 0.8, 0.9, seed=1001, n_even=0, n_odd=5, l=4, tol=1e-6)
+    t0 = time.perf_counter()
+    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_MG, mixed=1, odd_eig=0,
+                                 coarse_solver=rte.RTE_COARSE_QUICK)
+    out = {"workload": "served 3D request: 32^3 cubes (Kuhn tetrahedra), 512 sphere triangles, g 0.8",
+           "n_R+": len(inst.vert), "n_S+": h.dims.nSp, "assembly_s": time.perf_counter() - t0}
+    B = torch.from_numpy(np.random.default_rng(91).standard_normal((h.dims.nSp, h.dims.nRp))).cuda()
+    X = torch.empty_like(B)
+    for e0, name in ((rte.RTE_E0_CG, "jacobi_cg"), (rte.RTE_E0_MG, "multigrid_cg")):
+        res = {}
+        for prec, pname, tol in ((rte.RTE_MIXED, "fp32", 1e-6), (rte.RTE_FP64, "fp64", 1e-10)):
+            o = rte.default_solve_opts(e0_solver=e0, precision=prec, cg_tol=tol, cg_max_iter=20000)
+            h.apply_E0inv(B, X, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.apply_E0inv(B, X, o)
+            torch.cuda.synchronize()
+            res[pname] = {"ms": 1e3 * (time.perf_counter() - t0), "cg_tol": tol,
+                          "max_iters": max(h.last_cg_iters())}
+            log(f"[3d E_0^-1] {name} {pname}: {res[pname]['ms']:.1f} ms, {res[pname]['max_iters']} iterations")
+        out[name] = res
+    o = rte.default_solve_opts(l=4, tol=1e-6, max_iter=400, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_MG,
+                               precision=rte.RTE_MIXED, cg_max_iter=2000)
+    U = torch.empty_like(B)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = h.solve(U, opts=o)
+    torch.cuda.synchronize()
+    out["mixed_solve_multigrid"] = {"s": time.perf_counter() - t0, "iters": info.iters, "rel_resid": info.rel_resid}
+    log(f"[3d solve] multigrid E_0, mixed: {info.iters} iterations in {out['mixed_solve_multigrid']['s']:.2f} s")
+    h.close()
+    return out
+
+
 def x_max(v):
     m = max(v)
     return int(m) if float(m).is_integer() else m
@@ -770,6 +809,8 @@ def main():
     h.close()
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+    # the 3D request's E_0^{-1}: Jacobi against multigrid-preconditioned CG
+    out["e0inv_3d_request"] = e0inv_3d(torch, rte, inputs, log)
     if not args.no_batched:
         # the batched form on 16 instances of its distribution (the full 64 are bench.py --only batch)
         out["batched"] = batched_form(torch, rte, inputs, 16, args.tol, log, with_server=False)

@@ -78,7 +78,19 @@ typedef enum rte_e0_solver {
                              (sliced-ELL storage, per-direction early exit); with
                              precision RTE_MIXED its vectors and values are FP32 (dot
                              products FP64) and it stops at max(cg_tol, 1e-6)          */
-    RTE_E0_BANDED = 1     /* banded Cholesky factors per direction, factored once      */
+    RTE_E0_BANDED = 1,    /* banded Cholesky factors per direction, factored once      */
+    RTE_E0_MG = 2         /* CG on every direction block at once, preconditioned by one
+                             geometric multigrid V-cycle per iteration (Sec. 5.5 names
+                             multigrid as the E_0 solver): lattice meshes only (the
+                             Freudenthal triangulation of a box, vertex i + m (j + m k),
+                             else RTE_E_ARG at assembly); nested lattices with the P1
+                             interpolant, Galerkin coarse blocks, four Jacobi-scaled
+                             Chebyshev steps before and after the coarse correction on
+                             [0.02 lam, lam], lam = Gershgorin's bound of D^-1 E_0, eight
+                             on the coarsest level on the same interval.  Levels are added
+                             while the cells per axis are even and at least 4.  Precision
+                             and stopping as RTE_E0_CG; the hierarchy is built at assembly
+                             (e0_solver = RTE_E0_MG)                                  */
 } rte_e0_solver;
 
 /* How P_1 approximates E^{-1} (Sec. 5.3).  The paper takes l steps of the preconditioned
@@ -153,7 +165,8 @@ typedef struct rte_assemble_opts {
                                     of (S+, M_S+)  (Sec. 5.4)                                */
     int32_t n_odd;               /* N- >= 1 odd: PCG preconditioner uses the top
                                     (N+1)(N+2)/2 eigenpairs of (S-, M_S-)  (Sec. 5.1)        */
-    int32_t e0_solver;           /* rte_e0_solver prepared at assembly (CG is always there)  */
+    int32_t e0_solver;           /* rte_e0_solver prepared at assembly (CG is always there;
+                                    BANDED and MG need it here)                              */
     int32_t mixed;               /* 1: also prepare BF16/FP32 operator copies; 2: the same,  */
                                  /*    and keep only the FP32 E_0 band factors (FP64 banded */
                                  /*    E_0 solves then fail with RTE_E_ARG; halves the      */
@@ -298,6 +311,15 @@ rte_status rte_apply_E(rte_handle* h, const rte_solve_opts* opts, const double* 
  * Enqueue only. */
 rte_status rte_apply_E0(rte_handle* h, const double* X, double* Y, void* hip_stream);
 
+/* Y = B X, one multigrid V-cycle per direction block (the preconditioner of RTE_E0_MG; the
+ * multigrid remark of Sec. 5.5): four Chebyshev steps from 0, the residual restricted by P^T,
+ * the coarser levels' cycle, the correction prolongated by P, four Chebyshev steps; eight on the
+ * coarsest level.  B is symmetric positive definite and fixed (linear in X).  Device FP64
+ * n_R+ x n_S+ column-major vectors, not aliased.  The handle must be assembled with
+ * e0_solver = RTE_E0_MG (else RTE_E_ARG).  Builds the hierarchy's FP64 data on the first call
+ * when the handle was assembled with mixed = 2 (then it allocates); otherwise enqueue only. */
+rte_status rte_apply_mg(rte_handle* h, const double* X, double* Y, void* hip_stream);
+
 /* Y = E_0^{-1} X, block by block over the directions (Sec. 5.3).  Device FP64 vectors;
  * with opts->precision == RTE_MIXED the banded solver uses FP32 factors. */
 rte_status rte_apply_E0inv(rte_handle* h, const rte_solve_opts* opts, const double* X,
@@ -339,8 +361,9 @@ rte_status rte_derived_outputs(rte_handle* h, const double* U_even, double* phi,
 /* Copy an assembled array to host memory, for inspection and tests.
  * which: 0 S+ [n_S+ x n_S+], 1 S- [n_S- x n_S-], 2 m_k [n_S+], 3 T_k [n_S+ x 9],
  * 4 q = l+ [n_R+ x n_S+], 5 even eigenvalues [d_N+], 6 even eigenvectors
- * [n_S+ x d_N+], 7 odd eigenvalues [n_S-].  host_bytes must equal the array size in
- * bytes (FP64).  Blocking. */
+ * [n_S+ x d_N+], 7 odd eigenvalues [n_S-] (all FP64), 8 the iterations every direction took
+ * in the last E_0^{-1} by CG (RTE_E0_CG or RTE_E0_MG; int32 [n_S+], RTE_E_ARG before the first).
+ * host_bytes must equal the array size in bytes.  Blocking. */
 rte_status rte_get_array(rte_handle* h, int32_t which, void* host_dst, size_t host_bytes);
 
 /* Release the handle (synchronises its stream first).  NULL is accepted.  RTE_E_HIP if a

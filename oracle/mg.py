@@ -35,8 +35,8 @@ import numpy as np
 import scipy.sparse as sp
 
 # smoother settings of the reading above
-NU = 2            # Chebyshev steps before and after the coarse correction
-LO = 0.15         # lower end of the smoothing interval, as a fraction of lam
+NU = 4            # Chebyshev steps before and after the coarse correction
+LO = 0.02         # lower end of the smoothing interval, as a fraction of lam
 NU_COARSE = 8     # Chebyshev steps on the coarsest level
 LO_COARSE = 0.02
 

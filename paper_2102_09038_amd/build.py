@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "librte.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels_dense.hip", "kernels_ops.hip", "kernels_band.hip", "kernels_mixed.hip", "kernels_cg.hip", "assemble.cpp", "solver.cpp",
+SOURCES = ["kernels_dense.hip", "kernels_ops.hip", "kernels_band.hip", "kernels_mixed.hip", "kernels_cg.hip", "kernels_mg.hip", "assemble.cpp", "solver.cpp",
            "solver_batch.cpp", "autotune.cpp", "derived.hip", "coarse_block.hip", "noalloc.hip", "host.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

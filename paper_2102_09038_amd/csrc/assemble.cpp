@@ -315,6 +315,7 @@ size_t Handle::footprint() const {
                Sp_f.bytes() + Sm_f.bytes() + Gc_bf.bytes() + coefD.bytes() + L0f.bytes() + L0Uf.bytes() + red.bytes() +
                scal.bytes();
     for (auto& w : ws) b += w.bytes();
+    for (auto& l : mgl) b += l.bytes();
     return b;
 }
 
@@ -403,6 +404,7 @@ struct Asm {
     void even_basis();
     void coarse();
     void e0_data();
+    void mg_hierarchy();
     void reduced_precision();
 };
 
@@ -1180,14 +1182,54 @@ void Asm::e0_data() {
         RTE_HIP(hipStreamSynchronize(s));
         if (hb) fail(RTE_E_ARG, "an E_0 block lost positive definiteness in the band factorisation");
         h.have_e0_banded = true;
-    } else if (o->e0_solver == RTE_E0_CG) {
+    } else if (o->e0_solver == RTE_E0_CG || o->e0_solver == RTE_E0_MG) {
         // the explicit block values of the CG: FP64 unless only the mixed form is wanted
         // (mixed = 2; an FP64 CG then builds them on first use), FP32 with mixed != 0
+        if (o->e0_solver == RTE_E0_MG) mg_hierarchy();
         if (o->mixed != 2) sv::cg_prepare(&h, false, s);
         if (o->mixed) sv::cg_prepare(&h, true, s);
+        if (o->e0_solver == RTE_E0_MG) {
+            if (o->mixed != 2) sv::mg_prepare(&h, false, s);
+            if (o->mixed) sv::mg_prepare(&h, true, s);
+        }
     } else {
         fail(RTE_E_ARG, "unknown e0_solver");
     }
+}
+
+// the multigrid hierarchy of the E_0 blocks (RTE_E0_MG): lattice meshes only; levels 1.. by
+// Galerkin products of the value classes (host), their sliced-ELL patterns and class values
+// uploaded (the per-direction values follow in mg_prepare)
+void Asm::mg_hierarchy() {
+    const int m = lattice_m(D);
+    if (!m) fail(RTE_E_ARG, "e0_solver RTE_E0_MG needs a lattice mesh (Freudenthal triangulation of a box)");
+    const std::vector<int> sizes = mg_level_sizes(m);
+    h.mgl.clear();
+    h.mgl.resize(sizes.size());
+    h.mgl[0].m = m;
+    h.mgl[0].n = nRp;
+    h.mgl[0].nnz = nnz;
+    std::vector<int> prp = rp, pci = ci;
+    Vec pcls = cls;
+    for (size_t l = 1; l < sizes.size(); ++l) {
+        MgHostLevel L = mg_coarsen(d, sizes[l - 1], h.ncls, prp, pci, pcls);
+        Handle::MgLevel& g = h.mgl[l];
+        g.m = L.m;
+        g.n = L.n;
+        g.nnz = L.rp[L.n];
+        std::vector<int> sptr, ecol, epos;
+        g.len = sliced_ell(L.n, L.rp, L.ci, &sptr, &ecol, &epos);
+        g.nslice = (L.n + 63) / 64;
+        for (int sl = 0; sl < g.nslice; ++sl) g.wmax = std::max(g.wmax, sptr[sl + 1] - sptr[sl]);
+        g.sptr.upload(sptr, s);
+        g.col.upload(ecol, s);
+        g.e.upload(epos, s);
+        g.cls.upload(L.cls, s);
+        prp = std::move(L.rp);
+        pci = std::move(L.ci);
+        pcls = std::move(L.cls);
+    }
+    h.mg_m = m;
 }
 
 // reduced-precision copies of the mixed-precision path, and the handle's small buffers

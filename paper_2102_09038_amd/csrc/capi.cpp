@@ -35,7 +35,8 @@ void check_opts(const rte_solve_opts* o) {
     if (o->precision != RTE_FP64 && o->precision != RTE_MIXED) rte::fail(RTE_E_ARG, "unknown precision");
     if (o->odd_solver != RTE_ODD_PCG && o->odd_solver != RTE_ODD_EXACT && o->odd_solver != RTE_ODD_CONDENSED)
         rte::fail(RTE_E_ARG, "unknown odd solver");
-    if (o->e0_solver != RTE_E0_CG && o->e0_solver != RTE_E0_BANDED) rte::fail(RTE_E_ARG, "unknown E_0 solver");
+    if (o->e0_solver != RTE_E0_CG && o->e0_solver != RTE_E0_BANDED && o->e0_solver != RTE_E0_MG)
+        rte::fail(RTE_E_ARG, "unknown E_0 solver");
     if (o->inner != RTE_INNER_RICHARDSON && o->inner != RTE_INNER_PCG) rte::fail(RTE_E_ARG, "unknown inner iteration");
     if (!(o->pcg_tol_resid > 0) || !(o->pcg_tol_inner > 0) || !(o->cg_tol > 0) || o->pcg_max_iter < 1 ||
         o->cg_max_iter < 1)
@@ -168,6 +169,15 @@ rte_status rte_apply_E0(rte_handle* hh, const double* X, double* Y, void* hip_st
         rte::Handle* h = as_handle(hh);
         if (!X || !Y) rte::fail(RTE_E_ARG, "null operand");
         rte::apply_E0(h, X, Y, as_stream(hip_stream));
+        return RTE_OK;
+    });
+}
+
+rte_status rte_apply_mg(rte_handle* hh, const double* X, double* Y, void* hip_stream) {
+    return guarded([&] {
+        rte::Handle* h = as_handle(hh);
+        if (!X || !Y) rte::fail(RTE_E_ARG, "null operand");
+        rte::apply_mg(h, X, Y, as_stream(hip_stream));
         return RTE_OK;
     });
 }
@@ -325,6 +335,11 @@ rte_status rte_get_array(rte_handle* hh, int32_t which, void* host_dst, size_t h
             case 5: src = h->h_lamp.data(); bytes = h->h_lamp.size() * 8; device = false; break;
             case 6: src = h->h_Wp.data(); bytes = h->h_Wp.size() * 8; device = false; break;
             case 7: src = h->h_lamm_full.data(); bytes = h->h_lamm_full.size() * 8; device = false; break;
+            case 8:
+                if (h->cg_iters.n < (size_t)h->nS) rte::fail(RTE_E_ARG, "no CG solve of E_0 has run");
+                src = h->cg_iters.p;
+                bytes = (size_t)h->nS * sizeof(int32_t);
+                break;
             default: rte::fail(RTE_E_ARG, "unknown array id");
         }
         if (bytes != host_bytes) rte::fail(RTE_E_ARG, "host_bytes does not match the array size");

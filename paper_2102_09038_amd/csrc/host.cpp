@@ -211,6 +211,156 @@ size_t sliced_ell(int n, const std::vector<int>& rp, const std::vector<int>& ci,
     return len;
 }
 
+int lattice_m(const rte_problem_desc* D) {
+    const int d = D->dim, nv = D->n_vert;
+    int m = (int)std::lround(std::pow((double)nv, 1.0 / d));
+    while (m > 1 && (d == 2 ? m * m : m * m * m) > nv) --m;
+    while ((d == 2 ? (m + 1) * (m + 1) : (m + 1) * (m + 1) * (m + 1)) <= nv) ++m;
+    if (m < 2 || (d == 2 ? m * m : m * m * m) != nv) return 0;
+    double lo[3], hi[3];
+    for (int a = 0; a < d; ++a) {
+        lo[a] = D->vert[a];
+        hi[a] = D->vert[(size_t)(nv - 1) * d + a];
+        if (!(hi[a] > lo[a])) return 0;
+    }
+    for (int v = 0; v < nv; ++v) {
+        int c = v;
+        for (int a = 0; a < d; ++a, c /= m) {
+            const double x = lo[a] + (hi[a] - lo[a]) * (c % m) / (m - 1);
+            if (std::fabs(D->vert[(size_t)v * d + a] - x) > 1e-12 * std::max(1.0, std::fabs(hi[a] - lo[a]))) return 0;
+        }
+    }
+    // every cell edge: lattice offset with entries in {0, 1} from its smaller-indexed end
+    const int nvc = d + 1;
+    if (D->n_cell != (d == 2 ? 2 : 6) * (int)std::pow(m - 1, d)) return 0;
+    for (int j = 0; j < D->n_cell; ++j)
+        for (int a = 0; a < nvc; ++a)
+            for (int b = 0; b < nvc; ++b) {
+                int u = D->cell[nvc * j + a], w = D->cell[nvc * j + b];
+                if (u >= w) continue;
+                for (int t = 0; t < d; ++t, u /= m, w /= m) {
+                    const int off = w % m - u % m;
+                    if (off != 0 && off != 1) return 0;
+                }
+            }
+    return m;
+}
+
+std::vector<int> mg_level_sizes(int m) {
+    std::vector<int> out{m};
+    while ((out.back() - 1) % 2 == 0 && out.back() - 1 >= 4) out.push_back((out.back() - 1) / 2 + 1);
+    return out;
+}
+
+MgHostLevel mg_coarsen(int d, int m, int ncls, const std::vector<int>& rp, const std::vector<int>& ci,
+                       const std::vector<double>& cls) {
+    MgHostLevel L;
+    L.m = (m - 1) / 2 + 1;
+    const int mc = L.m;
+    const int nc = d == 2 ? mc * mc : mc * mc * mc;
+    L.n = nc;
+    const int nnz_f = rp.back();
+    auto coords = [&](int v, int mm, int* c) {
+        for (int a = 0; a < d; ++a, v /= mm) c[a] = v % mm;
+    };
+    auto index = [&](const int* c, int mm) {
+        int v = 0;
+        for (int a = d - 1; a >= 0; --a) v = v * mm + c[a];
+        return v;
+    };
+    // the coarse P1 pattern: I and I +- e_S for every nonempty axis set S, in bounds
+    const int nsets = (1 << d) - 1;
+    L.rp.assign(nc + 1, 0);
+    std::vector<std::vector<int>> rows(nc);
+    for (int I = 0; I < nc; ++I) {
+        int c[3];
+        coords(I, mc, c);
+        std::vector<int>& r = rows[I];
+        r.push_back(I);
+        for (int S = 1; S <= nsets; ++S)
+            for (int sg = -1; sg <= 1; sg += 2) {
+                int q[3];
+                bool in = true;
+                for (int a = 0; a < d; ++a) {
+                    q[a] = c[a] + ((S >> a) & 1) * sg;
+                    in = in && q[a] >= 0 && q[a] < mc;
+                }
+                if (in) r.push_back(index(q, mc));
+            }
+        std::sort(r.begin(), r.end());
+        L.rp[I + 1] = L.rp[I] + (int)r.size();
+    }
+    L.ci.resize(L.rp[nc]);
+    for (int I = 0; I < nc; ++I) std::copy(rows[I].begin(), rows[I].end(), L.ci.begin() + L.rp[I]);
+    const int nnz_c = L.rp[nc];
+    L.cls.assign((size_t)ncls * nnz_c, 0.0);
+    // coarse parents of fine vertex f with their weights (1 at an even vertex, else 1/2 at the
+    // two ends of the coarse edge f bisects)
+    auto parents = [&](int f, int* pv, double* pw) {
+        int c[3], lo[3], hi[3];
+        coords(f, m, c);
+        for (int a = 0; a < d; ++a) {
+            lo[a] = c[a] / 2;
+            hi[a] = (c[a] + 1) / 2;
+        }
+        const int il = index(lo, mc), ih = index(hi, mc);
+        if (il == ih) {
+            pv[0] = il;
+            pw[0] = 1.0;
+            return 1;
+        }
+        pv[0] = il; pw[0] = 0.5;
+        pv[1] = ih; pw[1] = 0.5;
+        return 2;
+    };
+    for (int I = 0; I < nc; ++I) {
+        int c[3];
+        coords(I, mc, c);
+        // the fine vertices coarse vertex I interpolates to, with weights: 2I, and 2I +- e_S
+        int fv[32];
+        double fw[32];
+        int nf = 0;
+        {
+            int q[3];
+            for (int a = 0; a < d; ++a) q[a] = 2 * c[a];
+            fv[nf] = index(q, m);
+            fw[nf++] = 1.0;
+        }
+        for (int S = 1; S <= nsets; ++S)
+            for (int sg = -1; sg <= 1; sg += 2) {
+                int q[3];
+                bool in = true;
+                for (int a = 0; a < d; ++a) {
+                    q[a] = 2 * c[a] + ((S >> a) & 1) * sg;
+                    in = in && q[a] >= 0 && q[a] < m;
+                }
+                if (in) {
+                    fv[nf] = index(q, m);
+                    fw[nf++] = 0.5;
+                }
+            }
+        const int* cb = L.ci.data() + L.rp[I];
+        const int* ce = L.ci.data() + L.rp[I + 1];
+        for (int t = 0; t < nf; ++t) {
+            const int f = fv[t];
+            for (int e = rp[f]; e < rp[f + 1]; ++e) {
+                int pv[2];
+                double pw[2];
+                const int np = parents(ci[e], pv, pw);
+                for (int u = 0; u < np; ++u) {
+                    const int* hit = std::lower_bound(cb, ce, pv[u]);
+                    if (hit == ce || *hit != pv[u]) continue;    // an exact zero outside the pattern
+                    const size_t ec = (size_t)(hit - L.ci.data());
+                    const double w = fw[t] * pw[u];
+                    for (int cc = 0; cc < ncls; ++cc)
+                        L.cls[(size_t)cc * nnz_c + ec] += w * cls[(size_t)cc * nnz_f + e];
+                }
+            }
+        }
+    }
+    return L;
+}
+
 size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o, size_t* peak) {
     if (!D || !o) fail(RTE_E_ARG, "null descriptor or options");
     const int d = D->dim;
@@ -290,11 +440,29 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
     // inverse diagonals, three CG vectors and the per-tile partials
     const size_t ell = sliced_ell(nRp, rp, ci, nullptr, nullptr, nullptr);
     b += ell * 8 + ((size_t)nRp / 64 + 2) * 4;
-    if (o->e0_solver == RTE_E0_CG) {
+    if (o->e0_solver == RTE_E0_CG || o->e0_solver == RTE_E0_MG) {
         const size_t ntiles = ((size_t)nRp + 255) / 256;
         b += 3 * even * 8 + 4 * nS * ntiles * 8 + 3 * nS * 8 + (nS + 1) * 4;
         if (o->mixed != 2) b += nS * ell * 8 + even * 8;
         if (o->mixed) b += nS * ell * 4 + even * 4;
+    }
+    if (o->e0_solver == RTE_E0_MG) {
+        // per level: inverse diagonals and Chebyshev intervals per precision, five work vectors;
+        // levels 1..: the sliced-ELL pattern (P1 stencil widths 7 / 15), class values, explicit values
+        const int m = lattice_m(D);
+        if (m) {
+            const std::vector<int> sizes = mg_level_sizes(m);
+            const size_t per = (o->mixed != 2 ? 8 : 0) + (o->mixed ? 4 : 0);
+            const size_t w = d == 2 ? 7 : 15;
+            for (size_t l = 0; l < sizes.size(); ++l) {
+                const size_t nl = d == 2 ? (size_t)sizes[l] * sizes[l] : (size_t)sizes[l] * sizes[l] * sizes[l];
+                b += nS * nl * per + 2 * nS * 8 * 2 + 5 * nl * nS * 8;
+                if (l > 0) {
+                    const size_t len = (nl + 63) / 64 * 64 * w;
+                    b += 2 * len * 4 + (nl / 64 + 2) * 4 + (size_t)kMaxClasses * nl * w * 8 + nS * len * per;
+                }
+            }
+        }
     }
     // solver workspace: two odd-sized buffers, eleven even vectors, coarse vectors, reductions
     b += 2 * (size_t)nRm * nSm * 8 + 11 * even * 8 + 2 * nc * 8 + (1 << 16);

@@ -130,6 +130,27 @@ void band_cholesky(std::vector<double>& A, int n, int bw);
 size_t sliced_ell(int n, const std::vector<int>& rp, const std::vector<int>& ci, std::vector<int>* sptr,
                   std::vector<int>* col, std::vector<int>* epos);
 
+// ---- geometric multigrid for the E_0 blocks on lattice meshes (multigrid remark of Sec. 5.5)
+// The mesh is the Freudenthal (Kuhn) triangulation of a box when its vertices are the points of
+// an m^d lattice numbered i + m (j + m k) and every cell edge joins lattice points whose
+// difference has entries in {0, 1}.  Returns m, or 0 for any other mesh.
+int lattice_m(const rte_problem_desc* D);
+// Vertices per axis of the levels, finest first: a level is added while the cell count per
+// axis is even and at least 4.
+std::vector<int> mg_level_sizes(int m);
+// One coarse level: the P1 pattern of its lattice (CSR, sorted columns) and the Galerkin
+// products P^T C_c P of the finer level's value classes C_c ([ncls * nnz]); P is the P1
+// interpolant between the nested lattices.  The entries outside the coarse P1 pattern are
+// exact zeros (the supports of two coarse basis functions that share no coarse cell meet in
+// a null set) and are not formed.
+struct MgHostLevel {
+    int m = 0, n = 0;
+    std::vector<int> rp, ci;
+    std::vector<double> cls;
+};
+MgHostLevel mg_coarsen(int d, int m, int ncls, const std::vector<int>& rp, const std::vector<int>& ci,
+                       const std::vector<double>& cls);
+
 // Device bytes a handle of this problem holds once assembled with o and given the workspace
 // of a solve, and the peak during assembly (*peak, nullable).  Host work only.
 size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o, size_t* peak);

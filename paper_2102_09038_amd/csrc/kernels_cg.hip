@@ -22,6 +22,7 @@
 // that XCD's L2.
 #include <climits>
 
+#include "dev_reduce.h"
 #include "ops.h"
 
 namespace rte {
@@ -29,46 +30,11 @@ namespace {
 
 constexpr int CTB = 256;                 // threads (rows) per work-group: 4 slices of 64
 
-__device__ __forceinline__ bool cg_tile(int ntiles, int nS, int& k, int& t) {
-    const int b = blockIdx.x;
-    const int xcd = b & 7, local = b >> 3;
-    k = xcd + 8 * (local / ntiles);
-    t = local % ntiles;
-    return k < nS;
-}
+using dev::block_sum;
+using dev::partial_sum;
+using dev::wave_sum;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// sum over the work-group in a fixed order; the result is returned to every thread
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[w] = v;
-    __syncthreads();
-    const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    __syncthreads();
-    return r;
-}
-
-// sum of n partials in a fixed order (lane l takes l, l + 64, ...; then a fixed butterfly),
-// computed by every thread of the work-group, identical bits in every work-group
-__device__ __forceinline__ double partial_sum(const double* __restrict__ part, int n, double* sh) {
-    double v = 0.0;
-    if (threadIdx.x < 64)
-        for (int i = threadIdx.x; i < n; i += 64) v += part[i];
-    if (threadIdx.x < 64) v = wave_sum(v);
-    __syncthreads();
-    if (threadIdx.x == 0) sh[4] = v;
-    __syncthreads();
-    const double r = sh[4];
-    __syncthreads();
-    return r;
-}
+__device__ __forceinline__ bool cg_tile(int ntiles, int nS, int& k, int& t) { return dev::dir_tile(ntiles, nS, k, t); }
 
 // explicit values of every direction's block in the sliced ELL layout:
 // val[k * len + q] = sum_c coef[k, c] cls[c, e(q)] (0 on padding), dinv = 1 / diag
@@ -324,6 +290,18 @@ void cg_fill_values(const Handle* h, const int* ell_e, size_t len, float* val, h
                        ell_e, h->cls.p, h->coefE0.p, val);
     RTE_CHECK_LAUNCH();
 }
+void fill_block_values(int nS, size_t len, int nnz, int ncls, const int* ell_e, const double* cls,
+                       const double* coef, double* val, hipStream_t s) {
+    hipLaunchKernelGGL(cg_fill_kernel<double>, dim3(grid_of(len * nS)), dim3(256), 0, s, nS, len, nnz, ncls, ell_e, cls,
+                       coef, val);
+    RTE_CHECK_LAUNCH();
+}
+void fill_block_values(int nS, size_t len, int nnz, int ncls, const int* ell_e, const double* cls,
+                       const double* coef, float* val, hipStream_t s) {
+    hipLaunchKernelGGL(cg_fill_kernel<float>, dim3(grid_of(len * nS)), dim3(256), 0, s, nS, len, nnz, ncls, ell_e, cls,
+                       coef, val);
+    RTE_CHECK_LAUNCH();
+}
 void cg_fill_dinv(const double* diag, size_t n, double* dinv, hipStream_t s) {
     hipLaunchKernelGGL(cg_dinv_kernel<double>, dim3(grid_of(n)), dim3(256), 0, s, n, diag, dinv);
     RTE_CHECK_LAUNCH();
@@ -353,25 +331,22 @@ void spmv_launch(const CgArgs& a, int it, const T* val, const T* X, T* Y, const 
     RTE_CHECK_LAUNCH();
 }
 
-// the phases of one solve: set-up, one iteration, the live-count read (its copy to the host
-// is waited for by the caller)
+// the phases of one Jacobi-preconditioned solve: set-up and one iteration
 template <typename T>
-struct CgRun {
-    const CgArgs& a;
+struct CgRun : CgPhases {
     const T *val, *dinv;
     T *R, *P, *Q;
-    hipStream_t s;
     int ntiles;
     unsigned grid;
     double *part_a, *part_b;
     CgRun(const CgArgs& a_, const T* v, const T* d, T* r, T* p, T* q, hipStream_t s_)
-        : a(a_), val(v), dinv(d), R(r), P(p), Q(q), s(s_) {
+        : CgPhases(a_, s_), val(v), dinv(d), R(r), P(p), Q(q) {
         ntiles = (a.n + CTB - 1) / CTB;
         grid = (unsigned)ntiles * 8u * (unsigned)((a.nS + 7) / 8);
         part_a = a.part;                                   // [2 nS ntiles]
         part_b = a.part + (size_t)2 * a.nS * ntiles;       // [2 nS ntiles]
     }
-    void start() {
+    void start() override {
         hipLaunchKernelGGL(cg_init_kernel<T>, dim3(grid), dim3(CTB), 0, s, a.n, a.nS, ntiles, a.B, a.X, R, P, dinv,
                            part_a);
         RTE_CHECK_LAUNCH();
@@ -379,7 +354,7 @@ struct CgRun {
                            a.done, a.iters);
         RTE_CHECK_LAUNCH();
     }
-    void iterate(int it) {
+    void iterate(int it) override {
         spmv_launch<T>(a, it, val, (const T*)P, Q, a.done, part_a, s);
         hipLaunchKernelGGL(cg_update_kernel<T>, dim3(grid), dim3(CTB), 0, s, a.n, a.nS, ntiles, spmv_tiles(a), it,
                            (const T*)P, (const T*)Q, R, a.X, dinv, (const double*)a.rz, (const int*)a.done,
@@ -389,81 +364,91 @@ struct CgRun {
                            a.rz, (const double*)a.stop, a.done, a.iters, (const double*)part_b);
         RTE_CHECK_LAUNCH();
     }
-    // after iteration it: is this a check point (every check_every iterations, and the last)
-    bool check_point(int it) const { return (it + 1) % a.check_every == 0 || it + 1 == a.maxit; }
-    void count(int it) {
-        hipLaunchKernelGGL(cg_count_kernel, dim3(1), dim3(CTB), 0, s, a.nS, a.maxit, it + 1 == a.maxit ? 1 : 0,
-                           a.done, a.iters, a.active);
-        RTE_CHECK_LAUNCH();
-        RTE_HIP(hipMemcpyAsync(a.host_active, a.active, sizeof(int), hipMemcpyDeviceToHost, s));
-    }
 };
+
+std::unique_ptr<CgPhases> phases_of(const CgJob& j) {
+    if (j.mg) return mg_phases(j);
+    if (j.f32)
+        return std::make_unique<CgRun<float>>(j.a, static_cast<const float*>(j.val), static_cast<const float*>(j.dinv),
+                                              static_cast<float*>(j.R), static_cast<float*>(j.P),
+                                              static_cast<float*>(j.Q), j.s);
+    return std::make_unique<CgRun<double>>(j.a, static_cast<const double*>(j.val), static_cast<const double*>(j.dinv),
+                                           static_cast<double*>(j.R), static_cast<double*>(j.P),
+                                           static_cast<double*>(j.Q), j.s);
+}
+
+void run_one(CgPhases& run) {
+    run.start();
+    for (int it = 0; it < run.a.maxit; ++it) {
+        run.iterate(it);
+        if (run.check_point(it)) {
+            run.count(it);
+            RTE_HIP(hipStreamSynchronize(run.s));
+            if (*run.a.host_active == 0) break;
+        }
+    }
+}
 
 template <typename T>
 void cg_solve_t(const CgArgs& a, const T* val, const T* dinv, T* R, T* P, T* Q, hipStream_t s) {
     CgRun<T> run(a, val, dinv, R, P, Q, s);
-    run.start();
-    for (int it = 0; it < a.maxit; ++it) {
-        run.iterate(it);
-        if (run.check_point(it)) {
-            run.count(it);
-            RTE_HIP(hipStreamSynchronize(s));
-            if (*a.host_active == 0) break;
-        }
-    }
+    run_one(run);
 }
 
 // every running solve takes iteration it on its stream; at a check point of any of them the
 // host waits for those that counted and retires the finished ones
 void cg_solve_many(std::vector<CgJob>& jobs) {
-    std::vector<CgRun<double>> r64;
-    std::vector<CgRun<float>> r32;
-    r64.reserve(jobs.size());
-    r32.reserve(jobs.size());
-    struct Ref { bool f32; size_t i; bool live; };
-    std::vector<Ref> refs;
-    for (auto& j : jobs) {
-        if (j.f32) {
-            r32.emplace_back(j.a, static_cast<const float*>(j.val), static_cast<const float*>(j.dinv),
-                             static_cast<float*>(j.R), static_cast<float*>(j.P), static_cast<float*>(j.Q), j.s);
-            refs.push_back({true, r32.size() - 1, true});
-        } else {
-            r64.emplace_back(j.a, static_cast<const double*>(j.val), static_cast<const double*>(j.dinv),
-                             static_cast<double*>(j.R), static_cast<double*>(j.P), static_cast<double*>(j.Q), j.s);
-            refs.push_back({false, r64.size() - 1, true});
-        }
+    std::vector<std::unique_ptr<CgPhases>> runs;
+    runs.reserve(jobs.size());
+    for (auto& j : jobs) runs.push_back(phases_of(j));
+    if (runs.size() == 1) {
+        run_one(*runs[0]);
+        return;
     }
-    for (auto& rf : refs) {
-        if (rf.f32) r32[rf.i].start();
-        else r64[rf.i].start();
-    }
+    std::vector<char> live(runs.size(), 1);
+    for (auto& r : runs) r->start();
     for (int it = 0;; ++it) {
         bool any = false;
-        for (size_t k = 0; k < refs.size(); ++k) {
-            Ref& rf = refs[k];
-            if (!rf.live || it >= jobs[k].a.maxit) {
-                rf.live = false;
+        for (size_t k = 0; k < runs.size(); ++k) {
+            if (!live[k] || it >= runs[k]->a.maxit) {
+                live[k] = 0;
                 continue;
             }
             any = true;
-            if (rf.f32) r32[rf.i].iterate(it);
-            else r64[rf.i].iterate(it);
+            runs[k]->iterate(it);
         }
         if (!any) break;
         std::vector<size_t> counted;
-        for (size_t k = 0; k < refs.size(); ++k) {
-            Ref& rf = refs[k];
-            if (!rf.live) continue;
-            const bool cp = rf.f32 ? r32[rf.i].check_point(it) : r64[rf.i].check_point(it);
-            if (!cp) continue;
-            if (rf.f32) r32[rf.i].count(it);
-            else r64[rf.i].count(it);
+        for (size_t k = 0; k < runs.size(); ++k) {
+            if (!live[k] || !runs[k]->check_point(it)) continue;
+            runs[k]->count(it);
             counted.push_back(k);
         }
-        for (size_t k : counted) RTE_HIP(hipStreamSynchronize(jobs[k].s));
+        for (size_t k : counted) RTE_HIP(hipStreamSynchronize(runs[k]->s));
         for (size_t k : counted)
-            if (*jobs[k].a.host_active == 0) refs[k].live = false;
+            if (*runs[k]->a.host_active == 0) live[k] = 0;
     }
+}
+
+void cg_spmv_it(const CgArgs& a, int it, const double* val, const double* X, double* Y, hipStream_t s) {
+    spmv_launch<double>(a, it, val, X, Y, a.done, a.part, s);
+}
+void cg_spmv_it(const CgArgs& a, int it, const float* val, const float* X, float* Y, hipStream_t s) {
+    spmv_launch<float>(a, it, val, X, Y, a.done, a.part, s);
+}
+
+void cg_setup(const CgArgs& a, const double* part, hipStream_t s) {
+    const int ntiles = (a.n + CTB - 1) / CTB;
+    hipLaunchKernelGGL(cg_setup_kernel, dim3(a.nS), dim3(CTB), 0, s, a.nS, ntiles, part, a.tol, a.rz, a.stop, a.done,
+                       a.iters);
+    RTE_CHECK_LAUNCH();
+}
+
+void cg_count(const CgArgs& a, int it, hipStream_t s) {
+    hipLaunchKernelGGL(cg_count_kernel, dim3(1), dim3(CTB), 0, s, a.nS, a.maxit, it + 1 == a.maxit ? 1 : 0, a.done,
+                       a.iters, a.active);
+    RTE_CHECK_LAUNCH();
+    RTE_HIP(hipMemcpyAsync(a.host_active, a.active, sizeof(int), hipMemcpyDeviceToHost, s));
 }
 
 void cg_solve(const CgArgs& a, const double* val, const double* dinv, double* R, double* P, double* Q, hipStream_t s) {

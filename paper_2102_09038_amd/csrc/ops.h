@@ -1,6 +1,8 @@
 // Launchers of the sparse / Kronecker glue kernels (kernels_ops.hip) and of the
 // per-direction E_0 solvers (kernels_e0.hip).
 #pragma once
+#include <memory>
+
 #include "rte_internal.h"
 
 namespace rte {
@@ -140,23 +142,82 @@ struct CgArgs {
 // val[k len + q] = explicit value of entry q of block k from the pattern classes; dinv = 1/diag
 void cg_fill_values(const Handle* h, const int* ell_e, size_t len, double* val, hipStream_t s);
 void cg_fill_values(const Handle* h, const int* ell_e, size_t len, float* val, hipStream_t s);
+// the same from explicit class values cls [ncls * nnz] and coefficients coef [nS * ncls]
+void fill_block_values(int nS, size_t len, int nnz, int ncls, const int* ell_e, const double* cls,
+                       const double* coef, double* val, hipStream_t s);
+void fill_block_values(int nS, size_t len, int nnz, int ncls, const int* ell_e, const double* cls,
+                       const double* coef, float* val, hipStream_t s);
 void cg_fill_dinv(const double* diag, size_t n, double* dinv, hipStream_t s);
 void cg_fill_dinv(const double* diag, size_t n, float* dinv, hipStream_t s);
 // X = E_0^{-1} B, Jacobi-preconditioned CG on every direction block at once (vectors R, P, Q
 // of the value type, n x nS); blocking (reads the live count every check_every iterations)
 void cg_solve(const CgArgs& a, const double* val, const double* dinv, double* R, double* P, double* Q, hipStream_t s);
 void cg_solve(const CgArgs& a, const float* val, const float* dinv, float* R, float* P, float* Q, hipStream_t s);
+// pieces the multigrid-preconditioned CG shares with the Jacobi CG: the SpMV Y = E_0 X of the
+// directions still running at iteration it with its partials p.q (a.part), and the live count
+// with its copy to a.host_active (waited for by the caller)
+void cg_spmv_it(const CgArgs& a, int it, const double* val, const double* X, double* Y, hipStream_t s);
+void cg_spmv_it(const CgArgs& a, int it, const float* val, const float* X, float* Y, hipStream_t s);
+void cg_count(const CgArgs& a, int it, hipStream_t s);
+// per direction from the tile partials part ([nS ntiles] b.b, then [nS ntiles] r.z of the
+// start): rz_0, the stopping threshold tol^2 b.b and the running state
+void cg_setup(const CgArgs& a, const double* part, hipStream_t s);
+
+// ---- geometric multigrid V-cycle for the E_0 blocks (kernels_mg.hip)
+constexpr int kMgMaxLevels = 12;
+constexpr int kMgNu = 4;              // Chebyshev steps before and after the coarse correction
+constexpr int kMgNuCoarse = 8;        // Chebyshev steps on the coarsest level
+constexpr double kMgLo = 0.02;        // smoothing interval [lo lam, lam]
+constexpr double kMgLoCoarse = 0.02;
+struct MgLevelArgs {
+    int m = 0, n = 0, nslice = 0, wmax = 0;   // lattice vertices per axis, rows, slices, widest slice
+    size_t len = 0;                           // ELL entries per direction
+    const int *sptr = nullptr, *col = nullptr;
+    const void *val = nullptr, *dinv = nullptr;   // [nS * len], [nS * n] of the value type
+    const double* cheb = nullptr;             // [2 nS]: theta, delta of every direction
+    void *x = nullptr, *r = nullptr, *b = nullptr, *d0 = nullptr, *d1 = nullptr;   // [nS * n] each
+};
+struct MgArgs {
+    int d = 0, nS = 0, L = 0;
+    bool f32 = false;
+    MgLevelArgs lev[kMgMaxLevels];
+};
+// z = B r for every direction still running at iteration it (done[k] >= it, all when done is
+// null): r is lev[0].b; returns the buffer d of level 0 with z = lev[0].x + d (the last
+// smoothing step's sum is left to the caller, which fuses it).  Enqueue only.
+const void* mg_vcycle(const MgArgs& g, int it, const int* done, hipStream_t s);
+// Y = B X (FP64 vectors), one V-cycle per direction, through the cycle's buffers
+void mg_apply(const MgArgs& g, const double* X, double* Y, hipStream_t s);
+// the inverse diagonals and Chebyshev intervals of level l from its explicit values
+// (lo = the level's interval fraction); part is scratch of [nS * ceil(n / 256)] doubles
+void mg_level_setup(const MgArgs& g, int l, double lo, double* part, hipStream_t s);
+
+// one CG solve driven in phases, Jacobi (kernels_cg.hip) or multigrid (kernels_mg.hip)
+struct CgJob;
+struct CgPhases {
+    virtual ~CgPhases() = default;
+    virtual void start() = 0;
+    virtual void iterate(int it) = 0;
+    // after iteration it: a check point (every check_every iterations, and the last)
+    bool check_point(int it) const { return (it + 1) % a.check_every == 0 || it + 1 == a.maxit; }
+    void count(int it) { cg_count(a, it, s); }
+    const CgArgs& a;
+    hipStream_t s;
+    CgPhases(const CgArgs& a_, hipStream_t s_) : a(a_), s(s_) {}
+};
 // Several such solves (different handles) advanced in lockstep, each on its own stream, with
 // one host synchronisation per check interval for all of them; each solve's launches and
-// arithmetic are exactly those of cg_solve on its stream
+// arithmetic are exactly those of its solo run on its stream
 struct CgJob {
     CgArgs a;
     bool f32 = false;                 // value and vector type: FP32 (else FP64)
     const void* val = nullptr;
     const void* dinv = nullptr;
     void *R = nullptr, *P = nullptr, *Q = nullptr;
+    const MgArgs* mg = nullptr;       // multigrid preconditioner (else Jacobi with dinv)
     hipStream_t s = nullptr;
 };
+std::unique_ptr<CgPhases> mg_phases(const CgJob& j);
 void cg_solve_many(std::vector<CgJob>& jobs);
 // Y = E_0 X on every direction (FP64), the CG's own SpMV kernel
 void cg_spmv(const CgArgs& a, const double* val, const double* X, double* Y, hipStream_t s);

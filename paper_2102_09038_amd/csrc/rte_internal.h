@@ -166,6 +166,28 @@ struct Handle {
     DBuf<float> ell_v32, ell_dinv32;
     DBuf<double> cg_part, cg_scal;   // per-tile partials [4 nS ntiles]; rz [2 nS] and stop [nS]
     DBuf<int> cg_state;             // done [nS], active [1]
+    // E_0 by CG preconditioned by a geometric multigrid V-cycle (RTE_E0_MG; lattice meshes,
+    // kernels_mg.hip).  Level 0 is the fine pattern above; levels 1.. have their own sliced-ELL
+    // pattern and Galerkin class values.  Per precision, every level holds explicit values
+    // (level 0: the CG's), inverse diagonals and per direction the smoother's Chebyshev interval
+    // (theta, delta); the cycle's work vectors x, r, b, d0, d1 per level follow.
+    struct MgLevel {
+        int m = 0, n = 0, nnz = 0, nslice = 0, wmax = 0;
+        size_t len = 0;
+        DBuf<int> sptr, col, e;
+        DBuf<double> cls;
+        DBuf<double> v64, dinv64, cheb64;
+        DBuf<float> v32, dinv32;
+        DBuf<double> cheb32;
+        DBuf<unsigned char> work;
+        int work_f32 = -1;           // value type the work vectors are sized for (-1: none)
+        size_t bytes() const {
+            return sptr.bytes() + col.bytes() + e.bytes() + cls.bytes() + v64.bytes() + dinv64.bytes() +
+                   cheb64.bytes() + v32.bytes() + dinv32.bytes() + cheb32.bytes() + work.bytes();
+        }
+    };
+    int mg_m = 0;                  // lattice vertices per axis when the hierarchy exists, else 0
+    std::vector<MgLevel> mgl;
     DBuf<double> q;                // [nRp*nS] even load l+
     double qnorm = 0;
 
@@ -225,6 +247,7 @@ void apply_scatter(Handle* h, int parity, int dtin, const void* X, int dtout, vo
 void apply_E(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s,
              int64_t* pcg_iters);
 void apply_E0(Handle* h, const double* X, double* Y, hipStream_t s);
+void apply_mg(Handle* h, const double* X, double* Y, hipStream_t s);
 void apply_E0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s,
                  int64_t* cg_total, int* cg_max);
 void precond(Handle* h, const rte_solve_opts* o, int which, const double* r, double* out,

@@ -250,8 +250,94 @@ void residual_like(Handle* h, const rte_solve_opts* o, const double* X, const do
     apply_E_core(h, o, X, G, q0, Y, tol, s, pcg, lowp);
 }
 
-k::CgJob cg_job(Handle* h, const rte_solve_opts* o, const double* X, double* Y, bool lowp, hipStream_t s) {
+// the per-precision data of the multigrid hierarchy: values of levels 1.., inverse diagonals
+// and Chebyshev intervals of every level, the cycle's work vectors (built once)
+void mg_prepare(Handle* h, bool f32, hipStream_t s) {
+    if (!h->mg_m || h->mgl.empty())
+        fail(RTE_E_ARG, "e0_solver RTE_E0_MG needs a handle assembled with e0_solver = RTE_E0_MG");
+    if ((int)h->mgl.size() > k::kMgMaxLevels) fail(RTE_E_ARG, "multigrid: too many levels");
+    cg_prepare(h, f32, s);
+    const size_t nS = (size_t)h->nS;
+    const int L = (int)h->mgl.size();
+    bool fresh = false;
+    for (int l = 0; l < L; ++l) {
+        Handle::MgLevel& g = h->mgl[l];
+        if (f32 ? !g.dinv32.p : !g.dinv64.p) {
+            fresh = true;
+            if (l > 0) {
+                if (f32) {
+                    g.v32.alloc(nS * g.len);
+                    k::fill_block_values(h->nS, g.len, g.nnz, h->ncls, g.e.p, g.cls.p, h->coefE0.p, g.v32.p, s);
+                } else {
+                    g.v64.alloc(nS * g.len);
+                    k::fill_block_values(h->nS, g.len, g.nnz, h->ncls, g.e.p, g.cls.p, h->coefE0.p, g.v64.p, s);
+                }
+            }
+            if (f32) {
+                g.dinv32.alloc(nS * g.n);
+                g.cheb32.alloc(2 * nS);
+            } else {
+                g.dinv64.alloc(nS * g.n);
+                g.cheb64.alloc(2 * nS);
+            }
+        }
+        if (!g.work.p) g.work.alloc(5 * (size_t)g.n * nS * sizeof(double));
+    }
+    if (fresh) {
+        const k::MgArgs a = mg_args(h, f32);
+        DBuf<double> part(nS * (((size_t)h->mgl[0].n + 255) / 256));
+        for (int l = 0; l < L; ++l) k::mg_level_setup(a, l, l == L - 1 ? k::kMgLoCoarse : k::kMgLo, part.p, s);
+        RTE_HIP(hipStreamSynchronize(s));
+    }
+}
+
+k::MgArgs mg_args(Handle* h, bool f32) {
+    k::MgArgs a;
+    a.d = h->d;
+    a.nS = h->nS;
+    a.L = (int)h->mgl.size();
+    a.f32 = f32;
+    for (int l = 0; l < a.L; ++l) {
+        Handle::MgLevel& g = h->mgl[l];
+        k::MgLevelArgs& A = a.lev[l];
+        A.m = g.m;
+        A.n = g.n;
+        if (l == 0) {
+            A.nslice = h->ell_nslice;
+            A.wmax = h->ell_wmax;
+            A.len = h->ell_len;
+            A.sptr = h->ell_sptr.p;
+            A.col = h->ell_col.p;
+            A.val = f32 ? static_cast<const void*>(h->ell_v32.p) : static_cast<const void*>(h->ell_v64.p);
+        } else {
+            A.nslice = g.nslice;
+            A.wmax = g.wmax;
+            A.len = g.len;
+            A.sptr = g.sptr.p;
+            A.col = g.col.p;
+            A.val = f32 ? static_cast<const void*>(g.v32.p) : static_cast<const void*>(g.v64.p);
+        }
+        A.dinv = f32 ? static_cast<const void*>(g.dinv32.p) : static_cast<const void*>(g.dinv64.p);
+        A.cheb = f32 ? g.cheb32.p : g.cheb64.p;
+        const size_t vb = (size_t)g.n * h->nS * (f32 ? sizeof(float) : sizeof(double));
+        unsigned char* w = g.work.p;
+        A.x = w;
+        A.r = w + vb;
+        A.b = w + 2 * vb;
+        A.d0 = w + 3 * vb;
+        A.d1 = w + 4 * vb;
+    }
+    return a;
+}
+
+k::CgJob cg_job(Handle* h, const rte_solve_opts* o, const double* X, double* Y, bool lowp, hipStream_t s,
+                k::MgArgs* mg) {
     const bool f32 = lowp;
+    if (o->e0_solver == RTE_E0_MG) {
+        if (!mg) fail(RTE_E_ARG, "multigrid CG without room for its arguments");
+        mg_prepare(h, f32, s);
+        *mg = mg_args(h, f32);
+    }
     cg_prepare(h, f32, s);
     k::CgJob j;
     k::CgArgs& a = j.a;
@@ -280,6 +366,10 @@ k::CgJob cg_job(Handle* h, const rte_solve_opts* o, const double* X, double* Y, 
     j.P = ws(h, W_CGP);
     j.Q = ws(h, W_CGQ);
     j.s = s;
+    if (o->e0_solver == RTE_E0_MG) {
+        j.mg = mg;
+        j.a.check_every = 4;      // an iteration costs about five SpMVs: read the live count more often
+    }
     return j;
 }
 
@@ -318,19 +408,17 @@ void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipSt
         k::permute_cols(h->iperm.p, h->nRp, h->nS, Yb, Y, false, s);
         return;
     }
-    // CG on every direction block at once (kernels_cg.hip); in mixed precision its vectors and
-    // block values are FP32 (dot products FP64) and it stops at a relative residual of
-    // max(cg_tol, 1e-6), the FP32 floor of a preconditioner solve
-    k::CgJob j = cg_job(h, o, X, Y, lowp, s);
+    // CG on every direction block at once (kernels_cg.hip), Jacobi- or multigrid-preconditioned
+    // (kernels_mg.hip); in mixed precision its vectors and block values are FP32 (dot products
+    // FP64) and it stops at a relative residual of max(cg_tol, 1e-6), the FP32 floor of a
+    // preconditioner solve
+    k::MgArgs g;
+    k::CgJob j = cg_job(h, o, X, Y, lowp, s, &g);
     DBuf<int>& iters = h->cg_iters;
     {
         Timed t(h, s, P_E0);
-        if (j.f32)
-            k::cg_solve(j.a, static_cast<const float*>(j.val), static_cast<const float*>(j.dinv),
-                        static_cast<float*>(j.R), static_cast<float*>(j.P), static_cast<float*>(j.Q), s);
-        else
-            k::cg_solve(j.a, static_cast<const double*>(j.val), static_cast<const double*>(j.dinv),
-                        static_cast<double*>(j.R), static_cast<double*>(j.P), static_cast<double*>(j.Q), s);
+        std::vector<k::CgJob> one{j};
+        k::cg_solve_many(one);
     }
     if (cgt || cgmax) {
         std::vector<int> hi(h->nS);
@@ -459,6 +547,11 @@ void apply_E0(Handle* h, const double* X, double* Y, hipStream_t s) {
     a.col = h->ell_col.p;
     a.part = h->cg_part.p;
     k::cg_spmv(a, h->ell_v64.p, X, Y, s);
+}
+
+void apply_mg(Handle* h, const double* X, double* Y, hipStream_t s) {
+    mg_prepare(h, false, s);
+    k::mg_apply(mg_args(h, false), X, Y, s);
 }
 
 void apply_E0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s,

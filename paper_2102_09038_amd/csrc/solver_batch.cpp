@@ -120,7 +120,7 @@ size_t slot_bytes(Handle* h, const rte_solve_opts* o) {
     if (h->ws.size() < W_COUNT) h->ws.resize(W_COUNT);
     for (int id : kSlotWs)
         if (!h->ws[id].p) b += ws_bytes(h, id);
-    if (o->e0_solver == RTE_E0_CG)
+    if (o->e0_solver != RTE_E0_BANDED)
         for (int id : {W_CGR, W_CGP, W_CGQ})
             if (!h->ws[id].p) b += ws_bytes(h, id);
     return b;
@@ -209,7 +209,7 @@ void grouped_e0inv(Batch* B, int pi, XF x_of, YF y_of, hipStream_t s) {
     // (each solve reads its live count on the host; one host wait per check for all of them)
     std::vector<BatchSlot*> cg;
     for (auto& sl : B->slots)
-        if (sl.live && sl.o.e0_solver == RTE_E0_CG) cg.push_back(&sl);
+        if (sl.live && sl.o.e0_solver != RTE_E0_BANDED) cg.push_back(&sl);
     const int used = std::min((int)cg.size(), Batch::kLanes);
     if (cg.size() >= 2) {
         RTE_HIP(hipEventRecord(B->ev_fork, s));
@@ -220,9 +220,11 @@ void grouped_e0inv(Batch* B, int pi, XF x_of, YF y_of, hipStream_t s) {
         e0inv(cg[0]->h, &cg[0]->o, x_of(*cg[0]), y_of(*cg[0]), s, nullptr, nullptr, lowp);
     } else if (cg.size() >= 2) {
         std::vector<k::CgJob> jobs;
+        std::vector<k::MgArgs> mgs(cg.size());
         jobs.reserve(cg.size());
         for (size_t j = 0; j < cg.size(); ++j)
-            jobs.push_back(cg_job(cg[j]->h, &cg[j]->o, x_of(*cg[j]), y_of(*cg[j]), lowp, B->lane[j % used]));
+            jobs.push_back(
+                cg_job(cg[j]->h, &cg[j]->o, x_of(*cg[j]), y_of(*cg[j]), lowp, B->lane[j % used], &mgs[j]));
         k::cg_solve_many(jobs);
         for (int l = 0; l < used; ++l) {
             RTE_HIP(hipEventRecord(B->ev_join[l], B->lane[l]));
@@ -346,11 +348,14 @@ void batch_destroy(Batch* B) { delete B; }
 int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, double* U, hipStream_t s) {
     if (o->e0_solver == RTE_E0_BANDED && !h->have_e0_banded)
         fail(RTE_E_ARG, "a banded E_0 slot needs a handle assembled with e0_solver = RTE_E0_BANDED");
-    if (o->e0_solver != RTE_E0_BANDED && o->e0_solver != RTE_E0_CG) fail(RTE_E_ARG, "unknown E_0 solver");
-    if (o->e0_solver == RTE_E0_CG && B->use_graphs) fail(RTE_E_ARG, "graph mode needs banded E_0 slots");
+    if (o->e0_solver != RTE_E0_BANDED && o->e0_solver != RTE_E0_CG && o->e0_solver != RTE_E0_MG)
+        fail(RTE_E_ARG, "unknown E_0 solver");
+    if (o->e0_solver == RTE_E0_MG && !h->mg_m)
+        fail(RTE_E_ARG, "a multigrid E_0 slot needs a handle assembled with e0_solver = RTE_E0_MG");
+    if (o->e0_solver != RTE_E0_BANDED && B->use_graphs) fail(RTE_E_ARG, "graph mode needs banded E_0 slots");
     if (o->odd_solver == RTE_ODD_PCG) fail(RTE_E_ARG, "batch slots use the exact or condensed odd solve");
     if (o->inner != RTE_INNER_RICHARDSON) fail(RTE_E_ARG, "batch slots use the Richardson inner iteration");
-    if (o->precision == RTE_MIXED && !(h->have_mixed && (h->L0f.p || o->e0_solver == RTE_E0_CG)))
+    if (o->precision == RTE_MIXED && !(h->have_mixed && (h->L0f.p || o->e0_solver != RTE_E0_BANDED)))
         fail(RTE_E_ARG, "a mixed-precision slot needs a handle assembled with mixed != 0");
     if (o->precision == RTE_FP64 && o->e0_solver == RTE_E0_BANDED && !h->L0.p)
         fail(RTE_E_ARG, "an FP64 slot needs the FP64 band factors");
@@ -367,9 +372,11 @@ int batch_admit(Batch* B, Handle* h, const rte_solve_opts* o, const double* U0, 
     const size_t bytes = slot_bytes(h, o);
     if (B->budget && B->used_bytes + bytes > B->budget) fail(RTE_E_NOMEM, "the batch's device-memory budget is full");
     for (int wid : kSlotWs) ws(h, wid);
-    if (o->e0_solver == RTE_E0_CG) {
-        // the CG's block values and vectors now, so that stepping allocates nothing
+    if (o->e0_solver != RTE_E0_BANDED) {
+        // the CG's block values and vectors (and the multigrid's data) now, so that stepping
+        // allocates nothing
         cg_prepare(h, o->precision == RTE_MIXED, s);
+        if (o->e0_solver == RTE_E0_MG) mg_prepare(h, o->precision == RTE_MIXED, s);
         for (int wid : {W_CGR, W_CGP, W_CGQ}) ws(h, wid);
     }
     B->precision = o->precision;

@@ -39,8 +39,14 @@ void cg_prepare(Handle* h, bool f32, hipStream_t s);
 void apply_E_core(Handle* h, const rte_solve_opts* o, const double* X, const double* G, const double* q0, double* Y,
                   double tol, hipStream_t s, int64_t* pcg, bool lowp);
 // the CG solve Y = E_0^{-1} X of a handle (its arguments and buffers, on stream s); lowp: FP32
-// vectors and block values, stopping at a relative residual of max(cg_tol, 1e-6)
-k::CgJob cg_job(Handle* h, const rte_solve_opts* o, const double* X, double* Y, bool lowp, hipStream_t s);
+// vectors and block values, stopping at a relative residual of max(cg_tol, 1e-6).  With
+// o->e0_solver == RTE_E0_MG the multigrid preconditioner's arguments go to *mg, which must
+// outlive the solve
+k::CgJob cg_job(Handle* h, const rte_solve_opts* o, const double* X, double* Y, bool lowp, hipStream_t s,
+                k::MgArgs* mg);
+// the multigrid hierarchy's per-precision data (built once) and its launch arguments
+void mg_prepare(Handle* h, bool f32, hipStream_t s);
+k::MgArgs mg_args(Handle* h, bool f32);
 // Y = E_0^{-1} X by the handle's banded factors or its CG (o->e0_solver); lowp: FP32 factors / CG
 void e0inv(Handle* h, const rte_solve_opts* o, const double* X, double* Y, hipStream_t s, int64_t* cgt,
            int* cgmax, bool lowp);

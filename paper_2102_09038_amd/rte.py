@@ -19,10 +19,10 @@ RTE_OK, RTE_E_ARG, RTE_E_PHYS, RTE_E_MESH, RTE_E_NOMEM, RTE_E_HIP, RTE_E_NOTCONV
 RTE_FP64, RTE_MIXED = 0, 1
 RTE_DT_F64, RTE_DT_F32, RTE_DT_BF16 = 0, 1, 2
 RTE_ODD_PCG, RTE_ODD_EXACT, RTE_ODD_CONDENSED = 0, 1, 2
-RTE_E0_CG, RTE_E0_BANDED = 0, 1
+RTE_E0_CG, RTE_E0_BANDED, RTE_E0_MG = 0, 1, 2
 RTE_INNER_RICHARDSON, RTE_INNER_PCG = 0, 1
 RTE_COARSE_AUTO, RTE_COARSE_INVERSE, RTE_COARSE_BAND, RTE_COARSE_BLOCK, RTE_COARSE_QUICK = 0, 1, 2, 3, 4
-ARRAY_SP, ARRAY_SM, ARRAY_M, ARRAY_T, ARRAY_Q, ARRAY_LAMP, ARRAY_WP, ARRAY_LAMM = range(8)
+ARRAY_SP, ARRAY_SM, ARRAY_M, ARRAY_T, ARRAY_Q, ARRAY_LAMP, ARRAY_WP, ARRAY_LAMM, ARRAY_CG_ITERS = range(9)
 STATUS_NAMES = ["OK", "E_ARG", "E_PHYS", "E_MESH", "E_NOMEM", "E_HIP", "E_NOTCONV", "E_NONFINITE"]
 
 
@@ -93,6 +93,7 @@ EXPORTS = {
     "rte_apply_E": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_apply_E0": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_apply_E0inv": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rte_apply_mg": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rte_precond": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_int32, C.c_void_p, C.c_void_p,
                               C.c_void_p]),
     "rte_solve": (C.c_int, [C.c_void_p, C.POINTER(rte_solve_opts), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -293,6 +294,12 @@ class Handle:
         _check(lib.rte_get_array(self.h, which, out.ctypes.data, out.nbytes))
         return out
 
+    def last_cg_iters(self) -> list:
+        """Iterations every direction took in the last E_0^{-1} by CG."""
+        out = np.empty(self.dims.nSp, dtype=np.int32)
+        _check(lib.rte_get_array(self.h, ARRAY_CG_ITERS, out.ctypes.data, out.nbytes))
+        return out.tolist()
+
     # --- operators on torch device tensors (column-major matrices are passed as the
     #     transposed-contiguous storage: a (n_rows, n_cols) Fortran matrix == a torch tensor
     #     of shape (n_cols, n_rows) contiguous)
@@ -311,6 +318,9 @@ class Handle:
 
     def apply_E0(self, X, Y, stream=None):
         _check(lib.rte_apply_E0(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), _stream(stream)))
+
+    def apply_mg(self, X, Y, stream=None):
+        _check(lib.rte_apply_mg(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), _stream(stream)))
 
     def apply_E0inv(self, X, Y, opts=None, stream=None):
         o = opts or default_solve_opts()

@@ -23,6 +23,8 @@ import threading
 import time
 from typing import Callable, List, Optional
 
+import numpy as np
+
 from . import rte
 
 
@@ -46,6 +48,22 @@ class Request:
         return self.done_at - self.arrival
 
 
+def _is_lattice(vert) -> bool:
+    """vert are the points of an m^d lattice of a box, numbered i + m (j + m k) (the meshes the
+    multigrid E_0 solve accepts; the library checks the cells itself)."""
+    nv, d = vert.shape
+    m = int(round(nv ** (1.0 / d)))
+    if m < 2 or m ** d != nv:
+        return False
+    lo, hi = vert.min(axis=0), vert.max(axis=0)
+    idx = np.arange(nv)
+    for a in range(d):
+        c = (idx // m ** a) % m
+        if not np.allclose(vert[:, a], lo[a] + (hi[a] - lo[a]) * c / (m - 1), rtol=0, atol=1e-12):
+            return False
+    return True
+
+
 class Server:
     """One lockstep batch plus assembly workers.
 
@@ -64,9 +82,12 @@ class Server:
         self.torch = torch
         self.budget = int(budget)
         self.opts = solve_opts
-        # the same options with the CG E_0 solve, for the requests that use it
+        # the same options with the CG E_0 solves (multigrid-preconditioned on lattice meshes,
+        # Jacobi otherwise), for the requests that use them
         self.opts_cg = rte.rte_solve_opts.from_buffer_copy(solve_opts)
         self.opts_cg.e0_solver = rte.RTE_E0_CG
+        self.opts_mg = rte.rte_solve_opts.from_buffer_copy(solve_opts)
+        self.opts_mg.e0_solver = rte.RTE_E0_MG
         self.batch = rte.Batch(max_slots=max_slots, hbm_budget=0, use_graphs=use_graphs)
         self.batch_cg = rte.Batch(max_slots=max_slots, hbm_budget=0, use_graphs=False)
         self.workers = workers
@@ -89,8 +110,11 @@ class Server:
     # ---------------------------------------------------------------------------- helpers
     @staticmethod
     def e0_solver_for(inst) -> int:
-        """Band factors for 2D meshes, the all-direction CG for 3D ones (bands too wide)."""
-        return rte.RTE_E0_BANDED if inst.dim == 2 else rte.RTE_E0_CG
+        """Band factors for 2D meshes; for 3D ones (bands too wide) the all-direction CG,
+        preconditioned by the multigrid V-cycle when the mesh is a lattice."""
+        if inst.dim == 2:
+            return rte.RTE_E0_BANDED
+        return rte.RTE_E0_MG if _is_lattice(inst.vert) else rte.RTE_E0_CG
 
     def _estimate(self, req):
         if not hasattr(req, "_est"):
@@ -173,9 +197,11 @@ class Server:
                         raise h
                     self.reserved -= peak - b          # the assembly peak is over
                     U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
-                    cg = self.e0_solver_for(req.inst) == rte.RTE_E0_CG
+                    e0 = self.e0_solver_for(req.inst)
+                    cg = e0 != rte.RTE_E0_BANDED
                     which = self.batch_cg if cg else self.batch
-                    slot = which.admit(h, U, self.opts_cg if cg else self.opts, stream=self.stream.cuda_stream)
+                    o = self.opts if not cg else self.opts_mg if e0 == rte.RTE_E0_MG else self.opts_cg
+                    slot = which.admit(h, U, o, stream=self.stream.cuda_stream)
                     req.admitted_at = now()
                     self.slot_of[(int(cg), slot)] = (req, h, b, U)
                 if self.slot_of:

@@ -101,6 +101,90 @@ rte_status status_of(const rte_problem_desc& D, const rte_assemble_opts& o) {
     }
 }
 
+// The multigrid hierarchy's host part: the meshes are lattices (and a vertex swap is not); the
+// coarse pattern is the coarse lattice's P1 pattern (symmetric, sorted, diagonal present); the
+// coarse class values equal the pattern entries of P^T C P formed densely by brute force, with
+// P built independently from lattice coordinates (weight 1 at even vertices, 1/2 at the two ends
+// of the coarse edge a fine vertex bisects).
+void check_multigrid(const Mesh& mesh, const rte_problem_desc& D, const std::vector<int>& rp,
+                     const std::vector<int>& ci) {
+    const int d = D.dim, n = D.n_vert;
+    const int m = rte::lattice_m(&D);
+    check(m > 0 && (d == 2 ? m * m : m * m * m) == n, "lattice recognised");
+    {
+        std::vector<double> v(mesh.vert);
+        std::swap(v[d * 1], v[d * 2]);
+        std::swap(v[d * 1 + 1], v[d * 2 + 1]);
+        rte_problem_desc B = D;
+        B.vert = v.data();
+        check(rte::lattice_m(&B) == 0, "swapped vertices are not a lattice");
+        std::vector<int32_t> cell(mesh.cell);
+        std::swap(cell[1], cell[2]);
+        std::swap(cell[d + 1 + 0], cell[d + 1 + 3 % (d + 1)]);
+        B = D;
+        B.cell = cell.data();
+        (void)rte::lattice_m(&B);      // any answer; only memory safety is checked here
+    }
+    const std::vector<int> sizes = rte::mg_level_sizes(m);
+    check(sizes.size() >= 2, "at least two levels");
+    // coarsen one level with two random classes on the fine pattern (only the in-pattern
+    // entries are compared: for such matrices the rest of P^T C P need not vanish)
+    const int ncls = 2, nnz = rp[n];
+    std::vector<double> cls((size_t)ncls * nnz);
+    unsigned long long st = 12345;
+    for (double& x : cls) {
+        st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+        x = (double)(st >> 11) / 9007199254740992.0 - 0.5;
+    }
+    const rte::MgHostLevel L = rte::mg_coarsen(d, m, ncls, rp, ci, cls);
+    const int mc = L.m, nc = L.n;
+    check(mc == sizes[1] && nc == (d == 2 ? mc * mc : mc * mc * mc), "coarse size");
+    check((int)L.rp.size() == nc + 1 && L.rp[nc] == (int)L.ci.size() && (int)L.cls.size() == ncls * L.rp[nc],
+          "coarse CSR shape");
+    std::set<std::pair<int, int>> ent;
+    for (int I = 0; I < nc; ++I) {
+        bool diag = false;
+        for (int e = L.rp[I]; e < L.rp[I + 1]; ++e) {
+            if (e > L.rp[I]) check(L.ci[e] > L.ci[e - 1], "coarse rows sorted");
+            diag |= L.ci[e] == I;
+            ent.insert({I, L.ci[e]});
+        }
+        check(diag, "coarse diagonal present");
+        check(L.rp[I + 1] - L.rp[I] <= (d == 2 ? 7 : 15), "coarse stencil width");
+    }
+    for (const auto& pr : ent) check(ent.count({pr.second, pr.first}) == 1, "coarse pattern symmetric");
+    if (nc > 800) return;                 // the dense product below is for small lattices
+    std::vector<double> P((size_t)n * nc, 0.0);
+    for (int f = 0; f < n; ++f) {
+        int c[3], lo = 0, hi = 0, mul = 1;
+        for (int a = 0, v = f; a < d; ++a, v /= m) c[a] = v % m;
+        for (int a = 0; a < d; ++a, mul *= mc) {
+            lo += (c[a] / 2) * mul;
+            hi += ((c[a] + 1) / 2) * mul;
+        }
+        if (lo == hi) P[(size_t)f * nc + lo] = 1.0;
+        else P[(size_t)f * nc + lo] = P[(size_t)f * nc + hi] = 0.5;
+    }
+    double worst = 0.0, scale = 0.0;
+    for (int c = 0; c < ncls; ++c) {
+        std::vector<double> CP((size_t)n * nc, 0.0);       // C P
+        for (int i = 0; i < n; ++i)
+            for (int e = rp[i]; e < rp[i + 1]; ++e)
+                for (int J = 0; J < nc; ++J) CP[(size_t)i * nc + J] += cls[(size_t)c * nnz + e] * P[(size_t)ci[e] * nc + J];
+        for (int I = 0; I < nc; ++I)
+            for (int e = L.rp[I]; e < L.rp[I + 1]; ++e) {
+                const int J = L.ci[e];
+                double v = 0.0;
+                for (int f = 0; f < n; ++f) v += P[(size_t)f * nc + I] * CP[(size_t)f * nc + J];
+                worst = std::max(worst, std::fabs(v - L.cls[(size_t)c * L.rp[nc] + e]));
+                scale = std::max(scale, std::fabs(v));
+            }
+    }
+    check(worst <= 1e-12 * std::max(scale, 1.0), "coarse class values are the pattern entries of P^T C P");
+    std::printf("multigrid: lattice %d, levels %zu, coarse n %d nnz %d, worst |P^T C P - coarse| %.1e\n", m,
+                sizes.size(), nc, L.rp[nc], worst);
+}
+
 void check_mesh(const Mesh& m, const char* name) {
     const rte_problem_desc D = m.desc();
     const rte_assemble_opts o = opts();
@@ -206,6 +290,7 @@ void check_mesh(const Mesh& m, const char* name) {
     check(rte::estimate_footprint(&D, &oc, nullptr) > 0, "CG footprint");
     std::printf("%s: n_vert %d, nnz %zu, band %d -> %d, ELL %zu, footprint %zu bytes\n", name, n, ci.size(),
                 rte::band_width(ident, rp, ci), rte::band_width(perm, rp, ci), len, b1);
+    check_multigrid(m, D, rp, ci);
 }
 
 void check_band_cholesky() {

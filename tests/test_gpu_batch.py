@@ -238,10 +238,10 @@ def test_estimated_footprint_matches_admitted_slot(handles):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_cg_slots_in_lockstep_equal_single_solves(prec):
-    """Slots whose E_0 is solved by CG advance together on the batch's stream lanes (more slots
-    than lanes, so lanes are shared), beside a banded slot; one CG slot stops at a small
-    iteration cap, so the slots leave the lockstep at different check points.  Every slot must
-    equal its solo solve bit for bit."""
+    """Slots whose E_0 is solved by CG (Jacobi- or multigrid-preconditioned) advance together on
+    the batch's stream lanes (more slots than lanes, so lanes are shared), beside a banded slot;
+    one CG slot stops at a small iteration cap, so the slots leave the lockstep at different
+    check points.  Every slot must equal its solo solve bit for bit."""
     from paper_2102_09038_amd import rte
     insts = [
         inputs.tiny_instance(n=4, sphere_level=1, g=0.5, ratio=0.9, n_even=0, n_odd=3, l=4),
@@ -251,7 +251,7 @@ def test_batch_cg_slots_in_lockstep_equal_single_solves(prec):
         inputs.make_instance("cg-3d-6", 3, 6, 1, 0.8, 0.9, block=2, seed=32, n_even=0, n_odd=3, l=4),
         inputs.tiny_instance(n=8, sphere_level=1, g=0.4, ratio=0.9, n_even=0, n_odd=3, l=4, seed=9),
     ]
-    e0 = [rte.RTE_E0_CG] * 5 + [rte.RTE_E0_BANDED]
+    e0 = [rte.RTE_E0_CG, rte.RTE_E0_MG, rte.RTE_E0_CG, rte.RTE_E0_MG, rte.RTE_E0_CG, rte.RTE_E0_BANDED]
     hs = [rte.Handle.from_instance(i, e0_solver=e, mixed=1) for i, e in zip(insts, e0)]
     precision = rte.RTE_FP64 if prec == "fp64" else rte.RTE_MIXED
     opts = []
