@@ -556,12 +556,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the short served-form run")
     ap.add_argument("--no-batched", action="store_true", help="skip the short batched-form run")
-    ap.add_argument("--only", choices=["kernels", "batch", "serve", "rates"], default=None,
+    ap.add_argument("--only", choices=["kernels", "batch", "serve", "rates", "e0inv3d"], default=None,
                     help="'kernels': assemble the realistic instance, run the dominant kernels twice each "
                          "and a plain 4 GiB device copy (the reference for HBM counter passes), then exit; "
                          "'batch': the batched form (seeded instances of uneven size, mixed precision, "
                          "lockstep batch) against the same instances solved one at a time in FP64; "
-                         "'rates': the convergence-rate study on the lattice stand-in")
+                         "'rates': the convergence-rate study on the lattice stand-in; "
+                         "'e0inv3d': E_0^{-1} of the served 3D request by the Jacobi and the multigrid CG, "
+                         "and its mixed solve")
     ap.add_argument("--count", type=int, default=64, help="instances of the batched form")
     ap.add_argument("--rates", default="50,200,1000,half",
                     help="served form: Poisson arrival rates in requests/s ('half' = half the capacity "
@@ -590,6 +592,9 @@ def main():
         return
     if args.only == "rates":
         rates_study(args, torch, rte, inputs)
+        return
+    if args.only == "e0inv3d":
+        print(json.dumps(e0inv_3d(torch, rte, inputs, lambda m: print(m, file=sys.stderr, flush=True))))
         return
     inst = inputs.config_realistic()
     ta = time.perf_counter()
