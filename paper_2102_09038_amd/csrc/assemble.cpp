@@ -1128,7 +1128,7 @@ void Asm::coarse() {
         const bool inv_fits = (double)nc * nc * sizeof(double) <= kEcinvMaxBytes;
         const bool band_fits = k::band_groups(bw, 2) != 0;
         int how = o->coarse_solver;
-        if (how == RTE_COARSE_QUICK) how = (band_fits && k::band_factor_fits(bw)) ? RTE_COARSE_BAND : RTE_COARSE_AUTO;
+        if (how == RTE_COARSE_QUICK) how = (band_fits && k::band_factor_fits(bw)) ? RTE_COARSE_BAND : RTE_COARSE_BLOCK;
         if (how == RTE_COARSE_AUTO) how = inv_fits ? RTE_COARSE_INVERSE : band_fits ? RTE_COARSE_BAND : RTE_COARSE_BLOCK;
         if (how == RTE_COARSE_INVERSE) {
             if (!inv_fits) fail(RTE_E_ARG, "the explicit coarse inverse exceeds its memory budget");

@@ -416,7 +416,7 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
         const bool inv_fits = (double)nc * nc * 8 <= kEcinvMaxBytes, band_fits = k::band_groups((int)cbw, 2) != 0;
         int how = o->coarse_solver;
         if (how == RTE_COARSE_QUICK)
-            how = (band_fits && k::band_factor_fits((int)cbw)) ? RTE_COARSE_BAND : RTE_COARSE_AUTO;
+            how = (band_fits && k::band_factor_fits((int)cbw)) ? RTE_COARSE_BAND : RTE_COARSE_BLOCK;
         if (how == RTE_COARSE_AUTO) how = inv_fits ? RTE_COARSE_INVERSE : band_fits ? RTE_COARSE_BAND : RTE_COARSE_BLOCK;
         if (how == RTE_COARSE_INVERSE) {
             b += nc * nc * 8;
