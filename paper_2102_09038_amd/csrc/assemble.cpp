@@ -1150,6 +1150,7 @@ void Asm::coarse() {
                 band_cholesky(band, nc, bw);
                 h.Lc.upload(band_to_blocked(band, nc, bw, false), s);
                 h.LcU.upload(band_to_blocked(band, nc, bw, true), s);
+                k::band_invert_diag(h.Lc.p, h.LcU.p, nc, bw, 1, 0, s);
             }
         } else {
             DBuf<double> dband;

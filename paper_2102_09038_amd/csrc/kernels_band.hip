@@ -152,6 +152,54 @@ __global__ __launch_bounds__(1024) void e0_band_factor_kernel(int n, int bw, dou
     if (failed && threadIdx.x == 0) atomicOr(bad, 1);
 }
 
+// ----------------------------------------------------------------------------- diagonal blocks
+// After the factorisation, the 64 x 64 diagonal block of every row block (rows and columns
+// 64B .. 64B+63, lower triangle; in BL at (r, t = bw + c - r), in BU at (c, t = r - c)) is
+// replaced by its inverse, which the solve applies as a product of independent broadcasts
+// instead of a 64-step substitution.  With bw >= 63 every entry of the block's lower triangle
+// lies in the band, so the inverse (dense below its diagonal) fits the same slots; the
+// diagonal keeps 1 / L(r,r), the inverse's own diagonal.  One work-group of 64 threads per
+// (row block, system): the block in LDS, thread j forms column j of the inverse by forward
+// substitution (L x = e_j) in FP64, four partial sums per dot product.
+__global__ __launch_bounds__(64) void band_diag_invert_kernel(int n, int bw, double* __restrict__ BLall,
+                                                              double* __restrict__ BUall, size_t stride_sys) {
+    __shared__ double Lb[64 * 64];    // Lb[i * 64 + k] = L(r0 + i, r0 + k), k < i; Lb[i * 65] = 1 / L(i, i)
+    __shared__ double X[64 * 64];     // X[i * 64 + j] = inverse entry (i, j), j <= i
+    const int B = blockIdx.x, lane = threadIdx.x;
+    double* BL = BLall + stride_sys * blockIdx.y;
+    double* BU = BUall + stride_sys * blockIdx.y;
+    const int r0 = 64 * B;
+    const int nb = min(64, n - r0);
+    for (int j = 0; j < 64; ++j) {
+        double v = 0.0;
+        if (lane < nb && j <= lane) v = BL[blk_idx(r0 + lane, bw + j - lane, bw)];
+        Lb[lane * 64 + j] = v;
+        X[lane * 64 + j] = 0.0;
+    }
+    __syncthreads();
+    if (lane < nb) {
+        const int j = lane;
+        X[j * 65] = Lb[j * 65];
+        for (int i = j + 1; i < nb; ++i) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int k = j;
+            for (; k + 3 < i; k += 4) {
+                a0 = fma(Lb[i * 64 + k], X[k * 64 + j], a0);
+                a1 = fma(Lb[i * 64 + k + 1], X[(k + 1) * 64 + j], a1);
+                a2 = fma(Lb[i * 64 + k + 2], X[(k + 2) * 64 + j], a2);
+                a3 = fma(Lb[i * 64 + k + 3], X[(k + 3) * 64 + j], a3);
+            }
+            for (; k < i; ++k) a0 = fma(Lb[i * 64 + k], X[k * 64 + j], a0);
+            X[i * 64 + j] = -((a0 + a1) + (a2 + a3)) * Lb[i * 65];
+        }
+    }
+    __syncthreads();
+    if (lane < nb) {
+        for (int j = 0; j <= lane; ++j) BL[blk_idx(r0 + lane, bw + j - lane, bw)] = X[lane * 64 + j];
+        for (int i = lane; i < nb; ++i) BU[blk_idx(r0 + lane, i - lane, bw)] = X[i * 64 + lane];
+    }
+}
+
 // ----------------------------------------------------------------------------- solve
 // One wave per system: L L^T x = b.  Rows in blocks of 64 (lane = row within the block).
 // A row block of a factor is G = ceil((bw+1)/VEC) groups of 16 bytes per lane; each group
@@ -248,6 +296,7 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    const bool inv = k::band_diag_inverted(bw);
     for (int st = 0; st < nstep; ++st) {
         const bool fwd = st < nblk;
         const int B = fwd ? st : nstep - 1 - st;
@@ -315,6 +364,40 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
         }
         s += ((double)acc[0] + (double)acc[1]) + ((double)acc[2] + (double)acc[3]);
         __syncthreads();
+        double res;
+        if (inv) {
+            // the block's inverse (captured like the block): y = D^{-1} s over the rows of the
+            // block, 64 independent broadcasts
+            double y = 0.0;
+            if (fwd) {
+#pragma unroll 1
+                for (int c = 0; c < 4; ++c) {
+                    double Dc[16];
+#pragma unroll
+                    for (int uu = 0; uu < 16; ++uu) Dc[uu] = (double)D[(16 * c + uu) * 64 + lane];
+#pragma unroll
+                    for (int uu = 0; uu < 16; ++uu) {
+                        const int u = 16 * c + uu;
+                        const double f = fma(Dc[uu], bcast(s, u), y);
+                        y = (u <= lane) ? f : y;
+                    }
+                }
+            } else {
+#pragma unroll 1
+                for (int c = 0; c < 4; ++c) {
+                    double Dc[16];
+#pragma unroll
+                    for (int uu = 0; uu < 16; ++uu) Dc[uu] = (double)D[(16 * c + uu) * 64 + lane];
+#pragma unroll
+                    for (int uu = 0; uu < 16; ++uu) {
+                        const int u = 16 * c + uu;
+                        const double f = fma(Dc[uu], bcast(s, u), y);
+                        y = (u >= lane && 64 * B + u < n) ? f : y;
+                    }
+                }
+            }
+            res = ok ? y : 0.0;
+        } else {
         const double dinv = ok ? (double)D[65 * lane] : 0.0;
         if (fwd) {
 #pragma unroll 1
@@ -345,7 +428,8 @@ __device__ __forceinline__ void band_solve_system(const GLOBAL FT* __restrict__ 
                 }
             }
         }
-        const double res = s * dinv;
+        res = s * dinv;
+        }
         ylast = res;
         if (ok) {
             win[row & Wm] = (FT)res;
@@ -651,6 +735,7 @@ void e0_band_factor(const Handle* h, int bw, const int* perm, const int* iperm, 
     hipLaunchKernelGGL(e0_band_factor_kernel, dim3(h->nS), dim3(bw >= 120 ? 1024 : 512), lds, s, h->nRp, bw, BL, BU,
                        stride_sys, bad);
     RTE_CHECK_LAUNCH();
+    band_invert_diag(BL, BU, h->nRp, bw, h->nS, stride_sys, s);
 }
 
 void band_factor_one(int n, int bw, double* BL, double* BU, int* bad, hipStream_t s) {
@@ -659,6 +744,13 @@ void band_factor_one(int n, int bw, double* BL, double* BU, int* bad, hipStream_
     raise_factor_window();
     hipLaunchKernelGGL(e0_band_factor_kernel, dim3(1), dim3(bw >= 120 ? 1024 : 512), lds, s, n, bw, BL, BU,
                        (size_t)0, bad);
+    RTE_CHECK_LAUNCH();
+    band_invert_diag(BL, BU, n, bw, 1, 0, s);
+}
+
+void band_invert_diag(double* BL, double* BU, int n, int bw, int nsys, size_t stride_sys, hipStream_t s) {
+    if (!band_diag_inverted(bw) || n <= 0 || nsys <= 0) return;
+    hipLaunchKernelGGL(band_diag_invert_kernel, dim3((n + 63) / 64, nsys), dim3(64), 0, s, n, bw, BL, BU, stride_sys);
     RTE_CHECK_LAUNCH();
 }
 

@@ -60,6 +60,13 @@ void coarse_project(const Handle* h, const double* T, double* rhs, hipStream_t s
 // (kernels_band.hip); b and x are read / written at iperm[band row] when iperm is given
 void band_solve_blk(const double* BL, const double* BU, int n, int bw, int nsys, size_t stride_sys,
                     const double* b, double* x, size_t stride_vec, const int* iperm, hipStream_t s, int G = 0);
+// Whether the band factors of half-bandwidth bw hold each 64 x 64 diagonal block as its inverse
+// (bw >= 63: the band then holds the whole inverse; the solve applies it as a product)
+constexpr bool band_diag_inverted(int bw) { return bw >= 63; }
+// Replace every diagonal block of the factors (default FP64 layout) by its inverse when
+// band_diag_inverted(bw); the factorisations below call it, a host factor uploaded into the
+// layout must too
+void band_invert_diag(double* BL, double* BU, int n, int bw, int nsys, size_t stride_sys, hipStream_t s);
 // Cholesky factorisation of one SPD band matrix on the device (the E_0 factor kernel with one
 // work-group): BL holds the lower band in the blocked layout on entry (offset t = c - r + bw),
 // and L on exit, BU (zeroed by the caller) rows of L^T; the diagonal entries become
