@@ -75,6 +75,100 @@ __device__ __forceinline__ void bf16_step_mfma(const BTile& As, const BTile& Bs,
     }
 }
 
+// Large-tile form for whole tiles (M, N multiples of 256, K of 64, 16-byte aligned operand
+// rows): tile 256 x 256 x 64, eight waves in 2 x 4 (two per SIMD), each 128 x 64 as 4 x 8
+// blocks of v_mfma_f32_16x16x32_bf16.  The tiles go from global memory straight into LDS
+// (global_load_lds_dwordx4: one wave moves 1 KiB, eight tile rows of 64 k, lane l into slot
+// l % 8 of row l / 8); the bank swizzle above is kept by letting lane l fetch the global chunk
+// that belongs in its slot, (l % 8) ^ ((row / 2) % 8).  The next step's loads go into the
+// other buffer at the start of a step; the wait and barrier at its end make them visible.
+// Same fragments and K order as the 128 x 128 kernel, so the same bits, with half the operand
+// bytes per MFMA (the 128 x 128 tiles re-read their panels from L2 and the Infinity Cache).
+constexpr int LBM = 256, LBN = 256;
+typedef uint16_t LTile[LBM][HBK];
+
+__global__ __launch_bounds__(512, 1) void gemm_bf16_l_kernel(int M, int N, int K, float alpha,
+                                                             const uint16_t* __restrict__ A, int lda,
+                                                             const uint16_t* __restrict__ B, int ldb, float beta,
+                                                             float* __restrict__ C, int ldc, int map) {
+    __shared__ __attribute__((aligned(16))) LTile As[2];
+    __shared__ __attribute__((aligned(16))) LTile Bs[2];
+    const int tm = M / LBM, tn = N / LBN;
+    const int b = (map & 1) ? (int)blockIdx.x : xcd_swz(blockIdx.x, tm * tn);
+    const bool mfast = (tm < tn) != ((map & 2) != 0);
+    const int bm = mfast ? b % tm : b / tn, bn = mfast ? b / tm : b % tn;
+    const int m0 = bm * LBM, n0 = bn * LBN;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave & 1, wn = wave >> 1;
+    const int nk = K / HBK;
+    // wave w moves tile rows 8 q .. 8 q + 7 of both tiles, q = w + 8 i, i = 0..3; lane l takes
+    // row 8 q + l / 8, whose swizzle ((row / 2) % 8 = (4 w + l / 16) % 8) is the same for every
+    // i, so one base address per lane and operand serves all four loads
+    const int lr = lane >> 3;
+    const int c = (lane & 7) ^ ((4 * wave + (lr >> 1)) & 7);
+    const uint16_t* Al = A + (size_t)(m0 + 8 * wave + lr) * lda + 8 * c;
+    const uint16_t* Bl = B + (size_t)(n0 + 8 * wave + lr) * ldb + 8 * c;
+    const size_t sa = (size_t)64 * lda, sb = (size_t)64 * ldb;
+    auto issue = [&](int kt, int buf) {
+        const size_t k0 = (size_t)kt * HBK;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = wave + 8 * i;
+            __builtin_amdgcn_global_load_lds(Al + i * sa + k0, &As[buf][8 * q][0], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(Bl + i * sb + k0, &Bs[buf][8 * q][0], 16, 0, 0);
+        }
+    };
+    f4v acc[4][8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[j][i] = f4v{0, 0, 0, 0};
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) issue(kt + 1, cur ^ 1);
+#pragma unroll
+        for (int kk = 0; kk < HBK / 32; ++kk) {
+            const int ch = kk * 4 + (lane >> 4);
+            bf8v af[8], bfr[4];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int r = wm * 128 + i * 16 + (lane & 15);
+                af[i] = *reinterpret_cast<const bf8v*>(&As[cur][r][swz(r, ch)]);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = wn * 64 + j * 16 + (lane & 15);
+                bfr[j] = *reinterpret_cast<const bf8v*>(&Bs[cur][r][swz(r, ch)]);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[j][i], 0, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);       // this wave's tile loads have landed in LDS
+        __syncthreads();
+    }
+    // acc[j][i][v] = C(m = m0 + wm*128 + i*16 + lane%16, n = n0 + wn*64 + j*16 + 4*(lane/16) + v)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int gm = m0 + wm * 128 + i * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gn = n0 + wn * 64 + j * 16 + 4 * (lane >> 4) + v;
+                float* cp = C + gm + (size_t)ldc * gn;
+                const float val = alpha * acc[j][i][v];
+                *cp = (beta == 0.0f) ? val : fmaf(beta, *cp, val);
+            }
+        }
+}
+
 __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(int M, int N, int K, float alpha,
                                                            const uint16_t* __restrict__ A, int lda,
                                                            const uint16_t* __restrict__ B, int ldb, float beta,
@@ -275,6 +369,13 @@ void gemm_bf16(int M, int N, int K, float alpha, const uint16_t* A, int lda, con
                float beta, float* C, int ldc, hipStream_t s) {
     if (M <= 0 || N <= 0) return;
     if (K % 8 || lda % 8 || ldb % 8) fail(RTE_E_ARG, "BF16 GEMM needs K, lda, ldb multiples of 8");
+    const bool aligned = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (reinterpret_cast<uintptr_t>(B) % 16 == 0);
+    if (M % LBM == 0 && N % LBN == 0 && K % HBK == 0 && aligned) {
+        hipLaunchKernelGGL(gemm_bf16_l_kernel, dim3((M / LBM) * (N / LBN)), dim3(512), 0, s, M, N, K, alpha, A, lda, B,
+                           ldb, beta, C, ldc, gemm_map(kGemmBF16, M, N, K));
+        RTE_CHECK_LAUNCH();
+        return;
+    }
     const int nb = ((M + HBM_ - 1) / HBM_) * ((N + HBN - 1) / HBN);
     hipLaunchKernelGGL(gemm_bf16_kernel, dim3(nb), dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
                        gemm_map(kGemmBF16, M, N, K));
