@@ -13,6 +13,8 @@ solve).
 * The served form's 3D request (32^3 cubes, 512 sphere triangles): sampled directions of
   E_0^{-1} against the LU, and a mixed solve to 1e-6 whose residual is recomputed in FP64.
 * A mesh that is not a lattice is refused at assembly.
+* The host footprint estimate against the bytes an admitted multigrid slot holds, including the
+  served 3D configuration.
 """
 import time
 
@@ -210,4 +212,35 @@ def test_mg_3d_request_full_size():
     r = float(torch.linalg.norm(EU - KU - q) / torch.linalg.norm(q))
     print(f"[3d mg] recomputed relative residual {r:.2e}")
     assert r <= 1.01e-6
+    h.close()
+
+
+@pytest.mark.parametrize("case", ["2d-16", "3d-8", "3d-16-served"])
+def test_mg_estimated_footprint_matches_admitted_slot(case):
+    """rte_estimate_footprint (host only, before assembly) against the bytes a multigrid slot
+    holds once admitted (handle and workspace), including the served 3D configuration (FP32
+    only, no odd eigendecomposition, the quick coarse set-up: block-tridiagonal Cholesky)."""
+    from paper_2102_09038_amd import rte
+    if case == "2d-16":
+        inst, kw = CASES["2d-16-s32"](), dict(mixed=1)
+    elif case == "3d-8":
+        inst, kw = CASES["3d-8-s32"](), dict(mixed=1)
+    else:
+        inst = inputs.make_instance("mg-3d-16", 3, 16, 2, 0.8, 0.9, block=8, seed=66, n_even=0, n_odd=5, l=4,
+                                    tol=1e-6)
+        kw = dict(mixed=2, odd_eig=0, coarse_solver=rte.RTE_COARSE_QUICK)
+    est, peak = rte.estimate_footprint(inst, e0_solver=rte.RTE_E0_MG, **kw)
+    h = rte.Handle.from_instance(inst, e0_solver=rte.RTE_E0_MG, **kw)
+    o = rte.default_solve_opts(l=4, tol=1e-6, max_iter=200, precision=rte.RTE_MIXED, e0_solver=rte.RTE_E0_MG,
+                               odd_solver=rte.RTE_ODD_CONDENSED)
+    b = rte.Batch(max_slots=1)
+    U = torch.empty((h.dims.nSp, h.dims.nRp), dtype=torch.float64, device="cuda")
+    b.admit(h, U, o)
+    actual = b.usage()[2]
+    print(f"[{case}] estimated {est} bytes (peak {peak}), slot holds {actual}")
+    assert 0.8 * actual <= est <= 1.5 * actual + (1 << 20)
+    assert b.step(1000) == 0
+    (s, st, info), = b.poll()
+    assert st == rte.RTE_OK and info.rel_resid <= 1e-6
+    b.close()
     h.close()
