@@ -26,6 +26,10 @@ that remark:
   Pre- and post-smoothing use the same polynomial, so B is symmetric.
 * CG preconditioned by one V-cycle per iteration, from x = 0, stopping when
   r.r <= tol^2 b.b (the stopping rule of the all-direction CG).
+* Smoother precision: the cycle may work on every level's matrix rounded entry by entry to
+  FP32 or to BF16 (round to nearest even, BF16 by way of FP32), its Jacobi scaling and
+  Gershgorin bound taken from the rounded matrix; the CG's own products keep the exact E_0.
+  The rounded matrices are symmetric, so the cycle stays a fixed symmetric operator.
 """
 from __future__ import annotations
 
@@ -82,16 +86,34 @@ def level_sizes(m: int) -> list[int]:
     return out
 
 
-def hierarchy(A: sp.spmatrix, m: int, d: int) -> list[dict]:
+def round_f32(v: np.ndarray) -> np.ndarray:
+    """Each value rounded to the nearest FP32 number (ties to even), as FP64."""
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def round_bf16(v: np.ndarray) -> np.ndarray:
+    """Each value rounded to FP32, then to the nearest BF16 number (ties to even), as FP64."""
+    u = np.asarray(v, dtype=np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def hierarchy(A: sp.spmatrix, m: int, d: int, smoother: str | None = None) -> list[dict]:
     """Levels finest first: operator, prolongation to the finer level, Jacobi scaling and the
-    Gershgorin bound lam of D^{-1} A."""
+    Gershgorin bound lam of D^{-1} A.  smoother "f32" or "bf16": every level's operator (the
+    Galerkin products taken exactly, then rounded) in that precision."""
+    rnd = {None: None, "f32": round_f32, "bf16": round_bf16}[smoother]
     sizes = level_sizes(m)
     levels = []
     Al = sp.csr_matrix(A)
     for li, ml in enumerate(sizes):
-        dg = Al.diagonal()
-        lam = float(np.max(np.asarray(abs(Al).sum(axis=1)).ravel() / dg))
-        lev = {"A": Al, "m": ml, "dinv": 1.0 / dg, "lam": lam}
+        As = Al
+        if rnd is not None:
+            As = Al.copy()
+            As.data = rnd(As.data)
+        dg = As.diagonal()
+        lam = float(np.max(np.asarray(abs(As).sum(axis=1)).ravel() / dg))
+        lev = {"A": As, "m": ml, "dinv": 1.0 / dg, "lam": lam}
         levels.append(lev)
         if li + 1 < len(sizes):
             P = prolongation(ml, d)
@@ -132,10 +154,10 @@ def vcycle(levels, r, l=0, nu=NU, lo=LO, nu_c=NU_COARSE, lo_c=LO_COARSE):
     return chebyshev(L["A"], L["dinv"], L["lam"], lo, nu, r, x)
 
 
-def mg_cg(A, b, m, d, tol, maxit=1000, levels=None):
+def mg_cg(A, b, m, d, tol, maxit=1000, levels=None, smoother=None):
     """CG on A x = b preconditioned by one V-cycle per iteration (Saad, Alg. 9.1), x_0 = 0.
     Returns (x, iterations)."""
-    levels = hierarchy(A, m, d) if levels is None else levels
+    levels = hierarchy(A, m, d, smoother) if levels is None else levels
     x = np.zeros_like(b)
     bb = float(b @ b)
     if bb == 0.0:

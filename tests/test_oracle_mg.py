@@ -11,7 +11,10 @@ other than the code itself:
 * Gershgorin's bound is an upper bound of the spectrum of D^{-1} A;
 * the V-cycle is symmetric and positive definite;
 * CG with the V-cycle reaches the sparse-LU solution, with iteration counts that barely grow
-  when the mesh is refined (against Jacobi CG, whose counts grow with the refinement).
+  when the mesh is refined (against Jacobi CG, whose counts grow with the refinement);
+* the smoother-precision roundings: BF16 rounding at exact halfway points goes to the even
+  neighbour, stays within half a unit in the last place, is odd-symmetric; the cycle on the
+  rounded levels is still symmetric positive definite and its CG still reaches the LU solution.
 """
 import numpy as np
 import pytest
@@ -133,3 +136,35 @@ def test_mg_cg_solves_and_scales():
     (_, j4, m4), (_, j8, m8) = res[4], res[8]
     assert m8 < j8 / 3
     assert m8 - m4 <= 4 and j8 > j4 + 10
+
+
+def test_bf16_rounding():
+    one = 1.0
+    assert mg.round_bf16(np.array([one + 2.0 ** -8]))[0] == 1.0                  # tie: to even (1.0)
+    assert mg.round_bf16(np.array([one + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6   # tie: to even
+    assert mg.round_bf16(np.array([one + 2.0 ** -8 + 2.0 ** -20]))[0] == 1.0 + 2.0 ** -7
+    x = np.random.default_rng(5).standard_normal(10000) * 10.0 ** np.random.default_rng(6).uniform(-5, 5, 10000)
+    r = mg.round_bf16(x)
+    assert np.all(np.abs(r - x) <= 2.0 ** -8 * np.abs(x) * (1 + 1e-12))
+    np.testing.assert_array_equal(mg.round_bf16(-x), -r)
+    assert np.all(mg.round_bf16(r) == r)                                          # idempotent
+    np.testing.assert_array_equal(mg.round_f32(x), x.astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("smoother", ["f32", "bf16"])
+def test_rounded_smoother_cycle(smoother):
+    A = e0_blocks(3, 4, [2])[0]
+    levels = mg.hierarchy(A, 5, 3, smoother)
+    rng = np.random.default_rng(8)
+    x, y = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
+    Bx, By = mg.vcycle(levels, x), mg.vcycle(levels, y)
+    assert abs(Bx @ y - x @ By) <= 1e-12 * np.linalg.norm(Bx) * np.linalg.norm(y)
+    assert x @ Bx > 0 and y @ By > 0
+    exact = mg.hierarchy(A, 5, 3)
+    for L, E in zip(levels, exact):
+        d = (L["A"] - E["A"]).toarray()
+        assert np.abs(d).max() <= (2.0 ** -8 if smoother == "bf16" else 2.0 ** -24) * np.abs(E["A"].toarray()).max()
+    b = rng.standard_normal(A.shape[0])
+    xs, its = mg.mg_cg(A, b, 5, 3, tol=1e-13, levels=levels)
+    xr = spla.spsolve(sp.csc_matrix(A), b)
+    assert np.linalg.norm(xs - xr) <= 1e-10 * np.linalg.norm(xr)
