@@ -88,9 +88,11 @@ typedef enum rte_e0_solver {
                              Chebyshev steps before and after the coarse correction on
                              [0.02 lam, lam], lam = Gershgorin's bound of D^-1 E_0, eight
                              on the coarsest level on the same interval.  Levels are added
-                             while the cells per axis are even and at least 4.  Precision
-                             and stopping as RTE_E0_CG; the hierarchy is built at assembly
-                             (e0_solver = RTE_E0_MG)                                  */
+                             while the cells per axis are even and at least 4.  The cycle
+                             reads the level matrices rounded to FP32 (FP64 solves) or BF16
+                             (mixed solves); the CG's own products use the full-precision
+                             E_0.  Precision and stopping as RTE_E0_CG; the hierarchy is
+                             built at assembly (e0_solver = RTE_E0_MG)                */
 } rte_e0_solver;
 
 /* How P_1 approximates E^{-1} (Sec. 5.3).  The paper takes l steps of the preconditioned
@@ -316,7 +318,8 @@ rte_status rte_apply_E0(rte_handle* h, const double* X, double* Y, void* hip_str
 /* Y = B X, one multigrid V-cycle per direction block (the preconditioner of RTE_E0_MG; the
  * multigrid remark of Sec. 5.5): four Chebyshev steps from 0, the residual restricted by P^T,
  * the coarser levels' cycle, the correction prolongated by P, four Chebyshev steps; eight on the
- * coarsest level.  B is symmetric positive definite and fixed (linear in X).  Device FP64
+ * coarsest level, on the level matrices rounded to FP32 (the FP64 solves' smoother precision).
+ * B is symmetric positive definite and fixed (linear in X).  Device FP64
  * n_R+ x n_S+ column-major vectors, not aliased.  The handle must be assembled with
  * e0_solver = RTE_E0_MG (else RTE_E_ARG).  Builds the hierarchy's FP64 data on the first call
  * when the handle was assembled with mixed = 2 (then it allocates); otherwise enqueue only. */

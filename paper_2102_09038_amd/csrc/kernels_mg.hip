@@ -20,6 +20,12 @@
 // r_0 = b - A x; the last x + d of a level is left to the launch that reads it (the prolongation
 // of the finer level, or the CG's z = x + d).
 //
+// Smoother precision: the cycle reads every level's matrix in a reduced precision, FP32 when
+// the vectors are FP64 and BF16 when they are FP32 (values rounded to nearest even; inverse
+// diagonals and Gershgorin bounds from the rounded values).  The rounded matrices are
+// symmetric, so the cycle is still a fixed symmetric preconditioner; the CG's own SpMV uses
+// the full-precision values.  The smoothing launches stream half the value bytes.
+//
 // CG (Saad's preconditioned CG with one V-cycle as the preconditioner), per direction:
 //   spmv     q = A p, partials p.q                                   (the Jacobi CG's kernel)
 //   update   alpha = rz / p.q; x += alpha p; r -= alpha q; partials r.r; d_0 of the cycle
@@ -59,6 +65,24 @@ __device__ __forceinline__ T ld_stream(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
+// the smoother's value type for a vector type, and its conversion
+template <typename T> struct SmoothVal;
+template <> struct SmoothVal<double> { typedef float V; };
+template <> struct SmoothVal<float> { typedef uint16_t V; };      // BF16 bits
+__device__ __forceinline__ double sval(float v, double) { return (double)v; }
+__device__ __forceinline__ float sval(uint16_t v, float) { return __uint_as_float((uint32_t)v << 16); }
+
+// round to nearest even: FP64 -> FP32 (the conversion), FP32 -> BF16 (bits)
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ void round_to(double v, float& out) { out = (float)v; }
+__device__ __forceinline__ void round_to(double v, uint16_t& out) { out = to_bf16((float)v); }
+__device__ __forceinline__ void round_to(float v, uint16_t& out) { out = to_bf16(v); }
+
 // the Chebyshev coefficients of step j: d_{j+1} = c1 d_j + c2 D^{-1} r_{j+1}
 __device__ __forceinline__ void cheb_coef(double theta, double delta, int j, double& c1, double& c2) {
     const double sigma = theta / delta;
@@ -74,9 +98,10 @@ __device__ __forceinline__ void cheb_coef(double theta, double delta, int j, dou
     }
 }
 
-// acc = row i of A g for direction k (lane = row of the slice), the sliced ELL layout of the CG
-template <int WMAX, typename T>
-__device__ __forceinline__ T ell_row(const int* __restrict__ sptr, const int* __restrict__ col, const T* __restrict__ v,
+// acc = row i of A g for direction k (lane = row of the slice), the sliced ELL layout of the CG,
+// the values in the smoother precision VT
+template <int WMAX, typename T, typename VT>
+__device__ __forceinline__ T ell_row(const int* __restrict__ sptr, const int* __restrict__ col, const VT* __restrict__ v,
                                      const T* __restrict__ g, int sl, int lane) {
     const int g0 = sptr[sl];
     const int wd = sptr[sl + 1] - g0;
@@ -84,7 +109,7 @@ __device__ __forceinline__ T ell_row(const int* __restrict__ sptr, const int* __
     T acc = (T)0;
     if constexpr (WMAX > 0) {
         int c[WMAX];
-        T x[WMAX];
+        VT x[WMAX];
 #pragma unroll
         for (int j = 0; j < WMAX; ++j) {
             const size_t q = base + 64 * (size_t)min(j, wd - 1);
@@ -95,11 +120,11 @@ __device__ __forceinline__ T ell_row(const int* __restrict__ sptr, const int* __
 #pragma unroll
         for (int j = 0; j < WMAX; ++j) gv[j] = g[c[j]];
 #pragma unroll
-        for (int j = 0; j < WMAX; ++j) acc += (j < wd ? x[j] : (T)0) * gv[j];
+        for (int j = 0; j < WMAX; ++j) acc += (j < wd ? sval(x[j], T()) : (T)0) * gv[j];
     } else {
         for (int j = 0; j < wd; ++j) {
             const size_t q = base + 64 * (size_t)j;
-            acc += ld_stream(v + q) * g[col[q]];
+            acc += sval(ld_stream(v + q), T()) * g[col[q]];
         }
     }
     return acc;
@@ -110,10 +135,10 @@ __device__ __forceinline__ T ell_row(const int* __restrict__ sptr, const int* __
 // step j: q = A d_j;  r' = r_j - q;  x_{j+1} = (first ? 0 : x_j) + d_j;  then, unless last,
 //         r = r', d_{j+1} = c1 d_j + c2 D^{-1} r'; when last, r = r' only if Rout is given
 //                                                                     (G = d_j)
-template <int WMAX, typename T, bool RESID>
+template <int WMAX, typename T, bool RESID, typename VT = typename SmoothVal<T>::V>
 __global__ __launch_bounds__(MTB) void mg_smooth_kernel(int n, int nS, int ntiles, int nslice, int it,
                                                         const int* __restrict__ sptr, const int* __restrict__ col,
-                                                        const T* __restrict__ val, size_t len,
+                                                        const VT* __restrict__ val, size_t len,
                                                         const T* __restrict__ G, const T* Rin, T* Rout, T* X,
                                                         int first, int last, T* __restrict__ Dn,
                                                         const T* __restrict__ dinv, const double* __restrict__ cheb,
@@ -125,7 +150,7 @@ __global__ __launch_bounds__(MTB) void mg_smooth_kernel(int n, int nS, int ntile
     const int sl = t * (MTB / 64) + (threadIdx.x >> 6);
     if (sl >= nslice) return;
     const T* g = G + (size_t)n * k;
-    const T acc = ell_row<WMAX, T>(sptr, col, val + len * k, g, sl, lane);
+    const T acc = ell_row<WMAX, T, VT>(sptr, col, val + len * k, g, sl, lane);
     const int i = sl * 64 + lane;
     if (i >= n) return;
     const size_t o = (size_t)n * k + i;
@@ -247,10 +272,10 @@ __global__ void mg_cast_kernel(size_t n, const double* __restrict__ X, T* __rest
 }
 
 // inverse diagonal of every row and Gershgorin's ratio sum_j |a_ij| / a_ii, its maximum per tile
-template <int WMAX, typename T>
+template <int WMAX, typename T, typename VT = typename SmoothVal<T>::V>
 __global__ __launch_bounds__(MTB) void mg_diag_kernel(int n, int nS, int ntiles, int nslice,
                                                       const int* __restrict__ sptr, const int* __restrict__ col,
-                                                      const T* __restrict__ val, size_t len, T* __restrict__ dinv,
+                                                      const VT* __restrict__ val, size_t len, T* __restrict__ dinv,
                                                       double* __restrict__ part) {
     __shared__ double sh[8];
     int k, t;
@@ -262,11 +287,11 @@ __global__ __launch_bounds__(MTB) void mg_diag_kernel(int n, int nS, int ntiles,
     if (sl < nslice && i < n) {
         const int g0 = sptr[sl];
         const int wd = sptr[sl + 1] - g0;
-        const T* v = val + len * k;
+        const VT* v = val + len * k;
         double dg = 0.0, ab = 0.0;
         for (int j = 0; j < wd; ++j) {
             const size_t q = (size_t)(g0 + j) * 64 + lane;
-            const double a = (double)v[q];
+            const double a = (double)sval(v[q], T());
             if (col[q] == i) dg += a;
             ab += fabs(a);
         }
@@ -289,6 +314,29 @@ __global__ __launch_bounds__(64) void mg_cheb_kernel(int nS, int ntiles, double 
         cheb[2 * k + 1] = 0.5 * (m - lo * m);
     }
 }
+
+// smoother values of a level from its class values: formed in FP64, then rounded
+template <typename VT>
+__global__ void mg_fill_kernel(int nS, size_t len, int nnz, int ncls, const int* __restrict__ ell_e,
+                               const double* __restrict__ cls, const double* __restrict__ coef, VT* __restrict__ val) {
+    const size_t total = len * nS;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(q / len);
+        const int e = ell_e[q % len];
+        double v = 0.0;
+        if (e >= 0)
+            for (int c = 0; c < ncls; ++c) v = fma(coef[(size_t)k * ncls + c], cls[(size_t)c * nnz + e], v);
+        round_to(v, val[q]);
+    }
+}
+
+template <typename TS, typename VT>
+__global__ void mg_round_kernel(const TS* __restrict__ src, VT* __restrict__ dst, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        round_to(src[i], dst[i]);
+}
+
+inline unsigned grid_elems(size_t n) { return (unsigned)std::min<size_t>((n + 255) / 256, 65536); }
 
 // ---- the CG around the cycle
 
@@ -414,8 +462,9 @@ void smooth_launch(const MgArgs& g, int l, int it, const T* G, const T* Rin, T* 
     auto f = L.wmax <= 7    ? mg_smooth_kernel<7, T, RESID>
              : L.wmax <= 15 ? mg_smooth_kernel<15, T, RESID>
                             : mg_smooth_kernel<0, T, RESID>;
+    typedef typename SmoothVal<T>::V VT;
     hipLaunchKernelGGL(f, grid_dir(L.n, g.nS), dim3(MTB), 0, s, L.n, g.nS, ntiles, L.nslice, it, L.sptr, L.col,
-                       static_cast<const T*>(L.val), L.len, G, Rin, Rout, X, first, last, Dn,
+                       static_cast<const VT*>(L.val), L.len, G, Rin, Rout, X, first, last, Dn,
                        static_cast<const T*>(L.dinv), L.cheb, j, done);
     RTE_CHECK_LAUNCH();
 }
@@ -532,9 +581,10 @@ template <typename T>
 void level_setup_t(const MgArgs& g, int l, double lo, double* part, hipStream_t s) {
     const MgLevelArgs& L = g.lev[l];
     const int ntiles = tiles_of(L.n);
+    typedef typename SmoothVal<T>::V VT;
     auto f = mg_diag_kernel<0, T>;
     hipLaunchKernelGGL(f, grid_dir(L.n, g.nS), dim3(MTB), 0, s, L.n, g.nS, ntiles, L.nslice, L.sptr, L.col,
-                       static_cast<const T*>(L.val), L.len, static_cast<T*>(const_cast<void*>(L.dinv)), part);
+                       static_cast<const VT*>(L.val), L.len, static_cast<T*>(const_cast<void*>(L.dinv)), part);
     RTE_CHECK_LAUNCH();
     hipLaunchKernelGGL(mg_cheb_kernel, dim3(g.nS), dim3(64), 0, s, g.nS, ntiles, lo, (const double*)part,
                        const_cast<double*>(L.cheb));
@@ -577,6 +627,27 @@ void mg_apply(const MgArgs& g, const double* X, double* Y, hipStream_t s) {
 void mg_level_setup(const MgArgs& g, int l, double lo, double* part, hipStream_t s) {
     if (g.f32) level_setup_t<float>(g, l, lo, part, s);
     else level_setup_t<double>(g, l, lo, part, s);
+}
+
+void mg_fill_smoother(int nS, size_t len, int nnz, int ncls, const int* ell_e, const double* cls, const double* coef,
+                      float* val, hipStream_t s) {
+    hipLaunchKernelGGL(mg_fill_kernel<float>, dim3(grid_elems(len * nS)), dim3(256), 0, s, nS, len, nnz, ncls, ell_e,
+                       cls, coef, val);
+    RTE_CHECK_LAUNCH();
+}
+void mg_fill_smoother(int nS, size_t len, int nnz, int ncls, const int* ell_e, const double* cls, const double* coef,
+                      uint16_t* val, hipStream_t s) {
+    hipLaunchKernelGGL(mg_fill_kernel<uint16_t>, dim3(grid_elems(len * nS)), dim3(256), 0, s, nS, len, nnz, ncls,
+                       ell_e, cls, coef, val);
+    RTE_CHECK_LAUNCH();
+}
+void mg_round(const double* src, float* dst, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL((mg_round_kernel<double, float>), dim3(grid_elems(n)), dim3(256), 0, s, src, dst, n);
+    RTE_CHECK_LAUNCH();
+}
+void mg_round(const float* src, uint16_t* dst, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL((mg_round_kernel<float, uint16_t>), dim3(grid_elems(n)), dim3(256), 0, s, src, dst, n);
+    RTE_CHECK_LAUNCH();
 }
 
 std::unique_ptr<CgPhases> mg_phases(const CgJob& j) {

@@ -180,7 +180,9 @@ struct MgLevelArgs {
     int m = 0, n = 0, nslice = 0, wmax = 0;   // lattice vertices per axis, rows, slices, widest slice
     size_t len = 0;                           // ELL entries per direction
     const int *sptr = nullptr, *col = nullptr;
-    const void *val = nullptr, *dinv = nullptr;   // [nS * len], [nS * n] of the value type
+    // [nS * len] the level's values in the smoother precision (FP32 for FP64 vectors, BF16 for
+    // FP32 vectors); [nS * n] inverse diagonals of the vector type
+    const void *val = nullptr, *dinv = nullptr;
     const double* cheb = nullptr;             // [2 nS]: theta, delta of every direction
     void *x = nullptr, *r = nullptr, *b = nullptr, *d0 = nullptr, *d1 = nullptr;   // [nS * n] each
 };
@@ -195,9 +197,17 @@ struct MgArgs {
 const void* mg_vcycle(const MgArgs& g, int it, const int* done, hipStream_t s);
 // Y = B X (FP64 vectors), one V-cycle per direction, through the cycle's buffers
 void mg_apply(const MgArgs& g, const double* X, double* Y, hipStream_t s);
-// the inverse diagonals and Chebyshev intervals of level l from its explicit values
+// the inverse diagonals and Chebyshev intervals of level l from its smoother values
 // (lo = the level's interval fraction); part is scratch of [nS * ceil(n / 256)] doubles
 void mg_level_setup(const MgArgs& g, int l, double lo, double* part, hipStream_t s);
+// smoother values of a coarse level from its class values (formed in FP64, rounded to FP32,
+// then for BF16 to BF16, ties to even), and of level 0 by rounding the CG's values
+void mg_fill_smoother(int nS, size_t len, int nnz, int ncls, const int* ell_e, const double* cls, const double* coef,
+                      float* val, hipStream_t s);
+void mg_fill_smoother(int nS, size_t len, int nnz, int ncls, const int* ell_e, const double* cls, const double* coef,
+                      uint16_t* val, hipStream_t s);
+void mg_round(const double* src, float* dst, size_t n, hipStream_t s);
+void mg_round(const float* src, uint16_t* dst, size_t n, hipStream_t s);
 
 // one CG solve driven in phases, Jacobi (kernels_cg.hip) or multigrid (kernels_mg.hip)
 struct CgJob;

@@ -168,22 +168,25 @@ struct Handle {
     DBuf<int> cg_state;             // done [nS], active [1]
     // E_0 by CG preconditioned by a geometric multigrid V-cycle (RTE_E0_MG; lattice meshes,
     // kernels_mg.hip).  Level 0 is the fine pattern above; levels 1.. have their own sliced-ELL
-    // pattern and Galerkin class values.  Per precision, every level holds explicit values
-    // (level 0: the CG's), inverse diagonals and per direction the smoother's Chebyshev interval
-    // (theta, delta); the cycle's work vectors x, r, b, d0, d1 per level follow.
+    // pattern and Galerkin class values.  The cycle works on every level's explicit values
+    // rounded to the smoother precision: FP32 (s32) for FP64 solves, BF16 (s16) for mixed ones
+    // (the CG's own products use the full-precision level-0 values above).  Per precision:
+    // inverse diagonals and per direction the Chebyshev interval (theta, delta), both from the
+    // rounded values; then the cycle's work vectors x, r, b, d0, d1 per level.
     struct MgLevel {
         int m = 0, n = 0, nnz = 0, nslice = 0, wmax = 0;
         size_t len = 0;
         DBuf<int> sptr, col, e;
         DBuf<double> cls;
-        DBuf<double> v64, dinv64, cheb64;
-        DBuf<float> v32, dinv32;
+        DBuf<float> s32;
+        DBuf<uint16_t> s16;
+        DBuf<double> dinv64, cheb64;
+        DBuf<float> dinv32;
         DBuf<double> cheb32;
         DBuf<unsigned char> work;
-        int work_f32 = -1;           // value type the work vectors are sized for (-1: none)
         size_t bytes() const {
-            return sptr.bytes() + col.bytes() + e.bytes() + cls.bytes() + v64.bytes() + dinv64.bytes() +
-                   cheb64.bytes() + v32.bytes() + dinv32.bytes() + cheb32.bytes() + work.bytes();
+            return sptr.bytes() + col.bytes() + e.bytes() + cls.bytes() + s32.bytes() + s16.bytes() +
+                   dinv64.bytes() + cheb64.bytes() + dinv32.bytes() + cheb32.bytes() + work.bytes();
         }
     };
     int mg_m = 0;                  // lattice vertices per axis when the hierarchy exists, else 0

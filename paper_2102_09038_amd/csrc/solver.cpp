@@ -264,14 +264,17 @@ void mg_prepare(Handle* h, bool f32, hipStream_t s) {
         Handle::MgLevel& g = h->mgl[l];
         if (f32 ? !g.dinv32.p : !g.dinv64.p) {
             fresh = true;
-            if (l > 0) {
-                if (f32) {
-                    g.v32.alloc(nS * g.len);
-                    k::fill_block_values(h->nS, g.len, g.nnz, h->ncls, g.e.p, g.cls.p, h->coefE0.p, g.v32.p, s);
-                } else {
-                    g.v64.alloc(nS * g.len);
-                    k::fill_block_values(h->nS, g.len, g.nnz, h->ncls, g.e.p, g.cls.p, h->coefE0.p, g.v64.p, s);
-                }
+            // the smoother's values: BF16 for FP32 vectors, FP32 for FP64 vectors; level 0 by
+            // rounding the CG's values, coarse levels from their class values
+            const size_t len = l == 0 ? h->ell_len : g.len;
+            if (f32) {
+                g.s16.alloc(nS * len);
+                if (l == 0) k::mg_round(h->ell_v32.p, g.s16.p, nS * len, s);
+                else k::mg_fill_smoother(h->nS, len, g.nnz, h->ncls, g.e.p, g.cls.p, h->coefE0.p, g.s16.p, s);
+            } else {
+                g.s32.alloc(nS * len);
+                if (l == 0) k::mg_round(h->ell_v64.p, g.s32.p, nS * len, s);
+                else k::mg_fill_smoother(h->nS, len, g.nnz, h->ncls, g.e.p, g.cls.p, h->coefE0.p, g.s32.p, s);
             }
             if (f32) {
                 g.dinv32.alloc(nS * g.n);
@@ -308,15 +311,14 @@ k::MgArgs mg_args(Handle* h, bool f32) {
             A.len = h->ell_len;
             A.sptr = h->ell_sptr.p;
             A.col = h->ell_col.p;
-            A.val = f32 ? static_cast<const void*>(h->ell_v32.p) : static_cast<const void*>(h->ell_v64.p);
         } else {
             A.nslice = g.nslice;
             A.wmax = g.wmax;
             A.len = g.len;
             A.sptr = g.sptr.p;
             A.col = g.col.p;
-            A.val = f32 ? static_cast<const void*>(g.v32.p) : static_cast<const void*>(g.v64.p);
         }
+        A.val = f32 ? static_cast<const void*>(g.s16.p) : static_cast<const void*>(g.s32.p);
         A.dinv = f32 ? static_cast<const void*>(g.dinv32.p) : static_cast<const void*>(g.dinv64.p);
         A.cheb = f32 ? g.cheb32.p : g.cheb64.p;
         const size_t vb = (size_t)g.n * h->nS * (f32 ? sizeof(float) : sizeof(double));

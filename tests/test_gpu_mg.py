@@ -2,10 +2,11 @@
 oracle (oracle/mg.py for the cycle, sparse LU for the blocks, the Richardson iterate for the
 solve).
 
-* One V-cycle (rte_apply_mg, FP64) against the oracle's cycle on every direction, 1e-10
-  relative: 2D and 3D lattices with several levels, a lattice whose coarsest level has an odd
-  cell count, and one with a single level (the cycle is then eight Chebyshev steps); row counts
-  that leave ragged tiles.
+* One V-cycle (rte_apply_mg, FP64 vectors, the level matrices in the FP32 smoother precision)
+  against the oracle's cycle on the same FP32-rounded levels on every direction, 1e-10 relative:
+  2D and 3D lattices with several levels, a lattice whose coarsest level has an odd cell count,
+  and one with a single level (the cycle is then eight Chebyshev steps); row counts that leave
+  ragged tiles.
 * E_0^{-1} in FP64 at cg_tol 1e-13 against the LU (1e-10), with a zero right-hand side in one
   direction and bitwise repeatability; FP32 (mixed) to 1e-4.  The largest per-direction
   iteration count at tol 1e-8 against the oracle's multigrid CG (within one).
@@ -82,7 +83,7 @@ def test_vcycle_matches_oracle(mgcase):
     Yg = from_dev(Y)
     worst = 0.0
     for k in range(D.nS):
-        levels = mg.hierarchy(ops.E0_block(k), m, inst.dim)
+        levels = mg.hierarchy(ops.E0_block(k), m, inst.dim, smoother="f32")
         worst = max(worst, rel(Yg[:, k], mg.vcycle(levels, X[:, k])))
     print(f"[{name}] V-cycle worst direction {worst:.2e}")
     assert worst < 1e-10
@@ -131,7 +132,7 @@ def test_mg_iteration_counts(mgcase):
     X = torch.empty_like(to_dev(B))
     h.apply_E0inv(to_dev(B), X, o)
     iters = h.last_cg_iters()
-    ref = [mg.mg_cg(ops.E0_block(k), B[:, k], m, inst.dim, tol=1e-8)[1] for k in range(D.nS)]
+    ref = [mg.mg_cg(ops.E0_block(k), B[:, k], m, inst.dim, tol=1e-8, smoother="f32")[1] for k in range(D.nS)]
     print(f"[{name}] iterations device {max(iters)} (oracle {max(ref)}), per direction {iters}")
     assert all(abs(a - b) <= 1 for a, b in zip(iters, ref))
 
