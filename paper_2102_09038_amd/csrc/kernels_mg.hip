@@ -100,7 +100,7 @@ __device__ __forceinline__ void cheb_coef(double theta, double delta, int j, dou
 
 // acc = row i of A g for direction k (lane = row of the slice), the sliced ELL layout of the CG,
 // the values in the smoother precision VT
-template <int WMAX, typename T, typename VT>
+template <int WMAX, typename T, typename VT, bool NT = true>
 __device__ __forceinline__ T ell_row(const int* __restrict__ sptr, const int* __restrict__ col, const VT* __restrict__ v,
                                      const T* __restrict__ g, int sl, int lane) {
     const int g0 = sptr[sl];
@@ -114,7 +114,7 @@ __device__ __forceinline__ T ell_row(const int* __restrict__ sptr, const int* __
         for (int j = 0; j < WMAX; ++j) {
             const size_t q = base + 64 * (size_t)min(j, wd - 1);
             c[j] = col[q];
-            x[j] = ld_stream(v + q);
+            x[j] = NT ? ld_stream(v + q) : v[q];
         }
         T gv[WMAX];
 #pragma unroll
@@ -124,10 +124,35 @@ __device__ __forceinline__ T ell_row(const int* __restrict__ sptr, const int* __
     } else {
         for (int j = 0; j < wd; ++j) {
             const size_t q = base + 64 * (size_t)j;
-            acc += sval(ld_stream(v + q), T()) * g[col[q]];
+            acc += sval(NT ? ld_stream(v + q) : v[q], T()) * g[col[q]];
         }
     }
     return acc;
+}
+
+// The row update of a smoothing step (the vectors of one direction; acc = row i of A G):
+// RESID:  r = Rin - acc;  Rout = r;  Dn = D^{-1} r / theta
+// step j: r = Rin - acc;  X = (first ? 0 : X) + G;  then, unless last, Rout = r and
+//         Dn = c1 G + c2 D^{-1} r; when last, Rout = r only if Rout is given
+template <typename T, bool RESID>
+__device__ __forceinline__ void smooth_row(T acc, int i, const T* G, const T* Rin, T* Rout, T* X, int first, int last,
+                                           T* Dn, const T* __restrict__ dinv, double theta, double delta, int j) {
+    const T r = Rin[i] - acc;
+    if constexpr (RESID) {
+        Rout[i] = r;
+        Dn[i] = dinv[i] * r / (T)theta;
+    } else {
+        const T dj = G[i];
+        X[i] = (first ? (T)0 : X[i]) + dj;
+        if (last) {
+            if (Rout) Rout[i] = r;
+            return;
+        }
+        Rout[i] = r;
+        double c1, c2;
+        cheb_coef(theta, delta, j, c1, c2);
+        Dn[i] = (T)c1 * dj + (T)c2 * (dinv[i] * r);
+    }
 }
 
 // One smoothing launch on a level, for every direction still running (done[k] >= it):
@@ -153,24 +178,9 @@ __global__ __launch_bounds__(MTB) void mg_smooth_kernel(int n, int nS, int ntile
     const T acc = ell_row<WMAX, T, VT>(sptr, col, val + len * k, g, sl, lane);
     const int i = sl * 64 + lane;
     if (i >= n) return;
-    const size_t o = (size_t)n * k + i;
-    const double theta = cheb[2 * k], delta = cheb[2 * k + 1];
-    const T r = Rin[o] - acc;
-    if constexpr (RESID) {
-        Rout[o] = r;
-        Dn[o] = dinv[o] * r / (T)theta;
-    } else {
-        const T dj = g[i];
-        X[o] = (first ? (T)0 : X[o]) + dj;
-        if (last) {
-            if (Rout) Rout[o] = r;
-            return;
-        }
-        Rout[o] = r;
-        double c1, c2;
-        cheb_coef(theta, delta, j, c1, c2);
-        Dn[o] = (T)c1 * dj + (T)c2 * (dinv[o] * r);
-    }
+    const size_t o = (size_t)n * k;
+    smooth_row<T, RESID>(acc, i, g, Rin + o, Rout ? Rout + o : nullptr, X ? X + o : nullptr, first, last, Dn + o,
+                         dinv + o, cheb[2 * k], cheb[2 * k + 1], j);
 }
 
 __device__ __forceinline__ void lattice_coords(int v, int m, int d, int* c) {
@@ -182,22 +192,12 @@ __device__ __forceinline__ int lattice_index(const int* c, int m, int d) {
     return v;
 }
 
-// b_c = P^T r_f (coarse vertex I: r at fine 2I, plus half of r at 2I +- e_S for every nonempty
-// axis set S, in bounds), and the coarse level's d_0 = D^{-1} b_c / theta
+// (P^T r)_I for one direction's fine vector r: r at fine 2I, plus half of r at 2I +- e_S for
+// every nonempty axis set S, in bounds
 template <typename T>
-__global__ __launch_bounds__(MTB) void mg_restrict_kernel(int d, int mf, int mc, int nf, int nc, int nS, int ntiles,
-                                                          int it, const T* __restrict__ Rf, T* __restrict__ Bc,
-                                                          T* __restrict__ Dc, const T* __restrict__ dinv_c,
-                                                          const double* __restrict__ cheb_c,
-                                                          const int* __restrict__ done) {
-    int k, t;
-    if (!dir_tile(ntiles, nS, k, t)) return;
-    if (done && done[k] < it) return;
-    const int I = t * MTB + threadIdx.x;
-    if (I >= nc) return;
+__device__ __forceinline__ T restrict_row(int d, int mf, int mc, const T* r, int I) {
     int c[3];
     lattice_coords(I, mc, d, c);
-    const T* r = Rf + (size_t)nf * k;
     int q[3];
     for (int a = 0; a < d; ++a) q[a] = 2 * c[a];
     T acc = r[lattice_index(q, mf, d)];
@@ -211,12 +211,44 @@ __global__ __launch_bounds__(MTB) void mg_restrict_kernel(int d, int mf, int mc,
             }
             if (in) acc += (T)0.5 * r[lattice_index(q, mf, d)];
         }
+    return acc;
+}
+
+// b_c = P^T r_f, and the coarse level's d_0 = D^{-1} b_c / theta
+template <typename T>
+__global__ __launch_bounds__(MTB) void mg_restrict_kernel(int d, int mf, int mc, int nf, int nc, int nS, int ntiles,
+                                                          int it, const T* __restrict__ Rf, T* __restrict__ Bc,
+                                                          T* __restrict__ Dc, const T* __restrict__ dinv_c,
+                                                          const double* __restrict__ cheb_c,
+                                                          const int* __restrict__ done) {
+    int k, t;
+    if (!dir_tile(ntiles, nS, k, t)) return;
+    if (done && done[k] < it) return;
+    const int I = t * MTB + threadIdx.x;
+    if (I >= nc) return;
+    const T acc = restrict_row(d, mf, mc, Rf + (size_t)nf * k, I);
     const size_t o = (size_t)nc * k + I;
     Bc[o] = acc;
     Dc[o] = dinv_c[o] * acc / (T)cheb_c[2 * k];
 }
 
-// x_f += P e, e = x_c + d_c (the coarse level's last smoothing step)
+// (P e)_f for one direction, e = x_c + d_c (the coarse level's last smoothing step)
+template <typename T>
+__device__ __forceinline__ T prolong_row(int d, int mf, int mc, const T* Xc, const T* Dc, int f) {
+    int c[3], lo[3], hi[3];
+    lattice_coords(f, mf, d, c);
+    for (int a = 0; a < d; ++a) {
+        lo[a] = c[a] / 2;
+        hi[a] = (c[a] + 1) / 2;
+    }
+    const int il = lattice_index(lo, mc, d), ih = lattice_index(hi, mc, d);
+    const T el = Xc[il] + Dc[il];
+    T e = el;
+    if (ih != il) e = (T)0.5 * (el + (Xc[ih] + Dc[ih]));
+    return e;
+}
+
+// x_f += P e, e = x_c + d_c
 template <typename T>
 __global__ __launch_bounds__(MTB) void mg_prolong_kernel(int d, int mf, int mc, int nf, int nc, int nS, int ntiles,
                                                          int it, const T* __restrict__ Xc, const T* __restrict__ Dc,
@@ -226,18 +258,8 @@ __global__ __launch_bounds__(MTB) void mg_prolong_kernel(int d, int mf, int mc, 
     if (done && done[k] < it) return;
     const int f = t * MTB + threadIdx.x;
     if (f >= nf) return;
-    int c[3], lo[3], hi[3];
-    lattice_coords(f, mf, d, c);
-    for (int a = 0; a < d; ++a) {
-        lo[a] = c[a] / 2;
-        hi[a] = (c[a] + 1) / 2;
-    }
     const size_t oc = (size_t)nc * k;
-    const int il = lattice_index(lo, mc, d), ih = lattice_index(hi, mc, d);
-    const T el = Xc[oc + il] + Dc[oc + il];
-    T e = el;
-    if (ih != il) e = (T)0.5 * (el + (Xc[oc + ih] + Dc[oc + ih]));
-    Xf[(size_t)nf * k + f] += e;
+    Xf[(size_t)nf * k + f] += prolong_row(d, mf, mc, Xc + oc, Dc + oc, f);
 }
 
 // D = D^{-1} B / theta (the start of a cycle)
@@ -469,13 +491,143 @@ void smooth_launch(const MgArgs& g, int l, int it, const T* G, const T* Rin, T* 
     RTE_CHECK_LAUNCH();
 }
 
+// ---- the coarse tail of the cycle in one launch
+//
+// The coarse levels hold a few hundred rows per direction, and their per-level launches are
+// bound by launch latency, not by their bytes.  From level t0 down (the coarse levels whose five
+// vectors fit in kTailLds bytes of LDS together; level 0 is never among them) one work-group per
+// direction runs the rest of the cycle: the restriction from level t0 - 1, the descent, the
+// coarsest level, the ascent and the prolongation back into level t0 - 1, with the vectors of
+// every tail level in LDS and barriers in place of launch boundaries.  Matrix values, columns and
+// inverse diagonals are read from global memory (the coarse levels of all directions stay in
+// L2).  Each row's arithmetic is that of the per-level launches (the same row functions).
+constexpr int TTB = 1024;                      // threads of a tail work-group
+constexpr size_t kTailLds = 64 * 1024;         // LDS bytes for the tail's vectors
+
+template <int WMAX, typename T>
+__global__ __launch_bounds__(TTB) void mg_tail_kernel(MgArgs g, int t0, int it, const int* __restrict__ done) {
+    typedef typename SmoothVal<T>::V VT;
+    extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds[];
+    const int k = blockIdx.x;                  // on XCD k mod 8, where the per-level launches put direction k
+    if (done && done[k] < it) return;
+    const int L = g.L, tid = threadIdx.x;
+    T* const lds = reinterpret_cast<T*>(tail_lds);
+    // the vectors x, r, b, d0, d1 of tail level l (n_l each) from lds + 5 (n_t0 + ... + n_{l-1})
+    auto vec = [&](int l) __attribute__((always_inline)) {
+        size_t o = 0;
+        for (int j = t0; j < l; ++j) o += 5 * (size_t)g.lev[j].n;
+        return lds + o;
+    };
+    // one smoothing step of level l (smooth_row), then a barrier
+    auto step = [&](int l, const T* G, const T* Rin, T* Rout, T* X, int first, int last, T* Dn, int j,
+                    bool resid) __attribute__((always_inline)) {
+        const MgLevelArgs& V = g.lev[l];
+        const VT* val = static_cast<const VT*>(V.val) + V.len * k;
+        const T* dinv = static_cast<const T*>(V.dinv) + (size_t)V.n * k;
+        const double theta = V.cheb[2 * k], delta = V.cheb[2 * k + 1];
+        for (int i = tid; i < V.n; i += TTB) {
+            const T acc = ell_row<WMAX, T, VT, false>(V.sptr, V.col, val, G, i >> 6, i & 63);
+            if (resid) smooth_row<T, true>(acc, i, G, Rin, Rout, X, first, last, Dn, dinv, theta, delta, j);
+            else smooth_row<T, false>(acc, i, G, Rin, Rout, X, first, last, Dn, dinv, theta, delta, j);
+        }
+        __syncthreads();
+    };
+    // b and d_0 of level c from the residual rf of level c - 1, then a barrier
+    auto restrict_to = [&](int c, const T* rf) __attribute__((always_inline)) {
+        const MgLevelArgs& C = g.lev[c];
+        T* v = vec(c);
+        const T* dinv = static_cast<const T*>(C.dinv) + (size_t)C.n * k;
+        const double theta = C.cheb[2 * k];
+        for (int I = tid; I < C.n; I += TTB) {
+            const T acc = restrict_row(g.d, g.lev[c - 1].m, C.m, rf, I);
+            v[2 * C.n + I] = acc;
+            v[3 * C.n + I] = dinv[I] * acc / (T)theta;
+        }
+        __syncthreads();
+    };
+
+    restrict_to(t0, static_cast<const T*>(g.lev[t0 - 1].r) + (size_t)g.lev[t0 - 1].n * k);
+    // descent: nu steps from 0, the last forming the residual; restriction to the next level
+    for (int l = t0; l + 1 < L; ++l) {
+        const int n = g.lev[l].n;
+        T* v = vec(l);
+        T *x = v, *r = v + n, *b = v + 2 * n, *cur = v + 3 * n, *nxt = v + 4 * n;
+        for (int j = 0; j < kMgNu; ++j) {
+            step(l, cur, j == 0 ? b : r, r, x, j == 0, j + 1 == kMgNu, nxt, j, false);
+            T* t = cur; cur = nxt; nxt = t;
+        }
+        restrict_to(l + 1, r);
+    }
+    // coarsest level: nu_c steps from 0, the last one's x + d left to the prolongation
+    const T* ec;
+    {
+        const int n = g.lev[L - 1].n;
+        T* v = vec(L - 1);
+        T *x = v, *r = v + n, *b = v + 2 * n, *cur = v + 3 * n, *nxt = v + 4 * n;
+        for (int j = 0; j + 1 < kMgNuCoarse; ++j) {
+            step(L - 1, cur, j == 0 ? b : r, r, x, j == 0, 0, nxt, j, false);
+            T* t = cur; cur = nxt; nxt = t;
+        }
+        ec = cur;
+    }
+    // ascent: x += P e, residual and d_0, nu - 1 full steps
+    for (int l = L - 2; l >= t0; --l) {
+        const int n = g.lev[l].n;
+        T* v = vec(l);
+        T *x = v, *r = v + n, *b = v + 2 * n, *cur = v + 3 * n, *nxt = v + 4 * n;
+        const T* xc = vec(l + 1);
+        for (int f = tid; f < n; f += TTB) x[f] += prolong_row(g.d, g.lev[l].m, g.lev[l + 1].m, xc, ec, f);
+        __syncthreads();
+        step(l, x, b, r, nullptr, 0, 0, cur, 0, true);
+        for (int j = 0; j + 1 < kMgNu; ++j) {
+            step(l, cur, r, r, x, 0, 0, nxt, j, false);
+            T* t = cur; cur = nxt; nxt = t;
+        }
+        ec = cur;
+    }
+    // x of level t0 - 1 (global) += P e
+    const MgLevelArgs& F = g.lev[t0 - 1];
+    T* xf = static_cast<T*>(F.x) + (size_t)F.n * k;
+    const T* xc = vec(t0);
+    for (int f = tid; f < F.n; f += TTB) xf[f] += prolong_row(g.d, F.m, g.lev[t0].m, xc, ec, f);
+}
+
+// the first level of the fused tail: the longest run of coarsest levels, level 0 excluded, whose
+// five vectors fit in kTailLds bytes; L when there is none
+inline int tail_start(const MgArgs& g, size_t elem) {
+    size_t rows = 0;
+    int t0 = g.L;
+    for (int l = g.L - 1; l >= 1; --l) {
+        rows += (size_t)g.lev[l].n;
+        if (5 * rows * elem > kTailLds) break;
+        t0 = l;
+    }
+    return t0;
+}
+
+template <typename T>
+void tail_launch(const MgArgs& g, int t0, int it, const int* done, hipStream_t s) {
+    int wmax = 0;
+    size_t rows = 0;
+    for (int l = t0; l < g.L; ++l) {
+        wmax = std::max(wmax, g.lev[l].wmax);
+        rows += (size_t)g.lev[l].n;
+    }
+    const size_t lds = 5 * rows * sizeof(T);
+    if (t0 < 1 || t0 >= g.L || lds > kTailLds) fail(RTE_E_ARG, "multigrid: bad coarse tail");
+    auto f = wmax <= 7 ? mg_tail_kernel<7, T> : wmax <= 15 ? mg_tail_kernel<15, T> : mg_tail_kernel<0, T>;
+    hipLaunchKernelGGL(f, dim3(g.nS), dim3(TTB), lds, s, g, t0, it, done);
+    RTE_CHECK_LAUNCH();
+}
+
 template <typename T>
 const T* vcycle_t(const MgArgs& g, int it, const int* done, hipStream_t s) {
     const int L = g.L;
+    const int t0 = tail_start(g, sizeof(T));       // levels t0.. run in the fused tail (none when L)
     const T* ecur[kMgMaxLevels] = {};
     // descent: nu Chebyshev steps from 0 (d_0 is in d0), the last also forming the residual;
-    // restriction to the next level with its d_0
-    for (int l = 0; l + 1 < L; ++l) {
+    // restriction to the next level with its d_0 (into the tail's first level: the tail's own)
+    for (int l = 0; l + 1 < L && l < t0; ++l) {
         const MgLevelArgs& V = g.lev[l];
         T* x = static_cast<T*>(V.x);
         T* r = static_cast<T*>(V.r);
@@ -487,13 +639,16 @@ const T* vcycle_t(const MgArgs& g, int it, const int* done, hipStream_t s) {
                                     j, done, s);
             std::swap(cur, nxt);
         }
+        if (l + 1 == t0) break;
         const MgLevelArgs& C = g.lev[l + 1];
         hipLaunchKernelGGL(mg_restrict_kernel<T>, grid_dir(C.n, g.nS), dim3(MTB), 0, s, g.d, V.m, C.m, V.n, C.n, g.nS,
                            tiles_of(C.n), it, (const T*)r, static_cast<T*>(C.b), static_cast<T*>(C.d0),
                            static_cast<const T*>(C.dinv), C.cheb, done);
         RTE_CHECK_LAUNCH();
     }
-    {   // coarsest level: kMgNuCoarse steps from 0, the last one's x + d left to the prolongation
+    if (t0 < L) {
+        tail_launch<T>(g, t0, it, done, s);            // ends with x of level t0 - 1 += P e
+    } else {   // coarsest level: kMgNuCoarse steps from 0, the last one's x + d left to the prolongation
         const MgLevelArgs& V = g.lev[L - 1];
         T* x = static_cast<T*>(V.x);
         T* r = static_cast<T*>(V.r);
@@ -506,15 +661,18 @@ const T* vcycle_t(const MgArgs& g, int it, const int* done, hipStream_t s) {
         }
         ecur[L - 1] = cur;
     }
-    // ascent: x += P e, residual and d_0, nu - 1 full steps; the last x + d left to the caller
-    for (int l = L - 2; l >= 0; --l) {
+    // ascent: x += P e (for level t0 - 1 the tail did it), residual and d_0, nu - 1 full steps;
+    // the last x + d left to the caller
+    for (int l = std::min(L - 2, t0 - 1); l >= 0; --l) {
         const MgLevelArgs& V = g.lev[l];
         const MgLevelArgs& C = g.lev[l + 1];
         T* x = static_cast<T*>(V.x);
         T* r = static_cast<T*>(V.r);
-        hipLaunchKernelGGL(mg_prolong_kernel<T>, grid_dir(V.n, g.nS), dim3(MTB), 0, s, g.d, V.m, C.m, V.n, C.n, g.nS,
-                           tiles_of(V.n), it, static_cast<const T*>(C.x), ecur[l + 1], x, done);
-        RTE_CHECK_LAUNCH();
+        if (l + 1 < t0) {
+            hipLaunchKernelGGL(mg_prolong_kernel<T>, grid_dir(V.n, g.nS), dim3(MTB), 0, s, g.d, V.m, C.m, V.n, C.n,
+                               g.nS, tiles_of(V.n), it, static_cast<const T*>(C.x), ecur[l + 1], x, done);
+            RTE_CHECK_LAUNCH();
+        }
         T* cur = static_cast<T*>(V.d0);
         T* nxt = static_cast<T*>(V.d1);
         smooth_launch<T, true>(g, l, it, x, static_cast<const T*>(V.b), r, nullptr, 0, 0, cur, 0, done, s);
