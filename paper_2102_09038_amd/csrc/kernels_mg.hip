@@ -18,7 +18,8 @@
 // gathered from one buffer, d_{j+1} written to the other).  The residual that the restriction
 // reads is the recurrence's r (one more SpMV step); the post-smoothing starts with the SpMV
 // r_0 = b - A x; the last x + d of a level is left to the launch that reads it (the prolongation
-// of the finer level, or the CG's z = x + d).
+// of the finer level, or the CG's z = x + d).  The coarse levels, where launches are bound by their
+// latency, run in one launch per cycle instead (the fused tail below).
 //
 // Smoother precision: the cycle reads every level's matrix in a reduced precision, FP32 when
 // the vectors are FP64 and BF16 when they are FP32 (values rounded to nearest even; inverse
