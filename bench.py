@@ -632,6 +632,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = args.steps / dt
+    print(f"[fp64] {args.steps} solves in {dt:.2f} s", file=sys.stderr, flush=True)
 
     t_e0 = sum(i.t_e0inv for i in infos)
     n_e0 = sum(i.n_e0inv for i in infos)
@@ -738,6 +739,7 @@ def main():
         minfos.append(info)
     torch.cuda.synchronize()
     mdt = time.perf_counter() - t0
+    print(f"[mixed] {args.steps} solves in {mdt:.2f} s", file=sys.stderr, flush=True)
     tb = sum(i.t_gemm_bf16 for i in minfos)
     fb = sum(i.gemm_bf16_flops for i in minfos)
     nb = sum(i.n_gemm_bf16 for i in minfos)
@@ -771,6 +773,9 @@ def main():
                        "frac": e0m_gbs / HBM_PEAK_GBS, "avg_launch_ms": 1e3 * t_e0m / max(n_e0m, 1),
                        "bytes_per_launch": e0m_bytes, "traffic": measured_traffic("band_solve_f32")},
     }
+    # the side measurements below (other correction space, other inner iteration) repeat each
+    # solve a fixed few times, whatever --steps says, so the whole line stays within minutes
+    side_steps, side_warmup = min(args.steps, 4), min(args.warmup, 1)
     # ---- the same workload with the larger correction space N+ = 4 (d_N = 15, 249615 coarse
     #      unknowns solved by the block-tridiagonal Cholesky)
     h4 = rte.Handle.from_instance(inputs.config_realistic(n_even=4), e0_solver=rte.RTE_E0_BANDED, mixed=1, odd_eig=0)
@@ -780,14 +785,16 @@ def main():
                                     odd_solver=base_opts.odd_solver, e0_solver=base_opts.e0_solver,
                                     precision=base_opts.precision)
         U4 = torch.empty_like(U)
-        for _ in range(args.warmup):
+        for _ in range(side_warmup):
             h4.solve(U4, opts=o4)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        i4 = [h4.solve(U4, opts=o4)[1] for _ in range(args.steps)]
+        i4 = [h4.solve(U4, opts=o4)[1] for _ in range(side_steps)]
         torch.cuda.synchronize()
         dt4 = time.perf_counter() - t0
-        out["n_even_4"][name] = {"value": args.steps / dt4, "unit": "solves/s", "ms_per_step": 1e3 * dt4 / args.steps,
+        print(f"[n_even 4 {name}] {side_steps} solves in {dt4:.2f} s", file=sys.stderr, flush=True)
+        out["n_even_4"][name] = {"value": side_steps / dt4, "unit": "solves/s", "ms_per_step": 1e3 * dt4 / side_steps,
+                                 "steps": side_steps, "warmup": side_warmup,
                                  "iters": [i.iters for i in i4], "rel_resid": [i.rel_resid for i in i4],
                                  "rel_diff_vs_fp64_solution": float(torch.linalg.norm(U4 - U64) / torch.linalg.norm(U64))}
     h4.close()
@@ -799,16 +806,18 @@ def main():
                                     odd_solver=base_opts.odd_solver, e0_solver=base_opts.e0_solver,
                                     precision=base_opts.precision, inner=rte.RTE_INNER_PCG)
         Up = torch.empty_like(U)
-        for _ in range(args.warmup):
+        for _ in range(side_warmup):
             h.solve(Up, opts=po)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pinfos = [h.solve(Up, opts=po)[1] for _ in range(args.steps)]
+        pinfos = [h.solve(Up, opts=po)[1] for _ in range(side_steps)]
         torch.cuda.synchronize()
         pdt = time.perf_counter() - t0
+        print(f"[inner pcg {name}] {side_steps} solves in {pdt:.2f} s", file=sys.stderr, flush=True)
         out["inner_pcg"][name] = {
-            "value": args.steps / pdt, "unit": "solves/s", "ms_per_step": 1e3 * pdt / args.steps,
-            "speedup_vs_richardson_inner": (args.steps / pdt) / base_value,
+            "value": side_steps / pdt, "unit": "solves/s", "ms_per_step": 1e3 * pdt / side_steps,
+            "steps": side_steps, "warmup": side_warmup,
+            "speedup_vs_richardson_inner": (side_steps / pdt) / base_value,
             "iters": [i.iters for i in pinfos], "rel_resid": [i.rel_resid for i in pinfos],
             "rel_diff_vs_fp64_solution": float(torch.linalg.norm(Up - U64) / torch.linalg.norm(U64))}
     h.close()
