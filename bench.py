@@ -483,6 +483,26 @@ def e0inv_3d(torch, rte, inputs, log):
                           "max_iters": max(h.last_cg_iters())}
             log(f"[3d E_0^-1] {name} {pname}: {res[pname]['ms']:.1f} ms, {res[pname]['max_iters']} iterations")
         out[name] = res
+    # the CG's SpMV on this request (rte_apply_E0, FP64, all 256 directions), timed like the 2D
+    # one: HIP events on its stream; the explicit values, the column pattern, X and Y once
+    len_ell = ell_entries(inst)
+    nb = h.dims.nSp * len_ell * 8 + len_ell * 4 + 2 * h.dims.nRp * h.dims.nSp * 8
+    stream = torch.cuda.current_stream()
+    h.apply_E0(B, X, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_spmv = 20
+    ev0.record(stream)
+    for _ in range(n_spmv):
+        h.apply_E0(B, X, stream=stream.cuda_stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / n_spmv
+    gbs = nb / (ms * 1e-3) / 1e9
+    out["spmv"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                   "kernel": "cg_spmv_kernel<double> (E_0 X, sliced ELL, all directions)", "avg_launch_ms": ms,
+                   "launches": n_spmv, "bytes_per_launch": nb, "ell_entries_per_direction": len_ell}
+    log(f"[3d spmv] {ms:.4f} ms, {gbs:.0f} GB/s = {gbs / HBM_PEAK_GBS:.3f} of {HBM_PEAK_GBS:.0f} GB/s")
     o = rte.default_solve_opts(l=4, tol=1e-6, max_iter=400, odd_solver=rte.RTE_ODD_CONDENSED, e0_solver=rte.RTE_E0_MG,
                                precision=rte.RTE_MIXED, cg_max_iter=2000)
     U = torch.empty_like(B)
