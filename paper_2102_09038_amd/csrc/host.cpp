@@ -448,7 +448,7 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
     }
     if (o->e0_solver == RTE_E0_MG) {
         // per level: smoother values (FP32 for FP64 solves, BF16 for mixed ones), inverse
-        // diagonals and Chebyshev intervals per precision, five work vectors; levels 1..: the
+        // diagonals, Chebyshev intervals and coefficients per precision, five work vectors; levels 1..: the
         // sliced-ELL pattern (P1 stencil widths 7 / 15) and class values
         const int m = lattice_m(D);
         if (m) {
@@ -459,7 +459,7 @@ size_t estimate_footprint(const rte_problem_desc* D, const rte_assemble_opts* o,
             for (size_t l = 0; l < sizes.size(); ++l) {
                 const size_t nl = d == 2 ? (size_t)sizes[l] * sizes[l] : (size_t)sizes[l] * sizes[l] * sizes[l];
                 const size_t len = (nl + 63) / 64 * 64 * w;
-                b += nS * nl * per + 2 * nS * 8 * 2 + 5 * nl * nS * 8 + nS * len * sv;
+                b += nS * nl * per + 2 * nS * (1 + kMgChebSteps) * 8 * 2 + 5 * nl * nS * 8 + nS * len * sv;
                 if (l > 0) b += 2 * len * 4 + (nl / 64 + 2) * 4 + (size_t)kMaxClasses * nl * w * 8;
             }
         }

@@ -28,6 +28,9 @@ struct Error : std::runtime_error {
 constexpr int kMaxClasses = 16;                         // sparse value classes of the P1 pattern
 constexpr double kEcinvMaxBytes = 12.0 * (1 << 30);     // budget of an explicit E_c^{-1}
 constexpr int kFacCols = 9;     // columns per thread of the band factorisation's trailing update
+// Chebyshev steps whose coefficients are tabulated per multigrid level and direction (at least
+// the steps of a smoothing pass on any level)
+constexpr int kMgChebSteps = 8;
 
 namespace k {
 // Blocked band layout of a factor with band width bw (kernels_band.hip): rows in blocks of

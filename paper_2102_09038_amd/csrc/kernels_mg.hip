@@ -135,9 +135,10 @@ __device__ __forceinline__ T ell_row(const int* __restrict__ sptr, const int* __
 // RESID:  r = Rin - acc;  Rout = r;  Dn = D^{-1} r / theta
 // step j: r = Rin - acc;  X = (first ? 0 : X) + G;  then, unless last, Rout = r and
 //         Dn = c1 G + c2 D^{-1} r; when last, Rout = r only if Rout is given
+// (c1, c2: the tabulated coefficients of the step)
 template <typename T, bool RESID>
 __device__ __forceinline__ void smooth_row(T acc, int i, const T* G, const T* Rin, T* Rout, T* X, int first, int last,
-                                           T* Dn, const T* __restrict__ dinv, double theta, double delta, int j) {
+                                           T* Dn, const T* __restrict__ dinv, double theta, double c1, double c2) {
     const T r = Rin[i] - acc;
     if constexpr (RESID) {
         Rout[i] = r;
@@ -150,8 +151,6 @@ __device__ __forceinline__ void smooth_row(T acc, int i, const T* G, const T* Ri
             return;
         }
         Rout[i] = r;
-        double c1, c2;
-        cheb_coef(theta, delta, j, c1, c2);
         Dn[i] = (T)c1 * dj + (T)c2 * (dinv[i] * r);
     }
 }
@@ -180,8 +179,9 @@ __global__ __launch_bounds__(MTB) void mg_smooth_kernel(int n, int nS, int ntile
     const int i = sl * 64 + lane;
     if (i >= n) return;
     const size_t o = (size_t)n * k;
+    const double* cf = cheb + 2 * (size_t)nS + ((size_t)k * kMgChebSteps + j) * 2;
     smooth_row<T, RESID>(acc, i, g, Rin + o, Rout ? Rout + o : nullptr, X ? X + o : nullptr, first, last, Dn + o,
-                         dinv + o, cheb[2 * k], cheb[2 * k + 1], j);
+                         dinv + o, cheb[2 * k], cf[0], cf[1]);
 }
 
 __device__ __forceinline__ void lattice_coords(int v, int m, int d, int* c) {
@@ -325,16 +325,25 @@ __global__ __launch_bounds__(MTB) void mg_diag_kernel(int n, int nS, int ntiles,
     if (threadIdx.x == 0) part[(size_t)k * ntiles + t] = ratio;
 }
 
-// lam = the largest ratio of direction k; theta = (lam + lo lam) / 2, delta = (lam - lo lam) / 2
+// lam = the largest ratio of direction k; theta = (lam + lo lam) / 2, delta = (lam - lo lam) / 2;
+// the coefficients c1, c2 of steps 0 .. kMgChebSteps - 1 after them (lane j: step j)
 __global__ __launch_bounds__(64) void mg_cheb_kernel(int nS, int ntiles, double lo, const double* __restrict__ part,
                                                      double* __restrict__ cheb) {
     const int k = blockIdx.x;
     double m = 0.0;
     for (int i = threadIdx.x; i < ntiles; i += 64) m = fmax(m, part[(size_t)k * ntiles + i]);
     m = dev::wave_max(m);
+    const double theta = 0.5 * (m + lo * m), delta = 0.5 * (m - lo * m);
     if (threadIdx.x == 0) {
-        cheb[2 * k] = 0.5 * (m + lo * m);
-        cheb[2 * k + 1] = 0.5 * (m - lo * m);
+        cheb[2 * k] = theta;
+        cheb[2 * k + 1] = delta;
+    }
+    if (threadIdx.x < kMgChebSteps) {
+        double c1, c2;
+        cheb_coef(theta, delta, threadIdx.x, c1, c2);
+        double* cf = cheb + 2 * (size_t)nS + ((size_t)k * kMgChebSteps + threadIdx.x) * 2;
+        cf[0] = c1;
+        cf[1] = c2;
     }
 }
 
@@ -525,11 +534,13 @@ __global__ __launch_bounds__(TTB) void mg_tail_kernel(MgArgs g, int t0, int it, 
         const MgLevelArgs& V = g.lev[l];
         const VT* val = static_cast<const VT*>(V.val) + V.len * k;
         const T* dinv = static_cast<const T*>(V.dinv) + (size_t)V.n * k;
-        const double theta = V.cheb[2 * k], delta = V.cheb[2 * k + 1];
+        const double theta = V.cheb[2 * k];
+        const double* cf = V.cheb + 2 * (size_t)g.nS + ((size_t)k * kMgChebSteps + j) * 2;
+        const double c1 = cf[0], c2 = cf[1];
         for (int i = tid; i < V.n; i += TTB) {
             const T acc = ell_row<WMAX, T, VT, false>(V.sptr, V.col, val, G, i >> 6, i & 63);
-            if (resid) smooth_row<T, true>(acc, i, G, Rin, Rout, X, first, last, Dn, dinv, theta, delta, j);
-            else smooth_row<T, false>(acc, i, G, Rin, Rout, X, first, last, Dn, dinv, theta, delta, j);
+            if (resid) smooth_row<T, true>(acc, i, G, Rin, Rout, X, first, last, Dn, dinv, theta, c1, c2);
+            else smooth_row<T, false>(acc, i, G, Rin, Rout, X, first, last, Dn, dinv, theta, c1, c2);
         }
         __syncthreads();
     };

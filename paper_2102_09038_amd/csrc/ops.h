@@ -176,6 +176,7 @@ constexpr int kMgNu = 4;              // Chebyshev steps before and after the co
 constexpr int kMgNuCoarse = 8;        // Chebyshev steps on the coarsest level
 constexpr double kMgLo = 0.02;        // smoothing interval [lo lam, lam]
 constexpr double kMgLoCoarse = 0.02;
+static_assert(kMgChebSteps >= kMgNu && kMgChebSteps >= kMgNuCoarse, "Chebyshev coefficient table too short");
 struct MgLevelArgs {
     int m = 0, n = 0, nslice = 0, wmax = 0;   // lattice vertices per axis, rows, slices, widest slice
     size_t len = 0;                           // ELL entries per direction
@@ -183,7 +184,8 @@ struct MgLevelArgs {
     // [nS * len] the level's values in the smoother precision (FP32 for FP64 vectors, BF16 for
     // FP32 vectors); [nS * n] inverse diagonals of the vector type
     const void *val = nullptr, *dinv = nullptr;
-    const double* cheb = nullptr;             // [2 nS]: theta, delta of every direction
+    // [2 nS]: theta, delta of every direction, then [nS][kMgChebSteps][2]: c1, c2 of step j
+    const double* cheb = nullptr;
     void *x = nullptr, *r = nullptr, *b = nullptr, *d0 = nullptr, *d1 = nullptr;   // [nS * n] each
 };
 struct MgArgs {

@@ -278,10 +278,10 @@ void mg_prepare(Handle* h, bool f32, hipStream_t s) {
             }
             if (f32) {
                 g.dinv32.alloc(nS * g.n);
-                g.cheb32.alloc(2 * nS);
+                g.cheb32.alloc(2 * nS * (1 + rte::kMgChebSteps));
             } else {
                 g.dinv64.alloc(nS * g.n);
-                g.cheb64.alloc(2 * nS);
+                g.cheb64.alloc(2 * nS * (1 + rte::kMgChebSteps));
             }
         }
         if (!g.work.p) g.work.alloc(5 * (size_t)g.n * nS * sizeof(double));
